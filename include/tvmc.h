@@ -1,0 +1,163 @@
+/*
+ * tvmc.h -- C ABI of the MI355X (gfx950) implementation of trajectory-unravelled
+ * time-dependent variational Monte Carlo (otVMC).
+ *
+ * Method: Apostoli, D'Alberto, Genoni, Bertaina, Galli, "Unraveling Open Quantum Dynamics
+ * with Time-Dependent Variational Monte Carlo".  Each trajectory carries complex variational
+ * parameters theta (M of them) and follows the otVMC equations (Eq. 8):
+ *     sum_k' S_kk' dtheta_k' = -i F_k dt + sum_n N^n_k o dW_n,
+ * with O_k = d log psi / d theta_k, E_eff = (H_eff^Strat psi)(x)/psi(x) (Eq. 5),
+ * B^n = (L_n psi)(x)/psi(x), S = <O* O> - <O*><O>, F = <O* E_eff> - <O*><E_eff>,
+ * N^n = <O* B^n> - <O*><B^n>, all estimated from Metropolis samples of |psi|^2.  The
+ * increment is D = -i F dt + sum_n N^n dW_n (paragraph after Eq. 9), the solve is
+ * (S + eps I) delta = D, and the Stratonovich predictor-correctors of App. C advance theta.
+ *
+ * Conventions (hbar = 1):
+ *   H = sum_{i<j} J_ij sz_i sz_j + hx sum_i sx_i        (the LITF Hamiltonian, Eq. 10, with
+ *       the couplings and field passed in: the paper's sign is J_ij < 0, hx = -h)
+ *   L_n = sqrt(rate_n) * op_n(site_n), op in {sigma^-, sigma^+, sigma^z}   (Eq. 1)
+ *   configuration sigma_i = +-1 (sz eigenvalues); bit i of a packed word set <=> sigma_i = +1.
+ *
+ * Parameter layout theta (interleaved re, im doubles):
+ *   Jastrow (Eq. 12): [a_0..a_{N-1}, eta_01, eta_02, .., eta_0,N-1, eta_12, .., eta_N-2,N-1]
+ *   RBM     (Eq. 11): [a_0..a_{N-1}, b_0..b_{N'-1}, w_00, w_01, .., w_0,N'-1, w_10, ..]  (reserved)
+ *
+ * Ownership: every host pointer passed in is read during the call and may be freed after it.
+ * The device workspace is allocated by the caller (size from tvmc_workspace_size), must stay
+ * alive and untouched until tvmc_destroy, and is never freed by the library.  The library
+ * allocates no device memory.  Work is enqueued asynchronously on the caller's HIP stream;
+ * getters and tvmc_synchronize block on that stream.  No call throws or aborts: failures are
+ * reported as tvmc_status, with a message from tvmc_last_error.
+ */
+#ifndef TVMC_H
+#define TVMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tvmc_ctx tvmc_ctx;
+
+typedef enum {
+    TVMC_OK = 0,
+    TVMC_E_INVAL = 1,        /* bad argument or unsupported size */
+    TVMC_E_NOMEM = 2,        /* workspace too small */
+    TVMC_E_DEVICE = 3,       /* a HIP runtime call failed */
+    TVMC_E_NUMERIC = 4,      /* non-positive pivot or non-finite update in some trajectory */
+    TVMC_E_STATE = 5,        /* stage calls out of order */
+    TVMC_E_UNSUPPORTED = 6
+} tvmc_status;
+
+enum { TVMC_JUMP_SIGMA_MINUS = 0, TVMC_JUMP_SIGMA_PLUS = 1, TVMC_JUMP_SIGMA_Z = 2 };
+enum { TVMC_ANSATZ_JASTROW = 0, TVMC_ANSATZ_RBM = 1 };
+enum { TVMC_SCHEME_HEUN = 0, TVMC_SCHEME_MIDPOINT = 1 };
+/* FP64: S accumulated with FP64 vector FMAs.  MFMA: S accumulated on int8 matrix cores; for
+ * the Jastrow ansatz every O_k is +-1, so both give the same S bit for bit.  Solve and theta
+ * stay FP64 in both. */
+enum { TVMC_PREC_FP64 = 0, TVMC_PREC_MFMA = 1 };
+
+/* One Lindblad problem (Eq. 1 with the Hamiltonian of Eq. 10), shared by all trajectories. */
+typedef struct {
+    int32_t n_sites;              /* N, 1..64 */
+    const double *J;              /* host, N*N row-major, symmetric, zero diagonal */
+    double hx;
+    int32_t n_jumps;              /* 0..256 */
+    const int32_t *jump_kind;     /* host, n_jumps entries of TVMC_JUMP_* */
+    const int32_t *jump_site;     /* host, n_jumps entries in [0, N) */
+    const double *jump_rate;      /* host, n_jumps entries >= 0 */
+} tvmc_problem;
+
+typedef struct {
+    int32_t kind;                 /* TVMC_ANSATZ_JASTROW (TVMC_ANSATZ_RBM is reserved) */
+    int32_t n_hidden;
+} tvmc_ansatz;
+
+typedef struct {
+    int32_t n_traj;               /* trajectories integrated together (grid dimension) */
+    int32_t traj_offset;          /* id of the first trajectory: selects its random streams */
+    int32_t n_samples;            /* Metropolis samples per evaluation, multiple of n_chains */
+    int32_t n_chains;             /* Markov chains per trajectory, multiple of 8 or < 8 */
+    int32_t burn_sweeps;          /* sweeps (N proposals each) before recording, per evaluation */
+    int32_t thin_sweeps;          /* sweeps between recorded samples */
+    int32_t init_sweeps;          /* extra burn-in at the very first evaluation */
+    int32_t scheme;               /* TVMC_SCHEME_* (App. C) */
+    double dt;
+    double diag_shift;            /* eps of (S + eps I) */
+    int32_t precision;            /* TVMC_PREC_* */
+    int32_t obs_every;            /* record moments at steps that are multiples of this (0: never) */
+    int32_t n_obs_max;            /* capacity of the moment history */
+    uint64_t seed;                /* Philox4x32-10 key */
+} tvmc_config;
+
+/* Quantities readable with tvmc_get (per trajectory unless noted). */
+enum {
+    TVMC_Q_THETA = 0,       /* double[2M] current theta */
+    TVMC_Q_THETA_EVAL = 1,  /* double[2M] theta of the current evaluation */
+    TVMC_Q_DELTA0 = 2,      /* double[2M] predictor increment */
+    TVMC_Q_DELTA1 = 3,      /* double[2M] corrector increment */
+    TVMC_Q_SAMPLES = 4,     /* uint64[n_samples] packed configurations of the last sampling */
+    TVMC_Q_ELOC = 5,        /* double[2 n_samples] local energy of H */
+    TVMC_Q_S = 6,           /* double[M*M] S + eps I, lower triangle valid (before the solve) */
+    TVMC_Q_D = 7,           /* double[2M] D */
+    TVMC_Q_OBAR = 8,        /* double[M] <O_k> (real for the Jastrow ansatz) */
+    TVMC_Q_BMEAN = 9,       /* double[2 n_jumps] <B^n> */
+    TVMC_Q_DW = 10,         /* double[n_jumps] Wiener increments of the current step */
+    TVMC_Q_ACCEPTS = 11,    /* uint32[n_chains] accepted proposals in the last sampling */
+    TVMC_Q_CHAINS = 12,     /* uint64[n_chains] chain configurations */
+    TVMC_Q_MOMENTS = 13,    /* double[9] moments (mx,my,mz,sxx,syy,szz,sxy,sxz,syz) */
+    TVMC_Q_OBS_HIST = 14    /* double[n_obs_max*9] moment history; traj selects the trajectory */
+};
+
+/* Bytes of device workspace needed for this problem, ansatz and configuration. */
+tvmc_status tvmc_workspace_size(const tvmc_problem *problem, const tvmc_ansatz *ansatz,
+                                const tvmc_config *config, size_t *bytes);
+
+/* Create a context: copies the problem into the workspace, sets theta = theta0 (host,
+ * interleaved, M complex values shared by every trajectory; NULL = all zeros, the +x coherent
+ * state of the Jastrow ansatz) and draws the initial chain configurations uniformly.
+ * stream: a hipStream_t (NULL = default stream). */
+tvmc_status tvmc_init(const tvmc_problem *problem, const tvmc_ansatz *ansatz, const tvmc_config *config,
+                      const double *theta0, void *d_workspace, size_t workspace_bytes, void *stream,
+                      tvmc_ctx **out);
+
+/* Metropolis sampling of |psi|^2 at the current evaluation point (text after Eq. 9); at the
+ * predictor stage it also draws the step's Wiener increments.  Requires the stage to be ready. */
+tvmc_status tvmc_sample(tvmc_ctx *ctx);
+/* Local estimators, <B^n>, D and S + eps I (definitions after Eq. 8).  Requires tvmc_sample. */
+tvmc_status tvmc_estimate(tvmc_ctx *ctx);
+/* Regularised solve (S + eps I) delta = D in FP64 (Cholesky).  Requires tvmc_estimate. */
+tvmc_status tvmc_sr_solve(tvmc_ctx *ctx);
+/* Predictor-corrector update of App. C for the current stage.  Requires tvmc_sr_solve. */
+tvmc_status tvmc_update(tvmc_ctx *ctx);
+/* n_steps full steps (noise, predictor, corrector); records moments every obs_every steps
+ * from the predictor samples.  Requires the predictor stage to be ready. */
+tvmc_status tvmc_sde_step(tvmc_ctx *ctx, int32_t n_steps);
+/* Moments of the collective spin from the last samples (observables paragraph of the LITF
+ * section); copies double[n_traj][9] to moments_out when it is not NULL. */
+tvmc_status tvmc_observables(tvmc_ctx *ctx, double *moments_out);
+/* Trajectory average (Eq. 3) of the last moments: out[0..2] = M, out[3..11] = C (row-major),
+ * out[12] = xi^2 (Wineland, minimum over the plane orthogonal to M). */
+tvmc_status tvmc_ensemble(tvmc_ctx *ctx, double *out);
+/* Copy a quantity (TVMC_Q_*) of one trajectory to host memory of at least `bytes` bytes. */
+tvmc_status tvmc_get(tvmc_ctx *ctx, int32_t what, int32_t traj, void *host_out, size_t bytes);
+/* Overwrite theta (TVMC_Q_THETA) or the chain configurations (TVMC_Q_CHAINS) of a trajectory. */
+tvmc_status tvmc_set(tvmc_ctx *ctx, int32_t what, int32_t traj, const void *host_in, size_t bytes);
+/* Current step index and stage (0 predictor, 1 corrector). */
+tvmc_status tvmc_position(const tvmc_ctx *ctx, int32_t *step, int32_t *stage);
+/* Wait for the stream and report TVMC_E_NUMERIC if any trajectory failed. */
+tvmc_status tvmc_synchronize(tvmc_ctx *ctx);
+/* Average duration in milliseconds of the last n launches of the named kernel group
+ * ("sample", "estimate", "sbuild", "solve", "update"), measured with HIP events on the
+ * context's stream when timing was enabled with tvmc_set_timing. */
+tvmc_status tvmc_set_timing(tvmc_ctx *ctx, int32_t enable);
+tvmc_status tvmc_timing(tvmc_ctx *ctx, const char *group, double *avg_ms, int32_t *count);
+const char *tvmc_last_error(const tvmc_ctx *ctx);
+tvmc_status tvmc_destroy(tvmc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

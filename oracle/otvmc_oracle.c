@@ -423,7 +423,8 @@ static int chol_solve(int m, cplx *A, cplx *b)
  *   -> delta = (S + eps I)^{-1} D.
  * E_eff uses H_eff^Strat of Eq. 5 without its c-number terms (they cancel in F, which is a
  * covariance); <L_n + L_n^dag> is the Monte Carlo estimate 2 Re<B^n> from the same samples.
- * want_solve = 0 samples and evaluates observables only.
+ * want_solve = 0 samples and evaluates observables only; 2 also computes the means, F, N^n
+ * and D but neither S nor the solve (for large-N checks where S is checked separately).
  */
 int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, const double *theta,
              int8_t *chains, int32_t traj, int32_t step, int32_t stage, int32_t first, const double *dw,
@@ -512,7 +513,7 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
     int status = ORC_OK;
     if (want_solve) {
         cplx *ob = calloc(m, sizeof(cplx)), *bm = calloc(nch + 1, sizeof(cplx));
-        cplx *S = malloc(sizeof(cplx) * (size_t)m * m), *F = malloc(sizeof(cplx) * m);
+        cplx *S = malloc(sizeof(cplx) * (want_solve == 1 ? (size_t)m * m : 1)), *F = malloc(sizeof(cplx) * m);
         cplx *Nn = malloc(sizeof(cplx) * (size_t)(nch + 1) * m), *D = malloc(sizeof(cplx) * m);
         cplx *eeff = malloc(sizeof(cplx) * ns);
         if (!ob || !bm || !S || !F || !Nn || !D || !eeff) return ORC_E_NOMEM;
@@ -540,7 +541,7 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
          * N^n_k = <O_k^* B^n> - <O_k^*><B^n>  (definitions after Eq. 8) */
         for (int k = 0; k < m; ++k) {
             const cplx *ok = O + (size_t)k * ns;
-            for (int l = k; l < m; ++l) {   /* S is Hermitian by definition: fill l >= k, mirror */
+            for (int l = k; l < m && want_solve == 1; ++l) {   /* S is Hermitian by definition: fill l >= k, mirror */
                 const cplx *ol = O + (size_t)l * ns;
                 cplx v = 0.0;
                 for (int x = 0; x < ns; ++x) v += wgt[x] * conj(ok[x]) * ol[x];
@@ -572,7 +573,7 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
                         out->Nn[2 * ((size_t)c * m + k)] = creal(Nn[(size_t)c * m + k]);
                         out->Nn[2 * ((size_t)c * m + k) + 1] = cimag(Nn[(size_t)c * m + k]);
                     }
-                if (out->S)
+                if (out->S && want_solve == 1)
                     for (int l = 0; l < m; ++l) {
                         out->S[2 * ((size_t)k * m + l)] = creal(S[(size_t)k * m + l]);
                         out->S[2 * ((size_t)k * m + l) + 1] = cimag(S[(size_t)k * m + l]);
@@ -582,9 +583,11 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
                 for (int c = 0; c < nch; ++c) { out->bmean[2 * c] = creal(bm[c]); out->bmean[2 * c + 1] = cimag(bm[c]); }
         }
         /* regularised solve (S + eps I) delta = D */
-        for (int k = 0; k < m; ++k) S[(size_t)k * m + k] += cf->diag_shift;
-        status = chol_solve(m, S, D);
-        if (out && out->delta)
+        if (want_solve == 1) {
+            for (int k = 0; k < m; ++k) S[(size_t)k * m + k] += cf->diag_shift;
+            status = chol_solve(m, S, D);
+        }
+        if (out && out->delta && want_solve == 1)
             for (int k = 0; k < m; ++k) { out->delta[2 * k] = creal(D[k]); out->delta[2 * k + 1] = cimag(D[k]); }
         free(ob); free(bm); free(S); free(F); free(Nn); free(D); free(eeff);
     }

@@ -1,0 +1,97 @@
+// Device-side building blocks shared by the otVMC kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tvmc {
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+// two 32x32->64 multiplications with multipliers 0xD2511F53 / 0xCD9E8D57, key schedule
+// bumped by the Weyl constants 0x9E3779B9 / 0xBB67AE85.
+// Counter layout used by this library:
+//   Metropolis proposal p of chain c : (p, stage<<31 | c, step, 1<<24 | traj)
+//   Wiener increments, channel pair q: (q, 0, step, 2<<24 | traj)
+//   initial configuration of chain c : (0, c, 0, 3<<24 | traj)
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                              uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// 53-bit uniform in [0, 1) from the top 27 bits of a and the top 26 bits of b.
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double spin(uint64_t mask, int i) { return ((mask >> i) & 1ull) ? 1.0 : -1.0; }
+
+// Jastrow pair index of eta_{jk} (j < k) after the N one-body parameters.
+__host__ __device__ __forceinline__ int pair_index(int n, int j, int k) {
+    return n + j * n - j * (j + 1) / 2 + (k - j - 1);
+}
+
+// Everything a kernel may touch, as raw device pointers into the caller's workspace.
+struct Dev {
+    int n, m, nch, ns, nc, per, nt, nobs;
+    int burn, thin, init_sweeps, scheme, traj0;
+    uint32_t key0, key1;
+    double hx, dt, eps;
+    const double *J;          // [N*N]
+    const int *jkind;         // [nch]
+    const int *jsite;         // [nch]
+    const double *jrate;      // [nch]
+    const int *pa;            // [M] first site of O_k (k < N: the site itself)
+    const int *pb;            // [M] second site of O_k (-1 for one-body terms)
+    double2 *theta, *theta_eval, *d0, *d1;   // [T][M]
+    double *eta_re, *eta_im;  // [T][N*N] dense symmetric pair parameters of the evaluation point
+    double2 *epair;           // [T][2][N*N] exp(+-4 eta_jk) for two-flip ratios
+    uint64_t *chains;         // [T][C]
+    uint64_t *samples;        // [T][Ns]
+    uint32_t *sbits;          // [T][N][Ns/32] site-major bit planes of the samples
+    double2 *R;               // [T][Ns][N] single-flip ratios psi(s^(i))/psi(s)
+    double2 *eloc;            // [T][Ns] local energy of H
+    uint32_t *acc;            // [T][C]
+    double *dw;               // [T][nch]
+    double2 *bmean;           // [T][nch]
+    double2 *G;               // [T][Ns]
+    double2 *gbar;            // [T]
+    double *obar;             // [T][M]
+    double2 *D;               // [T][M]
+    double *S;                // [T][M][M]
+    double *mom_part;         // [T][mom_blocks][9]
+    double *mom;              // [T][9]
+    double *hist;             // [nobs][T][9]
+    double *ens;              // [16]
+    int *flags;               // [T]
+    int mom_blocks;
+};
+
+}  // namespace tvmc

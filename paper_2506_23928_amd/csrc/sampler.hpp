@@ -1,0 +1,158 @@
+// Metropolis sampling of |psi_theta|^2 for the two-body Jastrow ansatz (Eq. 12) and the
+// local quantities the estimators need (text after Eq. 9; definitions after Eq. 8).
+//
+// One wavefront per Markov chain; lane i owns spin i (N <= 64).  The configuration lives in a
+// wave-uniform 64-bit mask.  Lane i keeps the complex field f_i = a_i + sum_{k!=i} eta_ik s_k,
+// so the flip log-ratio of site i is -2 s_i f_i (O(1)); an accepted flip of site i updates
+// every lane's field with one row of eta, read from LDS (the dense symmetric eta of the
+// trajectory, staged once per workgroup and shared by its CPB chains).  Random numbers for
+// 64 consecutive proposals are drawn at once, one Philox block per lane, and read back with
+// readlane, so the sequential part of a proposal is a readlane, a compare and (on accept)
+// one LDS row.
+#pragma once
+#include "common.hpp"
+
+namespace tvmc {
+
+// theta (or theta_eval) -> dense symmetric eta, split into real / imaginary planes.
+__global__ void k_prepare_jastrow(Dev a, const double2 *__restrict__ src) {
+    const int t = blockIdx.y;
+    const int n = a.n, nn = n * n;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nn) return;
+    const int i = idx / n, k = idx % n;
+    double re = 0.0, im = 0.0;
+    if (i != k) {
+        const double2 v = src[(size_t)t * a.m + pair_index(n, i < k ? i : k, i < k ? k : i)];
+        re = v.x;
+        im = v.y;
+    }
+    a.eta_re[(size_t)t * nn + idx] = re;
+    a.eta_im[(size_t)t * nn + idx] = im;
+}
+
+// Uniformly random initial configurations (an exact sample of |psi|^2 at the +x state).
+__global__ void k_init_chains(Dev a) {
+    const int t = blockIdx.y;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.nc) return;
+    uint32_t r[4];
+    philox4x32_10(0u, (uint32_t)c, 0u, (3u << 24) | (uint32_t)(a.traj0 + t), a.key0, a.key1, r);
+    uint64_t m = (uint64_t)r[0] | ((uint64_t)r[1] << 32);
+    if (a.n < 64) m &= (1ull << a.n) - 1ull;
+    a.chains[(size_t)t * a.nc + c] = m;
+}
+
+// Real Gaussian Wiener increments dW ~ N(0, dt), Box-Muller on two 53-bit uniforms.
+__global__ void k_draw_dw(Dev a, int step) {
+    const int t = blockIdx.x;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int q = threadIdx.x; 2 * q < a.nch; q += blockDim.x) {
+        uint32_t r[4];
+        philox4x32_10((uint32_t)q, 0u, (uint32_t)step, (2u << 24) | (uint32_t)(a.traj0 + t), a.key0, a.key1, r);
+        const double u1 = u53(r[0], r[1]), u2 = u53(r[2], r[3]);
+        const double rad = sqrt(-2.0 * log(1.0 - u1));
+        double sn, cs;
+        sincos(two_pi * u2, &sn, &cs);
+        a.dw[(size_t)t * a.nch + 2 * q] = sqrt(a.dt) * (rad * cs);
+        if (2 * q + 1 < a.nch) a.dw[(size_t)t * a.nch + 2 * q + 1] = sqrt(a.dt) * (rad * sn);
+    }
+}
+
+template <int CPB>
+__global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, int stage, int burn) {
+    __shared__ double lre[64 * 64];
+    __shared__ double lim[64 * 64];
+    const int n = a.n;
+    const int t = blockIdx.y;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * CPB + w;
+    {
+        const double *er = a.eta_re + (size_t)t * n * n;
+        const double *ei = a.eta_im + (size_t)t * n * n;
+        for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+            lre[i] = er[i];
+            lim[i] = ei[i];
+        }
+    }
+    __syncthreads();
+    const bool act = lane < n;
+    const double2 *th = a.theta_eval + (size_t)t * a.m;
+    uint64_t mask = a.chains[(size_t)t * a.nc + c];
+
+    // fields in the order a_i, then k = 0..N-1 (each term is exact: s_k = +-1)
+    double fre = 0.0, fim = 0.0;
+    if (act) {
+        fre = th[lane].x;
+        fim = th[lane].y;
+        for (int k = 0; k < n; ++k) {
+            if (k == lane) continue;
+            const double sk = spin(mask, k);
+            fre += lre[k * n + lane] * sk;
+            fim += lim[k * n + lane] * sk;
+        }
+    }
+
+    const uint32_t ctr1 = ((uint32_t)stage << 31) | (uint32_t)c;
+    const uint32_t ctr3 = (1u << 24) | (uint32_t)(a.traj0 + t);
+    const int64_t total = (int64_t)(burn + a.per * a.thin) * n;
+    const int64_t first_rec = (int64_t)burn * n, rec_stride = (int64_t)a.thin * n;
+    int rec = 0;
+    uint32_t nacc = 0;
+    const size_t tbase = (size_t)t * a.ns;
+
+    for (int64_t base = 0; base < total; base += 64) {
+        uint32_t r[4];
+        philox4x32_10((uint32_t)(base + lane), ctr1, (uint32_t)step, ctr3, a.key0, a.key1, r);
+        const int site_l = (int)(((uint64_t)r[0] * (uint64_t)n) >> 32);
+        const double logu_l = log(u53(r[1], r[2]));
+        const int cnt = (int)((total - base) < 64 ? (total - base) : 64);
+        for (int j = 0; j < cnt; ++j) {
+            const int i = __builtin_amdgcn_readlane(site_l, j);
+            const double lu = readlane_d(logu_l, j);
+            const double fi = readlane_d(fre, i);
+            const double si = spin(mask, i);
+            const double dre = -2.0 * si * fi;
+            if (lu < 2.0 * dre) {
+                mask ^= (1ull << i);
+                const double c2 = -2.0 * si;
+                if (act) {
+                    fre += c2 * lre[i * n + lane];
+                    fim += c2 * lim[i * n + lane];
+                }
+                ++nacc;
+            }
+            const int64_t q = base + j;
+            if (q >= first_rec && ((q - first_rec + 1) % rec_stride) == 0) {
+                const size_t sidx = tbase + (size_t)c * a.per + rec;
+                ++rec;
+                double ere = 0.0, eim = 0.0;
+                if (act) {
+                    const double sl = spin(mask, lane);
+                    const double dr = -2.0 * sl * fre, di = -2.0 * sl * fim;
+                    const double ex = exp(dr);
+                    double sn, cs;
+                    sincos(di, &sn, &cs);
+                    const double2 R = make_double2(ex * cs, ex * sn);
+                    a.R[sidx * n + lane] = R;
+                    double hj = 0.0;
+                    for (int k = 0; k < n; ++k) hj += a.J[k * n + lane] * spin(mask, k);
+                    ere = 0.5 * sl * hj + a.hx * R.x;
+                    eim = a.hx * R.y;
+                }
+                ere = wave_sum(ere);
+                eim = wave_sum(eim);
+                if (lane == 0) {
+                    a.samples[sidx] = mask;
+                    a.eloc[sidx] = make_double2(ere, eim);
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        a.chains[(size_t)t * a.nc + c] = mask;
+        a.acc[(size_t)t * a.nc + c] = nacc;
+    }
+}
+
+}  // namespace tvmc

@@ -1,0 +1,76 @@
+// Assembly of S + eps I for the Jastrow ansatz (definition after Eq. 8, diagonal shift of the
+// regularised solve).  Every O_k is +-1 (s_i, or s_j s_k), so sum_s O_sk O_sl is an exact
+// integer in either variant below, and the centring S_kl = sum/N_s - <O_k><O_l> uses the same
+// separately rounded operations in both: they produce the same bits for any N_s (and S is
+// exact outright when N_s is a power of two).  Only the lower triangle (k >= l) is written;
+// the Cholesky factorisation reads nothing else.
+#pragma once
+#include "common.hpp"
+
+namespace tvmc {
+
+// sum/N_s - <O_k><O_l>, each product and the difference rounded separately (no fused
+// multiply-add), so the result does not depend on how the compiler contracts it.
+__device__ __forceinline__ double centre(double sum, double inv, double ok, double ol) {
+    return __dsub_rn(__dmul_rn(sum, inv), __dmul_rn(ok, ol));
+}
+
+__device__ __forceinline__ double o_value(uint64_t mk, int p, int q) {
+    const uint64_t par = (q < 0) ? (((mk >> p) & 1ull) ^ 1ull) : (((mk >> p) ^ (mk >> q)) & 1ull);
+    return par ? -1.0 : 1.0;   // par = 1 <=> O = -1
+}
+
+// Plain form: 64x64 tile per workgroup, 4x4 register tile per thread, FP64 FMAs.
+__global__ __launch_bounds__(256) void k_sbuild_f64(Dev a) {
+    __shared__ uint64_t smask[256];
+    const int t = blockIdx.y;
+    // lower-triangular tile index -> (bi, bj), bi >= bj
+    const int tile = blockIdx.x;
+    int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
+    while (bi * (bi + 1) / 2 > tile) --bi;
+    const int bj = tile - bi * (bi + 1) / 2;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    int rp[4], rq[4], cp[4], cq[4];
+    for (int u = 0; u < 4; ++u) {
+        const int k = bi * 64 + ty * 4 + u, l = bj * 64 + tx * 4 + u;
+        rp[u] = k < a.m ? a.pa[k] : 0;
+        rq[u] = k < a.m ? a.pb[k] : -1;
+        cp[u] = l < a.m ? a.pa[l] : 0;
+        cq[u] = l < a.m ? a.pb[l] : -1;
+    }
+    double acc[4][4] = {};
+    const uint64_t *smp = a.samples + (size_t)t * a.ns;
+    for (int s0 = 0; s0 < a.ns; s0 += 256) {
+        __syncthreads();
+        if (s0 + threadIdx.x < a.ns) smask[threadIdx.x] = smp[s0 + threadIdx.x];
+        __syncthreads();
+        const int cnt = (a.ns - s0) < 256 ? (a.ns - s0) : 256;
+        for (int s = 0; s < cnt; ++s) {
+            const uint64_t mk = smask[s];
+            double ov[4], cv[4];
+            for (int u = 0; u < 4; ++u) {
+                ov[u] = o_value(mk, rp[u], rq[u]);
+                cv[u] = o_value(mk, cp[u], cq[u]);
+            }
+            for (int u = 0; u < 4; ++u)
+                for (int v = 0; v < 4; ++v) acc[u][v] += ov[u] * cv[v];
+        }
+    }
+    const double inv = 1.0 / (double)a.ns;
+    const double *ob = a.obar + (size_t)t * a.m;
+    double *S = a.S + (size_t)t * a.m * a.m;
+    for (int u = 0; u < 4; ++u) {
+        const int k = bi * 64 + ty * 4 + u;
+        if (k >= a.m) continue;
+        for (int v = 0; v < 4; ++v) {
+            const int l = bj * 64 + tx * 4 + v;
+            if (l >= a.m || l > k) continue;
+            double sv = centre(acc[u][v], inv, ob[k], ob[l]);
+            if (k == l) sv = __dadd_rn(sv, a.eps);
+            S[(size_t)k * a.m + l] = sv;
+        }
+    }
+}
+
+}  // namespace tvmc

@@ -1,0 +1,638 @@
+// C ABI of the otVMC library (declarations and contracts in include/tvmc.h).
+// Host side: argument checks, the workspace layout, the stage machine of one SDE step, and
+// kernel launches on the caller's stream.  No device allocation happens here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tvmc.h"
+#include "cholesky.hpp"
+#include "common.hpp"
+#include "estimate.hpp"
+#include "observe.hpp"
+#include "sampler.hpp"
+#include "sbuild.hpp"
+#include "sbuild_mfma.hpp"
+
+using namespace tvmc;
+
+namespace {
+
+struct Timer {
+    std::vector<hipEvent_t> start, stop;
+    size_t used = 0;
+};
+
+}  // namespace
+
+struct tvmc_ctx {
+    Dev d{};
+    hipStream_t stream = nullptr;
+    tvmc_config cfg{};
+    int step = 0, stage = 0, phase = 0, nobs = 0;
+    int cpb = 1;
+    char err[512] = {0};
+    bool timing = false;
+    std::vector<std::string> groups;
+    std::vector<Timer> timers;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
+        bmean, G, gbar, obar, D, S, mom_part, mom, hist, ens, flags, total;
+};
+
+int mom_blocks_for(int ns) {
+    int b = (ns + MOM_WAVES - 1) / MOM_WAVES;
+    return b < 64 ? b : 64;
+}
+
+Layout layout(int n, int m, int nch, int T, int ns, int nc, int nobs) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + (bytes ? bytes : 1));
+        return at;
+    };
+    const size_t tt = (size_t)T;
+    L.J = take(sizeof(double) * n * n);
+    L.jk = take(sizeof(int) * (nch + 1));
+    L.js = take(sizeof(int) * (nch + 1));
+    L.jr = take(sizeof(double) * (nch + 1));
+    L.pa = take(sizeof(int) * m);
+    L.pb = take(sizeof(int) * m);
+    L.theta = take(sizeof(double2) * tt * m);
+    L.theta_eval = take(sizeof(double2) * tt * m);
+    L.d0 = take(sizeof(double2) * tt * m);
+    L.d1 = take(sizeof(double2) * tt * m);
+    L.eta_re = take(sizeof(double) * tt * n * n);
+    L.eta_im = take(sizeof(double) * tt * n * n);
+    L.epair = take(sizeof(double2) * tt * 2 * n * n);
+    L.chains = take(sizeof(uint64_t) * tt * nc);
+    L.samples = take(sizeof(uint64_t) * tt * ns);
+    L.sbits = take(sizeof(uint32_t) * tt * n * ((ns + 31) / 32));
+    L.R = take(sizeof(double2) * tt * ns * n);
+    L.eloc = take(sizeof(double2) * tt * ns);
+    L.acc = take(sizeof(uint32_t) * tt * nc);
+    L.dw = take(sizeof(double) * tt * (nch + 1));
+    L.bmean = take(sizeof(double2) * tt * (nch + 1));
+    L.G = take(sizeof(double2) * tt * ns);
+    L.gbar = take(sizeof(double2) * tt);
+    L.obar = take(sizeof(double) * tt * m);
+    L.D = take(sizeof(double2) * tt * m);
+    L.S = take(sizeof(double) * tt * m * m);
+    L.mom_part = take(sizeof(double) * tt * mom_blocks_for(ns) * 9);
+    L.mom = take(sizeof(double) * tt * 9);
+    L.hist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt * 9);
+    L.ens = take(sizeof(double) * 16);
+    L.flags = take(sizeof(int) * tt);
+    L.total = o;
+    return L;
+}
+
+void set_err(tvmc_ctx *c, const char *fmt, ...) {
+    if (!c) return;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+}
+
+thread_local char g_err[512];
+
+tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_config *c, char *msg, size_t len) {
+    if (!p || !a || !c) return snprintf(msg, len, "null argument"), TVMC_E_INVAL;
+    if (p->n_sites < 1 || p->n_sites > 64) return snprintf(msg, len, "n_sites must be in [1, 64]"), TVMC_E_INVAL;
+    if (!p->J) return snprintf(msg, len, "J is null"), TVMC_E_INVAL;
+    if (p->n_jumps < 0 || p->n_jumps > 256) return snprintf(msg, len, "n_jumps must be in [0, 256]"), TVMC_E_INVAL;
+    if (p->n_jumps > 0 && (!p->jump_kind || !p->jump_site || !p->jump_rate))
+        return snprintf(msg, len, "jump arrays are null"), TVMC_E_INVAL;
+    for (int i = 0; i < p->n_jumps; ++i) {
+        if (p->jump_kind[i] < 0 || p->jump_kind[i] > 2) return snprintf(msg, len, "bad jump kind"), TVMC_E_INVAL;
+        if (p->jump_site[i] < 0 || p->jump_site[i] >= p->n_sites) return snprintf(msg, len, "bad jump site"), TVMC_E_INVAL;
+        if (!(p->jump_rate[i] >= 0.0) || !std::isfinite(p->jump_rate[i]))
+            return snprintf(msg, len, "bad jump rate"), TVMC_E_INVAL;
+    }
+    for (int i = 0; i < p->n_sites * p->n_sites; ++i)
+        if (!std::isfinite(p->J[i])) return snprintf(msg, len, "J not finite"), TVMC_E_INVAL;
+    for (int i = 0; i < p->n_sites; ++i) {
+        if (p->J[i * p->n_sites + i] != 0.0) return snprintf(msg, len, "J diagonal must be zero"), TVMC_E_INVAL;
+        for (int j = 0; j < i; ++j)
+            if (p->J[i * p->n_sites + j] != p->J[j * p->n_sites + i])
+                return snprintf(msg, len, "J must be symmetric"), TVMC_E_INVAL;
+    }
+    if (a->kind != TVMC_ANSATZ_JASTROW)
+        return snprintf(msg, len, "only the Jastrow ansatz is implemented on this path"), TVMC_E_UNSUPPORTED;
+    if (c->n_traj < 1 || (int64_t)c->traj_offset + c->n_traj > (1 << 24) || c->traj_offset < 0)
+        return snprintf(msg, len, "trajectory ids must lie in [0, 2^24)"), TVMC_E_INVAL;
+    if (c->n_chains < 1 || c->n_samples < 1 || c->n_samples % c->n_chains)
+        return snprintf(msg, len, "n_samples must be a positive multiple of n_chains"), TVMC_E_INVAL;
+    if (c->n_chains >= 8 && c->n_chains % 8) return snprintf(msg, len, "n_chains must be < 8 or a multiple of 8"), TVMC_E_INVAL;
+    if (c->burn_sweeps < 0 || c->thin_sweeps < 1 || c->init_sweeps < 0)
+        return snprintf(msg, len, "bad sweep counts"), TVMC_E_INVAL;
+    if ((int64_t)(c->burn_sweeps + c->init_sweeps + (int64_t)(c->n_samples / c->n_chains) * c->thin_sweeps) * p->n_sites >=
+        ((int64_t)1 << 31))
+        return snprintf(msg, len, "too many proposals per evaluation"), TVMC_E_INVAL;
+    if (!(c->dt > 0.0) || !(c->diag_shift >= 0.0)) return snprintf(msg, len, "bad dt or diag_shift"), TVMC_E_INVAL;
+    if (c->scheme != 0 && c->scheme != 1) return snprintf(msg, len, "bad scheme"), TVMC_E_INVAL;
+    if (c->precision != 0 && c->precision != 1) return snprintf(msg, len, "bad precision"), TVMC_E_INVAL;
+    if (c->precision == TVMC_PREC_MFMA && c->n_samples % 64)
+        return snprintf(msg, len, "the MFMA S-build needs n_samples to be a multiple of 64"), TVMC_E_INVAL;
+    if (c->obs_every < 0 || c->n_obs_max < 0) return snprintf(msg, len, "bad observation settings"), TVMC_E_INVAL;
+    return TVMC_OK;
+}
+
+#define HIPCHECK(ctx, call)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            set_err(ctx, "%s failed: %s", #call, hipGetErrorString(e_));                 \
+            return TVMC_E_DEVICE;                                                        \
+        }                                                                                \
+    } while (0)
+
+#define LAUNCHCHECK(ctx, name)                                                           \
+    do {                                                                                 \
+        hipError_t e_ = hipGetLastError();                                               \
+        if (e_ != hipSuccess) {                                                          \
+            set_err(ctx, "launch of %s failed: %s", name, hipGetErrorString(e_));        \
+            return TVMC_E_DEVICE;                                                        \
+        }                                                                                \
+    } while (0)
+
+struct Scope {
+    tvmc_ctx *c;
+    int g = -1;
+    Scope(tvmc_ctx *ctx, const char *group) : c(ctx) {
+        if (!c->timing) return;
+        for (size_t i = 0; i < c->groups.size(); ++i)
+            if (c->groups[i] == group) g = (int)i;
+        if (g < 0) {
+            c->groups.push_back(group);
+            c->timers.emplace_back();
+            g = (int)c->groups.size() - 1;
+        }
+        Timer &tm = c->timers[g];
+        if (tm.used == tm.start.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+                g = -1;
+                return;
+            }
+            tm.start.push_back(a);
+            tm.stop.push_back(b);
+        }
+        (void)hipEventRecord(tm.start[tm.used], c->stream);
+    }
+    ~Scope() {
+        if (g < 0) return;
+        Timer &tm = c->timers[g];
+        (void)hipEventRecord(tm.stop[tm.used], c->stream);
+        ++tm.used;
+    }
+};
+
+tvmc_status run_sample(tvmc_ctx *c) {
+    Dev &d = c->d;
+    const int T = d.nt;
+    if (c->stage == 0) {
+        hipLaunchKernelGGL(k_draw_dw, dim3(T), dim3(64), 0, c->stream, d, c->step);
+        LAUNCHCHECK(c, "k_draw_dw");
+        HIPCHECK(c, hipMemcpyAsync(d.theta_eval, d.theta, sizeof(double2) * (size_t)T * d.m, hipMemcpyDeviceToDevice,
+                                   c->stream));
+    }
+    const int nn = d.n * d.n;
+    hipLaunchKernelGGL(k_prepare_jastrow, dim3((nn + 255) / 256, T), dim3(256), 0, c->stream, d,
+                       (const double2 *)d.theta_eval);
+    LAUNCHCHECK(c, "k_prepare_jastrow");
+    const int burn = d.burn + ((c->step == 0 && c->stage == 0) ? d.init_sweeps : 0);
+    {
+        Scope sc(c, "sample");
+        dim3 grid(d.nc / c->cpb, T);
+        switch (c->cpb) {
+        case 8: hipLaunchKernelGGL(k_sample_jastrow<8>, grid, dim3(512), 0, c->stream, d, c->step, c->stage, burn); break;
+        case 4: hipLaunchKernelGGL(k_sample_jastrow<4>, grid, dim3(256), 0, c->stream, d, c->step, c->stage, burn); break;
+        case 2: hipLaunchKernelGGL(k_sample_jastrow<2>, grid, dim3(128), 0, c->stream, d, c->step, c->stage, burn); break;
+        default: hipLaunchKernelGGL(k_sample_jastrow<1>, grid, dim3(64), 0, c->stream, d, c->step, c->stage, burn); break;
+        }
+        LAUNCHCHECK(c, "k_sample_jastrow");
+    }
+    c->phase = 1;
+    return TVMC_OK;
+}
+
+tvmc_status run_estimate(tvmc_ctx *c) {
+    Dev &d = c->d;
+    const int T = d.nt;
+    {
+        Scope sc(c, "estimate");
+        if (d.nch > 0) {
+            hipLaunchKernelGGL(k_channel_means, dim3(T), dim3(128), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_channel_means");
+        }
+        hipLaunchKernelGGL(k_build_G, dim3((d.ns + 255) / 256, T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_build_G");
+        hipLaunchKernelGGL(k_gbar, dim3(T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_gbar");
+        hipLaunchKernelGGL(k_obar_D, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_obar_D");
+    }
+    {
+        Scope sc(c, "sbuild");
+        if (c->cfg.precision == TVMC_PREC_MFMA) {
+            tvmc_status st = launch_sbuild_mfma(d, c->stream);
+            if (st != TVMC_OK) {
+                set_err(c, "launch of the int8 MFMA S-build failed");
+                return st;
+            }
+        } else {
+            const int nt = (d.m + 63) / 64;
+            hipLaunchKernelGGL(k_sbuild_f64, dim3(nt * (nt + 1) / 2, T), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_sbuild_f64");
+        }
+    }
+    c->phase = 2;
+    return TVMC_OK;
+}
+
+tvmc_status run_solve(tvmc_ctx *c) {
+    Dev &d = c->d;
+    {
+        Scope sc(c, "solve");
+        hipLaunchKernelGGL(k_chol_solve, dim3(d.nt), dim3(256), 0, c->stream, d, c->stage);
+        LAUNCHCHECK(c, "k_chol_solve");
+    }
+    c->phase = 3;
+    return TVMC_OK;
+}
+
+tvmc_status run_update(tvmc_ctx *c) {
+    Dev &d = c->d;
+    {
+        Scope sc(c, "update");
+        hipLaunchKernelGGL(k_update, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage);
+        LAUNCHCHECK(c, "k_update");
+    }
+    if (c->stage == 0) {
+        c->stage = 1;
+    } else {
+        c->stage = 0;
+        ++c->step;
+    }
+    c->phase = 0;
+    return TVMC_OK;
+}
+
+tvmc_status run_moments(tvmc_ctx *c, int slot) {
+    Dev &d = c->d;
+    const int T = d.nt, nn = d.n * d.n;
+    Scope sc(c, "observe");
+    hipLaunchKernelGGL(k_prepare_pairs, dim3((nn + 255) / 256, T), dim3(256), 0, c->stream, d);
+    LAUNCHCHECK(c, "k_prepare_pairs");
+    hipLaunchKernelGGL(k_moments, dim3(d.mom_blocks, T), dim3(64 * MOM_WAVES), 0, c->stream, d);
+    LAUNCHCHECK(c, "k_moments");
+    hipLaunchKernelGGL(k_moments_reduce, dim3((T + 127) / 128), dim3(128), 0, c->stream, d, slot);
+    LAUNCHCHECK(c, "k_moments_reduce");
+    return TVMC_OK;
+}
+
+size_t q_bytes(const tvmc_ctx *c, int what) {
+    const Dev &d = c->d;
+    switch (what) {
+    case TVMC_Q_THETA: case TVMC_Q_THETA_EVAL: case TVMC_Q_DELTA0: case TVMC_Q_DELTA1: case TVMC_Q_D:
+        return sizeof(double2) * d.m;
+    case TVMC_Q_SAMPLES: return sizeof(uint64_t) * d.ns;
+    case TVMC_Q_ELOC: return sizeof(double2) * d.ns;
+    case TVMC_Q_S: return sizeof(double) * (size_t)d.m * d.m;
+    case TVMC_Q_OBAR: return sizeof(double) * d.m;
+    case TVMC_Q_BMEAN: return sizeof(double2) * d.nch;
+    case TVMC_Q_DW: return sizeof(double) * d.nch;
+    case TVMC_Q_ACCEPTS: return sizeof(uint32_t) * d.nc;
+    case TVMC_Q_CHAINS: return sizeof(uint64_t) * d.nc;
+    case TVMC_Q_MOMENTS: return sizeof(double) * 9;
+    case TVMC_Q_OBS_HIST: return sizeof(double) * 9 * (size_t)d.nobs;
+    default: return 0;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+tvmc_status tvmc_workspace_size(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_config *c, size_t *bytes) {
+    tvmc_status st = check_args(p, a, c, g_err, sizeof(g_err));
+    if (st != TVMC_OK) return st;
+    if (!bytes) return TVMC_E_INVAL;
+    const int n = p->n_sites, m = n + n * (n - 1) / 2;
+    *bytes = layout(n, m, p->n_jumps, c->n_traj, c->n_samples, c->n_chains, c->n_obs_max).total;
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_config *c, const double *theta0,
+                      void *ws, size_t ws_bytes, void *stream, tvmc_ctx **out) {
+    if (!out) return TVMC_E_INVAL;
+    *out = nullptr;
+    tvmc_status st = check_args(p, a, c, g_err, sizeof(g_err));
+    if (st != TVMC_OK) return st;
+    const int n = p->n_sites, m = n + n * (n - 1) / 2, nch = p->n_jumps, T = c->n_traj;
+    const Layout L = layout(n, m, nch, T, c->n_samples, c->n_chains, c->n_obs_max);
+    if (!ws) return snprintf(g_err, sizeof(g_err), "workspace is null"), TVMC_E_INVAL;
+    if (ws_bytes < L.total) return snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu", ws_bytes, L.total), TVMC_E_NOMEM;
+    if ((uintptr_t)ws % 256) return snprintf(g_err, sizeof(g_err), "workspace must be 256-byte aligned"), TVMC_E_INVAL;
+
+    tvmc_ctx *ctx = new (std::nothrow) tvmc_ctx();
+    if (!ctx) return TVMC_E_NOMEM;
+    ctx->stream = (hipStream_t)stream;
+    ctx->cfg = *c;
+    ctx->cpb = c->n_chains % 8 == 0 ? 8 : (c->n_chains % 4 == 0 ? 4 : (c->n_chains % 2 == 0 ? 2 : 1));
+    char *base = (char *)ws;
+    Dev &d = ctx->d;
+    d.n = n;
+    d.m = m;
+    d.nch = nch;
+    d.ns = c->n_samples;
+    d.nc = c->n_chains;
+    d.per = c->n_samples / c->n_chains;
+    d.nt = T;
+    d.nobs = c->n_obs_max;
+    d.burn = c->burn_sweeps;
+    d.thin = c->thin_sweeps;
+    d.init_sweeps = c->init_sweeps;
+    d.scheme = c->scheme;
+    d.traj0 = c->traj_offset;
+    d.key0 = (uint32_t)c->seed;
+    d.key1 = (uint32_t)(c->seed >> 32);
+    d.hx = p->hx;
+    d.dt = c->dt;
+    d.eps = c->diag_shift;
+    d.mom_blocks = mom_blocks_for(c->n_samples);
+    d.J = (const double *)(base + L.J);
+    d.jkind = (const int *)(base + L.jk);
+    d.jsite = (const int *)(base + L.js);
+    d.jrate = (const double *)(base + L.jr);
+    d.pa = (const int *)(base + L.pa);
+    d.pb = (const int *)(base + L.pb);
+    d.theta = (double2 *)(base + L.theta);
+    d.theta_eval = (double2 *)(base + L.theta_eval);
+    d.d0 = (double2 *)(base + L.d0);
+    d.d1 = (double2 *)(base + L.d1);
+    d.eta_re = (double *)(base + L.eta_re);
+    d.eta_im = (double *)(base + L.eta_im);
+    d.epair = (double2 *)(base + L.epair);
+    d.chains = (uint64_t *)(base + L.chains);
+    d.samples = (uint64_t *)(base + L.samples);
+    d.sbits = (uint32_t *)(base + L.sbits);
+    d.R = (double2 *)(base + L.R);
+    d.eloc = (double2 *)(base + L.eloc);
+    d.acc = (uint32_t *)(base + L.acc);
+    d.dw = (double *)(base + L.dw);
+    d.bmean = (double2 *)(base + L.bmean);
+    d.G = (double2 *)(base + L.G);
+    d.gbar = (double2 *)(base + L.gbar);
+    d.obar = (double *)(base + L.obar);
+    d.D = (double2 *)(base + L.D);
+    d.S = (double *)(base + L.S);
+    d.mom_part = (double *)(base + L.mom_part);
+    d.mom = (double *)(base + L.mom);
+    d.hist = (double *)(base + L.hist);
+    d.ens = (double *)(base + L.ens);
+    d.flags = (int *)(base + L.flags);
+
+    std::vector<int> pa(m), pb(m);
+    for (int i = 0; i < n; ++i) {
+        pa[i] = i;
+        pb[i] = -1;
+    }
+    for (int j = 0; j < n; ++j)
+        for (int k = j + 1; k < n; ++k) {
+            pa[pair_index(n, j, k)] = j;
+            pb[pair_index(n, j, k)] = k;
+        }
+    std::vector<double2> th((size_t)T * m);
+    for (int t = 0; t < T; ++t)
+        for (int k = 0; k < m; ++k)
+            th[(size_t)t * m + k] = theta0 ? make_double2(theta0[2 * k], theta0[2 * k + 1]) : make_double2(0.0, 0.0);
+    auto fail = [&](tvmc_status s) {
+        snprintf(g_err, sizeof(g_err), "%s", ctx->err);
+        delete ctx;
+        return s;
+    };
+#define INITCHECK(call)                                                                    \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            set_err(ctx, "%s failed: %s", #call, hipGetErrorString(e_));                   \
+            return fail(TVMC_E_DEVICE);                                                    \
+        }                                                                                  \
+    } while (0)
+    INITCHECK(hipMemcpyAsync((void *)d.J, p->J, sizeof(double) * n * n, hipMemcpyHostToDevice, ctx->stream));
+    if (nch > 0) {
+        INITCHECK(hipMemcpyAsync((void *)d.jkind, p->jump_kind, sizeof(int) * nch, hipMemcpyHostToDevice, ctx->stream));
+        INITCHECK(hipMemcpyAsync((void *)d.jsite, p->jump_site, sizeof(int) * nch, hipMemcpyHostToDevice, ctx->stream));
+        INITCHECK(hipMemcpyAsync((void *)d.jrate, p->jump_rate, sizeof(double) * nch, hipMemcpyHostToDevice, ctx->stream));
+    }
+    INITCHECK(hipMemcpyAsync((void *)d.pa, pa.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
+    INITCHECK(hipMemcpyAsync((void *)d.pb, pb.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
+    INITCHECK(hipMemcpyAsync(d.theta, th.data(), sizeof(double2) * th.size(), hipMemcpyHostToDevice, ctx->stream));
+    INITCHECK(hipMemsetAsync(d.flags, 0, sizeof(int) * T, ctx->stream));
+    INITCHECK(hipMemsetAsync(d.d0, 0, sizeof(double2) * (size_t)T * m, ctx->stream));
+    INITCHECK(hipMemsetAsync(d.d1, 0, sizeof(double2) * (size_t)T * m, ctx->stream));
+    hipLaunchKernelGGL(k_init_chains, dim3((c->n_chains + 63) / 64, T), dim3(64), 0, ctx->stream, d);
+    INITCHECK(hipGetLastError());
+    INITCHECK(hipStreamSynchronize(ctx->stream));
+#undef INITCHECK
+    *out = ctx;
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_sample(tvmc_ctx *c) {
+    if (!c) return TVMC_E_INVAL;
+    if (c->phase != 0) return set_err(c, "tvmc_sample: the previous evaluation was not completed"), TVMC_E_STATE;
+    return run_sample(c);
+}
+
+tvmc_status tvmc_estimate(tvmc_ctx *c) {
+    if (!c) return TVMC_E_INVAL;
+    if (c->phase != 1) return set_err(c, "tvmc_estimate: call tvmc_sample first"), TVMC_E_STATE;
+    return run_estimate(c);
+}
+
+tvmc_status tvmc_sr_solve(tvmc_ctx *c) {
+    if (!c) return TVMC_E_INVAL;
+    if (c->phase != 2) return set_err(c, "tvmc_sr_solve: call tvmc_estimate first"), TVMC_E_STATE;
+    return run_solve(c);
+}
+
+tvmc_status tvmc_update(tvmc_ctx *c) {
+    if (!c) return TVMC_E_INVAL;
+    if (c->phase != 3) return set_err(c, "tvmc_update: call tvmc_sr_solve first"), TVMC_E_STATE;
+    return run_update(c);
+}
+
+tvmc_status tvmc_sde_step(tvmc_ctx *c, int32_t n_steps) {
+    if (!c || n_steps < 0) return TVMC_E_INVAL;
+    if (c->phase != 0 || c->stage != 0) return set_err(c, "tvmc_sde_step: a step is half done"), TVMC_E_STATE;
+    for (int s = 0; s < n_steps; ++s) {
+        for (int stage = 0; stage < 2; ++stage) {
+            tvmc_status st = run_sample(c);
+            if (st != TVMC_OK) return st;
+            if (stage == 0 && c->cfg.obs_every > 0 && c->step % c->cfg.obs_every == 0 && c->nobs < c->d.nobs) {
+                st = run_moments(c, c->nobs++);
+                if (st != TVMC_OK) return st;
+            }
+            if ((st = run_estimate(c)) != TVMC_OK) return st;
+            if ((st = run_solve(c)) != TVMC_OK) return st;
+            if ((st = run_update(c)) != TVMC_OK) return st;
+        }
+    }
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_observables(tvmc_ctx *c, double *out) {
+    if (!c) return TVMC_E_INVAL;
+    if (c->phase < 1) return set_err(c, "tvmc_observables: no samples at the current evaluation point"), TVMC_E_STATE;
+    tvmc_status st = run_moments(c, -1);
+    if (st != TVMC_OK) return st;
+    if (out) {
+        HIPCHECK(c, hipMemcpyAsync(out, c->d.mom, sizeof(double) * 9 * c->d.nt, hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+    }
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_ensemble(tvmc_ctx *c, double *out) {
+    if (!c || !out) return TVMC_E_INVAL;
+    hipLaunchKernelGGL(k_ensemble, dim3(1), dim3(64), 0, c->stream, c->d);
+    LAUNCHCHECK(c, "k_ensemble");
+    HIPCHECK(c, hipMemcpyAsync(out, c->d.ens, sizeof(double) * 13, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_get(tvmc_ctx *c, int32_t what, int32_t traj, void *host, size_t bytes) {
+    if (!c || !host) return TVMC_E_INVAL;
+    const Dev &d = c->d;
+    if (traj < 0 || traj >= d.nt) return set_err(c, "tvmc_get: trajectory out of range"), TVMC_E_INVAL;
+    const size_t nb = q_bytes(c, what);
+    if (nb == 0) return set_err(c, "tvmc_get: unknown quantity %d", what), TVMC_E_INVAL;
+    if (bytes < nb) return set_err(c, "tvmc_get: buffer too small (%zu < %zu)", bytes, nb), TVMC_E_INVAL;
+    const size_t t = (size_t)traj;
+    const void *src = nullptr;
+    switch (what) {
+    case TVMC_Q_THETA: src = d.theta + t * d.m; break;
+    case TVMC_Q_THETA_EVAL: src = d.theta_eval + t * d.m; break;
+    case TVMC_Q_DELTA0: src = d.d0 + t * d.m; break;
+    case TVMC_Q_DELTA1: src = d.d1 + t * d.m; break;
+    case TVMC_Q_SAMPLES: src = d.samples + t * d.ns; break;
+    case TVMC_Q_ELOC: src = d.eloc + t * d.ns; break;
+    case TVMC_Q_S: src = d.S + t * d.m * d.m; break;
+    case TVMC_Q_D: src = d.D + t * d.m; break;
+    case TVMC_Q_OBAR: src = d.obar + t * d.m; break;
+    case TVMC_Q_BMEAN: src = d.bmean + t * d.nch; break;
+    case TVMC_Q_DW: src = d.dw + t * d.nch; break;
+    case TVMC_Q_ACCEPTS: src = d.acc + t * d.nc; break;
+    case TVMC_Q_CHAINS: src = d.chains + t * d.nc; break;
+    case TVMC_Q_MOMENTS: src = d.mom + t * 9; break;
+    default: break;
+    }
+    if (what == TVMC_Q_OBS_HIST) {
+        for (int s = 0; s < d.nobs; ++s)
+            HIPCHECK(c, hipMemcpyAsync((double *)host + 9 * s, d.hist + ((size_t)s * d.nt + t) * 9, sizeof(double) * 9,
+                                       hipMemcpyDeviceToHost, c->stream));
+    } else if (nb > 0) {
+        HIPCHECK(c, hipMemcpyAsync(host, src, nb, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_set(tvmc_ctx *c, int32_t what, int32_t traj, const void *host, size_t bytes) {
+    if (!c || !host) return TVMC_E_INVAL;
+    const Dev &d = c->d;
+    if (traj < 0 || traj >= d.nt) return set_err(c, "tvmc_set: trajectory out of range"), TVMC_E_INVAL;
+    if (what != TVMC_Q_THETA && what != TVMC_Q_CHAINS) return set_err(c, "tvmc_set: only theta and chains"), TVMC_E_INVAL;
+    const size_t nb = q_bytes(c, what);
+    if (bytes < nb) return set_err(c, "tvmc_set: buffer too small"), TVMC_E_INVAL;
+    void *dst = what == TVMC_Q_THETA ? (void *)(d.theta + (size_t)traj * d.m) : (void *)(d.chains + (size_t)traj * d.nc);
+    if (what == TVMC_Q_CHAINS && d.n < 64)
+        for (int i = 0; i < d.nc; ++i)
+            if (((const uint64_t *)host)[i] >> d.n) return set_err(c, "tvmc_set: chain word has bits above N"), TVMC_E_INVAL;
+    if (what == TVMC_Q_THETA)
+        for (size_t i = 0; i < 2 * (size_t)d.m; ++i)
+            if (!std::isfinite(((const double *)host)[i])) return set_err(c, "tvmc_set: theta not finite"), TVMC_E_INVAL;
+    HIPCHECK(c, hipMemcpyAsync(dst, host, nb, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_position(const tvmc_ctx *c, int32_t *step, int32_t *stage) {
+    if (!c || !step || !stage) return TVMC_E_INVAL;
+    *step = c->step;
+    *stage = c->stage;
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_synchronize(tvmc_ctx *c) {
+    if (!c) return TVMC_E_INVAL;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    std::vector<int> f(c->d.nt);
+    HIPCHECK(c, hipMemcpy(f.data(), c->d.flags, sizeof(int) * f.size(), hipMemcpyDeviceToHost));
+    for (int t = 0; t < c->d.nt; ++t)
+        if (f[t]) {
+            set_err(c, "trajectory %d: non-positive pivot or non-finite increment", c->d.traj0 + t);
+            return TVMC_E_NUMERIC;
+        }
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_set_timing(tvmc_ctx *c, int32_t enable) {
+    if (!c) return TVMC_E_INVAL;
+    c->timing = enable != 0;
+    for (auto &t : c->timers) t.used = 0;
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_timing(tvmc_ctx *c, const char *group, double *avg_ms, int32_t *count) {
+    if (!c || !group || !avg_ms || !count) return TVMC_E_INVAL;
+    *avg_ms = 0.0;
+    *count = 0;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    for (size_t g = 0; g < c->groups.size(); ++g) {
+        if (c->groups[g] != group) continue;
+        Timer &tm = c->timers[g];
+        double tot = 0.0;
+        for (size_t i = 0; i < tm.used; ++i) {
+            float ms = 0.f;
+            HIPCHECK(c, hipEventElapsedTime(&ms, tm.start[i], tm.stop[i]));
+            tot += ms;
+        }
+        *count = (int32_t)tm.used;
+        *avg_ms = tm.used ? tot / tm.used : 0.0;
+    }
+    return TVMC_OK;
+}
+
+const char *tvmc_last_error(const tvmc_ctx *c) { return c ? c->err : g_err; }
+
+tvmc_status tvmc_destroy(tvmc_ctx *c) {
+    if (!c) return TVMC_E_INVAL;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &t : c->timers) {
+        for (auto e : t.start) (void)hipEventDestroy(e);
+        for (auto e : t.stop) (void)hipEventDestroy(e);
+    }
+    delete c;
+    return TVMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+"""Python binding of libtvmc (include/tvmc.h): argument marshalling only.
+
+Every step of the path runs in the HIP kernels of ``csrc/``; PyTorch only provides the device
+workspace and the stream.  The binding refuses to run without the built library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtvmc.so")
+
+TVMC_OK, TVMC_E_INVAL, TVMC_E_NOMEM, TVMC_E_DEVICE, TVMC_E_NUMERIC, TVMC_E_STATE, TVMC_E_UNSUPPORTED = range(7)
+SIGMA_MINUS, SIGMA_PLUS, SIGMA_Z = 0, 1, 2
+JASTROW, RBM = 0, 1
+HEUN, MIDPOINT = 0, 1
+PREC_FP64, PREC_MFMA = 0, 1
+(Q_THETA, Q_THETA_EVAL, Q_DELTA0, Q_DELTA1, Q_SAMPLES, Q_ELOC, Q_S, Q_D, Q_OBAR, Q_BMEAN, Q_DW, Q_ACCEPTS,
+ Q_CHAINS, Q_MOMENTS, Q_OBS_HIST) = range(15)
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class tvmc_problem(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("J", _dp), ("hx", ctypes.c_double), ("n_jumps", ctypes.c_int32),
+                ("jump_kind", _i32p), ("jump_site", _i32p), ("jump_rate", _dp)]
+
+
+class tvmc_ansatz(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_hidden", ctypes.c_int32)]
+
+
+class tvmc_config(ctypes.Structure):
+    _fields_ = [("n_traj", ctypes.c_int32), ("traj_offset", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+                ("n_chains", ctypes.c_int32), ("burn_sweeps", ctypes.c_int32), ("thin_sweeps", ctypes.c_int32),
+                ("init_sweeps", ctypes.c_int32), ("scheme", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("diag_shift", ctypes.c_double), ("precision", ctypes.c_int32), ("obs_every", ctypes.c_int32),
+                ("n_obs_max", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class TvmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("tvmc status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+EXPORTED = ["tvmc_workspace_size", "tvmc_init", "tvmc_sample", "tvmc_estimate", "tvmc_sr_solve", "tvmc_update",
+            "tvmc_sde_step", "tvmc_observables", "tvmc_ensemble", "tvmc_get", "tvmc_set", "tvmc_position",
+            "tvmc_synchronize", "tvmc_set_timing", "tvmc_timing", "tvmc_last_error", "tvmc_destroy"]
+
+
+def lib():
+    """Load libtvmc.so; raise if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libtvmc.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.tvmc_last_error.restype = ctypes.c_char_p
+        L.tvmc_last_error.argtypes = [ctypes.c_void_p]
+        for name in EXPORTED:
+            if name != "tvmc_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st, ctx=None):
+    if st != TVMC_OK:
+        msg = lib().tvmc_last_error(ctx).decode(errors="replace")
+        raise TvmcError(st, msg)
+
+
+class Problem:
+    """H = sum_{i<j} J_ij sz_i sz_j + hx sum_i sx_i; jumps = [(kind, site, rate), ...]."""
+
+    def __init__(self, J, hx, jumps):
+        self.J = np.ascontiguousarray(J, dtype=np.float64)
+        self.n = self.J.shape[0]
+        self.hx = float(hx)
+        self.jumps = [tuple(j) for j in jumps]
+        self.kind = np.ascontiguousarray([j[0] for j in jumps] or [0], dtype=np.int32)
+        self.site = np.ascontiguousarray([j[1] for j in jumps] or [0], dtype=np.int32)
+        self.rate = np.ascontiguousarray([j[2] for j in jumps] or [0.0], dtype=np.float64)
+
+    def c(self):
+        return tvmc_problem(self.n, self.J.ctypes.data_as(_dp), self.hx, len(self.jumps),
+                            self.kind.ctypes.data_as(_i32p), self.site.ctypes.data_as(_i32p),
+                            self.rate.ctypes.data_as(_dp))
+
+
+def n_params(kind: int, n: int, n_hidden: int = 0) -> int:
+    return n + n * (n - 1) // 2 if kind == JASTROW else n + n_hidden + n * n_hidden
+
+
+def make_config(n_traj, n_samples, n_chains, dt, diag_shift=1e-4, burn_sweeps=2, thin_sweeps=1, init_sweeps=0,
+                scheme=HEUN, precision=PREC_FP64, obs_every=0, n_obs_max=0, seed=0, traj_offset=0):
+    return tvmc_config(n_traj, traj_offset, n_samples, n_chains, burn_sweeps, thin_sweeps, init_sweeps, scheme, dt,
+                       diag_shift, precision, obs_every, n_obs_max, ctypes.c_uint64(seed))
+
+
+# ---------------------------------------------------------------- functions named as in the C ABI
+def tvmc_workspace_size(problem: Problem, ansatz: tvmc_ansatz, config: tvmc_config) -> int:
+    b = ctypes.c_size_t(0)
+    pc = problem.c()
+    _check(lib().tvmc_workspace_size(ctypes.byref(pc), ctypes.byref(ansatz), ctypes.byref(config), ctypes.byref(b)))
+    return b.value
+
+
+def tvmc_init(problem, ansatz, config, theta0, workspace_ptr, workspace_bytes, stream):
+    ctx = ctypes.c_void_p()
+    pc = problem.c()
+    th = None
+    if theta0 is not None:
+        th = np.ascontiguousarray(np.asarray(theta0, dtype=np.complex128)).view(np.float64)
+    _check(lib().tvmc_init(ctypes.byref(pc), ctypes.byref(ansatz), ctypes.byref(config),
+                           th.ctypes.data_as(_dp) if th is not None else None, ctypes.c_void_p(workspace_ptr),
+                           ctypes.c_size_t(workspace_bytes), ctypes.c_void_p(stream), ctypes.byref(ctx)))
+    return ctx
+
+
+def tvmc_sample(ctx):
+    _check(lib().tvmc_sample(ctx), ctx)
+
+
+def tvmc_estimate(ctx):
+    _check(lib().tvmc_estimate(ctx), ctx)
+
+
+def tvmc_sr_solve(ctx):
+    _check(lib().tvmc_sr_solve(ctx), ctx)
+
+
+def tvmc_update(ctx):
+    _check(lib().tvmc_update(ctx), ctx)
+
+
+def tvmc_sde_step(ctx, n_steps: int):
+    _check(lib().tvmc_sde_step(ctx, ctypes.c_int32(n_steps)), ctx)
+
+
+def tvmc_observables(ctx, n_traj: int, copy=True):
+    out = np.zeros((n_traj, 9)) if copy else None
+    _check(lib().tvmc_observables(ctx, out.ctypes.data_as(_dp) if copy else None), ctx)
+    return out
+
+
+def tvmc_ensemble(ctx):
+    out = np.zeros(13)
+    _check(lib().tvmc_ensemble(ctx, out.ctypes.data_as(_dp)), ctx)
+    return out[0:3], out[3:12].reshape(3, 3), float(out[12])
+
+
+def tvmc_synchronize(ctx):
+    _check(lib().tvmc_synchronize(ctx), ctx)
+
+
+def tvmc_destroy(ctx):
+    _check(lib().tvmc_destroy(ctx))
+
+
+class Context:
+    """One batch of trajectories of one problem, with its workspace held as a torch tensor."""
+
+    _shapes = {Q_THETA: ("c", "m"), Q_THETA_EVAL: ("c", "m"), Q_DELTA0: ("c", "m"), Q_DELTA1: ("c", "m"),
+               Q_SAMPLES: ("u8", "ns"), Q_ELOC: ("c", "ns"), Q_S: ("d", "mm"), Q_D: ("c", "m"), Q_OBAR: ("d", "m"),
+               Q_BMEAN: ("c", "nch"), Q_DW: ("d", "nch"), Q_ACCEPTS: ("u4", "nc"), Q_CHAINS: ("u8", "nc"),
+               Q_MOMENTS: ("d", "9"), Q_OBS_HIST: ("d", "hist")}
+
+    def __init__(self, problem: Problem, config: tvmc_config, kind=JASTROW, n_hidden=0, theta0=None, device="cuda",
+                 stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required")
+        self.problem = problem
+        self.config = config
+        self.ansatz = tvmc_ansatz(kind, n_hidden)
+        self.m = n_params(kind, problem.n, n_hidden)
+        nbytes = tvmc_workspace_size(problem, self.ansatz, config)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        ptr = self.workspace.data_ptr()
+        ptr += (-ptr) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device=self.workspace.device)
+        self.ctx = tvmc_init(problem, self.ansatz, config, theta0, ptr, nbytes, self.stream.cuda_stream)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            lib().tvmc_destroy(ctx)
+            self.ctx = None
+
+    # stage calls
+    def sample(self):
+        tvmc_sample(self.ctx)
+
+    def estimate(self):
+        tvmc_estimate(self.ctx)
+
+    def sr_solve(self):
+        tvmc_sr_solve(self.ctx)
+
+    def update(self):
+        tvmc_update(self.ctx)
+
+    def sde_step(self, n_steps=1):
+        tvmc_sde_step(self.ctx, n_steps)
+
+    def observables(self):
+        return tvmc_observables(self.ctx, self.config.n_traj)
+
+    def ensemble(self):
+        return tvmc_ensemble(self.ctx)
+
+    def synchronize(self):
+        tvmc_synchronize(self.ctx)
+
+    def position(self):
+        s, g = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().tvmc_position(self.ctx, ctypes.byref(s), ctypes.byref(g)), self.ctx)
+        return s.value, g.value
+
+    def set_timing(self, on=True):
+        _check(lib().tvmc_set_timing(self.ctx, ctypes.c_int32(int(on))), self.ctx)
+
+    def timing(self, group):
+        ms, cnt = ctypes.c_double(), ctypes.c_int32()
+        _check(lib().tvmc_timing(self.ctx, group.encode(), ctypes.byref(ms), ctypes.byref(cnt)), self.ctx)
+        return ms.value, cnt.value
+
+    def _count(self, key):
+        c = self.config
+        return {"m": self.m, "ns": c.n_samples, "mm": self.m * self.m, "nch": len(self.problem.jumps),
+                "nc": c.n_chains, "9": 9, "hist": 9 * c.n_obs_max}[key]
+
+    def get(self, what, traj=0):
+        dt, key = self._shapes[what]
+        cnt = self._count(key)
+        np_dt = {"c": np.complex128, "d": np.float64, "u8": np.uint64, "u4": np.uint32}[dt]
+        out = np.zeros(max(cnt, 1), dtype=np_dt)
+        _check(lib().tvmc_get(self.ctx, ctypes.c_int32(what), ctypes.c_int32(traj), out.ctypes.data_as(ctypes.c_void_p),
+                              ctypes.c_size_t(out.nbytes)), self.ctx)
+        out = out[:cnt]
+        if what == Q_S:
+            out = out.reshape(self.m, self.m)
+        if what == Q_OBS_HIST:
+            out = out.reshape(-1, 9)
+        return out
+
+    def set(self, what, traj, values):
+        np_dt = np.complex128 if what == Q_THETA else np.uint64
+        arr = np.ascontiguousarray(np.asarray(values, dtype=np_dt))
+        _check(lib().tvmc_set(self.ctx, ctypes.c_int32(what), ctypes.c_int32(traj), arr.ctypes.data_as(ctypes.c_void_p),
+                              ctypes.c_size_t(arr.nbytes)), self.ctx)
+
+
+def unpack_samples(words: np.ndarray, n: int) -> np.ndarray:
+    """uint64 configuration words -> int8 spins (+1 where the bit is set)."""
+    bits = (np.asarray(words, dtype=np.uint64)[:, None] >> np.arange(n, dtype=np.uint64)[None, :]) & np.uint64(1)
+    return np.where(bits == 1, 1, -1).astype(np.int8)

@@ -1,0 +1,64 @@
+"""The C-ABI library loads on the CPU and exports every entry point include/tvmc.h declares
+(no compute calls: there may be no GPU here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tvmc.h")
+LIB = os.path.join(ROOT, "paper_2506_23928_amd", "libtvmc.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:tvmc_status|const char \*)\s*(tvmc_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_stage_calls():
+    names = _declared()
+    for n in ("tvmc_init", "tvmc_sample", "tvmc_estimate", "tvmc_sr_solve", "tvmc_sde_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first (__graft_entry__.build())"
+    lib = ctypes.CDLL(LIB)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (tvmc_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_binding_names_match_the_header():
+    from paper_2506_23928_amd import tvmc
+    assert sorted(tvmc.EXPORTED) == _declared()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    from paper_2506_23928_amd import tvmc
+    prog = tmp_path / "layout.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tvmc.h"\nint main(){'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tvmc_problem), offsetof(tvmc_problem, jump_rate),'
+                    'sizeof(tvmc_config), offsetof(tvmc_config, dt), offsetof(tvmc_config, precision),'
+                    'offsetof(tvmc_config, seed), sizeof(tvmc_ansatz)); return 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(prog)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    P, C, A = tvmc.tvmc_problem, tvmc.tvmc_config, tvmc.tvmc_ansatz
+    want = [ctypes.sizeof(P), P.jump_rate.offset, ctypes.sizeof(C), C.dt.offset, C.precision.offset, C.seed.offset,
+            ctypes.sizeof(A)]
+    assert got == want
+
+
+def test_product_couplings_match_the_definition():
+    # the library's host-side problem builder against brute-force sums (Eq. 10, Kac factor)
+    import numpy as np
+    from paper_2506_23928_amd.problem import kac_couplings
+    n, alpha = 9, 1.5
+    J = kac_couplings("obc", n, alpha)
+    kac = sum(abs(i - j) ** -alpha for i in range(n) for j in range(i + 1, n)) / (n - 1)
+    assert abs(J[0, 3] - 3 ** -alpha / kac) < 1e-14 and J[4, 4] == 0.0
+    Jp = kac_couplings("pbc", 10, 1.0)
+    assert abs(Jp[0, 9] - Jp[0, 1]) < 1e-15 and abs(Jp[0, 5] / Jp[0, 1] - 0.2) < 1e-14

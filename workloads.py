@@ -1,0 +1,65 @@
+"""Seeded synthetic workloads shaped like the paper's quenches (inputs only).
+
+This module holds no arithmetic of the method: it names the problem parameters (geometry,
+system size, power-law exponent, field, dissipation rates), the sampler and integrator
+settings, and draws the random initial parameters that a workload starts from.  Both the GPU
+library and the CPU oracle receive these inputs and build everything else themselves.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SIGMA_MINUS, SIGMA_PLUS, SIGMA_Z = 0, 1, 2
+
+# Quench workloads: a +x coherent spin state evolved under the dissipative long-range Ising
+# model.  Fields: geometry, n (spins), alpha, jscale (J), h (transverse field), decay and
+# dephasing rates per site, ansatz, samples per evaluation, chains, trajectories, dt, t_end,
+# diagonal shift, observation interval (steps), seed.
+WORKLOADS = {
+    # plain FP64 check: 1D open chain N=8, Jastrow (36 parameters), 32 trajectories
+    "chain8_fp64": dict(geom="obc", n=8, alpha=1.5, jscale=1.0, h=1.0, decay=0.1, dephase=0.0, ansatz="jastrow",
+                        n_samples=1024, n_chains=16, n_traj=32, dt=0.01, t_end=1.0, diag_shift=1e-4, obs_every=10,
+                        burn_sweeps=2, thin_sweeps=1, seed=0),
+    # N=64 open chain, decay + dephasing (128 jump channels), Jastrow with 2080 parameters
+    "chain64_jastrow": dict(geom="obc", n=64, alpha=1.5, jscale=1.0, h=0.5, decay=0.05, dephase=0.02,
+                            ansatz="jastrow", n_samples=4096, n_chains=64, n_traj=256, dt=0.005, t_end=2.0,
+                            diag_shift=1e-4, obs_every=20, burn_sweeps=2, thin_sweeps=1, seed=0),
+    # N=64 open chain at h = 0, where the site-resolved closed form of App. D is exact
+    "chain64_jastrow_h0": dict(geom="obc", n=64, alpha=1.5, jscale=1.0, h=0.0, decay=0.1, dephase=0.0,
+                               ansatz="jastrow", n_samples=4096, n_chains=64, n_traj=256, dt=0.005, t_end=1.0,
+                               diag_shift=1e-4, obs_every=20, burn_sweeps=2, thin_sweeps=1, seed=1),
+}
+
+
+def jumps(w: dict):
+    """Local decay sqrt(gamma) sigma^- (and dephasing sqrt(gamma_phi) sigma^z) on every site."""
+    out = []
+    if w["decay"] > 0:
+        out += [(SIGMA_MINUS, i, w["decay"]) for i in range(w["n"])]
+    if w["dephase"] > 0:
+        out += [(SIGMA_Z, i, w["dephase"]) for i in range(w["n"])]
+    return out
+
+
+def n_steps(w: dict) -> int:
+    return int(round(w["t_end"] / w["dt"]))
+
+
+def random_theta(m: int, scale: float, seed: int) -> np.ndarray:
+    """Complex parameters scale*(z1 + i z2), z standard normal (seeded)."""
+    rng = np.random.default_rng(seed)
+    return scale * (rng.standard_normal(m) + 1j * rng.standard_normal(m))
+
+
+def random_problem(n: int, seed: int, n_extra: int = 3):
+    """A small random LITF-like problem for parity tests: random symmetric couplings, random
+    field, decay on every site plus a few sigma^z / sigma^+ channels on random sites."""
+    rng = np.random.default_rng(seed)
+    J = rng.standard_normal((n, n)) * 0.4
+    J = np.triu(J, 1)
+    J = J + J.T
+    hx = float(rng.uniform(0.2, 1.2))
+    js = [(SIGMA_MINUS, i, float(rng.uniform(0.02, 0.3))) for i in range(n)]
+    for _ in range(n_extra):
+        js.append((int(rng.choice([SIGMA_PLUS, SIGMA_Z])), int(rng.integers(n)), float(rng.uniform(0.01, 0.1))))
+    return J, hx, js
