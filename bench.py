@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput of trajectory-unravelled tVMC on one MI355X.
+
+A step is one Heun step of every trajectory of the workload: noise, then for the predictor and
+the corrector Metropolis sampling, local estimators, D, S + eps I, the FP64 Cholesky solve and
+the update; moments of the collective spin are recorded every `obs_every` steps from the
+predictor samples, as in a production run.  value = trajectory-steps per second with every
+input already resident in HBM.
+
+Extra objects on the JSON line:
+  roofline      the dominant kernel's algorithmic work per launch over its average launch time
+                (HIP events on the library's stream inside the timed region) against the peak
+                of the unit it runs on;
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload, on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published dense peaks
+    "fp64": 78.6,            # TFLOP/s, vector and matrix
+    "int8": 5000.0,          # TOP/s, matrix cores
+    "hbm": 8000.0,           # GB/s
+}
+
+
+def kernel_sources_sha() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2506_23928_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str):
+    """HBM bytes per launch from profiles/hbm_traffic_<kernel>.txt, if it was measured on the
+    current kernel sources (key=value lines written from rocprofv3 --pmc runs)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s.txt" % kernel)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != kernel_sources_sha():
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_context(tv, w, precision, n_traj=None, traj_offset=0):
+    from paper_2506_23928_amd.problem import kac_couplings
+    import workloads as wl
+    J = kac_couplings(w["geom"], w["n"], w["alpha"], w["jscale"])
+    prob = tv.Problem(J, w["h"], wl.jumps(w))
+    steps = wl.n_steps(w)
+    cfg = tv.make_config(n_traj or w["n_traj"], w["n_samples"], w["n_chains"], w["dt"], w["diag_shift"],
+                         w["burn_sweeps"], w["thin_sweeps"], 0, tv.HEUN, precision, w["obs_every"],
+                         steps // w["obs_every"] + 2, w["seed"], traj_offset)
+    return tv.Context(prob, cfg)
+
+
+def cpu_baseline(w, budget_s=30.0):
+    """The oracle as it stands on a bounded sample: P host threads, each running one predictor
+    evaluation of its own trajectory (sampling, estimators, S, F, N^n, D, Cholesky solve); one
+    trajectory-step is two evaluations."""
+    import numpy as np
+    import oracle as orc
+    import workloads as wl
+    cores = min(os.cpu_count() or 1, 16)
+    J = orc.couplings(w["geom"], w["n"], w["alpha"], w["jscale"])
+    pb = orc.Problem(J, w["h"], wl.jumps(w))
+    m = orc.n_params(0, w["n"])
+    cfg = orc.Config(n_samples=w["n_samples"], n_chains=w["n_chains"], burn_sweeps=w["burn_sweeps"],
+                     thin_sweeps=w["thin_sweeps"], dt=w["dt"], diag_shift=w["diag_shift"], seed=w["seed"])
+    done = []
+
+    def work(traj):
+        ch = orc.init_chains(w["seed"], traj, w["n"], w["n_chains"])
+        dw = orc.draw_dw(w["seed"], traj, 0, len(wl.jumps(w)), w["dt"])
+        r = orc.evaluate(pb, 0, 0, cfg, np.zeros(m), ch, traj=traj, first=True, dw=dw, want_moments=False)
+        done.append(r["status"])
+
+    t0 = time.perf_counter()
+    ths = [threading.Thread(target=work, args=(t,)) for t in range(cores)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    el = time.perf_counter() - t0
+    return {"value": (len(done) / 2.0) / el, "unit": "trajectory-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "%d trajectories x 1 predictor evaluation (half a Heun step) of %s, one per host thread, "
+                      "%.1f s wall" % (cores, w["name"], el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="chain64_jastrow")
+    ap.add_argument("--precision", choices=["mfma", "fp64"], default="mfma")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (trajectories shard across GPUs by design, "
+              "but no multi-GPU path is built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2506_23928_amd as tv
+    import workloads as wl
+    w = dict(wl.WORKLOADS[args.workload])
+    w["name"] = args.workload
+    prec = tv.PREC_MFMA if args.precision == "mfma" else tv.PREC_FP64
+    n, m, T = w["n"], tv.n_params(tv.JASTROW, w["n"]), w["n_traj"]
+    print("bench: workload %s N=%d M=%d trajectories=%d samples=%d chains=%d jumps=%d precision=%s" % (
+        args.workload, n, m, T, w["n_samples"], w["n_chains"], len(wl.jumps(w)), args.precision), file=sys.stderr,
+        flush=True)
+
+    ctx = build_context(tv, w, prec)
+    for _ in range(args.warmup):
+        ctx.sde_step(1)
+    ctx.synchronize()
+    print("bench: warmup done", file=sys.stderr, flush=True)
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.sde_step(1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.synchronize()
+    groups = {}
+    for g in ("sample", "estimate", "transpose", "sbuild", "solve", "update", "observe"):
+        ms, cnt = ctx.timing(g)
+        if cnt:
+            groups[g] = {"avg_ms": ms, "launches": cnt, "total_ms": ms * cnt}
+    ctx.set_timing(False)
+    value = T * args.steps / el
+    print("bench: %d steps in %.3f s -> %.1f trajectory-steps/s" % (args.steps, el, value), file=sys.stderr,
+          flush=True)
+
+    # dominant kernel: the FP64 Cholesky solve (one launch covers every trajectory)
+    dom = max(groups, key=lambda g: groups[g]["total_ms"])
+    if dom == "solve":
+        flops = T * (m ** 3 / 3.0 + m * m / 2.0 + m / 6.0 + 4.0 * m * m)
+        achieved = flops / (groups["solve"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_chol_solve", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_chol_solve")}
+    elif dom == "sbuild":
+        ops = T * (m * (m + 1) / 2.0) * w["n_samples"] * 2.0
+        achieved = ops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_sbuild_i8", "bound": "mfma", "achieved": achieved, "peak": PEAKS["int8"],
+                "unit": "TOP/s", "frac": achieved / PEAKS["int8"], "traffic": read_traffic("k_sbuild_i8")}
+    else:
+        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None}
+    del ctx
+    torch.cuda.empty_cache()
+
+    plain = None
+    if not args.no_plain:
+        # the plain form: FP64 S-build, one trajectory per launch
+        pctx = build_context(tv, w, tv.PREC_FP64, n_traj=1)
+        pctx.sde_step(1)
+        pctx.synchronize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pctx.sde_step(2)
+        torch.cuda.synchronize()
+        plain = 2.0 / (time.perf_counter() - t1)
+        del pctx
+        torch.cuda.empty_cache()
+        print("bench: plain form (FP64 S, one trajectory per launch) %.3f trajectory-steps/s" % plain,
+              file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w)
+
+    out = {
+        "metric": "trajectory-steps/s at N=64 (batched+learned vs plain) at fixed xi^2 error",
+        "value": value, "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "n_spins": n, "n_params": m, "n_traj": T, "n_samples": w["n_samples"],
+                   "n_chains": w["n_chains"], "n_jumps": len(wl.jumps(w)), "dt": w["dt"], "ansatz": "jastrow",
+                   "s_build": "int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU",
+                   "solve": "FP64 Cholesky", "obs_every": w["obs_every"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "plain_form_value": plain,
+        "kernel_ms": {g: round(v["avg_ms"], 4) for g, v in groups.items()},
+        "kernel_sources_sha": kernel_sources_sha(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

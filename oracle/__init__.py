@@ -190,7 +190,7 @@ class Config:
 
 
 def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, chains, traj=0, step=0, stage=0,
-             first=True, dw=None, want_solve=True):
+             first=True, dw=None, want_solve=True, want_moments=True):
     """One evaluation of Eq. 8's right-hand side at theta; returns a dict of every quantity.
 
     ``chains`` (int8 [n_chains, N]) is advanced in place, as the sampler would.  want_solve:
@@ -214,7 +214,8 @@ def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, cha
                   _p(r["S"].view(np.float64), _c_dp), _p(r["F"].view(np.float64), _c_dp),
                   _p(r["Nn"].view(np.float64), _c_dp), _p(r["D"].view(np.float64), _c_dp),
                   _p(r["bmean"].view(np.float64), _c_dp), _p(r["obar"].view(np.float64), _c_dp),
-                  _p(r["delta"].view(np.float64), _c_dp), _p(r["accepts"], _c_i64p), _p(r["obs"], _c_dp))
+                  _p(r["delta"].view(np.float64), _c_dp), _p(r["accepts"], _c_i64p),
+                  _p(r["obs"], _c_dp) if want_moments else None)
     ch = chains if chains is not None else np.zeros((1, n), np.int8)
     assert ch.dtype == np.int8 and ch.flags.c_contiguous
     pc = problem._c()

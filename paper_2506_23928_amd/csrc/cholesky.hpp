@@ -1,177 +1,226 @@
 // Regularised solve (S + eps I) delta = D in FP64 (the solve of the paragraph after Eq. 9).
 //
-// One workgroup per trajectory factors its own matrix: left-looking blocked Cholesky with
-// NB-column panels.  Panel j is first updated with the already-factored columns (a GEMM
-// staged through LDS), then its diagonal block is factored in LDS and the rows below are
-// solved against it.  The forward substitution L y = D runs panel by panel alongside the
-// factorisation (column-oriented), the backward substitution L^T x = y afterwards.
+// One workgroup (4 waves) per trajectory factors its own matrix, left-looking, in panels of
+// CN = 64 columns, on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+//   for each panel j and each chunk of CR = 128 rows at or below it:
+//     C = A[rows, panel] - L[rows, 0:j] L[panel, 0:j]^T       (MFMA, operands staged in LDS
+//                                                              with the next chunk prefetched)
+//     first chunk: factor the 64x64 diagonal block in LDS and invert it (Linv);
+//     rows below:  L[rows, panel] = C Linv^T                  (MFMA)
+// The forward substitution L y = D rides along panel by panel; the backward substitution
+// L^T x = y afterwards reads L once more and reuses the stored block inverses.
 // The real factor of the Jastrow S is applied to the real and imaginary parts of D.
 #pragma once
 #include "common.hpp"
 
 namespace tvmc {
 
-constexpr int CH_NB = 32;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int CN = 64;        // panel width
+constexpr int CR = 128;       // rows per chunk (4 waves x 32 rows)
+constexpr int CK = 16;        // k-slice staged through LDS
+constexpr int CSP = CN + 1;   // padded LDS row of Cs / Ls
+constexpr int CKP = CK + 1;   // padded LDS row of As / Bs
+
+__host__ __device__ inline int chol_panels(int m) { return (m + CN - 1) / CN; }
 
 __global__ __launch_bounds__(256) void k_chol_solve(Dev a, int which) {
-    __shared__ double As[64][CH_NB + 1];
-    __shared__ double Bs[CH_NB][CH_NB + 1];
-    __shared__ double Ld[CH_NB][CH_NB + 1];
-    __shared__ double yre[CH_NB], yim[CH_NB];
-    __shared__ double red[32][2 * CH_NB + 1];
+    __shared__ double Cs[CR * CSP];
+    __shared__ double Ls[CN * CSP];
+    __shared__ double As[CR * CKP];
+    __shared__ double Bs[CN * CKP];
+    __shared__ double yre[CN], yim[CN];
     __shared__ int bad;
-    const int t = blockIdx.x, tid = threadIdx.x;
+    const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
     const int M = a.m;
     double *A = a.S + (size_t)t * M * M;
+    double *linv = a.linv + (size_t)t * chol_panels(M) * CN * CN;
     double2 *z = (which ? a.d1 : a.d0) + (size_t)t * M;
     const double2 *Dv = a.D + (size_t)t * M;
     if (tid == 0) bad = 0;
     for (int i = tid; i < M; i += 256) z[i] = Dv[i];
     __syncthreads();
 
-    for (int j0 = 0; j0 < M; j0 += CH_NB) {
-        const int jb = (M - j0) < CH_NB ? (M - j0) : CH_NB;
-        // 1. panel update: A[j0:M, j0:j0+jb] -= L[j0:M, 0:j0] L[j0:j0+jb, 0:j0]^T
-        if (j0 > 0) {
-            const int ty = tid >> 3, tx = tid & 7;
-            for (int r0 = j0; r0 < M; r0 += 64) {
-                double acc[2][4] = {};
-                for (int k0 = 0; k0 < j0; k0 += CH_NB) {
-                    for (int e = tid; e < 64 * CH_NB; e += 256) {
-                        const int rr = e / CH_NB, kk = e % CH_NB;
-                        As[rr][kk] = (r0 + rr < M) ? A[(size_t)(r0 + rr) * M + k0 + kk] : 0.0;
+    for (int j0 = 0, p = 0; j0 < M; j0 += CN, ++p) {
+        const int jb = (M - j0) < CN ? (M - j0) : CN;
+        for (int r0 = j0; r0 < M; r0 += CR) {
+            v4d acc[2][4];
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 4; ++v) acc[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
+            // ---- C = A - L[rows, 0:j0] L[panel, 0:j0]^T
+            if (j0 > 0) {
+                double pa[CR * CK / 256], pb[CN * CK / 256];
+                auto fetch = [&](int kc) {
+                    for (int q = 0; q < CR * CK / 256; ++q) {
+                        const int e = tid + 256 * q, rr = e / CK, kk = e % CK;
+                        pa[q] = (r0 + rr < M) ? A[(size_t)(r0 + rr) * M + kc + kk] : 0.0;
                     }
-                    for (int e = tid; e < CH_NB * CH_NB; e += 256) {
-                        const int cc = e / CH_NB, kk = e % CH_NB;
-                        Bs[cc][kk] = (cc < jb) ? A[(size_t)(j0 + cc) * M + k0 + kk] : 0.0;
+                    for (int q = 0; q < CN * CK / 256; ++q) {
+                        const int e = tid + 256 * q, cc = e / CK, kk = e % CK;
+                        pb[q] = (cc < jb) ? A[(size_t)(j0 + cc) * M + kc + kk] : 0.0;
+                    }
+                };
+                fetch(0);
+                for (int kc = 0; kc < j0; kc += CK) {
+                    __syncthreads();
+                    for (int q = 0; q < CR * CK / 256; ++q) {
+                        const int e = tid + 256 * q;
+                        As[(e / CK) * CKP + e % CK] = pa[q];
+                    }
+                    for (int q = 0; q < CN * CK / 256; ++q) {
+                        const int e = tid + 256 * q;
+                        Bs[(e / CK) * CKP + e % CK] = pb[q];
                     }
                     __syncthreads();
-                    for (int kk = 0; kk < CH_NB; ++kk) {
-                        const double a0 = As[2 * ty][kk], a1 = As[2 * ty + 1][kk];
-                        for (int q = 0; q < 4; ++q) {
-                            const double b = Bs[4 * tx + q][kk];
-                            acc[0][q] += a0 * b;
-                            acc[1][q] += a1 * b;
+                    if (kc + CK < j0) fetch(kc + CK);
+                    for (int ks = 0; ks < CK / 4; ++ks) {
+                        double fa[2], fb[4];
+                        for (int u = 0; u < 2; ++u) fa[u] = As[(wave * 32 + u * 16 + li) * CKP + ks * 4 + lk];
+                        for (int v = 0; v < 4; ++v) fb[v] = Bs[(v * 16 + li) * CKP + ks * 4 + lk];
+                        for (int u = 0; u < 2; ++u)
+                            for (int v = 0; v < 4; ++v)
+                                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[v], acc[u][v], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+            // FP64 accumulator layout: register r of lane (lk, li) holds row lk + 4r, column li
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 4; ++v)
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
+                        const double orig = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : 0.0;
+                        Cs[row * CSP + col] = orig - acc[u][v][r];
+                    }
+            __syncthreads();
+            int rstart = 0;
+            if (r0 == j0) {
+                // ---- factor the diagonal block in LDS (right-looking, column by column)
+                for (int c = 0; c < jb; ++c) {
+                    if (tid == 0) {
+                        const double d = Cs[c * CSP + c];
+                        if (!(d > 0.0)) bad = 1;
+                        Cs[c * CSP + c] = sqrt(d);
+                    }
+                    __syncthreads();
+                    for (int r = c + 1 + tid; r < jb; r += 256) Cs[r * CSP + c] /= Cs[c * CSP + c];
+                    __syncthreads();
+                    const int nr = jb - c - 1;
+                    for (int e = tid; e < nr * nr; e += 256) {
+                        const int r = c + 1 + e / nr, k = c + 1 + e % nr;
+                        if (k <= r) Cs[r * CSP + k] -= Cs[r * CSP + c] * Cs[k * CSP + c];
+                    }
+                    __syncthreads();
+                }
+                for (int e = tid; e < jb * jb; e += 256) {
+                    const int r = e / jb, c = e % jb;
+                    if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
+                }
+                // ---- Linv: column c of the inverse of the lower-triangular block, by thread c
+                if (tid < CN) {
+                    const int c = tid;
+                    for (int r = 0; r < CN; ++r) Ls[r * CSP + c] = 0.0;
+                    if (c < jb) {
+                        Ls[c * CSP + c] = 1.0 / Cs[c * CSP + c];
+                        for (int r = c + 1; r < jb; ++r) {
+                            double s = 0.0;
+                            for (int k = c; k < r; ++k) s += Cs[r * CSP + k] * Ls[k * CSP + c];
+                            Ls[r * CSP + c] = -s / Cs[r * CSP + r];
                         }
                     }
-                    __syncthreads();
                 }
-                for (int u = 0; u < 2; ++u) {
-                    const int r = r0 + 2 * ty + u;
-                    if (r >= M) continue;
-                    for (int q = 0; q < 4; ++q) {
-                        const int cc = 4 * tx + q;
-                        if (cc < jb) A[(size_t)r * M + j0 + cc] -= acc[u][q];
+                __syncthreads();
+                // ---- forward substitution of this panel: y = Linv z_panel
+                if (tid < jb) {
+                    double sr = 0.0, si = 0.0;
+                    for (int k = 0; k <= tid; ++k) {
+                        const double l = Ls[tid * CSP + k];
+                        const double2 zk = z[j0 + k];
+                        sr += l * zk.x;
+                        si += l * zk.y;
                     }
+                    yre[tid] = sr;
+                    yim[tid] = si;
+                } else if (tid < CN) {
+                    yre[tid] = 0.0;
+                    yim[tid] = 0.0;
                 }
+                for (int e = tid; e < CN * CN; e += 256) linv[(size_t)p * CN * CN + e] = Ls[(e / CN) * CSP + e % CN];
+                __syncthreads();
+                if (tid < jb) z[j0 + tid] = make_double2(yre[tid], yim[tid]);
+                rstart = CN;
+            }
+            // ---- rows below the diagonal block: X = C Linv^T (B[k][j] = Linv[j][k])
+            v4d x[2][4];
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 4; ++v) x[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int ks = 0; ks < CN / 4; ++ks) {
+                double fa[2], fb[4];
+                for (int u = 0; u < 2; ++u) fa[u] = Cs[(wave * 32 + u * 16 + li) * CSP + ks * 4 + lk];
+                for (int v = 0; v < 4; ++v) fb[v] = Ls[(v * 16 + li) * CSP + ks * 4 + lk];
+                for (int u = 0; u < 2; ++u)
+                    for (int v = 0; v < 4; ++v) x[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[v], x[u][v], 0, 0, 0);
             }
             __syncthreads();
-        }
-        // 2. factor the diagonal block in LDS
-        for (int e = tid; e < CH_NB * CH_NB; e += 256) {
-            const int r = e / CH_NB, cc = e % CH_NB;
-            Ld[r][cc] = (r < jb && cc <= r) ? A[(size_t)(j0 + r) * M + j0 + cc] : 0.0;
-        }
-        __syncthreads();
-        for (int cc = 0; cc < jb; ++cc) {
-            if (tid == 0) {
-                const double d = Ld[cc][cc];
-                if (!(d > 0.0)) bad = 1;
-                Ld[cc][cc] = sqrt(d);
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 4; ++v)
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
+                        if (row >= rstart) Cs[row * CSP + col] = x[u][v][r];
+                    }
+            __syncthreads();
+            const int nrows = (M - r0) < CR ? (M - r0) : CR;
+            for (int e = tid; e < (nrows - rstart) * jb; e += 256) {
+                const int rr = rstart + e / jb, c = e % jb;
+                A[(size_t)(r0 + rr) * M + j0 + c] = Cs[rr * CSP + c];
             }
-            __syncthreads();
-            for (int r = cc + 1 + tid; r < jb; r += 256) Ld[r][cc] /= Ld[cc][cc];
-            __syncthreads();
-            for (int e = tid; e < CH_NB * CH_NB; e += 256) {
-                const int r = e / CH_NB, k = e % CH_NB;
-                if (k > cc && r >= k && r < jb) Ld[r][k] -= Ld[r][cc] * Ld[k][cc];
-            }
-            __syncthreads();
-        }
-        for (int e = tid; e < CH_NB * CH_NB; e += 256) {
-            const int r = e / CH_NB, cc = e % CH_NB;
-            if (r < jb && cc <= r) A[(size_t)(j0 + r) * M + j0 + cc] = Ld[r][cc];
-        }
-        // forward substitution for this block: y_j = L_jj^{-1} z_j
-        if (tid == 0) {
-            for (int r = 0; r < jb; ++r) {
-                double vr = z[j0 + r].x, vi = z[j0 + r].y;
-                for (int k = 0; k < r; ++k) {
-                    vr -= Ld[r][k] * yre[k];
-                    vi -= Ld[r][k] * yim[k];
+            for (int rr = rstart + tid; rr < nrows; rr += 256) {
+                double2 zr = z[r0 + rr];
+                for (int c = 0; c < jb; ++c) {
+                    const double xv = Cs[rr * CSP + c];
+                    zr.x -= xv * yre[c];
+                    zr.y -= xv * yim[c];
                 }
-                yre[r] = vr / Ld[r][r];
-                yim[r] = vi / Ld[r][r];
-                z[j0 + r] = make_double2(yre[r], yim[r]);
+                z[r0 + rr] = zr;
             }
+            __syncthreads();
         }
-        __syncthreads();
-        // 3. rows below: L[r, panel] = A[r, panel] L_jj^{-T}; z_r -= L[r, panel] y_j
-        for (int r = j0 + jb + tid; r < M; r += 256) {
-            double x[CH_NB];
-            for (int cc = 0; cc < jb; ++cc) x[cc] = A[(size_t)r * M + j0 + cc];
-            double zr = z[r].x, zi = z[r].y;
-            for (int cc = 0; cc < jb; ++cc) {
-                double v = x[cc];
-                for (int k = 0; k < cc; ++k) v -= x[k] * Ld[cc][k];
-                x[cc] = v / Ld[cc][cc];
-                A[(size_t)r * M + j0 + cc] = x[cc];
-                zr -= x[cc] * yre[cc];
-                zi -= x[cc] * yim[cc];
-            }
-            z[r] = make_double2(zr, zi);
-        }
-        __syncthreads();
     }
 
-    // backward substitution L^T x = y (z holds y; overwritten by x from the last block up)
-    const int nblk = (M + CH_NB - 1) / CH_NB;
-    for (int b = nblk - 1; b >= 0; --b) {
-        const int j0 = b * CH_NB;
-        const int jb = (M - j0) < CH_NB ? (M - j0) : CH_NB;
-        const int cg = tid & 7, rl = tid >> 3;   // 8 column groups of 4, 32 row lanes
-        double pr[4] = {}, pi[4] = {};
-        for (int r = j0 + jb + rl; r < M; r += 32) {
+    // ---- backward substitution L^T x = y, last panel first; wave w owns 16 panel columns
+    for (int p = chol_panels(M) - 1; p >= 0; --p) {
+        const int j0 = p * CN, jb = (M - j0) < CN ? (M - j0) : CN;
+        double sr[16], si[16];
+        for (int q = 0; q < 16; ++q) sr[q] = si[q] = 0.0;
+        for (int r = j0 + jb + lane; r < M; r += 64) {
             const double2 xr = z[r];
-            for (int q = 0; q < 4; ++q) {
-                const int cc = 4 * cg + q;
-                if (cc < jb) {
-                    const double l = A[(size_t)r * M + j0 + cc];
-                    pr[q] += l * xr.x;
-                    pi[q] += l * xr.y;
-                }
+            const double *row = A + (size_t)r * M + j0 + wave * 16;
+            for (int q = 0; q < 16; ++q) {
+                const double l = (wave * 16 + q < jb) ? row[q] : 0.0;
+                sr[q] += l * xr.x;
+                si[q] += l * xr.y;
             }
         }
-        for (int q = 0; q < 4; ++q) {
-            red[rl][2 * (4 * cg + q)] = pr[q];
-            red[rl][2 * (4 * cg + q) + 1] = pi[q];
-        }
-        for (int e = tid; e < CH_NB * CH_NB; e += 256) {
-            const int r = e / CH_NB, cc = e % CH_NB;
-            Ld[r][cc] = (r < jb && cc <= r) ? A[(size_t)(j0 + r) * M + j0 + cc] : 0.0;
+        for (int q = 0; q < 16; ++q) {
+            const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
+            if (lane == 0) {
+                const int c = wave * 16 + q;
+                yre[c] = c < jb ? z[j0 + c].x - tr : 0.0;
+                yim[c] = c < jb ? z[j0 + c].y - ti : 0.0;
+            }
         }
         __syncthreads();
-        if (tid < jb) {
-            double sr = 0.0, si = 0.0;
-            for (int l = 0; l < 32; ++l) {
-                sr += red[l][2 * tid];
-                si += red[l][2 * tid + 1];
+        if (tid < jb) {   // x_c = sum_{k >= c} Linv[k][c] w_k
+            const double *lv = linv + (size_t)p * CN * CN;
+            double xr = 0.0, xi = 0.0;
+            for (int k = tid; k < jb; ++k) {
+                const double l = lv[k * CN + tid];
+                xr += l * yre[k];
+                xi += l * yim[k];
             }
-            yre[tid] = z[j0 + tid].x - sr;
-            yim[tid] = z[j0 + tid].y - si;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int cc = jb - 1; cc >= 0; --cc) {
-                double vr = yre[cc], vi = yim[cc];
-                for (int k = cc + 1; k < jb; ++k) {
-                    vr -= Ld[k][cc] * yre[k];
-                    vi -= Ld[k][cc] * yim[k];
-                }
-                yre[cc] = vr / Ld[cc][cc];
-                yim[cc] = vi / Ld[cc][cc];
-                z[j0 + cc] = make_double2(yre[cc], yim[cc]);
-            }
+            z[j0 + tid] = make_double2(xr, xi);
         }
         __syncthreads();
     }

@@ -86,6 +86,7 @@ struct Dev {
     double *obar;             // [T][M]
     double2 *D;               // [T][M]
     double *S;                // [T][M][M]
+    double *linv;             // [T][panels][64*64] inverses of the Cholesky diagonal blocks
     double *mom_part;         // [T][mom_blocks][9]
     double *mom;              // [T][9]
     double *hist;             // [nobs][T][9]

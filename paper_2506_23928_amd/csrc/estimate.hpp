@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_obar_D(Dev a) {
         }
     }
     const double inv = 1.0 / (double)a.ns;
-    const double ob = __dmul_rn((double)cnt, inv);
+    const double ob = (double)cnt * inv;
     const double2 gb = a.gbar[t];
     a.obar[(size_t)t * a.m + k] = ob;
     a.D[(size_t)t * a.m + k] = make_double2(re * inv - ob * gb.x, im * inv - ob * gb.y);

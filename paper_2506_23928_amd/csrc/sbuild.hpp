@@ -12,7 +12,15 @@ namespace tvmc {
 // sum/N_s - <O_k><O_l>, each product and the difference rounded separately (no fused
 // multiply-add), so the result does not depend on how the compiler contracts it.
 __device__ __forceinline__ double centre(double sum, double inv, double ok, double ol) {
-    return __dsub_rn(__dmul_rn(sum, inv), __dmul_rn(ok, ol));
+#pragma clang fp contract(off)
+    const double a = sum * inv;
+    const double b = ok * ol;
+    return a - b;
+}
+
+__device__ __forceinline__ double add_shift(double v, double eps) {
+#pragma clang fp contract(off)
+    return v + eps;
 }
 
 __device__ __forceinline__ double o_value(uint64_t mk, int p, int q) {
@@ -67,7 +75,7 @@ __global__ __launch_bounds__(256) void k_sbuild_f64(Dev a) {
             const int l = bj * 64 + tx * 4 + v;
             if (l >= a.m || l > k) continue;
             double sv = centre(acc[u][v], inv, ob[k], ob[l]);
-            if (k == l) sv = __dadd_rn(sv, a.eps);
+            if (k == l) sv = add_shift(sv, a.eps);
             S[(size_t)k * a.m + l] = sv;
         }
     }

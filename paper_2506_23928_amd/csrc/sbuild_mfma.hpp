@@ -93,14 +93,17 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
                 const int l = bj * SB_TILE + wc * 64 + v * 16 + (lane & 15);
                 if (k >= a.m || l >= a.m || l > k) continue;
                 double sv = centre((double)acc[u][v][r], inv, ob[k], ob[l]);
-                if (k == l) sv = __dadd_rn(sv, a.eps);
+                if (k == l) sv = add_shift(sv, a.eps);
                 S[(size_t)k * a.m + l] = sv;
             }
 }
 
-inline tvmc_status launch_sbuild_mfma(const Dev &d, hipStream_t st) {
+inline tvmc_status launch_transpose_bits(const Dev &d, hipStream_t st) {
     hipLaunchKernelGGL(k_transpose_bits, dim3(d.ns / 32, d.nt), dim3(64), 0, st, d);
-    if (hipGetLastError() != hipSuccess) return TVMC_E_DEVICE;
+    return hipGetLastError() == hipSuccess ? TVMC_OK : TVMC_E_DEVICE;
+}
+
+inline tvmc_status launch_sbuild_mfma(const Dev &d, hipStream_t st) {
     const int nt = (d.m + SB_TILE - 1) / SB_TILE;
     hipLaunchKernelGGL(k_sbuild_i8, dim3(nt * (nt + 1) / 2, d.nt), dim3(256), 0, st, d);
     if (hipGetLastError() != hipSuccess) return TVMC_E_DEVICE;

@@ -48,7 +48,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, D, S, mom_part, mom, hist, ens, flags, total;
+        bmean, G, gbar, obar, D, S, linv, mom_part, mom, hist, ens, flags, total;
 };
 
 int mom_blocks_for(int ns) {
@@ -91,6 +91,7 @@ Layout layout(int n, int m, int nch, int T, int ns, int nc, int nobs) {
     L.obar = take(sizeof(double) * tt * m);
     L.D = take(sizeof(double2) * tt * m);
     L.S = take(sizeof(double) * tt * m * m);
+    L.linv = take(sizeof(double) * tt * chol_panels(m) * CN * CN);
     L.mom_part = take(sizeof(double) * tt * mom_blocks_for(ns) * 9);
     L.mom = take(sizeof(double) * tt * 9);
     L.hist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt * 9);
@@ -247,6 +248,13 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         hipLaunchKernelGGL(k_obar_D, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
         LAUNCHCHECK(c, "k_obar_D");
     }
+    if (c->cfg.precision == TVMC_PREC_MFMA) {
+        Scope sc(c, "transpose");
+        if (launch_transpose_bits(d, c->stream) != TVMC_OK) {
+            set_err(c, "launch of k_transpose_bits failed");
+            return TVMC_E_DEVICE;
+        }
+    }
     {
         Scope sc(c, "sbuild");
         if (c->cfg.precision == TVMC_PREC_MFMA) {
@@ -402,6 +410,7 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
     d.obar = (double *)(base + L.obar);
     d.D = (double2 *)(base + L.D);
     d.S = (double *)(base + L.S);
+    d.linv = (double *)(base + L.linv);
     d.mom_part = (double *)(base + L.mom_part);
     d.mom = (double *)(base + L.mom);
     d.hist = (double *)(base + L.hist);

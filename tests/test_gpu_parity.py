@@ -247,7 +247,8 @@ def test_full_size_launch_configuration(tv, orc):
     for t in (0, TT - 1):
         chains = orc.init_chains(w["seed"], t, n, nc)
         dw = orc.draw_dw(w["seed"], t, 0, len(jumps), w["dt"])
-        r = orc.evaluate(pb, 0, 0, cfg, np.zeros(m), chains, traj=t, first=True, dw=dw, want_solve=2)
+        r = orc.evaluate(pb, 0, 0, cfg, np.zeros(m), chains, traj=t, first=True, dw=dw, want_solve=2,
+                         want_moments=False)
         _check_eval(tv, ctx, t, r, n, w["diag_shift"], "full size")
         assert _rel(ctx.get(T.Q_BMEAN, t), r["bmean"]) < 1e-13
         assert _rel(ctx.get(T.Q_D, t), r["D"]) < 1e-12
