@@ -19,7 +19,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int CN = 64;        // panel width
 constexpr int CR = 128;       // rows per chunk (4 waves x 32 rows)
-constexpr int CK = 16;        // k-slice staged through LDS
+constexpr int CK = 32;        // k-slice staged through LDS
 constexpr int CSP = CN + 1;   // padded LDS row of Cs / Ls
 constexpr int CKP = CK + 1;   // padded LDS row of As / Bs
 
@@ -46,10 +46,16 @@ __global__ __launch_bounds__(256) void k_chol_solve(Dev a, int which) {
     for (int j0 = 0, p = 0; j0 < M; j0 += CN, ++p) {
         const int jb = (M - j0) < CN ? (M - j0) : CN;
         for (int r0 = j0; r0 < M; r0 += CR) {
+            // ---- C = A - L[rows, 0:j0] L[panel, 0:j0]^T: the accumulators start from A (FP64
+            // accumulator layout: register r of lane (lk, li) holds row lk + 4r, column li) and
+            // the row operand is staged negated
             v4d acc[2][4];
             for (int u = 0; u < 2; ++u)
-                for (int v = 0; v < 4; ++v) acc[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
-            // ---- C = A - L[rows, 0:j0] L[panel, 0:j0]^T
+                for (int v = 0; v < 4; ++v)
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
+                        acc[u][v][r] = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : 0.0;
+                    }
             if (j0 > 0) {
                 double pa[CR * CK / 256], pb[CN * CK / 256];
                 auto fetch = [&](int kc) {
@@ -67,7 +73,7 @@ __global__ __launch_bounds__(256) void k_chol_solve(Dev a, int which) {
                     __syncthreads();
                     for (int q = 0; q < CR * CK / 256; ++q) {
                         const int e = tid + 256 * q;
-                        As[(e / CK) * CKP + e % CK] = pa[q];
+                        As[(e / CK) * CKP + e % CK] = -pa[q];
                     }
                     for (int q = 0; q < CN * CK / 256; ++q) {
                         const int e = tid + 256 * q;
@@ -86,31 +92,32 @@ __global__ __launch_bounds__(256) void k_chol_solve(Dev a, int which) {
                 }
             }
             __syncthreads();
-            // FP64 accumulator layout: register r of lane (lk, li) holds row lk + 4r, column li
             for (int u = 0; u < 2; ++u)
                 for (int v = 0; v < 4; ++v)
                     for (int r = 0; r < 4; ++r) {
                         const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
-                        const double orig = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : 0.0;
-                        Cs[row * CSP + col] = orig - acc[u][v][r];
+                        Cs[row * CSP + col] = acc[u][v][r];
                     }
             __syncthreads();
             int rstart = 0;
             if (r0 == j0) {
-                // ---- factor the diagonal block in LDS (right-looking, column by column)
-                for (int c = 0; c < jb; ++c) {
-                    if (tid == 0) {
-                        const double d = Cs[c * CSP + c];
-                        if (!(d > 0.0)) bad = 1;
-                        Cs[c * CSP + c] = sqrt(d);
-                    }
-                    __syncthreads();
-                    for (int r = c + 1 + tid; r < jb; r += 256) Cs[r * CSP + c] /= Cs[c * CSP + c];
-                    __syncthreads();
-                    const int nr = jb - c - 1;
-                    for (int e = tid; e < nr * nr; e += 256) {
-                        const int r = c + 1 + e / nr, k = c + 1 + e % nr;
-                        if (k <= r) Cs[r * CSP + k] -= Cs[r * CSP + c] * Cs[k * CSP + c];
+                // ---- factor the diagonal block in LDS, right-looking; thread (row fr, phase fs)
+                // updates columns fs, fs+4, ... of its row.  Column c is read unscaled during
+                // step c and scaled after the barrier, so one barrier per column suffices.
+                {
+                    const int fr = tid >> 2, fs = tid & 3;
+                    for (int c = 0; c < jb; ++c) {
+                        const double piv = Cs[c * CSP + c];
+                        if (tid == 0 && !(piv > 0.0)) bad = 1;
+                        const double d = sqrt(piv), inv = 1.0 / d;
+                        double lrc = 0.0;
+                        if (fr > c && fr < jb) {
+                            lrc = Cs[fr * CSP + c] * inv;
+                            for (int k = c + 1 + fs; k <= fr; k += 4) Cs[fr * CSP + k] -= lrc * (Cs[k * CSP + c] * inv);
+                        }
+                        __syncthreads();
+                        if (fs == 0 && fr > c && fr < jb) Cs[fr * CSP + c] = lrc;
+                        if (tid == 0) Cs[c * CSP + c] = d;
                     }
                     __syncthreads();
                 }
@@ -118,16 +125,20 @@ __global__ __launch_bounds__(256) void k_chol_solve(Dev a, int which) {
                     const int r = e / jb, c = e % jb;
                     if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
                 }
-                // ---- Linv: column c of the inverse of the lower-triangular block, by thread c
-                if (tid < CN) {
-                    const int c = tid;
-                    for (int r = 0; r < CN; ++r) Ls[r * CSP + c] = 0.0;
+                // ---- Linv, the inverse of the lower-triangular block by forward substitution:
+                // wave w owns columns 16w..16w+15, four lanes per column share each row's sum
+                // (rows of one column are written and read back by the same wave, in order)
+                {
+                    const int c = wave * 16 + (lane >> 2), fs = lane & 3;
+                    for (int r = fs; r < CN; r += 4) Ls[r * CSP + c] = 0.0;
                     if (c < jb) {
-                        Ls[c * CSP + c] = 1.0 / Cs[c * CSP + c];
+                        if (fs == 0) Ls[c * CSP + c] = 1.0 / Cs[c * CSP + c];
                         for (int r = c + 1; r < jb; ++r) {
-                            double s = 0.0;
-                            for (int k = c; k < r; ++k) s += Cs[r * CSP + k] * Ls[k * CSP + c];
-                            Ls[r * CSP + c] = -s / Cs[r * CSP + r];
+                            double sum = 0.0;
+                            for (int k = c + fs; k < r; k += 4) sum += Cs[r * CSP + k] * Ls[k * CSP + c];
+                            sum += __shfl_xor(sum, 1, 64);
+                            sum += __shfl_xor(sum, 2, 64);
+                            if (fs == 0) Ls[r * CSP + c] = -sum / Cs[r * CSP + r];
                         }
                     }
                 }

@@ -27,22 +27,47 @@ __device__ __forceinline__ double jump_ll(int kind, int site, double g, uint64_t
     return g + g;
 }
 
-// <B^n> per channel: one thread per channel, samples summed in order.
-__global__ void k_channel_means(Dev a) {
-    const int t = blockIdx.x;
+// <B^n> per channel.  A workgroup takes CM_CH channels of one trajectory; each thread sums a
+// strided subset of the samples, then the block reduces in a fixed order (reproducible).
+constexpr int CM_CH = 8;
+__global__ __launch_bounds__(256) void k_channel_means(Dev a) {
+    __shared__ double red[4][2 * CM_CH];
+    const int t = blockIdx.y, c0 = blockIdx.x * CM_CH;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t *smp = a.samples + (size_t)t * a.ns;
     const double2 *R = a.R + (size_t)t * a.ns * a.n;
-    for (int ch = threadIdx.x; ch < a.nch; ch += blockDim.x) {
-        const int kind = a.jkind[ch], st = a.jsite[ch];
-        const double sq = sqrt(a.jrate[ch]);
-        double re = 0.0, im = 0.0;
-        for (int s = 0; s < a.ns; ++s) {
-            const double2 b = jump_local(kind, st, sq, smp[s], R + (size_t)s * a.n);
-            re += b.x;
-            im += b.y;
+    int kind[CM_CH], st[CM_CH];
+    double sq[CM_CH], re[CM_CH], im[CM_CH];
+    for (int q = 0; q < CM_CH; ++q) {
+        const int ch = c0 + q < a.nch ? c0 + q : a.nch - 1;
+        kind[q] = a.jkind[ch];
+        st[q] = a.jsite[ch];
+        sq[q] = sqrt(a.jrate[ch]);
+        re[q] = im[q] = 0.0;
+    }
+    for (int s = threadIdx.x; s < a.ns; s += blockDim.x) {
+        const uint64_t mk = smp[s];
+        const double2 *Rrow = R + (size_t)s * a.n;
+        for (int q = 0; q < CM_CH; ++q) {
+            const double2 b = jump_local(kind[q], st[q], sq[q], mk, Rrow);
+            re[q] += b.x;
+            im[q] += b.y;
         }
+    }
+    for (int q = 0; q < CM_CH; ++q) {
+        const double r = wave_sum(re[q]), i = wave_sum(im[q]);
+        if (lane == 0) {
+            red[wave][2 * q] = r;
+            red[wave][2 * q + 1] = i;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < CM_CH && c0 + (int)threadIdx.x < a.nch) {
+        const int q = threadIdx.x;
+        const double r = (red[0][2 * q] + red[1][2 * q]) + (red[2][2 * q] + red[3][2 * q]);
+        const double i = (red[0][2 * q + 1] + red[1][2 * q + 1]) + (red[2][2 * q + 1] + red[3][2 * q + 1]);
         const double norm = 1.0 / (double)a.ns;
-        a.bmean[(size_t)t * a.nch + ch] = make_double2(re * norm, im * norm);
+        a.bmean[(size_t)t * a.nch + c0 + q] = make_double2(r * norm, i * norm);
     }
 }
 

@@ -95,18 +95,20 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, in
 
     const uint32_t ctr1 = ((uint32_t)stage << 31) | (uint32_t)c;
     const uint32_t ctr3 = (1u << 24) | (uint32_t)(a.traj0 + t);
-    const int64_t total = (int64_t)(burn + a.per * a.thin) * n;
-    const int64_t first_rec = (int64_t)burn * n, rec_stride = (int64_t)a.thin * n;
+    // proposal counts fit in 31 bits (checked on the host)
+    const int total = (burn + a.per * a.thin) * n;
+    const int rec_stride = a.thin * n;
+    int next_rec = burn * n + rec_stride - 1;   // proposal after which the next sample is taken
     int rec = 0;
     uint32_t nacc = 0;
     const size_t tbase = (size_t)t * a.ns;
 
-    for (int64_t base = 0; base < total; base += 64) {
+    for (int base = 0; base < total; base += 64) {
         uint32_t r[4];
         philox4x32_10((uint32_t)(base + lane), ctr1, (uint32_t)step, ctr3, a.key0, a.key1, r);
         const int site_l = (int)(((uint64_t)r[0] * (uint64_t)n) >> 32);
         const double logu_l = log(u53(r[1], r[2]));
-        const int cnt = (int)((total - base) < 64 ? (total - base) : 64);
+        const int cnt = (total - base) < 64 ? (total - base) : 64;
         for (int j = 0; j < cnt; ++j) {
             const int i = __builtin_amdgcn_readlane(site_l, j);
             const double lu = readlane_d(logu_l, j);
@@ -122,10 +124,10 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, in
                 }
                 ++nacc;
             }
-            const int64_t q = base + j;
-            if (q >= first_rec && ((q - first_rec + 1) % rec_stride) == 0) {
+            if (base + j == next_rec) {
                 const size_t sidx = tbase + (size_t)c * a.per + rec;
                 ++rec;
+                next_rec += rec_stride;
                 double ere = 0.0, eim = 0.0;
                 if (act) {
                     const double sl = spin(mask, lane);

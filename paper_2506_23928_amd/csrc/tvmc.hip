@@ -238,7 +238,7 @@ tvmc_status run_estimate(tvmc_ctx *c) {
     {
         Scope sc(c, "estimate");
         if (d.nch > 0) {
-            hipLaunchKernelGGL(k_channel_means, dim3(T), dim3(128), 0, c->stream, d);
+            hipLaunchKernelGGL(k_channel_means, dim3((d.nch + CM_CH - 1) / CM_CH, T), dim3(256), 0, c->stream, d);
             LAUNCHCHECK(c, "k_channel_means");
         }
         hipLaunchKernelGGL(k_build_G, dim3((d.ns + 255) / 256, T), dim3(256), 0, c->stream, d);
