@@ -20,7 +20,7 @@
  *
  * Parameter layout theta (interleaved re, im doubles):
  *   Jastrow (Eq. 12): [a_0..a_{N-1}, eta_01, eta_02, .., eta_0,N-1, eta_12, .., eta_N-2,N-1]
- *   RBM     (Eq. 11): [a_0..a_{N-1}, b_0..b_{N'-1}, w_00, w_01, .., w_0,N'-1, w_10, ..]  (reserved)
+ *   RBM     (Eq. 11): [a_0..a_{N-1}, b_0..b_{N'-1}, w_00, w_01, .., w_0,N'-1, w_10, ..]
  *
  * Ownership: every host pointer passed in is read during the call and may be freed after it.
  * The device workspace is allocated by the caller (size from tvmc_workspace_size), must stay
@@ -55,8 +55,8 @@ enum { TVMC_JUMP_SIGMA_MINUS = 0, TVMC_JUMP_SIGMA_PLUS = 1, TVMC_JUMP_SIGMA_Z = 
 enum { TVMC_ANSATZ_JASTROW = 0, TVMC_ANSATZ_RBM = 1 };
 enum { TVMC_SCHEME_HEUN = 0, TVMC_SCHEME_MIDPOINT = 1 };
 /* FP64: S accumulated with FP64 vector FMAs.  MFMA: S accumulated on int8 matrix cores; for
- * the Jastrow ansatz every O_k is +-1, so both give the same S bit for bit.  Solve and theta
- * stay FP64 in both. */
+ * the Jastrow ansatz every O_k is +-1, so both give the same S bit for bit (the RBM supports
+ * FP64 only).  Solve and theta stay FP64 in both. */
 enum { TVMC_PREC_FP64 = 0, TVMC_PREC_MFMA = 1 };
 
 /* One Lindblad problem (Eq. 1 with the Hamiltonian of Eq. 10), shared by all trajectories. */
@@ -71,8 +71,8 @@ typedef struct {
 } tvmc_problem;
 
 typedef struct {
-    int32_t kind;                 /* TVMC_ANSATZ_JASTROW (TVMC_ANSATZ_RBM is reserved) */
-    int32_t n_hidden;
+    int32_t kind;                 /* TVMC_ANSATZ_JASTROW or TVMC_ANSATZ_RBM */
+    int32_t n_hidden;             /* RBM hidden units N', 1..256 (ignored for Jastrow) */
 } tvmc_ansatz;
 
 typedef struct {
@@ -100,9 +100,10 @@ enum {
     TVMC_Q_DELTA1 = 3,      /* double[2M] corrector increment */
     TVMC_Q_SAMPLES = 4,     /* uint64[n_samples] packed configurations of the last sampling */
     TVMC_Q_ELOC = 5,        /* double[2 n_samples] local energy of H */
-    TVMC_Q_S = 6,           /* double[M*M] S + eps I, lower triangle valid (before the solve) */
+    TVMC_Q_S = 6,           /* double[M*M] S + eps I, lower triangle valid (before the solve); for the
+                               RBM the real embedding [[Re S, -Im S], [Im S, Re S]], double[4 M*M] */
     TVMC_Q_D = 7,           /* double[2M] D */
-    TVMC_Q_OBAR = 8,        /* double[M] <O_k> (real for the Jastrow ansatz) */
+    TVMC_Q_OBAR = 8,        /* <O_k>: double[M] for the Jastrow ansatz (real), double[2M] for the RBM */
     TVMC_Q_BMEAN = 9,       /* double[2 n_jumps] <B^n> */
     TVMC_Q_DW = 10,         /* double[n_jumps] Wiener increments of the current step */
     TVMC_Q_ACCEPTS = 11,    /* uint32[n_chains] accepted proposals in the last sampling */

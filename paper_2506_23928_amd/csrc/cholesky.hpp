@@ -9,7 +9,8 @@
 //     rows below:  L[rows, panel] = C Linv^T                  (MFMA)
 // The forward substitution L y = D rides along panel by panel; the backward substitution
 // L^T x = y afterwards reads L once more and reuses the stored block inverses.
-// The real factor of the Jastrow S is applied to the real and imaginary parts of D.
+// The real factor of the Jastrow S is applied to the real and imaginary parts of D; a complex
+// Hermitian S (RBM) is solved through its real embedding [[Re S, -Im S], [Im S, Re S]].
 #pragma once
 #include "common.hpp"
 
@@ -25,7 +26,19 @@ constexpr int CKP = CK + 1;   // padded LDS row of As / Bs
 
 __host__ __device__ inline int chol_panels(int m) { return (m + CN - 1) / CN; }
 
-__global__ __launch_bounds__(256) void k_chol_solve(Dev a, int which) {
+// One real symmetric positive-definite system per trajectory: A [T][M][M] (lower triangle,
+// overwritten by L), right-hand sides rhs [T][M] (two real columns packed as double2),
+// solution x [T][M], block inverses linv [T][panels][64*64], failure flags [T].
+struct CholArgs {
+    double *A;
+    const double2 *rhs;
+    double2 *x;
+    double *linv;
+    int *flags;
+    int m;
+};
+
+__global__ __launch_bounds__(256) void k_chol_solve(CholArgs a) {
     __shared__ double Cs[CR * CSP];
     __shared__ double Ls[CN * CSP];
     __shared__ double As[CR * CKP];
@@ -35,10 +48,10 @@ __global__ __launch_bounds__(256) void k_chol_solve(Dev a, int which) {
     const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int M = a.m;
-    double *A = a.S + (size_t)t * M * M;
+    double *A = a.A + (size_t)t * M * M;
     double *linv = a.linv + (size_t)t * chol_panels(M) * CN * CN;
-    double2 *z = (which ? a.d1 : a.d0) + (size_t)t * M;
-    const double2 *Dv = a.D + (size_t)t * M;
+    double2 *z = a.x + (size_t)t * M;
+    const double2 *Dv = a.rhs + (size_t)t * M;
     if (tid == 0) bad = 0;
     for (int i = tid; i < M; i += 256) z[i] = Dv[i];
     __syncthreads();

@@ -61,6 +61,7 @@ __host__ __device__ __forceinline__ int pair_index(int n, int j, int k) {
 // Everything a kernel may touch, as raw device pointers into the caller's workspace.
 struct Dev {
     int n, m, nch, ns, nc, per, nt, nobs;
+    int kind, nh, me;         // ansatz (0 Jastrow, 1 RBM), hidden units, dimension of the real solve
     int burn, thin, init_sweeps, scheme, traj0;
     uint32_t key0, key1;
     double hx, dt, eps;
@@ -83,7 +84,12 @@ struct Dev {
     double2 *bmean;           // [T][nch]
     double2 *G;               // [T][Ns]
     double2 *gbar;            // [T]
-    double *obar;             // [T][M]
+    double *obar;             // [T][M] (Jastrow, real)
+    double2 *obarc;           // [T][M] (RBM, complex)
+    double *w_re, *w_im;      // [T][N][N'] RBM weights, split planes
+    double2 *cT, *sT;         // [T][N'][N] cosh 2w, sinh 2w (transposed)
+    double2 *tt;              // [T][Ns][N'] tanh g_j per sample
+    double2 *rhs2, *x2;       // [T][2M] right-hand side / solution of the real embedding
     double2 *D;               // [T][M]
     double *S;                // [T][M][M]
     double *linv;             // [T][panels][64*64] inverses of the Cholesky diagonal blocks

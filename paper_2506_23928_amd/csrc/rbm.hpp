@@ -1,0 +1,390 @@
+// Restricted-Boltzmann-machine ansatz (Eq. 11):
+//   log psi(s) = sum_i a_i s_i + sum_j log 2cosh(g_j),   g_j = b_j + sum_i w_ij s_i,
+//   O = (s_i ; tanh g_j ; s_i tanh g_j),  M = N + N' + N N' complex parameters.
+// Sampling: one wavefront per chain, lane j owns hidden units j, j+64, ...; it keeps g_j and
+// log|cosh g_j|.  The accept test needs only Re(log psi' - log psi) = -2 s_i Re a_i +
+// sum_j (log|cosh(g_j - 2 s_i w_ij)| - log|cosh g_j|), one wave reduction per proposal.
+// Single-flip ratios use cosh(g - 2 s w)/cosh g = cosh 2w - s tanh(g) sinh 2w with the
+// cosh 2w / sinh 2w tables built once per evaluation, so a sample's N ratios cost N N'
+// complex multiply-adds (products renormalised every 16 factors).
+// The complex Hermitian S is assembled directly as its real embedding
+// [[Re S, -Im S], [Im S, Re S]] (lower triangle), solved by the real FP64 Cholesky.
+#pragma once
+#include "common.hpp"
+
+namespace tvmc {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// log|cosh(x + i y)| = |x| - log 2 + log((1 + e)^2 - 4 e sin^2 y) / 2 with e = exp(-2|x|)
+__device__ __forceinline__ double log_abs_cosh(double x, double y) {
+    const double ax = fabs(x), e = exp(-2.0 * ax), sy = sin(y);
+    return ax - 0.69314718055994530942 + 0.5 * log((1.0 + e) * (1.0 + e) - 4.0 * e * sy * sy);
+}
+
+// tanh(x + i y) = (sinh 2x + i sin 2y) / (cosh 2x + cos 2y), written with e = exp(-2|x|)
+__device__ __forceinline__ double2 ctanh_(double x, double y) {
+    const double ax = fabs(x), e = exp(-2.0 * ax), e2 = e * e;
+    double s2, c2;
+    sincos(2.0 * y, &s2, &c2);
+    // multiply numerator and denominator by 2 e^{-2|x|}
+    const double den = 1.0 + e2 + 2.0 * e * c2;
+    const double re = (1.0 - e2) / den, im = 2.0 * e * s2 / den;
+    return make_double2(x < 0.0 ? -re : re, im);
+}
+
+// theta -> w planes [T][N][N'] and the tables cosh 2w, sinh 2w transposed [T][N'][N]
+__global__ void k_prepare_rbm(Dev a, const double2 *__restrict__ src) {
+    const int t = blockIdx.y;
+    const int n = a.n, nh = a.nh;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * nh) return;
+    const int i = idx / nh, j = idx % nh;
+    const double2 w = src[(size_t)t * a.m + n + nh + idx];
+    a.w_re[(size_t)t * n * nh + idx] = w.x;
+    a.w_im[(size_t)t * n * nh + idx] = w.y;
+    const double x = 2.0 * w.x, y = 2.0 * w.y;
+    double sy, cy;
+    sincos(y, &sy, &cy);
+    const double ch = cosh(x), sh = sinh(x);
+    a.cT[((size_t)t * nh + j) * n + i] = make_double2(ch * cy, sh * sy);
+    a.sT[((size_t)t * nh + j) * n + i] = make_double2(sh * cy, ch * sy);
+}
+
+template <int CPB, int QH>
+__global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int stage, int burn) {
+    __shared__ double lwr[64 * 64];
+    __shared__ double lwi[64 * 64];
+    __shared__ double2 tl[CPB][64 * QH];
+    const int n = a.n, nh = a.nh;
+    const int t = blockIdx.y;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * CPB + w;
+    const bool in_lds = n * nh <= 64 * 64;
+    const double *gwr = a.w_re + (size_t)t * n * nh, *gwi = a.w_im + (size_t)t * n * nh;
+    if (in_lds) {
+        for (int i = threadIdx.x; i < n * nh; i += blockDim.x) {
+            lwr[i] = gwr[i];
+            lwi[i] = gwi[i];
+        }
+    }
+    __syncthreads();
+    const double *wr = in_lds ? lwr : gwr;
+    const double *wi = in_lds ? lwi : gwi;
+    const double2 *th = a.theta_eval + (size_t)t * a.m;
+    uint64_t mask = a.chains[(size_t)t * a.nc + c];
+
+    double gre[QH], gim[QH], lc[QH];
+    for (int q = 0; q < QH; ++q) {
+        const int j = lane + 64 * q;
+        gre[q] = gim[q] = lc[q] = 0.0;
+        if (j < nh) {
+            double xr = th[n + j].x, xi = th[n + j].y;   // b_j + sum_i w_ij s_i, i in order
+            for (int i = 0; i < n; ++i) {
+                const double si = spin(mask, i);
+                xr += wr[i * nh + j] * si;
+                xi += wi[i * nh + j] * si;
+            }
+            gre[q] = xr;
+            gim[q] = xi;
+            lc[q] = log_abs_cosh(xr, xi);
+        }
+    }
+
+    const uint32_t ctr1 = ((uint32_t)stage << 31) | (uint32_t)c;
+    const uint32_t ctr3 = (1u << 24) | (uint32_t)(a.traj0 + t);
+    const int total = (burn + a.per * a.thin) * n;
+    const int rec_stride = a.thin * n;
+    int next_rec = burn * n + rec_stride - 1;
+    int rec = 0;
+    uint32_t nacc = 0;
+    const size_t tbase = (size_t)t * a.ns;
+    const double2 *cT = a.cT + (size_t)t * nh * n, *sT = a.sT + (size_t)t * nh * n;
+
+    for (int base = 0; base < total; base += 64) {
+        uint32_t r[4];
+        philox4x32_10((uint32_t)(base + lane), ctr1, (uint32_t)step, ctr3, a.key0, a.key1, r);
+        const int site_l = (int)(((uint64_t)r[0] * (uint64_t)n) >> 32);
+        const double logu_l = log(u53(r[1], r[2]));
+        const int cnt = (total - base) < 64 ? (total - base) : 64;
+        for (int jj = 0; jj < cnt; ++jj) {
+            const int i = __builtin_amdgcn_readlane(site_l, jj);
+            const double lu = readlane_d(logu_l, jj);
+            const double si = spin(mask, i);
+            double ln[QH], dsum = 0.0;
+            for (int q = 0; q < QH; ++q) {
+                const int j = lane + 64 * q;
+                ln[q] = 0.0;
+                if (j < nh) {
+                    ln[q] = log_abs_cosh(gre[q] - 2.0 * si * wr[i * nh + j], gim[q] - 2.0 * si * wi[i * nh + j]);
+                    dsum += ln[q] - lc[q];
+                }
+            }
+            const double dre = -2.0 * si * th[i].x + wave_sum(dsum);
+            if (lu < 2.0 * dre) {
+                mask ^= (1ull << i);
+                for (int q = 0; q < QH; ++q) {
+                    const int j = lane + 64 * q;
+                    if (j < nh) {
+                        gre[q] -= 2.0 * si * wr[i * nh + j];
+                        gim[q] -= 2.0 * si * wi[i * nh + j];
+                        lc[q] = ln[q];
+                    }
+                }
+                ++nacc;
+            }
+            if (base + jj == next_rec) {
+                const size_t sidx = tbase + (size_t)c * a.per + rec;
+                ++rec;
+                next_rec += rec_stride;
+                for (int q = 0; q < QH; ++q) {
+                    const int j = lane + 64 * q;
+                    if (j < nh) {
+                        const double2 tj = ctanh_(gre[q], gim[q]);
+                        tl[w][j] = tj;
+                        a.tt[sidx * nh + j] = tj;
+                    }
+                }
+                double ere = 0.0, eim = 0.0;
+                if (lane < n) {
+                    const double sl = spin(mask, lane);
+                    // prod_j (cosh 2w_lj - s_l t_j sinh 2w_lj), renormalised every 16 factors
+                    double pr = 1.0, pi = 0.0, lsum = 0.0;
+                    for (int j = 0; j < nh; ++j) {
+                        const double2 ch = cT[(size_t)j * n + lane], sh = sT[(size_t)j * n + lane];
+                        const double2 ts = cmul(tl[w][j], sh);
+                        const double fr = ch.x - sl * ts.x, fi = ch.y - sl * ts.y;
+                        const double nr = pr * fr - pi * fi, ni = pr * fi + pi * fr;
+                        pr = nr;
+                        pi = ni;
+                        if ((j & 15) == 15) {
+                            const double mg = sqrt(pr * pr + pi * pi);
+                            lsum += log(mg);
+                            pr /= mg;
+                            pi /= mg;
+                        }
+                    }
+                    const double er = lsum - 2.0 * sl * th[lane].x, ei = -2.0 * sl * th[lane].y;
+                    const double ex = exp(er);
+                    double sn, cs;
+                    sincos(ei, &sn, &cs);
+                    const double2 R = cmul(make_double2(pr, pi), make_double2(ex * cs, ex * sn));
+                    a.R[sidx * n + lane] = R;
+                    double hj = 0.0;
+                    for (int k = 0; k < n; ++k) hj += a.J[k * n + lane] * spin(mask, k);
+                    ere = 0.5 * sl * hj + a.hx * R.x;
+                    eim = a.hx * R.y;
+                }
+                ere = wave_sum(ere);
+                eim = wave_sum(eim);
+                if (lane == 0) {
+                    a.samples[sidx] = mask;
+                    a.eloc[sidx] = make_double2(ere, eim);
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        a.chains[(size_t)t * a.nc + c] = mask;
+        a.acc[(size_t)t * a.nc + c] = nacc;
+    }
+}
+
+// O_k of sample s (complex): one-body s_i, hidden tanh g_j, weights s_i tanh g_j
+__device__ __forceinline__ double2 rbm_o(const Dev &a, int k, uint64_t mk, const double2 *tts) {
+    if (k < a.n) return make_double2(spin(mk, k), 0.0);
+    if (k < a.n + a.nh) return tts[k - a.n];
+    const int idx = k - a.n - a.nh, i = idx / a.nh, j = idx % a.nh;
+    const double si = spin(mk, i);
+    const double2 tj = tts[j];
+    return make_double2(si * tj.x, si * tj.y);
+}
+
+// <O_k> and D_k = <O_k^* G> - <O_k>^* <G>
+__global__ __launch_bounds__(256) void k_obar_D_rbm(Dev a) {
+    const int t = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.m) return;
+    const uint64_t *smp = a.samples + (size_t)t * a.ns;
+    const double2 *G = a.G + (size_t)t * a.ns;
+    const double2 *tt = a.tt + (size_t)t * a.ns * a.nh;
+    double obr = 0.0, obi = 0.0, dr = 0.0, di = 0.0;
+    for (int s = 0; s < a.ns; ++s) {
+        const double2 o = rbm_o(a, k, smp[s], tt + (size_t)s * a.nh);
+        const double2 g = G[s];
+        obr += o.x;
+        obi += o.y;
+        dr += o.x * g.x + o.y * g.y;   // conj(o) g
+        di += o.x * g.y - o.y * g.x;
+    }
+    const double inv = 1.0 / (double)a.ns;
+    obr *= inv;
+    obi *= inv;
+    const double2 gb = a.gbar[t];
+    a.obarc[(size_t)t * a.m + k] = make_double2(obr, obi);
+    a.D[(size_t)t * a.m + k] = make_double2(dr * inv - (obr * gb.x + obi * gb.y), di * inv - (obr * gb.y - obi * gb.x));
+}
+
+// Complex S + eps I written as the lower triangle of its real embedding (size 2M), plain FP64:
+// 32x32 complex tile per workgroup, 2x2 complex register tile per thread, samples staged 8 at
+// a time (configuration word and tanh g row) through LDS.
+constexpr int RB_T = 32;
+constexpr int RB_S = 8;
+__global__ __launch_bounds__(256) void k_sbuild_rbm_f64(Dev a) {
+    __shared__ uint64_t smask[RB_S];
+    __shared__ double2 stt[RB_S][256];
+    const int t = blockIdx.y;
+    const int tile = blockIdx.x;
+    int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
+    while (bi * (bi + 1) / 2 > tile) --bi;
+    const int bj = tile - bi * (bi + 1) / 2;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int m = a.m, nh = a.nh;
+    double2 acc[2][2] = {};
+    const uint64_t *smp = a.samples + (size_t)t * a.ns;
+    const double2 *tt = a.tt + (size_t)t * a.ns * nh;
+    for (int s0 = 0; s0 < a.ns; s0 += RB_S) {
+        const int cnt = (a.ns - s0) < RB_S ? (a.ns - s0) : RB_S;
+        __syncthreads();
+        if (threadIdx.x < cnt) smask[threadIdx.x] = smp[s0 + threadIdx.x];
+        for (int e = threadIdx.x; e < cnt * nh; e += blockDim.x) stt[e / nh][e % nh] = tt[(size_t)(s0 + e / nh) * nh + e % nh];
+        __syncthreads();
+        for (int s = 0; s < cnt; ++s) {
+            double2 ov[2], cv[2];
+            for (int u = 0; u < 2; ++u) {
+                const int k = bi * RB_T + ty * 2 + u, l = bj * RB_T + tx * 2 + u;
+                ov[u] = k < m ? rbm_o(a, k, smask[s], stt[s]) : make_double2(0.0, 0.0);
+                cv[u] = l < m ? rbm_o(a, l, smask[s], stt[s]) : make_double2(0.0, 0.0);
+            }
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 2; ++v) {   // conj(o_k) o_l
+                    acc[u][v].x += ov[u].x * cv[v].x + ov[u].y * cv[v].y;
+                    acc[u][v].y += ov[u].x * cv[v].y - ov[u].y * cv[v].x;
+                }
+        }
+    }
+    const double inv = 1.0 / (double)a.ns;
+    const double2 *ob = a.obarc + (size_t)t * m;
+    const size_t me = 2 * (size_t)m;
+    double *S = a.S + (size_t)t * me * me;
+    for (int u = 0; u < 2; ++u) {
+        const int k = bi * RB_T + ty * 2 + u;
+        if (k >= m) continue;
+        for (int v = 0; v < 2; ++v) {
+            const int l = bj * RB_T + tx * 2 + v;
+            if (l >= m || l > k) continue;
+            // S_kl = <O_k^* O_l> - <O_k>^* <O_l>
+            double re = acc[u][v].x * inv - (ob[k].x * ob[l].x + ob[k].y * ob[l].y);
+            const double im = acc[u][v].y * inv - (ob[k].x * ob[l].y - ob[k].y * ob[l].x);
+            if (k == l) re += a.eps;
+            S[(size_t)k * me + l] = re;                    // Re S (upper-left block)
+            S[(size_t)(m + k) * me + m + l] = re;          // Re S (lower-right block)
+            S[(size_t)(m + k) * me + l] = im;              // Im S_kl (lower-left block)
+            if (k != l) S[(size_t)(m + l) * me + k] = -im; // Im S_lk = -Im S_kl
+        }
+    }
+}
+
+// right-hand side of the embedding: (Re D ; Im D), and the solution back to delta = u + i v
+__global__ void k_embed_rhs(Dev a) {
+    const int t = blockIdx.y, k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.m) return;
+    const double2 d = a.D[(size_t)t * a.m + k];
+    a.rhs2[(size_t)t * 2 * a.m + k] = make_double2(d.x, 0.0);
+    a.rhs2[(size_t)t * 2 * a.m + a.m + k] = make_double2(d.y, 0.0);
+}
+
+__global__ void k_unembed(Dev a, int which) {
+    const int t = blockIdx.y, k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.m) return;
+    const double2 *x = a.x2 + (size_t)t * 2 * a.m;
+    double2 *d = (which ? a.d1 : a.d0) + (size_t)t * a.m;
+    d[k] = make_double2(x[k].x, x[a.m + k].x);
+}
+
+// Moments for the RBM: two-flip ratios psi(s^(ab))/psi(s) = exp(-2 s_a a_a - 2 s_b a_b)
+// prod_j [cosh(u+v) - tanh(g_j) sinh(u+v)],  u = 2 s_a w_aj, v = 2 s_b w_bj.
+constexpr int RMOM_WAVES = 4;
+__global__ __launch_bounds__(64 * RMOM_WAVES) void k_moments_rbm(Dev a) {
+    __shared__ double part[RMOM_WAVES][9];
+    __shared__ double2 tl[RMOM_WAVES][256];
+    const int t = blockIdx.y;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = a.n, nh = a.nh;
+    const double N = (double)n;
+    double acc[9] = {};
+    const double2 *cT = a.cT + (size_t)t * nh * n, *sT = a.sT + (size_t)t * nh * n;
+    const double2 *th = a.theta_eval + (size_t)t * a.m;
+    for (int s = blockIdx.x * RMOM_WAVES + w; s < a.ns; s += gridDim.x * RMOM_WAVES) {
+        const size_t sidx = (size_t)t * a.ns + s;
+        const uint64_t mk = a.samples[sidx];
+        for (int j = lane; j < nh; j += 64) tl[w][j] = a.tt[sidx * nh + j];
+        const bool act = lane < n;
+        const double sa = spin(mk, lane);
+        const double2 Ra = act ? a.R[sidx * n + lane] : make_double2(0.0, 0.0);
+        double v[9] = {};
+        if (act) {
+            v[0] = Ra.x;
+            v[1] = sa * Ra.y;
+            v[2] = sa;
+        }
+        for (int b = 0; b < n; ++b) {
+            if (!act || b == lane) continue;
+            const double sb = spin(mk, b), ss = sa * sb;
+            double pr = 1.0, pi = 0.0, lsum = 0.0;
+            for (int j = 0; j < nh; ++j) {
+                const double2 ca = cT[(size_t)j * n + lane], sa_ = sT[(size_t)j * n + lane];
+                const double2 cb = cT[(size_t)j * n + b], sb_ = sT[(size_t)j * n + b];
+                const double2 cc = cmul(ca, cb), s2 = cmul(sa_, cb), s3 = cmul(ca, sb_), s4 = cmul(sa_, sb_);
+                const double2 chu = make_double2(cc.x + ss * s4.x, cc.y + ss * s4.y);
+                const double2 shu = make_double2(sa * s2.x + sb * s3.x, sa * s2.y + sb * s3.y);
+                const double2 tsh = cmul(tl[w][j], shu);
+                const double fr = chu.x - tsh.x, fi = chu.y - tsh.y;
+                const double nr = pr * fr - pi * fi, ni = pr * fi + pi * fr;
+                pr = nr;
+                pi = ni;
+                if ((j & 15) == 15) {
+                    const double mg = sqrt(pr * pr + pi * pi);
+                    lsum += log(mg);
+                    pr /= mg;
+                    pi /= mg;
+                }
+            }
+            const double er = lsum - 2.0 * sa * th[lane].x - 2.0 * sb * th[b].x;
+            const double ei = -2.0 * sa * th[lane].y - 2.0 * sb * th[b].y;
+            const double ex = exp(er);
+            double sn, cs;
+            sincos(ei, &sn, &cs);
+            const double2 Rab = cmul(make_double2(pr, pi), make_double2(ex * cs, ex * sn));
+            v[3] += Rab.x;
+            v[4] += -ss * Rab.x;
+            v[5] += ss;
+            v[6] += sb * Rab.y;
+            v[7] += sb * Ra.x;
+            v[8] += ss * Ra.y;
+        }
+        for (int q = 0; q < 9; ++q) v[q] = wave_sum(v[q]);
+        acc[0] += v[0] / N;
+        acc[1] += v[1] / N;
+        acc[2] += v[2] / N;
+        acc[3] += (N + v[3]) / (N * N);
+        acc[4] += (N + v[4]) / (N * N);
+        acc[5] += (N + v[5]) / (N * N);
+        acc[6] += v[6] / (N * N);
+        acc[7] += v[7] / (N * N);
+        acc[8] += v[8] / (N * N);
+    }
+    if (lane == 0)
+        for (int q = 0; q < 9; ++q) part[w][q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double s = 0.0;
+        for (int ww = 0; ww < RMOM_WAVES; ++ww) s += part[ww][threadIdx.x];
+        a.mom_part[((size_t)t * a.mom_blocks + blockIdx.x) * 9 + threadIdx.x] = s;
+    }
+}
+
+}  // namespace tvmc

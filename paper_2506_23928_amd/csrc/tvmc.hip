@@ -15,6 +15,7 @@
 #include "common.hpp"
 #include "estimate.hpp"
 #include "observe.hpp"
+#include "rbm.hpp"
 #include "sampler.hpp"
 #include "sbuild.hpp"
 #include "sbuild_mfma.hpp"
@@ -48,7 +49,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, D, S, linv, mom_part, mom, hist, ens, flags, total;
+        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, rhs2, x2, D, S, linv, mom_part, mom, hist, ens, flags, total;
 };
 
 int mom_blocks_for(int ns) {
@@ -56,7 +57,10 @@ int mom_blocks_for(int ns) {
     return b < 64 ? b : 64;
 }
 
-Layout layout(int n, int m, int nch, int T, int ns, int nc, int nobs) {
+int n_params(int kind, int n, int nh) { return kind == TVMC_ANSATZ_RBM ? n + nh + n * nh : n + n * (n - 1) / 2; }
+int solve_dim(int kind, int m) { return kind == TVMC_ANSATZ_RBM ? 2 * m : m; }
+
+Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -88,10 +92,20 @@ Layout layout(int n, int m, int nch, int T, int ns, int nc, int nobs) {
     L.bmean = take(sizeof(double2) * tt * (nch + 1));
     L.G = take(sizeof(double2) * tt * ns);
     L.gbar = take(sizeof(double2) * tt);
+    const bool rbm = kind == TVMC_ANSATZ_RBM;
+    const size_t me = (size_t)solve_dim(kind, m);
     L.obar = take(sizeof(double) * tt * m);
+    L.obarc = take(rbm ? sizeof(double2) * tt * m : 0);
+    L.w_re = take(rbm ? sizeof(double) * tt * n * nh : 0);
+    L.w_im = take(rbm ? sizeof(double) * tt * n * nh : 0);
+    L.cT = take(rbm ? sizeof(double2) * tt * n * nh : 0);
+    L.sT = take(rbm ? sizeof(double2) * tt * n * nh : 0);
+    L.tt = take(rbm ? sizeof(double2) * tt * ns * nh : 0);
+    L.rhs2 = take(rbm ? sizeof(double2) * tt * me : 0);
+    L.x2 = take(rbm ? sizeof(double2) * tt * me : 0);
     L.D = take(sizeof(double2) * tt * m);
-    L.S = take(sizeof(double) * tt * m * m);
-    L.linv = take(sizeof(double) * tt * chol_panels(m) * CN * CN);
+    L.S = take(sizeof(double) * tt * me * me);
+    L.linv = take(sizeof(double) * tt * chol_panels((int)me) * CN * CN);
     L.mom_part = take(sizeof(double) * tt * mom_blocks_for(ns) * 9);
     L.mom = take(sizeof(double) * tt * 9);
     L.hist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt * 9);
@@ -132,8 +146,11 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
             if (p->J[i * p->n_sites + j] != p->J[j * p->n_sites + i])
                 return snprintf(msg, len, "J must be symmetric"), TVMC_E_INVAL;
     }
-    if (a->kind != TVMC_ANSATZ_JASTROW)
-        return snprintf(msg, len, "only the Jastrow ansatz is implemented on this path"), TVMC_E_UNSUPPORTED;
+    if (a->kind != TVMC_ANSATZ_JASTROW && a->kind != TVMC_ANSATZ_RBM) return snprintf(msg, len, "bad ansatz"), TVMC_E_INVAL;
+    if (a->kind == TVMC_ANSATZ_RBM && (a->n_hidden < 1 || a->n_hidden > 256))
+        return snprintf(msg, len, "RBM hidden units must be in [1, 256]"), TVMC_E_INVAL;
+    if (a->kind == TVMC_ANSATZ_RBM && c->precision == TVMC_PREC_MFMA)
+        return snprintf(msg, len, "the matrix-core S-build is implemented for the Jastrow ansatz only"), TVMC_E_UNSUPPORTED;
     if (c->n_traj < 1 || (int64_t)c->traj_offset + c->n_traj > (1 << 24) || c->traj_offset < 0)
         return snprintf(msg, len, "trajectory ids must lie in [0, 2^24)"), TVMC_E_INVAL;
     if (c->n_chains < 1 || c->n_samples < 1 || c->n_samples % c->n_chains)
@@ -213,10 +230,45 @@ tvmc_status run_sample(tvmc_ctx *c) {
                                    c->stream));
     }
     const int nn = d.n * d.n;
+    const int burn = d.burn + ((c->step == 0 && c->stage == 0) ? d.init_sweeps : 0);
+    if (d.kind == TVMC_ANSATZ_RBM) {
+        hipLaunchKernelGGL(k_prepare_rbm, dim3((d.n * d.nh + 255) / 256, T), dim3(256), 0, c->stream, d,
+                           (const double2 *)d.theta_eval);
+        LAUNCHCHECK(c, "k_prepare_rbm");
+        Scope sc(c, "sample");
+        dim3 grid(d.nc / c->cpb, T);
+        const int qh = (d.nh + 63) / 64;
+#define RBM_LAUNCH(CPB, QH) hipLaunchKernelGGL((k_sample_rbm<CPB, QH>), grid, dim3(64 * CPB), 0, c->stream, d, c->step, c->stage, burn)
+        if (qh == 1) {
+            switch (c->cpb) {
+            case 8: RBM_LAUNCH(8, 1); break;
+            case 4: RBM_LAUNCH(4, 1); break;
+            case 2: RBM_LAUNCH(2, 1); break;
+            default: RBM_LAUNCH(1, 1); break;
+            }
+        } else if (qh == 2) {
+            switch (c->cpb) {
+            case 8: RBM_LAUNCH(8, 2); break;
+            case 4: RBM_LAUNCH(4, 2); break;
+            case 2: RBM_LAUNCH(2, 2); break;
+            default: RBM_LAUNCH(1, 2); break;
+            }
+        } else {
+            switch (c->cpb) {
+            case 8: RBM_LAUNCH(8, 4); break;
+            case 4: RBM_LAUNCH(4, 4); break;
+            case 2: RBM_LAUNCH(2, 4); break;
+            default: RBM_LAUNCH(1, 4); break;
+            }
+        }
+#undef RBM_LAUNCH
+        LAUNCHCHECK(c, "k_sample_rbm");
+        c->phase = 1;
+        return TVMC_OK;
+    }
     hipLaunchKernelGGL(k_prepare_jastrow, dim3((nn + 255) / 256, T), dim3(256), 0, c->stream, d,
                        (const double2 *)d.theta_eval);
     LAUNCHCHECK(c, "k_prepare_jastrow");
-    const int burn = d.burn + ((c->step == 0 && c->stage == 0) ? d.init_sweeps : 0);
     {
         Scope sc(c, "sample");
         dim3 grid(d.nc / c->cpb, T);
@@ -245,8 +297,21 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         LAUNCHCHECK(c, "k_build_G");
         hipLaunchKernelGGL(k_gbar, dim3(T), dim3(256), 0, c->stream, d);
         LAUNCHCHECK(c, "k_gbar");
-        hipLaunchKernelGGL(k_obar_D, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
-        LAUNCHCHECK(c, "k_obar_D");
+        if (d.kind == TVMC_ANSATZ_RBM) {
+            hipLaunchKernelGGL(k_obar_D_rbm, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_obar_D_rbm");
+        } else {
+            hipLaunchKernelGGL(k_obar_D, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_obar_D");
+        }
+    }
+    if (d.kind == TVMC_ANSATZ_RBM) {
+        Scope sc(c, "sbuild");
+        const int nt = (d.m + RB_T - 1) / RB_T;
+        hipLaunchKernelGGL(k_sbuild_rbm_f64, dim3(nt * (nt + 1) / 2, T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_sbuild_rbm_f64");
+        c->phase = 2;
+        return TVMC_OK;
     }
     if (c->cfg.precision == TVMC_PREC_MFMA) {
         Scope sc(c, "transpose");
@@ -277,8 +342,19 @@ tvmc_status run_solve(tvmc_ctx *c) {
     Dev &d = c->d;
     {
         Scope sc(c, "solve");
-        hipLaunchKernelGGL(k_chol_solve, dim3(d.nt), dim3(256), 0, c->stream, d, c->stage);
-        LAUNCHCHECK(c, "k_chol_solve");
+        if (d.kind == TVMC_ANSATZ_RBM) {
+            hipLaunchKernelGGL(k_embed_rhs, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_embed_rhs");
+            CholArgs ca{d.S, d.rhs2, d.x2, d.linv, d.flags, d.me};
+            hipLaunchKernelGGL(k_chol_solve, dim3(d.nt), dim3(256), 0, c->stream, ca);
+            LAUNCHCHECK(c, "k_chol_solve");
+            hipLaunchKernelGGL(k_unembed, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage);
+            LAUNCHCHECK(c, "k_unembed");
+        } else {
+            CholArgs ca{d.S, d.D, c->stage ? d.d1 : d.d0, d.linv, d.flags, d.m};
+            hipLaunchKernelGGL(k_chol_solve, dim3(d.nt), dim3(256), 0, c->stream, ca);
+            LAUNCHCHECK(c, "k_chol_solve");
+        }
     }
     c->phase = 3;
     return TVMC_OK;
@@ -305,10 +381,15 @@ tvmc_status run_moments(tvmc_ctx *c, int slot) {
     Dev &d = c->d;
     const int T = d.nt, nn = d.n * d.n;
     Scope sc(c, "observe");
-    hipLaunchKernelGGL(k_prepare_pairs, dim3((nn + 255) / 256, T), dim3(256), 0, c->stream, d);
-    LAUNCHCHECK(c, "k_prepare_pairs");
-    hipLaunchKernelGGL(k_moments, dim3(d.mom_blocks, T), dim3(64 * MOM_WAVES), 0, c->stream, d);
-    LAUNCHCHECK(c, "k_moments");
+    if (d.kind == TVMC_ANSATZ_RBM) {
+        hipLaunchKernelGGL(k_moments_rbm, dim3(d.mom_blocks, T), dim3(64 * RMOM_WAVES), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_moments_rbm");
+    } else {
+        hipLaunchKernelGGL(k_prepare_pairs, dim3((nn + 255) / 256, T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_prepare_pairs");
+        hipLaunchKernelGGL(k_moments, dim3(d.mom_blocks, T), dim3(64 * MOM_WAVES), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_moments");
+    }
     hipLaunchKernelGGL(k_moments_reduce, dim3((T + 127) / 128), dim3(128), 0, c->stream, d, slot);
     LAUNCHCHECK(c, "k_moments_reduce");
     return TVMC_OK;
@@ -321,8 +402,8 @@ size_t q_bytes(const tvmc_ctx *c, int what) {
         return sizeof(double2) * d.m;
     case TVMC_Q_SAMPLES: return sizeof(uint64_t) * d.ns;
     case TVMC_Q_ELOC: return sizeof(double2) * d.ns;
-    case TVMC_Q_S: return sizeof(double) * (size_t)d.m * d.m;
-    case TVMC_Q_OBAR: return sizeof(double) * d.m;
+    case TVMC_Q_S: return sizeof(double) * (size_t)d.me * d.me;
+    case TVMC_Q_OBAR: return (d.kind == TVMC_ANSATZ_RBM ? sizeof(double2) : sizeof(double)) * d.m;
     case TVMC_Q_BMEAN: return sizeof(double2) * d.nch;
     case TVMC_Q_DW: return sizeof(double) * d.nch;
     case TVMC_Q_ACCEPTS: return sizeof(uint32_t) * d.nc;
@@ -341,8 +422,8 @@ tvmc_status tvmc_workspace_size(const tvmc_problem *p, const tvmc_ansatz *a, con
     tvmc_status st = check_args(p, a, c, g_err, sizeof(g_err));
     if (st != TVMC_OK) return st;
     if (!bytes) return TVMC_E_INVAL;
-    const int n = p->n_sites, m = n + n * (n - 1) / 2;
-    *bytes = layout(n, m, p->n_jumps, c->n_traj, c->n_samples, c->n_chains, c->n_obs_max).total;
+    const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden);
+    *bytes = layout(a->kind, n, a->n_hidden, m, p->n_jumps, c->n_traj, c->n_samples, c->n_chains, c->n_obs_max).total;
     return TVMC_OK;
 }
 
@@ -352,8 +433,9 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
     *out = nullptr;
     tvmc_status st = check_args(p, a, c, g_err, sizeof(g_err));
     if (st != TVMC_OK) return st;
-    const int n = p->n_sites, m = n + n * (n - 1) / 2, nch = p->n_jumps, T = c->n_traj;
-    const Layout L = layout(n, m, nch, T, c->n_samples, c->n_chains, c->n_obs_max);
+    const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden), nch = p->n_jumps, T = c->n_traj;
+    const int nh = a->kind == TVMC_ANSATZ_RBM ? a->n_hidden : 0;
+    const Layout L = layout(a->kind, n, nh, m, nch, T, c->n_samples, c->n_chains, c->n_obs_max);
     if (!ws) return snprintf(g_err, sizeof(g_err), "workspace is null"), TVMC_E_INVAL;
     if (ws_bytes < L.total) return snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu", ws_bytes, L.total), TVMC_E_NOMEM;
     if ((uintptr_t)ws % 256) return snprintf(g_err, sizeof(g_err), "workspace must be 256-byte aligned"), TVMC_E_INVAL;
@@ -367,6 +449,9 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
     Dev &d = ctx->d;
     d.n = n;
     d.m = m;
+    d.kind = a->kind;
+    d.nh = nh;
+    d.me = solve_dim(a->kind, m);
     d.nch = nch;
     d.ns = c->n_samples;
     d.nc = c->n_chains;
@@ -408,6 +493,14 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
     d.G = (double2 *)(base + L.G);
     d.gbar = (double2 *)(base + L.gbar);
     d.obar = (double *)(base + L.obar);
+    d.obarc = (double2 *)(base + L.obarc);
+    d.w_re = (double *)(base + L.w_re);
+    d.w_im = (double *)(base + L.w_im);
+    d.cT = (double2 *)(base + L.cT);
+    d.sT = (double2 *)(base + L.sT);
+    d.tt = (double2 *)(base + L.tt);
+    d.rhs2 = (double2 *)(base + L.rhs2);
+    d.x2 = (double2 *)(base + L.x2);
     d.D = (double2 *)(base + L.D);
     d.S = (double *)(base + L.S);
     d.linv = (double *)(base + L.linv);
@@ -417,16 +510,14 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
     d.ens = (double *)(base + L.ens);
     d.flags = (int *)(base + L.flags);
 
-    std::vector<int> pa(m), pb(m);
-    for (int i = 0; i < n; ++i) {
-        pa[i] = i;
-        pb[i] = -1;
-    }
-    for (int j = 0; j < n; ++j)
-        for (int k = j + 1; k < n; ++k) {
-            pa[pair_index(n, j, k)] = j;
-            pb[pair_index(n, j, k)] = k;
-        }
+    std::vector<int> pa(m, 0), pb(m, -1);
+    for (int i = 0; i < n; ++i) pa[i] = i;
+    if (a->kind == TVMC_ANSATZ_JASTROW)
+        for (int j = 0; j < n; ++j)
+            for (int k = j + 1; k < n; ++k) {
+                pa[pair_index(n, j, k)] = j;
+                pb[pair_index(n, j, k)] = k;
+            }
     std::vector<double2> th((size_t)T * m);
     for (int t = 0; t < T; ++t)
         for (int k = 0; k < m; ++k)
@@ -544,9 +635,9 @@ tvmc_status tvmc_get(tvmc_ctx *c, int32_t what, int32_t traj, void *host, size_t
     case TVMC_Q_DELTA1: src = d.d1 + t * d.m; break;
     case TVMC_Q_SAMPLES: src = d.samples + t * d.ns; break;
     case TVMC_Q_ELOC: src = d.eloc + t * d.ns; break;
-    case TVMC_Q_S: src = d.S + t * d.m * d.m; break;
+    case TVMC_Q_S: src = d.S + t * d.me * d.me; break;
     case TVMC_Q_D: src = d.D + t * d.m; break;
-    case TVMC_Q_OBAR: src = d.obar + t * d.m; break;
+    case TVMC_Q_OBAR: src = d.kind == TVMC_ANSATZ_RBM ? (const void *)(d.obarc + t * d.m) : (const void *)(d.obar + t * d.m); break;
     case TVMC_Q_BMEAN: src = d.bmean + t * d.nch; break;
     case TVMC_Q_DW: src = d.dw + t * d.nch; break;
     case TVMC_Q_ACCEPTS: src = d.acc + t * d.nc; break;

@@ -232,13 +232,20 @@ class Context:
         _check(lib().tvmc_timing(self.ctx, group.encode(), ctypes.byref(ms), ctypes.byref(cnt)), self.ctx)
         return ms.value, cnt.value
 
+    @property
+    def solve_dim(self):
+        """Dimension of the real system solved: M (Jastrow) or 2M (RBM, real embedding)."""
+        return 2 * self.m if self.ansatz.kind == RBM else self.m
+
     def _count(self, key):
         c = self.config
-        return {"m": self.m, "ns": c.n_samples, "mm": self.m * self.m, "nch": len(self.problem.jumps),
+        return {"m": self.m, "ns": c.n_samples, "mm": self.solve_dim ** 2, "nch": len(self.problem.jumps),
                 "nc": c.n_chains, "9": 9, "hist": 9 * c.n_obs_max}[key]
 
     def get(self, what, traj=0):
         dt, key = self._shapes[what]
+        if what == Q_OBAR and self.ansatz.kind == RBM:
+            dt = "c"
         cnt = self._count(key)
         np_dt = {"c": np.complex128, "d": np.float64, "u8": np.uint64, "u4": np.uint32}[dt]
         out = np.zeros(max(cnt, 1), dtype=np_dt)
@@ -246,7 +253,7 @@ class Context:
                               ctypes.c_size_t(out.nbytes)), self.ctx)
         out = out[:cnt]
         if what == Q_S:
-            out = out.reshape(self.m, self.m)
+            out = out.reshape(self.solve_dim, self.solve_dim)
         if what == Q_OBS_HIST:
             out = out.reshape(-1, 9)
         return out
