@@ -90,7 +90,17 @@ typedef struct {
     int32_t obs_every;            /* record moments at steps that are multiples of this (0: never) */
     int32_t n_obs_max;            /* capacity of the moment history */
     uint64_t seed;                /* Philox4x32-10 key */
+    /* learned proposal (Jastrow ansatz): a masked autoregressive network per trajectory, trained
+     * on the trajectory's own samples, proposes one independent Metropolis-Hastings move at the
+     * start of every sweep; single-spin flips remain the fallback */
+    int32_t proposal;             /* TVMC_PROPOSAL_* */
+    int32_t ar_hidden;            /* hidden units of the network, 1..256 */
+    int32_t ar_train_every;       /* train at steps that are multiples of this (0: only on request) */
+    int32_t ar_train_iters;       /* Adam steps per training */
+    double ar_lr;                 /* Adam learning rate */
 } tvmc_config;
+
+enum { TVMC_PROPOSAL_FLIP = 0, TVMC_PROPOSAL_LEARNED = 1 };
 
 /* Quantities readable with tvmc_get (per trajectory unless noted). */
 enum {
@@ -109,7 +119,13 @@ enum {
     TVMC_Q_ACCEPTS = 11,    /* uint32[n_chains] accepted proposals in the last sampling */
     TVMC_Q_CHAINS = 12,     /* uint64[n_chains] chain configurations */
     TVMC_Q_MOMENTS = 13,    /* double[9] moments (mx,my,mz,sxx,syy,szz,sxy,sxz,syz) */
-    TVMC_Q_OBS_HIST = 14    /* double[n_obs_max*9] moment history; traj selects the trajectory */
+    TVMC_Q_OBS_HIST = 14,   /* double[n_obs_max*9] moment history; traj selects the trajectory */
+    TVMC_Q_AR_PARAMS = 15,  /* float[P] network parameters W1 [H][N] | b1 [H] | W2 [N][H] | b2 [N],
+                               P = 2 N H + N + H (settable) */
+    TVMC_Q_AR_GRAD = 16,    /* float[P] gradient of the mean negative log-likelihood */
+    TVMC_Q_AR_LOGQ = 17,    /* float[n_samples] log q of the last samples */
+    TVMC_Q_AR_LOSS = 18,    /* double[1] mean negative log-likelihood */
+    TVMC_Q_AR_ACCEPTS = 19  /* uint32[n_chains] accepted learned proposals in the last sampling */
 };
 
 /* Bytes of device workspace needed for this problem, ansatz and configuration. */
@@ -136,6 +152,10 @@ tvmc_status tvmc_update(tvmc_ctx *ctx);
 /* n_steps full steps (noise, predictor, corrector); records moments every obs_every steps
  * from the predictor samples.  Requires the predictor stage to be ready. */
 tvmc_status tvmc_sde_step(tvmc_ctx *ctx, int32_t n_steps);
+/* Train the learned proposal on the last samples (needs TVMC_PROPOSAL_LEARNED): n_iters Adam
+ * steps, each on log q, the loss and the gradient of the current parameters; n_iters = 0 only
+ * evaluates log q, the loss and the gradient.  Requires samples at the current point. */
+tvmc_status tvmc_train_proposal(tvmc_ctx *ctx, int32_t n_iters);
 /* Moments of the collective spin from the last samples (observables paragraph of the LITF
  * section); copies double[n_traj][9] to moments_out when it is not NULL. */
 tvmc_status tvmc_observables(tvmc_ctx *ctx, double *moments_out);

@@ -99,6 +99,16 @@ struct Dev {
     double *ens;              // [16]
     int *flags;               // [T]
     int mom_blocks;
+    // learned proposal (MADE): hidden width, parameter count per trajectory, buffers
+    int ar, ah;
+    size_t arnp;
+    float *arP, *arG, *arM, *arV;     // [T][arnp] master parameters, gradient, Adam moments
+    uint16_t *arW1b, *arW2Tb;         // [T][H][N] BF16 inference copies (W1, W2 transposed)
+    float *arh, *arda;                // [T][Ns][H] training activations
+    float *arg;                       // [T][Ns][N]
+    float *arlogq;                    // [T][Ns]
+    double *arloss;                   // [T]
+    uint32_t *aracc;                  // [T][C] accepted learned proposals
 };
 
 }  // namespace tvmc

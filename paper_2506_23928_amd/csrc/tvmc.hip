@@ -35,7 +35,7 @@ struct tvmc_ctx {
     Dev d{};
     hipStream_t stream = nullptr;
     tvmc_config cfg{};
-    int step = 0, stage = 0, phase = 0, nobs = 0;
+    int step = 0, stage = 0, phase = 0, nobs = 0, adam_t = 0;
     int cpb = 1;
     char err[512] = {0};
     bool timing = false;
@@ -49,7 +49,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, rhs2, x2, D, S, linv, mom_part, mom, hist, ens, flags, total;
+        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, rhs2, x2, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1b, arW2Tb, arh, arda,
+        arg, arlogq, arloss, aracc, total;
 };
 
 int mom_blocks_for(int ns) {
@@ -60,7 +61,7 @@ int mom_blocks_for(int ns) {
 int n_params(int kind, int n, int nh) { return kind == TVMC_ANSATZ_RBM ? n + nh + n * nh : n + n * (n - 1) / 2; }
 int solve_dim(int kind, int m) { return kind == TVMC_ANSATZ_RBM ? 2 * m : m; }
 
-Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs) {
+Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs, int ar, int ah) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -111,6 +112,19 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.hist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt * 9);
     L.ens = take(sizeof(double) * 16);
     L.flags = take(sizeof(int) * tt);
+    const size_t np = ar ? ar_params(n, ah) : 0;
+    L.arP = take(sizeof(float) * tt * np);
+    L.arG = take(sizeof(float) * tt * np);
+    L.arM = take(sizeof(float) * tt * np);
+    L.arV = take(sizeof(float) * tt * np);
+    L.arW1b = take(ar ? sizeof(uint16_t) * tt * ah * n : 0);
+    L.arW2Tb = take(ar ? sizeof(uint16_t) * tt * ah * n : 0);
+    L.arh = take(ar ? sizeof(float) * tt * ns * ah : 0);
+    L.arda = take(ar ? sizeof(float) * tt * ns * ah : 0);
+    L.arg = take(ar ? sizeof(float) * tt * ns * n : 0);
+    L.arlogq = take(ar ? sizeof(float) * tt * ns : 0);
+    L.arloss = take(sizeof(double) * tt);
+    L.aracc = take(sizeof(uint32_t) * tt * nc);
     L.total = o;
     return L;
 }
@@ -167,6 +181,15 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
     if (c->precision == TVMC_PREC_MFMA && c->n_samples % 64)
         return snprintf(msg, len, "the MFMA S-build needs n_samples to be a multiple of 64"), TVMC_E_INVAL;
     if (c->obs_every < 0 || c->n_obs_max < 0) return snprintf(msg, len, "bad observation settings"), TVMC_E_INVAL;
+    if (c->proposal != TVMC_PROPOSAL_FLIP && c->proposal != TVMC_PROPOSAL_LEARNED)
+        return snprintf(msg, len, "bad proposal"), TVMC_E_INVAL;
+    if (c->proposal == TVMC_PROPOSAL_LEARNED) {
+        if (a->kind != TVMC_ANSATZ_JASTROW)
+            return snprintf(msg, len, "the learned proposal is implemented for the Jastrow ansatz"), TVMC_E_UNSUPPORTED;
+        if (c->ar_hidden < 1 || c->ar_hidden > 256) return snprintf(msg, len, "ar_hidden must be in [1, 256]"), TVMC_E_INVAL;
+        if (c->ar_train_every < 0 || c->ar_train_iters < 0 || !(c->ar_lr > 0.0))
+            return snprintf(msg, len, "bad training settings"), TVMC_E_INVAL;
+    }
     return TVMC_OK;
 }
 
@@ -272,12 +295,23 @@ tvmc_status run_sample(tvmc_ctx *c) {
     {
         Scope sc(c, "sample");
         dim3 grid(d.nc / c->cpb, T);
-        switch (c->cpb) {
-        case 8: hipLaunchKernelGGL(k_sample_jastrow<8>, grid, dim3(512), 0, c->stream, d, c->step, c->stage, burn); break;
-        case 4: hipLaunchKernelGGL(k_sample_jastrow<4>, grid, dim3(256), 0, c->stream, d, c->step, c->stage, burn); break;
-        case 2: hipLaunchKernelGGL(k_sample_jastrow<2>, grid, dim3(128), 0, c->stream, d, c->step, c->stage, burn); break;
-        default: hipLaunchKernelGGL(k_sample_jastrow<1>, grid, dim3(64), 0, c->stream, d, c->step, c->stage, burn); break;
+#define JAS_LAUNCH(CPB, AR) hipLaunchKernelGGL((k_sample_jastrow<CPB, AR>), grid, dim3(64 * CPB), 0, c->stream, d, c->step, c->stage, burn)
+        if (d.ar) {
+            switch (c->cpb) {
+            case 8: JAS_LAUNCH(8, true); break;
+            case 4: JAS_LAUNCH(4, true); break;
+            case 2: JAS_LAUNCH(2, true); break;
+            default: JAS_LAUNCH(1, true); break;
+            }
+        } else {
+            switch (c->cpb) {
+            case 8: JAS_LAUNCH(8, false); break;
+            case 4: JAS_LAUNCH(4, false); break;
+            case 2: JAS_LAUNCH(2, false); break;
+            default: JAS_LAUNCH(1, false); break;
+            }
         }
+#undef JAS_LAUNCH
         LAUNCHCHECK(c, "k_sample_jastrow");
     }
     c->phase = 1;
@@ -377,6 +411,30 @@ tvmc_status run_update(tvmc_ctx *c) {
     return TVMC_OK;
 }
 
+tvmc_status run_train(tvmc_ctx *c, int iters) {
+    Dev &d = c->d;
+    const int T = d.nt;
+    Scope sc(c, "train");
+    const int tiles = ((d.ah + 31) / 32) * ((d.n + 31) / 32);
+    for (int it = 0; it <= iters; ++it) {
+        hipLaunchKernelGGL(k_ar_forward, dim3((d.ns + AR_WAVES - 1) / AR_WAVES, T), dim3(64 * AR_WAVES), 0, c->stream, d,
+                           1);
+        LAUNCHCHECK(c, "k_ar_forward");
+        hipLaunchKernelGGL(k_ar_grad, dim3(tiles, 2, T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_ar_grad");
+        hipLaunchKernelGGL(k_ar_loss, dim3(T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_ar_loss");
+        if (it == iters) break;
+        ++c->adam_t;
+        hipLaunchKernelGGL(k_ar_adam, dim3((unsigned)((d.arnp + 255) / 256), T), dim3(256), 0, c->stream, d,
+                           (float)c->cfg.ar_lr, c->adam_t);
+        LAUNCHCHECK(c, "k_ar_adam");
+        hipLaunchKernelGGL(k_ar_copy, dim3((d.ah * d.n + 255) / 256, T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_ar_copy");
+    }
+    return TVMC_OK;
+}
+
 tvmc_status run_moments(tvmc_ctx *c, int slot) {
     Dev &d = c->d;
     const int T = d.nt, nn = d.n * d.n;
@@ -410,6 +468,10 @@ size_t q_bytes(const tvmc_ctx *c, int what) {
     case TVMC_Q_CHAINS: return sizeof(uint64_t) * d.nc;
     case TVMC_Q_MOMENTS: return sizeof(double) * 9;
     case TVMC_Q_OBS_HIST: return sizeof(double) * 9 * (size_t)d.nobs;
+    case TVMC_Q_AR_PARAMS: case TVMC_Q_AR_GRAD: return d.ar ? sizeof(float) * d.arnp : 0;
+    case TVMC_Q_AR_LOGQ: return d.ar ? sizeof(float) * d.ns : 0;
+    case TVMC_Q_AR_LOSS: return d.ar ? sizeof(double) : 0;
+    case TVMC_Q_AR_ACCEPTS: return d.ar ? sizeof(uint32_t) * d.nc : 0;
     default: return 0;
     }
 }
@@ -423,7 +485,8 @@ tvmc_status tvmc_workspace_size(const tvmc_problem *p, const tvmc_ansatz *a, con
     if (st != TVMC_OK) return st;
     if (!bytes) return TVMC_E_INVAL;
     const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden);
-    *bytes = layout(a->kind, n, a->n_hidden, m, p->n_jumps, c->n_traj, c->n_samples, c->n_chains, c->n_obs_max).total;
+    *bytes = layout(a->kind, n, a->n_hidden, m, p->n_jumps, c->n_traj, c->n_samples, c->n_chains, c->n_obs_max,
+                    c->proposal, c->ar_hidden).total;
     return TVMC_OK;
 }
 
@@ -435,7 +498,8 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
     if (st != TVMC_OK) return st;
     const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden), nch = p->n_jumps, T = c->n_traj;
     const int nh = a->kind == TVMC_ANSATZ_RBM ? a->n_hidden : 0;
-    const Layout L = layout(a->kind, n, nh, m, nch, T, c->n_samples, c->n_chains, c->n_obs_max);
+    const Layout L = layout(a->kind, n, nh, m, nch, T, c->n_samples, c->n_chains, c->n_obs_max, c->proposal,
+                            c->ar_hidden);
     if (!ws) return snprintf(g_err, sizeof(g_err), "workspace is null"), TVMC_E_INVAL;
     if (ws_bytes < L.total) return snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu", ws_bytes, L.total), TVMC_E_NOMEM;
     if ((uintptr_t)ws % 256) return snprintf(g_err, sizeof(g_err), "workspace must be 256-byte aligned"), TVMC_E_INVAL;
@@ -509,6 +573,21 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
     d.hist = (double *)(base + L.hist);
     d.ens = (double *)(base + L.ens);
     d.flags = (int *)(base + L.flags);
+    d.ar = c->proposal;
+    d.ah = c->proposal ? c->ar_hidden : 0;
+    d.arnp = c->proposal ? ar_params(n, c->ar_hidden) : 0;
+    d.arP = (float *)(base + L.arP);
+    d.arG = (float *)(base + L.arG);
+    d.arM = (float *)(base + L.arM);
+    d.arV = (float *)(base + L.arV);
+    d.arW1b = (uint16_t *)(base + L.arW1b);
+    d.arW2Tb = (uint16_t *)(base + L.arW2Tb);
+    d.arh = (float *)(base + L.arh);
+    d.arda = (float *)(base + L.arda);
+    d.arg = (float *)(base + L.arg);
+    d.arlogq = (float *)(base + L.arlogq);
+    d.arloss = (double *)(base + L.arloss);
+    d.aracc = (uint32_t *)(base + L.aracc);
 
     std::vector<int> pa(m, 0), pb(m, -1);
     for (int i = 0; i < n; ++i) pa[i] = i;
@@ -549,6 +628,12 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
     INITCHECK(hipMemsetAsync(d.d1, 0, sizeof(double2) * (size_t)T * m, ctx->stream));
     hipLaunchKernelGGL(k_init_chains, dim3((c->n_chains + 63) / 64, T), dim3(64), 0, ctx->stream, d);
     INITCHECK(hipGetLastError());
+    if (d.ar) {
+        hipLaunchKernelGGL(k_ar_init, dim3((unsigned)((d.arnp + 255) / 256), T), dim3(256), 0, ctx->stream, d);
+        INITCHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_ar_copy, dim3((d.ah * n + 255) / 256, T), dim3(256), 0, ctx->stream, d);
+        INITCHECK(hipGetLastError());
+    }
     INITCHECK(hipStreamSynchronize(ctx->stream));
 #undef INITCHECK
     *out = ctx;
@@ -590,12 +675,23 @@ tvmc_status tvmc_sde_step(tvmc_ctx *c, int32_t n_steps) {
                 st = run_moments(c, c->nobs++);
                 if (st != TVMC_OK) return st;
             }
+            if (stage == 0 && c->d.ar && c->cfg.ar_train_every > 0 && c->step % c->cfg.ar_train_every == 0) {
+                st = run_train(c, c->cfg.ar_train_iters);
+                if (st != TVMC_OK) return st;
+            }
             if ((st = run_estimate(c)) != TVMC_OK) return st;
             if ((st = run_solve(c)) != TVMC_OK) return st;
             if ((st = run_update(c)) != TVMC_OK) return st;
         }
     }
     return TVMC_OK;
+}
+
+tvmc_status tvmc_train_proposal(tvmc_ctx *c, int32_t n_iters) {
+    if (!c || n_iters < 0) return TVMC_E_INVAL;
+    if (!c->d.ar) return set_err(c, "tvmc_train_proposal: the learned proposal is not enabled"), TVMC_E_STATE;
+    if (c->phase < 1) return set_err(c, "tvmc_train_proposal: no samples at the current evaluation point"), TVMC_E_STATE;
+    return run_train(c, n_iters);
 }
 
 tvmc_status tvmc_observables(tvmc_ctx *c, double *out) {
@@ -643,6 +739,11 @@ tvmc_status tvmc_get(tvmc_ctx *c, int32_t what, int32_t traj, void *host, size_t
     case TVMC_Q_ACCEPTS: src = d.acc + t * d.nc; break;
     case TVMC_Q_CHAINS: src = d.chains + t * d.nc; break;
     case TVMC_Q_MOMENTS: src = d.mom + t * 9; break;
+    case TVMC_Q_AR_PARAMS: src = d.arP + t * d.arnp; break;
+    case TVMC_Q_AR_GRAD: src = d.arG + t * d.arnp; break;
+    case TVMC_Q_AR_LOGQ: src = d.arlogq + t * d.ns; break;
+    case TVMC_Q_AR_LOSS: src = d.arloss + t; break;
+    case TVMC_Q_AR_ACCEPTS: src = d.aracc + t * d.nc; break;
     default: break;
     }
     if (what == TVMC_Q_OBS_HIST) {
@@ -660,9 +761,20 @@ tvmc_status tvmc_set(tvmc_ctx *c, int32_t what, int32_t traj, const void *host, 
     if (!c || !host) return TVMC_E_INVAL;
     const Dev &d = c->d;
     if (traj < 0 || traj >= d.nt) return set_err(c, "tvmc_set: trajectory out of range"), TVMC_E_INVAL;
-    if (what != TVMC_Q_THETA && what != TVMC_Q_CHAINS) return set_err(c, "tvmc_set: only theta and chains"), TVMC_E_INVAL;
+    if (what != TVMC_Q_THETA && what != TVMC_Q_CHAINS && what != TVMC_Q_AR_PARAMS)
+        return set_err(c, "tvmc_set: only theta, chains and the proposal parameters"), TVMC_E_INVAL;
     const size_t nb = q_bytes(c, what);
+    if (nb == 0) return set_err(c, "tvmc_set: quantity not present"), TVMC_E_INVAL;
     if (bytes < nb) return set_err(c, "tvmc_set: buffer too small"), TVMC_E_INVAL;
+    if (what == TVMC_Q_AR_PARAMS) {
+        for (size_t i = 0; i < d.arnp; ++i)
+            if (!std::isfinite(((const float *)host)[i])) return set_err(c, "tvmc_set: parameters not finite"), TVMC_E_INVAL;
+        HIPCHECK(c, hipMemcpyAsync(d.arP + (size_t)traj * d.arnp, host, nb, hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_ar_copy, dim3((d.ah * d.n + 255) / 256, d.nt), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_ar_copy");
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        return TVMC_OK;
+    }
     void *dst = what == TVMC_Q_THETA ? (void *)(d.theta + (size_t)traj * d.m) : (void *)(d.chains + (size_t)traj * d.nc);
     if (what == TVMC_Q_CHAINS && d.n < 64)
         for (int i = 0; i < d.nc; ++i)

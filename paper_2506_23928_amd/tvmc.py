@@ -19,7 +19,8 @@ JASTROW, RBM = 0, 1
 HEUN, MIDPOINT = 0, 1
 PREC_FP64, PREC_MFMA = 0, 1
 (Q_THETA, Q_THETA_EVAL, Q_DELTA0, Q_DELTA1, Q_SAMPLES, Q_ELOC, Q_S, Q_D, Q_OBAR, Q_BMEAN, Q_DW, Q_ACCEPTS,
- Q_CHAINS, Q_MOMENTS, Q_OBS_HIST) = range(15)
+ Q_CHAINS, Q_MOMENTS, Q_OBS_HIST, Q_AR_PARAMS, Q_AR_GRAD, Q_AR_LOGQ, Q_AR_LOSS, Q_AR_ACCEPTS) = range(20)
+PROPOSAL_FLIP, PROPOSAL_LEARNED = 0, 1
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -39,7 +40,9 @@ class tvmc_config(ctypes.Structure):
                 ("n_chains", ctypes.c_int32), ("burn_sweeps", ctypes.c_int32), ("thin_sweeps", ctypes.c_int32),
                 ("init_sweeps", ctypes.c_int32), ("scheme", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("diag_shift", ctypes.c_double), ("precision", ctypes.c_int32), ("obs_every", ctypes.c_int32),
-                ("n_obs_max", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("n_obs_max", ctypes.c_int32), ("seed", ctypes.c_uint64), ("proposal", ctypes.c_int32),
+                ("ar_hidden", ctypes.c_int32), ("ar_train_every", ctypes.c_int32), ("ar_train_iters", ctypes.c_int32),
+                ("ar_lr", ctypes.c_double)]
 
 
 class TvmcError(RuntimeError):
@@ -50,7 +53,7 @@ class TvmcError(RuntimeError):
 
 _lib = None
 EXPORTED = ["tvmc_workspace_size", "tvmc_init", "tvmc_sample", "tvmc_estimate", "tvmc_sr_solve", "tvmc_update",
-            "tvmc_sde_step", "tvmc_observables", "tvmc_ensemble", "tvmc_get", "tvmc_set", "tvmc_position",
+            "tvmc_sde_step", "tvmc_train_proposal", "tvmc_observables", "tvmc_ensemble", "tvmc_get", "tvmc_set", "tvmc_position",
             "tvmc_synchronize", "tvmc_set_timing", "tvmc_timing", "tvmc_last_error", "tvmc_destroy"]
 
 
@@ -99,9 +102,11 @@ def n_params(kind: int, n: int, n_hidden: int = 0) -> int:
 
 
 def make_config(n_traj, n_samples, n_chains, dt, diag_shift=1e-4, burn_sweeps=2, thin_sweeps=1, init_sweeps=0,
-                scheme=HEUN, precision=PREC_FP64, obs_every=0, n_obs_max=0, seed=0, traj_offset=0):
+                scheme=HEUN, precision=PREC_FP64, obs_every=0, n_obs_max=0, seed=0, traj_offset=0,
+                proposal=PROPOSAL_FLIP, ar_hidden=128, ar_train_every=20, ar_train_iters=50, ar_lr=3e-3):
     return tvmc_config(n_traj, traj_offset, n_samples, n_chains, burn_sweeps, thin_sweeps, init_sweeps, scheme, dt,
-                       diag_shift, precision, obs_every, n_obs_max, ctypes.c_uint64(seed))
+                       diag_shift, precision, obs_every, n_obs_max, ctypes.c_uint64(seed), proposal, ar_hidden,
+                       ar_train_every, ar_train_iters, ar_lr)
 
 
 # ---------------------------------------------------------------- functions named as in the C ABI
@@ -144,6 +149,10 @@ def tvmc_sde_step(ctx, n_steps: int):
     _check(lib().tvmc_sde_step(ctx, ctypes.c_int32(n_steps)), ctx)
 
 
+def tvmc_train_proposal(ctx, n_iters: int):
+    _check(lib().tvmc_train_proposal(ctx, ctypes.c_int32(n_iters)), ctx)
+
+
 def tvmc_observables(ctx, n_traj: int, copy=True):
     out = np.zeros((n_traj, 9)) if copy else None
     _check(lib().tvmc_observables(ctx, out.ctypes.data_as(_dp) if copy else None), ctx)
@@ -170,7 +179,8 @@ class Context:
     _shapes = {Q_THETA: ("c", "m"), Q_THETA_EVAL: ("c", "m"), Q_DELTA0: ("c", "m"), Q_DELTA1: ("c", "m"),
                Q_SAMPLES: ("u8", "ns"), Q_ELOC: ("c", "ns"), Q_S: ("d", "mm"), Q_D: ("c", "m"), Q_OBAR: ("d", "m"),
                Q_BMEAN: ("c", "nch"), Q_DW: ("d", "nch"), Q_ACCEPTS: ("u4", "nc"), Q_CHAINS: ("u8", "nc"),
-               Q_MOMENTS: ("d", "9"), Q_OBS_HIST: ("d", "hist")}
+               Q_MOMENTS: ("d", "9"), Q_OBS_HIST: ("d", "hist"), Q_AR_PARAMS: ("f", "arnp"), Q_AR_GRAD: ("f", "arnp"),
+               Q_AR_LOGQ: ("f", "ns"), Q_AR_LOSS: ("d", "1"), Q_AR_ACCEPTS: ("u4", "nc")}
 
     def __init__(self, problem: Problem, config: tvmc_config, kind=JASTROW, n_hidden=0, theta0=None, device="cuda",
                  stream=None):
@@ -240,14 +250,15 @@ class Context:
     def _count(self, key):
         c = self.config
         return {"m": self.m, "ns": c.n_samples, "mm": self.solve_dim ** 2, "nch": len(self.problem.jumps),
-                "nc": c.n_chains, "9": 9, "hist": 9 * c.n_obs_max}[key]
+                "nc": c.n_chains, "9": 9, "hist": 9 * c.n_obs_max, "1": 1,
+                "arnp": 2 * self.problem.n * c.ar_hidden + self.problem.n + c.ar_hidden}[key]
 
     def get(self, what, traj=0):
         dt, key = self._shapes[what]
         if what == Q_OBAR and self.ansatz.kind == RBM:
             dt = "c"
         cnt = self._count(key)
-        np_dt = {"c": np.complex128, "d": np.float64, "u8": np.uint64, "u4": np.uint32}[dt]
+        np_dt = {"c": np.complex128, "d": np.float64, "u8": np.uint64, "u4": np.uint32, "f": np.float32}[dt]
         out = np.zeros(max(cnt, 1), dtype=np_dt)
         _check(lib().tvmc_get(self.ctx, ctypes.c_int32(what), ctypes.c_int32(traj), out.ctypes.data_as(ctypes.c_void_p),
                               ctypes.c_size_t(out.nbytes)), self.ctx)
@@ -258,8 +269,11 @@ class Context:
             out = out.reshape(-1, 9)
         return out
 
+    def train_proposal(self, n_iters):
+        tvmc_train_proposal(self.ctx, n_iters)
+
     def set(self, what, traj, values):
-        np_dt = np.complex128 if what == Q_THETA else np.uint64
+        np_dt = {Q_THETA: np.complex128, Q_AR_PARAMS: np.float32}.get(what, np.uint64)
         arr = np.ascontiguousarray(np.asarray(values, dtype=np_dt))
         _check(lib().tvmc_set(self.ctx, ctypes.c_int32(what), ctypes.c_int32(traj), arr.ctypes.data_as(ctypes.c_void_p),
                               ctypes.c_size_t(arr.nbytes)), self.ctx)
