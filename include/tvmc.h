@@ -59,7 +59,8 @@ enum { TVMC_SCHEME_HEUN = 0, TVMC_SCHEME_MIDPOINT = 1 };
  * FP64 only).  Solve and theta stay FP64 in both. */
 enum { TVMC_PREC_FP64 = 0, TVMC_PREC_MFMA = 1 };
 
-/* One Lindblad problem (Eq. 1 with the Hamiltonian of Eq. 10), shared by all trajectories. */
+/* One Lindblad problem (Eq. 1 with the Hamiltonian of Eq. 10), shared by all trajectories of a
+ * context (see tvmc_init_batch for one problem per trajectory). */
 typedef struct {
     int32_t n_sites;              /* N, 1..64 */
     const double *J;              /* host, N*N row-major, symmetric, zero diagonal */
@@ -139,6 +140,15 @@ tvmc_status tvmc_workspace_size(const tvmc_problem *problem, const tvmc_ansatz *
 tvmc_status tvmc_init(const tvmc_problem *problem, const tvmc_ansatz *ansatz, const tvmc_config *config,
                       const double *theta0, void *d_workspace, size_t workspace_bytes, void *stream,
                       tvmc_ctx **out);
+
+/* Batches with one problem per trajectory (n_problems = n_traj; 1 means shared): the problems
+ * must share N, hx and the jump channels (kind and site); J and the rates may differ.  Used
+ * for uneven batches (one context per system size, each on its own stream). */
+tvmc_status tvmc_workspace_size_batch(const tvmc_problem *problems, int32_t n_problems, const tvmc_ansatz *ansatz,
+                                      const tvmc_config *config, size_t *bytes);
+tvmc_status tvmc_init_batch(const tvmc_problem *problems, int32_t n_problems, const tvmc_ansatz *ansatz,
+                            const tvmc_config *config, const double *theta0, void *d_workspace,
+                            size_t workspace_bytes, void *stream, tvmc_ctx **out);
 
 /* Metropolis sampling of |psi|^2 at the current evaluation point (text after Eq. 9); at the
  * predictor stage it also draws the step's Wiener increments.  Requires the stage to be ready. */

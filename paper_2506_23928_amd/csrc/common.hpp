@@ -65,10 +65,11 @@ struct Dev {
     int burn, thin, init_sweeps, scheme, traj0;
     uint32_t key0, key1;
     double hx, dt, eps;
-    const double *J;          // [N*N]
+    const double *J;          // [N*N] or [T][N*N] (j_stride = N*N when each trajectory has its own)
+    size_t j_stride, r_stride;  // per-trajectory strides of J and of the jump rates (0: shared)
     const int *jkind;         // [nch]
     const int *jsite;         // [nch]
-    const double *jrate;      // [nch]
+    const double *jrate;      // [nch] or [T][nch]
     const int *pa;            // [M] first site of O_k (k < N: the site itself)
     const int *pb;            // [M] second site of O_k (-1 for one-body terms)
     double2 *theta, *theta_eval, *d0, *d1;   // [T][M]

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_channel_means(Dev a) {
         const int ch = c0 + q < a.nch ? c0 + q : a.nch - 1;
         kind[q] = a.jkind[ch];
         st[q] = a.jsite[ch];
-        sq[q] = sqrt(a.jrate[ch]);
+        sq[q] = sqrt(a.jrate[t * a.r_stride + ch]);
         re[q] = im[q] = 0.0;
     }
     for (int s = threadIdx.x; s < a.ns; s += blockDim.x) {
@@ -79,8 +79,8 @@ __global__ __launch_bounds__(256) void k_build_G(Dev a) {
     for (int ch = threadIdx.x; ch < a.nch; ch += blockDim.x) {
         skind[ch] = a.jkind[ch];
         ssite[ch] = a.jsite[ch];
-        srate[ch] = a.jrate[ch];
-        ssq[ch] = sqrt(a.jrate[ch]);
+        srate[ch] = a.jrate[t * a.r_stride + ch];
+        ssq[ch] = sqrt(a.jrate[t * a.r_stride + ch]);
         sdw[ch] = a.dw[(size_t)t * a.nch + ch];
         sc[ch] = 2.0 * (2.0 * a.bmean[(size_t)t * a.nch + ch].x);
     }

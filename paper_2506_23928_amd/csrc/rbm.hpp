@@ -173,7 +173,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
                     const double2 R = cmul(make_double2(pr, pi), make_double2(ex * cs, ex * sn));
                     a.R[sidx * n + lane] = R;
                     double hj = 0.0;
-                    for (int k = 0; k < n; ++k) hj += a.J[k * n + lane] * spin(mask, k);
+                    for (int k = 0; k < n; ++k) hj += a.J[t * a.j_stride + k * n + lane] * spin(mask, k);
                     ere = 0.5 * sl * hj + a.hx * R.x;
                     eim = a.hx * R.y;
                 }

@@ -61,7 +61,7 @@ int mom_blocks_for(int ns) {
 int n_params(int kind, int n, int nh) { return kind == TVMC_ANSATZ_RBM ? n + nh + n * nh : n + n * (n - 1) / 2; }
 int solve_dim(int kind, int m) { return kind == TVMC_ANSATZ_RBM ? 2 * m : m; }
 
-Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs, int ar, int ah) {
+Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs, int ar, int ah, int nprob) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -70,10 +70,10 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
         return at;
     };
     const size_t tt = (size_t)T;
-    L.J = take(sizeof(double) * n * n);
+    L.J = take(sizeof(double) * n * n * (size_t)nprob);
     L.jk = take(sizeof(int) * (nch + 1));
     L.js = take(sizeof(int) * (nch + 1));
-    L.jr = take(sizeof(double) * (nch + 1));
+    L.jr = take(sizeof(double) * (nch + 1) * (size_t)nprob);
     L.pa = take(sizeof(int) * m);
     L.pb = take(sizeof(int) * m);
     L.theta = take(sizeof(double2) * tt * m);
@@ -189,6 +189,23 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
         if (c->ar_hidden < 1 || c->ar_hidden > 256) return snprintf(msg, len, "ar_hidden must be in [1, 256]"), TVMC_E_INVAL;
         if (c->ar_train_every < 0 || c->ar_train_iters < 0 || !(c->ar_lr > 0.0))
             return snprintf(msg, len, "bad training settings"), TVMC_E_INVAL;
+    }
+    return TVMC_OK;
+}
+
+tvmc_status check_batch(const tvmc_problem *p, int np, const tvmc_ansatz *a, const tvmc_config *c, char *msg,
+                        size_t len) {
+    if (!p || np < 1) return snprintf(msg, len, "no problems"), TVMC_E_INVAL;
+    if (!c || (np != 1 && np != c->n_traj))
+        return snprintf(msg, len, "n_problems must be 1 or n_traj"), TVMC_E_INVAL;
+    for (int q = 0; q < np; ++q) {
+        tvmc_status st = check_args(p + q, a, c, msg, len);
+        if (st != TVMC_OK) return st;
+        if (p[q].n_sites != p[0].n_sites || p[q].n_jumps != p[0].n_jumps || p[q].hx != p[0].hx)
+            return snprintf(msg, len, "problems of one batch must share N, hx and the jump channels"), TVMC_E_INVAL;
+        for (int i = 0; i < p[0].n_jumps; ++i)
+            if (p[q].jump_kind[i] != p[0].jump_kind[i] || p[q].jump_site[i] != p[0].jump_site[i])
+                return snprintf(msg, len, "problems of one batch must share the jump channels"), TVMC_E_INVAL;
     }
     return TVMC_OK;
 }
@@ -480,26 +497,32 @@ size_t q_bytes(const tvmc_ctx *c, int what) {
 
 extern "C" {
 
-tvmc_status tvmc_workspace_size(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_config *c, size_t *bytes) {
-    tvmc_status st = check_args(p, a, c, g_err, sizeof(g_err));
+tvmc_status tvmc_workspace_size_batch(const tvmc_problem *p, int32_t np, const tvmc_ansatz *a, const tvmc_config *c,
+                                      size_t *bytes) {
+    tvmc_status st = check_batch(p, np, a, c, g_err, sizeof(g_err));
     if (st != TVMC_OK) return st;
     if (!bytes) return TVMC_E_INVAL;
     const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden);
     *bytes = layout(a->kind, n, a->n_hidden, m, p->n_jumps, c->n_traj, c->n_samples, c->n_chains, c->n_obs_max,
-                    c->proposal, c->ar_hidden).total;
+                    c->proposal, c->ar_hidden, np).total;
     return TVMC_OK;
 }
 
-tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_config *c, const double *theta0,
-                      void *ws, size_t ws_bytes, void *stream, tvmc_ctx **out) {
+tvmc_status tvmc_workspace_size(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_config *c, size_t *bytes) {
+    return tvmc_workspace_size_batch(p, 1, a, c, bytes);
+}
+
+tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansatz *a, const tvmc_config *c,
+                            const double *theta0, void *ws, size_t ws_bytes, void *stream, tvmc_ctx **out) {
     if (!out) return TVMC_E_INVAL;
     *out = nullptr;
-    tvmc_status st = check_args(p, a, c, g_err, sizeof(g_err));
+    tvmc_status st = check_batch(pbs, np, a, c, g_err, sizeof(g_err));
     if (st != TVMC_OK) return st;
+    const tvmc_problem *p = pbs;
     const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden), nch = p->n_jumps, T = c->n_traj;
     const int nh = a->kind == TVMC_ANSATZ_RBM ? a->n_hidden : 0;
     const Layout L = layout(a->kind, n, nh, m, nch, T, c->n_samples, c->n_chains, c->n_obs_max, c->proposal,
-                            c->ar_hidden);
+                            c->ar_hidden, np);
     if (!ws) return snprintf(g_err, sizeof(g_err), "workspace is null"), TVMC_E_INVAL;
     if (ws_bytes < L.total) return snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu", ws_bytes, L.total), TVMC_E_NOMEM;
     if ((uintptr_t)ws % 256) return snprintf(g_err, sizeof(g_err), "workspace must be 256-byte aligned"), TVMC_E_INVAL;
@@ -534,6 +557,8 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
     d.eps = c->diag_shift;
     d.mom_blocks = mom_blocks_for(c->n_samples);
     d.J = (const double *)(base + L.J);
+    d.j_stride = np > 1 ? (size_t)n * n : 0;
+    d.r_stride = np > 1 ? (size_t)nch : 0;
     d.jkind = (const int *)(base + L.jk);
     d.jsite = (const int *)(base + L.js);
     d.jrate = (const double *)(base + L.jr);
@@ -614,11 +639,16 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
             return fail(TVMC_E_DEVICE);                                                    \
         }                                                                                  \
     } while (0)
-    INITCHECK(hipMemcpyAsync((void *)d.J, p->J, sizeof(double) * n * n, hipMemcpyHostToDevice, ctx->stream));
+    for (int q = 0; q < np; ++q) {
+        INITCHECK(hipMemcpyAsync((void *)(d.J + (size_t)q * n * n), pbs[q].J, sizeof(double) * n * n,
+                                 hipMemcpyHostToDevice, ctx->stream));
+        if (nch > 0)
+            INITCHECK(hipMemcpyAsync((void *)(d.jrate + (size_t)q * nch), pbs[q].jump_rate, sizeof(double) * nch,
+                                     hipMemcpyHostToDevice, ctx->stream));
+    }
     if (nch > 0) {
         INITCHECK(hipMemcpyAsync((void *)d.jkind, p->jump_kind, sizeof(int) * nch, hipMemcpyHostToDevice, ctx->stream));
         INITCHECK(hipMemcpyAsync((void *)d.jsite, p->jump_site, sizeof(int) * nch, hipMemcpyHostToDevice, ctx->stream));
-        INITCHECK(hipMemcpyAsync((void *)d.jrate, p->jump_rate, sizeof(double) * nch, hipMemcpyHostToDevice, ctx->stream));
     }
     INITCHECK(hipMemcpyAsync((void *)d.pa, pa.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
     INITCHECK(hipMemcpyAsync((void *)d.pb, pb.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
@@ -638,6 +668,11 @@ tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_co
 #undef INITCHECK
     *out = ctx;
     return TVMC_OK;
+}
+
+tvmc_status tvmc_init(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_config *c, const double *theta0,
+                      void *ws, size_t ws_bytes, void *stream, tvmc_ctx **out) {
+    return tvmc_init_batch(p, 1, a, c, theta0, ws, ws_bytes, stream, out);
 }
 
 tvmc_status tvmc_sample(tvmc_ctx *c) {

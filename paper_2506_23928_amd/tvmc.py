@@ -52,7 +52,7 @@ class TvmcError(RuntimeError):
 
 
 _lib = None
-EXPORTED = ["tvmc_workspace_size", "tvmc_init", "tvmc_sample", "tvmc_estimate", "tvmc_sr_solve", "tvmc_update",
+EXPORTED = ["tvmc_workspace_size", "tvmc_init", "tvmc_workspace_size_batch", "tvmc_init_batch", "tvmc_sample", "tvmc_estimate", "tvmc_sr_solve", "tvmc_update",
             "tvmc_sde_step", "tvmc_train_proposal", "tvmc_observables", "tvmc_ensemble", "tvmc_get", "tvmc_set", "tvmc_position",
             "tvmc_synchronize", "tvmc_set_timing", "tvmc_timing", "tvmc_last_error", "tvmc_destroy"]
 
@@ -129,6 +129,31 @@ def tvmc_init(problem, ansatz, config, theta0, workspace_ptr, workspace_bytes, s
     return ctx
 
 
+def _problem_array(problems):
+    arr = (tvmc_problem * len(problems))(*[p.c() for p in problems])
+    return arr
+
+
+def tvmc_workspace_size_batch(problems, ansatz: tvmc_ansatz, config: tvmc_config) -> int:
+    b = ctypes.c_size_t(0)
+    arr = _problem_array(problems)
+    _check(lib().tvmc_workspace_size_batch(arr, ctypes.c_int32(len(problems)), ctypes.byref(ansatz),
+                                           ctypes.byref(config), ctypes.byref(b)))
+    return b.value
+
+
+def tvmc_init_batch(problems, ansatz, config, theta0, workspace_ptr, workspace_bytes, stream):
+    ctx = ctypes.c_void_p()
+    arr = _problem_array(problems)
+    th = None
+    if theta0 is not None:
+        th = np.ascontiguousarray(np.asarray(theta0, dtype=np.complex128)).view(np.float64)
+    _check(lib().tvmc_init_batch(arr, ctypes.c_int32(len(problems)), ctypes.byref(ansatz), ctypes.byref(config),
+                                 th.ctypes.data_as(_dp) if th is not None else None, ctypes.c_void_p(workspace_ptr),
+                                 ctypes.c_size_t(workspace_bytes), ctypes.c_void_p(stream), ctypes.byref(ctx)))
+    return ctx
+
+
 def tvmc_sample(ctx):
     _check(lib().tvmc_sample(ctx), ctx)
 
@@ -174,7 +199,9 @@ def tvmc_destroy(ctx):
 
 
 class Context:
-    """One batch of trajectories of one problem, with its workspace held as a torch tensor."""
+    """One batch of trajectories with its workspace held as a torch tensor.  `problem` is one
+    Problem shared by every trajectory, or a list of n_traj Problems (same N, hx and jump
+    channels; couplings and rates may differ per trajectory)."""
 
     _shapes = {Q_THETA: ("c", "m"), Q_THETA_EVAL: ("c", "m"), Q_DELTA0: ("c", "m"), Q_DELTA1: ("c", "m"),
                Q_SAMPLES: ("u8", "ns"), Q_ELOC: ("c", "ns"), Q_S: ("d", "mm"), Q_D: ("c", "m"), Q_OBAR: ("d", "m"),
@@ -187,16 +214,18 @@ class Context:
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required")
-        self.problem = problem
+        batch = isinstance(problem, (list, tuple))
+        self.problems = list(problem) if batch else [problem]
+        self.problem = self.problems[0]
         self.config = config
         self.ansatz = tvmc_ansatz(kind, n_hidden)
-        self.m = n_params(kind, problem.n, n_hidden)
-        nbytes = tvmc_workspace_size(problem, self.ansatz, config)
+        self.m = n_params(kind, self.problem.n, n_hidden)
+        nbytes = tvmc_workspace_size_batch(self.problems, self.ansatz, config)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         ptr = self.workspace.data_ptr()
         ptr += (-ptr) % 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(device=self.workspace.device)
-        self.ctx = tvmc_init(problem, self.ansatz, config, theta0, ptr, nbytes, self.stream.cuda_stream)
+        self.ctx = tvmc_init_batch(self.problems, self.ansatz, config, theta0, ptr, nbytes, self.stream.cuda_stream)
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)

@@ -63,3 +63,21 @@ def random_problem(n: int, seed: int, n_extra: int = 3):
     for _ in range(n_extra):
         js.append((int(rng.choice([SIGMA_PLUS, SIGMA_Z])), int(rng.integers(n)), float(rng.uniform(0.01, 0.1))))
     return J, hx, js
+
+
+# Uneven batch: open chains with N drawn uniformly from {16, 24, 32, 48, 64}, alpha ~ U[0.5, 3],
+# decay rate gamma ~ U[0.01, 0.2], per trajectory; h = 1; Jastrow; 2048 samples; Heun dt = 0.01
+# to t = 1.  The per-trajectory parameters come from numpy's seeded generator (they are inputs,
+# not random numbers of the method).
+UNEVEN = dict(sizes=(16, 24, 32, 48, 64), alpha=(0.5, 3.0), gamma=(0.01, 0.2), h=1.0, jscale=1.0, n_traj=512,
+              n_samples=2048, n_chains=64, dt=0.01, t_end=1.0, diag_shift=1e-4, burn_sweeps=2, thin_sweeps=1,
+              seed=0)
+
+
+def uneven_params(n_traj: int, seed: int = 0, w: dict = UNEVEN):
+    """Per-trajectory (N, alpha, gamma) of the uneven batch."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.array(w["sizes"]), size=n_traj)
+    alpha = rng.uniform(*w["alpha"], size=n_traj)
+    gamma = rng.uniform(*w["gamma"], size=n_traj)
+    return [(int(n), float(a), float(g)) for n, a, g in zip(ns, alpha, gamma)]
