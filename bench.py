@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 PEAKS = {  # MI355X published dense peaks
     "fp64": 78.6,            # TFLOP/s, vector and matrix
     "int8": 5000.0,          # TOP/s, matrix cores
+    "bf16": 2500.0,          # TFLOP/s, matrix cores
     "hbm": 8000.0,           # GB/s
 }
 
@@ -61,16 +62,30 @@ def read_traffic(kernel: str):
         return None
 
 
-def build_context(tv, w, precision, n_traj=None, traj_offset=0):
+def ansatz_of(tv, w):
+    """(kind, n_hidden, M, theta0) of a workload."""
+    import workloads as wl
+    if w.get("ansatz", "jastrow") == "rbm":
+        nh = w["n_hidden"]
+        return tv.RBM, nh, tv.n_params(tv.RBM, w["n"], nh), wl.rbm_theta0(w["n"], nh, w["w_scale"], w["seed"])
+    return tv.JASTROW, 0, tv.n_params(tv.JASTROW, w["n"]), None
+
+
+def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None):
     from paper_2506_23928_amd.problem import kac_couplings
     import workloads as wl
     J = kac_couplings(w["geom"], w["n"], w["alpha"], w["jscale"])
     prob = tv.Problem(J, w["h"], wl.jumps(w))
     steps = wl.n_steps(w)
+    kind, nh, _, th0 = ansatz_of(tv, w)
+    if proposal is None:
+        proposal = tv.PROPOSAL_LEARNED if w.get("proposal") == "learned" else tv.PROPOSAL_FLIP
     cfg = tv.make_config(n_traj or w["n_traj"], w["n_samples"], w["n_chains"], w["dt"], w["diag_shift"],
                          w["burn_sweeps"], w["thin_sweeps"], 0, tv.HEUN, precision, w["obs_every"],
-                         steps // w["obs_every"] + 2, w["seed"], traj_offset)
-    return tv.Context(prob, cfg)
+                         steps // w["obs_every"] + 2, w["seed"], traj_offset, proposal=proposal,
+                         ar_hidden=w.get("ar_hidden", 128), ar_train_every=w.get("ar_train_every", 20),
+                         ar_train_iters=w.get("ar_train_iters", 50), ar_lr=w.get("ar_lr", 3e-3))
+    return tv.Context(prob, cfg, kind=kind, n_hidden=nh, theta0=th0)
 
 
 def cpu_baseline(w, budget_s=30.0):
@@ -138,11 +153,13 @@ def main():
     import workloads as wl
     w = dict(wl.WORKLOADS[args.workload])
     w["name"] = args.workload
+    kind, nh, m, _ = ansatz_of(tv, w)
     prec = tv.PREC_MFMA if args.precision == "mfma" else tv.PREC_FP64
-    n, m, T = w["n"], tv.n_params(tv.JASTROW, w["n"]), w["n_traj"]
-    print("bench: workload %s N=%d M=%d trajectories=%d samples=%d chains=%d jumps=%d precision=%s" % (
-        args.workload, n, m, T, w["n_samples"], w["n_chains"], len(wl.jumps(w)), args.precision), file=sys.stderr,
-        flush=True)
+    n, T = w["n"], w["n_traj"]
+    me = 2 * m if kind == tv.RBM else m
+    print("bench: workload %s N=%d M=%d trajectories=%d samples=%d chains=%d jumps=%d precision=%s proposal=%s" % (
+        args.workload, n, m, T, w["n_samples"], w["n_chains"], len(wl.jumps(w)), args.precision,
+        w.get("proposal", "flip")), file=sys.stderr, flush=True)
 
     ctx = build_context(tv, w, prec)
     for _ in range(args.warmup):
@@ -158,7 +175,7 @@ def main():
     el = time.perf_counter() - t0
     ctx.synchronize()
     groups = {}
-    for g in ("sample", "estimate", "transpose", "sbuild", "solve", "update", "observe"):
+    for g in ("sample", "estimate", "transpose", "sbuild", "solve", "update", "observe", "train"):
         ms, cnt = ctx.timing(g)
         if cnt:
             groups[g] = {"avg_ms": ms, "launches": cnt, "total_ms": ms * cnt}
@@ -170,10 +187,24 @@ def main():
     # dominant kernel: the FP64 Cholesky solve (one launch covers every trajectory)
     dom = max(groups, key=lambda g: groups[g]["total_ms"])
     if dom == "solve":
-        flops = T * (m ** 3 / 3.0 + m * m / 2.0 + m / 6.0 + 4.0 * m * m)
+        flops = T * (me ** 3 / 3.0 + me * me / 2.0 + me / 6.0 + 4.0 * me * me)
         achieved = flops / (groups["solve"]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": "k_chol_solve", "bound": "mfma", "achieved": achieved, "peak": PEAKS["fp64"],
                 "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_chol_solve")}
+    elif dom == "sbuild" and kind == tv.RBM and prec == tv.PREC_MFMA:
+        # complex Hermitian S: M (M + 1) / 2 entries, N_s complex multiply-adds (8 flops) each,
+        # on BF16 matrix cores (three split products per real product)
+        flops = T * (m * (m + 1) / 2.0) * w["n_samples"] * 8.0
+        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_sbuild_rbm_bf16", "bound": "mfma", "achieved": achieved, "peak": PEAKS["bf16"] / 3.0,
+                "unit": "TFLOP/s", "frac": achieved / (PEAKS["bf16"] / 3.0), "traffic": read_traffic("k_sbuild_rbm_bf16"),
+                "note": "peak = BF16 dense peak / 3 (three split products per real product)"}
+    elif dom == "sbuild" and kind == tv.RBM:
+        # complex Hermitian S: M (M + 1) / 2 entries, N_s complex multiply-adds (8 flops) each
+        flops = T * (m * (m + 1) / 2.0) * w["n_samples"] * 8.0
+        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_sbuild_rbm_f64", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_sbuild_rbm_f64")}
     elif dom == "sbuild":
         ops = T * (m * (m + 1) / 2.0) * w["n_samples"] * 2.0
         achieved = ops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
@@ -188,7 +219,7 @@ def main():
     plain = None
     if not args.no_plain:
         # the plain form: FP64 S-build, one trajectory per launch
-        pctx = build_context(tv, w, tv.PREC_FP64, n_traj=1)
+        pctx = build_context(tv, w, tv.PREC_FP64, n_traj=1, proposal=tv.PROPOSAL_FLIP)
         pctx.sde_step(1)
         pctx.synchronize()
         torch.cuda.synchronize()
@@ -212,8 +243,10 @@ def main():
         "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "n_spins": n, "n_params": m, "n_traj": T, "n_samples": w["n_samples"],
-                   "n_chains": w["n_chains"], "n_jumps": len(wl.jumps(w)), "dt": w["dt"], "ansatz": "jastrow",
-                   "s_build": "int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU",
+                   "n_chains": w["n_chains"], "n_jumps": len(wl.jumps(w)), "dt": w["dt"],
+                   "ansatz": w.get("ansatz", "jastrow"), "n_hidden": nh, "proposal": w.get("proposal", "flip"),
+                   "s_build": ("int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU") if kind == tv.JASTROW
+                   else ("BF16-split MFMA, FP32 accumulate" if prec == tv.PREC_MFMA else "FP64 VALU (complex)"),
                    "solve": "FP64 Cholesky", "obs_every": w["obs_every"]},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -91,7 +91,7 @@ typedef struct {
     int32_t obs_every;            /* record moments at steps that are multiples of this (0: never) */
     int32_t n_obs_max;            /* capacity of the moment history */
     uint64_t seed;                /* Philox4x32-10 key */
-    /* learned proposal (Jastrow ansatz): a masked autoregressive network per trajectory, trained
+    /* learned proposal (either ansatz): a masked autoregressive network per trajectory, trained
      * on the trajectory's own samples, proposes one independent Metropolis-Hastings move at the
      * start of every sweep; single-spin flips remain the fallback */
     int32_t proposal;             /* TVMC_PROPOSAL_* */

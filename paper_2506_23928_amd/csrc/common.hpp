@@ -62,6 +62,8 @@ __host__ __device__ __forceinline__ int pair_index(int n, int j, int k) {
 struct Dev {
     int n, m, nch, ns, nc, per, nt, nobs;
     int kind, nh, me;         // ansatz (0 Jastrow, 1 RBM), hidden units, dimension of the real solve
+    int mp;                   // M rounded up to 64 (rows of the RBM's BF16 operand planes)
+    uint16_t *rbmP;           // RBM precision form: [T][4][mp][ns] BF16 split of the centred O
     int burn, thin, init_sweeps, scheme, traj0;
     uint32_t key0, key1;
     double hx, dt, eps;

@@ -11,6 +11,7 @@
 // [[Re S, -Im S], [Im S, Re S]] (lower triangle), solved by the real FP64 Cholesky.
 #pragma once
 #include "common.hpp"
+#include "made.hpp"
 
 namespace tvmc {
 
@@ -53,11 +54,12 @@ __global__ void k_prepare_rbm(Dev a, const double2 *__restrict__ src) {
     a.sT[((size_t)t * nh + j) * n + i] = make_double2(sh * cy, ch * sy);
 }
 
-template <int CPB, int QH>
+template <int CPB, int QH, bool AR>
 __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int stage, int burn) {
     __shared__ double lwr[64 * 64];
     __shared__ double lwi[64 * 64];
     __shared__ double2 tl[CPB][64 * QH];
+    __shared__ float arh_s[AR ? CPB : 1][AR ? 256 : 1];
     const int n = a.n, nh = a.nh;
     const int t = blockIdx.y;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -103,6 +105,12 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
     const size_t tbase = (size_t)t * a.ns;
     const double2 *cT = a.cT + (size_t)t * nh * n, *sT = a.sT + (size_t)t * nh * n;
 
+    // learned proposal: one independent proposal at the start of every sweep
+    int next_ar = 0;
+    uint32_t ar_idx = 0, ar_nacc = 0;
+    float lq_cur = 0.f;
+    bool lq_valid = false;
+
     for (int base = 0; base < total; base += 64) {
         uint32_t r[4];
         philox4x32_10((uint32_t)(base + lane), ctr1, (uint32_t)step, ctr3, a.key0, a.key1, r);
@@ -110,6 +118,48 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
         const double logu_l = log(u53(r[1], r[2]));
         const int cnt = (total - base) < 64 ? (total - base) : 64;
         for (int jj = 0; jj < cnt; ++jj) {
+            if (AR && base + jj == next_ar) {
+                next_ar += n;
+                float *hs = arh_s[AR ? w : 0];
+                if (!lq_valid) {
+                    lq_cur = ar_logq(a, t, mask, lane, hs);
+                    lq_valid = true;
+                }
+                float lqn;
+                double uacc;
+                const uint64_t mnew = ar_draw(a, t, ctr1, step, ar_idx++, lane, lqn, uacc);
+                // hidden pre-activations of s' (same summation order as at the start) and
+                // Re log psi(s') - Re log psi(s)
+                double ngr[QH], ngi[QH], nlc[QH], dsum = 0.0;
+                for (int q = 0; q < QH; ++q) {
+                    const int j = lane + 64 * q;
+                    ngr[q] = ngi[q] = nlc[q] = 0.0;
+                    if (j < nh) {
+                        double xr = th[n + j].x, xi = th[n + j].y;
+                        for (int i = 0; i < n; ++i) {
+                            const double si = spin(mnew, i);
+                            xr += wr[i * nh + j] * si;
+                            xi += wi[i * nh + j] * si;
+                        }
+                        ngr[q] = xr;
+                        ngi[q] = xi;
+                        nlc[q] = log_abs_cosh(xr, xi);
+                        dsum += nlc[q] - lc[q];
+                    }
+                }
+                if (lane < n) dsum += th[lane].x * (spin(mnew, lane) - spin(mask, lane));
+                const double dlog = 2.0 * wave_sum(dsum) + ((double)lq_cur - (double)lqn);
+                if (log(uacc) < dlog) {
+                    mask = mnew;
+                    for (int q = 0; q < QH; ++q) {
+                        gre[q] = ngr[q];
+                        gim[q] = ngi[q];
+                        lc[q] = nlc[q];
+                    }
+                    lq_cur = lqn;
+                    ++ar_nacc;
+                }
+            }
             const int i = __builtin_amdgcn_readlane(site_l, jj);
             const double lu = readlane_d(logu_l, jj);
             const double si = spin(mask, i);
@@ -134,6 +184,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
                     }
                 }
                 ++nacc;
+                lq_valid = false;
             }
             if (base + jj == next_rec) {
                 const size_t sidx = tbase + (size_t)c * a.per + rec;
@@ -189,6 +240,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
     if (lane == 0) {
         a.chains[(size_t)t * a.nc + c] = mask;
         a.acc[(size_t)t * a.nc + c] = nacc;
+        if (AR) a.aracc[(size_t)t * a.nc + c] = ar_nacc;
     }
 }
 

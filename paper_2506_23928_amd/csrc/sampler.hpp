@@ -60,35 +60,6 @@ __global__ void k_draw_dw(Dev a, int step) {
     }
 }
 
-__device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// log q(s) of the BF16 network for configuration mk (every lane returns the same value).
-// hs: this wave's LDS scratch of H floats.
-__device__ float ar_logq(const Dev &a, int t, uint64_t mk, int lane, float *hs) {
-    const int n = a.n, h = a.ah;
-    const float *b1 = a.arP + (size_t)t * a.arnp + (size_t)h * n;
-    const float *b2 = b1 + h + (size_t)n * h;
-    const uint16_t *W1 = a.arW1b + (size_t)t * h * n, *W2T = a.arW2Tb + (size_t)t * h * n;
-    for (int k = lane; k < h; k += 64) {
-        float x = b1[k];
-        const int dk = ar_degree(k, n);
-        for (int j = 0; j < dk; ++j) x += bf2f(W1[(size_t)k * n + j]) * (float)spin(mk, j);
-        hs[k] = fmaxf(x, 0.f);
-    }
-    float lq = 0.f;
-    if (lane < n) {
-        float l = b2[lane];
-        for (int k = 0; k < h; ++k)
-            if (ar_degree(k, n) <= lane) l += bf2f(W2T[(size_t)k * n + lane]) * hs[k];
-        lq = log_sigmoid_f((float)spin(mk, lane) * l);
-    }
-    return wave_sum_f(lq);
-}
-
 template <int CPB, bool AR>
 __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, int stage, int burn) {
     __shared__ double lre[64 * 64];
@@ -153,47 +124,9 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, in
                     lq_cur = ar_logq(a, t, mask, lane, hs);
                     lq_valid = true;
                 }
-                // Philox stream 6: 16 blocks of site uniforms, one block for the accept uniform
-                uint32_t rr[4] = {0u, 0u, 0u, 0u};
-                if (lane < 17)
-                    philox4x32_10(ar_idx * 17u + (uint32_t)lane, ctr1, (uint32_t)step,
-                                  (6u << 24) | (uint32_t)(a.traj0 + t), a.key0, a.key1, rr);
-                uint32_t word = 0u;
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const uint32_t v = (uint32_t)__shfl((int)rr[q4], lane >> 2, 64);
-                    if ((lane & 3) == q4) word = v;
-                }
-                const float usite = ((float)(word >> 8) + 0.5f) * (1.0f / 16777216.0f);
-                const double uacc = u53((uint32_t)__builtin_amdgcn_readlane((int)rr[0], 16),
-                                        (uint32_t)__builtin_amdgcn_readlane((int)rr[1], 16));
-                ++ar_idx;
-                // sample s' ~ q autoregressively
-                const int h = a.ah;
-                const float *b1 = a.arP + (size_t)t * a.arnp + (size_t)h * n;
-                const float *b2 = b1 + h + (size_t)n * h;
-                const uint16_t *W1 = a.arW1b + (size_t)t * h * n, *W2T = a.arW2Tb + (size_t)t * h * n;
-                float ak[4];
-                for (int q = 0; q < 4; ++q) ak[q] = (lane + 64 * q < h) ? b1[lane + 64 * q] : 0.f;
-                uint64_t mnew = 0ull;
-                float lqn = 0.f;
-                for (int ii = 0; ii < n; ++ii) {
-                    float part = 0.f;
-                    for (int q = 0; q < 4; ++q) {
-                        const int k = lane + 64 * q;
-                        if (k < h && ar_degree(k, n) <= ii) part += bf2f(W2T[(size_t)k * n + ii]) * fmaxf(ak[q], 0.f);
-                    }
-                    const float l = b2[ii] + wave_sum_f(part);
-                    const float pu = 1.f / (1.f + expf(-l));
-                    const float ui = __shfl(usite, ii, 64);
-                    const bool up = ui < pu;
-                    const float sv = up ? 1.f : -1.f;
-                    lqn += log_sigmoid_f(sv * l);
-                    if (up) mnew |= (1ull << ii);
-                    for (int q = 0; q < 4; ++q) {
-                        const int k = lane + 64 * q;
-                        if (k < h && ar_degree(k, n) > ii) ak[q] += bf2f(W1[(size_t)k * n + ii]) * sv;
-                    }
-                }
+                float lqn;
+                double uacc;
+                const uint64_t mnew = ar_draw(a, t, ctr1, step, ar_idx++, lane, lqn, uacc);
                 // fields of s' and Re log psi of both configurations
                 double nre = 0.0, nim = 0.0, lpc = 0.0, lpn = 0.0;
                 if (act) {

@@ -19,6 +19,7 @@
 #include "sampler.hpp"
 #include "sbuild.hpp"
 #include "sbuild_mfma.hpp"
+#include "sbuild_rbm_mfma.hpp"
 
 using namespace tvmc;
 
@@ -50,7 +51,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
         bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, rhs2, x2, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1b, arW2Tb, arh, arda,
-        arg, arlogq, arloss, aracc, total;
+        arg, arlogq, arloss, aracc, rbmP, total;
 };
 
 int mom_blocks_for(int ns) {
@@ -61,7 +62,7 @@ int mom_blocks_for(int ns) {
 int n_params(int kind, int n, int nh) { return kind == TVMC_ANSATZ_RBM ? n + nh + n * nh : n + n * (n - 1) / 2; }
 int solve_dim(int kind, int m) { return kind == TVMC_ANSATZ_RBM ? 2 * m : m; }
 
-Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs, int ar, int ah, int nprob) {
+Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs, int ar, int ah, int nprob, int prec) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -125,6 +126,8 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.arlogq = take(ar ? sizeof(float) * tt * ns : 0);
     L.arloss = take(sizeof(double) * tt);
     L.aracc = take(sizeof(uint32_t) * tt * nc);
+    const size_t mp = ((size_t)m + 63) / 64 * 64;
+    L.rbmP = take(rbm && prec == TVMC_PREC_MFMA ? sizeof(uint16_t) * tt * 4 * mp * ns : 0);
     L.total = o;
     return L;
 }
@@ -163,8 +166,6 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
     if (a->kind != TVMC_ANSATZ_JASTROW && a->kind != TVMC_ANSATZ_RBM) return snprintf(msg, len, "bad ansatz"), TVMC_E_INVAL;
     if (a->kind == TVMC_ANSATZ_RBM && (a->n_hidden < 1 || a->n_hidden > 256))
         return snprintf(msg, len, "RBM hidden units must be in [1, 256]"), TVMC_E_INVAL;
-    if (a->kind == TVMC_ANSATZ_RBM && c->precision == TVMC_PREC_MFMA)
-        return snprintf(msg, len, "the matrix-core S-build is implemented for the Jastrow ansatz only"), TVMC_E_UNSUPPORTED;
     if (c->n_traj < 1 || (int64_t)c->traj_offset + c->n_traj > (1 << 24) || c->traj_offset < 0)
         return snprintf(msg, len, "trajectory ids must lie in [0, 2^24)"), TVMC_E_INVAL;
     if (c->n_chains < 1 || c->n_samples < 1 || c->n_samples % c->n_chains)
@@ -184,8 +185,6 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
     if (c->proposal != TVMC_PROPOSAL_FLIP && c->proposal != TVMC_PROPOSAL_LEARNED)
         return snprintf(msg, len, "bad proposal"), TVMC_E_INVAL;
     if (c->proposal == TVMC_PROPOSAL_LEARNED) {
-        if (a->kind != TVMC_ANSATZ_JASTROW)
-            return snprintf(msg, len, "the learned proposal is implemented for the Jastrow ansatz"), TVMC_E_UNSUPPORTED;
         if (c->ar_hidden < 1 || c->ar_hidden > 256) return snprintf(msg, len, "ar_hidden must be in [1, 256]"), TVMC_E_INVAL;
         if (c->ar_train_every < 0 || c->ar_train_iters < 0 || !(c->ar_lr > 0.0))
             return snprintf(msg, len, "bad training settings"), TVMC_E_INVAL;
@@ -278,29 +277,20 @@ tvmc_status run_sample(tvmc_ctx *c) {
         Scope sc(c, "sample");
         dim3 grid(d.nc / c->cpb, T);
         const int qh = (d.nh + 63) / 64;
-#define RBM_LAUNCH(CPB, QH) hipLaunchKernelGGL((k_sample_rbm<CPB, QH>), grid, dim3(64 * CPB), 0, c->stream, d, c->step, c->stage, burn)
-        if (qh == 1) {
-            switch (c->cpb) {
-            case 8: RBM_LAUNCH(8, 1); break;
-            case 4: RBM_LAUNCH(4, 1); break;
-            case 2: RBM_LAUNCH(2, 1); break;
-            default: RBM_LAUNCH(1, 1); break;
-            }
-        } else if (qh == 2) {
-            switch (c->cpb) {
-            case 8: RBM_LAUNCH(8, 2); break;
-            case 4: RBM_LAUNCH(4, 2); break;
-            case 2: RBM_LAUNCH(2, 2); break;
-            default: RBM_LAUNCH(1, 2); break;
-            }
+#define RBM_LAUNCH(CPB, QH, AR) hipLaunchKernelGGL((k_sample_rbm<CPB, QH, AR>), grid, dim3(64 * CPB), 0, c->stream, d, c->step, c->stage, burn)
+#define RBM_CPB(QH, AR)                         \
+    switch (c->cpb) {                           \
+    case 8: RBM_LAUNCH(8, QH, AR); break;       \
+    case 4: RBM_LAUNCH(4, QH, AR); break;       \
+    case 2: RBM_LAUNCH(2, QH, AR); break;       \
+    default: RBM_LAUNCH(1, QH, AR); break;      \
+    }
+        if (d.ar) {
+            if (qh == 1) { RBM_CPB(1, true) } else if (qh == 2) { RBM_CPB(2, true) } else { RBM_CPB(4, true) }
         } else {
-            switch (c->cpb) {
-            case 8: RBM_LAUNCH(8, 4); break;
-            case 4: RBM_LAUNCH(4, 4); break;
-            case 2: RBM_LAUNCH(2, 4); break;
-            default: RBM_LAUNCH(1, 4); break;
-            }
+            if (qh == 1) { RBM_CPB(1, false) } else if (qh == 2) { RBM_CPB(2, false) } else { RBM_CPB(4, false) }
         }
+#undef RBM_CPB
 #undef RBM_LAUNCH
         LAUNCHCHECK(c, "k_sample_rbm");
         c->phase = 1;
@@ -357,10 +347,22 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         }
     }
     if (d.kind == TVMC_ANSATZ_RBM) {
-        Scope sc(c, "sbuild");
-        const int nt = (d.m + RB_T - 1) / RB_T;
-        hipLaunchKernelGGL(k_sbuild_rbm_f64, dim3(nt * (nt + 1) / 2, T), dim3(256), 0, c->stream, d);
-        LAUNCHCHECK(c, "k_sbuild_rbm_f64");
+        if (c->cfg.precision == TVMC_PREC_MFMA) {
+            {
+                Scope sc(c, "transpose");
+                hipLaunchKernelGGL(k_rbm_split, dim3((d.ns + 255) / 256, d.mp, T), dim3(256), 0, c->stream, d);
+                LAUNCHCHECK(c, "k_rbm_split");
+            }
+            Scope sc(c, "sbuild");
+            const int nt = d.mp / RQ_T;
+            hipLaunchKernelGGL(k_sbuild_rbm_bf16, dim3(nt * (nt + 1) / 2, T), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_sbuild_rbm_bf16");
+        } else {
+            Scope sc(c, "sbuild");
+            const int nt = (d.m + RB_T - 1) / RB_T;
+            hipLaunchKernelGGL(k_sbuild_rbm_f64, dim3(nt * (nt + 1) / 2, T), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_sbuild_rbm_f64");
+        }
         c->phase = 2;
         return TVMC_OK;
     }
@@ -504,7 +506,7 @@ tvmc_status tvmc_workspace_size_batch(const tvmc_problem *p, int32_t np, const t
     if (!bytes) return TVMC_E_INVAL;
     const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden);
     *bytes = layout(a->kind, n, a->n_hidden, m, p->n_jumps, c->n_traj, c->n_samples, c->n_chains, c->n_obs_max,
-                    c->proposal, c->ar_hidden, np).total;
+                    c->proposal, c->ar_hidden, np, c->precision).total;
     return TVMC_OK;
 }
 
@@ -522,7 +524,7 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden), nch = p->n_jumps, T = c->n_traj;
     const int nh = a->kind == TVMC_ANSATZ_RBM ? a->n_hidden : 0;
     const Layout L = layout(a->kind, n, nh, m, nch, T, c->n_samples, c->n_chains, c->n_obs_max, c->proposal,
-                            c->ar_hidden, np);
+                            c->ar_hidden, np, c->precision);
     if (!ws) return snprintf(g_err, sizeof(g_err), "workspace is null"), TVMC_E_INVAL;
     if (ws_bytes < L.total) return snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu", ws_bytes, L.total), TVMC_E_NOMEM;
     if ((uintptr_t)ws % 256) return snprintf(g_err, sizeof(g_err), "workspace must be 256-byte aligned"), TVMC_E_INVAL;
@@ -588,6 +590,8 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.cT = (double2 *)(base + L.cT);
     d.sT = (double2 *)(base + L.sT);
     d.tt = (double2 *)(base + L.tt);
+    d.mp = (m + 63) / 64 * 64;
+    d.rbmP = (uint16_t *)(base + L.rbmP);
     d.rhs2 = (double2 *)(base + L.rhs2);
     d.x2 = (double2 *)(base + L.x2);
     d.D = (double2 *)(base + L.D);

@@ -129,3 +129,35 @@ def test_learned_proposal_crosses_modes_single_flips_cannot(tv):
         switches[learned] = int(np.sum(mag[:, 1:] != mag[:, :-1]))
     assert switches[False] <= 2, switches
     assert switches[True] > 100, switches
+
+
+def test_learned_chain_rbm_samples_psi_squared(tv):
+    """The same exactness check with the RBM ansatz (N = 7, N' = 5): the learned independent
+    moves and the single flips together must sample |psi_RBM|^2."""
+    import oracle.exact as ex
+    from paper_2506_23928_amd import tvmc as T
+    n, nh, h, ns, nc = 7, 5, 32, 32768, 64
+    m = n + nh + n * nh
+    th0 = wl.random_theta(m, 0.3, seed=12)
+    J, _, jumps = wl.random_problem(n, seed=n)
+    cfg = tv.make_config(1, ns, nc, 0.01, 1e-3, 2, 1, 20, seed=4, proposal=tv.PROPOSAL_LEARNED, ar_hidden=h,
+                         ar_train_every=0, ar_train_iters=20, ar_lr=1e-2)
+    ctx = tv.Context(tv.Problem(J, 0.6, jumps), cfg, kind=tv.RBM, n_hidden=nh, theta0=th0)
+    ctx.sample()
+    ctx.train_proposal(60)
+    ctx.estimate()
+    ctx.sr_solve()
+    ctx.update()
+    ctx.sample()       # the corrector point, sampled with the trained network
+    ctx.synchronize()
+    th_e = ctx.get(T.Q_THETA_EVAL, 0)
+    smp = tv.unpack_samples(ctx.get(T.Q_SAMPLES, 0), n)
+    idx = ((smp > 0).astype(np.int64) * (1 << np.arange(n))).sum(1)
+    counts = np.bincount(idx, minlength=1 << n)
+    p = np.abs(ex.rbm_psi(n, nh)(th_e)) ** 2
+    p /= p.sum()
+    e = p * ns
+    chi2 = np.sum((counts - e) ** 2 / e)
+    assert chi2 < 2.0 * (1 << n), chi2
+    ar = ctx.get(T.Q_AR_ACCEPTS, 0)
+    assert ar.sum() > 0.2 * nc * (ns // nc + 2), ar.sum()

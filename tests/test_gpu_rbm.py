@@ -141,3 +141,95 @@ def test_rbm_weights_from_global_memory(tv, orc):
     assert _rel(ctx.get(T.Q_ELOC, 0), r["eloc"]) < 1e-12
     assert _rel(ctx.get(T.Q_BMEAN, 0), r["bmean"]) < 1e-12
     assert _rel(ctx.get(T.Q_D, 0), r["D"]) < 1e-11
+
+
+def _bf16_bound(Sref, ns):
+    """Entry-wise bound of the BF16-split S-build: the split of each operand keeps 2^-17 of it,
+    the dropped lo*lo term is below 2^-16 of a product, and the FP32 sum of N_s products adds
+    at most N_s 2^-24 of the sum of magnitudes, which the centred second moments bound by
+    Cauchy-Schwarz: |dS_kl| <= (2^-15 + N_s 2^-24) sqrt(S_kk S_ll)."""
+    d = np.sqrt(np.abs(np.diag(Sref).real))
+    return (2.0 ** -15 + ns * 2.0 ** -24) * np.outer(d, d) + 1e-15
+
+
+@pytest.mark.parametrize("n,nh,ns,nc", [(5, 3, 128, 4), (6, 70, 256, 8)])
+def test_rbm_bf16_sbuild_matches_oracle(tv, orc, n, nh, ns, nc):
+    """The matrix-core precision form of the RBM S against the oracle's FP64 S on the same
+    (bit-exact) samples, entry by entry within the split/accumulation bound; one tile (M = 23)
+    and a ragged 8x8 tile grid (M = 496)."""
+    from paper_2506_23928_amd import tvmc as T
+    J, hx, jumps = wl.random_problem(n, seed=60 + n)
+    m = orc.n_params(1, n, nh)
+    th0 = wl.random_theta(m, 0.2, seed=nh + 1)
+    seed, dt, eps = 8, 0.01, 1e-3
+    cfg_o = orc.Config(n_samples=ns, n_chains=nc, burn_sweeps=2, thin_sweeps=1, dt=dt, diag_shift=eps, seed=seed)
+    pb = orc.Problem(J, hx, jumps)
+    cfg = tv.make_config(2, ns, nc, dt, eps, 2, 1, 0, tv.HEUN, tv.PREC_MFMA, seed=seed)
+    ctx = tv.Context(tv.Problem(J, hx, jumps), cfg, kind=tv.RBM, n_hidden=nh, theta0=th0)
+    ctx.sample()
+    ctx.estimate()
+    Ss = [ctx.get(T.Q_S, t) for t in range(2)]      # the solve factorises S in place
+    ctx.sr_solve()
+    ctx.synchronize()
+    for t in range(2):
+        chains = orc.init_chains(seed, t, n, nc)
+        dw = orc.draw_dw(seed, t, 0, len(jumps), dt)
+        r = orc.evaluate(pb, 1, nh, cfg_o, th0, chains, traj=t, first=True, dw=dw, want_moments=False)
+        assert np.array_equal(tv.unpack_samples(ctx.get(T.Q_SAMPLES, t), n), r["samples"])
+        S = Ss[t]
+        E = _embed(r["S"] + eps * np.eye(m))
+        B = _bf16_bound(r["S"], ns)
+        Bb = np.block([[B, B], [B, B]])
+        low = np.tril_indices(2 * m)
+        err = np.abs(S[low] - E[low])
+        assert np.all(err <= Bb[low]), (err / Bb[low]).max()
+        assert _rel(ctx.get(T.Q_D, t), r["D"]) < 1e-12
+        # the FP64 solve of the BF16 S: its own residual
+        Sf = np.tril(S) + np.tril(S, -1).T
+        x = ctx.get(T.Q_DELTA0, t)
+        xe = np.concatenate([x.real, x.imag])
+        De = np.concatenate([r["D"].real, r["D"].imag])
+        assert np.abs(Sf @ xe - De).max() < 1e-9 * np.abs(De).max()
+
+
+def test_rbm_bf16_full_size_launch(tv, orc):
+    """The N = 64 RBM workload with the learned proposal in the launch configuration the
+    benchmark times (64 trajectories, 8192 samples, N' = 64, M = 4224, BF16-split S).  The
+    oracle has no learned sampler, so on the GPU's own samples of the first and last
+    trajectory: <O_k> and ~1800 S entries (60 sampled parameters, every pair) against FP64 sums
+    over the oracle's log-derivatives, within the split/accumulation bound."""
+    from paper_2506_23928_amd import tvmc as T
+    import bench
+    w = dict(wl.WORKLOADS["chain64_rbm_learned"])
+    ctx = bench.build_context(tv, w, tv.PREC_MFMA)
+    n, nh, ns, TT = w["n"], w["n_hidden"], w["n_samples"], w["n_traj"]
+    m = orc.n_params(1, n, nh)
+    ctx.sample()
+    ctx.estimate()
+    Ss = {t: ctx.get(T.Q_S, t) for t in (0, TT - 1)}      # the solve factorises S in place
+    ctx.sr_solve()
+    ctx.synchronize()
+    th0 = wl.rbm_theta0(n, nh, w["w_scale"], w["seed"])
+    rng = np.random.default_rng(1)
+    for t in (0, TT - 1):
+        smp = tv.unpack_samples(ctx.get(T.Q_SAMPLES, t), n)
+        O = np.zeros((ns, 60), np.complex128)
+        ks = np.concatenate([[0, n, n + nh, m - 1], rng.integers(0, m, 56)])
+        for s in range(ns):
+            O[s] = orc.local_quantities(1, n, nh, th0, smp[s], two_flip=False)[2][ks]
+        Oc = O - O.mean(0)
+        Sref = Oc.conj().T @ Oc / ns
+        S = Ss[t]
+        B = _bf16_bound(Sref, ns)
+        for a_ in range(60):
+            for b_ in range(60):
+                k, l = ks[a_], ks[b_]
+                if l > k:
+                    continue
+                want = Sref[a_, b_] + (w["diag_shift"] if k == l else 0.0)
+                assert abs(S[k, l] - want.real) <= B[a_, b_], (k, l)
+                if k != l:
+                    assert abs(S[m + k, l] - want.imag) <= B[a_, b_], (k, l)
+        assert _rel(ctx.get(T.Q_OBAR, t)[ks], O.mean(0)) < 1e-12
+        x = ctx.get(T.Q_DELTA0, t)
+        assert np.all(np.isfinite(x))

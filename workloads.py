@@ -28,7 +28,28 @@ WORKLOADS = {
     "chain64_jastrow_h0": dict(geom="obc", n=64, alpha=1.5, jscale=1.0, h=0.0, decay=0.1, dephase=0.0,
                                ansatz="jastrow", n_samples=4096, n_chains=64, n_traj=256, dt=0.005, t_end=1.0,
                                diag_shift=1e-4, obs_every=20, burn_sweeps=2, thin_sweeps=1, seed=1),
+    # N=64 open chain, decay only, RBM with N' = 64 hidden units (4224 complex parameters),
+    # 8192 samples x 64 trajectories, masked autoregressive proposal (128 hidden units) retrained
+    # every 20 steps; h = 0 (App. D is exact there) and h = 0.5
+    "chain64_rbm_learned": dict(geom="obc", n=64, alpha=1.5, jscale=1.0, h=0.0, decay=0.1, dephase=0.0,
+                                ansatz="rbm", n_hidden=64, n_samples=8192, n_chains=64, n_traj=64, dt=0.01,
+                                t_end=1.0, diag_shift=1e-4, obs_every=10, burn_sweeps=2, thin_sweeps=1, seed=0,
+                                proposal="learned", ar_hidden=128, ar_train_every=20, ar_train_iters=50,
+                                ar_lr=3e-3, w_scale=0.01),
+    "chain64_rbm_learned_h05": dict(geom="obc", n=64, alpha=1.5, jscale=1.0, h=0.5, decay=0.1, dephase=0.0,
+                                    ansatz="rbm", n_hidden=64, n_samples=8192, n_chains=64, n_traj=64, dt=0.01,
+                                    t_end=1.0, diag_shift=1e-4, obs_every=10, burn_sweeps=2, thin_sweeps=1, seed=0,
+                                    proposal="learned", ar_hidden=128, ar_train_every=20, ar_train_iters=50,
+                                    ar_lr=3e-3, w_scale=0.01),
 }
+
+
+def rbm_theta0(n: int, nh: int, scale: float, seed: int) -> np.ndarray:
+    """RBM start: a = b = 0, w_ij = scale (z1 + i z2) with z standard normal (seeded); the same
+    for every trajectory."""
+    th = np.zeros(n + nh + n * nh, np.complex128)
+    th[n + nh:] = random_theta(n * nh, scale, seed)
+    return th
 
 
 def jumps(w: dict):
