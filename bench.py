@@ -71,7 +71,7 @@ def ansatz_of(tv, w):
     return tv.JASTROW, 0, tv.n_params(tv.JASTROW, w["n"]), None
 
 
-def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None):
+def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, solver=0):
     from paper_2506_23928_amd.problem import kac_couplings
     import workloads as wl
     J = kac_couplings(w["geom"], w["n"], w["alpha"], w["jscale"])
@@ -84,7 +84,7 @@ def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None):
                          w["burn_sweeps"], w["thin_sweeps"], 0, tv.HEUN, precision, w["obs_every"],
                          steps // w["obs_every"] + 2, w["seed"], traj_offset, proposal=proposal,
                          ar_hidden=w.get("ar_hidden", 128), ar_train_every=w.get("ar_train_every", 20),
-                         ar_train_iters=w.get("ar_train_iters", 50), ar_lr=w.get("ar_lr", 3e-3))
+                         ar_train_iters=w.get("ar_train_iters", 50), ar_lr=w.get("ar_lr", 3e-3), solver=solver)
     return tv.Context(prob, cfg, kind=kind, n_hidden=nh, theta0=th0)
 
 
@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="chain64_jastrow")
     ap.add_argument("--precision", choices=["mfma", "fp64"], default="mfma")
+    ap.add_argument("--solver", choices=["auto", "one", "multi"], default="auto",
+                    help="FP64 Cholesky with one or several workgroups per trajectory (auto: by batch size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -161,7 +163,8 @@ def main():
         args.workload, n, m, T, w["n_samples"], w["n_chains"], len(wl.jumps(w)), args.precision,
         w.get("proposal", "flip")), file=sys.stderr, flush=True)
 
-    ctx = build_context(tv, w, prec)
+    solver = {"auto": tv.tvmc.SOLVER_AUTO, "one": tv.tvmc.SOLVER_ONE_GROUP, "multi": tv.tvmc.SOLVER_MULTI_GROUP}[args.solver]
+    ctx = build_context(tv, w, prec, solver=solver)
     for _ in range(args.warmup):
         ctx.sde_step(1)
     ctx.synchronize()
@@ -189,7 +192,9 @@ def main():
     if dom == "solve":
         flops = T * (me ** 3 / 3.0 + me * me / 2.0 + me / 6.0 + 4.0 * me * me)
         achieved = flops / (groups["solve"]["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": "k_chol_solve", "bound": "mfma", "achieved": achieved, "peak": PEAKS["fp64"],
+        multi = args.solver == "multi" or (args.solver == "auto" and T < 192)
+        roof = {"kernel": "k_cmw_* (solve)" if multi else "k_chol_solve", "bound": "mfma", "achieved": achieved,
+                "peak": PEAKS["fp64"],
                 "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_chol_solve")}
     elif dom == "sbuild" and kind == tv.RBM and prec == tv.PREC_MFMA:
         # complex Hermitian S: M (M + 1) / 2 entries, N_s complex multiply-adds (8 flops) each,
@@ -247,7 +252,7 @@ def main():
                    "ansatz": w.get("ansatz", "jastrow"), "n_hidden": nh, "proposal": w.get("proposal", "flip"),
                    "s_build": ("int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU") if kind == tv.JASTROW
                    else ("BF16-split MFMA, FP32 accumulate" if prec == tv.PREC_MFMA else "FP64 VALU (complex)"),
-                   "solve": "FP64 Cholesky", "obs_every": w["obs_every"]},
+                   "solve": "FP64 Cholesky", "solver": args.solver, "obs_every": w["obs_every"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_form_value": plain,

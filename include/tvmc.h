@@ -99,9 +99,14 @@ typedef struct {
     int32_t ar_train_every;       /* train at steps that are multiples of this (0: only on request) */
     int32_t ar_train_iters;       /* Adam steps per training */
     double ar_lr;                 /* Adam learning rate */
+    int32_t solver;               /* TVMC_SOLVER_*: how the regularised system is solved */
 } tvmc_config;
 
 enum { TVMC_PROPOSAL_FLIP = 0, TVMC_PROPOSAL_LEARNED = 1 };
+/* FP64 Cholesky of S + eps I: one workgroup per trajectory (one launch per solve), or several
+ * workgroups per trajectory (a few launches per 64-column panel), which fills the device when
+ * the batch has fewer trajectories than compute units; AUTO picks by batch size. */
+enum { TVMC_SOLVER_AUTO = 0, TVMC_SOLVER_ONE_GROUP = 1, TVMC_SOLVER_MULTI_GROUP = 2 };
 
 /* Quantities readable with tvmc_get (per trajectory unless noted). */
 enum {

@@ -1,0 +1,264 @@
+// Regularised solve (S + eps I) delta = D in FP64 with several workgroups per trajectory, for
+// batches too small to fill the device with one workgroup per trajectory.  The factorisation
+// is the same left-looking panel algorithm as k_chol_solve, split into one launch per step so
+// that the row chunks of a panel run on different compute units:
+//   k_cmw_update(j0):  C[rows, panel] = A[rows, panel] - L[rows, 0:j0] L[panel, 0:j0]^T
+//                      (every chunk of CR rows at or below the panel; FP64 MFMA)
+//   k_cmw_diag(j0):    factor the diagonal block, invert it (Linv), forward substitution of
+//                      the panel's part of the right-hand side (one workgroup per trajectory)
+//   k_cmw_trsm(j0):    L[rows, panel] = C Linv^T for the chunks below, and the right-hand side
+//                      update z[rows] -= L[rows, panel] y_panel
+//   k_cmw_backward:    backward substitution L^T x = y with the stored block inverses.
+#pragma once
+#include "cholesky.hpp"
+
+namespace tvmc {
+
+__global__ __launch_bounds__(256) void k_cmw_init(CholArgs a) {
+    const int t = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < a.m) a.x[(size_t)t * a.m + i] = a.rhs[(size_t)t * a.m + i];
+}
+
+__global__ __launch_bounds__(256) void k_cmw_update(CholArgs a, int j0) {
+    __shared__ double As[CR * CKP];
+    __shared__ double Bs[CN * CKP];
+    const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int M = a.m;
+    const int r0 = j0 + blockIdx.x * CR;
+    if (r0 >= M) return;
+    const int jb = (M - j0) < CN ? (M - j0) : CN;
+    double *A = a.A + (size_t)t * M * M;
+    v4d acc[2][4];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 4; ++v)
+            for (int r = 0; r < 4; ++r) {
+                const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
+                acc[u][v][r] = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : 0.0;
+            }
+    double pa[CR * CK / 256], pb[CN * CK / 256];
+    auto fetch = [&](int kc) {
+        for (int q = 0; q < CR * CK / 256; ++q) {
+            const int e = tid + 256 * q, rr = e / CK, kk = e % CK;
+            pa[q] = (r0 + rr < M) ? A[(size_t)(r0 + rr) * M + kc + kk] : 0.0;
+        }
+        for (int q = 0; q < CN * CK / 256; ++q) {
+            const int e = tid + 256 * q, cc = e / CK, kk = e % CK;
+            pb[q] = (cc < jb) ? A[(size_t)(j0 + cc) * M + kc + kk] : 0.0;
+        }
+    };
+    fetch(0);
+    for (int kc = 0; kc < j0; kc += CK) {
+        __syncthreads();
+        for (int q = 0; q < CR * CK / 256; ++q) {
+            const int e = tid + 256 * q;
+            As[(e / CK) * CKP + e % CK] = -pa[q];
+        }
+        for (int q = 0; q < CN * CK / 256; ++q) {
+            const int e = tid + 256 * q;
+            Bs[(e / CK) * CKP + e % CK] = pb[q];
+        }
+        __syncthreads();
+        if (kc + CK < j0) fetch(kc + CK);
+        for (int ks = 0; ks < CK / 4; ++ks) {
+            double fa[2], fb[4];
+            for (int u = 0; u < 2; ++u) fa[u] = As[(wave * 32 + u * 16 + li) * CKP + ks * 4 + lk];
+            for (int v = 0; v < 4; ++v) fb[v] = Bs[(v * 16 + li) * CKP + ks * 4 + lk];
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 4; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[v], acc[u][v], 0, 0, 0);
+        }
+    }
+    // every read of the panel columns above happened before the last barrier of the k loop
+    // or belongs to this workgroup's own rows; chunks of other workgroups are disjoint
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 4; ++v)
+            for (int r = 0; r < 4; ++r) {
+                const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
+                if (r0 + row < M && col < jb) A[(size_t)(r0 + row) * M + j0 + col] = acc[u][v][r];
+            }
+}
+
+__global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p) {
+    __shared__ double Cs[CN * CSP];
+    __shared__ double Ls[CN * CSP];
+    __shared__ double yre[CN], yim[CN];
+    __shared__ int bad;
+    const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int M = a.m;
+    const int jb = (M - j0) < CN ? (M - j0) : CN;
+    double *A = a.A + (size_t)t * M * M;
+    double2 *z = a.x + (size_t)t * M;
+    if (tid == 0) bad = 0;
+    for (int e = tid; e < CN * CN; e += 256) {
+        const int r = e / CN, c = e % CN;
+        Cs[r * CSP + c] = (r < jb && c <= r) ? A[(size_t)(j0 + r) * M + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    // right-looking factor of the block in LDS; thread (row fr, phase fs) updates columns fs,
+    // fs+4, ... of its row; column c is read unscaled during step c and scaled after the barrier
+    {
+        const int fr = tid >> 2, fs = tid & 3;
+        for (int c = 0; c < jb; ++c) {
+            const double piv = Cs[c * CSP + c];
+            if (tid == 0 && !(piv > 0.0)) bad = 1;
+            const double d = sqrt(piv), inv = 1.0 / d;
+            double lrc = 0.0;
+            if (fr > c && fr < jb) {
+                lrc = Cs[fr * CSP + c] * inv;
+                for (int k = c + 1 + fs; k <= fr; k += 4) Cs[fr * CSP + k] -= lrc * (Cs[k * CSP + c] * inv);
+            }
+            __syncthreads();
+            if (fs == 0 && fr > c && fr < jb) Cs[fr * CSP + c] = lrc;
+            if (tid == 0) Cs[c * CSP + c] = d;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < jb * jb; e += 256) {
+        const int r = e / jb, c = e % jb;
+        if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
+    }
+    // Linv by forward substitution: wave w owns columns 16w..16w+15, four lanes per column
+    {
+        const int c = wave * 16 + (lane >> 2), fs = lane & 3;
+        for (int r = fs; r < CN; r += 4) Ls[r * CSP + c] = 0.0;
+        if (c < jb) {
+            if (fs == 0) Ls[c * CSP + c] = 1.0 / Cs[c * CSP + c];
+            for (int r = c + 1; r < jb; ++r) {
+                double sum = 0.0;
+                for (int k = c + fs; k < r; k += 4) sum += Cs[r * CSP + k] * Ls[k * CSP + c];
+                sum += __shfl_xor(sum, 1, 64);
+                sum += __shfl_xor(sum, 2, 64);
+                if (fs == 0) Ls[r * CSP + c] = -sum / Cs[r * CSP + r];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < jb) {
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k <= tid; ++k) {
+            const double l = Ls[tid * CSP + k];
+            const double2 zk = z[j0 + k];
+            sr += l * zk.x;
+            si += l * zk.y;
+        }
+        yre[tid] = sr;
+        yim[tid] = si;
+    }
+    double *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
+    for (int e = tid; e < CN * CN; e += 256) lv[e] = Ls[(e / CN) * CSP + e % CN];
+    __syncthreads();
+    if (tid < jb) z[j0 + tid] = make_double2(yre[tid], yim[tid]);
+    if (tid == 0 && bad) a.flags[t] = 1;
+}
+
+// rows below the diagonal block: X = C Linv^T (B[k][j] = Linv[j][k]) and z[rows] -= X y
+__global__ __launch_bounds__(256) void k_cmw_trsm(CholArgs a, int j0, int p) {
+    __shared__ double Ls[CN * CSP];
+    __shared__ double yre[CN], yim[CN];
+    const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int M = a.m;
+    const int jb = (M - j0) < CN ? (M - j0) : CN;
+    const int r0 = j0 + jb + blockIdx.x * CR;
+    if (r0 >= M) return;
+    double *A = a.A + (size_t)t * M * M;
+    double2 *z = a.x + (size_t)t * M;
+    const double *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
+    for (int e = tid; e < CN * CN; e += 256) Ls[(e / CN) * CSP + e % CN] = lv[e];
+    if (tid < CN) {
+        const double2 y = tid < jb ? z[j0 + tid] : make_double2(0.0, 0.0);
+        yre[tid] = y.x;
+        yim[tid] = y.y;
+    }
+    __syncthreads();
+    v4d x[2][4];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 4; ++v) x[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; ks < CN / 4; ++ks) {
+        double fa[2], fb[4];
+        for (int u = 0; u < 2; ++u) {
+            const int row = r0 + wave * 32 + u * 16 + li, col = ks * 4 + lk;
+            fa[u] = (row < M && col < jb) ? A[(size_t)row * M + j0 + col] : 0.0;
+        }
+        for (int v = 0; v < 4; ++v) fb[v] = Ls[(v * 16 + li) * CSP + ks * 4 + lk];
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 4; ++v) x[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[v], x[u][v], 0, 0, 0);
+    }
+    // every lane has finished reading C before any lane overwrites it
+    __syncthreads();
+    for (int u = 0; u < 2; ++u)
+        for (int r = 0; r < 4; ++r) {
+            const int row = r0 + wave * 32 + u * 16 + lk + 4 * r;
+            double sr = 0.0, si = 0.0;
+            for (int v = 0; v < 4; ++v) {
+                const int col = v * 16 + li;
+                const double xv = x[u][v][r];
+                if (row < M && col < jb) A[(size_t)row * M + j0 + col] = xv;
+                sr += xv * yre[col];
+                si += xv * yim[col];
+            }
+            // sum over the 16 lanes li that hold this row
+            for (int o = 1; o < 16; o <<= 1) {
+                sr += __shfl_xor(sr, o, 64);
+                si += __shfl_xor(si, o, 64);
+            }
+            if (li == 0 && row < M) {
+                const double2 zr = z[row];
+                z[row] = make_double2(zr.x - sr, zr.y - si);
+            }
+        }
+}
+
+// backward substitution L^T x = y, last panel first; wave w owns 16 panel columns
+__global__ __launch_bounds__(256) void k_cmw_backward(CholArgs a) {
+    __shared__ double yre[CN], yim[CN];
+    const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int M = a.m;
+    const double *A = a.A + (size_t)t * M * M;
+    const double *linv = a.linv + (size_t)t * chol_panels(M) * CN * CN;
+    double2 *z = a.x + (size_t)t * M;
+    for (int p = chol_panels(M) - 1; p >= 0; --p) {
+        const int j0 = p * CN, jb = (M - j0) < CN ? (M - j0) : CN;
+        double sr[16], si[16];
+        for (int q = 0; q < 16; ++q) sr[q] = si[q] = 0.0;
+        for (int r = j0 + jb + lane; r < M; r += 64) {
+            const double2 xr = z[r];
+            const double *row = A + (size_t)r * M + j0 + wave * 16;
+            for (int q = 0; q < 16; ++q) {
+                const double l = (wave * 16 + q < jb) ? row[q] : 0.0;
+                sr[q] += l * xr.x;
+                si[q] += l * xr.y;
+            }
+        }
+        for (int q = 0; q < 16; ++q) {
+            const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
+            if (lane == 0) {
+                const int c = wave * 16 + q;
+                yre[c] = c < jb ? z[j0 + c].x - tr : 0.0;
+                yim[c] = c < jb ? z[j0 + c].y - ti : 0.0;
+            }
+        }
+        __syncthreads();
+        if (tid < jb) {
+            const double *lv = linv + (size_t)p * CN * CN;
+            double xr = 0.0, xi = 0.0;
+            for (int k = tid; k < jb; ++k) {
+                const double l = lv[k * CN + tid];
+                xr += l * yre[k];
+                xi += l * yim[k];
+            }
+            z[j0 + tid] = make_double2(xr, xi);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int nf = 0;
+        for (int i = 0; i < M && !nf; ++i)
+            if (!isfinite(z[i].x) || !isfinite(z[i].y)) nf = 1;
+        if (nf) a.flags[t] = 1;
+    }
+}
+
+}  // namespace tvmc

@@ -12,6 +12,7 @@
 
 #include "../../include/tvmc.h"
 #include "cholesky.hpp"
+#include "cholesky_mw.hpp"
 #include "common.hpp"
 #include "estimate.hpp"
 #include "observe.hpp"
@@ -189,6 +190,8 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
         if (c->ar_train_every < 0 || c->ar_train_iters < 0 || !(c->ar_lr > 0.0))
             return snprintf(msg, len, "bad training settings"), TVMC_E_INVAL;
     }
+    if (c->solver < TVMC_SOLVER_AUTO || c->solver > TVMC_SOLVER_MULTI_GROUP)
+        return snprintf(msg, len, "bad solver"), TVMC_E_INVAL;
     return TVMC_OK;
 }
 
@@ -391,6 +394,36 @@ tvmc_status run_estimate(tvmc_ctx *c) {
     return TVMC_OK;
 }
 
+// The FP64 Cholesky solve: one workgroup per trajectory, or several per trajectory when the
+// batch alone would leave most compute units idle.
+tvmc_status launch_chol(tvmc_ctx *c, const CholArgs &ca) {
+    const int T = c->d.nt;
+    const bool multi = c->cfg.solver == TVMC_SOLVER_MULTI_GROUP || (c->cfg.solver == TVMC_SOLVER_AUTO && T < 192);
+    if (!multi) {
+        hipLaunchKernelGGL(k_chol_solve, dim3(T), dim3(256), 0, c->stream, ca);
+        LAUNCHCHECK(c, "k_chol_solve");
+        return TVMC_OK;
+    }
+    hipLaunchKernelGGL(k_cmw_init, dim3((ca.m + 255) / 256, T), dim3(256), 0, c->stream, ca);
+    LAUNCHCHECK(c, "k_cmw_init");
+    for (int j0 = 0, p = 0; j0 < ca.m; j0 += CN, ++p) {
+        if (j0 > 0) {
+            hipLaunchKernelGGL(k_cmw_update, dim3((ca.m - j0 + CR - 1) / CR, T), dim3(256), 0, c->stream, ca, j0);
+            LAUNCHCHECK(c, "k_cmw_update");
+        }
+        hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, c->stream, ca, j0, p);
+        LAUNCHCHECK(c, "k_cmw_diag");
+        const int below = ca.m - j0 - CN;
+        if (below > 0) {
+            hipLaunchKernelGGL(k_cmw_trsm, dim3((below + CR - 1) / CR, T), dim3(256), 0, c->stream, ca, j0, p);
+            LAUNCHCHECK(c, "k_cmw_trsm");
+        }
+    }
+    hipLaunchKernelGGL(k_cmw_backward, dim3(T), dim3(256), 0, c->stream, ca);
+    LAUNCHCHECK(c, "k_cmw_backward");
+    return TVMC_OK;
+}
+
 tvmc_status run_solve(tvmc_ctx *c) {
     Dev &d = c->d;
     {
@@ -399,14 +432,14 @@ tvmc_status run_solve(tvmc_ctx *c) {
             hipLaunchKernelGGL(k_embed_rhs, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d);
             LAUNCHCHECK(c, "k_embed_rhs");
             CholArgs ca{d.S, d.rhs2, d.x2, d.linv, d.flags, d.me};
-            hipLaunchKernelGGL(k_chol_solve, dim3(d.nt), dim3(256), 0, c->stream, ca);
-            LAUNCHCHECK(c, "k_chol_solve");
+            tvmc_status st = launch_chol(c, ca);
+            if (st != TVMC_OK) return st;
             hipLaunchKernelGGL(k_unembed, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage);
             LAUNCHCHECK(c, "k_unembed");
         } else {
             CholArgs ca{d.S, d.D, c->stage ? d.d1 : d.d0, d.linv, d.flags, d.m};
-            hipLaunchKernelGGL(k_chol_solve, dim3(d.nt), dim3(256), 0, c->stream, ca);
-            LAUNCHCHECK(c, "k_chol_solve");
+            tvmc_status st = launch_chol(c, ca);
+            if (st != TVMC_OK) return st;
         }
     }
     c->phase = 3;

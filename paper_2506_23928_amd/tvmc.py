@@ -21,6 +21,7 @@ PREC_FP64, PREC_MFMA = 0, 1
 (Q_THETA, Q_THETA_EVAL, Q_DELTA0, Q_DELTA1, Q_SAMPLES, Q_ELOC, Q_S, Q_D, Q_OBAR, Q_BMEAN, Q_DW, Q_ACCEPTS,
  Q_CHAINS, Q_MOMENTS, Q_OBS_HIST, Q_AR_PARAMS, Q_AR_GRAD, Q_AR_LOGQ, Q_AR_LOSS, Q_AR_ACCEPTS) = range(20)
 PROPOSAL_FLIP, PROPOSAL_LEARNED = 0, 1
+SOLVER_AUTO, SOLVER_ONE_GROUP, SOLVER_MULTI_GROUP = 0, 1, 2
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -42,7 +43,7 @@ class tvmc_config(ctypes.Structure):
                 ("diag_shift", ctypes.c_double), ("precision", ctypes.c_int32), ("obs_every", ctypes.c_int32),
                 ("n_obs_max", ctypes.c_int32), ("seed", ctypes.c_uint64), ("proposal", ctypes.c_int32),
                 ("ar_hidden", ctypes.c_int32), ("ar_train_every", ctypes.c_int32), ("ar_train_iters", ctypes.c_int32),
-                ("ar_lr", ctypes.c_double)]
+                ("ar_lr", ctypes.c_double), ("solver", ctypes.c_int32)]
 
 
 class TvmcError(RuntimeError):
@@ -103,10 +104,11 @@ def n_params(kind: int, n: int, n_hidden: int = 0) -> int:
 
 def make_config(n_traj, n_samples, n_chains, dt, diag_shift=1e-4, burn_sweeps=2, thin_sweeps=1, init_sweeps=0,
                 scheme=HEUN, precision=PREC_FP64, obs_every=0, n_obs_max=0, seed=0, traj_offset=0,
-                proposal=PROPOSAL_FLIP, ar_hidden=128, ar_train_every=20, ar_train_iters=50, ar_lr=3e-3):
+                proposal=PROPOSAL_FLIP, ar_hidden=128, ar_train_every=20, ar_train_iters=50, ar_lr=3e-3,
+                solver=0):
     return tvmc_config(n_traj, traj_offset, n_samples, n_chains, burn_sweeps, thin_sweeps, init_sweeps, scheme, dt,
                        diag_shift, precision, obs_every, n_obs_max, ctypes.c_uint64(seed), proposal, ar_hidden,
-                       ar_train_every, ar_train_iters, ar_lr)
+                       ar_train_every, ar_train_iters, ar_lr, solver)
 
 
 # ---------------------------------------------------------------- functions named as in the C ABI

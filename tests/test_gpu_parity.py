@@ -34,11 +34,12 @@ def _rel(a, b):
 
 
 def _pair(tv, orc, J, hx, jumps, T, ns, nc, dt, eps, seed, precision=0, burn=2, thin=1, init=0, scheme=0, traj0=0,
-          theta0=None, obs_every=0, nobs=0):
+          theta0=None, obs_every=0, nobs=0, solver=0):
     pb_o = orc.Problem(J, hx, jumps)
     cfg_o = orc.Config(n_samples=ns, n_chains=nc, burn_sweeps=burn, thin_sweeps=thin, init_sweeps=init, dt=dt,
                        diag_shift=eps, scheme=scheme, seed=seed, obs_every=obs_every)
-    cfg_g = tv.make_config(T, ns, nc, dt, eps, burn, thin, init, scheme, precision, obs_every, nobs, seed, traj0)
+    cfg_g = tv.make_config(T, ns, nc, dt, eps, burn, thin, init, scheme, precision, obs_every, nobs, seed, traj0,
+                           solver=solver)
     ctx = tv.Context(tv.Problem(J, hx, jumps), cfg_g, theta0=theta0)
     return pb_o, cfg_o, ctx
 
@@ -162,15 +163,17 @@ def test_closed_system_closed_form_on_gpu(tv, orc):
 def test_edge_shapes(tv, orc, n, ns, nc):
     """N = 1 (a single parameter), odd chain counts, ragged tiles (M = 91, 528), a full 64-bit
     word (N = 64, M = 2080) and sample counts that are not multiples of 256: one predictor
-    evaluation against the oracle, MFMA and FP64 S-builds against each other."""
+    evaluation against the oracle, MFMA and FP64 S-builds against each other, the one- and
+    several-workgroup solvers each against the oracle."""
     from paper_2506_23928_amd import tvmc as T
     J, hx, jumps = wl.random_problem(n, seed=n) if n > 1 else (np.zeros((1, 1)), 0.7, [(0, 0, 0.2)])
     m = orc.n_params(0, n)
     th0 = wl.random_theta(m, 0.05, seed=n)
     seed, dt, eps = 9, 0.01, 1e-3
     S_by_prec = []
-    for prec in ([0, 1] if ns % 64 == 0 else [0]):
-        pb, cfg, ctx = _pair(tv, orc, J, hx, jumps, 2, ns, nc, dt, eps, seed, precision=prec, theta0=th0)
+    for prec, solver in ([(0, 1), (1, 2)] if ns % 64 == 0 else [(0, 1), (0, 2)]):
+        pb, cfg, ctx = _pair(tv, orc, J, hx, jumps, 2, ns, nc, dt, eps, seed, precision=prec, theta0=th0,
+                             solver=solver)
         ctx.sample()
         ctx.estimate()
         S_by_prec.append(ctx.get(T.Q_S, 1))
@@ -184,9 +187,8 @@ def test_edge_shapes(tv, orc, n, ns, nc):
         assert np.array_equal(S_by_prec[-1][low], (r["S"].real + eps * np.eye(m))[low])
         assert _rel(ctx.get(T.Q_D, 1), r["D"]) < 1e-12
         assert _rel(ctx.get(T.Q_DELTA0, 1), r["delta"]) < 1e-9
-    if len(S_by_prec) == 2:
-        low = np.tril_indices(m)
-        assert np.array_equal(S_by_prec[0][low], S_by_prec[1][low])
+    low = np.tril_indices(m)
+    assert np.array_equal(S_by_prec[0][low], S_by_prec[1][low])
 
 
 def test_bad_arguments_are_rejected(tv):

@@ -152,8 +152,8 @@ def _bf16_bound(Sref, ns):
     return (2.0 ** -15 + ns * 2.0 ** -24) * np.outer(d, d) + 1e-15
 
 
-@pytest.mark.parametrize("n,nh,ns,nc", [(5, 3, 128, 4), (6, 70, 256, 8)])
-def test_rbm_bf16_sbuild_matches_oracle(tv, orc, n, nh, ns, nc):
+@pytest.mark.parametrize("n,nh,ns,nc,solver", [(5, 3, 128, 4, 1), (6, 70, 256, 8, 2), (6, 70, 256, 8, 1)])
+def test_rbm_bf16_sbuild_matches_oracle(tv, orc, n, nh, ns, nc, solver):
     """The matrix-core precision form of the RBM S against the oracle's FP64 S on the same
     (bit-exact) samples, entry by entry within the split/accumulation bound; one tile (M = 23)
     and a ragged 8x8 tile grid (M = 496)."""
@@ -164,7 +164,7 @@ def test_rbm_bf16_sbuild_matches_oracle(tv, orc, n, nh, ns, nc):
     seed, dt, eps = 8, 0.01, 1e-3
     cfg_o = orc.Config(n_samples=ns, n_chains=nc, burn_sweeps=2, thin_sweeps=1, dt=dt, diag_shift=eps, seed=seed)
     pb = orc.Problem(J, hx, jumps)
-    cfg = tv.make_config(2, ns, nc, dt, eps, 2, 1, 0, tv.HEUN, tv.PREC_MFMA, seed=seed)
+    cfg = tv.make_config(2, ns, nc, dt, eps, 2, 1, 0, tv.HEUN, tv.PREC_MFMA, seed=seed, solver=solver)
     ctx = tv.Context(tv.Problem(J, hx, jumps), cfg, kind=tv.RBM, n_hidden=nh, theta0=th0)
     ctx.sample()
     ctx.estimate()
