@@ -116,8 +116,8 @@ enum {
     TVMC_Q_DELTA1 = 3,      /* double[2M] corrector increment */
     TVMC_Q_SAMPLES = 4,     /* uint64[n_samples] packed configurations of the last sampling */
     TVMC_Q_ELOC = 5,        /* double[2 n_samples] local energy of H */
-    TVMC_Q_S = 6,           /* double[M*M] S + eps I, lower triangle valid (before the solve); for the
-                               RBM the real embedding [[Re S, -Im S], [Im S, Re S]], double[4 M*M] */
+    TVMC_Q_S = 6,           /* double[M*M] S + eps I, lower triangle valid (before the solve, which
+                               factorises it in place); for the RBM complex, double[2 M*M] interleaved */
     TVMC_Q_D = 7,           /* double[2M] D */
     TVMC_Q_OBAR = 8,        /* <O_k>: double[M] for the Jastrow ansatz (real), double[2M] for the RBM */
     TVMC_Q_BMEAN = 9,       /* double[2 n_jumps] <B^n> */

@@ -9,8 +9,8 @@
 //     rows below:  L[rows, panel] = C Linv^T                  (MFMA)
 // The forward substitution L y = D rides along panel by panel; the backward substitution
 // L^T x = y afterwards reads L once more and reuses the stored block inverses.
-// The real factor of the Jastrow S is applied to the real and imaginary parts of D; a complex
-// Hermitian S (RBM) is solved through its real embedding [[Re S, -Im S], [Im S, Re S]].
+// The real factor of the Jastrow S is applied to the real and imaginary parts of D (the
+// complex Hermitian S of the RBM has its own solver, cholesky_z.hpp).
 #pragma once
 #include "common.hpp"
 

@@ -1,0 +1,319 @@
+// Regularised solve for a complex Hermitian S (RBM ansatz): (S + eps I) delta = D with
+// S + eps I = L L^H, in FP64 on the matrix cores, several workgroups per trajectory.  The
+// steps mirror the real solver (left-looking panels of CN = 64 columns, one launch per step):
+//   k_zmw_update(j0):  C[rows, panel] = A[rows, panel] - L[rows, 0:j0] L[panel, 0:j0]^H
+//                      Re C -= Lr Lr'^T + Li Li'^T,  Im C -= Li Lr'^T - Lr Li'^T   (4 real MFMA products)
+//   k_zmw_diag(j0):    L_pp L_pp^H = C_pp in LDS, Linv = L_pp^-1, y_p = Linv z_p
+//   k_zmw_trsm(j0):    L[rows, panel] = C Linv^H, z[rows] -= L[rows, panel] y_p
+//   k_zmw_backward:    L^H x = y with x_p = Linv^H (y_p - L[below, p]^H x_below)
+// Matrices are complex [T][M][M] (lower triangle), interleaved (re, im).
+#pragma once
+#include "cholesky.hpp"
+
+namespace tvmc {
+
+struct ZCholArgs {
+    double2 *A;
+    const double2 *rhs;
+    double2 *x;
+    double2 *linv;   // [T][panels][64 * 64]
+    int *flags;
+    int m;
+};
+
+__global__ __launch_bounds__(256) void k_zmw_init(ZCholArgs a) {
+    const int t = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < a.m) a.x[(size_t)t * a.m + i] = a.rhs[(size_t)t * a.m + i];
+}
+
+constexpr int ZK = 16;          // k-slice staged through LDS
+constexpr int ZKP = ZK + 1;
+
+__global__ __launch_bounds__(256) void k_zmw_update(ZCholArgs a, int j0) {
+    __shared__ double Ar[CR * ZKP], Ai[CR * ZKP];
+    __shared__ double Br[CN * ZKP], Bi[CN * ZKP];
+    const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int M = a.m;
+    const int r0 = j0 + blockIdx.x * CR;
+    if (r0 >= M) return;
+    const int jb = (M - j0) < CN ? (M - j0) : CN;
+    double2 *A = a.A + (size_t)t * M * M;
+    v4d cre[2][4], cim[2][4];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 4; ++v)
+            for (int r = 0; r < 4; ++r) {
+                const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
+                const double2 c = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : make_double2(0.0, 0.0);
+                cre[u][v][r] = c.x;
+                cim[u][v][r] = c.y;
+            }
+    double2 pa[CR * ZK / 256], pb[CN * ZK / 256];
+    auto fetch = [&](int kc) {
+        for (int q = 0; q < CR * ZK / 256; ++q) {
+            const int e = tid + 256 * q, rr = e / ZK, kk = e % ZK;
+            pa[q] = (r0 + rr < M) ? A[(size_t)(r0 + rr) * M + kc + kk] : make_double2(0.0, 0.0);
+        }
+        for (int q = 0; q < CN * ZK / 256; ++q) {
+            const int e = tid + 256 * q, cc = e / ZK, kk = e % ZK;
+            pb[q] = (cc < jb) ? A[(size_t)(j0 + cc) * M + kc + kk] : make_double2(0.0, 0.0);
+        }
+    };
+    fetch(0);
+    for (int kc = 0; kc < j0; kc += ZK) {
+        __syncthreads();
+        for (int q = 0; q < CR * ZK / 256; ++q) {
+            const int e = tid + 256 * q;
+            Ar[(e / ZK) * ZKP + e % ZK] = -pa[q].x;
+            Ai[(e / ZK) * ZKP + e % ZK] = -pa[q].y;
+        }
+        for (int q = 0; q < CN * ZK / 256; ++q) {
+            const int e = tid + 256 * q;
+            Br[(e / ZK) * ZKP + e % ZK] = pb[q].x;
+            Bi[(e / ZK) * ZKP + e % ZK] = pb[q].y;
+        }
+        __syncthreads();
+        if (kc + ZK < j0) fetch(kc + ZK);
+        for (int ks = 0; ks < ZK / 4; ++ks) {
+            double far_[2], fai[2], fbr[4], fbi[4];
+            for (int u = 0; u < 2; ++u) {
+                far_[u] = Ar[(wave * 32 + u * 16 + li) * ZKP + ks * 4 + lk];   // -Lr (rows)
+                fai[u] = Ai[(wave * 32 + u * 16 + li) * ZKP + ks * 4 + lk];    // -Li (rows)
+            }
+            for (int v = 0; v < 4; ++v) {
+                fbr[v] = Br[(v * 16 + li) * ZKP + ks * 4 + lk];                // Lr' (panel rows)
+                fbi[v] = Bi[(v * 16 + li) * ZKP + ks * 4 + lk];                // Li'
+            }
+            for (int u = 0; u < 2; ++u)
+                for (int v = 0; v < 4; ++v) {
+                    cre[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(far_[u], fbr[v], cre[u][v], 0, 0, 0);
+                    cre[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fai[u], fbi[v], cre[u][v], 0, 0, 0);
+                    cim[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fai[u], fbr[v], cim[u][v], 0, 0, 0);
+                    cim[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(far_[u], -fbi[v], cim[u][v], 0, 0, 0);
+                }
+        }
+    }
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 4; ++v)
+            for (int r = 0; r < 4; ++r) {
+                const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
+                if (r0 + row < M && col < jb)
+                    A[(size_t)(r0 + row) * M + j0 + col] = make_double2(cre[u][v][r], cim[u][v][r]);
+            }
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zmulc(double2 a, double2 b) {   // a conj(b)
+    return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+__global__ __launch_bounds__(256) void k_zmw_diag(ZCholArgs a, int j0, int p) {
+    __shared__ double2 Cs[CN * CSP];
+    __shared__ double2 Ls[CN * CSP];
+    __shared__ double2 ys[CN];
+    __shared__ int bad;
+    const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int M = a.m;
+    const int jb = (M - j0) < CN ? (M - j0) : CN;
+    double2 *A = a.A + (size_t)t * M * M;
+    double2 *z = a.x + (size_t)t * M;
+    if (tid == 0) bad = 0;
+    for (int e = tid; e < CN * CN; e += 256) {
+        const int r = e / CN, c = e % CN;
+        Cs[r * CSP + c] = (r < jb && c <= r) ? A[(size_t)(j0 + r) * M + j0 + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    // right-looking factor in LDS: thread (row fr, phase fs); column c read unscaled in step c
+    {
+        const int fr = tid >> 2, fs = tid & 3;
+        for (int c = 0; c < jb; ++c) {
+            const double piv = Cs[c * CSP + c].x;
+            if (tid == 0 && !(piv > 0.0)) bad = 1;
+            const double d = sqrt(piv), inv = 1.0 / d;
+            double2 lrc = make_double2(0.0, 0.0);
+            if (fr > c && fr < jb) {
+                const double2 crc = Cs[fr * CSP + c];
+                lrc = make_double2(crc.x * inv, crc.y * inv);
+                for (int k = c + 1 + fs; k <= fr; k += 4) {   // C_rk -= L_rc conj(L_kc)
+                    const double2 ckc = Cs[k * CSP + c];
+                    const double2 lkc = make_double2(ckc.x * inv, ckc.y * inv);
+                    const double2 pr = zmulc(lrc, lkc);
+                    Cs[fr * CSP + k].x -= pr.x;
+                    Cs[fr * CSP + k].y -= pr.y;
+                }
+            }
+            __syncthreads();
+            if (fs == 0 && fr > c && fr < jb) Cs[fr * CSP + c] = lrc;
+            if (tid == 0) Cs[c * CSP + c] = make_double2(d, 0.0);
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < jb * jb; e += 256) {
+        const int r = e / jb, c = e % jb;
+        if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
+    }
+    // Linv: Linv_cc = 1 / L_cc, Linv_rc = -(sum_{c <= k < r} L_rk Linv_kc) / L_rr
+    {
+        const int c = wave * 16 + (lane >> 2), fs = lane & 3;
+        for (int r = fs; r < CN; r += 4) Ls[r * CSP + c] = make_double2(0.0, 0.0);
+        if (c < jb) {
+            if (fs == 0) Ls[c * CSP + c] = make_double2(1.0 / Cs[c * CSP + c].x, 0.0);
+            for (int r = c + 1; r < jb; ++r) {
+                double sr = 0.0, si = 0.0;
+                for (int k = c + fs; k < r; k += 4) {
+                    const double2 pr = zmul(Cs[r * CSP + k], Ls[k * CSP + c]);
+                    sr += pr.x;
+                    si += pr.y;
+                }
+                sr += __shfl_xor(sr, 1, 64);
+                sr += __shfl_xor(sr, 2, 64);
+                si += __shfl_xor(si, 1, 64);
+                si += __shfl_xor(si, 2, 64);
+                const double lrr = Cs[r * CSP + r].x;
+                if (fs == 0) Ls[r * CSP + c] = make_double2(-sr / lrr, -si / lrr);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < jb) {   // y = Linv z_panel
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k <= tid; ++k) {
+            const double2 pr = zmul(Ls[tid * CSP + k], z[j0 + k]);
+            sr += pr.x;
+            si += pr.y;
+        }
+        ys[tid] = make_double2(sr, si);
+    }
+    double2 *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
+    for (int e = tid; e < CN * CN; e += 256) lv[e] = Ls[(e / CN) * CSP + e % CN];
+    __syncthreads();
+    if (tid < jb) z[j0 + tid] = ys[tid];
+    if (tid == 0 && bad) a.flags[t] = 1;
+}
+
+// X = C Linv^H: X_ij = sum_k C_ik conj(Linv_jk); B[k][j] = Linv_jk
+__global__ __launch_bounds__(256) void k_zmw_trsm(ZCholArgs a, int j0, int p) {
+    __shared__ double Lr[CN * CSP], Li[CN * CSP];
+    __shared__ double yr[CN], yi[CN];
+    const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int M = a.m;
+    const int jb = (M - j0) < CN ? (M - j0) : CN;
+    const int r0 = j0 + jb + blockIdx.x * CR;
+    if (r0 >= M) return;
+    double2 *A = a.A + (size_t)t * M * M;
+    double2 *z = a.x + (size_t)t * M;
+    const double2 *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
+    for (int e = tid; e < CN * CN; e += 256) {
+        const double2 l = lv[e];
+        Lr[(e / CN) * CSP + e % CN] = l.x;
+        Li[(e / CN) * CSP + e % CN] = l.y;
+    }
+    if (tid < CN) {
+        const double2 y = tid < jb ? z[j0 + tid] : make_double2(0.0, 0.0);
+        yr[tid] = y.x;
+        yi[tid] = y.y;
+    }
+    __syncthreads();
+    v4d xr[2][4], xi[2][4];
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 4; ++v) {
+            xr[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
+            xi[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
+        }
+    for (int ks = 0; ks < CN / 4; ++ks) {
+        double fcr[2], fci[2], fbr[4], fbi[4];
+        for (int u = 0; u < 2; ++u) {
+            const int row = r0 + wave * 32 + u * 16 + li, col = ks * 4 + lk;
+            const double2 c = (row < M && col < jb) ? A[(size_t)row * M + j0 + col] : make_double2(0.0, 0.0);
+            fcr[u] = c.x;
+            fci[u] = c.y;
+        }
+        for (int v = 0; v < 4; ++v) {
+            fbr[v] = Lr[(v * 16 + li) * CSP + ks * 4 + lk];
+            fbi[v] = Li[(v * 16 + li) * CSP + ks * 4 + lk];
+        }
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 4; ++v) {
+                xr[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr[u], fbr[v], xr[u][v], 0, 0, 0);
+                xr[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci[u], fbi[v], xr[u][v], 0, 0, 0);
+                xi[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci[u], fbr[v], xi[u][v], 0, 0, 0);
+                xi[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr[u], -fbi[v], xi[u][v], 0, 0, 0);
+            }
+    }
+    __syncthreads();
+    for (int u = 0; u < 2; ++u)
+        for (int r = 0; r < 4; ++r) {
+            const int row = r0 + wave * 32 + u * 16 + lk + 4 * r;
+            double sr = 0.0, si = 0.0;
+            for (int v = 0; v < 4; ++v) {
+                const int col = v * 16 + li;
+                const double a_ = xr[u][v][r], b_ = xi[u][v][r];
+                if (row < M && col < jb) A[(size_t)row * M + j0 + col] = make_double2(a_, b_);
+                sr += a_ * yr[col] - b_ * yi[col];
+                si += a_ * yi[col] + b_ * yr[col];
+            }
+            for (int o = 1; o < 16; o <<= 1) {
+                sr += __shfl_xor(sr, o, 64);
+                si += __shfl_xor(si, o, 64);
+            }
+            if (li == 0 && row < M) {
+                const double2 zr = z[row];
+                z[row] = make_double2(zr.x - sr, zr.y - si);
+            }
+        }
+}
+
+// L^H x = y, last panel first: w_c = y_c - sum_{r below} conj(L_rc) x_r, x_p = Linv^H w
+__global__ __launch_bounds__(256) void k_zmw_backward(ZCholArgs a) {
+    __shared__ double2 ws[CN];
+    const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int M = a.m;
+    const double2 *A = a.A + (size_t)t * M * M;
+    const double2 *linv = a.linv + (size_t)t * chol_panels(M) * CN * CN;
+    double2 *z = a.x + (size_t)t * M;
+    for (int p = chol_panels(M) - 1; p >= 0; --p) {
+        const int j0 = p * CN, jb = (M - j0) < CN ? (M - j0) : CN;
+        double sr[16], si[16];
+        for (int q = 0; q < 16; ++q) sr[q] = si[q] = 0.0;
+        for (int r = j0 + jb + lane; r < M; r += 64) {
+            const double2 xr = z[r];
+            const double2 *row = A + (size_t)r * M + j0 + wave * 16;
+            for (int q = 0; q < 16; ++q) {
+                const double2 l = (wave * 16 + q < jb) ? row[q] : make_double2(0.0, 0.0);
+                sr[q] += l.x * xr.x + l.y * xr.y;   // conj(l) x
+                si[q] += l.x * xr.y - l.y * xr.x;
+            }
+        }
+        for (int q = 0; q < 16; ++q) {
+            const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
+            if (lane == 0) {
+                const int c = wave * 16 + q;
+                ws[c] = c < jb ? make_double2(z[j0 + c].x - tr, z[j0 + c].y - ti) : make_double2(0.0, 0.0);
+            }
+        }
+        __syncthreads();
+        if (tid < jb) {   // x_c = sum_{k >= c} conj(Linv_kc) w_k
+            const double2 *lv = linv + (size_t)p * CN * CN;
+            double xr = 0.0, xi = 0.0;
+            for (int k = tid; k < jb; ++k) {
+                const double2 l = lv[k * CN + tid], w = ws[k];
+                xr += l.x * w.x + l.y * w.y;
+                xi += l.x * w.y - l.y * w.x;
+            }
+            z[j0 + tid] = make_double2(xr, xi);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int nf = 0;
+        for (int i = 0; i < M && !nf; ++i)
+            if (!isfinite(z[i].x) || !isfinite(z[i].y)) nf = 1;
+        if (nf) a.flags[t] = 1;
+    }
+}
+
+}  // namespace tvmc

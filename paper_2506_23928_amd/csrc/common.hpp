@@ -61,8 +61,8 @@ __host__ __device__ __forceinline__ int pair_index(int n, int j, int k) {
 // Everything a kernel may touch, as raw device pointers into the caller's workspace.
 struct Dev {
     int n, m, nch, ns, nc, per, nt, nobs;
-    int kind, nh, me;         // ansatz (0 Jastrow, 1 RBM), hidden units, dimension of the real solve
-    int mp;                   // M rounded up to 64 (rows of the RBM's BF16 operand planes)
+    int kind, nh;             // ansatz (0 Jastrow, 1 RBM), hidden units
+    int mp;                   // M rounded up to 128 (rows of the RBM's BF16 operand planes)
     uint16_t *rbmP;           // RBM precision form: [T][4][mp][ns] BF16 split of the centred O
     int burn, thin, init_sweeps, scheme, traj0;
     uint32_t key0, key1;
@@ -92,7 +92,6 @@ struct Dev {
     double *w_re, *w_im;      // [T][N][N'] RBM weights, split planes
     double2 *cT, *sT;         // [T][N'][N] cosh 2w, sinh 2w (transposed)
     double2 *tt;              // [T][Ns][N'] tanh g_j per sample
-    double2 *rhs2, *x2;       // [T][2M] right-hand side / solution of the real embedding
     double2 *D;               // [T][M]
     double *S;                // [T][M][M]
     double *linv;             // [T][panels][64*64] inverses of the Cholesky diagonal blocks

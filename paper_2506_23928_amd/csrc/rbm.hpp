@@ -7,8 +7,7 @@
 // Single-flip ratios use cosh(g - 2 s w)/cosh g = cosh 2w - s tanh(g) sinh 2w with the
 // cosh 2w / sinh 2w tables built once per evaluation, so a sample's N ratios cost N N'
 // complex multiply-adds (products renormalised every 16 factors).
-// The complex Hermitian S is assembled directly as its real embedding
-// [[Re S, -Im S], [Im S, Re S]] (lower triangle), solved by the real FP64 Cholesky.
+// The complex Hermitian S (lower triangle) is solved by the complex FP64 Cholesky.
 #pragma once
 #include "common.hpp"
 #include "made.hpp"
@@ -279,7 +278,7 @@ __global__ __launch_bounds__(256) void k_obar_D_rbm(Dev a) {
     a.D[(size_t)t * a.m + k] = make_double2(dr * inv - (obr * gb.x + obi * gb.y), di * inv - (obr * gb.y - obi * gb.x));
 }
 
-// Complex S + eps I written as the lower triangle of its real embedding (size 2M), plain FP64:
+// Complex S + eps I (lower triangle, interleaved re/im), plain FP64:
 // 32x32 complex tile per workgroup, 2x2 complex register tile per thread, samples staged 8 at
 // a time (configuration word and tanh g row) through LDS.
 constexpr int RB_T = 32;
@@ -320,8 +319,7 @@ __global__ __launch_bounds__(256) void k_sbuild_rbm_f64(Dev a) {
     }
     const double inv = 1.0 / (double)a.ns;
     const double2 *ob = a.obarc + (size_t)t * m;
-    const size_t me = 2 * (size_t)m;
-    double *S = a.S + (size_t)t * me * me;
+    double2 *S = (double2 *)a.S + (size_t)t * m * m;
     for (int u = 0; u < 2; ++u) {
         const int k = bi * RB_T + ty * 2 + u;
         if (k >= m) continue;
@@ -332,29 +330,9 @@ __global__ __launch_bounds__(256) void k_sbuild_rbm_f64(Dev a) {
             double re = acc[u][v].x * inv - (ob[k].x * ob[l].x + ob[k].y * ob[l].y);
             const double im = acc[u][v].y * inv - (ob[k].x * ob[l].y - ob[k].y * ob[l].x);
             if (k == l) re += a.eps;
-            S[(size_t)k * me + l] = re;                    // Re S (upper-left block)
-            S[(size_t)(m + k) * me + m + l] = re;          // Re S (lower-right block)
-            S[(size_t)(m + k) * me + l] = im;              // Im S_kl (lower-left block)
-            if (k != l) S[(size_t)(m + l) * me + k] = -im; // Im S_lk = -Im S_kl
+            S[(size_t)k * m + l] = make_double2(re, k == l ? 0.0 : im);
         }
     }
-}
-
-// right-hand side of the embedding: (Re D ; Im D), and the solution back to delta = u + i v
-__global__ void k_embed_rhs(Dev a) {
-    const int t = blockIdx.y, k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.m) return;
-    const double2 d = a.D[(size_t)t * a.m + k];
-    a.rhs2[(size_t)t * 2 * a.m + k] = make_double2(d.x, 0.0);
-    a.rhs2[(size_t)t * 2 * a.m + a.m + k] = make_double2(d.y, 0.0);
-}
-
-__global__ void k_unembed(Dev a, int which) {
-    const int t = blockIdx.y, k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.m) return;
-    const double2 *x = a.x2 + (size_t)t * 2 * a.m;
-    double2 *d = (which ? a.d1 : a.d0) + (size_t)t * a.m;
-    d[k] = make_double2(x[k].x, x[a.m + k].x);
 }
 
 // Moments for the RBM: two-flip ratios psi(s^(ab))/psi(s) = exp(-2 s_a a_a - 2 s_b a_b)

@@ -7,7 +7,7 @@
 //   Re S_kl = sum Re_k Re_l + Im_k Im_l,   Im S_kl = sum Re_k Im_l - Im_k Re_l,
 // i.e. 12 MFMAs per 16x16 complex block and 32 samples.  Centring before the products keeps
 // the FP32 sums free of the cancellation that <O^* O> - <O>^* <O> would suffer.
-// Output: S + eps I as the lower triangle of its real embedding, as in the FP64 kernel.
+// Output: S + eps I, lower triangle, complex interleaved, as in the FP64 kernel.
 #pragma once
 #include "common.hpp"
 #include "made.hpp"
@@ -57,11 +57,13 @@ __device__ __forceinline__ bf16x8_t neg_bf16x8(bf16x8_t v) {
 
 #define MFMA_BF16(A, B, C) __builtin_amdgcn_mfma_f32_16x16x32_bf16((A), (B), (C), 0, 0, 0)
 
-// One workgroup (4 waves) per 64x64 complex tile of the lower triangle; wave (wr, wc) takes the
-// 32x32 sub-tile, 2x2 blocks of 16x16.  Operand fragments come straight from P (16 bytes per
-// lane: row lane & 15, samples 8 (lane >> 4) .. +7 of the 32-sample step; the Gram product only
-// needs the row and column operands to use the same sample order).
-constexpr int RQ_T = 64;
+// One workgroup (4 waves) per 128x128 complex tile of the lower triangle; wave (wr, wc) takes
+// the 64x64 sub-tile, 4x4 blocks of 16x16 (128 FP32 accumulators).  Operand fragments come
+// straight from P (16 bytes per lane: row lane & 15, samples 8 (lane >> 4) .. +7 of the
+// 32-sample step; the Gram product only needs the row and column operands to use the same
+// sample order): per step a wave loads 32 fragments and issues 192 MFMAs.
+constexpr int RQ_T = 128;
+constexpr int RQ_W = 64;
 __global__ __launch_bounds__(256) void k_sbuild_rbm_bf16(Dev a) {
     const int t = blockIdx.y, tile = blockIdx.x;
     int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
@@ -71,33 +73,30 @@ __global__ __launch_bounds__(256) void k_sbuild_rbm_bf16(Dev a) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wr = w >> 1, wc = w & 1;
     if (bi == bj && wr < wc) return;            // strictly upper sub-tile of a diagonal tile
-    const int r0 = bi * RQ_T + wr * 32, c0 = bj * RQ_T + wc * 32;
+    const int r0 = bi * RQ_T + wr * RQ_W, c0 = bj * RQ_T + wc * RQ_W;
     const int m = a.m;
     if (r0 >= m || c0 >= m) return;
     const int rr = lane & 15, kg = lane >> 4;
     const size_t ns = (size_t)a.ns, plane = (size_t)a.mp * ns;
     const uint16_t *Pt = a.rbmP + (size_t)t * 4 * plane;
-    const uint16_t *ar_[2], *bc_[2];
-    for (int u = 0; u < 2; ++u) {
-        ar_[u] = Pt + (size_t)(r0 + u * 16 + rr) * ns + 8 * kg;
-        bc_[u] = Pt + (size_t)(c0 + u * 16 + rr) * ns + 8 * kg;
-    }
-    f32x4_t sre[2][2], sim[2][2];
-    for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) {
+    const uint16_t *rowp = Pt + (size_t)(r0 + rr) * ns + 8 * kg;
+    const uint16_t *colp = Pt + (size_t)(c0 + rr) * ns + 8 * kg;
+    f32x4_t sre[4][4], sim[4][4];
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
             sre[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
             sim[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         }
     for (size_t k0 = 0; k0 < ns; k0 += 32) {
-        bf16x8_t A[2][4], B[2][4];
-        for (int u = 0; u < 2; ++u)
+        bf16x8_t A[4][4], B[4][4];
+        for (int u = 0; u < 4; ++u)
             for (int q = 0; q < 4; ++q) {
-                A[u][q] = *(const bf16x8_t *)(ar_[u] + q * plane + k0);
-                B[u][q] = *(const bf16x8_t *)(bc_[u] + q * plane + k0);
+                A[u][q] = *(const bf16x8_t *)(rowp + (size_t)u * 16 * ns + q * plane + k0);
+                B[u][q] = *(const bf16x8_t *)(colp + (size_t)u * 16 * ns + q * plane + k0);
             }
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const bf16x8_t nih = neg_bf16x8(A[u][2]), nil = neg_bf16x8(A[u][3]);
-            for (int v = 0; v < 2; ++v) {
+            for (int v = 0; v < 4; ++v) {
                 f32x4_t x = sre[u][v];
                 x = MFMA_BF16(A[u][0], B[v][0], x);
                 x = MFMA_BF16(A[u][0], B[v][1], x);
@@ -118,20 +117,16 @@ __global__ __launch_bounds__(256) void k_sbuild_rbm_bf16(Dev a) {
         }
     }
     const double inv = 1.0 / (double)a.ns;
-    const size_t me = 2 * (size_t)m;
-    double *S = a.S + (size_t)t * me * me;
-    for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v)
+    double2 *S = (double2 *)a.S + (size_t)t * m * m;
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v)
             for (int e = 0; e < 4; ++e) {
                 const int k = r0 + u * 16 + 4 * kg + e, l = c0 + v * 16 + rr;   // D[4 (lane >> 4) + e][lane & 15]
                 if (k >= m || l >= m || l > k) continue;
                 double re = (double)sre[u][v][e] * inv;
                 const double im = (double)sim[u][v][e] * inv;
                 if (k == l) re += a.eps;
-                S[(size_t)k * me + l] = re;
-                S[(size_t)(m + k) * me + m + l] = re;
-                S[(size_t)(m + k) * me + l] = k == l ? 0.0 : im;
-                if (k != l) S[(size_t)(m + l) * me + k] = -im;
+                S[(size_t)k * m + l] = make_double2(re, k == l ? 0.0 : im);
             }
 }
 

@@ -13,6 +13,7 @@
 #include "../../include/tvmc.h"
 #include "cholesky.hpp"
 #include "cholesky_mw.hpp"
+#include "cholesky_z.hpp"
 #include "common.hpp"
 #include "estimate.hpp"
 #include "observe.hpp"
@@ -51,7 +52,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, rhs2, x2, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1b, arW2Tb, arh, arda,
+        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1b, arW2Tb, arh, arda,
         arg, arlogq, arloss, aracc, rbmP, total;
 };
 
@@ -61,7 +62,8 @@ int mom_blocks_for(int ns) {
 }
 
 int n_params(int kind, int n, int nh) { return kind == TVMC_ANSATZ_RBM ? n + nh + n * nh : n + n * (n - 1) / 2; }
-int solve_dim(int kind, int m) { return kind == TVMC_ANSATZ_RBM ? 2 * m : m; }
+// S + eps I per trajectory: real symmetric M x M (Jastrow) or complex Hermitian M x M (RBM)
+size_t s_doubles(int kind, int m) { return (kind == TVMC_ANSATZ_RBM ? 2 : 1) * (size_t)m * m; }
 
 Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs, int ar, int ah, int nprob, int prec) {
     Layout L{};
@@ -96,7 +98,6 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.G = take(sizeof(double2) * tt * ns);
     L.gbar = take(sizeof(double2) * tt);
     const bool rbm = kind == TVMC_ANSATZ_RBM;
-    const size_t me = (size_t)solve_dim(kind, m);
     L.obar = take(sizeof(double) * tt * m);
     L.obarc = take(rbm ? sizeof(double2) * tt * m : 0);
     L.w_re = take(rbm ? sizeof(double) * tt * n * nh : 0);
@@ -104,11 +105,9 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.cT = take(rbm ? sizeof(double2) * tt * n * nh : 0);
     L.sT = take(rbm ? sizeof(double2) * tt * n * nh : 0);
     L.tt = take(rbm ? sizeof(double2) * tt * ns * nh : 0);
-    L.rhs2 = take(rbm ? sizeof(double2) * tt * me : 0);
-    L.x2 = take(rbm ? sizeof(double2) * tt * me : 0);
     L.D = take(sizeof(double2) * tt * m);
-    L.S = take(sizeof(double) * tt * me * me);
-    L.linv = take(sizeof(double) * tt * chol_panels((int)me) * CN * CN);
+    L.S = take(sizeof(double) * tt * s_doubles(kind, m));
+    L.linv = take((rbm ? sizeof(double2) : sizeof(double)) * tt * chol_panels(m) * CN * CN);
     L.mom_part = take(sizeof(double) * tt * mom_blocks_for(ns) * 9);
     L.mom = take(sizeof(double) * tt * 9);
     L.hist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt * 9);
@@ -127,7 +126,7 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.arlogq = take(ar ? sizeof(float) * tt * ns : 0);
     L.arloss = take(sizeof(double) * tt);
     L.aracc = take(sizeof(uint32_t) * tt * nc);
-    const size_t mp = ((size_t)m + 63) / 64 * 64;
+    const size_t mp = ((size_t)m + RQ_T - 1) / RQ_T * RQ_T;
     L.rbmP = take(rbm && prec == TVMC_PREC_MFMA ? sizeof(uint16_t) * tt * 4 * mp * ns : 0);
     L.total = o;
     return L;
@@ -424,18 +423,37 @@ tvmc_status launch_chol(tvmc_ctx *c, const CholArgs &ca) {
     return TVMC_OK;
 }
 
+// The complex Hermitian solve (always several workgroups per trajectory).
+tvmc_status launch_zchol(tvmc_ctx *c, const ZCholArgs &za) {
+    const int T = c->d.nt;
+    hipLaunchKernelGGL(k_zmw_init, dim3((za.m + 255) / 256, T), dim3(256), 0, c->stream, za);
+    LAUNCHCHECK(c, "k_zmw_init");
+    for (int j0 = 0, p = 0; j0 < za.m; j0 += CN, ++p) {
+        if (j0 > 0) {
+            hipLaunchKernelGGL(k_zmw_update, dim3((za.m - j0 + CR - 1) / CR, T), dim3(256), 0, c->stream, za, j0);
+            LAUNCHCHECK(c, "k_zmw_update");
+        }
+        hipLaunchKernelGGL(k_zmw_diag, dim3(T), dim3(256), 0, c->stream, za, j0, p);
+        LAUNCHCHECK(c, "k_zmw_diag");
+        const int below = za.m - j0 - CN;
+        if (below > 0) {
+            hipLaunchKernelGGL(k_zmw_trsm, dim3((below + CR - 1) / CR, T), dim3(256), 0, c->stream, za, j0, p);
+            LAUNCHCHECK(c, "k_zmw_trsm");
+        }
+    }
+    hipLaunchKernelGGL(k_zmw_backward, dim3(T), dim3(256), 0, c->stream, za);
+    LAUNCHCHECK(c, "k_zmw_backward");
+    return TVMC_OK;
+}
+
 tvmc_status run_solve(tvmc_ctx *c) {
     Dev &d = c->d;
     {
         Scope sc(c, "solve");
         if (d.kind == TVMC_ANSATZ_RBM) {
-            hipLaunchKernelGGL(k_embed_rhs, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d);
-            LAUNCHCHECK(c, "k_embed_rhs");
-            CholArgs ca{d.S, d.rhs2, d.x2, d.linv, d.flags, d.me};
-            tvmc_status st = launch_chol(c, ca);
+            ZCholArgs za{(double2 *)d.S, d.D, c->stage ? d.d1 : d.d0, (double2 *)d.linv, d.flags, d.m};
+            tvmc_status st = launch_zchol(c, za);
             if (st != TVMC_OK) return st;
-            hipLaunchKernelGGL(k_unembed, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage);
-            LAUNCHCHECK(c, "k_unembed");
         } else {
             CholArgs ca{d.S, d.D, c->stage ? d.d1 : d.d0, d.linv, d.flags, d.m};
             tvmc_status st = launch_chol(c, ca);
@@ -512,7 +530,7 @@ size_t q_bytes(const tvmc_ctx *c, int what) {
         return sizeof(double2) * d.m;
     case TVMC_Q_SAMPLES: return sizeof(uint64_t) * d.ns;
     case TVMC_Q_ELOC: return sizeof(double2) * d.ns;
-    case TVMC_Q_S: return sizeof(double) * (size_t)d.me * d.me;
+    case TVMC_Q_S: return sizeof(double) * s_doubles(d.kind, d.m);
     case TVMC_Q_OBAR: return (d.kind == TVMC_ANSATZ_RBM ? sizeof(double2) : sizeof(double)) * d.m;
     case TVMC_Q_BMEAN: return sizeof(double2) * d.nch;
     case TVMC_Q_DW: return sizeof(double) * d.nch;
@@ -573,7 +591,6 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.m = m;
     d.kind = a->kind;
     d.nh = nh;
-    d.me = solve_dim(a->kind, m);
     d.nch = nch;
     d.ns = c->n_samples;
     d.nc = c->n_chains;
@@ -623,10 +640,8 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.cT = (double2 *)(base + L.cT);
     d.sT = (double2 *)(base + L.sT);
     d.tt = (double2 *)(base + L.tt);
-    d.mp = (m + 63) / 64 * 64;
+    d.mp = (m + RQ_T - 1) / RQ_T * RQ_T;
     d.rbmP = (uint16_t *)(base + L.rbmP);
-    d.rhs2 = (double2 *)(base + L.rhs2);
-    d.x2 = (double2 *)(base + L.x2);
     d.D = (double2 *)(base + L.D);
     d.S = (double *)(base + L.S);
     d.linv = (double *)(base + L.linv);
@@ -803,7 +818,7 @@ tvmc_status tvmc_get(tvmc_ctx *c, int32_t what, int32_t traj, void *host, size_t
     case TVMC_Q_DELTA1: src = d.d1 + t * d.m; break;
     case TVMC_Q_SAMPLES: src = d.samples + t * d.ns; break;
     case TVMC_Q_ELOC: src = d.eloc + t * d.ns; break;
-    case TVMC_Q_S: src = d.S + t * d.me * d.me; break;
+    case TVMC_Q_S: src = d.S + t * s_doubles(d.kind, d.m); break;
     case TVMC_Q_D: src = d.D + t * d.m; break;
     case TVMC_Q_OBAR: src = d.kind == TVMC_ANSATZ_RBM ? (const void *)(d.obarc + t * d.m) : (const void *)(d.obar + t * d.m); break;
     case TVMC_Q_BMEAN: src = d.bmean + t * d.nch; break;

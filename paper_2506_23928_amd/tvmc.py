@@ -275,8 +275,9 @@ class Context:
 
     @property
     def solve_dim(self):
-        """Dimension of the real system solved: M (Jastrow) or 2M (RBM, real embedding)."""
-        return 2 * self.m if self.ansatz.kind == RBM else self.m
+        """Dimension of the system solved (real symmetric for the Jastrow ansatz, complex
+        Hermitian for the RBM)."""
+        return self.m
 
     def _count(self, key):
         c = self.config
@@ -286,7 +287,7 @@ class Context:
 
     def get(self, what, traj=0):
         dt, key = self._shapes[what]
-        if what == Q_OBAR and self.ansatz.kind == RBM:
+        if what in (Q_OBAR, Q_S) and self.ansatz.kind == RBM:
             dt = "c"
         cnt = self._count(key)
         np_dt = {"c": np.complex128, "d": np.float64, "u8": np.uint64, "u4": np.uint32, "f": np.float32}[dt]

@@ -29,14 +29,9 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-def _embed(S):
-    m = S.shape[0]
-    E = np.zeros((2 * m, 2 * m))
-    E[:m, :m] = S.real
-    E[m:, m:] = S.real
-    E[m:, :m] = S.imag
-    E[:m, m:] = -S.imag
-    return E
+def _hermitian(S):
+    """The full Hermitian matrix from its lower triangle."""
+    return np.tril(S) + np.tril(S, -1).conj().T
 
 
 @pytest.mark.parametrize("n,nh,ns,nc,scheme", [(5, 3, 256, 8, 0), (6, 70, 128, 4, 1), (4, 1, 64, 2, 0),
@@ -72,8 +67,8 @@ def test_rbm_step_parity(tv, orc, n, nh, ns, nc, scheme):
             assert _rel(ctx.get(T.Q_BMEAN, t), r["bmean"]) < 1e-12
             assert _rel(ctx.get(T.Q_OBAR, t), r["obar"]) < 1e-12
             S = ctx.get(T.Q_S, t)
-            want = _embed(r["S"] + eps * np.eye(m))
-            low = np.tril_indices(2 * m)
+            want = r["S"] + eps * np.eye(m)
+            low = np.tril_indices(m)
             assert np.abs(S[low] - want[low]).max() < 1e-12 * np.abs(want).max()
             assert _rel(ctx.get(T.Q_D, t), r["D"]) < 1e-11
         ctx.sr_solve()
@@ -177,19 +172,16 @@ def test_rbm_bf16_sbuild_matches_oracle(tv, orc, n, nh, ns, nc, solver):
         r = orc.evaluate(pb, 1, nh, cfg_o, th0, chains, traj=t, first=True, dw=dw, want_moments=False)
         assert np.array_equal(tv.unpack_samples(ctx.get(T.Q_SAMPLES, t), n), r["samples"])
         S = Ss[t]
-        E = _embed(r["S"] + eps * np.eye(m))
+        E = r["S"] + eps * np.eye(m)
         B = _bf16_bound(r["S"], ns)
-        Bb = np.block([[B, B], [B, B]])
-        low = np.tril_indices(2 * m)
-        err = np.abs(S[low] - E[low])
-        assert np.all(err <= Bb[low]), (err / Bb[low]).max()
+        low = np.tril_indices(m)
+        for part in (np.real, np.imag):
+            err = np.abs(part(S[low]) - part(E[low]))
+            assert np.all(err <= B[low]), (err / B[low]).max()
         assert _rel(ctx.get(T.Q_D, t), r["D"]) < 1e-12
         # the FP64 solve of the BF16 S: its own residual
-        Sf = np.tril(S) + np.tril(S, -1).T
         x = ctx.get(T.Q_DELTA0, t)
-        xe = np.concatenate([x.real, x.imag])
-        De = np.concatenate([r["D"].real, r["D"].imag])
-        assert np.abs(Sf @ xe - De).max() < 1e-9 * np.abs(De).max()
+        assert np.abs(_hermitian(S) @ x - r["D"]).max() < 1e-9 * np.abs(r["D"]).max()
 
 
 def test_rbm_bf16_full_size_launch(tv, orc):
@@ -227,9 +219,9 @@ def test_rbm_bf16_full_size_launch(tv, orc):
                 if l > k:
                     continue
                 want = Sref[a_, b_] + (w["diag_shift"] if k == l else 0.0)
-                assert abs(S[k, l] - want.real) <= B[a_, b_], (k, l)
-                if k != l:
-                    assert abs(S[m + k, l] - want.imag) <= B[a_, b_], (k, l)
+                assert abs(S[k, l].real - want.real) <= B[a_, b_], (k, l)
+                assert abs(S[k, l].imag - want.imag) <= B[a_, b_], (k, l)
         assert _rel(ctx.get(T.Q_OBAR, t)[ks], O.mean(0)) < 1e-12
         x = ctx.get(T.Q_DELTA0, t)
-        assert np.all(np.isfinite(x))
+        D = ctx.get(T.Q_D, t)
+        assert np.abs(_hermitian(S) @ x - D).max() < 1e-9 * np.abs(D).max()
