@@ -4,8 +4,12 @@
 A step is one Heun step of every trajectory of the workload: noise, then for the predictor and
 the corrector Metropolis sampling, local estimators, D, S + eps I, the FP64 Cholesky solve and
 the update; moments of the collective spin are recorded every `obs_every` steps from the
-predictor samples, as in a production run.  value = trajectory-steps per second with every
-input already resident in HBM.
+predictor samples and the learned proposal is retrained every `ar_train_every` steps, as in a
+production run.  value = trajectory-steps per second with every input already resident in HBM.
+The default workload is the N = 64 open chain with the RBM ansatz (M = 4224), 8192 samples and
+64 trajectories, learned proposal, BF16-split matrix-core S and FP64 solve; `plain_form_value`
+is the same workload in the plain form (FP64 S, single-flip proposal, one trajectory per
+launch).
 
 Extra objects on the JSON line:
   roofline      the dominant kernel's algorithmic work per launch over its average launch time
@@ -88,26 +92,34 @@ def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, s
     return tv.Context(prob, cfg, kind=kind, n_hidden=nh, theta0=th0)
 
 
-def cpu_baseline(w, budget_s=30.0):
+def cpu_baseline(w, ns_sample=None):
     """The oracle as it stands on a bounded sample: P host threads, each running one predictor
-    evaluation of its own trajectory (sampling, estimators, S, F, N^n, D, Cholesky solve); one
-    trajectory-step is two evaluations."""
+    evaluation of its own trajectory (sampling, local estimators, S, F, N^n, D, Cholesky solve);
+    one trajectory-step is two evaluations.  With ns_sample below the workload's sample count
+    the oracle's own phase timers scale the sample-linear phases (sampling and estimators;
+    means, S, F, N^n, D) by n_samples / ns_sample, and the solve is taken as measured."""
     import numpy as np
     import oracle as orc
     import workloads as wl
     cores = min(os.cpu_count() or 1, 16)
     J = orc.couplings(w["geom"], w["n"], w["alpha"], w["jscale"])
     pb = orc.Problem(J, w["h"], wl.jumps(w))
-    m = orc.n_params(0, w["n"])
-    cfg = orc.Config(n_samples=w["n_samples"], n_chains=w["n_chains"], burn_sweeps=w["burn_sweeps"],
+    rbm = w.get("ansatz", "jastrow") == "rbm"
+    kind, nh = (1, w["n_hidden"]) if rbm else (0, 0)
+    m = orc.n_params(kind, w["n"], nh)
+    th0 = wl.rbm_theta0(w["n"], nh, w["w_scale"], w["seed"]) if rbm else np.zeros(m)
+    ns_full = w["n_samples"]
+    ns = ns_sample or ns_full
+    cfg = orc.Config(n_samples=ns, n_chains=w["n_chains"], burn_sweeps=w["burn_sweeps"],
                      thin_sweeps=w["thin_sweeps"], dt=w["dt"], diag_shift=w["diag_shift"], seed=w["seed"])
-    done = []
+    times = []
 
     def work(traj):
         ch = orc.init_chains(w["seed"], traj, w["n"], w["n_chains"])
         dw = orc.draw_dw(w["seed"], traj, 0, len(wl.jumps(w)), w["dt"])
-        r = orc.evaluate(pb, 0, 0, cfg, np.zeros(m), ch, traj=traj, first=True, dw=dw, want_moments=False)
-        done.append(r["status"])
+        r = orc.evaluate(pb, kind, nh, cfg, th0, ch, traj=traj, first=True, dw=dw, want_moments=False)
+        sec = r["seconds"]
+        times.append((sec[0] + sec[1]) * ns_full / ns + sec[2])
 
     t0 = time.perf_counter()
     ths = [threading.Thread(target=work, args=(t,)) for t in range(cores)]
@@ -116,9 +128,17 @@ def cpu_baseline(w, budget_s=30.0):
     for t in ths:
         t.join()
     el = time.perf_counter() - t0
-    return {"value": (len(done) / 2.0) / el, "unit": "trajectory-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "%d trajectories x 1 predictor evaluation (half a Heun step) of %s, one per host thread, "
-                      "%.1f s wall" % (cores, w["name"], el)}
+    t_eval = sum(times) / len(times)
+    if ns == ns_full:
+        sample = ("%d trajectories x 1 predictor evaluation (half a Heun step) of %s, one per host thread, "
+                  "%.1f s wall" % (cores, w["name"], el))
+    else:
+        sample = ("%d trajectories x 1 predictor evaluation of %s with %d of its %d samples, one per host thread "
+                  "(%.1f s wall); sampling, estimators, S, F, N^n and D scaled by %d (linear in the samples), "
+                  "the Cholesky solve as measured: %.1f s per full evaluation" % (
+                      cores, w["name"], ns, ns_full, el, ns_full // ns, t_eval))
+    return {"value": cores / t_eval / 2.0, "unit": "trajectory-steps/s", "cores": cores, "kind": "oracle",
+            "sample": sample}
 
 
 def main():
@@ -126,7 +146,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="chain64_jastrow")
+    ap.add_argument("--workload", default="chain64_rbm_learned")
     ap.add_argument("--precision", choices=["mfma", "fp64"], default="mfma")
     ap.add_argument("--solver", choices=["auto", "one", "multi"], default="auto",
                     help="FP64 Cholesky with one or several workgroups per trajectory (auto: by batch size)")
@@ -242,13 +262,14 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w)
+        cpu = cpu_baseline(w, ns_sample=256 if w.get("ansatz") == "rbm" else None)
 
     out = {
         "metric": "trajectory-steps/s at N=64 (batched+learned vs plain) at fixed xi^2 error",
         "value": value, "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64" if (prec == tv.PREC_FP64 or kind == tv.JASTROW) else "f64+bf16x3",
+        "data": "synthetic",
         "config": {"workload": args.workload, "n_spins": n, "n_params": m, "n_traj": T, "n_samples": w["n_samples"],
                    "n_chains": w["n_chains"], "n_jumps": len(wl.jumps(w)), "dt": w["dt"],
                    "ansatz": w.get("ansatz", "jastrow"), "n_hidden": nh, "proposal": w.get("proposal", "flip"),

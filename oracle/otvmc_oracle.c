@@ -22,11 +22,13 @@
  *   initial chain configuration block b: ctr = (b, c, 0, 3<<24 | traj)
  * Uniforms carry 53 bits: u = ((a>>5)*2^26 + (b>>6)) * 2^-53.
  */
+#define _POSIX_C_SOURCE 199309L
 #include <complex.h>
 #include <math.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
+#include <time.h>
 #include <string.h>
 
 typedef double complex cplx;
@@ -72,6 +74,7 @@ typedef struct {           /* optional outputs of one evaluation (any pointer ma
     double *delta;         /* [M][2] */
     int64_t *accepts;      /* [n_chains] */
     double *obs;           /* [9] per-trajectory moments (see orc_moments) */
+    double *seconds;       /* [3] wall time of: sampling and local quantities; means, S, F, N^n, D; solve */
 } orc_eval_out;
 
 /* ------------------------------------------------------------------ Philox4x32-10 */
@@ -385,6 +388,13 @@ static void config_moments(const orc_ansatz *an, int n, const cplx *th, const in
 }
 
 /* Complex Hermitian Cholesky A = L L^H (lower, in place) and solve A x = b. */
+static double wall_seconds(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
 static int chol_solve(int m, cplx *A, cplx *b)
 {
     for (int j = 0; j < m; ++j) {
@@ -433,6 +443,7 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
     int n = pb->n, m = orc_n_params(an, n), nch = pb->n_ch;
     int nh = an->kind == ORC_RBM ? an->n_hidden : 0;
     int ns;
+    double t0 = wall_seconds();
     int8_t *conf;
     double *wgt;
     if (cf->enumerate) {
@@ -511,6 +522,7 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
         for (int q = 0; q < 9; ++q) out->obs[q] = mom_acc[q] * norm;
 
     int status = ORC_OK;
+    double t1 = wall_seconds(), t2 = t1;
     if (want_solve) {
         cplx *ob = calloc(m, sizeof(cplx)), *bm = calloc(nch + 1, sizeof(cplx));
         cplx *S = malloc(sizeof(cplx) * (want_solve == 1 ? (size_t)m * m : 1)), *F = malloc(sizeof(cplx) * m);
@@ -583,6 +595,7 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
                 for (int c = 0; c < nch; ++c) { out->bmean[2 * c] = creal(bm[c]); out->bmean[2 * c + 1] = cimag(bm[c]); }
         }
         /* regularised solve (S + eps I) delta = D */
+        t2 = wall_seconds();
         if (want_solve == 1) {
             for (int k = 0; k < m; ++k) S[(size_t)k * m + k] += cf->diag_shift;
             status = chol_solve(m, S, D);
@@ -590,6 +603,12 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
         if (out && out->delta && want_solve == 1)
             for (int k = 0; k < m; ++k) { out->delta[2 * k] = creal(D[k]); out->delta[2 * k + 1] = cimag(D[k]); }
         free(ob); free(bm); free(S); free(F); free(Nn); free(D); free(eeff);
+    }
+    if (out && out->seconds) {
+        double t3 = wall_seconds();
+        out->seconds[0] = t1 - t0;
+        out->seconds[1] = t2 - t1;
+        out->seconds[2] = t3 - t2;
     }
     free(th); free(conf); free(wgt); free(O); free(eh); free(B); free(ll); free(gam); free(R);
     return status;
