@@ -195,7 +195,8 @@ def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, cha
     """One evaluation of Eq. 8's right-hand side at theta; returns a dict of every quantity.
 
     ``chains`` (int8 [n_chains, N]) is advanced in place, as the sampler would.  want_solve:
-    0 sampling and local quantities only, 1 everything, 2 everything but S and the solve."""
+    0 sampling and local quantities only, 1 everything, 2 everything but S and the solve,
+    3 everything with the solve done in sample space (r["S"] then holds T = O_c O_c^H / ns)."""
     n, m, nch = problem.n, n_params(kind, problem.n, n_hidden), problem.n_ch
     ns = (1 << n) if cfg.enumerate else cfg.n_samples
     a = _Ansatz(kind, n_hidden)
@@ -205,7 +206,8 @@ def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, cha
         dwa = np.zeros(1)
     r = {
         "samples": np.zeros((ns, n), np.int8), "eloc": np.zeros(ns, np.complex128),
-        "S": np.zeros((m, m) if int(want_solve) == 1 else (1, 1), np.complex128), "F": np.zeros(m, np.complex128),
+        "S": np.zeros((m, m) if int(want_solve) == 1 else (ns, ns) if int(want_solve) == 3 else (1, 1), np.complex128),
+        "F": np.zeros(m, np.complex128),
         "Nn": np.zeros((max(nch, 1), m), np.complex128), "D": np.zeros(m, np.complex128),
         "bmean": np.zeros(max(nch, 1), np.complex128), "obar": np.zeros(m, np.complex128),
         "delta": np.zeros(m, np.complex128), "accepts": np.zeros(max(cfg.n_chains, 1), np.int64),

@@ -434,7 +434,8 @@ static int chol_solve(int m, cplx *A, cplx *b)
  * E_eff uses H_eff^Strat of Eq. 5 without its c-number terms (they cancel in F, which is a
  * covariance); <L_n + L_n^dag> is the Monte Carlo estimate 2 Re<B^n> from the same samples.
  * want_solve = 0 samples and evaluates observables only; 2 also computes the means, F, N^n
- * and D but neither S nor the solve (for large-N checks where S is checked separately).
+ * and D but neither S nor the solve (for large-N checks where S is checked separately);
+ * 3 solves in sample space (Monte Carlo mode only) and returns T = O_c O_c^H / ns in S.
  */
 int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, const double *theta,
              int8_t *chains, int32_t traj, int32_t step, int32_t stage, int32_t first, const double *dw,
@@ -447,7 +448,7 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
     int8_t *conf;
     double *wgt;
     if (cf->enumerate) {
-        if (n > 20) return ORC_E_INVAL;
+        if (n > 20 || want_solve == 3) return ORC_E_INVAL;
         ns = 1 << n;
     } else {
         if (cf->n_chains <= 0 || cf->n_samples % cf->n_chains) return ORC_E_INVAL;
@@ -599,8 +600,42 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
         if (want_solve == 1) {
             for (int k = 0; k < m; ++k) S[(size_t)k * m + k] += cf->diag_shift;
             status = chol_solve(m, S, D);
+        } else if (want_solve == 3) {
+            /* The same solve in sample space.  With A[x][k] = (O_k(x) - <O_k>) / sqrt(ns) and
+             * g[x] = (G(x) - <G>) / sqrt(ns), G(x) = -i dt E_eff(x) + sum_n dW_n B^n(x), one has
+             * S = A^H A and D = A^H g, and (A^H A + eps I)^-1 A^H = A^H (A A^H + eps I)^-1, so
+             *   delta = A^H u / sqrt(ns),  (T + eps I) u = G - <G>,  T = A A^H (ns x ns). */
+            cplx *T = malloc(sizeof(cplx) * (size_t)ns * ns), *u = malloc(sizeof(cplx) * ns);
+            if (!T || !u) return ORC_E_NOMEM;
+            cplx gm = 0.0;
+            for (int x = 0; x < ns; ++x) {
+                cplx g = -I * cf->dt * eeff[x];
+                for (int c = 0; c < nch; ++c) g += dw[c] * B[(size_t)c * ns + x];
+                u[x] = g;
+                gm += g;
+            }
+            gm *= norm;
+            for (int x = 0; x < ns; ++x) u[x] -= gm;
+            for (int x = 0; x < ns; ++x)
+                for (int y = 0; y <= x; ++y) {
+                    cplx v = 0.0;
+                    for (int k = 0; k < m; ++k)
+                        v += (O[(size_t)k * ns + x] - ob[k]) * conj(O[(size_t)k * ns + y] - ob[k]);
+                    T[(size_t)x * ns + y] = v * norm;
+                    T[(size_t)y * ns + x] = conj(v) * norm;
+                }
+            if (out && out->S)
+                for (size_t e = 0; e < (size_t)ns * ns; ++e) { out->S[2 * e] = creal(T[e]); out->S[2 * e + 1] = cimag(T[e]); }
+            for (int x = 0; x < ns; ++x) T[(size_t)x * ns + x] += cf->diag_shift;
+            status = chol_solve(ns, T, u);
+            for (int k = 0; k < m; ++k) {
+                cplx v = 0.0;
+                for (int x = 0; x < ns; ++x) v += conj(O[(size_t)k * ns + x] - ob[k]) * u[x];
+                D[k] = v * norm;
+            }
+            free(T); free(u);
         }
-        if (out && out->delta && want_solve == 1)
+        if (out && out->delta && (want_solve == 1 || want_solve == 3))
             for (int k = 0; k < m; ++k) { out->delta[2 * k] = creal(D[k]); out->delta[2 * k + 1] = cimag(D[k]); }
         free(ob); free(bm); free(S); free(F); free(Nn); free(D); free(eeff);
     }
