@@ -107,6 +107,11 @@ enum { TVMC_PROPOSAL_FLIP = 0, TVMC_PROPOSAL_LEARNED = 1 };
  * workgroups per trajectory (a few launches per 64-column panel), which fills the device when
  * the batch has fewer trajectories than compute units; AUTO picks by batch size. */
 enum { TVMC_SOLVER_AUTO = 0, TVMC_SOLVER_ONE_GROUP = 1, TVMC_SOLVER_MULTI_GROUP = 2 };
+/* Sample space: the same increment through the push-through identity
+ * (A^H A + eps I)^-1 A^H = A^H (A A^H + eps I)^-1 with A = (O - <O>) / sqrt(N_s), i.e. an
+ * N_s x N_s system T u = G - <G> and delta = A^H u / sqrt(N_s); AUTO takes it when M > N_s.
+ * TVMC_Q_S then returns T + eps I (N_s x N_s, lower triangle). */
+enum { TVMC_SOLVER_SAMPLE_SPACE = 3 };
 
 /* Quantities readable with tvmc_get (per trajectory unless noted). */
 enum {

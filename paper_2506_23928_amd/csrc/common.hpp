@@ -63,6 +63,9 @@ struct Dev {
     int n, m, nch, ns, nc, per, nt, nobs;
     int kind, nh;             // ansatz (0 Jastrow, 1 RBM), hidden units
     int mp;                   // M rounded up to 128 (rows of the RBM's BF16 operand planes)
+    int ss;                   // 1: the solve runs in sample space (S holds T = O_c O_c^H / N_s)
+    double2 *ssrow, *ssrhs, *ssu;  // sample space: row means of K, G - <G>, solution u   [T][N_s]
+    double *ssbar;            // mean of the row means [T]
     uint16_t *rbmP;           // RBM precision form: [T][4][mp][ns] BF16 split of the centred O
     int burn, thin, init_sweeps, scheme, traj0;
     uint32_t key0, key1;

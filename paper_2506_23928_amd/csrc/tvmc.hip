@@ -14,6 +14,7 @@
 #include "cholesky.hpp"
 #include "cholesky_mw.hpp"
 #include "cholesky_z.hpp"
+#include "samplespace.hpp"
 #include "common.hpp"
 #include "estimate.hpp"
 #include "observe.hpp"
@@ -53,7 +54,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
         bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1b, arW2Tb, arh, arda,
-        arg, arlogq, arloss, aracc, rbmP, total;
+        arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, total;
 };
 
 int mom_blocks_for(int ns) {
@@ -62,10 +63,15 @@ int mom_blocks_for(int ns) {
 }
 
 int n_params(int kind, int n, int nh) { return kind == TVMC_ANSATZ_RBM ? n + nh + n * nh : n + n * (n - 1) / 2; }
+// whether the solve runs in sample space (N_s x N_s) rather than parameter space (M x M)
+int use_sample_space(const tvmc_config *c, int m) {
+    return c->solver == TVMC_SOLVER_SAMPLE_SPACE || (c->solver == TVMC_SOLVER_AUTO && m > c->n_samples);
+}
+
 // S + eps I per trajectory: real symmetric M x M (Jastrow) or complex Hermitian M x M (RBM)
 size_t s_doubles(int kind, int m) { return (kind == TVMC_ANSATZ_RBM ? 2 : 1) * (size_t)m * m; }
 
-Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs, int ar, int ah, int nprob, int prec) {
+Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs, int ar, int ah, int nprob, int prec, int ss) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -106,8 +112,13 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.sT = take(rbm ? sizeof(double2) * tt * n * nh : 0);
     L.tt = take(rbm ? sizeof(double2) * tt * ns * nh : 0);
     L.D = take(sizeof(double2) * tt * m);
-    L.S = take(sizeof(double) * tt * s_doubles(kind, m));
-    L.linv = take((rbm ? sizeof(double2) : sizeof(double)) * tt * chol_panels(m) * CN * CN);
+    const int dim = ss ? ns : m;   // dimension of the system solved
+    L.S = take(sizeof(double) * tt * s_doubles(kind, dim));
+    L.linv = take((rbm ? sizeof(double2) : sizeof(double)) * tt * chol_panels(dim) * CN * CN);
+    L.ssrow = take(ss ? sizeof(double2) * tt * ns : 0);
+    L.ssrhs = take(ss ? sizeof(double2) * tt * ns : 0);
+    L.ssu = take(ss ? sizeof(double2) * tt * ns : 0);
+    L.ssbar = take(ss ? sizeof(double) * tt : 0);
     L.mom_part = take(sizeof(double) * tt * mom_blocks_for(ns) * 9);
     L.mom = take(sizeof(double) * tt * 9);
     L.hist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt * 9);
@@ -127,7 +138,7 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.arloss = take(sizeof(double) * tt);
     L.aracc = take(sizeof(uint32_t) * tt * nc);
     const size_t mp = ((size_t)m + RQ_T - 1) / RQ_T * RQ_T;
-    L.rbmP = take(rbm && prec == TVMC_PREC_MFMA ? sizeof(uint16_t) * tt * 4 * mp * ns : 0);
+    L.rbmP = take(rbm && prec == TVMC_PREC_MFMA && !ss ? sizeof(uint16_t) * tt * 4 * mp * ns : 0);
     L.total = o;
     return L;
 }
@@ -189,8 +200,10 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
         if (c->ar_train_every < 0 || c->ar_train_iters < 0 || !(c->ar_lr > 0.0))
             return snprintf(msg, len, "bad training settings"), TVMC_E_INVAL;
     }
-    if (c->solver < TVMC_SOLVER_AUTO || c->solver > TVMC_SOLVER_MULTI_GROUP)
+    if (c->solver < TVMC_SOLVER_AUTO || c->solver > TVMC_SOLVER_SAMPLE_SPACE)
         return snprintf(msg, len, "bad solver"), TVMC_E_INVAL;
+    if (use_sample_space(c, n_params(a->kind, p->n_sites, a->n_hidden)) && c->n_samples > 65535)
+        return snprintf(msg, len, "the sample-space solve takes at most 65535 samples"), TVMC_E_INVAL;
     return TVMC_OK;
 }
 
@@ -348,6 +361,25 @@ tvmc_status run_estimate(tvmc_ctx *c) {
             LAUNCHCHECK(c, "k_obar_D");
         }
     }
+    if (d.ss) {
+        Scope sc(c, "sbuild");
+        if (d.kind == TVMC_ANSATZ_RBM) {
+            const int nb = (d.ns + TK_T - 1) / TK_T;
+            hipLaunchKernelGGL(k_tk_rbm, dim3(nb * nb, T), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_tk_rbm");
+        } else {
+            hipLaunchKernelGGL(k_tk_jastrow, dim3((d.ns + 255) / 256, d.ns, T), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_tk_jastrow");
+        }
+        hipLaunchKernelGGL(k_tk_rowmean, dim3(d.ns, T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_tk_rowmean");
+        hipLaunchKernelGGL(k_tk_rbar, dim3(T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_tk_rbar");
+        hipLaunchKernelGGL(k_tk_centre, dim3((d.ns + 255) / 256, d.ns, T), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_tk_centre");
+        c->phase = 2;
+        return TVMC_OK;
+    }
     if (d.kind == TVMC_ANSATZ_RBM) {
         if (c->cfg.precision == TVMC_PREC_MFMA) {
             {
@@ -397,7 +429,8 @@ tvmc_status run_estimate(tvmc_ctx *c) {
 // batch alone would leave most compute units idle.
 tvmc_status launch_chol(tvmc_ctx *c, const CholArgs &ca) {
     const int T = c->d.nt;
-    const bool multi = c->cfg.solver == TVMC_SOLVER_MULTI_GROUP || (c->cfg.solver == TVMC_SOLVER_AUTO && T < 192);
+    const bool multi = c->cfg.solver == TVMC_SOLVER_MULTI_GROUP ||
+                       (c->cfg.solver != TVMC_SOLVER_ONE_GROUP && T < 192);
     if (!multi) {
         hipLaunchKernelGGL(k_chol_solve, dim3(T), dim3(256), 0, c->stream, ca);
         LAUNCHCHECK(c, "k_chol_solve");
@@ -450,7 +483,19 @@ tvmc_status run_solve(tvmc_ctx *c) {
     Dev &d = c->d;
     {
         Scope sc(c, "solve");
-        if (d.kind == TVMC_ANSATZ_RBM) {
+        if (d.ss) {
+            tvmc_status st;
+            if (d.kind == TVMC_ANSATZ_RBM) {
+                ZCholArgs za{(double2 *)d.S, d.ssrhs, d.ssu, (double2 *)d.linv, d.flags, d.ns};
+                st = launch_zchol(c, za);
+            } else {
+                CholArgs ca{d.S, d.ssrhs, d.ssu, d.linv, d.flags, d.ns};
+                st = launch_chol(c, ca);
+            }
+            if (st != TVMC_OK) return st;
+            hipLaunchKernelGGL(k_pushback, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage);
+            LAUNCHCHECK(c, "k_pushback");
+        } else if (d.kind == TVMC_ANSATZ_RBM) {
             ZCholArgs za{(double2 *)d.S, d.D, c->stage ? d.d1 : d.d0, (double2 *)d.linv, d.flags, d.m};
             tvmc_status st = launch_zchol(c, za);
             if (st != TVMC_OK) return st;
@@ -530,7 +575,7 @@ size_t q_bytes(const tvmc_ctx *c, int what) {
         return sizeof(double2) * d.m;
     case TVMC_Q_SAMPLES: return sizeof(uint64_t) * d.ns;
     case TVMC_Q_ELOC: return sizeof(double2) * d.ns;
-    case TVMC_Q_S: return sizeof(double) * s_doubles(d.kind, d.m);
+    case TVMC_Q_S: return sizeof(double) * s_doubles(d.kind, d.ss ? d.ns : d.m);
     case TVMC_Q_OBAR: return (d.kind == TVMC_ANSATZ_RBM ? sizeof(double2) : sizeof(double)) * d.m;
     case TVMC_Q_BMEAN: return sizeof(double2) * d.nch;
     case TVMC_Q_DW: return sizeof(double) * d.nch;
@@ -557,7 +602,7 @@ tvmc_status tvmc_workspace_size_batch(const tvmc_problem *p, int32_t np, const t
     if (!bytes) return TVMC_E_INVAL;
     const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden);
     *bytes = layout(a->kind, n, a->n_hidden, m, p->n_jumps, c->n_traj, c->n_samples, c->n_chains, c->n_obs_max,
-                    c->proposal, c->ar_hidden, np, c->precision).total;
+                    c->proposal, c->ar_hidden, np, c->precision, use_sample_space(c, m)).total;
     return TVMC_OK;
 }
 
@@ -575,7 +620,7 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden), nch = p->n_jumps, T = c->n_traj;
     const int nh = a->kind == TVMC_ANSATZ_RBM ? a->n_hidden : 0;
     const Layout L = layout(a->kind, n, nh, m, nch, T, c->n_samples, c->n_chains, c->n_obs_max, c->proposal,
-                            c->ar_hidden, np, c->precision);
+                            c->ar_hidden, np, c->precision, use_sample_space(c, m));
     if (!ws) return snprintf(g_err, sizeof(g_err), "workspace is null"), TVMC_E_INVAL;
     if (ws_bytes < L.total) return snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu", ws_bytes, L.total), TVMC_E_NOMEM;
     if ((uintptr_t)ws % 256) return snprintf(g_err, sizeof(g_err), "workspace must be 256-byte aligned"), TVMC_E_INVAL;
@@ -642,6 +687,11 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.tt = (double2 *)(base + L.tt);
     d.mp = (m + RQ_T - 1) / RQ_T * RQ_T;
     d.rbmP = (uint16_t *)(base + L.rbmP);
+    d.ss = use_sample_space(c, m);
+    d.ssrow = (double2 *)(base + L.ssrow);
+    d.ssrhs = (double2 *)(base + L.ssrhs);
+    d.ssu = (double2 *)(base + L.ssu);
+    d.ssbar = (double *)(base + L.ssbar);
     d.D = (double2 *)(base + L.D);
     d.S = (double *)(base + L.S);
     d.linv = (double *)(base + L.linv);
@@ -818,7 +868,7 @@ tvmc_status tvmc_get(tvmc_ctx *c, int32_t what, int32_t traj, void *host, size_t
     case TVMC_Q_DELTA1: src = d.d1 + t * d.m; break;
     case TVMC_Q_SAMPLES: src = d.samples + t * d.ns; break;
     case TVMC_Q_ELOC: src = d.eloc + t * d.ns; break;
-    case TVMC_Q_S: src = d.S + t * s_doubles(d.kind, d.m); break;
+    case TVMC_Q_S: src = d.S + t * s_doubles(d.kind, d.ss ? d.ns : d.m); break;
     case TVMC_Q_D: src = d.D + t * d.m; break;
     case TVMC_Q_OBAR: src = d.kind == TVMC_ANSATZ_RBM ? (const void *)(d.obarc + t * d.m) : (const void *)(d.obar + t * d.m); break;
     case TVMC_Q_BMEAN: src = d.bmean + t * d.nch; break;

@@ -21,7 +21,7 @@ PREC_FP64, PREC_MFMA = 0, 1
 (Q_THETA, Q_THETA_EVAL, Q_DELTA0, Q_DELTA1, Q_SAMPLES, Q_ELOC, Q_S, Q_D, Q_OBAR, Q_BMEAN, Q_DW, Q_ACCEPTS,
  Q_CHAINS, Q_MOMENTS, Q_OBS_HIST, Q_AR_PARAMS, Q_AR_GRAD, Q_AR_LOGQ, Q_AR_LOSS, Q_AR_ACCEPTS) = range(20)
 PROPOSAL_FLIP, PROPOSAL_LEARNED = 0, 1
-SOLVER_AUTO, SOLVER_ONE_GROUP, SOLVER_MULTI_GROUP = 0, 1, 2
+SOLVER_AUTO, SOLVER_ONE_GROUP, SOLVER_MULTI_GROUP, SOLVER_SAMPLE_SPACE = 0, 1, 2, 3
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -274,10 +274,16 @@ class Context:
         return ms.value, cnt.value
 
     @property
+    def sample_space(self):
+        """Whether the solve runs in sample space (the library's rule: requested, or M > N_s)."""
+        c = self.config
+        return c.solver == SOLVER_SAMPLE_SPACE or (c.solver == SOLVER_AUTO and self.m > c.n_samples)
+
+    @property
     def solve_dim(self):
-        """Dimension of the system solved (real symmetric for the Jastrow ansatz, complex
-        Hermitian for the RBM)."""
-        return self.m
+        """Dimension of the system solved: M, or N_s in sample space (real symmetric for the
+        Jastrow ansatz, complex Hermitian for the RBM)."""
+        return self.config.n_samples if self.sample_space else self.m
 
     def _count(self, key):
         c = self.config

@@ -37,8 +37,10 @@ def _hermitian(S):
 @pytest.mark.parametrize("n,nh,ns,nc,scheme", [(5, 3, 256, 8, 0), (6, 70, 128, 4, 1), (4, 1, 64, 2, 0),
                                                (9, 20, 192, 3, 0)])
 def test_rbm_step_parity(tv, orc, n, nh, ns, nc, scheme):
-    """Predictor and corrector of one step: samples, accepts, local energies, <B^n>, <O_k>, S
-    (real embedding), D, both increments and theta; N' = 70 takes two hidden units per lane."""
+    """Predictor and corrector of one step: samples, accepts, local energies, <B^n>, <O_k>, S,
+    D, both increments and theta; N' = 70 takes two hidden units per lane.  Where M > N_s
+    (M = 496 and 209) the library solves in sample space: T against the oracle's sample-space
+    T, the increments against its sample-space solve."""
     from paper_2506_23928_amd import tvmc as T
     J, hx, jumps = wl.random_problem(n, seed=40 + n)
     m = orc.n_params(1, n, nh)
@@ -49,12 +51,16 @@ def test_rbm_step_parity(tv, orc, n, nh, ns, nc, scheme):
     pb = orc.Problem(J, hx, jumps)
     cfg = tv.make_config(TT, ns, nc, dt, eps, 2, 1, 3, scheme, tv.PREC_FP64, seed=seed, traj_offset=3)
     ctx = tv.Context(tv.Problem(J, hx, jumps), cfg, kind=tv.tvmc.RBM, n_hidden=nh, theta0=th0)
+    ss = ctx.sample_space
+    assert ss == (m > ns)
+    want_solve, dim = (3, ns) if ss else (1, m)
     ref = {}
     for t in range(TT):
         traj = 3 + t
         chains = orc.init_chains(seed, traj, n, nc)
         dw = orc.draw_dw(seed, traj, 0, len(jumps), dt)
-        ref[t] = [chains, dw, orc.evaluate(pb, 1, nh, cfg_o, th0, chains, traj=traj, first=True, dw=dw)]
+        ref[t] = [chains, dw, orc.evaluate(pb, 1, nh, cfg_o, th0, chains, traj=traj, first=True, dw=dw,
+                                           want_solve=want_solve)]
     for stage in (0, 1):
         ctx.sample()
         ctx.estimate()
@@ -67,8 +73,8 @@ def test_rbm_step_parity(tv, orc, n, nh, ns, nc, scheme):
             assert _rel(ctx.get(T.Q_BMEAN, t), r["bmean"]) < 1e-12
             assert _rel(ctx.get(T.Q_OBAR, t), r["obar"]) < 1e-12
             S = ctx.get(T.Q_S, t)
-            want = r["S"] + eps * np.eye(m)
-            low = np.tril_indices(m)
+            want = r["S"] + eps * np.eye(dim)
+            low = np.tril_indices(dim)
             assert np.abs(S[low] - want[low]).max() < 1e-12 * np.abs(want).max()
             assert _rel(ctx.get(T.Q_D, t), r["D"]) < 1e-11
         ctx.sr_solve()
@@ -81,7 +87,8 @@ def test_rbm_step_parity(tv, orc, n, nh, ns, nc, scheme):
                 chains, dw, r0 = ref[t]
                 th_e = th0 + (r0["delta"] if scheme == 0 else 0.5 * r0["delta"])
                 assert _rel(ctx.get(T.Q_THETA_EVAL, t), th_e) < 1e-8
-                ref[t].append(orc.evaluate(pb, 1, nh, cfg_o, th_e, chains, traj=3 + t, stage=1, first=False, dw=dw))
+                ref[t].append(orc.evaluate(pb, 1, nh, cfg_o, th_e, chains, traj=3 + t, stage=1, first=False, dw=dw,
+                                           want_solve=want_solve))
     ctx.synchronize()
     for t in range(TT):
         r0, r1 = ref[t][2], ref[t][3]
@@ -185,15 +192,16 @@ def test_rbm_bf16_sbuild_matches_oracle(tv, orc, n, nh, ns, nc, solver):
 
 
 def test_rbm_bf16_full_size_launch(tv, orc):
-    """The N = 64 RBM workload with the learned proposal in the launch configuration the
-    benchmark times (64 trajectories, 8192 samples, N' = 64, M = 4224, BF16-split S).  The
-    oracle has no learned sampler, so on the GPU's own samples of the first and last
-    trajectory: <O_k> and ~1800 S entries (60 sampled parameters, every pair) against FP64 sums
-    over the oracle's log-derivatives, within the split/accumulation bound."""
+    """The N = 64 RBM workload in the launch configuration the benchmark times (64
+    trajectories, 8192 samples, N' = 64, M = 4224, BF16-split S), with single-flip proposals
+    so that the oracle reproduces the samples: for the first and last trajectory the samples
+    bit for bit, <O_k> and ~1800 S entries (60 sampled parameters, every pair) against FP64
+    sums over the oracle's log-derivatives of its own samples, within the split/accumulation
+    bound, and the solve against its residual."""
     from paper_2506_23928_amd import tvmc as T
     import bench
     w = dict(wl.WORKLOADS["chain64_rbm_learned"])
-    ctx = bench.build_context(tv, w, tv.PREC_MFMA)
+    ctx = bench.build_context(tv, w, tv.PREC_MFMA, proposal=tv.PROPOSAL_FLIP)
     n, nh, ns, TT = w["n"], w["n_hidden"], w["n_samples"], w["n_traj"]
     m = orc.n_params(1, n, nh)
     ctx.sample()
@@ -202,9 +210,15 @@ def test_rbm_bf16_full_size_launch(tv, orc):
     ctx.sr_solve()
     ctx.synchronize()
     th0 = wl.rbm_theta0(n, nh, w["w_scale"], w["seed"])
+    pb = orc.Problem(orc.couplings(w["geom"], n, w["alpha"], w["jscale"]), w["h"], wl.jumps(w))
+    cfg_o = orc.Config(n_samples=ns, n_chains=w["n_chains"], burn_sweeps=w["burn_sweeps"],
+                       thin_sweeps=w["thin_sweeps"], dt=w["dt"], diag_shift=w["diag_shift"], seed=w["seed"])
     rng = np.random.default_rng(1)
     for t in (0, TT - 1):
-        smp = tv.unpack_samples(ctx.get(T.Q_SAMPLES, t), n)
+        r = orc.evaluate(pb, 1, nh, cfg_o, th0, orc.init_chains(w["seed"], t, n, w["n_chains"]), traj=t,
+                         first=True, want_solve=0, want_moments=False)
+        smp = r["samples"]
+        assert np.array_equal(tv.unpack_samples(ctx.get(T.Q_SAMPLES, t), n), smp)
         O = np.zeros((ns, 60), np.complex128)
         ks = np.concatenate([[0, n, n + nh, m - 1], rng.integers(0, m, 56)])
         for s in range(ns):

@@ -41,6 +41,12 @@ WORKLOADS = {
                                     t_end=1.0, diag_shift=1e-4, obs_every=10, burn_sweeps=2, thin_sweeps=1, seed=0,
                                     proposal="learned", ar_hidden=128, ar_train_every=20, ar_train_iters=50,
                                     ar_lr=3e-3, w_scale=0.01),
+    # N=64 open chain, RBM with hidden density 4 (N' = 256, 16704 complex parameters) and 4096
+    # samples x 32 trajectories: M > N_s, the sample-space solve
+    "chain64_rbm_wide": dict(geom="obc", n=64, alpha=1.5, jscale=1.0, h=0.5, decay=0.1, dephase=0.0,
+                             ansatz="rbm", n_hidden=256, n_samples=4096, n_chains=64, n_traj=32, dt=0.01,
+                             t_end=1.0, diag_shift=1e-4, obs_every=10, burn_sweeps=2, thin_sweeps=1, seed=0,
+                             proposal="flip", w_scale=0.01),
 }
 
 
