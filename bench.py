@@ -208,32 +208,43 @@ def main():
 
     # dominant kernel: the FP64 Cholesky solve (one launch covers every trajectory)
     dom = max(groups, key=lambda g: groups[g]["total_ms"])
+    ss, ns = ctx.sample_space, w["n_samples"]
+    dim = ns if ss else m                 # dimension of the system solved
     if dom == "solve":
-        if kind == tv.RBM:   # complex Hermitian Cholesky (4/3 M^3 real flops) and two triangular solves
-            flops = T * (4.0 * m ** 3 / 3.0 + 16.0 * m * m)
+        if kind == tv.RBM:   # complex Hermitian Cholesky (4/3 n^3 real flops) and two triangular solves
+            flops = T * (4.0 * dim ** 3 / 3.0 + 16.0 * dim * dim)
+            kname = "k_zmw_* (complex solve)"
         else:
-            flops = T * (m ** 3 / 3.0 + m * m / 2.0 + m / 6.0 + 4.0 * m * m)
+            flops = T * (dim ** 3 / 3.0 + dim * dim / 2.0 + dim / 6.0 + 4.0 * dim * dim)
+            multi = args.solver == "multi" or (args.solver != "one" and T < 192)
+            kname = "k_cmw_* (solve)" if multi else "k_chol_solve"
+        if ss:               # push-back delta = A^H u: M x N_s complex multiply-adds
+            flops += T * 8.0 * m * ns
         achieved = flops / (groups["solve"]["avg_ms"] * 1e-3) / 1e12
-        multi = args.solver == "multi" or (args.solver == "auto" and T < 192)
-        roof = {"kernel": "k_cmw_* (solve)" if multi else "k_chol_solve", "bound": "mfma", "achieved": achieved,
-                "peak": PEAKS["fp64"],
-                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_chol_solve")}
+        roof = {"kernel": kname, "bound": "mfma", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic(kname.split()[0])}
+    elif dom == "sbuild" and ss and kind == tv.RBM:
+        # K = (1 + q)(1 + g) - 1 with g = t t^H over N' hidden units: N_s^2 N' complex multiply-adds
+        flops = T * 8.0 * ns * ns * nh
+        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_tk_rbm", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_tk_rbm")}
     elif dom == "sbuild" and kind == tv.RBM and prec == tv.PREC_MFMA:
         # complex Hermitian S: M (M + 1) / 2 entries, N_s complex multiply-adds (8 flops) each,
         # on BF16 matrix cores (three split products per real product)
-        flops = T * (m * (m + 1) / 2.0) * w["n_samples"] * 8.0
+        flops = T * (m * (m + 1) / 2.0) * ns * 8.0
         achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": "k_sbuild_rbm_bf16", "bound": "mfma", "achieved": achieved, "peak": PEAKS["bf16"] / 3.0,
                 "unit": "TFLOP/s", "frac": achieved / (PEAKS["bf16"] / 3.0), "traffic": read_traffic("k_sbuild_rbm_bf16"),
                 "note": "peak = BF16 dense peak / 3 (three split products per real product)"}
     elif dom == "sbuild" and kind == tv.RBM:
         # complex Hermitian S: M (M + 1) / 2 entries, N_s complex multiply-adds (8 flops) each
-        flops = T * (m * (m + 1) / 2.0) * w["n_samples"] * 8.0
+        flops = T * (m * (m + 1) / 2.0) * ns * 8.0
         achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": "k_sbuild_rbm_f64", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
                 "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_sbuild_rbm_f64")}
-    elif dom == "sbuild":
-        ops = T * (m * (m + 1) / 2.0) * w["n_samples"] * 2.0
+    elif dom == "sbuild" and not ss:
+        ops = T * (m * (m + 1) / 2.0) * ns * 2.0
         achieved = ops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": "k_sbuild_i8", "bound": "mfma", "achieved": achieved, "peak": PEAKS["int8"],
                 "unit": "TOP/s", "frac": achieved / PEAKS["int8"], "traffic": read_traffic("k_sbuild_i8")}
@@ -275,7 +286,8 @@ def main():
                    "ansatz": w.get("ansatz", "jastrow"), "n_hidden": nh, "proposal": w.get("proposal", "flip"),
                    "s_build": ("int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU") if kind == tv.JASTROW
                    else ("BF16-split MFMA, FP32 accumulate" if prec == tv.PREC_MFMA else "FP64 VALU (complex)"),
-                   "solve": "FP64 Cholesky", "solver": args.solver, "obs_every": w["obs_every"]},
+                   "solve": "FP64 Cholesky" + (" (sample space)" if ss else ""), "solver": args.solver,
+                   "obs_every": w["obs_every"]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_form_value": plain,

@@ -87,13 +87,26 @@ __global__ __launch_bounds__(256) void k_sbuild_rbm_bf16(Dev a) {
             sre[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
             sim[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         }
+    // operands of step k0 + 32 are loaded while step k0 is multiplied (one wave per SIMD,
+    // so the load latency is hidden by the wave's own MFMAs)
+    bf16x8_t A[4][4], B[4][4], An[4][4], Bn[4][4];
+    for (int u = 0; u < 4; ++u)
+        for (int q = 0; q < 4; ++q) {
+            An[u][q] = *(const bf16x8_t *)(rowp + (size_t)u * 16 * ns + q * plane);
+            Bn[u][q] = *(const bf16x8_t *)(colp + (size_t)u * 16 * ns + q * plane);
+        }
     for (size_t k0 = 0; k0 < ns; k0 += 32) {
-        bf16x8_t A[4][4], B[4][4];
         for (int u = 0; u < 4; ++u)
             for (int q = 0; q < 4; ++q) {
-                A[u][q] = *(const bf16x8_t *)(rowp + (size_t)u * 16 * ns + q * plane + k0);
-                B[u][q] = *(const bf16x8_t *)(colp + (size_t)u * 16 * ns + q * plane + k0);
+                A[u][q] = An[u][q];
+                B[u][q] = Bn[u][q];
             }
+        if (k0 + 32 < ns)
+            for (int u = 0; u < 4; ++u)
+                for (int q = 0; q < 4; ++q) {
+                    An[u][q] = *(const bf16x8_t *)(rowp + (size_t)u * 16 * ns + q * plane + k0 + 32);
+                    Bn[u][q] = *(const bf16x8_t *)(colp + (size_t)u * 16 * ns + q * plane + k0 + 32);
+                }
         for (int u = 0; u < 4; ++u) {
             const bf16x8_t nih = neg_bf16x8(A[u][2]), nil = neg_bf16x8(A[u][3]);
             for (int v = 0; v < 4; ++v) {
