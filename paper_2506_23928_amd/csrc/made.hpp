@@ -5,7 +5,7 @@
 //   output i sees hidden units with d(k) <= i;  q(s_i = +1 | s_<i) = sigmoid(l_i);
 //   a_k = b1_k + sum_{j<d(k)} W1[k][j] s_j,  h = relu(a),  l_i = b2_i + sum_{d(k)<=i} W2[i][k] h_k.
 // Training: full-batch Adam on the mean negative log-likelihood, FP32 master weights; the
-// sampler reads BF16 copies (W1 and W2 transposed, [k][.]) and accumulates in FP32.  Every
+// sampler reads BF16 copies and accumulates in FP32.  Every
 // independent proposal uses the same BF16 network for q(s') and q(s), so the chain stays exact.
 #pragma once
 #include "common.hpp"
@@ -33,15 +33,43 @@ __device__ __forceinline__ ArView ar_view(float *base, int n, int h) {
 }
 __host__ __device__ inline size_t ar_params(int n, int h) { return (size_t)2 * n * h + n + h; }
 
-// refresh the BF16 inference copies: W1b [T][H][N], W2Tb [T][H][N] (W2 transposed)
+// refresh the BF16 inference copies of trajectory t: W1T [N][H] (W1 transposed), W2 [N][H]
+// (row i = the weights of output i) and W2T [H][N]; element (k, j) of W1 is W1T[j H + k]
 __device__ __forceinline__ void ar_copy_one(const Dev &a, int t, size_t e) {
     const int n = a.n, h = a.ah;
     ArView p = ar_view(a.arP + (size_t)t * a.arnp, n, h);
     if (e < (size_t)h * n) {
         const int k = (int)(e / n), j = (int)(e % n);
-        a.arW1b[(size_t)t * h * n + e] = f2bf(p.W1[e]);
-        a.arW2Tb[(size_t)t * h * n + (size_t)k * n + j] = f2bf(p.W2[(size_t)j * h + k]);
+        const size_t base = (size_t)t * h * n;
+        a.arW1Tb[base + (size_t)j * h + k] = f2bf(p.W1[e]);
+        a.arW2b[base + (size_t)j * h + k] = f2bf(p.W2[(size_t)j * h + k]);
+        a.arW2Tb[base + (size_t)k * n + j] = f2bf(p.W2[(size_t)j * h + k]);
     }
+}
+
+// Weights an independent proposal reads, in the [site][hidden unit] layout (consecutive lanes
+// read consecutive hidden units): from LDS when they fit there, else from global memory.
+constexpr int AR_LDS_W = 8192;    // H N entries per matrix staged in LDS (H <= 128 at N = 64)
+struct ArNet {
+    const uint16_t *W1T, *W2;      // element (k, i) at [i H + k]
+    const float *b1, *b2;
+};
+// Stage trajectory t's draw weights into LDS (whole workgroup; a barrier must follow).
+__device__ __forceinline__ ArNet ar_net(const Dev &a, int t, uint16_t *sW1T, uint16_t *sW2, float *sb1, float *sb2) {
+    const int n = a.n, h = a.ah;
+    const size_t base = (size_t)t * h * n;
+    const float *b1 = a.arP + (size_t)t * a.arnp + (size_t)h * n;
+    const float *b2 = b1 + h + (size_t)n * h;
+    for (int i = threadIdx.x; i < h; i += blockDim.x) sb1[i] = b1[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sb2[i] = b2[i];
+    if (h * n <= AR_LDS_W) {
+        for (int e = threadIdx.x; e < h * n; e += blockDim.x) {
+            sW1T[e] = a.arW1Tb[base + e];
+            sW2[e] = a.arW2b[base + e];
+        }
+        return ArNet{sW1T, sW2, sb1, sb2};
+    }
+    return ArNet{a.arW1Tb + base, a.arW2b + base, sb1, sb2};
 }
 
 // deterministic initialisation: W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) on unmasked entries,
@@ -225,11 +253,11 @@ __device__ float ar_logq(const Dev &a, int t, uint64_t mk, int lane, float *hs) 
     const int n = a.n, h = a.ah;
     const float *b1 = a.arP + (size_t)t * a.arnp + (size_t)h * n;
     const float *b2 = b1 + h + (size_t)n * h;
-    const uint16_t *W1 = a.arW1b + (size_t)t * h * n, *W2T = a.arW2Tb + (size_t)t * h * n;
+    const uint16_t *W1T = a.arW1Tb + (size_t)t * h * n, *W2T = a.arW2Tb + (size_t)t * h * n;
     for (int k = lane; k < h; k += 64) {
         float x = b1[k];
         const int dk = ar_degree(k, n);
-        for (int j = 0; j < dk; ++j) x += bf2f(W1[(size_t)k * n + j]) * (float)spin(mk, j);
+        for (int j = 0; j < dk; ++j) x += bf2f(W1T[(size_t)j * h + k]) * (float)spin(mk, j);
         hs[k] = fmaxf(x, 0.f);
     }
     float lq = 0.f;
@@ -246,8 +274,8 @@ __device__ float ar_logq(const Dev &a, int t, uint64_t mk, int lane, float *hs) 
 // returns the same s', log q(s') and accept uniform).  Philox stream 6, counter
 // (17 idx + block, ctr1, step, 6 << 24 | traj): blocks 0..15 give one 24-bit site uniform per
 // site (word lane & 3 of block lane >> 2), block 16 gives the 53-bit accept uniform.
-__device__ uint64_t ar_draw(const Dev &a, int t, uint32_t ctr1, int step, uint32_t idx, int lane, float &lqn,
-                            double &uacc) {
+__device__ uint64_t ar_draw(const Dev &a, const ArNet &net, int t, uint32_t ctr1, int step, uint32_t idx, int lane,
+                            float &lqn, double &uacc) {
     const int n = a.n, h = a.ah;
     uint32_t rr[4] = {0u, 0u, 0u, 0u};
     if (lane < 17)
@@ -260,18 +288,17 @@ __device__ uint64_t ar_draw(const Dev &a, int t, uint32_t ctr1, int step, uint32
     }
     const float usite = ((float)(word >> 8) + 0.5f) * (1.0f / 16777216.0f);
     uacc = u53((uint32_t)__builtin_amdgcn_readlane((int)rr[0], 16), (uint32_t)__builtin_amdgcn_readlane((int)rr[1], 16));
-    const float *b1 = a.arP + (size_t)t * a.arnp + (size_t)h * n;
-    const float *b2 = b1 + h + (size_t)n * h;
-    const uint16_t *W1 = a.arW1b + (size_t)t * h * n, *W2T = a.arW2Tb + (size_t)t * h * n;
+    const float *b2 = net.b2;
+    const uint16_t *W1T = net.W1T, *W2 = net.W2;
     float ak[4];
-    for (int q = 0; q < 4; ++q) ak[q] = (lane + 64 * q < h) ? b1[lane + 64 * q] : 0.f;
+    for (int q = 0; q < 4; ++q) ak[q] = (lane + 64 * q < h) ? net.b1[lane + 64 * q] : 0.f;
     uint64_t mnew = 0ull;
     float lq = 0.f;
     for (int ii = 0; ii < n; ++ii) {
         float part = 0.f;
         for (int q = 0; q < 4; ++q) {
             const int k = lane + 64 * q;
-            if (k < h && ar_degree(k, n) <= ii) part += bf2f(W2T[(size_t)k * n + ii]) * fmaxf(ak[q], 0.f);
+            if (k < h && ar_degree(k, n) <= ii) part += bf2f(W2[(size_t)ii * h + k]) * fmaxf(ak[q], 0.f);
         }
         const float l = b2[ii] + wave_sum_f(part);
         const float pu = 1.f / (1.f + expf(-l));
@@ -282,7 +309,7 @@ __device__ uint64_t ar_draw(const Dev &a, int t, uint32_t ctr1, int step, uint32
         if (up) mnew |= (1ull << ii);
         for (int q = 0; q < 4; ++q) {
             const int k = lane + 64 * q;
-            if (k < h && ar_degree(k, n) > ii) ak[q] += bf2f(W1[(size_t)k * n + ii]) * sv;
+            if (k < h && ar_degree(k, n) > ii) ak[q] += bf2f(W1T[(size_t)ii * h + k]) * sv;
         }
     }
     lqn = lq;

@@ -59,6 +59,8 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
     __shared__ double lwi[64 * 64];
     __shared__ double2 tl[CPB][64 * QH];
     __shared__ float arh_s[AR ? CPB : 1][AR ? 256 : 1];
+    __shared__ uint16_t arw_s[AR ? 2 * AR_LDS_W : 1];
+    __shared__ float arb_s[AR ? 256 + 64 : 1];
     const int n = a.n, nh = a.nh;
     const int t = blockIdx.y;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -71,6 +73,8 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
             lwi[i] = gwi[i];
         }
     }
+    ArNet net{};
+    if (AR) net = ar_net(a, t, arw_s, arw_s + AR_LDS_W, arb_s, arb_s + 256);
     __syncthreads();
     const double *wr = in_lds ? lwr : gwr;
     const double *wi = in_lds ? lwi : gwi;
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
                 }
                 float lqn;
                 double uacc;
-                const uint64_t mnew = ar_draw(a, t, ctr1, step, ar_idx++, lane, lqn, uacc);
+                const uint64_t mnew = ar_draw(a, net, t, ctr1, step, ar_idx++, lane, lqn, uacc);
                 // hidden pre-activations of s' (same summation order as at the start) and
                 // Re log psi(s') - Re log psi(s)
                 double ngr[QH], ngi[QH], nlc[QH], dsum = 0.0;

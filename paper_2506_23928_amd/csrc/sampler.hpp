@@ -65,6 +65,8 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, in
     __shared__ double lre[64 * 64];
     __shared__ double lim[64 * 64];
     __shared__ float arh_s[AR ? CPB : 1][AR ? 256 : 1];
+    __shared__ uint16_t arw_s[AR ? 2 * AR_LDS_W : 1];
+    __shared__ float arb_s[AR ? 256 + 64 : 1];
     const int n = a.n;
     const int t = blockIdx.y;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -77,6 +79,8 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, in
             lim[i] = ei[i];
         }
     }
+    ArNet net{};
+    if (AR) net = ar_net(a, t, arw_s, arw_s + AR_LDS_W, arb_s, arb_s + 256);
     __syncthreads();
     const bool act = lane < n;
     const double2 *th = a.theta_eval + (size_t)t * a.m;
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, in
                 }
                 float lqn;
                 double uacc;
-                const uint64_t mnew = ar_draw(a, t, ctr1, step, ar_idx++, lane, lqn, uacc);
+                const uint64_t mnew = ar_draw(a, net, t, ctr1, step, ar_idx++, lane, lqn, uacc);
                 // fields of s' and Re log psi of both configurations
                 double nre = 0.0, nim = 0.0, lpc = 0.0, lpn = 0.0;
                 if (act) {

@@ -53,7 +53,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1b, arW2Tb, arh, arda,
+        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1Tb, arW2b, arW2Tb, arh, arda,
         arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, total;
 };
 
@@ -129,7 +129,8 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.arG = take(sizeof(float) * tt * np);
     L.arM = take(sizeof(float) * tt * np);
     L.arV = take(sizeof(float) * tt * np);
-    L.arW1b = take(ar ? sizeof(uint16_t) * tt * ah * n : 0);
+    L.arW1Tb = take(ar ? sizeof(uint16_t) * tt * ah * n : 0);
+    L.arW2b = take(ar ? sizeof(uint16_t) * tt * ah * n : 0);
     L.arW2Tb = take(ar ? sizeof(uint16_t) * tt * ah * n : 0);
     L.arh = take(ar ? sizeof(float) * tt * ns * ah : 0);
     L.arda = take(ar ? sizeof(float) * tt * ns * ah : 0);
@@ -707,7 +708,8 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.arG = (float *)(base + L.arG);
     d.arM = (float *)(base + L.arM);
     d.arV = (float *)(base + L.arV);
-    d.arW1b = (uint16_t *)(base + L.arW1b);
+    d.arW1Tb = (uint16_t *)(base + L.arW1Tb);
+    d.arW2b = (uint16_t *)(base + L.arW2b);
     d.arW2Tb = (uint16_t *)(base + L.arW2Tb);
     d.arh = (float *)(base + L.arh);
     d.arda = (float *)(base + L.arda);
