@@ -58,77 +58,126 @@ __device__ __forceinline__ bf16x8_t neg_bf16x8(bf16x8_t v) {
 #define MFMA_BF16(A, B, C) __builtin_amdgcn_mfma_f32_16x16x32_bf16((A), (B), (C), 0, 0, 0)
 
 // One workgroup (4 waves) per 128x128 complex tile of the lower triangle; wave (wr, wc) takes
-// the 64x64 sub-tile, 4x4 blocks of 16x16 (128 FP32 accumulators).  Operand fragments come
-// straight from P (16 bytes per lane: row lane & 15, samples 8 (lane >> 4) .. +7 of the
-// 32-sample step; the Gram product only needs the row and column operands to use the same
-// sample order): per step a wave loads 32 fragments and issues 192 MFMAs.
+// the 64x64 sub-tile, 4x4 blocks of 16x16 (128 FP32 accumulators).  Per step of 32 samples
+// the workgroup stages the tile's row and column operands (4 planes x 128 rows x 32 samples
+// each, 64 KB) through LDS, loaded one step ahead into registers, so every fragment crosses
+// the L2 once per workgroup; rows are padded to 40 BF16 (80 B), which keeps the 16-byte
+// fragment reads of 16 consecutive rows on distinct banks.  A fragment is 16 bytes per lane:
+// row lane & 15, samples 8 (lane >> 4) .. +7 of the step (the Gram product only needs the
+// row and column operands to use the same sample order).  Per step a wave issues 192 MFMAs.
 constexpr int RQ_T = 128;
 constexpr int RQ_W = 64;
+constexpr int RQ_K = 32;          // samples per step
+constexpr int RQ_LD = 40;         // padded LDS row (BF16 elements)
+constexpr int RQ_BUF = 4 * RQ_T * RQ_LD;   // one staged matrix (40 KB)
 __global__ __launch_bounds__(256) void k_sbuild_rbm_bf16(Dev a) {
+    __shared__ uint16_t sbuf[2][2][RQ_BUF];    // [step parity][row / column operand], 160 KB
     const int t = blockIdx.y, tile = blockIdx.x;
     int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
     while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
     while (bi * (bi + 1) / 2 > tile) --bi;
     const int bj = tile - bi * (bi + 1) / 2;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int wr = w >> 1, wc = w & 1;
-    if (bi == bj && wr < wc) return;            // strictly upper sub-tile of a diagonal tile
-    const int r0 = bi * RQ_T + wr * RQ_W, c0 = bj * RQ_T + wc * RQ_W;
     const int m = a.m;
-    if (r0 >= m || c0 >= m) return;
+    const int r0 = bi * RQ_T + wr * RQ_W, c0 = bj * RQ_T + wc * RQ_W;
+    // strictly upper sub-tiles of diagonal tiles and padding rows do no MFMAs, but their
+    // waves still stage operands and meet every barrier
+    const bool active = !(bi == bj && wr < wc) && r0 < m && c0 < m;
     const int rr = lane & 15, kg = lane >> 4;
     const size_t ns = (size_t)a.ns, plane = (size_t)a.mp * ns;
     const uint16_t *Pt = a.rbmP + (size_t)t * 4 * plane;
-    const uint16_t *rowp = Pt + (size_t)(r0 + rr) * ns + 8 * kg;
-    const uint16_t *colp = Pt + (size_t)(c0 + rr) * ns + 8 * kg;
+    // staging: piece e = tid + 256 i (i < 8) of a matrix is plane e / 512, row (e / 4) % 128,
+    // samples 8 (e % 4) .. +7
+    const uint16_t *gA[8], *gB[8];
+    int lofs[8];
+    for (int i = 0; i < 8; ++i) {
+        const int e = tid + 256 * i, q = e >> 9, row = (e >> 2) & 127, part = e & 3;
+        gA[i] = Pt + q * plane + (size_t)(bi * RQ_T + row) * ns + 8 * part;
+        gB[i] = Pt + q * plane + (size_t)(bj * RQ_T + row) * ns + 8 * part;
+        lofs[i] = (q * RQ_T + row) * RQ_LD + 8 * part;
+    }
+    bf16x8_t pa[8], pb[8];
+    for (int i = 0; i < 8; ++i) {
+        pa[i] = *(const bf16x8_t *)gA[i];
+        pb[i] = *(const bf16x8_t *)gB[i];
+    }
     f32x4_t sre[4][4], sim[4][4];
     for (int u = 0; u < 4; ++u)
         for (int v = 0; v < 4; ++v) {
             sre[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
             sim[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         }
-    // operands of step k0 + 32 are loaded while step k0 is multiplied (one wave per SIMD,
-    // so the load latency is hidden by the wave's own MFMAs)
-    bf16x8_t A[4][4], B[4][4], An[4][4], Bn[4][4];
-    for (int u = 0; u < 4; ++u)
-        for (int q = 0; q < 4; ++q) {
-            An[u][q] = *(const bf16x8_t *)(rowp + (size_t)u * 16 * ns + q * plane);
-            Bn[u][q] = *(const bf16x8_t *)(colp + (size_t)u * 16 * ns + q * plane);
+    const int arow = wr * RQ_W + rr, brow = wc * RQ_W + rr;
+    // double-buffered staging: step k is read from buffer k & 1 while step k + 1 is written to
+    // the other one (last read in step k - 1, before the barrier that ends it) and step k + 2
+    // is loaded into registers; one barrier per step
+    for (int i = 0; i < 8; ++i) {
+        *(bf16x8_t *)(sbuf[0][0] + lofs[i]) = pa[i];
+        *(bf16x8_t *)(sbuf[0][1] + lofs[i]) = pb[i];
+    }
+    if (RQ_K < ns)
+        for (int i = 0; i < 8; ++i) {
+            pa[i] = *(const bf16x8_t *)(gA[i] + RQ_K);
+            pb[i] = *(const bf16x8_t *)(gB[i] + RQ_K);
         }
-    for (size_t k0 = 0; k0 < ns; k0 += 32) {
-        for (int u = 0; u < 4; ++u)
-            for (int q = 0; q < 4; ++q) {
-                A[u][q] = An[u][q];
-                B[u][q] = Bn[u][q];
-            }
-        if (k0 + 32 < ns)
+    __syncthreads();
+    int buf = 0;
+    for (size_t k0 = 0; k0 < ns; k0 += RQ_K, buf ^= 1) {
+        const uint16_t *sA = sbuf[buf][0], *sB = sbuf[buf][1];
+        bf16x8_t A[4][4], B[4][4];
+        if (active)
             for (int u = 0; u < 4; ++u)
                 for (int q = 0; q < 4; ++q) {
-                    An[u][q] = *(const bf16x8_t *)(rowp + (size_t)u * 16 * ns + q * plane + k0 + 32);
-                    Bn[u][q] = *(const bf16x8_t *)(colp + (size_t)u * 16 * ns + q * plane + k0 + 32);
+                    A[u][q] = *(const bf16x8_t *)(sA + (q * RQ_T + arow + 16 * u) * RQ_LD + 8 * kg);
+                    B[u][q] = *(const bf16x8_t *)(sB + (q * RQ_T + brow + 16 * u) * RQ_LD + 8 * kg);
                 }
-        for (int u = 0; u < 4; ++u) {
-            const bf16x8_t nih = neg_bf16x8(A[u][2]), nil = neg_bf16x8(A[u][3]);
-            for (int v = 0; v < 4; ++v) {
-                f32x4_t x = sre[u][v];
-                x = MFMA_BF16(A[u][0], B[v][0], x);
-                x = MFMA_BF16(A[u][0], B[v][1], x);
-                x = MFMA_BF16(A[u][1], B[v][0], x);
-                x = MFMA_BF16(A[u][2], B[v][2], x);
-                x = MFMA_BF16(A[u][2], B[v][3], x);
-                x = MFMA_BF16(A[u][3], B[v][2], x);
-                sre[u][v] = x;
-                f32x4_t y = sim[u][v];
-                y = MFMA_BF16(A[u][0], B[v][2], y);
-                y = MFMA_BF16(A[u][0], B[v][3], y);
-                y = MFMA_BF16(A[u][1], B[v][2], y);
-                y = MFMA_BF16(nih, B[v][0], y);
-                y = MFMA_BF16(nih, B[v][1], y);
-                y = MFMA_BF16(nil, B[v][0], y);
-                sim[u][v] = y;
+        if (k0 + RQ_K < ns) {
+            for (int i = 0; i < 8; ++i) {
+                *(bf16x8_t *)(sbuf[buf ^ 1][0] + lofs[i]) = pa[i];
+                *(bf16x8_t *)(sbuf[buf ^ 1][1] + lofs[i]) = pb[i];
             }
+            if (k0 + 2 * RQ_K < ns)
+                for (int i = 0; i < 8; ++i) {
+                    pa[i] = *(const bf16x8_t *)(gA[i] + k0 + 2 * RQ_K);
+                    pb[i] = *(const bf16x8_t *)(gB[i] + k0 + 2 * RQ_K);
+                }
         }
+        if (!active) {
+            __syncthreads();
+            continue;
+        }
+        for (int u = 0; u < 4; ++u)
+            for (int q = 0; q < 4; ++q) {
+                A[u][q] = *(const bf16x8_t *)(sA + (q * RQ_T + arow + 16 * u) * RQ_LD + 8 * kg);
+                B[u][q] = *(const bf16x8_t *)(sB + (q * RQ_T + brow + 16 * u) * RQ_LD + 8 * kg);
+            }
+        // term-major order: 16 independent accumulators between two MFMAs on the same one
+        //   Re += Ar.Br + Ai.Bi  (hi hi, hi lo, lo hi),  Im += Ar.Bi - Ai.Br
+        bf16x8_t NI[4][2];
+        for (int u = 0; u < 4; ++u) {
+            NI[u][0] = neg_bf16x8(A[u][2]);
+            NI[u][1] = neg_bf16x8(A[u][3]);
+        }
+#define RQ_TERM(ACC, AX, BX)                                                  \
+        for (int u = 0; u < 4; ++u)                                           \
+            for (int v = 0; v < 4; ++v) ACC[u][v] = MFMA_BF16(AX, BX, ACC[u][v]);
+        RQ_TERM(sre, A[u][0], B[v][0])
+        RQ_TERM(sim, A[u][0], B[v][2])
+        RQ_TERM(sre, A[u][0], B[v][1])
+        RQ_TERM(sim, A[u][0], B[v][3])
+        RQ_TERM(sre, A[u][1], B[v][0])
+        RQ_TERM(sim, A[u][1], B[v][2])
+        RQ_TERM(sre, A[u][2], B[v][2])
+        RQ_TERM(sim, NI[u][0], B[v][0])
+        RQ_TERM(sre, A[u][2], B[v][3])
+        RQ_TERM(sim, NI[u][0], B[v][1])
+        RQ_TERM(sre, A[u][3], B[v][2])
+        RQ_TERM(sim, NI[u][1], B[v][0])
+#undef RQ_TERM
+        __syncthreads();
     }
+    if (!active) return;
     const double inv = 1.0 / (double)a.ns;
     double2 *S = (double2 *)a.S + (size_t)t * m * m;
     for (int u = 0; u < 4; ++u)
