@@ -57,20 +57,23 @@ __device__ __forceinline__ bf16x8_t neg_bf16x8(bf16x8_t v) {
 
 #define MFMA_BF16(A, B, C) __builtin_amdgcn_mfma_f32_16x16x32_bf16((A), (B), (C), 0, 0, 0)
 
-// One workgroup (4 waves) per 128x128 complex tile of the lower triangle; wave (wr, wc) takes
-// the 64x64 sub-tile, 4x4 blocks of 16x16 (128 FP32 accumulators).  Per step of 32 samples
-// the workgroup stages the tile's row and column operands (4 planes x 128 rows x 32 samples
-// each, 64 KB) through LDS, loaded one step ahead into registers, so every fragment crosses
-// the L2 once per workgroup; rows are padded to 40 BF16 (80 B), which keeps the 16-byte
-// fragment reads of 16 consecutive rows on distinct banks.  A fragment is 16 bytes per lane:
-// row lane & 15, samples 8 (lane >> 4) .. +7 of the step (the Gram product only needs the
-// row and column operands to use the same sample order).  Per step a wave issues 192 MFMAs.
+// One workgroup (8 waves) per 128x128 complex tile of the lower triangle; wave (wr, wc) =
+// (w >> 2, w & 3) takes rows 64 wr .. +63 and columns 32 wc .. +31 of the tile, 4x2 blocks of
+// 16x16 (64 FP32 accumulators), which keeps a wave under 256 registers so that two waves
+// share each SIMD and hide each other's LDS and MFMA latencies.  Per step of 32 samples the
+// workgroup stages the tile's row and column operands (4 planes x 128 rows x 32 samples each,
+// 64 KB) through double-buffered LDS: step k is read from one buffer while step k + 1 is
+// written to the other and step k + 2 is loaded into registers, one barrier per step.  Rows
+// are padded to 40 BF16 (80 B), which keeps the 16-byte fragment reads of 16 consecutive rows
+// on distinct banks.  A fragment is 16 bytes per lane: row lane & 15, samples 8 (lane >> 4)
+// .. +7 of the step (the Gram product only needs the row and column operands to use the same
+// sample order).
 constexpr int RQ_T = 128;
-constexpr int RQ_W = 64;
 constexpr int RQ_K = 32;          // samples per step
 constexpr int RQ_LD = 40;         // padded LDS row (BF16 elements)
 constexpr int RQ_BUF = 4 * RQ_T * RQ_LD;   // one staged matrix (40 KB)
-__global__ __launch_bounds__(256) void k_sbuild_rbm_bf16(Dev a) {
+constexpr int RQ_THREADS = 512;
+__global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
     __shared__ uint16_t sbuf[2][2][RQ_BUF];    // [step parity][row / column operand], 160 KB
     const int t = blockIdx.y, tile = blockIdx.x;
     int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
@@ -78,46 +81,43 @@ __global__ __launch_bounds__(256) void k_sbuild_rbm_bf16(Dev a) {
     while (bi * (bi + 1) / 2 > tile) --bi;
     const int bj = tile - bi * (bi + 1) / 2;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const int wr = w >> 1, wc = w & 1;
+    const int wr = w >> 2, wc = w & 3;
     const int m = a.m;
-    const int r0 = bi * RQ_T + wr * RQ_W, c0 = bj * RQ_T + wc * RQ_W;
-    // strictly upper sub-tiles of diagonal tiles and padding rows do no MFMAs, but their
-    // waves still stage operands and meet every barrier
-    const bool active = !(bi == bj && wr < wc) && r0 < m && c0 < m;
+    const int r0 = bi * RQ_T + wr * 64, c0 = bj * RQ_T + wc * 32;
+    // sub-tiles strictly above the diagonal of a diagonal tile and padding rows do no MFMAs,
+    // but their waves still stage operands and meet every barrier
+    const bool active = !(bi == bj && c0 > r0 + 63) && r0 < m && c0 < m;
     const int rr = lane & 15, kg = lane >> 4;
     const size_t ns = (size_t)a.ns, plane = (size_t)a.mp * ns;
     const uint16_t *Pt = a.rbmP + (size_t)t * 4 * plane;
-    // staging: piece e = tid + 256 i (i < 8) of a matrix is plane e / 512, row (e / 4) % 128,
+    // staging: piece e = tid + 512 i (i < 4) of a matrix is plane e / 512, row (e / 4) % 128,
     // samples 8 (e % 4) .. +7
-    const uint16_t *gA[8], *gB[8];
-    int lofs[8];
-    for (int i = 0; i < 8; ++i) {
-        const int e = tid + 256 * i, q = e >> 9, row = (e >> 2) & 127, part = e & 3;
+    const uint16_t *gA[4], *gB[4];
+    int lofs[4];
+    for (int i = 0; i < 4; ++i) {
+        const int e = tid + RQ_THREADS * i, q = e >> 9, row = (e >> 2) & 127, part = e & 3;
         gA[i] = Pt + q * plane + (size_t)(bi * RQ_T + row) * ns + 8 * part;
         gB[i] = Pt + q * plane + (size_t)(bj * RQ_T + row) * ns + 8 * part;
         lofs[i] = (q * RQ_T + row) * RQ_LD + 8 * part;
     }
-    bf16x8_t pa[8], pb[8];
-    for (int i = 0; i < 8; ++i) {
+    bf16x8_t pa[4], pb[4];
+    for (int i = 0; i < 4; ++i) {
         pa[i] = *(const bf16x8_t *)gA[i];
         pb[i] = *(const bf16x8_t *)gB[i];
     }
-    f32x4_t sre[4][4], sim[4][4];
+    f32x4_t sre[4][2], sim[4][2];
     for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < 2; ++v) {
             sre[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
             sim[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         }
-    const int arow = wr * RQ_W + rr, brow = wc * RQ_W + rr;
-    // double-buffered staging: step k is read from buffer k & 1 while step k + 1 is written to
-    // the other one (last read in step k - 1, before the barrier that ends it) and step k + 2
-    // is loaded into registers; one barrier per step
-    for (int i = 0; i < 8; ++i) {
+    const int arow = wr * 64 + rr, brow = wc * 32 + rr;
+    for (int i = 0; i < 4; ++i) {
         *(bf16x8_t *)(sbuf[0][0] + lofs[i]) = pa[i];
         *(bf16x8_t *)(sbuf[0][1] + lofs[i]) = pb[i];
     }
     if (RQ_K < ns)
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < 4; ++i) {
             pa[i] = *(const bf16x8_t *)(gA[i] + RQ_K);
             pb[i] = *(const bf16x8_t *)(gB[i] + RQ_K);
         }
@@ -125,63 +125,58 @@ __global__ __launch_bounds__(256) void k_sbuild_rbm_bf16(Dev a) {
     int buf = 0;
     for (size_t k0 = 0; k0 < ns; k0 += RQ_K, buf ^= 1) {
         const uint16_t *sA = sbuf[buf][0], *sB = sbuf[buf][1];
-        bf16x8_t A[4][4], B[4][4];
-        if (active)
+        bf16x8_t A[4][4], B[2][4];
+        if (active) {
             for (int u = 0; u < 4; ++u)
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 4; ++q)
                     A[u][q] = *(const bf16x8_t *)(sA + (q * RQ_T + arow + 16 * u) * RQ_LD + 8 * kg);
-                    B[u][q] = *(const bf16x8_t *)(sB + (q * RQ_T + brow + 16 * u) * RQ_LD + 8 * kg);
-                }
+            for (int v = 0; v < 2; ++v)
+                for (int q = 0; q < 4; ++q)
+                    B[v][q] = *(const bf16x8_t *)(sB + (q * RQ_T + brow + 16 * v) * RQ_LD + 8 * kg);
+        }
         if (k0 + RQ_K < ns) {
-            for (int i = 0; i < 8; ++i) {
+            for (int i = 0; i < 4; ++i) {
                 *(bf16x8_t *)(sbuf[buf ^ 1][0] + lofs[i]) = pa[i];
                 *(bf16x8_t *)(sbuf[buf ^ 1][1] + lofs[i]) = pb[i];
             }
             if (k0 + 2 * RQ_K < ns)
-                for (int i = 0; i < 8; ++i) {
+                for (int i = 0; i < 4; ++i) {
                     pa[i] = *(const bf16x8_t *)(gA[i] + k0 + 2 * RQ_K);
                     pb[i] = *(const bf16x8_t *)(gB[i] + k0 + 2 * RQ_K);
                 }
         }
-        if (!active) {
-            __syncthreads();
-            continue;
-        }
-        for (int u = 0; u < 4; ++u)
-            for (int q = 0; q < 4; ++q) {
-                A[u][q] = *(const bf16x8_t *)(sA + (q * RQ_T + arow + 16 * u) * RQ_LD + 8 * kg);
-                B[u][q] = *(const bf16x8_t *)(sB + (q * RQ_T + brow + 16 * u) * RQ_LD + 8 * kg);
+        if (active) {
+            // term-major order: 8 independent accumulators between two MFMAs on the same one
+            //   Re += Ar.Br + Ai.Bi  (hi hi, hi lo, lo hi),  Im += Ar.Bi - Ai.Br
+            bf16x8_t NI[4][2];
+            for (int u = 0; u < 4; ++u) {
+                NI[u][0] = neg_bf16x8(A[u][2]);
+                NI[u][1] = neg_bf16x8(A[u][3]);
             }
-        // term-major order: 16 independent accumulators between two MFMAs on the same one
-        //   Re += Ar.Br + Ai.Bi  (hi hi, hi lo, lo hi),  Im += Ar.Bi - Ai.Br
-        bf16x8_t NI[4][2];
-        for (int u = 0; u < 4; ++u) {
-            NI[u][0] = neg_bf16x8(A[u][2]);
-            NI[u][1] = neg_bf16x8(A[u][3]);
-        }
 #define RQ_TERM(ACC, AX, BX)                                                  \
-        for (int u = 0; u < 4; ++u)                                           \
-            for (int v = 0; v < 4; ++v) ACC[u][v] = MFMA_BF16(AX, BX, ACC[u][v]);
-        RQ_TERM(sre, A[u][0], B[v][0])
-        RQ_TERM(sim, A[u][0], B[v][2])
-        RQ_TERM(sre, A[u][0], B[v][1])
-        RQ_TERM(sim, A[u][0], B[v][3])
-        RQ_TERM(sre, A[u][1], B[v][0])
-        RQ_TERM(sim, A[u][1], B[v][2])
-        RQ_TERM(sre, A[u][2], B[v][2])
-        RQ_TERM(sim, NI[u][0], B[v][0])
-        RQ_TERM(sre, A[u][2], B[v][3])
-        RQ_TERM(sim, NI[u][0], B[v][1])
-        RQ_TERM(sre, A[u][3], B[v][2])
-        RQ_TERM(sim, NI[u][1], B[v][0])
+            for (int u = 0; u < 4; ++u)                                       \
+                for (int v = 0; v < 2; ++v) ACC[u][v] = MFMA_BF16(AX, BX, ACC[u][v]);
+            RQ_TERM(sre, A[u][0], B[v][0])
+            RQ_TERM(sim, A[u][0], B[v][2])
+            RQ_TERM(sre, A[u][0], B[v][1])
+            RQ_TERM(sim, A[u][0], B[v][3])
+            RQ_TERM(sre, A[u][1], B[v][0])
+            RQ_TERM(sim, A[u][1], B[v][2])
+            RQ_TERM(sre, A[u][2], B[v][2])
+            RQ_TERM(sim, NI[u][0], B[v][0])
+            RQ_TERM(sre, A[u][2], B[v][3])
+            RQ_TERM(sim, NI[u][0], B[v][1])
+            RQ_TERM(sre, A[u][3], B[v][2])
+            RQ_TERM(sim, NI[u][1], B[v][0])
 #undef RQ_TERM
+        }
         __syncthreads();
     }
     if (!active) return;
     const double inv = 1.0 / (double)a.ns;
     double2 *S = (double2 *)a.S + (size_t)t * m * m;
     for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < 2; ++v)
             for (int e = 0; e < 4; ++e) {
                 const int k = r0 + u * 16 + 4 * kg + e, l = c0 + v * 16 + rr;   // D[4 (lane >> 4) + e][lane & 15]
                 if (k >= m || l >= m || l > k) continue;

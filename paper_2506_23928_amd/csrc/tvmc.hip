@@ -390,7 +390,7 @@ tvmc_status run_estimate(tvmc_ctx *c) {
             }
             Scope sc(c, "sbuild");
             const int nt = d.mp / RQ_T;
-            hipLaunchKernelGGL(k_sbuild_rbm_bf16, dim3(nt * (nt + 1) / 2, T), dim3(256), 0, c->stream, d);
+            hipLaunchKernelGGL(k_sbuild_rbm_bf16, dim3(nt * (nt + 1) / 2, T), dim3(RQ_THREADS), 0, c->stream, d);
             LAUNCHCHECK(c, "k_sbuild_rbm_bf16");
         } else {
             Scope sc(c, "sbuild");
