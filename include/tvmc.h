@@ -95,7 +95,7 @@ typedef struct {
      * on the trajectory's own samples, proposes one independent Metropolis-Hastings move at the
      * start of every sweep; single-spin flips remain the fallback */
     int32_t proposal;             /* TVMC_PROPOSAL_* */
-    int32_t ar_hidden;            /* hidden units of the network, 1..256 */
+    int32_t ar_hidden;            /* hidden units of the network, 1..256, ar_hidden * N <= 8192 */
     int32_t ar_train_every;       /* train at steps that are multiples of this (0: only on request) */
     int32_t ar_train_iters;       /* Adam steps per training */
     double ar_lr;                 /* Adam learning rate */

@@ -108,7 +108,7 @@ struct Dev {
     int ar, ah;
     size_t arnp;
     float *arP, *arG, *arM, *arV;     // [T][arnp] master parameters, gradient, Adam moments
-    uint16_t *arW1Tb, *arW2b, *arW2Tb;  // [T][N][H], [T][N][H], [T][H][N] BF16 inference copies
+    uint16_t *arW1Tb, *arW2Tb;       // [T][N][H], [T][H][N] BF16 inference copies (transposed)
     float *arh, *arda;                // [T][Ns][H] training activations
     float *arg;                       // [T][Ns][N]
     float *arlogq;                    // [T][Ns]

@@ -33,43 +33,43 @@ __device__ __forceinline__ ArView ar_view(float *base, int n, int h) {
 }
 __host__ __device__ inline size_t ar_params(int n, int h) { return (size_t)2 * n * h + n + h; }
 
-// refresh the BF16 inference copies of trajectory t: W1T [N][H] (W1 transposed), W2 [N][H]
-// (row i = the weights of output i) and W2T [H][N]; element (k, j) of W1 is W1T[j H + k]
+// refresh the BF16 inference copies of trajectory t: W1T [N][H] (W1 transposed) and W2T [H][N]
+// (W2 transposed); element (k, j) of W1 is W1T[j H + k], element (i, k) of W2 is W2T[k N + i]
 __device__ __forceinline__ void ar_copy_one(const Dev &a, int t, size_t e) {
     const int n = a.n, h = a.ah;
     ArView p = ar_view(a.arP + (size_t)t * a.arnp, n, h);
     if (e < (size_t)h * n) {
         const int k = (int)(e / n), j = (int)(e % n);
         const size_t base = (size_t)t * h * n;
-        a.arW1Tb[base + (size_t)j * h + k] = f2bf(p.W1[e]);
-        a.arW2b[base + (size_t)j * h + k] = f2bf(p.W2[(size_t)j * h + k]);
-        a.arW2Tb[base + (size_t)k * n + j] = f2bf(p.W2[(size_t)j * h + k]);
+        // masked entries are written as exact zeros: the sampler's walk relies on them
+        const int dk = ar_degree(k, n);
+        a.arW1Tb[base + (size_t)j * h + k] = j < dk ? f2bf(p.W1[e]) : (uint16_t)0;
+        a.arW2Tb[base + (size_t)k * n + j] = dk <= j ? f2bf(p.W2[(size_t)j * h + k]) : (uint16_t)0;
     }
 }
 
-// Weights an independent proposal reads, in the [site][hidden unit] layout (consecutive lanes
-// read consecutive hidden units): from LDS when they fit there, else from global memory.
-constexpr int AR_LDS_W = 8192;    // H N entries per matrix staged in LDS (H <= 128 at N = 64)
+// BF16 weights the sampler reads, staged in LDS per workgroup (all its chains belong to one
+// trajectory): W1T (element (k, j) of W1 at [j H + k]: consecutive lanes read consecutive
+// hidden units) and W2T (element (i, k) of W2 at [k N + i]: consecutive lanes read
+// consecutive outputs).  H N <= AR_LDS_W is checked at initialisation.
+constexpr int AR_LDS_W = 8192;    // H N entries per matrix (H <= 128 at N = 64)
 struct ArNet {
-    const uint16_t *W1T, *W2;      // element (k, i) at [i H + k]
+    const uint16_t *W1T, *W2T;
     const float *b1, *b2;
 };
-// Stage trajectory t's draw weights into LDS (whole workgroup; a barrier must follow).
-__device__ __forceinline__ ArNet ar_net(const Dev &a, int t, uint16_t *sW1T, uint16_t *sW2, float *sb1, float *sb2) {
+// Stage trajectory t's weights into LDS (whole workgroup; a barrier must follow).
+__device__ __forceinline__ ArNet ar_net(const Dev &a, int t, uint16_t *sW1T, uint16_t *sW2T, float *sb1, float *sb2) {
     const int n = a.n, h = a.ah;
     const size_t base = (size_t)t * h * n;
     const float *b1 = a.arP + (size_t)t * a.arnp + (size_t)h * n;
     const float *b2 = b1 + h + (size_t)n * h;
     for (int i = threadIdx.x; i < h; i += blockDim.x) sb1[i] = b1[i];
     for (int i = threadIdx.x; i < n; i += blockDim.x) sb2[i] = b2[i];
-    if (h * n <= AR_LDS_W) {
-        for (int e = threadIdx.x; e < h * n; e += blockDim.x) {
-            sW1T[e] = a.arW1Tb[base + e];
-            sW2[e] = a.arW2b[base + e];
-        }
-        return ArNet{sW1T, sW2, sb1, sb2};
+    for (int e = threadIdx.x; e < h * n; e += blockDim.x) {
+        sW1T[e] = a.arW1Tb[base + e];
+        sW2T[e] = a.arW2Tb[base + e];
     }
-    return ArNet{a.arW1Tb + base, a.arW2b + base, sb1, sb2};
+    return ArNet{sW1T, sW2T, sb1, sb2};
 }
 
 // deterministic initialisation: W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) on unmasked entries,
@@ -247,27 +247,62 @@ __device__ __forceinline__ float wave_sum_f(float v) {
     return v;
 }
 
+// The autoregressive walk over sites 0..N-1 that both draws s' ~ q and evaluates log q(s),
+// so that the two use bitwise the same q.  Lane k (and k + 64, ...) holds the pre-activation
+// a_k of hidden unit k; lane i holds the logit l_i of site i.  Hidden unit k has inputs j <
+// d(k) and outputs i >= d(k), so it is complete once site d(k) - 1 is known: at site ii the
+// units of degree ii (k = ii - 1 + c (N - 1)) add W2[i][k] relu(a_k) to the logits (the
+// masked weights W2[i][k], i < d(k), are exactly zero), site ii is decided from l_ii, and
+// every unit adds W1[k][ii] s_ii (zero for the units with d(k) <= ii).  No cross-lane
+// reductions: only scalar reads of one lane.  draw: s_ii = +1 iff logit(u_ii) < l_ii, i.e.
+// u_ii < sigmoid(l_ii), with u_ii the site uniform of lane ii; otherwise s_ii is read from mk.
+// Inlined into the samplers, so the weight reads compile to LDS instructions.  Returns the
+// configuration and log q of it (all lanes).
+// value of lane l (uniform l): a scalar read instead of a cross-lane permute
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+struct ArWalk {
+    uint64_t cfg;
+    float lq;
+};
+__device__ __forceinline__ ArWalk ar_walk(int n, int h, const uint16_t *W1T, const uint16_t *W2T, const float *b1,
+                                          const float *b2, uint64_t mk, float usite, int lane, int draw) {
+    const int nm1 = n > 1 ? n - 1 : 1, nq = (h + 63) >> 6;
+    float ak[4];
+    for (int q = 0; q < 4; ++q) ak[q] = (lane + 64 * q < h) ? b1[lane + 64 * q] : 0.f;
+    const int li = lane < n ? lane : n - 1;          // W2T column this lane reads
+    float logit = lane < n ? b2[lane] : 0.f;
+    // logit of the site uniform, so that a site is decided without a transcendental
+    const float ulog = draw ? logf(usite) - log1pf(-usite) : 0.f;
+    float arg = 0.f;                                 // lane i: s_i l_i
+    uint64_t out = 0ull;
+    for (int ii = 0; ii < n; ++ii) {
+        if (ii >= 1)
+            for (int k = ii - 1; k < h; k += nm1) {
+                const int q = k >> 6;
+                const float av = q == 0 ? ak[0] : q == 1 ? ak[1] : q == 2 ? ak[2] : ak[3];
+                const float hk = fmaxf(readlane_f(av, k & 63), 0.f);
+                logit += bf2f(W2T[(size_t)k * n + li]) * hk;
+            }
+        const float l = readlane_f(logit, ii);
+        const bool up = draw ? (readlane_f(ulog, ii) < l) : (bool)((mk >> ii) & 1ull);
+        const float sv = up ? 1.f : -1.f;
+        arg = lane == ii ? sv * l : arg;
+        if (up) out |= (1ull << ii);
+        for (int q = 0; q < nq; ++q) {
+            const int k = lane + 64 * q;
+            ak[q] += (k < h ? bf2f(W1T[(size_t)ii * h + k]) : 0.f) * sv;
+        }
+    }
+    const float mylq = lane < n ? log_sigmoid_f(arg) : 0.f;
+    return ArWalk{out, wave_sum_f(mylq)};
+}
+
 // log q(s) of the BF16 network for configuration mk (every lane returns the same value).
-// hs: this wave's LDS scratch of H floats.
-__device__ float ar_logq(const Dev &a, int t, uint64_t mk, int lane, float *hs) {
-    const int n = a.n, h = a.ah;
-    const float *b1 = a.arP + (size_t)t * a.arnp + (size_t)h * n;
-    const float *b2 = b1 + h + (size_t)n * h;
-    const uint16_t *W1T = a.arW1Tb + (size_t)t * h * n, *W2T = a.arW2Tb + (size_t)t * h * n;
-    for (int k = lane; k < h; k += 64) {
-        float x = b1[k];
-        const int dk = ar_degree(k, n);
-        for (int j = 0; j < dk; ++j) x += bf2f(W1T[(size_t)j * h + k]) * (float)spin(mk, j);
-        hs[k] = fmaxf(x, 0.f);
-    }
-    float lq = 0.f;
-    if (lane < n) {
-        float l = b2[lane];
-        for (int k = 0; k < h; ++k)
-            if (ar_degree(k, n) <= lane) l += bf2f(W2T[(size_t)k * n + lane]) * hs[k];
-        lq = log_sigmoid_f((float)spin(mk, lane) * l);
-    }
-    return wave_sum_f(lq);
+__device__ __forceinline__ float ar_logq(const Dev &a, const ArNet &net, uint64_t mk, int lane) {
+    return ar_walk(a.n, a.ah, net.W1T, net.W2T, net.b1, net.b2, mk, 0.f, lane, 0).lq;
 }
 
 // One independent proposal s' ~ q drawn autoregressively with the BF16 network (every lane
@@ -276,7 +311,6 @@ __device__ float ar_logq(const Dev &a, int t, uint64_t mk, int lane, float *hs) 
 // site (word lane & 3 of block lane >> 2), block 16 gives the 53-bit accept uniform.
 __device__ uint64_t ar_draw(const Dev &a, const ArNet &net, int t, uint32_t ctr1, int step, uint32_t idx, int lane,
                             float &lqn, double &uacc) {
-    const int n = a.n, h = a.ah;
     uint32_t rr[4] = {0u, 0u, 0u, 0u};
     if (lane < 17)
         philox4x32_10(idx * 17u + (uint32_t)lane, ctr1, (uint32_t)step, (6u << 24) | (uint32_t)(a.traj0 + t), a.key0,
@@ -288,32 +322,9 @@ __device__ uint64_t ar_draw(const Dev &a, const ArNet &net, int t, uint32_t ctr1
     }
     const float usite = ((float)(word >> 8) + 0.5f) * (1.0f / 16777216.0f);
     uacc = u53((uint32_t)__builtin_amdgcn_readlane((int)rr[0], 16), (uint32_t)__builtin_amdgcn_readlane((int)rr[1], 16));
-    const float *b2 = net.b2;
-    const uint16_t *W1T = net.W1T, *W2 = net.W2;
-    float ak[4];
-    for (int q = 0; q < 4; ++q) ak[q] = (lane + 64 * q < h) ? net.b1[lane + 64 * q] : 0.f;
-    uint64_t mnew = 0ull;
-    float lq = 0.f;
-    for (int ii = 0; ii < n; ++ii) {
-        float part = 0.f;
-        for (int q = 0; q < 4; ++q) {
-            const int k = lane + 64 * q;
-            if (k < h && ar_degree(k, n) <= ii) part += bf2f(W2[(size_t)ii * h + k]) * fmaxf(ak[q], 0.f);
-        }
-        const float l = b2[ii] + wave_sum_f(part);
-        const float pu = 1.f / (1.f + expf(-l));
-        const float ui = __shfl(usite, ii, 64);
-        const bool up = ui < pu;
-        const float sv = up ? 1.f : -1.f;
-        lq += log_sigmoid_f(sv * l);
-        if (up) mnew |= (1ull << ii);
-        for (int q = 0; q < 4; ++q) {
-            const int k = lane + 64 * q;
-            if (k < h && ar_degree(k, n) > ii) ak[q] += bf2f(W1T[(size_t)ii * h + k]) * sv;
-        }
-    }
-    lqn = lq;
-    return mnew;
+    const ArWalk r = ar_walk(a.n, a.ah, net.W1T, net.W2T, net.b1, net.b2, 0ull, usite, lane, 1);
+    lqn = r.lq;
+    return r.cfg;
 }
 
 }  // namespace tvmc

@@ -53,19 +53,20 @@ __global__ void k_prepare_rbm(Dev a, const double2 *__restrict__ src) {
     a.sT[((size_t)t * nh + j) * n + i] = make_double2(sh * cy, ch * sy);
 }
 
-template <int CPB, int QH, bool AR>
+// W_LDS: the weights fit in LDS (N N' <= 4096) and are read from there; a template flag, so
+// that every weight read compiles to an LDS or a global instruction rather than a generic one.
+template <int CPB, int QH, bool AR, bool W_LDS>
 __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int stage, int burn) {
-    __shared__ double lwr[64 * 64];
-    __shared__ double lwi[64 * 64];
+    __shared__ double lwr[W_LDS ? 64 * 64 : 1];
+    __shared__ double lwi[W_LDS ? 64 * 64 : 1];
     __shared__ double2 tl[CPB][64 * QH];
-    __shared__ float arh_s[AR ? CPB : 1][AR ? 256 : 1];
     __shared__ uint16_t arw_s[AR ? 2 * AR_LDS_W : 1];
     __shared__ float arb_s[AR ? 256 + 64 : 1];
     const int n = a.n, nh = a.nh;
     const int t = blockIdx.y;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * CPB + w;
-    const bool in_lds = n * nh <= 64 * 64;
+    const bool in_lds = W_LDS;
     const double *gwr = a.w_re + (size_t)t * n * nh, *gwi = a.w_im + (size_t)t * n * nh;
     if (in_lds) {
         for (int i = threadIdx.x; i < n * nh; i += blockDim.x) {
@@ -76,8 +77,8 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
     ArNet net{};
     if (AR) net = ar_net(a, t, arw_s, arw_s + AR_LDS_W, arb_s, arb_s + 256);
     __syncthreads();
-    const double *wr = in_lds ? lwr : gwr;
-    const double *wi = in_lds ? lwi : gwi;
+    const double *wr = W_LDS ? lwr : gwr;
+    const double *wi = W_LDS ? lwi : gwi;
     const double2 *th = a.theta_eval + (size_t)t * a.m;
     uint64_t mask = a.chains[(size_t)t * a.nc + c];
 
@@ -123,9 +124,8 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
         for (int jj = 0; jj < cnt; ++jj) {
             if (AR && base + jj == next_ar) {
                 next_ar += n;
-                float *hs = arh_s[AR ? w : 0];
                 if (!lq_valid) {
-                    lq_cur = ar_logq(a, t, mask, lane, hs);
+                    lq_cur = ar_logq(a, net, mask, lane);
                     lq_valid = true;
                 }
                 float lqn;

@@ -64,7 +64,6 @@ template <int CPB, bool AR>
 __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, int stage, int burn) {
     __shared__ double lre[64 * 64];
     __shared__ double lim[64 * 64];
-    __shared__ float arh_s[AR ? CPB : 1][AR ? 256 : 1];
     __shared__ uint16_t arw_s[AR ? 2 * AR_LDS_W : 1];
     __shared__ float arb_s[AR ? 256 + 64 : 1];
     const int n = a.n;
@@ -123,9 +122,8 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, in
         for (int j = 0; j < cnt; ++j) {
             if (AR && base + j == next_ar) {
                 next_ar += n;
-                float *hs = arh_s[AR ? w : 0];
                 if (!lq_valid) {
-                    lq_cur = ar_logq(a, t, mask, lane, hs);
+                    lq_cur = ar_logq(a, net, mask, lane);
                     lq_valid = true;
                 }
                 float lqn;

@@ -53,7 +53,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1Tb, arW2b, arW2Tb, arh, arda,
+        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
         arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, total;
 };
 
@@ -130,7 +130,6 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.arM = take(sizeof(float) * tt * np);
     L.arV = take(sizeof(float) * tt * np);
     L.arW1Tb = take(ar ? sizeof(uint16_t) * tt * ah * n : 0);
-    L.arW2b = take(ar ? sizeof(uint16_t) * tt * ah * n : 0);
     L.arW2Tb = take(ar ? sizeof(uint16_t) * tt * ah * n : 0);
     L.arh = take(ar ? sizeof(float) * tt * ns * ah : 0);
     L.arda = take(ar ? sizeof(float) * tt * ns * ah : 0);
@@ -197,7 +196,8 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
     if (c->proposal != TVMC_PROPOSAL_FLIP && c->proposal != TVMC_PROPOSAL_LEARNED)
         return snprintf(msg, len, "bad proposal"), TVMC_E_INVAL;
     if (c->proposal == TVMC_PROPOSAL_LEARNED) {
-        if (c->ar_hidden < 1 || c->ar_hidden > 256) return snprintf(msg, len, "ar_hidden must be in [1, 256]"), TVMC_E_INVAL;
+        if (c->ar_hidden < 1 || c->ar_hidden > 256 || c->ar_hidden * p->n_sites > AR_LDS_W)
+            return snprintf(msg, len, "ar_hidden must be in [1, 256] with ar_hidden * n_sites <= %d", AR_LDS_W), TVMC_E_INVAL;
         if (c->ar_train_every < 0 || c->ar_train_iters < 0 || !(c->ar_lr > 0.0))
             return snprintf(msg, len, "bad training settings"), TVMC_E_INVAL;
     }
@@ -293,18 +293,24 @@ tvmc_status run_sample(tvmc_ctx *c) {
         Scope sc(c, "sample");
         dim3 grid(d.nc / c->cpb, T);
         const int qh = (d.nh + 63) / 64;
-#define RBM_LAUNCH(CPB, QH, AR) hipLaunchKernelGGL((k_sample_rbm<CPB, QH, AR>), grid, dim3(64 * CPB), 0, c->stream, d, c->step, c->stage, burn)
-#define RBM_CPB(QH, AR)                         \
-    switch (c->cpb) {                           \
-    case 8: RBM_LAUNCH(8, QH, AR); break;       \
-    case 4: RBM_LAUNCH(4, QH, AR); break;       \
-    case 2: RBM_LAUNCH(2, QH, AR); break;       \
-    default: RBM_LAUNCH(1, QH, AR); break;      \
+#define RBM_LAUNCH(CPB, QH, AR, WL) hipLaunchKernelGGL((k_sample_rbm<CPB, QH, AR, WL>), grid, dim3(64 * CPB), 0, c->stream, d, c->step, c->stage, burn)
+#define RBM_CPB(QH, AR, WL)                         \
+    switch (c->cpb) {                               \
+    case 8: RBM_LAUNCH(8, QH, AR, WL); break;       \
+    case 4: RBM_LAUNCH(4, QH, AR, WL); break;       \
+    case 2: RBM_LAUNCH(2, QH, AR, WL); break;       \
+    default: RBM_LAUNCH(1, QH, AR, WL); break;      \
     }
+        // N' <= 64 always fits in LDS (N <= 64); wider layers fit when N N' <= 4096
+        const bool wl = d.n * d.nh <= 64 * 64;
         if (d.ar) {
-            if (qh == 1) { RBM_CPB(1, true) } else if (qh == 2) { RBM_CPB(2, true) } else { RBM_CPB(4, true) }
+            if (qh == 1) { RBM_CPB(1, true, true) }
+            else if (qh == 2) { if (wl) { RBM_CPB(2, true, true) } else { RBM_CPB(2, true, false) } }
+            else { if (wl) { RBM_CPB(4, true, true) } else { RBM_CPB(4, true, false) } }
         } else {
-            if (qh == 1) { RBM_CPB(1, false) } else if (qh == 2) { RBM_CPB(2, false) } else { RBM_CPB(4, false) }
+            if (qh == 1) { RBM_CPB(1, false, true) }
+            else if (qh == 2) { if (wl) { RBM_CPB(2, false, true) } else { RBM_CPB(2, false, false) } }
+            else { if (wl) { RBM_CPB(4, false, true) } else { RBM_CPB(4, false, false) } }
         }
 #undef RBM_CPB
 #undef RBM_LAUNCH
@@ -709,7 +715,6 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.arM = (float *)(base + L.arM);
     d.arV = (float *)(base + L.arV);
     d.arW1Tb = (uint16_t *)(base + L.arW1Tb);
-    d.arW2b = (uint16_t *)(base + L.arW2b);
     d.arW2Tb = (uint16_t *)(base + L.arW2Tb);
     d.arh = (float *)(base + L.arh);
     d.arda = (float *)(base + L.arda);
