@@ -213,16 +213,17 @@ def main():
     if dom == "solve":
         if kind == tv.RBM:   # complex Hermitian Cholesky (4/3 n^3 real flops) and two triangular solves
             flops = T * (4.0 * dim ** 3 / 3.0 + 16.0 * dim * dim)
-            kname = "k_zmw_* (complex solve)"
+            kname = "k_zmw_solve"     # k_zmw_init, k_zmw_update, k_zmw_diag, k_zmw_trsm, k_zmw_backward
         else:
             flops = T * (dim ** 3 / 3.0 + dim * dim / 2.0 + dim / 6.0 + 4.0 * dim * dim)
             multi = args.solver == "multi" or (args.solver != "one" and T < 192)
-            kname = "k_cmw_* (solve)" if multi else "k_chol_solve"
+            kname = "k_cmw_solve" if multi else "k_chol_solve"   # k_cmw_*: the several-workgroup launches
         if ss:               # push-back delta = A^H u: M x N_s complex multiply-adds
             flops += T * 8.0 * m * ns
         achieved = flops / (groups["solve"]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": kname, "bound": "mfma", "achieved": achieved, "peak": PEAKS["fp64"],
-                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic(kname.split()[0])}
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic(kname),
+                "note": "one evaluation's solve (every launch of the solver for all trajectories)"}
     elif dom == "sbuild" and ss and kind == tv.RBM:
         # K = (1 + q)(1 + g) - 1 with g = t t^H over N' hidden units: N_s^2 N' complex multiply-adds
         flops = T * 8.0 * ns * ns * nh
