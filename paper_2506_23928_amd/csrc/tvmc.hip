@@ -38,6 +38,11 @@ struct Timer {
 struct tvmc_ctx {
     Dev d{};
     hipStream_t stream = nullptr;
+    // two side streams (default priority) for the several-workgroup solves: each takes half
+    // of the trajectories, so one half's small diagonal and TRSM launches overlap the other
+    // half's panel updates; forked from and joined back into `stream` with events
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
     tvmc_config cfg{};
     int step = 0, stage = 0, phase = 0, nobs = 0, adam_t = 0;
     int cpb = 1;
@@ -434,6 +439,79 @@ tvmc_status run_estimate(tvmc_ctx *c) {
 
 // The FP64 Cholesky solve: one workgroup per trajectory, or several per trajectory when the
 // batch alone would leave most compute units idle.
+// The several-workgroup solve of trajectories [0, T) of the arguments on stream st: one launch
+// per panel step (update, diagonal block, TRSM), then the backward substitution.
+template <typename Args, bool CPLX>
+tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
+    if constexpr (CPLX) {
+        hipLaunchKernelGGL(k_zmw_init, dim3((x.m + 255) / 256, T), dim3(256), 0, st, x);
+    } else {
+        hipLaunchKernelGGL(k_cmw_init, dim3((x.m + 255) / 256, T), dim3(256), 0, st, x);
+    }
+    LAUNCHCHECK(c, "solver init");
+    for (int j0 = 0, p = 0; j0 < x.m; j0 += CN, ++p) {
+        if (j0 > 0) {
+            if constexpr (CPLX)
+                hipLaunchKernelGGL(k_zmw_update, dim3((x.m - j0 + CR - 1) / CR, T), dim3(256), 0, st, x, j0);
+            else
+                hipLaunchKernelGGL(k_cmw_update, dim3((x.m - j0 + CR - 1) / CR, T), dim3(256), 0, st, x, j0);
+            LAUNCHCHECK(c, "panel update");
+        }
+        if constexpr (CPLX)
+            hipLaunchKernelGGL(k_zmw_diag, dim3(T), dim3(256), 0, st, x, j0, p);
+        else
+            hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, st, x, j0, p);
+        LAUNCHCHECK(c, "diagonal block");
+        const int below = x.m - j0 - CN;
+        if (below > 0) {
+            if constexpr (CPLX)
+                hipLaunchKernelGGL(k_zmw_trsm, dim3((below + CR - 1) / CR, T), dim3(256), 0, st, x, j0, p);
+            else
+                hipLaunchKernelGGL(k_cmw_trsm, dim3((below + CR - 1) / CR, T), dim3(256), 0, st, x, j0, p);
+            LAUNCHCHECK(c, "panel TRSM");
+        }
+    }
+    if constexpr (CPLX)
+        hipLaunchKernelGGL(k_zmw_backward, dim3(T), dim3(256), 0, st, x);
+    else
+        hipLaunchKernelGGL(k_cmw_backward, dim3(T), dim3(256), 0, st, x);
+    LAUNCHCHECK(c, "backward substitution");
+    return TVMC_OK;
+}
+
+// Arguments of trajectories [t0, t0 + n) of a batch (every array is trajectory-major).
+CholArgs sub_args(const CholArgs &a, int t0) {
+    const size_t m = (size_t)a.m;
+    return CholArgs{a.A + (size_t)t0 * m * m, a.rhs + (size_t)t0 * m, a.x + (size_t)t0 * m,
+                    a.linv + (size_t)t0 * chol_panels(a.m) * CN * CN, a.flags + t0, a.m};
+}
+ZCholArgs sub_args(const ZCholArgs &a, int t0) {
+    const size_t m = (size_t)a.m;
+    return ZCholArgs{a.A + (size_t)t0 * m * m, a.rhs + (size_t)t0 * m, a.x + (size_t)t0 * m,
+                     a.linv + (size_t)t0 * chol_panels(a.m) * CN * CN, a.flags + t0, a.m};
+}
+
+// The two halves of the batch on the side streams, joined back into the context's stream.
+template <typename Args, bool CPLX>
+tvmc_status solve_split(tvmc_ctx *c, const Args &x) {
+    const int T = c->d.nt;
+    if (T < 2 || !c->side[0]) return solve_sequence<Args, CPLX>(c, x, T, c->stream);
+    HIPCHECK(c, hipEventRecord(c->fork, c->stream));
+    const int half = T / 2;
+    for (int g = 0; g < 2; ++g) {
+        HIPCHECK(c, hipStreamWaitEvent(c->side[g], c->fork, 0));
+        const int t0 = g ? half : 0, n = g ? T - half : half;
+        tvmc_status st = solve_sequence<Args, CPLX>(c, sub_args(x, t0), n, c->side[g]);
+        if (st != TVMC_OK) return st;
+        HIPCHECK(c, hipEventRecord(c->join[g], c->side[g]));
+    }
+    HIPCHECK(c, hipStreamWaitEvent(c->stream, c->join[0], 0));
+    HIPCHECK(c, hipStreamWaitEvent(c->stream, c->join[1], 0));
+    return TVMC_OK;
+}
+
+// The FP64 Cholesky solve: one workgroup per trajectory, or several per trajectory when the
+// batch alone would leave most compute units idle.
 tvmc_status launch_chol(tvmc_ctx *c, const CholArgs &ca) {
     const int T = c->d.nt;
     const bool multi = c->cfg.solver == TVMC_SOLVER_MULTI_GROUP ||
@@ -443,48 +521,11 @@ tvmc_status launch_chol(tvmc_ctx *c, const CholArgs &ca) {
         LAUNCHCHECK(c, "k_chol_solve");
         return TVMC_OK;
     }
-    hipLaunchKernelGGL(k_cmw_init, dim3((ca.m + 255) / 256, T), dim3(256), 0, c->stream, ca);
-    LAUNCHCHECK(c, "k_cmw_init");
-    for (int j0 = 0, p = 0; j0 < ca.m; j0 += CN, ++p) {
-        if (j0 > 0) {
-            hipLaunchKernelGGL(k_cmw_update, dim3((ca.m - j0 + CR - 1) / CR, T), dim3(256), 0, c->stream, ca, j0);
-            LAUNCHCHECK(c, "k_cmw_update");
-        }
-        hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, c->stream, ca, j0, p);
-        LAUNCHCHECK(c, "k_cmw_diag");
-        const int below = ca.m - j0 - CN;
-        if (below > 0) {
-            hipLaunchKernelGGL(k_cmw_trsm, dim3((below + CR - 1) / CR, T), dim3(256), 0, c->stream, ca, j0, p);
-            LAUNCHCHECK(c, "k_cmw_trsm");
-        }
-    }
-    hipLaunchKernelGGL(k_cmw_backward, dim3(T), dim3(256), 0, c->stream, ca);
-    LAUNCHCHECK(c, "k_cmw_backward");
-    return TVMC_OK;
+    return solve_split<CholArgs, false>(c, ca);
 }
 
 // The complex Hermitian solve (always several workgroups per trajectory).
-tvmc_status launch_zchol(tvmc_ctx *c, const ZCholArgs &za) {
-    const int T = c->d.nt;
-    hipLaunchKernelGGL(k_zmw_init, dim3((za.m + 255) / 256, T), dim3(256), 0, c->stream, za);
-    LAUNCHCHECK(c, "k_zmw_init");
-    for (int j0 = 0, p = 0; j0 < za.m; j0 += CN, ++p) {
-        if (j0 > 0) {
-            hipLaunchKernelGGL(k_zmw_update, dim3((za.m - j0 + CR - 1) / CR, T), dim3(256), 0, c->stream, za, j0);
-            LAUNCHCHECK(c, "k_zmw_update");
-        }
-        hipLaunchKernelGGL(k_zmw_diag, dim3(T), dim3(256), 0, c->stream, za, j0, p);
-        LAUNCHCHECK(c, "k_zmw_diag");
-        const int below = za.m - j0 - CN;
-        if (below > 0) {
-            hipLaunchKernelGGL(k_zmw_trsm, dim3((below + CR - 1) / CR, T), dim3(256), 0, c->stream, za, j0, p);
-            LAUNCHCHECK(c, "k_zmw_trsm");
-        }
-    }
-    hipLaunchKernelGGL(k_zmw_backward, dim3(T), dim3(256), 0, c->stream, za);
-    LAUNCHCHECK(c, "k_zmw_backward");
-    return TVMC_OK;
-}
+tvmc_status launch_zchol(tvmc_ctx *c, const ZCholArgs &za) { return solve_split<ZCholArgs, true>(c, za); }
 
 tvmc_status run_solve(tvmc_ctx *c) {
     Dev &d = c->d;
@@ -737,6 +778,11 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
             th[(size_t)t * m + k] = theta0 ? make_double2(theta0[2 * k], theta0[2 * k + 1]) : make_double2(0.0, 0.0);
     auto fail = [&](tvmc_status s) {
         snprintf(g_err, sizeof(g_err), "%s", ctx->err);
+        for (int g = 0; g < 2; ++g) {
+            if (ctx->side[g]) (void)hipStreamDestroy(ctx->side[g]);
+            if (ctx->join[g]) (void)hipEventDestroy(ctx->join[g]);
+        }
+        if (ctx->fork) (void)hipEventDestroy(ctx->fork);
         delete ctx;
         return s;
     };
@@ -773,6 +819,11 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
         hipLaunchKernelGGL(k_ar_copy, dim3((d.ah * n + 255) / 256, T), dim3(256), 0, ctx->stream, d);
         INITCHECK(hipGetLastError());
     }
+    for (int g = 0; g < 2; ++g) {
+        INITCHECK(hipStreamCreateWithFlags(&ctx->side[g], hipStreamNonBlocking));
+        INITCHECK(hipEventCreateWithFlags(&ctx->join[g], hipEventDisableTiming));
+    }
+    INITCHECK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
     INITCHECK(hipStreamSynchronize(ctx->stream));
 #undef INITCHECK
     *out = ctx;
@@ -983,6 +1034,14 @@ const char *tvmc_last_error(const tvmc_ctx *c) { return c ? c->err : g_err; }
 tvmc_status tvmc_destroy(tvmc_ctx *c) {
     if (!c) return TVMC_E_INVAL;
     (void)hipStreamSynchronize(c->stream);
+    for (int g = 0; g < 2; ++g) {
+        if (c->side[g]) {
+            (void)hipStreamSynchronize(c->side[g]);
+            (void)hipStreamDestroy(c->side[g]);
+        }
+        if (c->join[g]) (void)hipEventDestroy(c->join[g]);
+    }
+    if (c->fork) (void)hipEventDestroy(c->fork);
     for (auto &t : c->timers) {
         for (auto e : t.start) (void)hipEventDestroy(e);
         for (auto e : t.stop) (void)hipEventDestroy(e);
