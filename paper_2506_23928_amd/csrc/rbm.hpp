@@ -339,7 +339,130 @@ __global__ __launch_bounds__(256) void k_sbuild_rbm_f64(Dev a) {
     }
 }
 
-// Moments for the RBM: two-flip ratios psi(s^(ab))/psi(s) = exp(-2 s_a a_a - 2 s_b a_b)
+// Moments for the RBM, factored form (N N' <= 4096): with u = 2 s_a w_aj, v = 2 s_b w_bj and
+// f_j(a) = cosh u - t_j sinh u (t_j = tanh g_j), the two-flip factor is
+//   cosh(u + v) - t_j sinh(u + v) = f_j(a) f_j(b) + (1 - t_j^2) sinh u sinh v,
+// so psi(s^(ab))/psi(s) = R_a R_b prod_j (1 + beta_j(a) alpha_j(b)) with alpha_j(a) =
+// sinh u / f_j(a), beta_j(a) = (1 - t_j^2) alpha_j(a) and R_a the single-flip ratio.  A
+// workgroup takes one sample at a time: alpha and beta for all (j, a) in LDS, then every
+// unordered pair a < b (pairs spread over the 4 waves, a on the lanes) multiplies N' factors
+// 1 + beta alpha, rescaled by a power of two every 16 (exact).  The pair terms are symmetric except
+// s_b Im R_ab, which enters as (s_a + s_b) Im R_ab.
+constexpr int RMF_WAVES = 4;
+__global__ __launch_bounds__(64 * RMF_WAVES) void k_moments_rbm_f(Dev a) {
+    __shared__ double2 al[64 * 64], be[64 * 64];      // [j][a]
+    __shared__ double2 tl[64];
+    __shared__ double part[RMF_WAVES][9];
+    const int t = blockIdx.y;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int n = a.n, nh = a.nh;
+    const double N = (double)n;
+    double acc[9] = {};
+    const double2 *cT = a.cT + (size_t)t * nh * n, *sT = a.sT + (size_t)t * nh * n;
+    for (int s = blockIdx.x; s < a.ns; s += gridDim.x) {
+        const size_t sidx = (size_t)t * a.ns + s;
+        const uint64_t mk = a.samples[sidx];
+        __syncthreads();   // the previous sample's tables are no longer read
+        for (int j = tid; j < nh; j += blockDim.x) tl[j] = a.tt[sidx * nh + j];
+        __syncthreads();
+        for (int e = tid; e < n * nh; e += blockDim.x) {
+            const int j = e / n, i = e % n;
+            const double si = spin(mk, i);
+            const double2 ch = cT[e], sh = sT[e], tj = tl[j];
+            const double2 sh_s = make_double2(si * sh.x, si * sh.y);            // sinh u
+            const double2 ts = cmul(tj, sh_s);
+            const double2 f = make_double2(ch.x - ts.x, ch.y - ts.y);           // f_j(i)
+            const double fi = 1.0 / (f.x * f.x + f.y * f.y);
+            const double2 alpha = make_double2((sh_s.x * f.x + sh_s.y * f.y) * fi, (sh_s.y * f.x - sh_s.x * f.y) * fi);
+            const double2 t2 = cmul(tj, tj);
+            al[e] = alpha;
+            be[e] = cmul(make_double2(1.0 - t2.x, -t2.y), alpha);
+        }
+        __syncthreads();
+        const bool act = lane < n;
+        const double sa = spin(mk, lane);
+        const double2 Ra = act ? a.R[sidx * n + lane] : make_double2(0.0, 0.0);
+        double v[9] = {};
+        if (w == 0 && act) {
+            // single-flip terms and the pair sums that need only R_a
+            int up = 0;
+            for (int b = 0; b < n; ++b) up += (int)((mk >> b) & 1ull);
+            const double ssum = (double)(2 * up - n) - sa;        // sum_{b != a} s_b
+            v[0] = Ra.x;
+            v[1] = sa * Ra.y;
+            v[2] = sa;
+            v[5] = sa * ssum;
+            v[7] = ssum * Ra.x;
+            v[8] = sa * ssum * Ra.y;
+        }
+        // wave w takes b = 1 + w + 4 c; four values of b at a time (b0 + 4 k) give four
+        // independent product chains per lane
+        const int li = act ? lane : 0;
+        for (int b0 = 1 + w; b0 < n; b0 += 4 * RMF_WAVES) {
+            double pr[4], pi[4];
+            int ex2[4], bk[4];   // products kept as (pr + i pi) 2^ex2, rescaled by powers of two
+            for (int k = 0; k < 4; ++k) {
+                pr[k] = 1.0;
+                pi[k] = 0.0;
+                ex2[k] = 0;
+                bk[k] = b0 + 4 * k < n ? b0 + 4 * k : n - 1;
+            }
+            int blast = b0;
+            for (int k = 1; k < 4; ++k)
+                if (b0 + 4 * k < n) blast = b0 + 4 * k;
+            if (!(act && lane < blast)) continue;   // pairs a < b of the group
+            for (int j = 0; j < nh; ++j) {
+                const double2 x = be[j * n + li];
+                for (int k = 0; k < 4; ++k) {
+                    const double2 y = al[j * n + bk[k]];
+                    const double fr = 1.0 + (x.x * y.x - x.y * y.y), fi = x.x * y.y + x.y * y.x;
+                    const double nr = pr[k] * fr - pi[k] * fi, ni = pr[k] * fi + pi[k] * fr;
+                    pr[k] = nr;
+                    pi[k] = ni;
+                }
+                if ((j & 15) == 15)
+                    for (int k = 0; k < 4; ++k) {
+                        int e;
+                        frexp(fabs(pr[k]) + fabs(pi[k]), &e);
+                        pr[k] = ldexp(pr[k], -e);
+                        pi[k] = ldexp(pi[k], -e);
+                        ex2[k] += e;
+                    }
+            }
+            for (int k = 0; k < 4; ++k) {
+                const int b = b0 + 4 * k;
+                if (b >= n) break;
+                if (lane >= b) continue;
+                const double sb = spin(mk, b), ss = sa * sb;
+                const double2 Rb = a.R[sidx * n + b];
+                const double2 Rab = cmul(cmul(Ra, Rb), make_double2(ldexp(pr[k], ex2[k]), ldexp(pi[k], ex2[k])));
+                v[3] += 2.0 * Rab.x;
+                v[4] += -2.0 * ss * Rab.x;
+                v[6] += (sa + sb) * Rab.y;
+            }
+        }
+        for (int q = 0; q < 9; ++q) acc[q] += v[q];
+    }
+    // per-sample normalisation as in the direct kernel: m = v / N, s = (N + v) / N^2 summed
+    // over samples; the N / N^2 constants are added once per sample below
+    for (int q = 0; q < 9; ++q) acc[q] = wave_sum(acc[q]);
+    if (lane == 0)
+        for (int q = 0; q < 9; ++q) part[w][q] = acc[q];
+    __syncthreads();
+    if (tid < 9) {
+        double v = 0.0;
+        for (int ww = 0; ww < RMF_WAVES; ++ww) v += part[ww][tid];
+        int cnt = 0;   // samples this workgroup took
+        for (int s = blockIdx.x; s < a.ns; s += gridDim.x) ++cnt;
+        double r;
+        if (tid < 3) r = v / N;
+        else if (tid < 6) r = (N * cnt + v) / (N * N);
+        else r = v / (N * N);
+        a.mom_part[((size_t)t * a.mom_blocks + blockIdx.x) * 9 + tid] = r;
+    }
+}
+
+// Moments for the RBM, direct form: two-flip ratios psi(s^(ab))/psi(s) = exp(-2 s_a a_a - 2 s_b a_b)
 // prod_j [cosh(u+v) - tanh(g_j) sinh(u+v)],  u = 2 s_a w_aj, v = 2 s_b w_bj.
 constexpr int RMOM_WAVES = 4;
 __global__ __launch_bounds__(64 * RMOM_WAVES) void k_moments_rbm(Dev a) {

@@ -602,7 +602,10 @@ tvmc_status run_moments(tvmc_ctx *c, int slot) {
     Dev &d = c->d;
     const int T = d.nt, nn = d.n * d.n;
     Scope sc(c, "observe");
-    if (d.kind == TVMC_ANSATZ_RBM) {
+    if (d.kind == TVMC_ANSATZ_RBM && d.n * d.nh <= 64 * 64) {
+        hipLaunchKernelGGL(k_moments_rbm_f, dim3(d.mom_blocks, T), dim3(64 * RMF_WAVES), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_moments_rbm_f");
+    } else if (d.kind == TVMC_ANSATZ_RBM) {
         hipLaunchKernelGGL(k_moments_rbm, dim3(d.mom_blocks, T), dim3(64 * RMOM_WAVES), 0, c->stream, d);
         LAUNCHCHECK(c, "k_moments_rbm");
     } else {
