@@ -107,52 +107,73 @@ __global__ void k_ar_copy(Dev a) {
 
 // Training forward/backward per sample (one wavefront per sample, lanes over hidden units and
 // sites).  Writes log q, the hidden activations h, g = d(loss)/d(logits) and da = d(loss)/da.
+// A workgroup takes AR_SAMPLES samples of one trajectory and first stages that trajectory's
+// FP32 weights in LDS with the masks applied (masked entries exactly zero, so the loops run
+// over all inputs without degree tests): W1 as [k][j] with rows padded to N + 1 and W2 as
+// [i][k] with rows padded to H + 1, which keeps every loop below on distinct banks.
 constexpr int AR_WAVES = 4;
+constexpr int AR_SAMPLES = 64;
 __global__ __launch_bounds__(64 * AR_WAVES) void k_ar_forward(Dev a, int want_grad) {
+    __shared__ float sW1[AR_LDS_W + 256];     // [k][j], row stride N + 1
+    __shared__ float sW2[AR_LDS_W + 64];      // [i][k], row stride H + 1
+    __shared__ float sb1[256], sb2[64];
     __shared__ float hs[AR_WAVES][256];
     __shared__ float gs[AR_WAVES][64];
     const int t = blockIdx.y, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int s = blockIdx.x * AR_WAVES + w;
-    const int n = a.n, h = a.ah;
-    if (s >= a.ns) return;
+    const int n = a.n, h = a.ah, s1 = n + 1, s2 = h + 1;
     const ArView p = ar_view(a.arP + (size_t)t * a.arnp, n, h);
-    const uint64_t mk = a.samples[(size_t)t * a.ns + s];
-    float av[4];
-    for (int q = 0; q < 4; ++q) {
-        const int k = lane + 64 * q;
-        av[q] = 0.f;
-        if (k < h) {
-            float x = p.b1[k];
-            const int dk = ar_degree(k, n);
-            for (int j = 0; j < dk; ++j) x += p.W1[(size_t)k * n + j] * (float)spin(mk, j);
-            av[q] = x;
-            hs[w][k] = fmaxf(x, 0.f);
+    for (int e = threadIdx.x; e < h * n; e += blockDim.x) {
+        const int k = e / n, j = e % n;
+        sW1[k * s1 + j] = j < ar_degree(k, n) ? p.W1[e] : 0.f;
+    }
+    for (int e = threadIdx.x; e < n * h; e += blockDim.x) {
+        const int i = e / h, k = e % h;
+        sW2[i * s2 + k] = ar_degree(k, n) <= i ? p.W2[e] : 0.f;
+    }
+    for (int k = threadIdx.x; k < h; k += blockDim.x) sb1[k] = p.b1[k];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sb2[i] = p.b2[i];
+    __syncthreads();
+    const int s_end = min(a.ns, (int)(blockIdx.x + 1) * AR_SAMPLES);
+    for (int s = blockIdx.x * AR_SAMPLES + w; s < s_end; s += AR_WAVES) {
+        const uint64_t mk = a.samples[(size_t)t * a.ns + s];
+        float av[4];
+        for (int q = 0; q < 4; ++q) {
+            const int k = lane + 64 * q;
+            av[q] = 0.f;
+            if (k < h) {
+                float x = sb1[k];
+                for (int j = 0; j < n; ++j) x += sW1[k * s1 + j] * (float)spin(mk, j);
+                av[q] = x;
+                hs[w][k] = fmaxf(x, 0.f);
+            }
         }
-    }
-    float lq = 0.f, gi = 0.f;
-    if (lane < n) {
-        float l = p.b2[lane];
-        for (int k = 0; k < h; ++k)
-            if (ar_degree(k, n) <= lane) l += p.W2[(size_t)lane * h + k] * hs[w][k];
-        const float si = (float)spin(mk, lane);
-        lq = log_sigmoid_f(si * l);
-        // d(-log sigmoid(s l))/dl / B
-        gi = -si * expf(log_sigmoid_f(-si * l)) / (float)a.ns;
-        gs[w][lane] = gi;
-    }
-    lq = (float)wave_sum((double)lq);
-    if (lane == 0) a.arlogq[(size_t)t * a.ns + s] = lq;
-    if (!want_grad) return;
-    const size_t sb = (size_t)t * a.ns + s;
-    if (lane < n) a.arg[sb * n + lane] = gi;
-    for (int q = 0; q < 4; ++q) {
-        const int k = lane + 64 * q;
-        if (k >= h) continue;
-        float dh = 0.f;
-        const int dk = ar_degree(k, n);
-        for (int i = dk; i < n; ++i) dh += gs[w][i] * p.W2[(size_t)i * h + k];
-        a.arh[sb * h + k] = hs[w][k];
-        a.arda[sb * h + k] = av[q] > 0.f ? dh : 0.f;
+        __builtin_amdgcn_wave_barrier();
+        float lq = 0.f, gi = 0.f;
+        if (lane < n) {
+            float l = sb2[lane];
+            for (int k = 0; k < h; ++k) l += sW2[lane * s2 + k] * hs[w][k];
+            const float si = (float)spin(mk, lane);
+            lq = log_sigmoid_f(si * l);
+            // d(-log sigmoid(s l))/dl / B
+            gi = -si * expf(log_sigmoid_f(-si * l)) / (float)a.ns;
+            gs[w][lane] = gi;
+        }
+        __builtin_amdgcn_wave_barrier();
+        lq = (float)wave_sum((double)lq);
+        if (lane == 0) a.arlogq[(size_t)t * a.ns + s] = lq;
+        if (want_grad) {
+            const size_t sb = (size_t)t * a.ns + s;
+            if (lane < n) a.arg[sb * n + lane] = gi;
+            for (int q = 0; q < 4; ++q) {
+                const int k = lane + 64 * q;
+                if (k >= h) continue;
+                float dh = 0.f;
+                for (int i = 0; i < n; ++i) dh += gs[w][i] * sW2[i * s2 + k];
+                a.arh[sb * h + k] = hs[w][k];
+                a.arda[sb * h + k] = av[q] > 0.f ? dh : 0.f;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 

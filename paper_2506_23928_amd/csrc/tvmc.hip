@@ -580,7 +580,7 @@ tvmc_status run_train(tvmc_ctx *c, int iters) {
     Scope sc(c, "train");
     const int tiles = ((d.ah + 31) / 32) * ((d.n + 31) / 32);
     for (int it = 0; it <= iters; ++it) {
-        hipLaunchKernelGGL(k_ar_forward, dim3((d.ns + AR_WAVES - 1) / AR_WAVES, T), dim3(64 * AR_WAVES), 0, c->stream, d,
+        hipLaunchKernelGGL(k_ar_forward, dim3((d.ns + AR_SAMPLES - 1) / AR_SAMPLES, T), dim3(64 * AR_WAVES), 0, c->stream, d,
                            1);
         LAUNCHCHECK(c, "k_ar_forward");
         hipLaunchKernelGGL(k_ar_grad, dim3(tiles, 2, T), dim3(256), 0, c->stream, d);
