@@ -51,6 +51,18 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+__device__ __forceinline__ double wave_prod(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __device__ __forceinline__ double spin(uint64_t mask, int i) { return ((mask >> i) & 1ull) ? 1.0 : -1.0; }
 
 // Jastrow pair index of eta_{jk} (j < k) after the N one-body parameters.
@@ -94,6 +106,7 @@ struct Dev {
     double2 *obarc;           // [T][M] (RBM, complex)
     double *w_re, *w_im;      // [T][N][N'] RBM weights, split planes
     double2 *cT, *sT;         // [T][N'][N] cosh 2w, sinh 2w (transposed)
+    double2 *cW, *sW;         // [T][N][N'] cosh 2w, sinh 2w (the sampler's single-flip ratios)
     double2 *tt;              // [T][Ns][N'] tanh g_j per sample
     double2 *D;               // [T][M]
     double *S;                // [T][M][M]

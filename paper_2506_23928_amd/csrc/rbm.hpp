@@ -49,8 +49,11 @@ __global__ void k_prepare_rbm(Dev a, const double2 *__restrict__ src) {
     double sy, cy;
     sincos(y, &sy, &cy);
     const double ch = cosh(x), sh = sinh(x);
-    a.cT[((size_t)t * nh + j) * n + i] = make_double2(ch * cy, sh * sy);
-    a.sT[((size_t)t * nh + j) * n + i] = make_double2(sh * cy, ch * sy);
+    const double2 cw = make_double2(ch * cy, sh * sy), sw = make_double2(sh * cy, ch * sy);
+    a.cT[((size_t)t * nh + j) * n + i] = cw;
+    a.sT[((size_t)t * nh + j) * n + i] = sw;
+    a.cW[(size_t)t * n * nh + idx] = cw;
+    a.sW[(size_t)t * n * nh + idx] = sw;
 }
 
 // W_LDS: the weights fit in LDS (N N' <= 4096) and are read from there; a template flag, so
@@ -82,10 +85,12 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
     const double2 *th = a.theta_eval + (size_t)t * a.m;
     uint64_t mask = a.chains[(size_t)t * a.nc + c];
 
-    double gre[QH], gim[QH], lc[QH];
+    // per hidden unit j (lane j, j + 64, ...): theta_j = b_j + sum_i w_ij s_i (updated in place)
+    // and t_j = tanh theta_j
+    double gre[QH], gim[QH], tr[QH], ti[QH];
     for (int q = 0; q < QH; ++q) {
         const int j = lane + 64 * q;
-        gre[q] = gim[q] = lc[q] = 0.0;
+        gre[q] = gim[q] = tr[q] = ti[q] = 0.0;
         if (j < nh) {
             double xr = th[n + j].x, xi = th[n + j].y;   // b_j + sum_i w_ij s_i, i in order
             for (int i = 0; i < n; ++i) {
@@ -95,8 +100,16 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
             }
             gre[q] = xr;
             gim[q] = xi;
-            lc[q] = log_abs_cosh(xr, xi);
+            const double2 tj = ctanh_(xr, xi);
+            tr[q] = tj.x;
+            ti[q] = tj.y;
         }
+    }
+    // lane l: |exp(a_l (s'_l - s_l))|^2 for s_l = +1 (ev_dn) and s_l = -1 (ev_up)
+    double ev_dn = 1.0, ev_up = 1.0;
+    if (lane < n) {
+        ev_dn = exp(-4.0 * th[lane].x);
+        ev_up = exp(4.0 * th[lane].x);
     }
 
     const uint32_t ctr1 = ((uint32_t)stage << 31) | (uint32_t)c;
@@ -108,6 +121,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
     uint32_t nacc = 0;
     const size_t tbase = (size_t)t * a.ns;
     const double2 *cT = a.cT + (size_t)t * nh * n, *sT = a.sT + (size_t)t * nh * n;
+    const double2 *cW = a.cW + (size_t)t * n * nh, *sW = a.sW + (size_t)t * n * nh;
 
     // learned proposal: one independent proposal at the start of every sweep
     int next_ar = 0;
@@ -119,8 +133,21 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
         uint32_t r[4];
         philox4x32_10((uint32_t)(base + lane), ctr1, (uint32_t)step, ctr3, a.key0, a.key1, r);
         const int site_l = (int)(((uint64_t)r[0] * (uint64_t)n) >> 32);
-        const double logu_l = log(u53(r[1], r[2]));
+        const double u_l = u53(r[1], r[2]);
         const int cnt = (total - base) < 64 ? (total - base) : 64;
+        // cosh 2w_ij, sinh 2w_ij of the next flip's site, loaded one flip ahead
+        double2 nc[QH], nsw[QH];
+        {
+            const int i0 = __builtin_amdgcn_readlane(site_l, 0);
+            for (int q = 0; q < QH; ++q) {
+                const int j = lane + 64 * q;
+                nc[q] = nsw[q] = make_double2(0.0, 0.0);
+                if (j < nh) {
+                    nc[q] = cW[i0 * nh + j];
+                    nsw[q] = sW[i0 * nh + j];
+                }
+            }
+        }
         for (int jj = 0; jj < cnt; ++jj) {
             if (AR && base + jj == next_ar) {
                 next_ar += n;
@@ -133,10 +160,10 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
                 const uint64_t mnew = ar_draw(a, net, t, ctr1, step, ar_idx++, lane, lqn, uacc);
                 // hidden pre-activations of s' (same summation order as at the start) and
                 // Re log psi(s') - Re log psi(s)
-                double ngr[QH], ngi[QH], nlc[QH], dsum = 0.0;
+                double ngr[QH], ngi[QH], dsum = 0.0;
                 for (int q = 0; q < QH; ++q) {
                     const int j = lane + 64 * q;
-                    ngr[q] = ngi[q] = nlc[q] = 0.0;
+                    ngr[q] = ngi[q] = 0.0;
                     if (j < nh) {
                         double xr = th[n + j].x, xi = th[n + j].y;
                         for (int i = 0; i < n; ++i) {
@@ -146,8 +173,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
                         }
                         ngr[q] = xr;
                         ngi[q] = xi;
-                        nlc[q] = log_abs_cosh(xr, xi);
-                        dsum += nlc[q] - lc[q];
+                        dsum += log_abs_cosh(xr, xi) - log_abs_cosh(gre[q], gim[q]);
                     }
                 }
                 if (lane < n) dsum += th[lane].x * (spin(mnew, lane) - spin(mask, lane));
@@ -155,35 +181,72 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
                 if (log(uacc) < dlog) {
                     mask = mnew;
                     for (int q = 0; q < QH; ++q) {
+                        const int j = lane + 64 * q;
                         gre[q] = ngr[q];
                         gim[q] = ngi[q];
-                        lc[q] = nlc[q];
+                        if (j < nh) {
+                            const double2 tj = ctanh_(ngr[q], ngi[q]);
+                            tr[q] = tj.x;
+                            ti[q] = tj.y;
+                        }
                     }
                     lq_cur = lqn;
                     ++ar_nacc;
                 }
             }
             const int i = __builtin_amdgcn_readlane(site_l, jj);
-            const double lu = readlane_d(logu_l, jj);
+            const double u = readlane_d(u_l, jj);
             const double si = spin(mask, i);
-            double ln[QH], dsum = 0.0;
+            double2 cw[QH], sw[QH];
             for (int q = 0; q < QH; ++q) {
-                const int j = lane + 64 * q;
-                ln[q] = 0.0;
-                if (j < nh) {
-                    ln[q] = log_abs_cosh(gre[q] - 2.0 * si * wr[i * nh + j], gim[q] - 2.0 * si * wi[i * nh + j]);
-                    dsum += ln[q] - lc[q];
+                cw[q] = nc[q];
+                sw[q] = nsw[q];
+            }
+            if (jj + 1 < cnt) {
+                const int i1 = __builtin_amdgcn_readlane(site_l, jj + 1);
+                for (int q = 0; q < QH; ++q) {
+                    const int j = lane + 64 * q;
+                    if (j < nh) {
+                        nc[q] = cW[i1 * nh + j];
+                        nsw[q] = sW[i1 * nh + j];
+                    }
                 }
             }
-            const double dre = -2.0 * si * th[i].x + wave_sum(dsum);
-            if (lu < 2.0 * dre) {
+            // cosh(theta_j - 2 s_i w_ij) / cosh(theta_j) = cosh 2w_ij - s_i t_j sinh 2w_ij; the
+            // ratio |psi(s')/psi(s)|^2 is the product of |.|^2 over j times the visible factor,
+            // formed as (product of frexp mantissas) * 2^(sum of exponents)
+            double fr[QH], fi[QH], pm = 1.0;
+            int pe = 0;
+            for (int q = 0; q < QH; ++q) {
+                const int j = lane + 64 * q;
+                fr[q] = 1.0;
+                fi[q] = 0.0;
+                if (j < nh) {
+                    const double tsr = tr[q] * sw[q].x - ti[q] * sw[q].y, tsi = tr[q] * sw[q].y + ti[q] * sw[q].x;
+                    fr[q] = cw[q].x - si * tsr;
+                    fi[q] = cw[q].y - si * tsi;
+                    int e;
+                    pm *= frexp(fr[q] * fr[q] + fi[q] * fi[q], &e);
+                    pe += e;
+                }
+            }
+            pm = wave_prod(pm);
+            pe = wave_sum_i(pe);
+            int ev;
+            const double mv = frexp(si > 0.0 ? readlane_d(ev_dn, i) : readlane_d(ev_up, i), &ev);
+            if (u < ldexp(pm * mv, pe + ev)) {
                 mask ^= (1ull << i);
                 for (int q = 0; q < QH; ++q) {
                     const int j = lane + 64 * q;
                     if (j < nh) {
                         gre[q] -= 2.0 * si * wr[i * nh + j];
                         gim[q] -= 2.0 * si * wi[i * nh + j];
-                        lc[q] = ln[q];
+                        // tanh(theta - b) = (t cosh b - sinh b) / (cosh b - t sinh b)
+                        const double gr = tr[q] * cw[q].x - ti[q] * cw[q].y - si * sw[q].x;
+                        const double gi = tr[q] * cw[q].y + ti[q] * cw[q].x - si * sw[q].y;
+                        const double inv = 1.0 / (fr[q] * fr[q] + fi[q] * fi[q]);
+                        tr[q] = (gr * fr[q] + gi * fi[q]) * inv;
+                        ti[q] = (gi * fr[q] - gr * fi[q]) * inv;
                     }
                 }
                 ++nacc;
@@ -199,6 +262,8 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
                         const double2 tj = ctanh_(gre[q], gim[q]);
                         tl[w][j] = tj;
                         a.tt[sidx * nh + j] = tj;
+                        tr[q] = tj.x;
+                        ti[q] = tj.y;
                     }
                 }
                 double ere = 0.0, eim = 0.0;

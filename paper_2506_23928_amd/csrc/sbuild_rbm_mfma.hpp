@@ -24,12 +24,15 @@ __device__ __forceinline__ void split_bf16(double x, uint16_t &hi, uint16_t &lo)
     lo = f2bf((float)(x - (double)bf2f(hi)));
 }
 
-// P [T][4][Mp][N_s] BF16 planes: 0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo; rows M..Mp-1 are zero.
-// Grid (ceil(N_s / 256), Mp, T); a thread writes one sample of one row in all four planes.
+// P holds the four BF16 planes 0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo in the order the S-build
+// stages them: [T][Mp / 128 row blocks][N_s / 32 steps][4 planes][128 rows][32 samples], so
+// that one step of one row block is a contiguous 32 KB chunk; rows M..Mp-1 are zero.
+// Grid (N_s / 32, Mp / 8, T); the 256 threads of a block take 32 samples (fastest) of 8 rows
+// and write 512 contiguous bytes per plane.
+constexpr int RQ_CHUNK = 4 * 128 * 32;   // elements of one staged step of one row block
 __global__ __launch_bounds__(256) void k_rbm_split(Dev a) {
-    const int t = blockIdx.z, r = blockIdx.y;
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= a.ns) return;
+    const int t = blockIdx.z, st = blockIdx.x;
+    const int r = blockIdx.y * 8 + (threadIdx.x >> 5), s = st * 32 + (threadIdx.x & 31);
     double re = 0.0, im = 0.0;
     if (r < a.m) {
         const size_t sidx = (size_t)t * a.ns + s;
@@ -41,12 +44,12 @@ __global__ __launch_bounds__(256) void k_rbm_split(Dev a) {
     uint16_t rh, rl, ih, il;
     split_bf16(re, rh, rl);
     split_bf16(im, ih, il);
-    const size_t plane = (size_t)a.mp * a.ns;
-    uint16_t *p = a.rbmP + (size_t)t * 4 * plane + (size_t)r * a.ns + s;
+    const int nst = a.ns / 32;
+    uint16_t *p = a.rbmP + ((size_t)(t * (a.mp / 128) + (r >> 7)) * nst + st) * RQ_CHUNK + (r & 127) * 32 + (s & 31);
     p[0] = rh;
-    p[plane] = rl;
-    p[2 * plane] = ih;
-    p[3 * plane] = il;
+    p[128 * 32] = rl;
+    p[2 * 128 * 32] = ih;
+    p[3 * 128 * 32] = il;
 }
 
 __device__ __forceinline__ bf16x8_t neg_bf16x8(bf16x8_t v) {
@@ -73,13 +76,33 @@ constexpr int RQ_K = 32;          // samples per step
 constexpr int RQ_LD = 40;         // padded LDS row (BF16 elements)
 constexpr int RQ_BUF = 4 * RQ_T * RQ_LD;   // one staged matrix (40 KB)
 constexpr int RQ_THREADS = 512;
+constexpr int RQ_BAND = 4;        // tile rows per band of the work order
 __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
     __shared__ uint16_t sbuf[2][2][RQ_BUF];    // [step parity][row / column operand], 160 KB
-    const int t = blockIdx.y, tile = blockIdx.x;
-    int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
-    while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
-    while (bi * (bi + 1) / 2 > tile) --bi;
-    const int bj = tile - bi * (bi + 1) / 2;
+    // Work order.  Workgroups are dealt round-robin to the 8 XCDs, so workgroup L runs on XCD
+    // L % 8; XCD x takes the contiguous run of work items x * per .. x * per + per - 1 in
+    // turn, and the items of a trajectory are ordered in bands of RQ_BAND tile rows, column by
+    // column, so that the tiles resident on one XCD at a time share few operand panels in its
+    // L2.  The grid is padded to a multiple of 8; padding workgroups exit at once.
+    const int nt = a.mp / RQ_T, ntl = nt * (nt + 1) / 2;
+    const int L = blockIdx.x, per = (int)gridDim.x / 8;
+    const int g = (L & 7) * per + (L >> 3);
+    if (g >= ntl * a.nt) return;
+    const int t = g / ntl, wdx = g % ntl;
+    int band = 0;
+    while ((band + 1) * RQ_BAND * ((band + 1) * RQ_BAND + 1) / 2 <= wdx) ++band;
+    const int b0 = band * RQ_BAND, bh = min(RQ_BAND, nt - b0);
+    int rem = wdx - b0 * (b0 + 1) / 2, bi, bj;
+    if (rem < b0 * bh) {          // full columns left of the band's diagonal block
+        bj = rem / bh;
+        bi = b0 + rem % bh;
+    } else {                      // the band's triangular diagonal block, column by column
+        rem -= b0 * bh;
+        int col = 0;
+        while (rem >= bh - col) rem -= bh - col++;
+        bj = b0 + col;
+        bi = bj + rem;
+    }
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int wr = w >> 2, wc = w & 3;
     const int m = a.m;
@@ -88,16 +111,17 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
     // but their waves still stage operands and meet every barrier
     const bool active = !(bi == bj && c0 > r0 + 63) && r0 < m && c0 < m;
     const int rr = lane & 15, kg = lane >> 4;
-    const size_t ns = (size_t)a.ns, plane = (size_t)a.mp * ns;
-    const uint16_t *Pt = a.rbmP + (size_t)t * 4 * plane;
-    // staging: piece e = tid + 512 i (i < 4) of a matrix is plane e / 512, row (e / 4) % 128,
-    // samples 8 (e % 4) .. +7
+    const size_t ns = (size_t)a.ns, nst = ns / RQ_K;
+    const uint16_t *Pt = a.rbmP + (size_t)t * (a.mp / RQ_T) * nst * RQ_CHUNK;
+    // staging: piece e = tid + 512 i (i < 4) of a step chunk is elements 8 e .. 8 e + 7, i.e.
+    // plane e / 512, row (e / 4) % 128, samples 8 (e % 4) .. +7; consecutive threads read
+    // consecutive 16 bytes
     const uint16_t *gA[4], *gB[4];
     int lofs[4];
     for (int i = 0; i < 4; ++i) {
         const int e = tid + RQ_THREADS * i, q = e >> 9, row = (e >> 2) & 127, part = e & 3;
-        gA[i] = Pt + q * plane + (size_t)(bi * RQ_T + row) * ns + 8 * part;
-        gB[i] = Pt + q * plane + (size_t)(bj * RQ_T + row) * ns + 8 * part;
+        gA[i] = Pt + (size_t)bi * nst * RQ_CHUNK + 8 * e;
+        gB[i] = Pt + (size_t)bj * nst * RQ_CHUNK + 8 * e;
         lofs[i] = (q * RQ_T + row) * RQ_LD + 8 * part;
     }
     bf16x8_t pa[4], pb[4];
@@ -118,12 +142,12 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
     }
     if (RQ_K < ns)
         for (int i = 0; i < 4; ++i) {
-            pa[i] = *(const bf16x8_t *)(gA[i] + RQ_K);
-            pb[i] = *(const bf16x8_t *)(gB[i] + RQ_K);
+            pa[i] = *(const bf16x8_t *)(gA[i] + RQ_CHUNK);
+            pb[i] = *(const bf16x8_t *)(gB[i] + RQ_CHUNK);
         }
     __syncthreads();
     int buf = 0;
-    for (size_t k0 = 0; k0 < ns; k0 += RQ_K, buf ^= 1) {
+    for (size_t k0 = 0, kc = 0; k0 < ns; k0 += RQ_K, kc += RQ_CHUNK, buf ^= 1) {
         const uint16_t *sA = sbuf[buf][0], *sB = sbuf[buf][1];
         bf16x8_t A[4][4], B[2][4];
         if (active) {
@@ -141,8 +165,8 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
             }
             if (k0 + 2 * RQ_K < ns)
                 for (int i = 0; i < 4; ++i) {
-                    pa[i] = *(const bf16x8_t *)(gA[i] + k0 + 2 * RQ_K);
-                    pb[i] = *(const bf16x8_t *)(gB[i] + k0 + 2 * RQ_K);
+                    pa[i] = *(const bf16x8_t *)(gA[i] + kc + 2 * RQ_CHUNK);
+                    pb[i] = *(const bf16x8_t *)(gB[i] + kc + 2 * RQ_CHUNK);
                 }
         }
         if (active) {

@@ -58,7 +58,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, tt, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
+        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
         arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, total;
 };
 
@@ -115,6 +115,8 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.w_im = take(rbm ? sizeof(double) * tt * n * nh : 0);
     L.cT = take(rbm ? sizeof(double2) * tt * n * nh : 0);
     L.sT = take(rbm ? sizeof(double2) * tt * n * nh : 0);
+    L.cW = take(rbm ? sizeof(double2) * tt * n * nh : 0);
+    L.sW = take(rbm ? sizeof(double2) * tt * n * nh : 0);
     L.tt = take(rbm ? sizeof(double2) * tt * ns * nh : 0);
     L.D = take(sizeof(double2) * tt * m);
     const int dim = ss ? ns : m;   // dimension of the system solved
@@ -396,12 +398,12 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         if (c->cfg.precision == TVMC_PREC_MFMA) {
             {
                 Scope sc(c, "transpose");
-                hipLaunchKernelGGL(k_rbm_split, dim3((d.ns + 255) / 256, d.mp, T), dim3(256), 0, c->stream, d);
+                hipLaunchKernelGGL(k_rbm_split, dim3(d.ns / 32, d.mp / 8, T), dim3(256), 0, c->stream, d);
                 LAUNCHCHECK(c, "k_rbm_split");
             }
             Scope sc(c, "sbuild");
             const int nt = d.mp / RQ_T;
-            hipLaunchKernelGGL(k_sbuild_rbm_bf16, dim3(nt * (nt + 1) / 2, T), dim3(RQ_THREADS), 0, c->stream, d);
+            hipLaunchKernelGGL(k_sbuild_rbm_bf16, dim3((nt * (nt + 1) / 2 * T + 7) / 8 * 8), dim3(RQ_THREADS), 0, c->stream, d);
             LAUNCHCHECK(c, "k_sbuild_rbm_bf16");
         } else {
             Scope sc(c, "sbuild");
@@ -735,6 +737,8 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.w_im = (double *)(base + L.w_im);
     d.cT = (double2 *)(base + L.cT);
     d.sT = (double2 *)(base + L.sT);
+    d.cW = (double2 *)(base + L.cW);
+    d.sW = (double2 *)(base + L.sW);
     d.tt = (double2 *)(base + L.tt);
     d.mp = (m + RQ_T - 1) / RQ_T * RQ_T;
     d.rbmP = (uint16_t *)(base + L.rbmP);
