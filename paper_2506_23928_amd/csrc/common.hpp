@@ -51,16 +51,36 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Reductions over the 64 lanes through DPP lane moves (no LDS round trips): within each row
+// of 16 lanes by quad permutations and mirrors, then across rows by the row broadcasts of
+// lanes 15 and 31, which leave the total in lane 63; it is returned to every lane.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double old, double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int DPP_QUAD_1032 = 0xB1, DPP_QUAD_2301 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140,
+              DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+
 __device__ __forceinline__ double wave_prod(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
-    return v;
+    v *= dpp_d<DPP_QUAD_1032, 0xF>(v, v);
+    v *= dpp_d<DPP_QUAD_2301, 0xF>(v, v);
+    v *= dpp_d<DPP_HALF_MIRROR, 0xF>(v, v);
+    v *= dpp_d<DPP_MIRROR, 0xF>(v, v);
+    v *= dpp_d<DPP_BCAST15, 0xA>(1.0, v);
+    v *= dpp_d<DPP_BCAST31, 0xC>(1.0, v);
+    return readlane_d(v, 63);
 }
 
 __device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_QUAD_1032, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_QUAD_2301, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_HALF_MIRROR, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_MIRROR, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_BCAST15, 0xA, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_BCAST31, 0xC, 0xF, false);
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ __forceinline__ double spin(uint64_t mask, int i) { return ((mask >> i) & 1ull) ? 1.0 : -1.0; }

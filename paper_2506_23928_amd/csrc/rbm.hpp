@@ -66,9 +66,15 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
     __shared__ uint16_t arw_s[AR ? 2 * AR_LDS_W : 1];
     __shared__ float arb_s[AR ? 256 + 64 : 1];
     const int n = a.n, nh = a.nh;
-    const int t = blockIdx.y;
+    // Workgroup L runs on XCD L % 8; XCD x takes work items x * per .. x * per + per - 1, so
+    // the N_c / CPB workgroups of a trajectory share one XCD's L2 (its cosh/sinh tables and
+    // weights).  The grid is padded to a multiple of 8; padding workgroups exit at once.
+    const int nb = a.nc / CPB, per = (int)gridDim.x / 8;
+    const int g = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+    if (g >= nb * a.nt) return;
+    const int t = g / nb;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int c = blockIdx.x * CPB + w;
+    const int c = (g % nb) * CPB + w;
     const bool in_lds = W_LDS;
     const double *gwr = a.w_re + (size_t)t * n * nh, *gwi = a.w_im + (size_t)t * n * nh;
     if (in_lds) {

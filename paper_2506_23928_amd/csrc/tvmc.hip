@@ -298,7 +298,7 @@ tvmc_status run_sample(tvmc_ctx *c) {
                            (const double2 *)d.theta_eval);
         LAUNCHCHECK(c, "k_prepare_rbm");
         Scope sc(c, "sample");
-        dim3 grid(d.nc / c->cpb, T);
+        dim3 grid((d.nc / c->cpb * T + 7) / 8 * 8);
         const int qh = (d.nh + 63) / 64;
 #define RBM_LAUNCH(CPB, QH, AR, WL) hipLaunchKernelGGL((k_sample_rbm<CPB, QH, AR, WL>), grid, dim3(64 * CPB), 0, c->stream, d, c->step, c->stage, burn)
 #define RBM_CPB(QH, AR, WL)                         \
