@@ -298,11 +298,15 @@ tvmc_status run_sample(tvmc_ctx *c) {
                            (const double2 *)d.theta_eval);
         LAUNCHCHECK(c, "k_prepare_rbm");
         Scope sc(c, "sample");
-        dim3 grid((d.nc / c->cpb * T + 7) / 8 * 8);
         const int qh = (d.nh + 63) / 64;
+        // 16 chains per workgroup (4 waves per SIMD, every chain resident at once) where the
+        // chain count allows and the per-chain LDS rows fit (N' <= 128)
+        const int cpb = (c->cpb == 8 && d.nc % 16 == 0 && qh <= 2) ? 16 : c->cpb;
+        dim3 grid((d.nc / cpb * T + 7) / 8 * 8);
 #define RBM_LAUNCH(CPB, QH, AR, WL) hipLaunchKernelGGL((k_sample_rbm<CPB, QH, AR, WL>), grid, dim3(64 * CPB), 0, c->stream, d, c->step, c->stage, burn)
 #define RBM_CPB(QH, AR, WL)                         \
-    switch (c->cpb) {                               \
+    switch (cpb) {                                  \
+    case 16: if constexpr (QH <= 2) { RBM_LAUNCH(16, QH, AR, WL); } break; \
     case 8: RBM_LAUNCH(8, QH, AR, WL); break;       \
     case 4: RBM_LAUNCH(4, QH, AR, WL); break;       \
     case 2: RBM_LAUNCH(2, QH, AR, WL); break;       \

@@ -35,7 +35,7 @@ def _hermitian(S):
 
 
 @pytest.mark.parametrize("n,nh,ns,nc,scheme", [(5, 3, 256, 8, 0), (6, 70, 128, 4, 1), (4, 1, 64, 2, 0),
-                                               (9, 20, 192, 3, 0)])
+                                               (9, 20, 192, 3, 0), (7, 12, 320, 16, 1), (6, 70, 256, 32, 0)])
 def test_rbm_step_parity(tv, orc, n, nh, ns, nc, scheme):
     """Predictor and corrector of one step: samples, accepts, local energies, <B^n>, <O_k>, S,
     D, both increments and theta; N' = 70 takes two hidden units per lane.  Where M > N_s
