@@ -5,7 +5,7 @@
 //                      Re C -= Lr Lr'^T + Li Li'^T,  Im C -= Li Lr'^T - Lr Li'^T   (4 real MFMA products)
 //   k_zmw_diag(j0):    L_pp L_pp^H = C_pp in LDS, Linv = L_pp^-1, y_p = Linv z_p
 //   k_zmw_trsm(j0):    L[rows, panel] = C Linv^H, z[rows] -= L[rows, panel] y_p
-//   k_zmw_backward:    L^H x = y with x_p = Linv^H (y_p - L[below, p]^H x_below)
+//   k_zmw_bwd(p):      L^H x = y by row panels: x_p = Linv^H w_p, w_c -= L[p, c]^H x_p (c < j0)
 // Matrices are complex [T][M][M] (lower triangle), interleaved (re, im).
 #pragma once
 #include "cholesky.hpp"
@@ -267,52 +267,66 @@ __global__ __launch_bounds__(256) void k_zmw_trsm(ZCholArgs a, int j0, int p) {
         }
 }
 
-// L^H x = y, last panel first: w_c = y_c - sum_{r below} conj(L_rc) x_r, x_p = Linv^H w
-__global__ __launch_bounds__(256) void k_zmw_backward(ZCholArgs a) {
-    __shared__ double2 ws[CN];
-    const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int M = a.m;
+// L^H x = y by row panels, last panel first, one launch per panel p (then a closing launch
+// p = -1).  w starts as y (in x) and, once every panel below p has been applied, w_p = y_p -
+// sum_{r below} conj(L_rp) x_r, so x_p = Linv_p^H w_p.  Launch p: every workgroup forms x_p in
+// LDS and subtracts conj(L[rows of p][c]) x_p from w_c for its chunk of ZB_COLS columns c < j0
+// (one column per thread, the panel's rows read row by row, coalesced); workgroup 0 also
+// writes x_{p+1} over w_{p+1}, which no workgroup of launch p reads.  The closing launch
+// writes x_0 and flags non-finite solutions.
+constexpr int ZB_COLS = 256;
+__device__ __forceinline__ void zbwd_x(const double2 *__restrict__ lv, const double2 *ws, double2 *xs, int jb, int tid) {
+    if (tid < jb) {   // x_c = sum_{k >= c} conj(Linv_kc) w_k
+        double xr = 0.0, xi = 0.0;
+        for (int k = tid; k < jb; ++k) {
+            const double2 l = lv[k * CN + tid], w = ws[k];
+            xr += l.x * w.x + l.y * w.y;
+            xi += l.x * w.y - l.y * w.x;
+        }
+        xs[tid] = make_double2(xr, xi);
+    }
+}
+
+__global__ __launch_bounds__(ZB_COLS) void k_zmw_bwd(ZCholArgs a, int p) {
+    __shared__ double2 ws[CN], xs[CN];
+    const int t = blockIdx.y, tid = threadIdx.x;
+    const int M = a.m, np = chol_panels(M);
     const double2 *A = a.A + (size_t)t * M * M;
-    const double2 *linv = a.linv + (size_t)t * chol_panels(M) * CN * CN;
+    const double2 *linv = a.linv + (size_t)t * np * CN * CN;
     double2 *z = a.x + (size_t)t * M;
-    for (int p = chol_panels(M) - 1; p >= 0; --p) {
-        const int j0 = p * CN, jb = (M - j0) < CN ? (M - j0) : CN;
-        double sr[16], si[16];
-        for (int q = 0; q < 16; ++q) sr[q] = si[q] = 0.0;
-        for (int r = j0 + jb + lane; r < M; r += 64) {
-            const double2 xr = z[r];
-            const double2 *row = A + (size_t)r * M + j0 + wave * 16;
-            for (int q = 0; q < 16; ++q) {
-                const double2 l = (wave * 16 + q < jb) ? row[q] : make_double2(0.0, 0.0);
-                sr[q] += l.x * xr.x + l.y * xr.y;   // conj(l) x
-                si[q] += l.x * xr.y - l.y * xr.x;
-            }
-        }
-        for (int q = 0; q < 16; ++q) {
-            const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
-            if (lane == 0) {
-                const int c = wave * 16 + q;
-                ws[c] = c < jb ? make_double2(z[j0 + c].x - tr, z[j0 + c].y - ti) : make_double2(0.0, 0.0);
-            }
-        }
+    if (blockIdx.x == 0 && p + 1 < np) {   // x_{p+1} over w_{p+1}
+        const int j1 = (p + 1) * CN, jb1 = min(CN, M - j1);
+        if (tid < jb1) ws[tid] = z[j1 + tid];
         __syncthreads();
-        if (tid < jb) {   // x_c = sum_{k >= c} conj(Linv_kc) w_k
-            const double2 *lv = linv + (size_t)p * CN * CN;
-            double xr = 0.0, xi = 0.0;
-            for (int k = tid; k < jb; ++k) {
-                const double2 l = lv[k * CN + tid], w = ws[k];
-                xr += l.x * w.x + l.y * w.y;
-                xi += l.x * w.y - l.y * w.x;
-            }
-            z[j0 + tid] = make_double2(xr, xi);
-        }
+        zbwd_x(linv + (size_t)(p + 1) * CN * CN, ws, xs, jb1, tid);
+        __syncthreads();
+        if (tid < jb1) z[j1 + tid] = xs[tid];
         __syncthreads();
     }
-    if (tid == 0) {
-        int nf = 0;
-        for (int i = 0; i < M && !nf; ++i)
-            if (!isfinite(z[i].x) || !isfinite(z[i].y)) nf = 1;
-        if (nf) a.flags[t] = 1;
+    if (p < 0) {
+        if (tid == 0) {
+            int nf = 0;
+            for (int i = 0; i < M && !nf; ++i)
+                if (!isfinite(z[i].x) || !isfinite(z[i].y)) nf = 1;
+            if (nf) a.flags[t] = 1;
+        }
+        return;
+    }
+    const int j0 = p * CN, jb = min(CN, M - j0);
+    if (tid < jb) ws[tid] = z[j0 + tid];
+    __syncthreads();
+    zbwd_x(linv + (size_t)p * CN * CN, ws, xs, jb, tid);
+    __syncthreads();
+    const int c = blockIdx.x * ZB_COLS + tid;
+    if (c < j0) {
+        double sr = 0.0, si = 0.0;
+        const double2 *col = A + (size_t)j0 * M + c;
+        for (int r = 0; r < jb; ++r) {
+            const double2 l = col[(size_t)r * M], x = xs[r];
+            sr += l.x * x.x + l.y * x.y;   // conj(l) x
+            si += l.x * x.y - l.y * x.x;
+        }
+        z[c] = make_double2(z[c].x - sr, z[c].y - si);
     }
 }
 

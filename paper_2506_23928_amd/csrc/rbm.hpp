@@ -2,11 +2,12 @@
 //   log psi(s) = sum_i a_i s_i + sum_j log 2cosh(g_j),   g_j = b_j + sum_i w_ij s_i,
 //   O = (s_i ; tanh g_j ; s_i tanh g_j),  M = N + N' + N N' complex parameters.
 // Sampling: one wavefront per chain, lane j owns hidden units j, j+64, ...; it keeps g_j and
-// log|cosh g_j|.  The accept test needs only Re(log psi' - log psi) = -2 s_i Re a_i +
-// sum_j (log|cosh(g_j - 2 s_i w_ij)| - log|cosh g_j|), one wave reduction per proposal.
-// Single-flip ratios use cosh(g - 2 s w)/cosh g = cosh 2w - s tanh(g) sinh 2w with the
-// cosh 2w / sinh 2w tables built once per evaluation, so a sample's N ratios cost N N'
-// complex multiply-adds (products renormalised every 16 factors).
+// t_j = tanh g_j.  Flipping spin i multiplies psi by exp(-2 s_i a_i) prod_j cosh(g_j - 2 s_i
+// w_ij) / cosh g_j, and each factor is cosh 2w_ij - s_i t_j sinh 2w_ij: with cosh 2w and
+// sinh 2w tabulated once per evaluation, the accept test is a product of |.|^2 over the lanes
+// (mantissas multiplied, exponents summed) compared with the uniform.  A learned proposal
+// (a whole new configuration) compares log|cosh| sums.  The N single-flip ratios of a recorded
+// sample (local energy) use the same factors, N N' complex multiply-adds per sample.
 // The complex Hermitian S (lower triangle) is solved by the complex FP64 Cholesky.
 #pragma once
 #include "common.hpp"
@@ -275,8 +276,10 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
                 double ere = 0.0, eim = 0.0;
                 if (lane < n) {
                     const double sl = spin(mask, lane);
-                    // prod_j (cosh 2w_lj - s_l t_j sinh 2w_lj), renormalised every 16 factors
-                    double pr = 1.0, pi = 0.0, lsum = 0.0;
+                    // prod_j (cosh 2w_lj - s_l t_j sinh 2w_lj), rescaled by a power of two every
+                    // 16 factors (exponents summed in pe)
+                    double pr = 1.0, pi = 0.0;
+                    int pe = 0;
                     for (int j = 0; j < nh; ++j) {
                         const double2 ch = cT[(size_t)j * n + lane], sh = sT[(size_t)j * n + lane];
                         const double2 ts = cmul(tl[w][j], sh);
@@ -285,17 +288,19 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int st
                         pr = nr;
                         pi = ni;
                         if ((j & 15) == 15) {
-                            const double mg = sqrt(pr * pr + pi * pi);
-                            lsum += log(mg);
-                            pr /= mg;
-                            pi /= mg;
+                            int e;
+                            frexp(fmax(fabs(pr), fabs(pi)), &e);
+                            pr = ldexp(pr, -e);
+                            pi = ldexp(pi, -e);
+                            pe += e;
                         }
                     }
-                    const double er = lsum - 2.0 * sl * th[lane].x, ei = -2.0 * sl * th[lane].y;
+                    const double er = -2.0 * sl * th[lane].x, ei = -2.0 * sl * th[lane].y;
                     const double ex = exp(er);
                     double sn, cs;
                     sincos(ei, &sn, &cs);
-                    const double2 R = cmul(make_double2(pr, pi), make_double2(ex * cs, ex * sn));
+                    const double2 Rm = cmul(make_double2(pr, pi), make_double2(ex * cs, ex * sn));
+                    const double2 R = make_double2(ldexp(Rm.x, pe), ldexp(Rm.y, pe));
                     a.R[sidx * n + lane] = R;
                     double hj = 0.0;
                     for (int k = 0; k < n; ++k) hj += a.J[t * a.j_stride + k * n + lane] * spin(mask, k);

@@ -477,10 +477,15 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
             LAUNCHCHECK(c, "panel TRSM");
         }
     }
-    if constexpr (CPLX)
-        hipLaunchKernelGGL(k_zmw_backward, dim3(T), dim3(256), 0, st, x);
-    else
+    if constexpr (CPLX) {
+        for (int p = chol_panels(x.m) - 1; p >= -1; --p) {
+            const int cols = p > 0 ? p * CN : 0;
+            hipLaunchKernelGGL(k_zmw_bwd, dim3(cols > 0 ? (cols + ZB_COLS - 1) / ZB_COLS : 1, T), dim3(ZB_COLS), 0, st,
+                               x, p);
+        }
+    } else {
         hipLaunchKernelGGL(k_cmw_backward, dim3(T), dim3(256), 0, st, x);
+    }
     LAUNCHCHECK(c, "backward substitution");
     return TVMC_OK;
 }
