@@ -65,8 +65,8 @@ __device__ __forceinline__ bf16x8_t neg_bf16x8(bf16x8_t v) {
 // 16x16 (64 FP32 accumulators), which keeps a wave under 256 registers so that two waves
 // share each SIMD and hide each other's LDS and MFMA latencies.  Per step of 32 samples the
 // workgroup stages the tile's row and column operands (4 planes x 128 rows x 32 samples each,
-// 64 KB) through double-buffered LDS: step k is read from one buffer while step k + 1 is
-// written to the other and step k + 2 is loaded into registers, one barrier per step.  Rows
+// 64 KB) through double-buffered LDS, with the fragments of the next step read while the
+// products of the current one are issued (the pipeline is described at the main loop).  Rows
 // are padded to 40 BF16 (80 B), which keeps the 16-byte fragment reads of 16 consecutive rows
 // on distinct banks.  A fragment is 16 bytes per lane: row lane & 15, samples 8 (lane >> 4)
 // .. +7 of the step (the Gram product only needs the row and column operands to use the same
@@ -124,11 +124,36 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
         gB[i] = Pt + (size_t)bj * nst * RQ_CHUNK + 8 * e;
         lofs[i] = (q * RQ_T + row) * RQ_LD + 8 * part;
     }
+    // Pipeline: at the start of step k the fragments of step k are in registers, LDS buffer
+    // (k+1)&1 holds step k+1 and registers pa/pb hold step k+2.  Step k writes step k+2 into
+    // buffer k&1 (whose step-k contents were read into registers during step k-1), loads step
+    // k+3 into pa/pb, and issues its 12 products plane by plane, reloading each fragment plane
+    // from buffer (k+1)&1 as soon as its last product of step k has been issued; one barrier
+    // ends the step.
     bf16x8_t pa[4], pb[4];
     for (int i = 0; i < 4; ++i) {
         pa[i] = *(const bf16x8_t *)gA[i];
         pb[i] = *(const bf16x8_t *)gB[i];
     }
+    for (int i = 0; i < 4; ++i) {
+        *(bf16x8_t *)(sbuf[0][0] + lofs[i]) = pa[i];
+        *(bf16x8_t *)(sbuf[0][1] + lofs[i]) = pb[i];
+    }
+    if (1 < nst) {
+        for (int i = 0; i < 4; ++i) {
+            pa[i] = *(const bf16x8_t *)(gA[i] + RQ_CHUNK);
+            pb[i] = *(const bf16x8_t *)(gB[i] + RQ_CHUNK);
+        }
+        for (int i = 0; i < 4; ++i) {
+            *(bf16x8_t *)(sbuf[1][0] + lofs[i]) = pa[i];
+            *(bf16x8_t *)(sbuf[1][1] + lofs[i]) = pb[i];
+        }
+    }
+    if (2 < nst)
+        for (int i = 0; i < 4; ++i) {
+            pa[i] = *(const bf16x8_t *)(gA[i] + 2 * RQ_CHUNK);
+            pb[i] = *(const bf16x8_t *)(gB[i] + 2 * RQ_CHUNK);
+        }
     f32x4_t sre[4][2], sim[4][2];
     for (int u = 0; u < 4; ++u)
         for (int v = 0; v < 2; ++v) {
@@ -136,66 +161,59 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
             sim[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         }
     const int arow = wr * 64 + rr, brow = wc * 32 + rr;
-    for (int i = 0; i < 4; ++i) {
-        *(bf16x8_t *)(sbuf[0][0] + lofs[i]) = pa[i];
-        *(bf16x8_t *)(sbuf[0][1] + lofs[i]) = pb[i];
-    }
-    if (RQ_K < ns)
-        for (int i = 0; i < 4; ++i) {
-            pa[i] = *(const bf16x8_t *)(gA[i] + RQ_CHUNK);
-            pb[i] = *(const bf16x8_t *)(gB[i] + RQ_CHUNK);
-        }
+#define RQ_LDA(BUF, Q) for (int u = 0; u < 4; ++u) A[u][Q] = *(const bf16x8_t *)(sbuf[BUF][0] + ((Q) * RQ_T + arow + 16 * u) * RQ_LD + 8 * kg);
+#define RQ_LDB(BUF, Q) for (int v = 0; v < 2; ++v) B[v][Q] = *(const bf16x8_t *)(sbuf[BUF][1] + ((Q) * RQ_T + brow + 16 * v) * RQ_LD + 8 * kg);
+#define RQ_TERM(ACC, AX, BX) for (int u = 0; u < 4; ++u) for (int v = 0; v < 2; ++v) ACC[u][v] = MFMA_BF16(AX, BX, ACC[u][v]);
+    bf16x8_t A[4][4], B[2][4];
     __syncthreads();
-    int buf = 0;
-    for (size_t k0 = 0, kc = 0; k0 < ns; k0 += RQ_K, kc += RQ_CHUNK, buf ^= 1) {
-        const uint16_t *sA = sbuf[buf][0], *sB = sbuf[buf][1];
-        bf16x8_t A[4][4], B[2][4];
-        if (active) {
-            for (int u = 0; u < 4; ++u)
-                for (int q = 0; q < 4; ++q)
-                    A[u][q] = *(const bf16x8_t *)(sA + (q * RQ_T + arow + 16 * u) * RQ_LD + 8 * kg);
-            for (int v = 0; v < 2; ++v)
-                for (int q = 0; q < 4; ++q)
-                    B[v][q] = *(const bf16x8_t *)(sB + (q * RQ_T + brow + 16 * v) * RQ_LD + 8 * kg);
-        }
-        if (k0 + RQ_K < ns) {
+    if (active) {
+        RQ_LDA(0, 0) RQ_LDA(0, 1) RQ_LDA(0, 2) RQ_LDA(0, 3)
+        RQ_LDB(0, 0) RQ_LDB(0, 1) RQ_LDB(0, 2) RQ_LDB(0, 3)
+    }
+    __syncthreads();
+    for (int k = 0; k < (int)nst; ++k) {
+        const int wb = k & 1, rb = wb ^ 1;
+        const bool more = k + 1 < (int)nst;
+        if (k + 2 < (int)nst) {
             for (int i = 0; i < 4; ++i) {
-                *(bf16x8_t *)(sbuf[buf ^ 1][0] + lofs[i]) = pa[i];
-                *(bf16x8_t *)(sbuf[buf ^ 1][1] + lofs[i]) = pb[i];
+                *(bf16x8_t *)(sbuf[wb][0] + lofs[i]) = pa[i];
+                *(bf16x8_t *)(sbuf[wb][1] + lofs[i]) = pb[i];
             }
-            if (k0 + 2 * RQ_K < ns)
+            if (k + 3 < (int)nst)
                 for (int i = 0; i < 4; ++i) {
-                    pa[i] = *(const bf16x8_t *)(gA[i] + kc + 2 * RQ_CHUNK);
-                    pb[i] = *(const bf16x8_t *)(gB[i] + kc + 2 * RQ_CHUNK);
+                    pa[i] = *(const bf16x8_t *)(gA[i] + (size_t)(k + 3) * RQ_CHUNK);
+                    pb[i] = *(const bf16x8_t *)(gB[i] + (size_t)(k + 3) * RQ_CHUNK);
                 }
         }
         if (active) {
-            // term-major order: 8 independent accumulators between two MFMAs on the same one
-            //   Re += Ar.Br + Ai.Bi  (hi hi, hi lo, lo hi),  Im += Ar.Bi - Ai.Br
-            bf16x8_t NI[4][2];
-            for (int u = 0; u < 4; ++u) {
-                NI[u][0] = neg_bf16x8(A[u][2]);
-                NI[u][1] = neg_bf16x8(A[u][3]);
+            //   Re += Ar.Br + Ai.Bi,  Im += Ar.Bi + Ai.(-Br), each as hi hi + hi lo + lo hi
+            bf16x8_t NB[2][2];
+            for (int v = 0; v < 2; ++v) {
+                NB[v][0] = neg_bf16x8(B[v][0]);
+                NB[v][1] = neg_bf16x8(B[v][1]);
             }
-#define RQ_TERM(ACC, AX, BX)                                                  \
-            for (int u = 0; u < 4; ++u)                                       \
-                for (int v = 0; v < 2; ++v) ACC[u][v] = MFMA_BF16(AX, BX, ACC[u][v]);
             RQ_TERM(sre, A[u][0], B[v][0])
             RQ_TERM(sim, A[u][0], B[v][2])
             RQ_TERM(sre, A[u][0], B[v][1])
             RQ_TERM(sim, A[u][0], B[v][3])
+            if (more) { RQ_LDA(rb, 0) RQ_LDB(rb, 1) }
             RQ_TERM(sre, A[u][1], B[v][0])
             RQ_TERM(sim, A[u][1], B[v][2])
+            if (more) { RQ_LDA(rb, 1) RQ_LDB(rb, 0) }
             RQ_TERM(sre, A[u][2], B[v][2])
-            RQ_TERM(sim, NI[u][0], B[v][0])
+            RQ_TERM(sim, A[u][2], NB[v][0])
             RQ_TERM(sre, A[u][2], B[v][3])
-            RQ_TERM(sim, NI[u][0], B[v][1])
+            RQ_TERM(sim, A[u][2], NB[v][1])
+            if (more) { RQ_LDA(rb, 2) RQ_LDB(rb, 3) }
             RQ_TERM(sre, A[u][3], B[v][2])
-            RQ_TERM(sim, NI[u][1], B[v][0])
-#undef RQ_TERM
+            RQ_TERM(sim, A[u][3], NB[v][0])
+            if (more) { RQ_LDA(rb, 3) RQ_LDB(rb, 2) }
         }
         __syncthreads();
     }
+#undef RQ_LDA
+#undef RQ_LDB
+#undef RQ_TERM
     if (!active) return;
     const double inv = 1.0 / (double)a.ns;
     double2 *S = (double2 *)a.S + (size_t)t * m * m;
