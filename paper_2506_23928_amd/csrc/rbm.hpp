@@ -334,28 +334,69 @@ __device__ __forceinline__ double2 rbm_o(const Dev &a, int k, uint64_t mk, const
 }
 
 // <O_k> and D_k = <O_k^* G> - <O_k>^* <G>
+// Lane l of the workgroup's 4 waves takes the 8 parameters k_c = 512 blockIdx.x + 64 c + l
+// (c < 8); wave w sums the samples of quarter w of the batch, and the four partial sums are
+// added in wave order.  Weight rows k_c with the same hidden unit j (all 8 of them when N'
+// divides 64 and the weights start on a multiple of 64) share one load of tanh g_j per sample.
+constexpr int OD_R = 8;
 __global__ __launch_bounds__(256) void k_obar_D_rbm(Dev a) {
-    const int t = blockIdx.y;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.m) return;
+    __shared__ double part[4][OD_R][4][64];
+    const int t = blockIdx.y, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = a.n, nh = a.nh, wb = n + nh;
+    int ki[OD_R], kj[OD_R];
+    int jl = -1;
+    for (int c = 0; c < OD_R; ++c) {
+        const int k = blockIdx.x * 64 * OD_R + 64 * c + lane;
+        ki[c] = kj[c] = -1;
+        if (k >= wb && k < a.m) {
+            ki[c] = (k - wb) / nh;
+            kj[c] = (k - wb) % nh;
+            if (jl < 0) jl = kj[c];
+        }
+    }
+    double acc[OD_R][4];
+    for (int c = 0; c < OD_R; ++c) acc[c][0] = acc[c][1] = acc[c][2] = acc[c][3] = 0.0;
     const uint64_t *smp = a.samples + (size_t)t * a.ns;
     const double2 *G = a.G + (size_t)t * a.ns;
-    const double2 *tt = a.tt + (size_t)t * a.ns * a.nh;
-    double obr = 0.0, obi = 0.0, dr = 0.0, di = 0.0;
-    for (int s = 0; s < a.ns; ++s) {
-        const double2 o = rbm_o(a, k, smp[s], tt + (size_t)s * a.nh);
+    const double2 *tt = a.tt + (size_t)t * a.ns * nh;
+    const int q = (a.ns + 3) / 4, s1 = min(a.ns, (w + 1) * q);
+    for (int s = w * q; s < s1; ++s) {
+        const uint64_t mk = smp[s];
         const double2 g = G[s];
-        obr += o.x;
-        obi += o.y;
-        dr += o.x * g.x + o.y * g.y;   // conj(o) g
-        di += o.x * g.y - o.y * g.x;
+        const double2 *tts = tt + (size_t)s * nh;
+        const double2 tv = jl >= 0 ? tts[jl] : make_double2(0.0, 0.0);
+        for (int c = 0; c < OD_R; ++c) {
+            const int k = blockIdx.x * 64 * OD_R + 64 * c + lane;
+            if (k >= a.m) continue;
+            double2 o;
+            if (ki[c] >= 0 && kj[c] == jl) {
+                const double si = spin(mk, ki[c]);
+                o = make_double2(si * tv.x, si * tv.y);
+            } else {
+                o = rbm_o(a, k, mk, tts);
+            }
+            acc[c][0] += o.x;
+            acc[c][1] += o.y;
+            acc[c][2] += o.x * g.x + o.y * g.y;   // conj(o) g
+            acc[c][3] += o.x * g.y - o.y * g.x;
+        }
     }
+    for (int c = 0; c < OD_R; ++c)
+        for (int v = 0; v < 4; ++v) part[w][c][v][lane] = acc[c][v];
+    __syncthreads();
+    if (w != 0) return;
     const double inv = 1.0 / (double)a.ns;
-    obr *= inv;
-    obi *= inv;
     const double2 gb = a.gbar[t];
-    a.obarc[(size_t)t * a.m + k] = make_double2(obr, obi);
-    a.D[(size_t)t * a.m + k] = make_double2(dr * inv - (obr * gb.x + obi * gb.y), di * inv - (obr * gb.y - obi * gb.x));
+    for (int c = 0; c < OD_R; ++c) {
+        const int k = blockIdx.x * 64 * OD_R + 64 * c + lane;
+        if (k >= a.m) continue;
+        double sum[4];
+        for (int v = 0; v < 4; ++v) sum[v] = part[0][c][v][lane] + part[1][c][v][lane] + part[2][c][v][lane] + part[3][c][v][lane];
+        const double obr = sum[0] * inv, obi = sum[1] * inv;
+        a.obarc[(size_t)t * a.m + k] = make_double2(obr, obi);
+        a.D[(size_t)t * a.m + k] =
+            make_double2(sum[2] * inv - (obr * gb.x + obi * gb.y), sum[3] * inv - (obr * gb.y - obi * gb.x));
+    }
 }
 
 // Complex S + eps I (lower triangle, interleaved re/im), plain FP64:

@@ -27,29 +27,69 @@ __device__ __forceinline__ void split_bf16(double x, uint16_t &hi, uint16_t &lo)
 // P holds the four BF16 planes 0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo in the order the S-build
 // stages them: [T][Mp / 128 row blocks][N_s / 32 steps][4 planes][128 rows][32 samples], so
 // that one step of one row block is a contiguous 32 KB chunk; rows M..Mp-1 are zero.
-// Grid (N_s / 32, Mp / 8, T); the 256 threads of a block take 32 samples (fastest) of 8 rows
-// and write 512 contiguous bytes per plane.
+// Grid (N_s / 32, ceil(Mp / 512), T); a block takes SPL_R slices of 64 rows, thread tid row
+// tid / 4 of each slice and the 8 samples 8 (tid % 4) .. +7 of the step, and writes 16 bytes
+// per plane: a wavefront writes 16 rows x 64 bytes, one contiguous kilobyte of each plane.  The
+// thread's rows differ by 64, so where N' divides 64 and the weights start on a multiple of 64
+// they share the hidden unit j and its 8 tanh values are loaded once.
 constexpr int RQ_CHUNK = 4 * 128 * 32;   // elements of one staged step of one row block
+constexpr int SPL_R = 8;
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
 __global__ __launch_bounds__(256) void k_rbm_split(Dev a) {
-    const int t = blockIdx.z, st = blockIdx.x;
-    const int r = blockIdx.y * 8 + (threadIdx.x >> 5), s = st * 32 + (threadIdx.x & 31);
-    double re = 0.0, im = 0.0;
-    if (r < a.m) {
-        const size_t sidx = (size_t)t * a.ns + s;
-        const double2 o = rbm_o(a, r, a.samples[sidx], a.tt + sidx * a.nh);
-        const double2 ob = a.obarc[(size_t)t * a.m + r];
-        re = o.x - ob.x;
-        im = o.y - ob.y;
-    }
-    uint16_t rh, rl, ih, il;
-    split_bf16(re, rh, rl);
-    split_bf16(im, ih, il);
+    const int t = blockIdx.z, st = blockIdx.x, n = a.n, nh = a.nh, wb = n + nh;
+    const int s0 = st * 32 + 8 * (threadIdx.x & 3);
+    const size_t sbase = (size_t)t * a.ns + s0;
+    const double2 *tts = a.tt + sbase * nh;
+    uint64_t mk[8];
+    for (int e = 0; e < 8; ++e) mk[e] = a.samples[sbase + e];
+    double2 tv[8];
+    int jc = -1;
     const int nst = a.ns / 32;
-    uint16_t *p = a.rbmP + ((size_t)(t * (a.mp / 128) + (r >> 7)) * nst + st) * RQ_CHUNK + (r & 127) * 32 + (s & 31);
-    p[0] = rh;
-    p[128 * 32] = rl;
-    p[2 * 128 * 32] = ih;
-    p[3 * 128 * 32] = il;
+    for (int sl = 0; sl < SPL_R; ++sl) {
+        const int r = (blockIdx.y * SPL_R + sl) * 64 + (threadIdx.x >> 2);
+        if (r >= a.mp) break;     // whole slices: Mp is a multiple of 128
+        double2 ob = make_double2(0.0, 0.0);
+        int wi = -1;
+        if (r < a.m) {
+            ob = a.obarc[(size_t)t * a.m + r];
+            if (r >= wb) {
+                wi = (r - wb) / nh;
+                const int j = (r - wb) % nh;
+                if (j != jc) {
+                    for (int e = 0; e < 8; ++e) tv[e] = tts[(size_t)e * nh + j];
+                    jc = j;
+                }
+            }
+        }
+        u16x8_t rh, rl, ih, il;
+        for (int e = 0; e < 8; ++e) {
+            double re = 0.0, im = 0.0;
+            if (r < a.m) {
+                double2 o;
+                if (wi >= 0) {
+                    const double si = spin(mk[e], wi);
+                    o = make_double2(si * tv[e].x, si * tv[e].y);
+                } else {
+                    o = rbm_o(a, r, mk[e], tts + (size_t)e * nh);
+                }
+                re = o.x - ob.x;
+                im = o.y - ob.y;
+            }
+            uint16_t h, l;
+            split_bf16(re, h, l);
+            rh[e] = h;
+            rl[e] = l;
+            split_bf16(im, h, l);
+            ih[e] = h;
+            il[e] = l;
+        }
+        uint16_t *p = a.rbmP + ((size_t)(t * (a.mp / 128) + (r >> 7)) * nst + st) * RQ_CHUNK + (r & 127) * 32 +
+                      8 * (threadIdx.x & 3);
+        *(u16x8_t *)p = rh;
+        *(u16x8_t *)(p + 128 * 32) = rl;
+        *(u16x8_t *)(p + 2 * 128 * 32) = ih;
+        *(u16x8_t *)(p + 3 * 128 * 32) = il;
+    }
 }
 
 __device__ __forceinline__ bf16x8_t neg_bf16x8(bf16x8_t v) {

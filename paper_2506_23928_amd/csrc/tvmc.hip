@@ -372,7 +372,7 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         hipLaunchKernelGGL(k_gbar, dim3(T), dim3(256), 0, c->stream, d);
         LAUNCHCHECK(c, "k_gbar");
         if (d.kind == TVMC_ANSATZ_RBM) {
-            hipLaunchKernelGGL(k_obar_D_rbm, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
+            hipLaunchKernelGGL(k_obar_D_rbm, dim3((d.m + 64 * OD_R - 1) / (64 * OD_R), T), dim3(256), 0, c->stream, d);
             LAUNCHCHECK(c, "k_obar_D_rbm");
         } else {
             hipLaunchKernelGGL(k_obar_D, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
@@ -402,7 +402,7 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         if (c->cfg.precision == TVMC_PREC_MFMA) {
             {
                 Scope sc(c, "transpose");
-                hipLaunchKernelGGL(k_rbm_split, dim3(d.ns / 32, d.mp / 8, T), dim3(256), 0, c->stream, d);
+                hipLaunchKernelGGL(k_rbm_split, dim3(d.ns / 32, (d.mp + 64 * SPL_R - 1) / (64 * SPL_R), T), dim3(256), 0, c->stream, d);
                 LAUNCHCHECK(c, "k_rbm_split");
             }
             Scope sc(c, "sbuild");
