@@ -35,14 +35,16 @@ struct Timer {
 
 }  // namespace
 
+constexpr int NSIDE = 2;   // side streams of the several-workgroup solves
+
 struct tvmc_ctx {
     Dev d{};
     hipStream_t stream = nullptr;
-    // two side streams (default priority) for the several-workgroup solves: each takes half
-    // of the trajectories, so one half's small diagonal and TRSM launches overlap the other
-    // half's panel updates; forked from and joined back into `stream` with events
-    hipStream_t side[2] = {nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    // NSIDE side streams (default priority) for the several-workgroup solves: each takes an
+    // equal share of the trajectories, so one share's small diagonal and TRSM launches overlap
+    // the others' panel updates; forked from and joined back into `stream` with events
+    hipStream_t side[NSIDE] = {};
+    hipEvent_t fork = nullptr, join[NSIDE] = {};
     tvmc_config cfg{};
     int step = 0, stage = 0, phase = 0, nobs = 0, adam_t = 0;
     int cpb = 1;
@@ -502,22 +504,22 @@ ZCholArgs sub_args(const ZCholArgs &a, int t0) {
                      a.linv + (size_t)t0 * chol_panels(a.m) * CN * CN, a.flags + t0, a.m};
 }
 
-// The two halves of the batch on the side streams, joined back into the context's stream.
+// The batch in min(T, NSIDE) contiguous shares on the side streams, joined back into the
+// context's stream.
 template <typename Args, bool CPLX>
 tvmc_status solve_split(tvmc_ctx *c, const Args &x) {
     const int T = c->d.nt;
-    if (T < 2 || !c->side[0]) return solve_sequence<Args, CPLX>(c, x, T, c->stream);
+    const int parts = T < NSIDE ? T : NSIDE;
+    if (parts < 2 || !c->side[0]) return solve_sequence<Args, CPLX>(c, x, T, c->stream);
     HIPCHECK(c, hipEventRecord(c->fork, c->stream));
-    const int half = T / 2;
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < parts; ++g) {
         HIPCHECK(c, hipStreamWaitEvent(c->side[g], c->fork, 0));
-        const int t0 = g ? half : 0, n = g ? T - half : half;
-        tvmc_status st = solve_sequence<Args, CPLX>(c, sub_args(x, t0), n, c->side[g]);
+        const int t0 = T * g / parts, t1 = T * (g + 1) / parts;
+        tvmc_status st = solve_sequence<Args, CPLX>(c, sub_args(x, t0), t1 - t0, c->side[g]);
         if (st != TVMC_OK) return st;
         HIPCHECK(c, hipEventRecord(c->join[g], c->side[g]));
     }
-    HIPCHECK(c, hipStreamWaitEvent(c->stream, c->join[0], 0));
-    HIPCHECK(c, hipStreamWaitEvent(c->stream, c->join[1], 0));
+    for (int g = 0; g < parts; ++g) HIPCHECK(c, hipStreamWaitEvent(c->stream, c->join[g], 0));
     return TVMC_OK;
 }
 
@@ -794,7 +796,7 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
             th[(size_t)t * m + k] = theta0 ? make_double2(theta0[2 * k], theta0[2 * k + 1]) : make_double2(0.0, 0.0);
     auto fail = [&](tvmc_status s) {
         snprintf(g_err, sizeof(g_err), "%s", ctx->err);
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < NSIDE; ++g) {
             if (ctx->side[g]) (void)hipStreamDestroy(ctx->side[g]);
             if (ctx->join[g]) (void)hipEventDestroy(ctx->join[g]);
         }
@@ -835,7 +837,7 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
         hipLaunchKernelGGL(k_ar_copy, dim3((d.ah * n + 255) / 256, T), dim3(256), 0, ctx->stream, d);
         INITCHECK(hipGetLastError());
     }
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < NSIDE; ++g) {
         INITCHECK(hipStreamCreateWithFlags(&ctx->side[g], hipStreamNonBlocking));
         INITCHECK(hipEventCreateWithFlags(&ctx->join[g], hipEventDisableTiming));
     }
@@ -1050,7 +1052,7 @@ const char *tvmc_last_error(const tvmc_ctx *c) { return c ? c->err : g_err; }
 tvmc_status tvmc_destroy(tvmc_ctx *c) {
     if (!c) return TVMC_E_INVAL;
     (void)hipStreamSynchronize(c->stream);
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < NSIDE; ++g) {
         if (c->side[g]) {
             (void)hipStreamSynchronize(c->side[g]);
             (void)hipStreamDestroy(c->side[g]);
