@@ -268,9 +268,9 @@ __device__ __forceinline__ float wave_sum_f(float v) {
     return v;
 }
 
-// The autoregressive walk over sites 0..N-1 that both draws s' ~ q and evaluates log q(s),
-// so that the two use bitwise the same q.  Lane k (and k + 64, ...) holds the pre-activation
-// a_k of hidden unit k; lane i holds the logit l_i of site i.  Hidden unit k has inputs j <
+// The autoregressive walk over sites 0..N-1 that draws s' ~ q together with log q(s')
+// (ar_logq evaluates log q of a given configuration with the same operations in the same
+// order).  Lane k (and k + 64, ...) holds the pre-activation a_k of hidden unit k; lane i holds the logit l_i of site i.  Hidden unit k has inputs j <
 // d(k) and outputs i >= d(k), so it is complete once site d(k) - 1 is known: at site ii the
 // units of degree ii (k = ii - 1 + c (N - 1)) add W2[i][k] relu(a_k) to the logits (the
 // masked weights W2[i][k], i < d(k), are exactly zero), site ii is decided from l_ii, and
@@ -321,9 +321,36 @@ __device__ __forceinline__ ArWalk ar_walk(int n, int h, const uint16_t *W1T, con
     return ArWalk{out, wave_sum_f(mylq)};
 }
 
-// log q(s) of the BF16 network for configuration mk (every lane returns the same value).
+// log q(s) of the BF16 network for a given configuration mk (every lane returns the same
+// value).  Nothing is decided on the way, so the pre-activations are formed first and the
+// logits afterwards, but with the walk's operations in the walk's order: each a_k adds the
+// input rows site by site, and each logit adds the hidden units in the order the walk
+// completes them (site ii = 1 .. N-1, units ii - 1 + c (N - 1)).  Units the walk adds after it
+// has read a logit, and rows it adds after a unit's last input, carry masked weights that are
+// exactly zero, so the result is the walk's log q bit for bit.
 __device__ __forceinline__ float ar_logq(const Dev &a, const ArNet &net, uint64_t mk, int lane) {
-    return ar_walk(a.n, a.ah, net.W1T, net.W2T, net.b1, net.b2, mk, 0.f, lane, 0).lq;
+    const int n = a.n, h = a.ah, nm1 = n > 1 ? n - 1 : 1, nq = (h + 63) >> 6;
+    float ak[4];
+    for (int q = 0; q < 4; ++q) ak[q] = (lane + 64 * q < h) ? net.b1[lane + 64 * q] : 0.f;
+    for (int ii = 0; ii < n; ++ii) {
+        const float sv = ((mk >> ii) & 1ull) ? 1.f : -1.f;
+        for (int q = 0; q < nq; ++q) {
+            const int k = lane + 64 * q;
+            ak[q] += (k < h ? bf2f(net.W1T[(size_t)ii * h + k]) : 0.f) * sv;
+        }
+    }
+    const int li = lane < n ? lane : n - 1;
+    float logit = lane < n ? net.b2[lane] : 0.f;
+    for (int ii = 1; ii < n; ++ii)
+        for (int k = ii - 1; k < h; k += nm1) {
+            const int q = k >> 6;
+            const float av = q == 0 ? ak[0] : q == 1 ? ak[1] : q == 2 ? ak[2] : ak[3];
+            const float hk = fmaxf(readlane_f(av, k & 63), 0.f);
+            logit += bf2f(net.W2T[(size_t)k * n + li]) * hk;
+        }
+    const float sv = ((mk >> li) & 1ull) ? 1.f : -1.f;
+    const float mylq = lane < n ? log_sigmoid_f(sv * logit) : 0.f;
+    return wave_sum_f(mylq);
 }
 
 // One independent proposal s' ~ q drawn autoregressively with the BF16 network (every lane
