@@ -104,21 +104,19 @@ __device__ __forceinline__ bf16x8_t neg_bf16x8(bf16x8_t v) {
 // (w >> 2, w & 3) takes rows 64 wr .. +63 and columns 32 wc .. +31 of the tile, 4x2 blocks of
 // 16x16 (64 FP32 accumulators), which keeps a wave under 256 registers so that two waves
 // share each SIMD and hide each other's LDS and MFMA latencies.  Per step of 32 samples the
-// workgroup stages the tile's row and column operands (4 planes x 128 rows x 32 samples each,
-// 64 KB) through double-buffered LDS, with the fragments of the next step read while the
-// products of the current one are issued (the pipeline is described at the main loop).  Rows
-// are padded to 40 BF16 (80 B), which keeps the 16-byte fragment reads of 16 consecutive rows
-// on distinct banks.  A fragment is 16 bytes per lane: row lane & 15, samples 8 (lane >> 4)
-// .. +7 of the step (the Gram product only needs the row and column operands to use the same
-// sample order).
+// workgroup copies the tile's row and column operands (4 planes x 128 rows x 32 samples each,
+// 64 KB) from global memory straight into double-buffered LDS (global_load_lds, no register
+// staging), with the fragments of the next step read while the products of the current one
+// are issued (the pipeline is described at the main loop).  A fragment is 16 bytes per lane:
+// row lane & 15, samples 8 (lane >> 4) .. +7 of the step (the Gram product only needs the row
+// and column operands to use the same sample order).
 constexpr int RQ_T = 128;
 constexpr int RQ_K = 32;          // samples per step
-constexpr int RQ_LD = 40;         // padded LDS row (BF16 elements)
-constexpr int RQ_BUF = 4 * RQ_T * RQ_LD;   // one staged matrix (40 KB)
 constexpr int RQ_THREADS = 512;
 constexpr int RQ_BAND = 4;        // tile rows per band of the work order
 __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
-    __shared__ uint16_t sbuf[2][2][RQ_BUF];    // [step parity][row / column operand], 160 KB
+    // [step parity][row / column operand][plane][128 rows][32 samples], 128 KB
+    __shared__ __attribute__((aligned(1024))) uint16_t sbuf[2][2][4 * RQ_T * RQ_K];
     // Work order.  Workgroups are dealt round-robin to the 8 XCDs, so workgroup L runs on XCD
     // L % 8; XCD x takes the contiguous run of work items x * per .. x * per + per - 1 in
     // turn, and the items of a trajectory are ordered in bands of RQ_BAND tile rows, column by
@@ -153,47 +151,28 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
     const int rr = lane & 15, kg = lane >> 4;
     const size_t ns = (size_t)a.ns, nst = ns / RQ_K;
     const uint16_t *Pt = a.rbmP + (size_t)t * (a.mp / RQ_T) * nst * RQ_CHUNK;
-    // staging: piece e = tid + 512 i (i < 4) of a step chunk is elements 8 e .. 8 e + 7, i.e.
-    // plane e / 512, row (e / 4) % 128, samples 8 (e % 4) .. +7; consecutive threads read
-    // consecutive 16 bytes
-    const uint16_t *gA[4], *gB[4];
-    int lofs[4];
-    for (int i = 0; i < 4; ++i) {
-        const int e = tid + RQ_THREADS * i, q = e >> 9, row = (e >> 2) & 127, part = e & 3;
-        gA[i] = Pt + (size_t)bi * nst * RQ_CHUNK + 8 * e;
-        gB[i] = Pt + (size_t)bj * nst * RQ_CHUNK + 8 * e;
-        lofs[i] = (q * RQ_T + row) * RQ_LD + 8 * part;
+    // LDS layout of a staged operand: [plane][128 rows][32 samples], rows of 64 bytes with the
+    // four 16-byte pieces of row r permuted by c -> c ^ ((r >> 2) & 3), which puts the 16-byte
+    // fragment reads of 16 consecutive rows on distinct banks.  The chunks are copied from
+    // global memory straight into LDS: wave instruction i (of 32 per operand and step) fills
+    // bytes 1024 i .. +1023, i.e. plane i / 8, rows 16 (i % 8) .. +15; lane L lands in row
+    // 16 (i % 8) + L / 4 at piece L % 4, so it reads the logical piece (L % 4) ^ ((row >> 2) & 3)
+    const uint16_t *gA = Pt + (size_t)bi * nst * RQ_CHUNK, *gB = Pt + (size_t)bj * nst * RQ_CHUNK;
+    int gofs[4];                                   // element offset in the chunk, per instruction
+    for (int j = 0; j < 4; ++j) {
+        const int i = w * 4 + j, q = i >> 3, row = (i & 7) * 16 + (lane >> 2);
+        gofs[j] = q * 4096 + row * 32 + (((lane & 3) ^ ((row >> 2) & 3)) * 8);
     }
-    // Pipeline: at the start of step k the fragments of step k are in registers, LDS buffer
-    // (k+1)&1 holds step k+1 and registers pa/pb hold step k+2.  Step k writes step k+2 into
-    // buffer k&1 (whose step-k contents were read into registers during step k-1), loads step
-    // k+3 into pa/pb, and issues its 12 products plane by plane, reloading each fragment plane
-    // from buffer (k+1)&1 as soon as its last product of step k has been issued; one barrier
-    // ends the step.
-    bf16x8_t pa[4], pb[4];
-    for (int i = 0; i < 4; ++i) {
-        pa[i] = *(const bf16x8_t *)gA[i];
-        pb[i] = *(const bf16x8_t *)gB[i];
+    typedef __attribute__((address_space(1))) void gvoid_t;
+    typedef __attribute__((address_space(3))) void lvoid_t;
+#define RQ_STAGE(BUF, STEP)                                                                     \
+    for (int j = 0; j < 4; ++j) {                                                               \
+        const int i = w * 4 + j;                                                                \
+        __builtin_amdgcn_global_load_lds((gvoid_t *)(gA + (size_t)(STEP) * RQ_CHUNK + gofs[j]),  \
+                                         (lvoid_t *)(sbuf[BUF][0] + i * 512), 16, 0, 0);       \
+        __builtin_amdgcn_global_load_lds((gvoid_t *)(gB + (size_t)(STEP) * RQ_CHUNK + gofs[j]),  \
+                                         (lvoid_t *)(sbuf[BUF][1] + i * 512), 16, 0, 0);       \
     }
-    for (int i = 0; i < 4; ++i) {
-        *(bf16x8_t *)(sbuf[0][0] + lofs[i]) = pa[i];
-        *(bf16x8_t *)(sbuf[0][1] + lofs[i]) = pb[i];
-    }
-    if (1 < nst) {
-        for (int i = 0; i < 4; ++i) {
-            pa[i] = *(const bf16x8_t *)(gA[i] + RQ_CHUNK);
-            pb[i] = *(const bf16x8_t *)(gB[i] + RQ_CHUNK);
-        }
-        for (int i = 0; i < 4; ++i) {
-            *(bf16x8_t *)(sbuf[1][0] + lofs[i]) = pa[i];
-            *(bf16x8_t *)(sbuf[1][1] + lofs[i]) = pb[i];
-        }
-    }
-    if (2 < nst)
-        for (int i = 0; i < 4; ++i) {
-            pa[i] = *(const bf16x8_t *)(gA[i] + 2 * RQ_CHUNK);
-            pb[i] = *(const bf16x8_t *)(gB[i] + 2 * RQ_CHUNK);
-        }
     f32x4_t sre[4][2], sim[4][2];
     for (int u = 0; u < 4; ++u)
         for (int v = 0; v < 2; ++v) {
@@ -201,10 +180,19 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
             sim[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         }
     const int arow = wr * 64 + rr, brow = wc * 32 + rr;
-#define RQ_LDA(BUF, Q) for (int u = 0; u < 4; ++u) A[u][Q] = *(const bf16x8_t *)(sbuf[BUF][0] + ((Q) * RQ_T + arow + 16 * u) * RQ_LD + 8 * kg);
-#define RQ_LDB(BUF, Q) for (int v = 0; v < 2; ++v) B[v][Q] = *(const bf16x8_t *)(sbuf[BUF][1] + ((Q) * RQ_T + brow + 16 * v) * RQ_LD + 8 * kg);
+#define RQ_SW(row) ((((kg) ^ (((row) >> 2) & 3))) * 8)
+#define RQ_LDA(BUF, Q) for (int u = 0; u < 4; ++u) A[u][Q] = *(const bf16x8_t *)(sbuf[BUF][0] + ((Q) * RQ_T + arow + 16 * u) * 32 + RQ_SW(arow + 16 * u));
+#define RQ_LDB(BUF, Q) for (int v = 0; v < 2; ++v) B[v][Q] = *(const bf16x8_t *)(sbuf[BUF][1] + ((Q) * RQ_T + brow + 16 * v) * 32 + RQ_SW(brow + 16 * v));
 #define RQ_TERM(ACC, AX, BX) for (int u = 0; u < 4; ++u) for (int v = 0; v < 2; ++v) ACC[u][v] = MFMA_BF16(AX, BX, ACC[u][v]);
+    // Pipeline: at the start of step k the fragments of step k are in registers and LDS buffer
+    // (k+1)&1 holds step k+1.  Step k copies step k+2 into buffer k&1 (whose step-k contents
+    // were read into registers during step k-1) and issues its 12 products plane by plane,
+    // reloading each fragment plane from buffer (k+1)&1 as soon as its last product of step k
+    // has been issued; the copy is waited for and one barrier ends the step.
+    RQ_STAGE(0, 0)
+    if (1 < nst) RQ_STAGE(1, 1)
     bf16x8_t A[4][4], B[2][4];
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (active) {
         RQ_LDA(0, 0) RQ_LDA(0, 1) RQ_LDA(0, 2) RQ_LDA(0, 3)
@@ -214,17 +202,7 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
     for (int k = 0; k < (int)nst; ++k) {
         const int wb = k & 1, rb = wb ^ 1;
         const bool more = k + 1 < (int)nst;
-        if (k + 2 < (int)nst) {
-            for (int i = 0; i < 4; ++i) {
-                *(bf16x8_t *)(sbuf[wb][0] + lofs[i]) = pa[i];
-                *(bf16x8_t *)(sbuf[wb][1] + lofs[i]) = pb[i];
-            }
-            if (k + 3 < (int)nst)
-                for (int i = 0; i < 4; ++i) {
-                    pa[i] = *(const bf16x8_t *)(gA[i] + (size_t)(k + 3) * RQ_CHUNK);
-                    pb[i] = *(const bf16x8_t *)(gB[i] + (size_t)(k + 3) * RQ_CHUNK);
-                }
-        }
+        if (k + 2 < (int)nst) RQ_STAGE(wb, k + 2)
         if (active) {
             //   Re += Ar.Br + Ai.Bi,  Im += Ar.Bi + Ai.(-Br), each as hi hi + hi lo + lo hi
             bf16x8_t NB[2][2];
@@ -249,8 +227,11 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
             RQ_TERM(sim, A[u][3], NB[v][0])
             if (more) { RQ_LDA(rb, 3) RQ_LDB(rb, 2) }
         }
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
+#undef RQ_STAGE
+#undef RQ_SW
 #undef RQ_LDA
 #undef RQ_LDB
 #undef RQ_TERM
