@@ -105,20 +105,21 @@ __global__ void k_ar_copy(Dev a) {
     if (e < (size_t)a.ah * a.n) ar_copy_one(a, t, e);
 }
 
-// Training forward/backward per sample (one wavefront per sample, lanes over hidden units and
-// sites).  Writes log q, the hidden activations h, g = d(loss)/d(logits) and da = d(loss)/da.
+// Training forward/backward per sample (a wavefront takes AR_SB samples at a time, lanes over
+// hidden units and sites).  Writes log q, the hidden activations h, g = d(loss)/d(logits) and da = d(loss)/da.
 // A workgroup takes AR_SAMPLES samples of one trajectory and first stages that trajectory's
 // FP32 weights in LDS with the masks applied (masked entries exactly zero, so the loops run
 // over all inputs without degree tests): W1 as [k][j] with rows padded to N + 1 and W2 as
 // [i][k] with rows padded to H + 1, which keeps every loop below on distinct banks.
-constexpr int AR_WAVES = 4;
-constexpr int AR_SAMPLES = 64;
+constexpr int AR_WAVES = 8;
+constexpr int AR_SAMPLES = 128;
+constexpr int AR_SB = 4;          // samples per wavefront pass: each weight read serves four
 __global__ __launch_bounds__(64 * AR_WAVES) void k_ar_forward(Dev a, int want_grad) {
     __shared__ float sW1[AR_LDS_W + 256];     // [k][j], row stride N + 1
     __shared__ float sW2[AR_LDS_W + 64];      // [i][k], row stride H + 1
     __shared__ float sb1[256], sb2[64];
-    __shared__ float hs[AR_WAVES][256];
-    __shared__ float gs[AR_WAVES][64];
+    __shared__ float hs[AR_WAVES][AR_SB][256];
+    __shared__ float gs[AR_WAVES][AR_SB][64];
     const int t = blockIdx.y, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = a.n, h = a.ah, s1 = n + 1, s2 = h + 1;
     const ArView p = ar_view(a.arP + (size_t)t * a.arnp, n, h);
@@ -134,43 +135,68 @@ __global__ __launch_bounds__(64 * AR_WAVES) void k_ar_forward(Dev a, int want_gr
     for (int i = threadIdx.x; i < n; i += blockDim.x) sb2[i] = p.b2[i];
     __syncthreads();
     const int s_end = min(a.ns, (int)(blockIdx.x + 1) * AR_SAMPLES);
-    for (int s = blockIdx.x * AR_SAMPLES + w; s < s_end; s += AR_WAVES) {
-        const uint64_t mk = a.samples[(size_t)t * a.ns + s];
-        float av[4];
+    for (int s0 = blockIdx.x * AR_SAMPLES + w * AR_SB; s0 < s_end; s0 += AR_WAVES * AR_SB) {
+        uint64_t mk[AR_SB];
+        for (int b = 0; b < AR_SB; ++b) mk[b] = s0 + b < s_end ? a.samples[(size_t)t * a.ns + s0 + b] : 0ull;
+        // per sample, the same multiply-adds in the same order as one sample at a time
+        float av[4][AR_SB];
         for (int q = 0; q < 4; ++q) {
             const int k = lane + 64 * q;
-            av[q] = 0.f;
+            for (int b = 0; b < AR_SB; ++b) av[q][b] = 0.f;
             if (k < h) {
-                float x = sb1[k];
-                for (int j = 0; j < n; ++j) x += sW1[k * s1 + j] * (float)spin(mk, j);
-                av[q] = x;
-                hs[w][k] = fmaxf(x, 0.f);
+                float x[AR_SB];
+                for (int b = 0; b < AR_SB; ++b) x[b] = sb1[k];
+                for (int j = 0; j < n; ++j) {
+                    const float wv = sW1[k * s1 + j];
+                    for (int b = 0; b < AR_SB; ++b) x[b] += wv * (float)spin(mk[b], j);
+                }
+                for (int b = 0; b < AR_SB; ++b) {
+                    av[q][b] = x[b];
+                    hs[w][b][k] = fmaxf(x[b], 0.f);
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
-        float lq = 0.f, gi = 0.f;
+        float lq[AR_SB], gi[AR_SB];
+        for (int b = 0; b < AR_SB; ++b) lq[b] = gi[b] = 0.f;
         if (lane < n) {
-            float l = sb2[lane];
-            for (int k = 0; k < h; ++k) l += sW2[lane * s2 + k] * hs[w][k];
-            const float si = (float)spin(mk, lane);
-            lq = log_sigmoid_f(si * l);
-            // d(-log sigmoid(s l))/dl / B
-            gi = -si * expf(log_sigmoid_f(-si * l)) / (float)a.ns;
-            gs[w][lane] = gi;
+            float l[AR_SB];
+            for (int b = 0; b < AR_SB; ++b) l[b] = sb2[lane];
+            for (int k = 0; k < h; ++k) {
+                const float wv = sW2[lane * s2 + k];
+                for (int b = 0; b < AR_SB; ++b) l[b] += wv * hs[w][b][k];
+            }
+            for (int b = 0; b < AR_SB; ++b) {
+                const float si = (float)spin(mk[b], lane);
+                lq[b] = log_sigmoid_f(si * l[b]);
+                // d(-log sigmoid(s l))/dl / B
+                gi[b] = -si * expf(log_sigmoid_f(-si * l[b])) / (float)a.ns;
+                gs[w][b][lane] = gi[b];
+            }
         }
         __builtin_amdgcn_wave_barrier();
-        lq = (float)wave_sum((double)lq);
-        if (lane == 0) a.arlogq[(size_t)t * a.ns + s] = lq;
+        for (int b = 0; b < AR_SB; ++b) {
+            const float lqs = (float)wave_sum((double)lq[b]);
+            if (lane == 0 && s0 + b < s_end) a.arlogq[(size_t)t * a.ns + s0 + b] = lqs;
+        }
         if (want_grad) {
-            const size_t sb = (size_t)t * a.ns + s;
-            if (lane < n) a.arg[sb * n + lane] = gi;
+            for (int b = 0; b < AR_SB; ++b)
+                if (lane < n && s0 + b < s_end) a.arg[((size_t)t * a.ns + s0 + b) * n + lane] = gi[b];
             for (int q = 0; q < 4; ++q) {
                 const int k = lane + 64 * q;
                 if (k >= h) continue;
-                float dh = 0.f;
-                for (int i = 0; i < n; ++i) dh += gs[w][i] * sW2[i * s2 + k];
-                a.arh[sb * h + k] = hs[w][k];
-                a.arda[sb * h + k] = av[q] > 0.f ? dh : 0.f;
+                float dh[AR_SB];
+                for (int b = 0; b < AR_SB; ++b) dh[b] = 0.f;
+                for (int i = 0; i < n; ++i) {
+                    const float wv = sW2[i * s2 + k];
+                    for (int b = 0; b < AR_SB; ++b) dh[b] += gs[w][b][i] * wv;
+                }
+                for (int b = 0; b < AR_SB; ++b) {
+                    if (s0 + b >= s_end) continue;
+                    const size_t sb = (size_t)t * a.ns + s0 + b;
+                    a.arh[sb * h + k] = hs[w][b][k];
+                    a.arda[sb * h + k] = av[q][b] > 0.f ? dh[b] : 0.f;
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
