@@ -43,13 +43,14 @@ class _Config(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_int32), ("n_chains", ctypes.c_int32), ("burn_sweeps", ctypes.c_int32),
                 ("thin_sweeps", ctypes.c_int32), ("init_sweeps", ctypes.c_int32), ("enumerate", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("diag_shift", ctypes.c_double), ("scheme", ctypes.c_int32),
-                ("n_steps", ctypes.c_int32), ("obs_every", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("n_steps", ctypes.c_int32), ("obs_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("linear", ctypes.c_int32)]
 
 
 class _EvalOut(ctypes.Structure):
     _fields_ = [("samples", _c_i8p), ("eloc", _c_dp), ("S", _c_dp), ("F", _c_dp), ("Nn", _c_dp), ("D", _c_dp),
                 ("bmean", _c_dp), ("obar", _c_dp), ("delta", _c_dp), ("accepts", _c_i64p), ("obs", _c_dp),
-                ("seconds", _c_dp)]
+                ("seconds", _c_dp), ("dlognorm", _c_dp)]
 
 
 def build(force: bool = True) -> str:
@@ -180,14 +181,14 @@ def local_quantities(kind, n, n_hidden, theta, sigma, two_flip=True):
 
 class Config:
     def __init__(self, n_samples=1024, n_chains=16, burn_sweeps=2, thin_sweeps=1, init_sweeps=0, enumerate=False,
-                 dt=0.01, diag_shift=1e-4, scheme=HEUN, n_steps=1, obs_every=0, seed=0):
+                 dt=0.01, diag_shift=1e-4, scheme=HEUN, n_steps=1, obs_every=0, seed=0, linear=False):
         self.__dict__.update(locals())
         del self.__dict__["self"]
 
     def _c(self):
         return _Config(self.n_samples, self.n_chains, self.burn_sweeps, self.thin_sweeps, self.init_sweeps,
                        int(bool(self.enumerate)), self.dt, self.diag_shift, self.scheme, self.n_steps,
-                       self.obs_every, ctypes.c_uint64(self.seed))
+                       self.obs_every, ctypes.c_uint64(self.seed), int(bool(self.linear)))
 
 
 def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, chains, traj=0, step=0, stage=0,
@@ -211,14 +212,15 @@ def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, cha
         "Nn": np.zeros((max(nch, 1), m), np.complex128), "D": np.zeros(m, np.complex128),
         "bmean": np.zeros(max(nch, 1), np.complex128), "obar": np.zeros(m, np.complex128),
         "delta": np.zeros(m, np.complex128), "accepts": np.zeros(max(cfg.n_chains, 1), np.int64),
-        "obs": np.zeros(9), "seconds": np.zeros(3),
+        "obs": np.zeros(9), "seconds": np.zeros(3), "dlognorm": np.zeros(1),
     }
     eo = _EvalOut(_p(r["samples"], _c_i8p), _p(r["eloc"].view(np.float64), _c_dp),
                   _p(r["S"].view(np.float64), _c_dp), _p(r["F"].view(np.float64), _c_dp),
                   _p(r["Nn"].view(np.float64), _c_dp), _p(r["D"].view(np.float64), _c_dp),
                   _p(r["bmean"].view(np.float64), _c_dp), _p(r["obar"].view(np.float64), _c_dp),
                   _p(r["delta"].view(np.float64), _c_dp), _p(r["accepts"], _c_i64p),
-                  _p(r["obs"], _c_dp) if want_moments else None, _p(r["seconds"], _c_dp))
+                  _p(r["obs"], _c_dp) if want_moments else None, _p(r["seconds"], _c_dp),
+                  _p(r["dlognorm"], _c_dp))
     ch = chains if chains is not None else np.zeros((1, n), np.int8)
     assert ch.dtype == np.int8 and ch.flags.c_contiguous
     pc = problem._c()
@@ -226,6 +228,7 @@ def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, cha
                         ctypes.c_int32(traj), ctypes.c_int32(step), ctypes.c_int32(stage), ctypes.c_int32(int(first)),
                         _p(dwa, _c_dp), ctypes.c_int32(int(want_solve)), ctypes.byref(eo))
     r["status"] = st
+    r["dlognorm"] = float(r["dlognorm"][0])
     r["Nn"] = r["Nn"][:nch]
     r["bmean"] = r["bmean"][:nch]
     return r
@@ -236,7 +239,8 @@ def run(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta0, n_traj:
     """Integrate n_traj trajectories; returns (theta [n_traj, M], moments [n_traj, n_out, 9], status).
 
     ``status`` is 0 when every trajectory finished; the per-trajectory codes are kept in
-    ``run.last_status``.  A failed trajectory's later moments are NaN."""
+    ``run.last_status``.  A failed trajectory's later moments are NaN.  For the linear SSE
+    (cfg.linear) ``run.last_lognorm`` [n_traj, n_out] holds log Q at the output times."""
     m = n_params(kind, problem.n, n_hidden)
     n_out = cfg.n_steps // cfg.obs_every + 1 if cfg.obs_every > 0 else 0
     th = np.zeros((n_traj, m), np.complex128)
@@ -245,22 +249,29 @@ def run(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta0, n_traj:
     a = _Ansatz(kind, n_hidden)
     t0 = _theta2(theta0)
     pc = problem._c()
+    lq = np.zeros((n_traj, max(n_out, 1)))
     st = lib().orc_run(ctypes.byref(pc), ctypes.byref(a), ctypes.byref(cfg._c()), _p(t0, _c_dp),
                        ctypes.c_int32(n_traj), ctypes.c_int32(traj0), ctypes.c_int32(n_threads),
-                       _p(th.view(np.float64), _c_dp), _p(obs, _c_dp), _p(stat, _c_i32p))
+                       _p(th.view(np.float64), _c_dp), _p(obs, _c_dp), _p(stat, _c_i32p), _p(lq, _c_dp))
     run.last_status = stat
+    run.last_lognorm = lq[:, :n_out]
     return th, obs[:, :n_out], st
 
 
-def ensemble(moments: np.ndarray, n: int):
+def ensemble(moments: np.ndarray, n: int, weights=None):
     """Trajectory average (Eq. 3) of per-trajectory moments -> (M [3], C [3,3], xi^2).
 
     moments[..., :] = (mx, my, mz, sxx, syy, szz, sxy, sxz, syz) per trajectory, with
     s_ab = (1/2)<{M_a, M_b}>.  C_ab = avg s_ab - M_a M_b, so the spread between trajectories is
     part of C.  xi^2 = N min_perp Var(M_perp) / |M|^2 (observables paragraph of the LITF
-    section): the smaller eigenvalue of C restricted to the plane orthogonal to M."""
+    section): the smaller eigenvalue of C restricted to the plane orthogonal to M.
+    weights [n_traj, ...] (the norms Q_j of the linear SSE): the weighted average of App. B,
+    (1/N_T) sum_j <A>_j Q_j, in place of the plain mean."""
     mo = np.asarray(moments, dtype=np.float64)
-    avg = mo.mean(axis=0)
+    if weights is None:
+        avg = mo.mean(axis=0)
+    else:
+        avg = (mo * np.asarray(weights, dtype=np.float64)[..., None]).mean(axis=0)
     M = avg[..., 0:3]
     s = np.zeros(avg.shape[:-1] + (3, 3))
     s[..., 0, 0], s[..., 1, 1], s[..., 2, 2] = avg[..., 3], avg[..., 4], avg[..., 5]

@@ -290,30 +290,56 @@ def sse_strat_drift_diff(psi, H, Ls):
     return a, bs
 
 
-def sse_path(psi0, H, Ls, dws, dt, scheme="heun"):
+def sse_lin_ito_drift_diff(psi, H, Ls):
+    """Drift and diffusion of the linear Ito SSE (App. B): no expectation values anywhere."""
+    a = -1j * (H @ psi)
+    bs = []
+    for L in Ls:
+        Lp = L @ psi
+        a = a - 0.5 * (L.conj().T @ Lp)
+        bs.append(Lp)
+    return a, bs
+
+
+def sse_lin_strat_drift_diff(psi, H, Ls):
+    """Drift -i H_eff^{Strat,lin} psi and diffusion L psi of the linear Stratonovich SSE (App. B)."""
+    a = -1j * (H @ psi)
+    bs = []
+    for L in Ls:
+        Lp = L @ psi
+        a = a - 0.5 * (L.conj().T @ Lp + L @ Lp)
+        bs.append(Lp)
+    return a, bs
+
+
+def sse_path(psi0, H, Ls, dws, dt, scheme="heun", linear=False):
     """Integrate one trajectory given the Wiener increments dws[step, channel].
 
-    scheme: 'ito_em' (Euler-Maruyama on Eq. 2), 'heun' (trapezoidal predictor-corrector on
-    Eq. 4), 'midpoint' (midpoint predictor-corrector on Eq. 4), 'strat_em' (Euler on Eq. 4,
-    not Stratonovich-consistent)."""
+    scheme: 'ito_em' (Euler-Maruyama on the Ito form), 'heun' (trapezoidal predictor-corrector
+    on the Stratonovich form), 'midpoint' (midpoint predictor-corrector on the Stratonovich
+    form), 'strat_em' (Euler on the Stratonovich form, not Stratonovich-consistent).
+    linear=False: the nonlinear SSE (Ito Eq. 2, Stratonovich Eqs. 4-5); linear=True: the
+    linear SSE of App. B, whose paths do not keep their norm."""
+    ito = sse_lin_ito_drift_diff if linear else sse_ito_drift_diff
+    strat = sse_lin_strat_drift_diff if linear else sse_strat_drift_diff
     psi = np.array(psi0, dtype=np.complex128)
     out = [psi.copy()]
     for dw in dws:
         if scheme == "ito_em":
-            a, bs = sse_ito_drift_diff(psi, H, Ls)
+            a, bs = ito(psi, H, Ls)
             psi = psi + a * dt + sum(b * w for b, w in zip(bs, dw))
         else:
-            a, bs = sse_strat_drift_diff(psi, H, Ls)
+            a, bs = strat(psi, H, Ls)
             inc0 = a * dt + sum(b * w for b, w in zip(bs, dw))
             if scheme == "strat_em":
                 psi = psi + inc0
             elif scheme == "heun":
                 pb = psi + inc0
-                a1, b1 = sse_strat_drift_diff(pb, H, Ls)
+                a1, b1 = strat(pb, H, Ls)
                 psi = psi + 0.5 * (inc0 + a1 * dt + sum(b * w for b, w in zip(b1, dw)))
             elif scheme == "midpoint":
                 pm = psi + 0.5 * inc0
-                a1, b1 = sse_strat_drift_diff(pm, H, Ls)
+                a1, b1 = strat(pm, H, Ls)
                 psi = psi + a1 * dt + sum(b * w for b, w in zip(b1, dw))
             else:
                 raise ValueError(scheme)

@@ -60,6 +60,7 @@ typedef struct {
     int32_t scheme;        /* ORC_HEUN, ORC_MIDPOINT, ORC_EULER (negative control) */
     int32_t n_steps, obs_every;
     uint64_t seed;
+    int32_t linear;        /* 1: the linear SSE of App. B (E_eff^lin, norm SDE, weighted averages) */
 } orc_config;
 
 typedef struct {           /* optional outputs of one evaluation (any pointer may be NULL) */
@@ -75,6 +76,7 @@ typedef struct {           /* optional outputs of one evaluation (any pointer ma
     int64_t *accepts;      /* [n_chains] */
     double *obs;           /* [9] per-trajectory moments (see orc_moments) */
     double *seconds;       /* [3] wall time of: sampling and local quantities; means, S, F, N^n, D; solve */
+    double *dlognorm;      /* [1] linear SSE: increment of log Q over the step (App. B, norm SDE) */
 } orc_eval_out;
 
 /* ------------------------------------------------------------------ Philox4x32-10 */
@@ -541,15 +543,26 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
             for (int x = 0; x < ns; ++x) v += wgt[x] * B[(size_t)c * ns + x];
             bm[c] = v * norm;
         }
-        /* E_eff(x) = E_H(x) - (i/2) sum_n [ (L^dag L)_loc - 2 <L+L^dag> B^n + (L^2)_loc ] */
+        /* E_eff(x) = E_H(x) - (i/2) sum_n [ (L^dag L)_loc - 2 <L+L^dag> B^n + (L^2)_loc ];
+         * for the linear SSE (App. B) E_eff^lin(x) = E_H(x) - (i/2) sum_n [ (L^dag L)_loc + (L^2)_loc ],
+         * the Stratonovich H_eff of the linear equation, which has no <L+L^dag> term */
         cplx eb = 0.0;
         for (int x = 0; x < ns; ++x) {
             cplx drive = 0.0;
-            for (int c = 0; c < nch; ++c) drive += 2.0 * (2.0 * creal(bm[c])) * B[(size_t)c * ns + x];
+            if (!cf->linear)
+                for (int c = 0; c < nch; ++c) drive += 2.0 * (2.0 * creal(bm[c])) * B[(size_t)c * ns + x];
             eeff[x] = eh[x] - 0.5 * I * (ll[x] - drive);
             eb += wgt[x] * eeff[x];
         }
         eb *= norm;
+        /* norm SDE of App. B: dQ = Q (2 Im<E_eff^lin> dt + 2 sum_n Re<B^n> o dW_n), i.e. in
+         * log Q the increment 2 Im<E_eff^lin> dt + 2 sum_n Re<B^n> dW_n at this evaluation point;
+         * the nonlinear SSE keeps the norm, Q = 1 */
+        if (out && out->dlognorm) {
+            double dq = 2.0 * cimag(eb) * cf->dt;
+            for (int c = 0; c < nch; ++c) dq += 2.0 * creal(bm[c]) * dw[c];
+            out->dlognorm[0] = cf->linear ? dq : 0.0;
+        }
         /* S_kl = <O_k^* O_l> - <O_k^*><O_l>;  F_k = <O_k^* E_eff> - <O_k^*><E_eff>;
          * N^n_k = <O_k^* B^n> - <O_k^*><B^n>  (definitions after Eq. 8) */
         for (int k = 0; k < m; ++k) {
@@ -660,6 +673,7 @@ typedef struct {
     double *theta_out;     /* [n_traj][M][2] */
     double *obs_out;       /* [n_traj][n_out][9] */
     int32_t *status_out;   /* [n_traj] */
+    double *lognorm_out;   /* [n_traj][n_out] log Q at the output times (may be NULL) */
     int next;
     pthread_mutex_t lock;
 } run_job;
@@ -672,7 +686,7 @@ typedef struct {
  * Observables come from the predictor samples at steps that are multiples of obs_every,
  * and from one extra sampling pass after the last step. */
 static int run_one(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, const double *theta0,
-                   int traj, double *th_out, double *obs_out)
+                   int traj, double *th_out, double *obs_out, double *lq_out)
 {
     int n = pb->n, m = orc_n_params(an, n), nch = pb->n_ch;
     double *th = malloc(sizeof(double) * 2 * m), *te = malloc(sizeof(double) * 2 * m);
@@ -682,27 +696,38 @@ static int run_one(const orc_problem *pb, const orc_ansatz *an, const orc_config
     memcpy(th, theta0, sizeof(double) * 2 * m);
     if (!cf->enumerate) orc_init_chains(cf->seed, traj, n, cf->n_chains, chains);
     int st = ORC_OK, iout = 0;
+    /* log Q of the linear SSE, integrated by the same scheme as theta (the norm SDE is in
+     * Stratonovich form); Q = 1 at t = 0 */
+    double lq = 0.0, q0 = 0.0, q1 = 0.0;
     for (int step = 0; step < cf->n_steps && st == ORC_OK; ++step) {
         orc_draw_dw(cf->seed, traj, step, nch, cf->dt, dw);
         orc_eval_out o0 = {0};
         o0.delta = d0;
-        if (cf->obs_every > 0 && step % cf->obs_every == 0) o0.obs = obs_out + 9 * (size_t)iout++;
+        o0.dlognorm = &q0;
+        if (cf->obs_every > 0 && step % cf->obs_every == 0) {
+            if (lq_out) lq_out[iout] = lq;
+            o0.obs = obs_out + 9 * (size_t)iout++;
+        }
         st = orc_eval(pb, an, cf, th, chains, traj, step, 0, step == 0, dw, 1, &o0);
         if (st) break;
         if (cf->scheme == ORC_EULER) {
             for (int k = 0; k < 2 * m; ++k) th[k] = th[k] + d0[k];
+            lq += q0;
             continue;
         }
         for (int k = 0; k < 2 * m; ++k) te[k] = (cf->scheme == ORC_HEUN) ? th[k] + d0[k] : th[k] + 0.5 * d0[k];
         orc_eval_out o1 = {0};
         o1.delta = d1;
+        o1.dlognorm = &q1;
         st = orc_eval(pb, an, cf, te, chains, traj, step, 1, 0, dw, 1, &o1);
         if (st) break;
         for (int k = 0; k < 2 * m; ++k)
             th[k] = (cf->scheme == ORC_HEUN) ? th[k] + 0.5 * (d0[k] + d1[k]) : th[k] + d1[k];
+        lq += (cf->scheme == ORC_HEUN) ? 0.5 * (q0 + q1) : q1;
     }
     if (st == ORC_OK && cf->obs_every > 0) {
         orc_eval_out o = {0};
+        if (lq_out) lq_out[iout] = lq;
         o.obs = obs_out + 9 * (size_t)iout;
         st = orc_eval(pb, an, cf, th, chains, traj, cf->n_steps, 0, cf->n_steps == 0, dw, 0, &o);
     }
@@ -722,17 +747,21 @@ static void *run_worker(void *arg)
         pthread_mutex_unlock(&jb->lock);
         if (t >= jb->n_traj) break;
         jb->status_out[t] = run_one(jb->pb, jb->an, jb->cf, jb->theta0, jb->traj0 + t,
-                                    jb->theta_out + (size_t)t * 2 * m, jb->obs_out + (size_t)t * n_out * 9);
+                                    jb->theta_out + (size_t)t * 2 * m, jb->obs_out + (size_t)t * n_out * 9,
+                                    jb->lognorm_out ? jb->lognorm_out + (size_t)t * n_out : NULL);
     }
     return NULL;
 }
 
-/* Run n_traj independent trajectories (ids traj0 .. traj0+n_traj-1) on n_threads threads. */
+/* Run n_traj independent trajectories (ids traj0 .. traj0+n_traj-1) on n_threads threads;
+ * lognorm_out (may be NULL) receives log Q at the output times (zero unless cf->linear). */
 int orc_run(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, const double *theta0,
-            int32_t n_traj, int32_t traj0, int32_t n_threads, double *theta_out, double *obs_out, int32_t *status_out)
+            int32_t n_traj, int32_t traj0, int32_t n_threads, double *theta_out, double *obs_out, int32_t *status_out,
+            double *lognorm_out)
 {
     if (cf->obs_every > 0 && cf->n_steps % cf->obs_every) return ORC_E_INVAL;
-    run_job jb = {pb, an, cf, theta0, n_traj, traj0, theta_out, obs_out, status_out, 0, PTHREAD_MUTEX_INITIALIZER};
+    run_job jb = {pb, an, cf, theta0, n_traj, traj0, theta_out, obs_out, status_out, lognorm_out, 0,
+                  PTHREAD_MUTEX_INITIALIZER};
     if (n_threads < 1) n_threads = 1;
     pthread_t *tid = malloc(sizeof(pthread_t) * n_threads);
     for (int i = 0; i < n_threads; ++i) pthread_create(&tid[i], NULL, run_worker, &jb);
