@@ -100,7 +100,16 @@ typedef struct {
     int32_t ar_train_iters;       /* Adam steps per training */
     double ar_lr;                 /* Adam learning rate */
     int32_t solver;               /* TVMC_SOLVER_*: how the regularised system is solved */
+    int32_t unravelling;          /* TVMC_SSE_*: which stochastic Schroedinger equation is unravelled */
 } tvmc_config;
+
+/* NONLINEAR: the norm-preserving SSE of Eq. 2 (Stratonovich form Eqs. 4-5).  LINEAR: the linear
+ * SSE of App. B: E_eff becomes the local value of H - (i/2) sum_n (L_n^dag L_n + L_n^2) (no
+ * <L + L^dag> drive, so F^lin = F - i sum_n <L_n + L_n^dag> N^n), and every trajectory also
+ * carries log Q, Q = e^{phi + phi*} <psi_theta|psi_theta>, integrated by the step's own scheme
+ * from dQ = Q (2 Im<E_eff^lin> dt + 2 sum_n Re<B^n> o dW_n); trajectory averages are then
+ * weighted, (1/N_T) sum_j <A>_j Q_j.  log Q starts at 0 (Q = 1). */
+enum { TVMC_SSE_NONLINEAR = 0, TVMC_SSE_LINEAR = 1 };
 
 enum { TVMC_PROPOSAL_FLIP = 0, TVMC_PROPOSAL_LEARNED = 1 };
 /* FP64 Cholesky of S + eps I: one workgroup per trajectory (one launch per solve), or several
@@ -136,7 +145,9 @@ enum {
     TVMC_Q_AR_GRAD = 16,    /* float[P] gradient of the mean negative log-likelihood */
     TVMC_Q_AR_LOGQ = 17,    /* float[n_samples] log q of the last samples */
     TVMC_Q_AR_LOSS = 18,    /* double[1] mean negative log-likelihood */
-    TVMC_Q_AR_ACCEPTS = 19  /* uint32[n_chains] accepted learned proposals in the last sampling */
+    TVMC_Q_AR_ACCEPTS = 19, /* uint32[n_chains] accepted learned proposals in the last sampling */
+    TVMC_Q_LOGNORM = 20,    /* double[1] log Q of the linear SSE at the current step (0 for the nonlinear SSE) */
+    TVMC_Q_LOGNORM_HIST = 21  /* double[n_obs_max] log Q at the times of the moment history */
 };
 
 /* Bytes of device workspace needed for this problem, ansatz and configuration. */
@@ -180,7 +191,9 @@ tvmc_status tvmc_train_proposal(tvmc_ctx *ctx, int32_t n_iters);
  * section); copies double[n_traj][9] to moments_out when it is not NULL. */
 tvmc_status tvmc_observables(tvmc_ctx *ctx, double *moments_out);
 /* Trajectory average (Eq. 3) of the last moments: out[0..2] = M, out[3..11] = C (row-major),
- * out[12] = xi^2 (Wineland, minimum over the plane orthogonal to M). */
+ * out[12] = xi^2 (Wineland, minimum over the plane orthogonal to M).  For the linear SSE the
+ * average is App. B's weighted one, each trajectory's moments times its Q at the time they were
+ * taken, divided by N_T. */
 tvmc_status tvmc_ensemble(tvmc_ctx *ctx, double *out);
 /* Copy a quantity (TVMC_Q_*) of one trajectory to host memory of at least `bytes` bytes. */
 tvmc_status tvmc_get(tvmc_ctx *ctx, int32_t what, int32_t traj, void *host_out, size_t bytes);

@@ -137,6 +137,12 @@ struct Dev {
     double *ens;              // [16]
     int *flags;               // [T]
     int mom_blocks;
+    // linear SSE (App. B): no <L+L^dag> drive in E_eff; log Q per trajectory
+    int linear;
+    double *lognorm;          // [T] log Q at the current step
+    double *dq0;              // [T] predictor-stage increment of log Q
+    double *momlq;            // [T] log Q when the moments in mom were taken
+    double *qhist;            // [nobs][T] log Q at the history records
     // learned proposal (MADE): hidden width, parameter count per trajectory, buffers
     int ar, ah;
     size_t arnp;

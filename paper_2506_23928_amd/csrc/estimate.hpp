@@ -5,7 +5,9 @@
 //   (L^+L)_loc + (L^2)_loc:          sigma^- -> g [s_i=+1], sigma^+ -> g [s_i=-1], sigma^z -> 2g
 //   E_eff(x) = E_H(x) - (i/2) sum_n [ (L^+L)_loc - 2 <L+L^+> B^n + (L^2)_loc ]    (Eq. 5)
 // with <L+L^+> = 2 Re <B^n> estimated from the same samples, the c-number terms of Eq. 5
-// dropped (they cancel in every covariance).  The increment vector of the regularised solve
+// dropped (they cancel in every covariance).  The linear SSE (App. B) drops the drive term:
+// E_eff^lin(x) = E_H(x) - (i/2) sum_n [ (L^+L)_loc + (L^2)_loc ], which has no c-number terms,
+// so <G> = -i dt <E_eff^lin> + sum_n <B^n> dW_n and 2 Re <G> is the increment of log Q.  The increment vector of the regularised solve
 // is D = -i F dt + sum_n N^n dW_n = cov(O*, G) with G(x) = -i dt E_eff(x) + sum_n B^n(x) dW_n,
 // so one covariance replaces F and every N^n.
 #pragma once
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(256) void k_build_G(Dev a) {
         srate[ch] = a.jrate[t * a.r_stride + ch];
         ssq[ch] = sqrt(a.jrate[t * a.r_stride + ch]);
         sdw[ch] = a.dw[(size_t)t * a.nch + ch];
-        sc[ch] = 2.0 * (2.0 * a.bmean[(size_t)t * a.nch + ch].x);
+        sc[ch] = a.linear ? 0.0 : 2.0 * (2.0 * a.bmean[(size_t)t * a.nch + ch].x);
     }
     __syncthreads();
     const int s = blockIdx.x * blockDim.x + threadIdx.x;

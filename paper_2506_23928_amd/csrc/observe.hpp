@@ -8,9 +8,16 @@ namespace tvmc {
 
 // stage 0: theta_eval = theta + d0 (Heun) or theta + d0/2 (midpoint)
 // stage 1: theta = theta + (d0 + d1)/2 (Heun) or theta + d1 (midpoint)
+// Linear SSE: log Q by the same scheme, its increment at an evaluation point being 2 Re <G>
+// (the norm SDE of App. B in Stratonovich form, so the chain rule holds for log Q).
 __global__ void k_update(Dev a, int stage) {
     const int t = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a.linear && k == 0) {
+        const double q = 2.0 * a.gbar[t].x;
+        if (stage == 0) a.dq0[t] = q;
+        else a.lognorm[t] += a.scheme == 0 ? 0.5 * (a.dq0[t] + q) : q;
+    }
     if (k >= a.m) return;
     const size_t i = (size_t)t * a.m + k;
     const double2 th = a.theta[i], d0 = a.d0[i];
@@ -107,15 +114,21 @@ __global__ void k_moments_reduce(Dev a, int slot) {
         a.mom[(size_t)t * 9 + q] = s;
         if (slot >= 0) a.hist[((size_t)slot * a.nt + t) * 9 + q] = s;
     }
+    a.momlq[t] = a.lognorm[t];
+    if (slot >= 0) a.qhist[(size_t)slot * a.nt + t] = a.lognorm[t];
 }
 
 // Trajectory average (Eq. 3) -> M, C, xi^2 = N lambda_min(C restricted to the plane
-// orthogonal to M) / |M|^2.
+// orthogonal to M) / |M|^2.  Linear SSE: each trajectory's moments weighted by its Q (App. B),
+// still divided by N_T.
 __global__ void k_ensemble(Dev a) {
     __shared__ double avg[9];
     if (threadIdx.x < 9) {
         double s = 0.0;
-        for (int t = 0; t < a.nt; ++t) s += a.mom[(size_t)t * 9 + threadIdx.x];
+        for (int t = 0; t < a.nt; ++t) {
+            const double v = a.mom[(size_t)t * 9 + threadIdx.x];
+            s += a.linear ? v * exp(a.momlq[t]) : v;
+        }
         avg[threadIdx.x] = s / (double)a.nt;
     }
     __syncthreads();

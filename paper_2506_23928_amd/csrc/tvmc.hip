@@ -60,7 +60,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
+        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, lognorm, qhist, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
         arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, total;
 };
 
@@ -133,6 +133,8 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.hist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt * 9);
     L.ens = take(sizeof(double) * 16);
     L.flags = take(sizeof(int) * tt);
+    L.lognorm = take(sizeof(double) * tt * 3);
+    L.qhist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt);
     const size_t np = ar ? ar_params(n, ah) : 0;
     L.arP = take(sizeof(float) * tt * np);
     L.arG = take(sizeof(float) * tt * np);
@@ -212,6 +214,8 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
     }
     if (c->solver < TVMC_SOLVER_AUTO || c->solver > TVMC_SOLVER_SAMPLE_SPACE)
         return snprintf(msg, len, "bad solver"), TVMC_E_INVAL;
+    if (c->unravelling != TVMC_SSE_NONLINEAR && c->unravelling != TVMC_SSE_LINEAR)
+        return snprintf(msg, len, "bad unravelling"), TVMC_E_INVAL;
     if (use_sample_space(c, n_params(a->kind, p->n_sites, a->n_hidden)) && c->n_samples > 65535)
         return snprintf(msg, len, "the sample-space solve takes at most 65535 samples"), TVMC_E_INVAL;
     return TVMC_OK;
@@ -651,6 +655,8 @@ size_t q_bytes(const tvmc_ctx *c, int what) {
     case TVMC_Q_AR_LOGQ: return d.ar ? sizeof(float) * d.ns : 0;
     case TVMC_Q_AR_LOSS: return d.ar ? sizeof(double) : 0;
     case TVMC_Q_AR_ACCEPTS: return d.ar ? sizeof(uint32_t) * d.nc : 0;
+    case TVMC_Q_LOGNORM: return sizeof(double);
+    case TVMC_Q_LOGNORM_HIST: return sizeof(double) * (size_t)d.nobs;
     default: return 0;
     }
 }
@@ -766,6 +772,11 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.hist = (double *)(base + L.hist);
     d.ens = (double *)(base + L.ens);
     d.flags = (int *)(base + L.flags);
+    d.linear = c->unravelling == TVMC_SSE_LINEAR;
+    d.lognorm = (double *)(base + L.lognorm);
+    d.dq0 = d.lognorm + T;
+    d.momlq = d.lognorm + 2 * (size_t)T;
+    d.qhist = (double *)(base + L.qhist);
     d.ar = c->proposal;
     d.ah = c->proposal ? c->ar_hidden : 0;
     d.arnp = c->proposal ? ar_params(n, c->ar_hidden) : 0;
@@ -827,6 +838,8 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     INITCHECK(hipMemcpyAsync((void *)d.pb, pb.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
     INITCHECK(hipMemcpyAsync(d.theta, th.data(), sizeof(double2) * th.size(), hipMemcpyHostToDevice, ctx->stream));
     INITCHECK(hipMemsetAsync(d.flags, 0, sizeof(int) * T, ctx->stream));
+    INITCHECK(hipMemsetAsync(d.lognorm, 0, sizeof(double) * 3 * (size_t)T, ctx->stream));
+    INITCHECK(hipMemsetAsync(d.qhist, 0, sizeof(double) * (size_t)(d.nobs > 0 ? d.nobs : 1) * T, ctx->stream));
     INITCHECK(hipMemsetAsync(d.d0, 0, sizeof(double2) * (size_t)T * m, ctx->stream));
     INITCHECK(hipMemsetAsync(d.d1, 0, sizeof(double2) * (size_t)T * m, ctx->stream));
     hipLaunchKernelGGL(k_init_chains, dim3((c->n_chains + 63) / 64, T), dim3(64), 0, ctx->stream, d);
@@ -957,12 +970,17 @@ tvmc_status tvmc_get(tvmc_ctx *c, int32_t what, int32_t traj, void *host, size_t
     case TVMC_Q_AR_LOGQ: src = d.arlogq + t * d.ns; break;
     case TVMC_Q_AR_LOSS: src = d.arloss + t; break;
     case TVMC_Q_AR_ACCEPTS: src = d.aracc + t * d.nc; break;
+    case TVMC_Q_LOGNORM: src = d.lognorm + t; break;
     default: break;
     }
     if (what == TVMC_Q_OBS_HIST) {
         for (int s = 0; s < d.nobs; ++s)
             HIPCHECK(c, hipMemcpyAsync((double *)host + 9 * s, d.hist + ((size_t)s * d.nt + t) * 9, sizeof(double) * 9,
                                        hipMemcpyDeviceToHost, c->stream));
+    } else if (what == TVMC_Q_LOGNORM_HIST) {
+        if (d.nobs > 0)
+            HIPCHECK(c, hipMemcpy2DAsync(host, sizeof(double), d.qhist + t, sizeof(double) * d.nt, sizeof(double),
+                                         d.nobs, hipMemcpyDeviceToHost, c->stream));
     } else if (nb > 0) {
         HIPCHECK(c, hipMemcpyAsync(host, src, nb, hipMemcpyDeviceToHost, c->stream));
     }

@@ -40,16 +40,30 @@ def test_struct_layouts_match_the_header(tmp_path):
     from paper_2506_23928_amd import tvmc
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tvmc.h"\nint main(){'
-                    'printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tvmc_problem), offsetof(tvmc_problem, jump_rate),'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tvmc_problem), offsetof(tvmc_problem, jump_rate),'
                     'sizeof(tvmc_config), offsetof(tvmc_config, dt), offsetof(tvmc_config, precision),'
-                    'offsetof(tvmc_config, seed), sizeof(tvmc_ansatz)); return 0;}\n')
+                    'offsetof(tvmc_config, seed), offsetof(tvmc_config, unravelling), sizeof(tvmc_ansatz));'
+                    ' return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(prog)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     P, C, A = tvmc.tvmc_problem, tvmc.tvmc_config, tvmc.tvmc_ansatz
     want = [ctypes.sizeof(P), P.jump_rate.offset, ctypes.sizeof(C), C.dt.offset, C.precision.offset, C.seed.offset,
-            ctypes.sizeof(A)]
+            C.unravelling.offset, ctypes.sizeof(A)]
     assert got == want
+
+
+def test_configuration_checks_run_on_the_host():
+    # tvmc_workspace_size validates the configuration without touching a device
+    import numpy as np
+    import pytest
+    from paper_2506_23928_amd import tvmc
+    pb = tvmc.Problem(np.zeros((4, 4)), 0.1, [(0, 0, 0.1)])
+    an = tvmc.tvmc_ansatz(tvmc.JASTROW, 0)
+    lin = tvmc.make_config(2, 64, 8, 0.01, unravelling=tvmc.SSE_LINEAR)
+    assert tvmc.tvmc_workspace_size(pb, an, lin) == tvmc.tvmc_workspace_size(pb, an, tvmc.make_config(2, 64, 8, 0.01))
+    with pytest.raises(tvmc.TvmcError):
+        tvmc.tvmc_workspace_size(pb, an, tvmc.make_config(2, 64, 8, 0.01, unravelling=2))
 
 
 def test_product_couplings_match_the_definition():
