@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "otvmc_oracle.c")
 _LIB = os.path.join(_HERE, "libotvmc_oracle.so")
 
 SIGMA_MINUS, SIGMA_PLUS, SIGMA_Z = 0, 1, 2
-JASTROW, RBM = 0, 1
+JASTROW, RBM, LJPH = 0, 1, 2
 HEUN, MIDPOINT, EULER = 0, 1, 2
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -35,8 +35,16 @@ class _Problem(ctypes.Structure):
                 ("kind", _c_i32p), ("site", _c_i32p), ("rate", _c_dp)]
 
 
-class _Ansatz(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("n_hidden", ctypes.c_int32)]
+class _AnsatzC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("range", ctypes.c_int32)]
+
+
+def _Ansatz(kind, n_hidden):
+    """The ansatz's second number is N' for the RBM and d for LJPHd (LJPH0 = LJH, LJPH(N-1) =
+    the all-pair Jastrow, the LJNH of the LITF section, in the same parameter order)."""
+    if kind == LJPH:
+        return _AnsatzC(kind, 0, n_hidden)
+    return _AnsatzC(kind, n_hidden, 0)
 
 
 class _Config(ctypes.Structure):

@@ -394,6 +394,26 @@ def jastrow_psi(n):
     return f
 
 
+def ljph_features(n, d):
+    """Features of the LJPHd ansatz (LITF section) as columns [s_i | own pairs | distances]:
+    pairs (j, k), j < k, k - j <= d in row-major order, then for each distance D > d the sum of
+    s_j s_{j+D} over the open chain."""
+    s = spins(n).astype(np.float64)
+    cols = [s[:, i] for i in range(n)]
+    cols += [s[:, j] * s[:, k] for j in range(n) for k in range(j + 1, n) if k - j <= d]
+    cols += [sum(s[:, j] * s[:, j + D] for j in range(n - D)) for D in range(d + 1, n)]
+    return np.stack(cols, axis=1)
+
+
+def ljph_psi(n, d):
+    """psi_theta(x) of LJPHd as a vector over all configurations."""
+    feats = ljph_features(n, d)
+
+    def f(theta):
+        return np.exp(feats @ np.asarray(theta))
+    return f
+
+
 def rbm_psi(n, nh):
     """psi_theta(x) of Eq. 11 as a vector over all configurations."""
     s = spins(n).astype(np.float64)

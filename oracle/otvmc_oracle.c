@@ -34,7 +34,7 @@
 typedef double complex cplx;
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_NOMEM = 2, ORC_E_NUMERIC = 4 };
-enum { ORC_JASTROW = 0, ORC_RBM = 1 };
+enum { ORC_JASTROW = 0, ORC_RBM = 1, ORC_LJPH = 2 };
 enum { ORC_SIGMA_MINUS = 0, ORC_SIGMA_PLUS = 1, ORC_SIGMA_Z = 2 };
 enum { ORC_HEUN = 0, ORC_MIDPOINT = 1, ORC_EULER = 2 };
 
@@ -49,8 +49,9 @@ typedef struct {
 } orc_problem;
 
 typedef struct {
-    int32_t kind;          /* ORC_JASTROW (all-pair two-body Jastrow) or ORC_RBM */
+    int32_t kind;          /* ORC_JASTROW (all-pair two-body Jastrow), ORC_RBM or ORC_LJPH */
     int32_t n_hidden;      /* RBM hidden units N' */
+    int32_t range;         /* LJPHd: d, pairs with |j-k| <= d keep their own eta */
 } orc_ansatz;
 
 typedef struct {
@@ -179,9 +180,15 @@ int orc_couplings(int32_t geom, int32_t lx, int32_t ly, double alpha, double jsc
 
 /* ------------------------------------------------------------------ ansatz */
 
+/* LJPHd (the partially inhomogeneous Jastrow of the LITF section): the biases a_i and the
+ * pairs at distance |j-k| <= d keep their own parameters, every farther pair shares one eta per
+ * distance D = d+1 .. N-1 (open chain).  Pairs with their own eta: d(2N-d-1)/2. */
+static int ljph_own_pairs(int n, int d) { return d * (2 * n - d - 1) / 2; }
+
 int32_t orc_n_params(const orc_ansatz *a, int32_t n)
 {
     if (a->kind == ORC_JASTROW) return n + n * (n - 1) / 2;
+    if (a->kind == ORC_LJPH) return n + ljph_own_pairs(n, a->range) + (n - 1 - a->range);
     return n + a->n_hidden + n * a->n_hidden;
 }
 
@@ -190,6 +197,20 @@ static int pair_index(int n, int j, int k)
 {
     if (j > k) { int t = j; j = k; k = t; }
     return n + j * n - j * (j + 1) / 2 + (k - j - 1);
+}
+
+/* index of the parameter that plays eta_{jk} (j != k): the Jastrow pair itself, or for LJPHd
+ * the pair's own parameter (same row-major order, rows cut at distance d) when |j-k| <= d and
+ * the shared parameter of its distance otherwise */
+static int eta_index(const orc_ansatz *an, int n, int j, int k)
+{
+    if (an->kind != ORC_LJPH) return pair_index(n, j, k);
+    if (j > k) { int t = j; j = k; k = t; }
+    int d = an->range, dist = k - j;
+    if (dist > d) return n + ljph_own_pairs(n, d) + (dist - d - 1);
+    int at = n;
+    for (int r = 0; r < j; ++r) at += (n - 1 - r < d) ? n - 1 - r : d;
+    return at + dist - 1;
 }
 
 /* log cosh(z) without overflow: cosh is even, and for Re z >= 0
@@ -215,9 +236,9 @@ static cplx logpsi(const orc_ansatz *an, int n, const cplx *th, const int8_t *s)
 {
     cplx lp = 0.0;
     for (int i = 0; i < n; ++i) lp += th[i] * (double)s[i];
-    if (an->kind == ORC_JASTROW) {
+    if (an->kind != ORC_RBM) {
         for (int j = 0; j < n; ++j)
-            for (int k = j + 1; k < n; ++k) lp += th[pair_index(n, j, k)] * (double)(s[j] * s[k]);
+            for (int k = j + 1; k < n; ++k) lp += th[eta_index(an, n, j, k)] * (double)(s[j] * s[k]);
     } else {
         int nh = an->n_hidden;
         cplx *g = malloc(sizeof(cplx) * nh);
@@ -232,10 +253,10 @@ static cplx logpsi(const orc_ansatz *an, int n, const cplx *th, const int8_t *s)
 static cplx flip1(const orc_ansatz *an, int n, const cplx *th, const int8_t *s, const cplx *gam, int i)
 {
     double si = (double)s[i];
-    if (an->kind == ORC_JASTROW) {
+    if (an->kind != ORC_RBM) {
         cplx f = th[i];
         for (int k = 0; k < n; ++k)
-            if (k != i) f += th[pair_index(n, i, k)] * (double)s[k];
+            if (k != i) f += th[eta_index(an, n, i, k)] * (double)s[k];
         return -2.0 * si * f;
     }
     int nh = an->n_hidden;
@@ -249,8 +270,8 @@ static cplx flip1(const orc_ansatz *an, int n, const cplx *th, const int8_t *s, 
 static cplx flip2(const orc_ansatz *an, int n, const cplx *th, const int8_t *s, const cplx *gam, int i, int k)
 {
     double si = (double)s[i], sk = (double)s[k];
-    if (an->kind == ORC_JASTROW)
-        return flip1(an, n, th, s, gam, i) + flip1(an, n, th, s, gam, k) + 4.0 * si * sk * th[pair_index(n, i, k)];
+    if (an->kind != ORC_RBM)
+        return flip1(an, n, th, s, gam, i) + flip1(an, n, th, s, gam, k) + 4.0 * si * sk * th[eta_index(an, n, i, k)];
     int nh = an->n_hidden;
     const cplx *w = th + n + nh;
     cplx d = -2.0 * th[i] * si - 2.0 * th[k] * sk;
@@ -267,6 +288,12 @@ static void log_derivs(const orc_ansatz *an, int n, const cplx *th, const int8_t
     if (an->kind == ORC_JASTROW) {
         for (int j = 0; j < n; ++j)
             for (int k = j + 1; k < n; ++k) O[pair_index(n, j, k) * stride] = (double)(s[j] * s[k]);
+    } else if (an->kind == ORC_LJPH) {
+        /* a shared eta multiplies every pair of its distance: O is the sum of their s_j s_k */
+        int m = orc_n_params(an, n);
+        for (int k = n; k < m; ++k) O[k * stride] = 0.0;
+        for (int j = 0; j < n; ++j)
+            for (int k = j + 1; k < n; ++k) O[eta_index(an, n, j, k) * stride] += (double)(s[j] * s[k]);
     } else {
         int nh = an->n_hidden;
         for (int j = 0; j < nh; ++j) O[(n + j) * stride] = ctanh(gam[j]);
