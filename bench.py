@@ -72,6 +72,8 @@ def ansatz_of(tv, w):
     if w.get("ansatz", "jastrow") == "rbm":
         nh = w["n_hidden"]
         return tv.RBM, nh, tv.n_params(tv.RBM, w["n"], nh), wl.rbm_theta0(w["n"], nh, w["w_scale"], w["seed"])
+    if w.get("ansatz") == "ljph":
+        return tv.LJPH, w["d"], tv.n_params(tv.LJPH, w["n"], w["d"]), None
     return tv.JASTROW, 0, tv.n_params(tv.JASTROW, w["n"]), None
 
 
@@ -105,7 +107,7 @@ def cpu_baseline(w, ns_sample=None):
     J = orc.couplings(w["geom"], w["n"], w["alpha"], w["jscale"])
     pb = orc.Problem(J, w["h"], wl.jumps(w))
     rbm = w.get("ansatz", "jastrow") == "rbm"
-    kind, nh = (1, w["n_hidden"]) if rbm else (0, 0)
+    kind, nh = (1, w["n_hidden"]) if rbm else (2, w["d"]) if w.get("ansatz") == "ljph" else (0, 0)
     m = orc.n_params(kind, w["n"], nh)
     th0 = wl.rbm_theta0(w["n"], nh, w["w_scale"], w["seed"]) if rbm else np.zeros(m)
     ns_full = w["n_samples"]
@@ -177,6 +179,8 @@ def main():
     w["name"] = args.workload
     kind, nh, m, _ = ansatz_of(tv, w)
     prec = tv.PREC_MFMA if args.precision == "mfma" else tv.PREC_FP64
+    if kind == tv.LJPH:
+        prec = tv.PREC_FP64      # a shared eta's O_k is an integer sum, not +-1: S in FP64
     n, T = w["n"], w["n_traj"]
     print("bench: workload %s N=%d M=%d trajectories=%d samples=%d chains=%d jumps=%d precision=%s proposal=%s" % (
         args.workload, n, m, T, w["n_samples"], w["n_chains"], len(wl.jumps(w)), args.precision,
@@ -244,6 +248,11 @@ def main():
         achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": "k_sbuild_rbm_f64", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
                 "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_sbuild_rbm_f64")}
+    elif dom == "sbuild" and not ss and prec == tv.PREC_FP64:
+        flops = T * (m * (m + 1) / 2.0) * ns * 2.0
+        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_sbuild_f64", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_sbuild_f64")}
     elif dom == "sbuild" and not ss:
         ops = T * (m * (m + 1) / 2.0) * ns * 2.0
         achieved = ops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
@@ -280,12 +289,13 @@ def main():
         "metric": "trajectory-steps/s at N=64 (batched+learned vs plain) at fixed xi^2 error",
         "value": value, "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if (prec == tv.PREC_FP64 or kind == tv.JASTROW) else "f64+bf16x3",
+        "dtype": "f64" if (prec == tv.PREC_FP64 or kind != tv.RBM) else "f64+bf16x3",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_spins": n, "n_params": m, "n_traj": T, "n_samples": w["n_samples"],
                    "n_chains": w["n_chains"], "n_jumps": len(wl.jumps(w)), "dt": w["dt"],
-                   "ansatz": w.get("ansatz", "jastrow"), "n_hidden": nh, "proposal": w.get("proposal", "flip"),
-                   "s_build": ("int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU") if kind == tv.JASTROW
+                   "ansatz": w.get("ansatz", "jastrow"), "n_hidden": nh if kind == tv.RBM else 0,
+                   **({"ljph_d": nh} if kind == tv.LJPH else {}), "proposal": w.get("proposal", "flip"),
+                   "s_build": ("int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU") if kind != tv.RBM
                    else ("BF16-split MFMA, FP32 accumulate" if prec == tv.PREC_MFMA else "FP64 VALU (complex)"),
                    "solve": "FP64 Cholesky" + (" (sample space)" if ss else ""), "solver": args.solver,
                    "obs_every": w["obs_every"]},

@@ -20,6 +20,10 @@
  *
  * Parameter layout theta (interleaved re, im doubles):
  *   Jastrow (Eq. 12): [a_0..a_{N-1}, eta_01, eta_02, .., eta_0,N-1, eta_12, .., eta_N-2,N-1]
+ *   LJPHd   (the partially inhomogeneous Jastrow of the LITF section, open chain):
+ *            [a_0..a_{N-1}, eta_jk for k - j <= d in the Jastrow order, eta_(d+1) .. eta_(N-1)],
+ *            the last block shared by every pair at that distance; d = N-1 is the Jastrow
+ *            layout itself and d = 0 the homogeneous LJH (2N - 1 parameters)
  *   RBM     (Eq. 11): [a_0..a_{N-1}, b_0..b_{N'-1}, w_00, w_01, .., w_0,N'-1, w_10, ..]
  *
  * Ownership: every host pointer passed in is read during the call and may be freed after it.
@@ -52,7 +56,7 @@ typedef enum {
 } tvmc_status;
 
 enum { TVMC_JUMP_SIGMA_MINUS = 0, TVMC_JUMP_SIGMA_PLUS = 1, TVMC_JUMP_SIGMA_Z = 2 };
-enum { TVMC_ANSATZ_JASTROW = 0, TVMC_ANSATZ_RBM = 1 };
+enum { TVMC_ANSATZ_JASTROW = 0, TVMC_ANSATZ_RBM = 1, TVMC_ANSATZ_LJPH = 2 };
 enum { TVMC_SCHEME_HEUN = 0, TVMC_SCHEME_MIDPOINT = 1 };
 /* FP64: S accumulated with FP64 vector FMAs.  MFMA: S accumulated on int8 matrix cores; for
  * the Jastrow ansatz every O_k is +-1, so both give the same S bit for bit (the RBM supports
@@ -72,8 +76,10 @@ typedef struct {
 } tvmc_problem;
 
 typedef struct {
-    int32_t kind;                 /* TVMC_ANSATZ_JASTROW or TVMC_ANSATZ_RBM */
-    int32_t n_hidden;             /* RBM hidden units N', 1..256 (ignored for Jastrow) */
+    int32_t kind;                 /* TVMC_ANSATZ_JASTROW, TVMC_ANSATZ_RBM or TVMC_ANSATZ_LJPH */
+    int32_t n_hidden;             /* RBM hidden units N', 1..256 (ignored otherwise) */
+    int32_t range;                /* LJPHd: d in [0, N-1] (ignored otherwise); needs TVMC_PREC_FP64 and
+                                     the parameter-space solve (a shared eta's O_k is an integer sum) */
 } tvmc_ansatz;
 
 typedef struct {

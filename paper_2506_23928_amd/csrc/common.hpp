@@ -90,6 +90,17 @@ __host__ __device__ __forceinline__ int pair_index(int n, int j, int k) {
     return n + j * n - j * (j + 1) / 2 + (k - j - 1);
 }
 
+// O_k of a packed configuration (bit i set <=> s_i = +1), as an integer
+__device__ __forceinline__ int o_int(uint64_t mk, int p, int q, int n) {
+    if (q == -2) {   // sum over j of s_j s_{j+p}: pairs that agree minus pairs that differ
+        const int len = n - p;
+        const uint64_t low = len >= 64 ? ~0ull : ((1ull << len) - 1ull);
+        return len - 2 * __popcll((mk ^ (mk >> p)) & low);
+    }
+    const uint64_t par = (q < 0) ? (((mk >> p) & 1ull) ^ 1ull) : (((mk >> p) ^ (mk >> q)) & 1ull);
+    return par ? -1 : 1;   // par = 1 <=> O = -1
+}
+
 // Everything a kernel may touch, as raw device pointers into the caller's workspace.
 struct Dev {
     int n, m, nch, ns, nc, per, nt, nobs;
@@ -108,7 +119,9 @@ struct Dev {
     const int *jsite;         // [nch]
     const double *jrate;      // [nch] or [T][nch]
     const int *pa;            // [M] first site of O_k (k < N: the site itself)
-    const int *pb;            // [M] second site of O_k (-1 for one-body terms)
+    const int *pb;            // [M] second site of O_k (-1 for one-body terms, -2 for a shared
+                              //     LJPHd distance pa: O_k = sum_j s_j s_{j+pa})
+    const int *pidx;          // [N*N] theta index of the eta multiplying s_j s_k (j != k)
     double2 *theta, *theta_eval, *d0, *d1;   // [T][M]
     double *eta_re, *eta_im;  // [T][N*N] dense symmetric pair parameters of the evaluation point
     double2 *epair;           // [T][2][N*N] exp(+-4 eta_jk) for two-flip ratios

@@ -130,7 +130,8 @@ __global__ __launch_bounds__(256) void k_gbar(Dev a) {
     if (threadIdx.x == 0) a.gbar[t] = make_double2(sre[0] / (double)a.ns, sim[0] / (double)a.ns);
 }
 
-// <O_k> and D_k = <O_k G> - <O_k><G> for the Jastrow ansatz (O_k = s_i or s_j s_k, real).
+// <O_k> and D_k = <O_k G> - <O_k><G> for the Jastrow ansaetze (O_k = s_i, s_j s_k, or an
+// LJPHd distance sum: real integers).
 __global__ __launch_bounds__(256) void k_obar_D(Dev a) {
     const int t = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -141,19 +142,18 @@ __global__ __launch_bounds__(256) void k_obar_D(Dev a) {
     int64_t cnt = 0;
     double re = 0.0, im = 0.0;
     for (int s = 0; s < a.ns; ++s) {
-        const uint64_t mk = smp[s];
-        const uint64_t par = (q < 0) ? ((mk >> p) & 1ull) : (((mk >> p) ^ (mk >> q)) & 1ull);
-        // one-body: O = s_p (+1 if bit set); two-body: O = s_p s_q (+1 if the bits agree)
-        const bool plus = (q < 0) ? (par == 1ull) : (par == 0ull);
+        const int o = o_int(smp[s], p, q, a.n);
         const double2 g = G[s];
-        if (plus) {
-            ++cnt;
+        cnt += o;
+        if (o == 1) {
             re += g.x;
             im += g.y;
-        } else {
-            --cnt;
+        } else if (o == -1) {
             re -= g.x;
             im -= g.y;
+        } else {
+            re += (double)o * g.x;
+            im += (double)o * g.y;
         }
     }
     const double inv = 1.0 / (double)a.ns;

@@ -15,7 +15,8 @@
 
 namespace tvmc {
 
-// theta (or theta_eval) -> dense symmetric eta, split into real / imaginary planes.
+// theta (or theta_eval) -> dense symmetric eta, split into real / imaginary planes (for LJPHd
+// every pair at a shared distance reads that distance's parameter).
 __global__ void k_prepare_jastrow(Dev a, const double2 *__restrict__ src) {
     const int t = blockIdx.y;
     const int n = a.n, nn = n * n;
@@ -24,7 +25,7 @@ __global__ void k_prepare_jastrow(Dev a, const double2 *__restrict__ src) {
     const int i = idx / n, k = idx % n;
     double re = 0.0, im = 0.0;
     if (i != k) {
-        const double2 v = src[(size_t)t * a.m + pair_index(n, i < k ? i : k, i < k ? k : i)];
+        const double2 v = src[(size_t)t * a.m + a.pidx[idx]];
         re = v.x;
         im = v.y;
     }

@@ -1,6 +1,7 @@
 // Assembly of S + eps I for the Jastrow ansatz (definition after Eq. 8, diagonal shift of the
-// regularised solve).  Every O_k is +-1 (s_i, or s_j s_k), so sum_s O_sk O_sl is an exact
-// integer in either variant below, and the centring S_kl = sum/N_s - <O_k><O_l> uses the same
+// regularised solve).  Every O_k is +-1 (s_i, or s_j s_k), or for a shared LJPHd distance D
+// the integer sum of s_j s_{j+D}, so sum_s O_sk O_sl is an exact integer in either variant
+// below (the int8 one takes +-1 only), and the centring S_kl = sum/N_s - <O_k><O_l> uses the same
 // separately rounded operations in both: they produce the same bits for any N_s (and S is
 // exact outright when N_s is a power of two).  Only the lower triangle (k >= l) is written;
 // the Cholesky factorisation reads nothing else.
@@ -23,10 +24,7 @@ __device__ __forceinline__ double add_shift(double v, double eps) {
     return v + eps;
 }
 
-__device__ __forceinline__ double o_value(uint64_t mk, int p, int q) {
-    const uint64_t par = (q < 0) ? (((mk >> p) & 1ull) ^ 1ull) : (((mk >> p) ^ (mk >> q)) & 1ull);
-    return par ? -1.0 : 1.0;   // par = 1 <=> O = -1
-}
+__device__ __forceinline__ double o_value(uint64_t mk, int p, int q, int n) { return (double)o_int(mk, p, q, n); }
 
 // Plain form: 64x64 tile per workgroup, 4x4 register tile per thread, FP64 FMAs.
 __global__ __launch_bounds__(256) void k_sbuild_f64(Dev a) {
@@ -58,8 +56,8 @@ __global__ __launch_bounds__(256) void k_sbuild_f64(Dev a) {
             const uint64_t mk = smask[s];
             double ov[4], cv[4];
             for (int u = 0; u < 4; ++u) {
-                ov[u] = o_value(mk, rp[u], rq[u]);
-                cv[u] = o_value(mk, cp[u], cq[u]);
+                ov[u] = o_value(mk, rp[u], rq[u], a.n);
+                cv[u] = o_value(mk, cp[u], cq[u], a.n);
             }
             for (int u = 0; u < 4; ++u)
                 for (int v = 0; v < 4; ++v) acc[u][v] += ov[u] * cv[v];

@@ -3,6 +3,7 @@
 // kernel launches on the caller's stream.  No device allocation happens here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -59,7 +60,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t J, jk, js, jr, pa, pb, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
+    size_t J, jk, js, jr, pa, pb, pidx, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
         bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, lognorm, qhist, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
         arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, total;
 };
@@ -69,9 +70,26 @@ int mom_blocks_for(int ns) {
     return b < 64 ? b : 64;
 }
 
-int n_params(int kind, int n, int nh) { return kind == TVMC_ANSATZ_RBM ? n + nh + n * nh : n + n * (n - 1) / 2; }
+// LJPHd: pairs within distance d that keep their own eta
+int ljph_own_pairs(int n, int d) { return d * (2 * n - d - 1) / 2; }
+int n_params(const tvmc_ansatz *a, int n) {
+    if (a->kind == TVMC_ANSATZ_RBM) return n + a->n_hidden + n * a->n_hidden;
+    if (a->kind == TVMC_ANSATZ_LJPH) return n + ljph_own_pairs(n, a->range) + (n - 1 - a->range);
+    return n + n * (n - 1) / 2;
+}
+// theta index of the parameter that multiplies s_j s_k (j != k)
+int eta_param(const tvmc_ansatz *a, int n, int j, int k) {
+    if (j > k) std::swap(j, k);
+    if (a->kind != TVMC_ANSATZ_LJPH) return pair_index(n, j, k);
+    const int d = a->range, dist = k - j;
+    if (dist > d) return n + ljph_own_pairs(n, d) + (dist - d - 1);
+    int at = n;
+    for (int r = 0; r < j; ++r) at += std::min(d, n - 1 - r);
+    return at + dist - 1;
+}
 // whether the solve runs in sample space (N_s x N_s) rather than parameter space (M x M)
-int use_sample_space(const tvmc_config *c, int m) {
+int use_sample_space(const tvmc_config *c, const tvmc_ansatz *a, int m) {
+    if (a->kind == TVMC_ANSATZ_LJPH) return 0;
     return c->solver == TVMC_SOLVER_SAMPLE_SPACE || (c->solver == TVMC_SOLVER_AUTO && m > c->n_samples);
 }
 
@@ -93,6 +111,7 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.jr = take(sizeof(double) * (nch + 1) * (size_t)nprob);
     L.pa = take(sizeof(int) * m);
     L.pb = take(sizeof(int) * m);
+    L.pidx = take(sizeof(int) * n * n);
     L.theta = take(sizeof(double2) * tt * m);
     L.theta_eval = take(sizeof(double2) * tt * m);
     L.d0 = take(sizeof(double2) * tt * m);
@@ -185,9 +204,18 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
             if (p->J[i * p->n_sites + j] != p->J[j * p->n_sites + i])
                 return snprintf(msg, len, "J must be symmetric"), TVMC_E_INVAL;
     }
-    if (a->kind != TVMC_ANSATZ_JASTROW && a->kind != TVMC_ANSATZ_RBM) return snprintf(msg, len, "bad ansatz"), TVMC_E_INVAL;
+    if (a->kind != TVMC_ANSATZ_JASTROW && a->kind != TVMC_ANSATZ_RBM && a->kind != TVMC_ANSATZ_LJPH)
+        return snprintf(msg, len, "bad ansatz"), TVMC_E_INVAL;
     if (a->kind == TVMC_ANSATZ_RBM && (a->n_hidden < 1 || a->n_hidden > 256))
         return snprintf(msg, len, "RBM hidden units must be in [1, 256]"), TVMC_E_INVAL;
+    if (a->kind == TVMC_ANSATZ_LJPH) {
+        if (a->range < 0 || a->range > p->n_sites - 1)
+            return snprintf(msg, len, "LJPHd range d must be in [0, N-1]"), TVMC_E_INVAL;
+        if (c->precision != TVMC_PREC_FP64)
+            return snprintf(msg, len, "LJPHd builds S in FP64 (its shared O_k are not +-1)"), TVMC_E_INVAL;
+        if (c->solver == TVMC_SOLVER_SAMPLE_SPACE)
+            return snprintf(msg, len, "LJPHd solves in parameter space"), TVMC_E_INVAL;
+    }
     if (c->n_traj < 1 || (int64_t)c->traj_offset + c->n_traj > (1 << 24) || c->traj_offset < 0)
         return snprintf(msg, len, "trajectory ids must lie in [0, 2^24)"), TVMC_E_INVAL;
     if (c->n_chains < 1 || c->n_samples < 1 || c->n_samples % c->n_chains)
@@ -216,7 +244,7 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
         return snprintf(msg, len, "bad solver"), TVMC_E_INVAL;
     if (c->unravelling != TVMC_SSE_NONLINEAR && c->unravelling != TVMC_SSE_LINEAR)
         return snprintf(msg, len, "bad unravelling"), TVMC_E_INVAL;
-    if (use_sample_space(c, n_params(a->kind, p->n_sites, a->n_hidden)) && c->n_samples > 65535)
+    if (use_sample_space(c, a, n_params(a, p->n_sites)) && c->n_samples > 65535)
         return snprintf(msg, len, "the sample-space solve takes at most 65535 samples"), TVMC_E_INVAL;
     return TVMC_OK;
 }
@@ -670,9 +698,9 @@ tvmc_status tvmc_workspace_size_batch(const tvmc_problem *p, int32_t np, const t
     tvmc_status st = check_batch(p, np, a, c, g_err, sizeof(g_err));
     if (st != TVMC_OK) return st;
     if (!bytes) return TVMC_E_INVAL;
-    const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden);
+    const int n = p->n_sites, m = n_params(a, n);
     *bytes = layout(a->kind, n, a->n_hidden, m, p->n_jumps, c->n_traj, c->n_samples, c->n_chains, c->n_obs_max,
-                    c->proposal, c->ar_hidden, np, c->precision, use_sample_space(c, m)).total;
+                    c->proposal, c->ar_hidden, np, c->precision, use_sample_space(c, a, m)).total;
     return TVMC_OK;
 }
 
@@ -687,10 +715,10 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     tvmc_status st = check_batch(pbs, np, a, c, g_err, sizeof(g_err));
     if (st != TVMC_OK) return st;
     const tvmc_problem *p = pbs;
-    const int n = p->n_sites, m = n_params(a->kind, n, a->n_hidden), nch = p->n_jumps, T = c->n_traj;
+    const int n = p->n_sites, m = n_params(a, n), nch = p->n_jumps, T = c->n_traj;
     const int nh = a->kind == TVMC_ANSATZ_RBM ? a->n_hidden : 0;
     const Layout L = layout(a->kind, n, nh, m, nch, T, c->n_samples, c->n_chains, c->n_obs_max, c->proposal,
-                            c->ar_hidden, np, c->precision, use_sample_space(c, m));
+                            c->ar_hidden, np, c->precision, use_sample_space(c, a, m));
     if (!ws) return snprintf(g_err, sizeof(g_err), "workspace is null"), TVMC_E_INVAL;
     if (ws_bytes < L.total) return snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu", ws_bytes, L.total), TVMC_E_NOMEM;
     if ((uintptr_t)ws % 256) return snprintf(g_err, sizeof(g_err), "workspace must be 256-byte aligned"), TVMC_E_INVAL;
@@ -731,6 +759,7 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.jrate = (const double *)(base + L.jr);
     d.pa = (const int *)(base + L.pa);
     d.pb = (const int *)(base + L.pb);
+    d.pidx = (const int *)(base + L.pidx);
     d.theta = (double2 *)(base + L.theta);
     d.theta_eval = (double2 *)(base + L.theta_eval);
     d.d0 = (double2 *)(base + L.d0);
@@ -759,7 +788,7 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.tt = (double2 *)(base + L.tt);
     d.mp = (m + RQ_T - 1) / RQ_T * RQ_T;
     d.rbmP = (uint16_t *)(base + L.rbmP);
-    d.ss = use_sample_space(c, m);
+    d.ss = use_sample_space(c, a, m);
     d.ssrow = (double2 *)(base + L.ssrow);
     d.ssrhs = (double2 *)(base + L.ssrhs);
     d.ssu = (double2 *)(base + L.ssu);
@@ -793,13 +822,22 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.arloss = (double *)(base + L.arloss);
     d.aracc = (uint32_t *)(base + L.aracc);
 
-    std::vector<int> pa(m, 0), pb(m, -1);
+    // what each O_k is: pb = -1: s_pa; pb >= 0: s_pa s_pb; pb = -2: the sum of s_j s_{j+pa}
+    // over the chain (a shared LJPHd distance).  pidx: theta index of the eta of each pair.
+    std::vector<int> pa(m, 0), pb(m, -1), pidx((size_t)n * n, 0);
     for (int i = 0; i < n; ++i) pa[i] = i;
-    if (a->kind == TVMC_ANSATZ_JASTROW)
+    if (a->kind != TVMC_ANSATZ_RBM)
         for (int j = 0; j < n; ++j)
             for (int k = j + 1; k < n; ++k) {
-                pa[pair_index(n, j, k)] = j;
-                pb[pair_index(n, j, k)] = k;
+                const int q = eta_param(a, n, j, k);
+                pidx[(size_t)j * n + k] = pidx[(size_t)k * n + j] = q;
+                if (a->kind == TVMC_ANSATZ_LJPH && k - j > a->range) {
+                    pa[q] = k - j;
+                    pb[q] = -2;
+                } else {
+                    pa[q] = j;
+                    pb[q] = k;
+                }
             }
     std::vector<double2> th((size_t)T * m);
     for (int t = 0; t < T; ++t)
@@ -836,6 +874,8 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     }
     INITCHECK(hipMemcpyAsync((void *)d.pa, pa.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
     INITCHECK(hipMemcpyAsync((void *)d.pb, pb.data(), sizeof(int) * m, hipMemcpyHostToDevice, ctx->stream));
+    INITCHECK(hipMemcpyAsync((void *)d.pidx, pidx.data(), sizeof(int) * pidx.size(), hipMemcpyHostToDevice,
+                             ctx->stream));
     INITCHECK(hipMemcpyAsync(d.theta, th.data(), sizeof(double2) * th.size(), hipMemcpyHostToDevice, ctx->stream));
     INITCHECK(hipMemsetAsync(d.flags, 0, sizeof(int) * T, ctx->stream));
     INITCHECK(hipMemsetAsync(d.lognorm, 0, sizeof(double) * 3 * (size_t)T, ctx->stream));

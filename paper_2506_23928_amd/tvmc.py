@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libtvmc.so")
 
 TVMC_OK, TVMC_E_INVAL, TVMC_E_NOMEM, TVMC_E_DEVICE, TVMC_E_NUMERIC, TVMC_E_STATE, TVMC_E_UNSUPPORTED = range(7)
 SIGMA_MINUS, SIGMA_PLUS, SIGMA_Z = 0, 1, 2
-JASTROW, RBM = 0, 1
+JASTROW, RBM, LJPH = 0, 1, 2
 HEUN, MIDPOINT = 0, 1
 PREC_FP64, PREC_MFMA = 0, 1
 (Q_THETA, Q_THETA_EVAL, Q_DELTA0, Q_DELTA1, Q_SAMPLES, Q_ELOC, Q_S, Q_D, Q_OBAR, Q_BMEAN, Q_DW, Q_ACCEPTS,
@@ -35,7 +35,7 @@ class tvmc_problem(ctypes.Structure):
 
 
 class tvmc_ansatz(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("n_hidden", ctypes.c_int32)]
+    _fields_ = [("kind", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("range", ctypes.c_int32)]
 
 
 class tvmc_config(ctypes.Structure):
@@ -100,8 +100,18 @@ class Problem:
                             self.rate.ctypes.data_as(_dp))
 
 
+def make_ansatz(kind: int, n_hidden: int = 0) -> tvmc_ansatz:
+    """The ansatz's second number is N' for the RBM and d for LJPHd."""
+    return tvmc_ansatz(kind, n_hidden, 0) if kind != LJPH else tvmc_ansatz(kind, 0, n_hidden)
+
+
 def n_params(kind: int, n: int, n_hidden: int = 0) -> int:
-    return n + n * (n - 1) // 2 if kind == JASTROW else n + n_hidden + n * n_hidden
+    if kind == RBM:
+        return n + n_hidden + n * n_hidden
+    if kind == LJPH:
+        d = n_hidden
+        return n + d * (2 * n - d - 1) // 2 + (n - 1 - d)
+    return n + n * (n - 1) // 2
 
 
 def make_config(n_traj, n_samples, n_chains, dt, diag_shift=1e-4, burn_sweeps=2, thin_sweeps=1, init_sweeps=0,
@@ -205,7 +215,8 @@ def tvmc_destroy(ctx):
 class Context:
     """One batch of trajectories with its workspace held as a torch tensor.  `problem` is one
     Problem shared by every trajectory, or a list of n_traj Problems (same N, hx and jump
-    channels; couplings and rates may differ per trajectory)."""
+    channels; couplings and rates may differ per trajectory).  `n_hidden` is N' for the RBM
+    and d for LJPHd."""
 
     _shapes = {Q_THETA: ("c", "m"), Q_THETA_EVAL: ("c", "m"), Q_DELTA0: ("c", "m"), Q_DELTA1: ("c", "m"),
                Q_SAMPLES: ("u8", "ns"), Q_ELOC: ("c", "ns"), Q_S: ("d", "mm"), Q_D: ("c", "m"), Q_OBAR: ("d", "m"),
@@ -223,7 +234,7 @@ class Context:
         self.problems = list(problem) if batch else [problem]
         self.problem = self.problems[0]
         self.config = config
-        self.ansatz = tvmc_ansatz(kind, n_hidden)
+        self.ansatz = make_ansatz(kind, n_hidden)
         self.m = n_params(kind, self.problem.n, n_hidden)
         nbytes = tvmc_workspace_size_batch(self.problems, self.ansatz, config)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)

@@ -59,11 +59,20 @@ def test_configuration_checks_run_on_the_host():
     import pytest
     from paper_2506_23928_amd import tvmc
     pb = tvmc.Problem(np.zeros((4, 4)), 0.1, [(0, 0, 0.1)])
-    an = tvmc.tvmc_ansatz(tvmc.JASTROW, 0)
+    an = tvmc.make_ansatz(tvmc.JASTROW, 0)
     lin = tvmc.make_config(2, 64, 8, 0.01, unravelling=tvmc.SSE_LINEAR)
     assert tvmc.tvmc_workspace_size(pb, an, lin) == tvmc.tvmc_workspace_size(pb, an, tvmc.make_config(2, 64, 8, 0.01))
     with pytest.raises(tvmc.TvmcError):
         tvmc.tvmc_workspace_size(pb, an, tvmc.make_config(2, 64, 8, 0.01, unravelling=2))
+    # LJPHd: d in [0, N-1], FP64 S, parameter-space solve; the workspace grows with M
+    lj = tvmc.make_ansatz(tvmc.LJPH, 1)
+    assert tvmc.tvmc_workspace_size(pb, lj, tvmc.make_config(2, 64, 8, 0.01)) > 0
+    for bad_an, bad_cfg in [(tvmc.make_ansatz(tvmc.LJPH, 4), tvmc.make_config(2, 64, 8, 0.01)),
+                            (tvmc.make_ansatz(tvmc.LJPH, -1), tvmc.make_config(2, 64, 8, 0.01)),
+                            (lj, tvmc.make_config(2, 64, 8, 0.01, precision=tvmc.PREC_MFMA)),
+                            (lj, tvmc.make_config(2, 64, 8, 0.01, solver=tvmc.SOLVER_SAMPLE_SPACE))]:
+        with pytest.raises(tvmc.TvmcError):
+            tvmc.tvmc_workspace_size(pb, bad_an, bad_cfg)
 
 
 def test_product_couplings_match_the_definition():

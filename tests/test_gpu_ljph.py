@@ -1,0 +1,117 @@
+"""LJPHd ansatz (partially inhomogeneous Jastrow, LITF section) on the GPU against the oracle.
+
+Bars as for the all-pair Jastrow: samples, accept counts, <O_k> and S + eps I bit-exact (the
+shared O_k are integer sums of +-1, so every sum is an exact integer in FP64), D to 1e-12 and
+theta to 1e-9 relative.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+LJPH = 2
+
+
+@pytest.fixture(scope="module")
+def tv():
+    import torch
+    assert torch.cuda.is_available(), "the GPU tests need a HIP device"
+    import paper_2506_23928_amd as tv
+    from paper_2506_23928_amd import tvmc
+    tvmc.lib()
+    return tv
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("n,d,ns,nc", [(6, 1, 512, 8), (6, 0, 256, 4), (9, 3, 320, 16), (64, 1, 256, 8)])
+def test_ljph_evaluation_parity(tv, orc, n, d, ns, nc):
+    """One predictor evaluation and solve of a random problem (sigma^-, sigma^+, sigma^z
+    channels), random parameters, ragged sample counts; N = 64 fills the 64-bit word."""
+    from paper_2506_23928_amd import tvmc as T
+    J, hx, jumps = wl.random_problem(n, seed=n + d)
+    m = orc.n_params(LJPH, n, d)
+    th0 = wl.random_theta(m, 0.05, seed=d + 1)
+    seed, dt, eps, TT = 6, 0.01, 1e-3, 2
+    for solver in (T.SOLVER_ONE_GROUP, T.SOLVER_MULTI_GROUP):
+        cfg = tv.make_config(TT, ns, nc, dt, eps, seed=seed, traj_offset=3, solver=solver)
+        ctx = tv.Context(tv.Problem(J, hx, jumps), cfg, kind=LJPH, n_hidden=d, theta0=th0)
+        ctx.sample()
+        ctx.estimate()
+        S = [ctx.get(T.Q_S, t) for t in range(TT)]
+        ctx.sr_solve()
+        ctx.synchronize()
+        cfg_o = orc.Config(n_samples=ns, n_chains=nc, dt=dt, diag_shift=eps, seed=seed)
+        pb = orc.Problem(J, hx, jumps)
+        for t in range(TT):
+            chains = orc.init_chains(seed, 3 + t, n, nc)
+            dw = orc.draw_dw(seed, 3 + t, 0, len(jumps), dt)
+            r = orc.evaluate(pb, LJPH, d, cfg_o, th0, chains, traj=3 + t, first=True, dw=dw)
+            assert np.array_equal(tv.unpack_samples(ctx.get(T.Q_SAMPLES, t), n), r["samples"])
+            assert np.array_equal(ctx.get(T.Q_ACCEPTS, t).astype(np.int64), r["accepts"])
+            assert _rel(ctx.get(T.Q_ELOC, t), r["eloc"]) < 1e-13
+            assert np.array_equal(ctx.get(T.Q_OBAR, t), r["obar"].real)
+            low = np.tril_indices(m)
+            assert np.array_equal(S[t][low], (r["S"].real + eps * np.eye(m))[low])
+            assert _rel(ctx.get(T.Q_D, t), r["D"]) < 1e-12
+            assert _rel(ctx.get(T.Q_DELTA0, t), r["delta"]) < 1e-9
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_ljph_trajectory_parity(tv, orc, scheme):
+    """12 steps of an N = 8 chain with LJPH1 (19 parameters), 3 trajectories, moments every 6
+    steps: theta and the moment history against the oracle's trajectory driver."""
+    from paper_2506_23928_amd import tvmc as T
+    n, d, ns, nc, TT, steps = 8, 1, 512, 8, 3, 12
+    J = orc.couplings("pbc", n, 1.0, 1.0)
+    jumps = [(0, i, 0.1) for i in range(n)] + [(2, i, 0.05) for i in range(n)]
+    m = orc.n_params(LJPH, n, d)
+    cfg_o = orc.Config(n_samples=ns, n_chains=nc, burn_sweeps=2, dt=0.01, diag_shift=1e-4, seed=2, n_steps=steps,
+                       obs_every=6, scheme=scheme)
+    th_o, obs_o, st = orc.run(orc.Problem(J, 0.5, jumps), LJPH, d, cfg_o, np.zeros(m), TT, n_threads=3)
+    assert st == 0
+    cfg = tv.make_config(TT, ns, nc, 0.01, 1e-4, 2, 1, 0, scheme, tv.PREC_FP64, 6, 3, 2)
+    ctx = tv.Context(tv.Problem(J, 0.5, jumps), cfg, kind=LJPH, n_hidden=d)
+    ctx.sde_step(steps)
+    ctx.sample()
+    ctx.observables()
+    ctx.synchronize()
+    for t in range(TT):
+        assert _rel(ctx.get(T.Q_THETA, t), th_o[t]) < 1e-9, t
+        assert np.abs(ctx.get(T.Q_OBS_HIST, t)[:2] - obs_o[t, :2]).max() < 1e-10
+        assert np.abs(ctx.get(T.Q_MOMENTS, t) - obs_o[t, 2]).max() < 1e-10
+
+
+def test_ljh_closed_system_closed_form_on_gpu(tv, orc):
+    """No jumps, h = 0, eps = 0, periodic couplings (a function of |j - k| alone): the shared
+    etas follow eta_D(t) = -i J_D t exactly, on the GPU path alone."""
+    from paper_2506_23928_amd import tvmc as T
+    n = 10
+    J = orc.couplings("pbc", n, 1.0, 1.0)
+    cfg = tv.make_config(3, 512, 8, 0.01, 0.0, seed=4)
+    ctx = tv.Context(tv.Problem(J, 0.0, []), cfg, kind=LJPH, n_hidden=0)
+    ctx.sde_step(10)
+    ctx.synchronize()
+    m = orc.n_params(LJPH, n, 0)
+    want = np.zeros(m, np.complex128)
+    want[n:] = -1j * 0.1 * J[0, 1:]
+    for t in range(3):
+        assert np.abs(ctx.get(T.Q_THETA, t) - want).max() < 1e-12
+
+
+def test_full_range_equals_the_all_pair_jastrow_on_gpu(tv, orc):
+    from paper_2506_23928_amd import tvmc as T
+    n = 7
+    J, hx, jumps = wl.random_problem(n, seed=2)
+    out = []
+    for kind, nh in ((0, 0), (LJPH, n - 1)):
+        cfg = tv.make_config(2, 256, 8, 0.01, 1e-4, seed=5)
+        ctx = tv.Context(tv.Problem(J, hx, jumps), cfg, kind=kind, n_hidden=nh)
+        ctx.sde_step(3)
+        ctx.synchronize()
+        out.append([ctx.get(T.Q_THETA, t) for t in range(2)])
+    assert all(np.array_equal(a, b) for a, b in zip(*out))

@@ -24,6 +24,12 @@ WORKLOADS = {
     "chain64_jastrow": dict(geom="obc", n=64, alpha=1.5, jscale=1.0, h=0.5, decay=0.05, dephase=0.02,
                             ansatz="jastrow", n_samples=4096, n_chains=64, n_traj=256, dt=0.005, t_end=2.0,
                             diag_shift=1e-4, obs_every=20, burn_sweeps=2, thin_sweeps=1, seed=0),
+    # N=64 periodic chain (nearest replica), alpha = 1, h = 0, decay: the setting of the paper's
+    # large-N quench with the LJPH1 ansatz (there at N = 160), at the largest N one 64-bit word
+    # holds; M = 3N - 3 = 189; App. D is exact here
+    "chain64_ljph1": dict(geom="pbc", n=64, alpha=1.0, jscale=1.0, h=0.0, decay=0.1, dephase=0.0, ansatz="ljph",
+                          d=1, n_samples=4096, n_chains=64, n_traj=256, dt=0.005, t_end=1.0, diag_shift=1e-4,
+                          obs_every=20, burn_sweeps=2, thin_sweeps=1, seed=0),
     # N=64 open chain at h = 0, where the site-resolved closed form of App. D is exact
     "chain64_jastrow_h0": dict(geom="obc", n=64, alpha=1.5, jscale=1.0, h=0.0, decay=0.1, dephase=0.0,
                                ansatz="jastrow", n_samples=4096, n_chains=64, n_traj=256, dt=0.005, t_end=1.0,
