@@ -179,8 +179,6 @@ def main():
     w["name"] = args.workload
     kind, nh, m, _ = ansatz_of(tv, w)
     prec = tv.PREC_MFMA if args.precision == "mfma" else tv.PREC_FP64
-    if kind == tv.LJPH:
-        prec = tv.PREC_FP64      # a shared eta's O_k is an integer sum, not +-1: S in FP64
     n, T = w["n"], w["n_traj"]
     print("bench: workload %s N=%d M=%d trajectories=%d samples=%d chains=%d jumps=%d precision=%s proposal=%s" % (
         args.workload, n, m, T, w["n_samples"], w["n_chains"], len(wl.jumps(w)), args.precision,

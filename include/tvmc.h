@@ -58,9 +58,10 @@ typedef enum {
 enum { TVMC_JUMP_SIGMA_MINUS = 0, TVMC_JUMP_SIGMA_PLUS = 1, TVMC_JUMP_SIGMA_Z = 2 };
 enum { TVMC_ANSATZ_JASTROW = 0, TVMC_ANSATZ_RBM = 1, TVMC_ANSATZ_LJPH = 2 };
 enum { TVMC_SCHEME_HEUN = 0, TVMC_SCHEME_MIDPOINT = 1 };
-/* FP64: S accumulated with FP64 vector FMAs.  MFMA: S accumulated on int8 matrix cores; for
- * the Jastrow ansatz every O_k is +-1, so both give the same S bit for bit (the RBM supports
- * FP64 only).  Solve and theta stay FP64 in both. */
+/* FP64: S accumulated with FP64 vector FMAs.  MFMA: for the Jastrow ansaetze S is accumulated on
+ * int8 matrix cores (every O_k is +-1, or an LJPHd distance sum of magnitude <= N-1), exactly,
+ * so both give the same S bit for bit; for the RBM it is the three-term BF16 split with FP32
+ * accumulation.  Solve and theta stay FP64 in both. */
 enum { TVMC_PREC_FP64 = 0, TVMC_PREC_MFMA = 1 };
 
 /* One Lindblad problem (Eq. 1 with the Hamiltonian of Eq. 10), shared by all trajectories of a
@@ -78,8 +79,8 @@ typedef struct {
 typedef struct {
     int32_t kind;                 /* TVMC_ANSATZ_JASTROW, TVMC_ANSATZ_RBM or TVMC_ANSATZ_LJPH */
     int32_t n_hidden;             /* RBM hidden units N', 1..256 (ignored otherwise) */
-    int32_t range;                /* LJPHd: d in [0, N-1] (ignored otherwise); needs TVMC_PREC_FP64 and
-                                     the parameter-space solve (a shared eta's O_k is an integer sum) */
+    int32_t range;                /* LJPHd: d in [0, N-1] (ignored otherwise); solved in parameter space
+                                     (a shared eta's O_k is an integer sum, |O_k| <= N-1) */
 } tvmc_ansatz;
 
 typedef struct {

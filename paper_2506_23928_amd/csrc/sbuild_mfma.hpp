@@ -1,10 +1,12 @@
-// S + eps I for the Jastrow ansatz on the int8 matrix cores (v_mfma_i32_16x16x64_i8).
+// S + eps I for the Jastrow ansaetze on the int8 matrix cores (v_mfma_i32_16x16x64_i8).
 //
-// O_sk is +-1, so sum_s O_sk O_sl is computed exactly as an int32 dot product of +-1 bytes.
+// O_sk is +-1, or for a shared LJPHd distance an integer of magnitude <= N - 1 <= 63, so
+// sum_s O_sk O_sl is computed exactly as an int32 dot product of int8 values.
 // Samples are first transposed to site-major bit planes (bit s of plane i = spin i of sample
 // s is up).  For a 64-sample chunk the sign bits of a parameter row are one XOR of two planes
 // (two-body) or a complement (one-body); four sign bits expand to four +-1 bytes with one
-// multiply.  A 128x128 output tile per workgroup (four waves, 64x64 each, 4x4 MFMA blocks)
+// multiply; a shared-distance row takes one popcount per sample from the packed samples.  A
+// 128x128 output tile per workgroup (four waves, 64x64 each, 4x4 MFMA blocks)
 // amortises that expansion over 128 output columns.  The epilogue centres in FP64 exactly as
 // the plain form does, so both forms give the same bits.
 #pragma once
@@ -31,6 +33,13 @@ constexpr int SB_ROWW = 20;   // u32 words per LDS row: 16 data + 4 padding
 __device__ __forceinline__ uint32_t expand4(uint32_t nib) {
     const uint32_t spread = (nib * 0x00204081u) & 0x01010101u;   // bit j -> byte j
     return 0x01010101u ^ (spread * 0xFEu);                        // 0x01 (+1) or 0xFF (-1)
+}
+
+// four samples' O of a shared distance p (sum of s_j s_{j+p}) as four int8 bytes
+__device__ __forceinline__ uint32_t dist_bytes4(const uint64_t *sp, int p, int n) {
+    uint32_t w = 0;
+    for (int b = 0; b < 4; ++b) w |= (uint32_t)(uint8_t)(int8_t)o_int(sp[b], p, -2, n) << (8 * b);
+    return w;
 }
 
 __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
@@ -64,10 +73,13 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
         const uint32_t na = va ? (aq < 0 ? ~pa_ : (pa_ ^ planes[(size_t)aq * nw + w])) : 0u;
         const uint32_t pb_ = planes[(size_t)bp * nw + w];
         const uint32_t nb = vb ? (bq < 0 ? ~pb_ : (pb_ ^ planes[(size_t)bq * nw + w])) : 0u;
+        const uint64_t *sp = a.samples + (size_t)t * a.ns + (size_t)w * 32;
         __syncthreads();
         for (int q = 0; q < 8; ++q) {
-            As[gr * SB_ROWW + gh * 8 + q] = va ? expand4((na >> (4 * q)) & 0xFu) : 0u;
-            Bs[gr * SB_ROWW + gh * 8 + q] = vb ? expand4((nb >> (4 * q)) & 0xFu) : 0u;
+            As[gr * SB_ROWW + gh * 8 + q] = !va ? 0u : aq == -2 ? dist_bytes4(sp + 4 * q, ap, a.n)
+                                                               : expand4((na >> (4 * q)) & 0xFu);
+            Bs[gr * SB_ROWW + gh * 8 + q] = !vb ? 0u : bq == -2 ? dist_bytes4(sp + 4 * q, bp, a.n)
+                                                               : expand4((nb >> (4 * q)) & 0xFu);
         }
         __syncthreads();
         v4i fa[4], fb[4];

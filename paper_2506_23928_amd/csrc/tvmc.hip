@@ -211,8 +211,9 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
     if (a->kind == TVMC_ANSATZ_LJPH) {
         if (a->range < 0 || a->range > p->n_sites - 1)
             return snprintf(msg, len, "LJPHd range d must be in [0, N-1]"), TVMC_E_INVAL;
-        if (c->precision != TVMC_PREC_FP64)
-            return snprintf(msg, len, "LJPHd builds S in FP64 (its shared O_k are not +-1)"), TVMC_E_INVAL;
+        const int64_t omax = p->n_sites - 1;   // largest |O_k| of a shared distance
+        if (c->precision == TVMC_PREC_MFMA && (int64_t)c->n_samples * omax * omax >= ((int64_t)1 << 31))
+            return snprintf(msg, len, "LJPHd int8 S-build: n_samples (N-1)^2 must stay below 2^31"), TVMC_E_INVAL;
         if (c->solver == TVMC_SOLVER_SAMPLE_SPACE)
             return snprintf(msg, len, "LJPHd solves in parameter space"), TVMC_E_INVAL;
     }

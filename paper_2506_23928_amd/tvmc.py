@@ -242,11 +242,12 @@ class Context:
         ptr += (-ptr) % 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(device=self.workspace.device)
         self.ctx = tvmc_init_batch(self.problems, self.ansatz, config, theta0, ptr, nbytes, self.stream.cuda_stream)
+        self._lib = lib()    # kept for __del__, which may run while the interpreter shuts down
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
         if ctx is not None and ctx.value:
-            lib().tvmc_destroy(ctx)
+            self._lib.tvmc_destroy(ctx)
             self.ctx = None
 
     # stage calls

@@ -64,15 +64,20 @@ def test_configuration_checks_run_on_the_host():
     assert tvmc.tvmc_workspace_size(pb, an, lin) == tvmc.tvmc_workspace_size(pb, an, tvmc.make_config(2, 64, 8, 0.01))
     with pytest.raises(tvmc.TvmcError):
         tvmc.tvmc_workspace_size(pb, an, tvmc.make_config(2, 64, 8, 0.01, unravelling=2))
-    # LJPHd: d in [0, N-1], FP64 S, parameter-space solve; the workspace grows with M
+    # LJPHd: d in [0, N-1], parameter-space solve, exact int8 sums; the workspace grows with M
     lj = tvmc.make_ansatz(tvmc.LJPH, 1)
     assert tvmc.tvmc_workspace_size(pb, lj, tvmc.make_config(2, 64, 8, 0.01)) > 0
     for bad_an, bad_cfg in [(tvmc.make_ansatz(tvmc.LJPH, 4), tvmc.make_config(2, 64, 8, 0.01)),
                             (tvmc.make_ansatz(tvmc.LJPH, -1), tvmc.make_config(2, 64, 8, 0.01)),
-                            (lj, tvmc.make_config(2, 64, 8, 0.01, precision=tvmc.PREC_MFMA)),
                             (lj, tvmc.make_config(2, 64, 8, 0.01, solver=tvmc.SOLVER_SAMPLE_SPACE))]:
         with pytest.raises(tvmc.TvmcError):
             tvmc.tvmc_workspace_size(pb, bad_an, bad_cfg)
+    # the int8 S-build sums n_samples products of magnitude up to (N-1)^2 in int32
+    pb64 = tvmc.Problem(np.zeros((64, 64)), 0.1, [(0, 0, 0.1)])
+    ok = tvmc.make_config(1, 1 << 19, 64, 0.01, precision=tvmc.PREC_MFMA)
+    assert tvmc.tvmc_workspace_size(pb64, lj, ok) > 0
+    with pytest.raises(tvmc.TvmcError):
+        tvmc.tvmc_workspace_size(pb64, lj, tvmc.make_config(1, 1 << 20, 64, 0.01, precision=tvmc.PREC_MFMA))
 
 
 def test_product_couplings_match_the_definition():

@@ -31,14 +31,18 @@ def _rel(a, b):
 @pytest.mark.parametrize("n,d,ns,nc", [(6, 1, 512, 8), (6, 0, 256, 4), (9, 3, 320, 16), (64, 1, 256, 8)])
 def test_ljph_evaluation_parity(tv, orc, n, d, ns, nc):
     """One predictor evaluation and solve of a random problem (sigma^-, sigma^+, sigma^z
-    channels), random parameters, ragged sample counts; N = 64 fills the 64-bit word."""
+    channels), random parameters, ragged sample counts; N = 64 fills the 64-bit word.  S from
+    the FP64 and the int8 S-builds, both bit-exact."""
     from paper_2506_23928_amd import tvmc as T
     J, hx, jumps = wl.random_problem(n, seed=n + d)
     m = orc.n_params(LJPH, n, d)
     th0 = wl.random_theta(m, 0.05, seed=d + 1)
     seed, dt, eps, TT = 6, 0.01, 1e-3, 2
-    for solver in (T.SOLVER_ONE_GROUP, T.SOLVER_MULTI_GROUP):
-        cfg = tv.make_config(TT, ns, nc, dt, eps, seed=seed, traj_offset=3, solver=solver)
+    runs = [(T.SOLVER_ONE_GROUP, tv.PREC_FP64), (T.SOLVER_MULTI_GROUP, tv.PREC_FP64)]
+    if ns % 64 == 0:
+        runs.append((T.SOLVER_ONE_GROUP, tv.PREC_MFMA))   # int8 matrix cores: the same exact S
+    for solver, prec in runs:
+        cfg = tv.make_config(TT, ns, nc, dt, eps, precision=prec, seed=seed, traj_offset=3, solver=solver)
         ctx = tv.Context(tv.Problem(J, hx, jumps), cfg, kind=LJPH, n_hidden=d, theta0=th0)
         ctx.sample()
         ctx.estimate()
@@ -115,3 +119,31 @@ def test_full_range_equals_the_all_pair_jastrow_on_gpu(tv, orc):
         ctx.synchronize()
         out.append([ctx.get(T.Q_THETA, t) for t in range(2)])
     assert all(np.array_equal(a, b) for a, b in zip(*out))
+
+
+def test_ljph1_full_size_launch(tv, orc):
+    """The 64-spin LJPH1 workload (M = 189, 4096 samples, 256 trajectories) in the benchmark's
+    launch configuration (int8 S-build): for the last trajectory the samples, <O_k> and S bit for
+    bit and D against the oracle's evaluation of the same point."""
+    from paper_2506_23928_amd import tvmc as T
+    import bench
+    w = dict(wl.WORKLOADS["chain64_ljph1"])
+    ctx = bench.build_context(tv, w, tv.PREC_MFMA)
+    ctx.sample()
+    ctx.estimate()
+    t = w["n_traj"] - 1
+    S = ctx.get(T.Q_S, t)
+    ctx.synchronize()
+    J = orc.couplings(w["geom"], w["n"], w["alpha"], w["jscale"])
+    pb = orc.Problem(J, w["h"], wl.jumps(w))
+    cfg = orc.Config(n_samples=w["n_samples"], n_chains=w["n_chains"], burn_sweeps=w["burn_sweeps"],
+                     thin_sweeps=w["thin_sweeps"], dt=w["dt"], diag_shift=w["diag_shift"], seed=w["seed"])
+    m = orc.n_params(LJPH, w["n"], w["d"])
+    chains = orc.init_chains(w["seed"], t, w["n"], w["n_chains"])
+    dw = orc.draw_dw(w["seed"], t, 0, len(wl.jumps(w)), w["dt"])
+    r = orc.evaluate(pb, LJPH, w["d"], cfg, np.zeros(m), chains, traj=t, first=True, dw=dw, want_moments=False)
+    assert np.array_equal(tv.unpack_samples(ctx.get(T.Q_SAMPLES, t), w["n"]), r["samples"])
+    assert np.array_equal(ctx.get(T.Q_OBAR, t), r["obar"].real)
+    low = np.tril_indices(m)
+    assert np.array_equal(S[low], (r["S"].real + w["diag_shift"] * np.eye(m))[low])
+    assert _rel(ctx.get(T.Q_D, t), r["D"]) < 1e-12

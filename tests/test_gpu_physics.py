@@ -50,3 +50,41 @@ def test_n64_squeezing_matches_appendix_d(orc):
         assert abs(M[0] - Me[0]) < 4 * se_mx + 1e-3, (t, M[0], Me[0], se_mx)
         assert abs(x2 - xe) < 4 * se_x2 + 5e-3, (t, x2, xe, se_x2)
         assert xe < 0.9          # the comparison is made where the state is squeezed
+
+
+def test_n64_ljph1_matches_appendix_d(orc):
+    """The LJPH1 ansatz (M = 3N - 3 = 189) on the periodic chain of the paper's large-N quench
+    (alpha = 1, h = 0, decay 0.1), here at N = 64: 4096 samples, 64 trajectories, int8 S-build,
+    against App. D up to t = 0.3 with the same budget as the all-pair Jastrow above.  (The
+    ansatz is an approximation: later, near the squeezing minimum, it drifts off by a few 1e-3.)"""
+    import torch
+    assert torch.cuda.is_available()
+    import oracle.exact as ex
+    import paper_2506_23928_amd as tv
+    from paper_2506_23928_amd import tvmc as T
+    from paper_2506_23928_amd.problem import kac_couplings
+    n, gamma, ns, nc, TT, dt = 64, 0.1, 4096, 64, 64, 0.005
+    obs_every, steps = 20, 60
+    J = kac_couplings("pbc", n, 1.0, 1.0)
+    jumps = [(tv.SIGMA_MINUS, i, gamma) for i in range(n)]
+    nobs = steps // obs_every
+    cfg = tv.make_config(TT, ns, nc, dt, 1e-4, 2, 1, 0, tv.HEUN, tv.PREC_MFMA, obs_every, nobs, 11)
+    ctx = tv.Context(tv.Problem(J, 0.0, jumps), cfg, kind=T.LJPH, n_hidden=1)
+    ctx.sde_step(steps)
+    ctx.sample()
+    ctx.observables()
+    ctx.synchronize()
+    hist = np.stack([ctx.get(T.Q_OBS_HIST, t) for t in range(TT)])[:, :nobs]
+    final = np.stack([ctx.get(T.Q_MOMENTS, t) for t in range(TT)])
+    mom = np.concatenate([hist, final[:, None]], axis=1)
+    Jo = orc.couplings("pbc", n, 1.0, 1.0)
+    for k in range(1, nobs + 1):
+        t = k * obs_every * dt
+        M, C, x2 = orc.ensemble(mom[:, k], n)
+        Me, Ce = ex.appd_general(Jo, gamma, t)
+        xe = ex.xi2(Me, Ce, n)
+        se_x2 = _jack(mom[:, k], lambda v: orc.ensemble(v, n)[2])
+        se_mx = _jack(mom[:, k, 0], lambda v: v.mean())
+        assert abs(M[0] - Me[0]) < 4 * se_mx + 1e-3, (t, M[0], Me[0], se_mx)
+        assert abs(x2 - xe) < 4 * se_x2 + 5e-3, (t, x2, xe, se_x2)
+        assert xe < 0.9
