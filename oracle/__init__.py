@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "libotvmc_oracle.so")
 SIGMA_MINUS, SIGMA_PLUS, SIGMA_Z = 0, 1, 2
 JASTROW, RBM, LJPH = 0, 1, 2
 HEUN, MIDPOINT, EULER = 0, 1, 2
+REG_SHIFT, REG_SNR = 0, 1
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_dp = ctypes.POINTER(ctypes.c_double)
@@ -52,13 +53,13 @@ class _Config(ctypes.Structure):
                 ("thin_sweeps", ctypes.c_int32), ("init_sweeps", ctypes.c_int32), ("enumerate", ctypes.c_int32),
                 ("dt", ctypes.c_double), ("diag_shift", ctypes.c_double), ("scheme", ctypes.c_int32),
                 ("n_steps", ctypes.c_int32), ("obs_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("linear", ctypes.c_int32)]
+                ("linear", ctypes.c_int32), ("regulariser", ctypes.c_int32), ("snr_tau", ctypes.c_double)]
 
 
 class _EvalOut(ctypes.Structure):
     _fields_ = [("samples", _c_i8p), ("eloc", _c_dp), ("S", _c_dp), ("F", _c_dp), ("Nn", _c_dp), ("D", _c_dp),
                 ("bmean", _c_dp), ("obar", _c_dp), ("delta", _c_dp), ("accepts", _c_i64p), ("obs", _c_dp),
-                ("seconds", _c_dp), ("dlognorm", _c_dp)]
+                ("seconds", _c_dp), ("dlognorm", _c_dp), ("eig", _c_dp)]
 
 
 def build(force: bool = True) -> str:
@@ -189,14 +190,28 @@ def local_quantities(kind, n, n_hidden, theta, sigma, two_flip=True):
 
 class Config:
     def __init__(self, n_samples=1024, n_chains=16, burn_sweeps=2, thin_sweeps=1, init_sweeps=0, enumerate=False,
-                 dt=0.01, diag_shift=1e-4, scheme=HEUN, n_steps=1, obs_every=0, seed=0, linear=False):
+                 dt=0.01, diag_shift=1e-4, scheme=HEUN, n_steps=1, obs_every=0, seed=0, linear=False,
+                 regulariser=0, snr_tau=4.0):
         self.__dict__.update(locals())
         del self.__dict__["self"]
 
     def _c(self):
         return _Config(self.n_samples, self.n_chains, self.burn_sweeps, self.thin_sweeps, self.init_sweeps,
                        int(bool(self.enumerate)), self.dt, self.diag_shift, self.scheme, self.n_steps,
-                       self.obs_every, ctypes.c_uint64(self.seed), int(bool(self.linear)))
+                       self.obs_every, ctypes.c_uint64(self.seed), int(bool(self.linear)), int(self.regulariser),
+                       float(self.snr_tau))
+
+
+def eigh_sym(A):
+    """The oracle's cyclic-Jacobi eigen-decomposition of a real symmetric matrix -> (lam, V)."""
+    A = np.array(A, dtype=np.float64, order="C")
+    m = A.shape[0]
+    V = np.zeros((m, m))
+    lam = np.zeros(m)
+    st = lib().orc_eigh_sym(ctypes.c_int32(m), _p(A, _c_dp), _p(V, _c_dp), _p(lam, _c_dp))
+    if st:
+        raise RuntimeError("Jacobi did not converge")
+    return lam, V
 
 
 def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, chains, traj=0, step=0, stage=0,
@@ -220,7 +235,7 @@ def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, cha
         "Nn": np.zeros((max(nch, 1), m), np.complex128), "D": np.zeros(m, np.complex128),
         "bmean": np.zeros(max(nch, 1), np.complex128), "obar": np.zeros(m, np.complex128),
         "delta": np.zeros(m, np.complex128), "accepts": np.zeros(max(cfg.n_chains, 1), np.int64),
-        "obs": np.zeros(9), "seconds": np.zeros(3), "dlognorm": np.zeros(1),
+        "obs": np.zeros(9), "seconds": np.zeros(3), "dlognorm": np.zeros(1), "eig": np.zeros((m, 2)),
     }
     eo = _EvalOut(_p(r["samples"], _c_i8p), _p(r["eloc"].view(np.float64), _c_dp),
                   _p(r["S"].view(np.float64), _c_dp), _p(r["F"].view(np.float64), _c_dp),
@@ -228,7 +243,7 @@ def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, cha
                   _p(r["bmean"].view(np.float64), _c_dp), _p(r["obar"].view(np.float64), _c_dp),
                   _p(r["delta"].view(np.float64), _c_dp), _p(r["accepts"], _c_i64p),
                   _p(r["obs"], _c_dp) if want_moments else None, _p(r["seconds"], _c_dp),
-                  _p(r["dlognorm"], _c_dp))
+                  _p(r["dlognorm"], _c_dp), _p(r["eig"], _c_dp))
     ch = chains if chains is not None else np.zeros((1, n), np.int8)
     assert ch.dtype == np.int8 and ch.flags.c_contiguous
     pc = problem._c()

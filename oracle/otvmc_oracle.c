@@ -62,7 +62,12 @@ typedef struct {
     int32_t n_steps, obs_every;
     uint64_t seed;
     int32_t linear;        /* 1: the linear SSE of App. B (E_eff^lin, norm SDE, weighted averages) */
+    int32_t regulariser;   /* ORC_REG_SHIFT: (S + eps I) delta = D by Cholesky; ORC_REG_SNR: the
+                              signal-to-noise filter in the eigenbasis of S + eps I (real S only) */
+    double snr_tau;        /* SNR threshold of the filter */
 } orc_config;
+
+enum { ORC_REG_SHIFT = 0, ORC_REG_SNR = 1 };
 
 typedef struct {           /* optional outputs of one evaluation (any pointer may be NULL) */
     int8_t *samples;       /* [n_samples][N], +-1 */
@@ -78,6 +83,7 @@ typedef struct {           /* optional outputs of one evaluation (any pointer ma
     double *obs;           /* [9] per-trajectory moments (see orc_moments) */
     double *seconds;       /* [3] wall time of: sampling and local quantities; means, S, F, N^n, D; solve */
     double *dlognorm;      /* [1] linear SSE: increment of log Q over the step (App. B, norm SDE) */
+    double *eig;           /* [M][2] SNR solve: eigenvalue of S + eps I and the SNR of D's component */
 } orc_eval_out;
 
 /* ------------------------------------------------------------------ Philox4x32-10 */
@@ -424,6 +430,96 @@ static double wall_seconds(void)
     return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
 }
 
+/* ------------------------------------------------------------------ SNR-regularised solve */
+
+/* Eigen-decomposition A = V diag(lam) V^T of a real symmetric m x m matrix (row-major, destroyed)
+ * by cyclic Jacobi rotations: every off-diagonal pair (p, q) in turn is zeroed by the plane
+ * rotation with t = tan(phi) the smaller root of t^2 + 2 t theta - 1 = 0,
+ * theta = (A_qq - A_pp) / (2 A_pq), until the off-diagonal mass is below 1e-30 of the total. */
+int orc_eigh_sym(int32_t m, double *A, double *V, double *lam)
+{
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) V[(size_t)i * m + j] = (i == j) ? 1.0 : 0.0;
+    int sweep = 0;
+    for (; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                double a = A[(size_t)i * m + j];
+                tot += a * a;
+                if (i != j) off += a * a;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                double apq = A[(size_t)p * m + q];
+                if (apq == 0.0) continue;
+                double theta = (A[(size_t)q * m + q] - A[(size_t)p * m + p]) / (2.0 * apq);
+                double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < m; ++k) {   /* columns p, q: A J */
+                    double akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
+                    A[(size_t)k * m + p] = c * akp - sn * akq;
+                    A[(size_t)k * m + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < m; ++k) {   /* rows p, q: J^T (A J) */
+                    double apk = A[(size_t)p * m + k], aqk = A[(size_t)q * m + k];
+                    A[(size_t)p * m + k] = c * apk - sn * aqk;
+                    A[(size_t)q * m + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < m; ++k) {   /* V J */
+                    double vkp = V[(size_t)k * m + p], vkq = V[(size_t)k * m + q];
+                    V[(size_t)k * m + p] = c * vkp - sn * vkq;
+                    V[(size_t)k * m + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < m; ++i) lam[i] = A[(size_t)i * m + i];
+    return sweep < 100 ? ORC_OK : ORC_E_NUMERIC;
+}
+
+/* The regulariser named in the text after Eq. 9: D is written in the eigenbasis of S, and each
+ * component rho_k = (V^T D)_k is kept in proportion to its signal-to-noise ratio.  With the
+ * per-sample contributions q_k(x) = u_k(x) (G(x) - <G>), u_k(x) = sum_l V_lk (O_l(x) - <O_l>),
+ * whose mean is rho_k: SNR_k = |rho_k| sqrt(N_s) / sqrt(<|q_k|^2> - |rho_k|^2), and
+ *   delta = sum_k V_k rho_k / lam_k * 1 / (1 + (tau / SNR_k)^6),
+ * the smooth cutoff of Schmitt and Heyl's scheme; eigenvalues below 1e-14 of the largest are
+ * dropped.  Real S only (O_k real): the Jastrow ansaetze. */
+static int snr_solve(int m, int ns, const double *wgt, double norm, const cplx *O, const cplx *ob, const cplx *S,
+                     double eps, const cplx *dG, double tau, cplx *D, double *eig_out)
+{
+    double *A = malloc(sizeof(double) * (size_t)m * m), *V = malloc(sizeof(double) * (size_t)m * m);
+    double *lam = malloc(sizeof(double) * m), *u = malloc(sizeof(double) * ns);
+    cplx *rho = malloc(sizeof(cplx) * m), *dl = calloc(m, sizeof(cplx));
+    if (!A || !V || !lam || !u || !rho || !dl) return ORC_E_NOMEM;
+    for (int k = 0; k < m; ++k)
+        for (int l = 0; l < m; ++l) A[(size_t)k * m + l] = creal(S[(size_t)k * m + l]) + (k == l ? eps : 0.0);
+    int st = orc_eigh_sym(m, A, V, lam);
+    double lmax = 0.0;
+    for (int k = 0; k < m; ++k) lmax = fmax(lmax, lam[k]);
+    for (int k = 0; k < m && st == ORC_OK; ++k) {
+        cplx r = 0.0;
+        for (int l = 0; l < m; ++l) r += V[(size_t)l * m + k] * D[l];
+        rho[k] = r;
+        double q2 = 0.0;
+        for (int x = 0; x < ns; ++x) {
+            double v = 0.0;
+            for (int l = 0; l < m; ++l) v += V[(size_t)l * m + k] * creal(O[(size_t)l * ns + x] - ob[l]);
+            u[x] = v;
+            q2 += wgt[x] * v * v * (creal(dG[x]) * creal(dG[x]) + cimag(dG[x]) * cimag(dG[x]));
+        }
+        double var = q2 * norm - (creal(r) * creal(r) + cimag(r) * cimag(r));
+        double snr = var > 0.0 ? cabs(r) * sqrt((double)ns) / sqrt(var) : INFINITY;
+        double keep = (lam[k] > 1e-14 * lmax && cabs(r) > 0.0) ? 1.0 / (1.0 + pow(tau / snr, 6.0)) : 0.0;
+        if (eig_out) { eig_out[2 * k] = lam[k]; eig_out[2 * k + 1] = snr; }
+        if (keep > 0.0)
+            for (int l = 0; l < m; ++l) dl[l] += V[(size_t)l * m + k] * (keep * rho[k] / lam[k]);
+    }
+    for (int l = 0; l < m; ++l) D[l] = dl[l];
+    free(A); free(V); free(lam); free(u); free(rho); free(dl);
+    return st;
+}
+
 static int chol_solve(int m, cplx *A, cplx *b)
 {
     for (int j = 0; j < m; ++j) {
@@ -637,7 +733,22 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
         }
         /* regularised solve (S + eps I) delta = D */
         t2 = wall_seconds();
-        if (want_solve == 1) {
+        if (want_solve == 1 && cf->regulariser == ORC_REG_SNR && an->kind == ORC_RBM) {
+            status = ORC_E_INVAL;
+        } else if (want_solve == 1 && cf->regulariser == ORC_REG_SNR) {
+            cplx *dG = malloc(sizeof(cplx) * ns), gm = 0.0;
+            if (!dG) return ORC_E_NOMEM;
+            for (int x = 0; x < ns; ++x) {   /* G(x) = -i dt E_eff(x) + sum_n dW_n B^n(x) */
+                cplx g = -I * cf->dt * eeff[x];
+                for (int c = 0; c < nch; ++c) g += dw[c] * B[(size_t)c * ns + x];
+                dG[x] = g;
+                gm += wgt[x] * g;
+            }
+            gm *= norm;
+            for (int x = 0; x < ns; ++x) dG[x] -= gm;
+            status = snr_solve(m, ns, wgt, norm, O, ob, S, cf->diag_shift, dG, cf->snr_tau, D, out ? out->eig : NULL);
+            free(dG);
+        } else if (want_solve == 1) {
             for (int k = 0; k < m; ++k) S[(size_t)k * m + k] += cf->diag_shift;
             status = chol_solve(m, S, D);
         } else if (want_solve == 3) {

@@ -1,0 +1,105 @@
+"""Pins of the oracle's SNR-regularised solve (the regulariser named in the text after Eq. 9).
+
+The functional form (smooth cutoff 1 / (1 + (tau / SNR)^6) in S's eigenbasis) comes from the
+scheme the paper cites and does not reproduce, so it is pinned by what fixes it independently:
+  the Jacobi eigen-decomposition against LAPACK (numpy.linalg.eigh)
+  tau = 0 keeps every component: the Cholesky solve of (S + eps I) delta = D
+  tau -> infinity removes every component: delta = 0
+  one spin (M = 1) with the closed-form local energy h exp(-2 a s): the filter by hand
+  G scaled by c (dt -> c dt, no jumps): SNR unchanged, delta scaled by c
+"""
+import numpy as np
+import pytest
+
+
+
+@pytest.mark.parametrize("m", [1, 2, 7, 40])
+def test_jacobi_matches_lapack(orc, m):
+    rng = np.random.default_rng(m)
+    X = rng.standard_normal((m, m))
+    A = X + X.T
+    lam, V = orc.eigh_sym(A)
+    ref = np.linalg.eigvalsh(A)
+    assert np.abs(np.sort(lam) - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+    assert np.abs(V.T @ V - np.eye(m)).max() < 1e-13
+    assert np.abs(A @ V - V * lam[None, :]).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def _case(orc, kind, nh, n=6, jumps=True, dt=0.01, seed=1):
+    J = orc.couplings("obc", n, 1.5, 1.0)
+    js = [(0, i, 0.2) for i in range(n)] if jumps else []
+    pb = orc.Problem(J, 0.8, js)
+    m = orc.n_params(kind, n, nh)
+    th = 0.1 * (np.random.default_rng(seed).standard_normal(m) + 1j * np.random.default_rng(seed + 1).standard_normal(m))
+    dw = orc.draw_dw(3, 0, 0, len(js), dt) if js else None
+    return pb, th, dw, m
+
+
+def _eval(orc, pb, kind, nh, th, dw, **cfg):
+    c = orc.Config(n_samples=256, n_chains=8, seed=3, **cfg)
+    r = orc.evaluate(pb, kind, nh, c, th, orc.init_chains(3, 0, pb.n, 8), dw=dw)
+    assert r["status"] == 0
+    return r
+
+
+@pytest.mark.parametrize("kind,nh", [(0, 0), (2, 1)])
+def test_tau_zero_is_the_regularised_solve(orc, kind, nh):
+    pb, th, dw, m = _case(orc, kind, nh)
+    r0 = _eval(orc, pb, kind, nh, th, dw, diag_shift=1e-3)
+    r1 = _eval(orc, pb, kind, nh, th, dw, diag_shift=1e-3, regulariser=orc.REG_SNR, snr_tau=0.0)
+    assert np.abs(r1["delta"] - r0["delta"]).max() < 1e-10 * np.abs(r0["delta"]).max()
+    lam = np.sort(r1["eig"][:, 0])
+    ref = np.linalg.eigvalsh(r0["S"].real + 1e-3 * np.eye(m))
+    assert np.abs(lam - ref).max() < 1e-13
+
+
+def test_infinite_tau_removes_everything(orc):
+    pb, th, dw, m = _case(orc, 0, 0)
+    r = _eval(orc, pb, 0, 0, th, dw, diag_shift=1e-3, regulariser=orc.REG_SNR, snr_tau=1e300)
+    assert np.all(r["delta"] == 0)
+
+
+def test_filter_acts_on_noisy_components(orc):
+    pb, th, dw, m = _case(orc, 0, 0)
+    r0 = _eval(orc, pb, 0, 0, th, dw, diag_shift=1e-3)
+    r4 = _eval(orc, pb, 0, 0, th, dw, diag_shift=1e-3, regulariser=orc.REG_SNR, snr_tau=4.0)
+    snr = r4["eig"][:, 1]
+    assert (snr < 4).any() and (snr > 4).any()
+    assert np.abs(r4["delta"] - r0["delta"]).max() > 1e-3 * np.abs(r0["delta"]).max()
+
+
+def test_single_spin_by_hand(orc):
+    # N = 1, H = h sigma^x, no jumps: O(s) = s, E_loc(s) = h psi(-s)/psi(s) = h exp(-2 a s),
+    # G(s) = -i dt E_loc(s); M = 1, so the eigenbasis is trivial and everything is by hand
+    h, dt, eps, tau = 0.7, 0.02, 1e-4, 4.0
+    pb = orc.Problem(np.zeros((1, 1)), h, [])
+    a = 0.3 - 0.2j
+    cfg = orc.Config(n_samples=64, n_chains=4, seed=5, dt=dt, diag_shift=eps, regulariser=orc.REG_SNR, snr_tau=tau)
+    r = orc.evaluate(pb, 0, 0, cfg, np.array([a]), orc.init_chains(5, 0, 1, 4))
+    s = r["samples"][:, 0].astype(np.float64)
+    ns = s.size
+    G = -1j * dt * h * np.exp(-2 * a * s)
+    dO, dG = s - s.mean(), G - G.mean()
+    lam = np.mean(dO * dO) + eps
+    rho = np.mean(dO * dG)
+    var = np.mean(np.abs(dO * dG) ** 2) - abs(rho) ** 2
+    snr = abs(rho) * np.sqrt(ns) / np.sqrt(var)
+    want = rho / lam / (1 + (tau / snr) ** 6)
+    assert abs(r["eig"][0, 0] - lam) < 1e-15
+    assert r["eig"][0, 1] == pytest.approx(snr, rel=1e-12)
+    assert r["delta"][0] == pytest.approx(want, rel=1e-12)
+
+
+def test_scale_invariance_of_the_filter(orc):
+    pb, th, _, m = _case(orc, 0, 0, jumps=False)
+    r1 = _eval(orc, pb, 0, 0, th, None, dt=0.01, diag_shift=1e-3, regulariser=orc.REG_SNR)
+    r2 = _eval(orc, pb, 0, 0, th, None, dt=0.03, diag_shift=1e-3, regulariser=orc.REG_SNR)
+    assert np.allclose(r1["eig"], r2["eig"], rtol=1e-10, atol=0)
+    assert np.abs(r2["delta"] - 3 * r1["delta"]).max() < 1e-12 * np.abs(r2["delta"]).max()
+
+
+def test_rbm_is_rejected(orc):
+    pb, th, dw, m = _case(orc, 1, 2, n=4)
+    c = orc.Config(n_samples=64, n_chains=4, seed=3, regulariser=orc.REG_SNR)
+    r = orc.evaluate(pb, 1, 2, c, th, orc.init_chains(3, 0, 4, 4), dw=dw)
+    assert r["status"] != 0
