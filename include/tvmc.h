@@ -108,7 +108,20 @@ typedef struct {
     double ar_lr;                 /* Adam learning rate */
     int32_t solver;               /* TVMC_SOLVER_*: how the regularised system is solved */
     int32_t unravelling;          /* TVMC_SSE_*: which stochastic Schroedinger equation is unravelled */
+    int32_t regulariser;          /* TVMC_REG_*: how (S + eps I) delta = D is regularised */
+    double snr_tau;               /* TVMC_REG_SNR: the SNR threshold (the paper uses 4) */
 } tvmc_config;
+
+/* SHIFT: the Cholesky solve of (S + eps I) delta = D.  SNR: the regulariser the paper names in
+ * the text after Eq. 9: D in the eigenbasis of S + eps I (S + eps I = V diag(lam) V^T), each
+ * component rho_k = (V^T D)_k kept with weight 1 / (1 + (tau / SNR_k)^6), where SNR_k =
+ * |rho_k| sqrt(N_s) / sqrt(<|q_k|^2> - |rho_k|^2) over the per-sample contributions
+ * q_k(x) = u_k(x) (G(x) - <G>), u_k(x) = sum_l V_lk (O_l(x) - <O_l>), G(x) = -i dt E_eff(x)
+ * + sum_n B^n(x) dW_n; delta = sum_k V_k keep_k rho_k / lam_k, eigenvalues below 1e-14 of the
+ * largest dropped.  Real S only (the Jastrow ansaetze), parameter space, M <= 2176; eps may be
+ * 0.  The eigen-decomposition (parallel Jacobi) overwrites S: after tvmc_sr_solve, TVMC_Q_S
+ * holds diag(lam) up to rounding, and TVMC_Q_EIG the pairs (lam_k, SNR_k). */
+enum { TVMC_REG_SHIFT = 0, TVMC_REG_SNR = 1 };
 
 /* NONLINEAR: the norm-preserving SSE of Eq. 2 (Stratonovich form Eqs. 4-5).  LINEAR: the linear
  * SSE of App. B: E_eff becomes the local value of H - (i/2) sum_n (L_n^dag L_n + L_n^2) (no
@@ -154,7 +167,8 @@ enum {
     TVMC_Q_AR_LOSS = 18,    /* double[1] mean negative log-likelihood */
     TVMC_Q_AR_ACCEPTS = 19, /* uint32[n_chains] accepted learned proposals in the last sampling */
     TVMC_Q_LOGNORM = 20,    /* double[1] log Q of the linear SSE at the current step (0 for the nonlinear SSE) */
-    TVMC_Q_LOGNORM_HIST = 21  /* double[n_obs_max] log Q at the times of the moment history */
+    TVMC_Q_LOGNORM_HIST = 21, /* double[n_obs_max] log Q at the times of the moment history */
+    TVMC_Q_EIG = 22           /* double[2M] (lam_k, SNR_k) of the last SNR solve, in the solver's order */
 };
 
 /* Bytes of device workspace needed for this problem, ansatz and configuration. */

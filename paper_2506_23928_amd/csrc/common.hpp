@@ -156,6 +156,13 @@ struct Dev {
     double *dq0;              // [T] predictor-stage increment of log Q
     double *momlq;            // [T] log Q when the moments in mom were taken
     double *qhist;            // [nobs][T] log Q at the history records
+    // SNR-regularised solve (real S)
+    int reg, snr_nxb;         // regulariser (1: SNR), 64-sample blocks of the variance sums
+    double snr_tau;
+    double *snrV;             // [T][M][M] eigenvectors as rows (V^T)
+    double2 *snrRho, *snrW;   // [T][M] V^T D and the kept, scaled components
+    double *snrEig;           // [T][M][2] eigenvalue, SNR
+    double *snrPart;          // [T][snr_nxb][M] partial sums of u_k^2 |G - <G>|^2
     // learned proposal (MADE): hidden width, parameter count per trajectory, buffers
     int ar, ah;
     size_t arnp;

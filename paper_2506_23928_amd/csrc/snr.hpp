@@ -1,0 +1,239 @@
+// SNR-regularised solve (the regulariser named in the text after Eq. 9) for a real symmetric S
+// (the Jastrow ansaetze): D is written in the eigenbasis of S + eps I and each component
+// rho_k = (V^T D)_k is kept with weight 1 / (1 + (tau / SNR_k)^6), the smooth cutoff of Schmitt
+// and Heyl's scheme, where SNR_k = |rho_k| sqrt(N_s) / sqrt(<|q_k|^2> - |rho_k|^2) is computed
+// from the per-sample contributions q_k(x) = u_k(x) (G(x) - <G>), u_k(x) = sum_l V_lk
+// (O_l(x) - <O_l>), whose mean is rho_k.  delta = sum_k V_k keep_k rho_k / lam_k; eigenvalues
+// below 1e-14 of the largest are dropped.
+//
+// Eigen-decomposition: parallel two-sided Jacobi, one workgroup per trajectory, in place on the
+// trajectory's S (global memory, L2 / Infinity-Cache resident).  A sweep is M' - 1 rounds of
+// M'/2 disjoint rotations (round-robin pairing, M' = M rounded up to even, the odd index out
+// paired with a dummy); a round computes every rotation from the current matrix, then applies
+// all of them to the rows (A <- J^T A, and to V^T), then to the columns (A <- A J).  Sweeps
+// continue until the off-diagonal mass is below 1e-30 of the total.
+#pragma once
+#include "common.hpp"
+
+namespace tvmc {
+
+constexpr int JAC_THREADS = 1024;
+constexpr int JAC_MAXP = 1088;       // rotation pairs per round: M <= 2176
+constexpr int JAC_MAX_SWEEPS = 40;
+
+// S + eps I (lower triangle) -> full symmetric matrix; V^T = I
+__global__ void k_snr_init(Dev a) {
+    const int t = blockIdx.y;
+    const size_t mm = (size_t)a.m * a.m;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= mm) return;
+    const int i = (int)(idx / a.m), j = (int)(idx % a.m);
+    double *S = a.S + (size_t)t * mm;
+    if (j > i) S[idx] = S[(size_t)j * a.m + i];
+    a.snrV[(size_t)t * mm + idx] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(Dev a) {
+    __shared__ int sp[JAC_MAXP], sq[JAC_MAXP];
+    __shared__ double sc[JAC_MAXP], ss[JAC_MAXP];
+    __shared__ double red[JAC_THREADS / 64][2];
+    __shared__ int done;
+    const int t = blockIdx.x, m = a.m;
+    const int mp = m + (m & 1), K = mp - 1, np = mp / 2;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *A = a.S + (size_t)t * m * m;
+    double *Vt = a.snrV + (size_t)t * m * m;
+    for (int sweep = 0;; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int e = tid; e < m * m; e += JAC_THREADS) {
+            const double v = A[e];
+            tot += v * v;
+            if (e / m != e % m) off += v * v;
+        }
+        off = wave_sum(off);
+        tot = wave_sum(tot);
+        if (lane == 0) {
+            red[wave][0] = off;
+            red[wave][1] = tot;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double o = 0.0, s = 0.0;
+            for (int w = 0; w < JAC_THREADS / 64; ++w) {
+                o += red[w][0];
+                s += red[w][1];
+            }
+            done = (o <= 1e-30 * s) ? 1 : (sweep == JAC_MAX_SWEEPS ? -1 : 0);
+        }
+        __syncthreads();
+        if (done != 0) break;
+        for (int r = 0; r < K; ++r) {
+            for (int i = tid; i < np; i += JAC_THREADS) {
+                int p = i == 0 ? r : (r + i) % K;
+                int q = i == 0 ? K : (r - i + K) % K;
+                if (p > q) {
+                    const int x = p;
+                    p = q;
+                    q = x;
+                }
+                double c = 1.0, s = 0.0;
+                if (q < m) {
+                    const double apq = A[(size_t)p * m + q];
+                    if (apq != 0.0) {
+                        const double theta = (A[(size_t)q * m + q] - A[(size_t)p * m + p]) / (2.0 * apq);
+                        const double tn = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                        c = 1.0 / sqrt(tn * tn + 1.0);
+                        s = tn * c;
+                    }
+                }
+                sp[i] = p;
+                sq[i] = q;
+                sc[i] = c;
+                ss[i] = s;
+            }
+            __syncthreads();
+            for (int e = tid; e < np * m; e += JAC_THREADS) {   // rows p, q of A and of V^T
+                const int i = e / m, j = e % m, p = sp[i], q = sq[i];
+                if (q >= m) continue;
+                const double c = sc[i], s = ss[i];
+                const double apj = A[(size_t)p * m + j], aqj = A[(size_t)q * m + j];
+                A[(size_t)p * m + j] = c * apj - s * aqj;
+                A[(size_t)q * m + j] = s * apj + c * aqj;
+                const double vpj = Vt[(size_t)p * m + j], vqj = Vt[(size_t)q * m + j];
+                Vt[(size_t)p * m + j] = c * vpj - s * vqj;
+                Vt[(size_t)q * m + j] = s * vpj + c * vqj;
+            }
+            __syncthreads();
+            for (int e = tid; e < np * m; e += JAC_THREADS) {   // columns p, q of A
+                const int i = e % np, k = e / np, p = sp[i], q = sq[i];
+                if (q >= m) continue;
+                const double c = sc[i], s = ss[i];
+                const double akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
+                A[(size_t)k * m + p] = c * akp - s * akq;
+                A[(size_t)k * m + q] = s * akp + c * akq;
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0 && done < 0) a.flags[t] = 1;
+}
+
+// rho_k = sum_l V_lk D_l
+__global__ void k_snr_rho(Dev a) {
+    const int t = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.m) return;
+    const double *v = a.snrV + ((size_t)t * a.m + k) * a.m;
+    const double2 *D = a.D + (size_t)t * a.m;
+    double re = 0.0, im = 0.0;
+    for (int l = 0; l < a.m; ++l) {
+        re += v[l] * D[l].x;
+        im += v[l] * D[l].y;
+    }
+    a.snrRho[(size_t)t * a.m + k] = make_double2(re, im);
+}
+
+// Partial sums over 64-sample blocks of u_k(x)^2 |G(x) - <G>|^2: a 64 x 64 (eigenvector x
+// sample) tile per workgroup, u = V^T (O - <O>) accumulated over 32-row slabs staged in LDS
+// (O_l(x) recomputed from the packed samples), 4 x 4 outputs per thread.
+constexpr int SV_K = 64, SV_X = 64, SV_L = 32;
+__global__ __launch_bounds__(256) void k_snr_var(Dev a) {
+    __shared__ double vs[SV_K][SV_L + 1];
+    __shared__ double os[SV_L][SV_X + 1];
+    __shared__ double red[16][SV_K];
+    const int t = blockIdx.z, k0 = blockIdx.x * SV_K, x0 = blockIdx.y * SV_X;
+    const int tid = threadIdx.x, tk = tid >> 4, tx = tid & 15;
+    const int m = a.m, ns = a.ns;
+    const double *Vt = a.snrV + (size_t)t * m * m;
+    const uint64_t *smp = a.samples + (size_t)t * ns;
+    const double *ob = a.obar + (size_t)t * m;
+    double u[4][4] = {};
+    for (int l0 = 0; l0 < m; l0 += SV_L) {
+        __syncthreads();
+        for (int e = tid; e < SV_K * SV_L; e += 256) {
+            const int kk = e / SV_L, ll = e % SV_L, k = k0 + kk, l = l0 + ll;
+            vs[kk][ll] = (k < m && l < m) ? Vt[(size_t)k * m + l] : 0.0;
+        }
+        for (int e = tid; e < SV_L * SV_X; e += 256) {
+            const int ll = e / SV_X, xx = e % SV_X, l = l0 + ll, x = x0 + xx;
+            os[ll][xx] = (l < m && x < ns) ? (double)o_int(smp[x], a.pa[l], a.pb[l], a.n) - ob[l] : 0.0;
+        }
+        __syncthreads();
+        for (int ll = 0; ll < SV_L; ++ll) {
+            double v[4], o[4];
+            for (int i = 0; i < 4; ++i) v[i] = vs[tk * 4 + i][ll];
+            for (int j = 0; j < 4; ++j) o[j] = os[ll][tx * 4 + j];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) u[i][j] += v[i] * o[j];
+        }
+    }
+    const double2 gb = a.gbar[t];
+    double g2[4];
+    for (int j = 0; j < 4; ++j) {
+        const int x = x0 + tx * 4 + j;
+        g2[j] = 0.0;
+        if (x < ns) {
+            const double2 g = a.G[(size_t)t * ns + x];
+            const double dr = g.x - gb.x, di = g.y - gb.y;
+            g2[j] = dr * dr + di * di;
+        }
+    }
+    for (int i = 0; i < 4; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < 4; ++j) s += u[i][j] * u[i][j] * g2[j];
+        red[tx][tk * 4 + i] = s;
+    }
+    __syncthreads();
+    if (tid < SV_K && k0 + tid < m) {
+        double s = 0.0;
+        for (int q = 0; q < 16; ++q) s += red[q][tid];
+        a.snrPart[((size_t)t * a.snr_nxb + blockIdx.y) * m + k0 + tid] = s;
+    }
+}
+
+// SNR_k, the kept weight and w_k = keep_k rho_k / lam_k; (lam_k, SNR_k) kept for inspection
+__global__ __launch_bounds__(256) void k_snr_finish(Dev a) {
+    __shared__ double red[4];
+    const int t = blockIdx.x, m = a.m, tid = threadIdx.x;
+    const double *A = a.S + (size_t)t * m * m;
+    double lmax = 0.0;
+    for (int k = tid; k < m; k += 256) lmax = fmax(lmax, A[(size_t)k * m + k]);
+    for (int o = 32; o > 0; o >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, o));
+    if ((tid & 63) == 0) red[tid >> 6] = lmax;
+    __syncthreads();
+    lmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    for (int k = tid; k < m; k += 256) {
+        double q2 = 0.0;
+        for (int b = 0; b < a.snr_nxb; ++b) q2 += a.snrPart[((size_t)t * a.snr_nxb + b) * m + k];
+        const double2 r = a.snrRho[(size_t)t * m + k];
+        const double ar = sqrt(r.x * r.x + r.y * r.y);
+        const double var = q2 / (double)a.ns - (r.x * r.x + r.y * r.y);
+        const double snr = var > 0.0 ? ar * sqrt((double)a.ns) / sqrt(var) : INFINITY;
+        const double lam = A[(size_t)k * m + k];
+        const double keep = (lam > 1e-14 * lmax && ar > 0.0) ? 1.0 / (1.0 + pow(a.snr_tau / snr, 6.0)) : 0.0;
+        a.snrW[(size_t)t * m + k] = keep > 0.0 ? make_double2(keep * r.x / lam, keep * r.y / lam) : make_double2(0.0, 0.0);
+        a.snrEig[((size_t)t * m + k) * 2] = lam;
+        a.snrEig[((size_t)t * m + k) * 2 + 1] = snr;
+    }
+}
+
+// delta_l = sum_k V_lk w_k
+__global__ void k_snr_back(Dev a, int stage) {
+    const int t = blockIdx.y;
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= a.m) return;
+    const double *Vt = a.snrV + (size_t)t * a.m * a.m;
+    const double2 *w = a.snrW + (size_t)t * a.m;
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < a.m; ++k) {
+        const double v = Vt[(size_t)k * a.m + l];
+        re += v * w[k].x;
+        im += v * w[k].y;
+    }
+    double2 *out = stage ? a.d1 : a.d0;
+    const double2 dl = make_double2(re, im);
+    out[(size_t)t * a.m + l] = dl;
+    if (!isfinite(re) || !isfinite(im)) a.flags[t] = 1;
+}
+
+}  // namespace tvmc

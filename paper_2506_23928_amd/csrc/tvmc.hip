@@ -21,6 +21,7 @@
 #include "observe.hpp"
 #include "rbm.hpp"
 #include "sampler.hpp"
+#include "snr.hpp"
 #include "sbuild.hpp"
 #include "sbuild_mfma.hpp"
 #include "sbuild_rbm_mfma.hpp"
@@ -61,7 +62,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, pidx, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, lognorm, qhist, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
+        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, lognorm, qhist, snrV, snrRho, snrW, snrEig, snrPart, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
         arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, total;
 };
 
@@ -89,14 +90,15 @@ int eta_param(const tvmc_ansatz *a, int n, int j, int k) {
 }
 // whether the solve runs in sample space (N_s x N_s) rather than parameter space (M x M)
 int use_sample_space(const tvmc_config *c, const tvmc_ansatz *a, int m) {
-    if (a->kind == TVMC_ANSATZ_LJPH) return 0;
+    if (a->kind == TVMC_ANSATZ_LJPH || c->regulariser == TVMC_REG_SNR) return 0;
     return c->solver == TVMC_SOLVER_SAMPLE_SPACE || (c->solver == TVMC_SOLVER_AUTO && m > c->n_samples);
 }
 
 // S + eps I per trajectory: real symmetric M x M (Jastrow) or complex Hermitian M x M (RBM)
 size_t s_doubles(int kind, int m) { return (kind == TVMC_ANSATZ_RBM ? 2 : 1) * (size_t)m * m; }
 
-Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs, int ar, int ah, int nprob, int prec, int ss) {
+Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, int nobs, int ar, int ah, int nprob, int prec, int ss,
+              int snr) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -154,6 +156,12 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.flags = take(sizeof(int) * tt);
     L.lognorm = take(sizeof(double) * tt * 3);
     L.qhist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt);
+    const size_t nxb = (size_t)(ns + 63) / 64;
+    L.snrV = take(snr ? sizeof(double) * tt * m * m : 0);
+    L.snrRho = take(snr ? sizeof(double2) * tt * m : 0);
+    L.snrW = take(snr ? sizeof(double2) * tt * m : 0);
+    L.snrEig = take(snr ? sizeof(double) * tt * m * 2 : 0);
+    L.snrPart = take(snr ? sizeof(double) * tt * nxb * m : 0);
     const size_t np = ar ? ar_params(n, ah) : 0;
     L.arP = take(sizeof(float) * tt * np);
     L.arG = take(sizeof(float) * tt * np);
@@ -245,6 +253,18 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
         return snprintf(msg, len, "bad solver"), TVMC_E_INVAL;
     if (c->unravelling != TVMC_SSE_NONLINEAR && c->unravelling != TVMC_SSE_LINEAR)
         return snprintf(msg, len, "bad unravelling"), TVMC_E_INVAL;
+    if (c->regulariser != TVMC_REG_SHIFT && c->regulariser != TVMC_REG_SNR)
+        return snprintf(msg, len, "bad regulariser"), TVMC_E_INVAL;
+    if (c->regulariser == TVMC_REG_SNR) {
+        if (a->kind == TVMC_ANSATZ_RBM)
+            return snprintf(msg, len, "the SNR solve needs a real S (Jastrow ansaetze)"), TVMC_E_INVAL;
+        if (c->solver == TVMC_SOLVER_SAMPLE_SPACE)
+            return snprintf(msg, len, "the SNR solve works in parameter space"), TVMC_E_INVAL;
+        if (n_params(a, p->n_sites) > 2 * JAC_MAXP)
+            return snprintf(msg, len, "the SNR solve takes at most %d parameters", 2 * JAC_MAXP), TVMC_E_INVAL;
+        if (!(c->snr_tau >= 0.0) || !std::isfinite(c->snr_tau))
+            return snprintf(msg, len, "bad snr_tau"), TVMC_E_INVAL;
+    }
     if (use_sample_space(c, a, n_params(a, p->n_sites)) && c->n_samples > 65535)
         return snprintf(msg, len, "the sample-space solve takes at most 65535 samples"), TVMC_E_INVAL;
     return TVMC_OK;
@@ -589,6 +609,20 @@ tvmc_status run_solve(tvmc_ctx *c) {
             if (st != TVMC_OK) return st;
             hipLaunchKernelGGL(k_pushback, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage);
             LAUNCHCHECK(c, "k_pushback");
+        } else if (d.reg == TVMC_REG_SNR) {
+            const size_t mm = (size_t)d.m * d.m;
+            hipLaunchKernelGGL(k_snr_init, dim3((unsigned)((mm + 255) / 256), d.nt), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_snr_init");
+            hipLaunchKernelGGL(k_jacobi, dim3(d.nt), dim3(JAC_THREADS), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_jacobi");
+            hipLaunchKernelGGL(k_snr_rho, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_snr_rho");
+            hipLaunchKernelGGL(k_snr_var, dim3((d.m + SV_K - 1) / SV_K, d.snr_nxb, d.nt), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_snr_var");
+            hipLaunchKernelGGL(k_snr_finish, dim3(d.nt), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_snr_finish");
+            hipLaunchKernelGGL(k_snr_back, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage);
+            LAUNCHCHECK(c, "k_snr_back");
         } else if (d.kind == TVMC_ANSATZ_RBM) {
             ZCholArgs za{(double2 *)d.S, d.D, c->stage ? d.d1 : d.d0, (double2 *)d.linv, d.flags, d.m};
             tvmc_status st = launch_zchol(c, za);
@@ -686,6 +720,7 @@ size_t q_bytes(const tvmc_ctx *c, int what) {
     case TVMC_Q_AR_ACCEPTS: return d.ar ? sizeof(uint32_t) * d.nc : 0;
     case TVMC_Q_LOGNORM: return sizeof(double);
     case TVMC_Q_LOGNORM_HIST: return sizeof(double) * (size_t)d.nobs;
+    case TVMC_Q_EIG: return d.reg == TVMC_REG_SNR ? sizeof(double) * 2 * d.m : 0;
     default: return 0;
     }
 }
@@ -701,7 +736,8 @@ tvmc_status tvmc_workspace_size_batch(const tvmc_problem *p, int32_t np, const t
     if (!bytes) return TVMC_E_INVAL;
     const int n = p->n_sites, m = n_params(a, n);
     *bytes = layout(a->kind, n, a->n_hidden, m, p->n_jumps, c->n_traj, c->n_samples, c->n_chains, c->n_obs_max,
-                    c->proposal, c->ar_hidden, np, c->precision, use_sample_space(c, a, m)).total;
+                    c->proposal, c->ar_hidden, np, c->precision, use_sample_space(c, a, m),
+                    c->regulariser == TVMC_REG_SNR).total;
     return TVMC_OK;
 }
 
@@ -719,7 +755,7 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     const int n = p->n_sites, m = n_params(a, n), nch = p->n_jumps, T = c->n_traj;
     const int nh = a->kind == TVMC_ANSATZ_RBM ? a->n_hidden : 0;
     const Layout L = layout(a->kind, n, nh, m, nch, T, c->n_samples, c->n_chains, c->n_obs_max, c->proposal,
-                            c->ar_hidden, np, c->precision, use_sample_space(c, a, m));
+                            c->ar_hidden, np, c->precision, use_sample_space(c, a, m), c->regulariser == TVMC_REG_SNR);
     if (!ws) return snprintf(g_err, sizeof(g_err), "workspace is null"), TVMC_E_INVAL;
     if (ws_bytes < L.total) return snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu", ws_bytes, L.total), TVMC_E_NOMEM;
     if ((uintptr_t)ws % 256) return snprintf(g_err, sizeof(g_err), "workspace must be 256-byte aligned"), TVMC_E_INVAL;
@@ -807,6 +843,14 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.dq0 = d.lognorm + T;
     d.momlq = d.lognorm + 2 * (size_t)T;
     d.qhist = (double *)(base + L.qhist);
+    d.reg = c->regulariser;
+    d.snr_tau = c->snr_tau;
+    d.snr_nxb = (c->n_samples + 63) / 64;
+    d.snrV = (double *)(base + L.snrV);
+    d.snrRho = (double2 *)(base + L.snrRho);
+    d.snrW = (double2 *)(base + L.snrW);
+    d.snrEig = (double *)(base + L.snrEig);
+    d.snrPart = (double *)(base + L.snrPart);
     d.ar = c->proposal;
     d.ah = c->proposal ? c->ar_hidden : 0;
     d.arnp = c->proposal ? ar_params(n, c->ar_hidden) : 0;
@@ -1012,6 +1056,7 @@ tvmc_status tvmc_get(tvmc_ctx *c, int32_t what, int32_t traj, void *host, size_t
     case TVMC_Q_AR_LOSS: src = d.arloss + t; break;
     case TVMC_Q_AR_ACCEPTS: src = d.aracc + t * d.nc; break;
     case TVMC_Q_LOGNORM: src = d.lognorm + t; break;
+    case TVMC_Q_EIG: src = d.snrEig + t * 2 * d.m; break;
     default: break;
     }
     if (what == TVMC_Q_OBS_HIST) {

@@ -20,10 +20,11 @@ HEUN, MIDPOINT = 0, 1
 PREC_FP64, PREC_MFMA = 0, 1
 (Q_THETA, Q_THETA_EVAL, Q_DELTA0, Q_DELTA1, Q_SAMPLES, Q_ELOC, Q_S, Q_D, Q_OBAR, Q_BMEAN, Q_DW, Q_ACCEPTS,
  Q_CHAINS, Q_MOMENTS, Q_OBS_HIST, Q_AR_PARAMS, Q_AR_GRAD, Q_AR_LOGQ, Q_AR_LOSS, Q_AR_ACCEPTS, Q_LOGNORM,
- Q_LOGNORM_HIST) = range(22)
+ Q_LOGNORM_HIST, Q_EIG) = range(23)
 PROPOSAL_FLIP, PROPOSAL_LEARNED = 0, 1
 SOLVER_AUTO, SOLVER_ONE_GROUP, SOLVER_MULTI_GROUP, SOLVER_SAMPLE_SPACE = 0, 1, 2, 3
 SSE_NONLINEAR, SSE_LINEAR = 0, 1
+REG_SHIFT, REG_SNR = 0, 1
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -45,7 +46,8 @@ class tvmc_config(ctypes.Structure):
                 ("diag_shift", ctypes.c_double), ("precision", ctypes.c_int32), ("obs_every", ctypes.c_int32),
                 ("n_obs_max", ctypes.c_int32), ("seed", ctypes.c_uint64), ("proposal", ctypes.c_int32),
                 ("ar_hidden", ctypes.c_int32), ("ar_train_every", ctypes.c_int32), ("ar_train_iters", ctypes.c_int32),
-                ("ar_lr", ctypes.c_double), ("solver", ctypes.c_int32), ("unravelling", ctypes.c_int32)]
+                ("ar_lr", ctypes.c_double), ("solver", ctypes.c_int32), ("unravelling", ctypes.c_int32),
+                ("regulariser", ctypes.c_int32), ("snr_tau", ctypes.c_double)]
 
 
 class TvmcError(RuntimeError):
@@ -117,10 +119,10 @@ def n_params(kind: int, n: int, n_hidden: int = 0) -> int:
 def make_config(n_traj, n_samples, n_chains, dt, diag_shift=1e-4, burn_sweeps=2, thin_sweeps=1, init_sweeps=0,
                 scheme=HEUN, precision=PREC_FP64, obs_every=0, n_obs_max=0, seed=0, traj_offset=0,
                 proposal=PROPOSAL_FLIP, ar_hidden=128, ar_train_every=20, ar_train_iters=50, ar_lr=3e-3,
-                solver=0, unravelling=SSE_NONLINEAR):
+                solver=0, unravelling=SSE_NONLINEAR, regulariser=REG_SHIFT, snr_tau=4.0):
     return tvmc_config(n_traj, traj_offset, n_samples, n_chains, burn_sweeps, thin_sweeps, init_sweeps, scheme, dt,
                        diag_shift, precision, obs_every, n_obs_max, ctypes.c_uint64(seed), proposal, ar_hidden,
-                       ar_train_every, ar_train_iters, ar_lr, solver, unravelling)
+                       ar_train_every, ar_train_iters, ar_lr, solver, unravelling, regulariser, snr_tau)
 
 
 # ---------------------------------------------------------------- functions named as in the C ABI
@@ -223,7 +225,7 @@ class Context:
                Q_BMEAN: ("c", "nch"), Q_DW: ("d", "nch"), Q_ACCEPTS: ("u4", "nc"), Q_CHAINS: ("u8", "nc"),
                Q_MOMENTS: ("d", "9"), Q_OBS_HIST: ("d", "hist"), Q_AR_PARAMS: ("f", "arnp"), Q_AR_GRAD: ("f", "arnp"),
                Q_AR_LOGQ: ("f", "ns"), Q_AR_LOSS: ("d", "1"), Q_AR_ACCEPTS: ("u4", "nc"), Q_LOGNORM: ("d", "1"),
-               Q_LOGNORM_HIST: ("d", "nobs")}
+               Q_LOGNORM_HIST: ("d", "nobs"), Q_EIG: ("d", "2m")}
 
     def __init__(self, problem: Problem, config: tvmc_config, kind=JASTROW, n_hidden=0, theta0=None, device="cuda",
                  stream=None):
@@ -303,7 +305,7 @@ class Context:
     def _count(self, key):
         c = self.config
         return {"m": self.m, "ns": c.n_samples, "mm": self.solve_dim ** 2, "nch": len(self.problem.jumps),
-                "nc": c.n_chains, "9": 9, "hist": 9 * c.n_obs_max, "nobs": c.n_obs_max, "1": 1,
+                "nc": c.n_chains, "9": 9, "hist": 9 * c.n_obs_max, "nobs": c.n_obs_max, "1": 1, "2m": 2 * self.m,
                 "arnp": 2 * self.problem.n * c.ar_hidden + self.problem.n + c.ar_hidden}[key]
 
     def get(self, what, traj=0):
@@ -320,6 +322,8 @@ class Context:
             out = out.reshape(self.solve_dim, self.solve_dim)
         if what == Q_OBS_HIST:
             out = out.reshape(-1, 9)
+        if what == Q_EIG:
+            out = out.reshape(-1, 2)
         return out
 
     def train_proposal(self, n_iters):

@@ -40,16 +40,17 @@ def test_struct_layouts_match_the_header(tmp_path):
     from paper_2506_23928_amd import tvmc
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tvmc.h"\nint main(){'
-                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tvmc_problem), offsetof(tvmc_problem, jump_rate),'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tvmc_problem), offsetof(tvmc_problem, jump_rate),'
                     'sizeof(tvmc_config), offsetof(tvmc_config, dt), offsetof(tvmc_config, precision),'
-                    'offsetof(tvmc_config, seed), offsetof(tvmc_config, unravelling), sizeof(tvmc_ansatz));'
+                    'offsetof(tvmc_config, seed), offsetof(tvmc_config, unravelling), offsetof(tvmc_config, snr_tau),'
+                    'sizeof(tvmc_ansatz));'
                     ' return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(prog)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     P, C, A = tvmc.tvmc_problem, tvmc.tvmc_config, tvmc.tvmc_ansatz
     want = [ctypes.sizeof(P), P.jump_rate.offset, ctypes.sizeof(C), C.dt.offset, C.precision.offset, C.seed.offset,
-            C.unravelling.offset, ctypes.sizeof(A)]
+            C.unravelling.offset, C.snr_tau.offset, ctypes.sizeof(A)]
     assert got == want
 
 
@@ -78,6 +79,17 @@ def test_configuration_checks_run_on_the_host():
     assert tvmc.tvmc_workspace_size(pb64, lj, ok) > 0
     with pytest.raises(tvmc.TvmcError):
         tvmc.tvmc_workspace_size(pb64, lj, tvmc.make_config(1, 1 << 20, 64, 0.01, precision=tvmc.PREC_MFMA))
+    # SNR solve: real S (Jastrow ansaetze), parameter space, M <= 2176, tau >= 0; it adds workspace
+    snr = tvmc.make_config(2, 64, 8, 0.01, regulariser=tvmc.REG_SNR)
+    assert tvmc.tvmc_workspace_size(pb, an, snr) > tvmc.tvmc_workspace_size(pb, an, tvmc.make_config(2, 64, 8, 0.01))
+    assert tvmc.tvmc_workspace_size(pb64, an, snr) > 0          # M = 2080
+    for bad_an, bad_cfg in [(tvmc.make_ansatz(tvmc.RBM, 2), snr),
+                            (an, tvmc.make_config(2, 64, 8, 0.01, regulariser=tvmc.REG_SNR, snr_tau=-1.0)),
+                            (an, tvmc.make_config(2, 64, 8, 0.01, regulariser=tvmc.REG_SNR,
+                                                  solver=tvmc.SOLVER_SAMPLE_SPACE)),
+                            (an, tvmc.make_config(2, 64, 8, 0.01, regulariser=2))]:
+        with pytest.raises(tvmc.TvmcError):
+            tvmc.tvmc_workspace_size(pb, bad_an, bad_cfg)
 
 
 def test_product_couplings_match_the_definition():
