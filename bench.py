@@ -77,7 +77,7 @@ def ansatz_of(tv, w):
     return tv.JASTROW, 0, tv.n_params(tv.JASTROW, w["n"]), None
 
 
-def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, solver=0):
+def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, solver=0, regulariser=0):
     from paper_2506_23928_amd.problem import kac_couplings
     import workloads as wl
     J = kac_couplings(w["geom"], w["n"], w["alpha"], w["jscale"])
@@ -90,11 +90,12 @@ def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, s
                          w["burn_sweeps"], w["thin_sweeps"], 0, tv.HEUN, precision, w["obs_every"],
                          steps // w["obs_every"] + 2, w["seed"], traj_offset, proposal=proposal,
                          ar_hidden=w.get("ar_hidden", 128), ar_train_every=w.get("ar_train_every", 20),
-                         ar_train_iters=w.get("ar_train_iters", 50), ar_lr=w.get("ar_lr", 3e-3), solver=solver)
+                         ar_train_iters=w.get("ar_train_iters", 50), ar_lr=w.get("ar_lr", 3e-3), solver=solver,
+                         regulariser=regulariser, snr_tau=w.get("snr_tau", 4.0))
     return tv.Context(prob, cfg, kind=kind, n_hidden=nh, theta0=th0)
 
 
-def cpu_baseline(w, ns_sample=None):
+def cpu_baseline(w, ns_sample=None, regulariser=0):
     """The oracle as it stands on a bounded sample: P host threads, each running one predictor
     evaluation of its own trajectory (sampling, local estimators, S, F, N^n, D, Cholesky solve);
     one trajectory-step is two evaluations.  With ns_sample below the workload's sample count
@@ -113,7 +114,8 @@ def cpu_baseline(w, ns_sample=None):
     ns_full = w["n_samples"]
     ns = ns_sample or ns_full
     cfg = orc.Config(n_samples=ns, n_chains=w["n_chains"], burn_sweeps=w["burn_sweeps"],
-                     thin_sweeps=w["thin_sweeps"], dt=w["dt"], diag_shift=w["diag_shift"], seed=w["seed"])
+                     thin_sweeps=w["thin_sweeps"], dt=w["dt"], diag_shift=w["diag_shift"], seed=w["seed"],
+                     regulariser=regulariser, snr_tau=w.get("snr_tau", 4.0))
     times = []
 
     def work(traj):
@@ -152,6 +154,8 @@ def main():
     ap.add_argument("--precision", choices=["mfma", "fp64"], default="mfma")
     ap.add_argument("--solver", choices=["auto", "one", "multi"], default="auto",
                     help="FP64 Cholesky with one or several workgroups per trajectory (auto: by batch size)")
+    ap.add_argument("--regulariser", choices=["shift", "snr"], default="shift",
+                    help="diagonal shift (Cholesky) or the SNR filter in S's eigenbasis (Jastrow ansaetze)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -185,7 +189,8 @@ def main():
         w.get("proposal", "flip")), file=sys.stderr, flush=True)
 
     solver = {"auto": tv.tvmc.SOLVER_AUTO, "one": tv.tvmc.SOLVER_ONE_GROUP, "multi": tv.tvmc.SOLVER_MULTI_GROUP}[args.solver]
-    ctx = build_context(tv, w, prec, solver=solver)
+    reg = tv.tvmc.REG_SNR if args.regulariser == "snr" else tv.tvmc.REG_SHIFT
+    ctx = build_context(tv, w, prec, solver=solver, regulariser=reg)
     for _ in range(args.warmup):
         ctx.sde_step(1)
     ctx.synchronize()
@@ -212,7 +217,13 @@ def main():
     dom = max(groups, key=lambda g: groups[g]["total_ms"])
     ss, ns = ctx.sample_space, w["n_samples"]
     dim = ns if ss else m                 # dimension of the system solved
-    if dom == "solve":
+    if dom == "solve" and reg == tv.tvmc.REG_SNR:
+        # Jacobi: per sweep M' - 1 rounds rotating every row of S and V^T and every column of S
+        # (12 flops per rotated pair of entries); the sweep count is not known here, so the
+        # figure is per sweep and the fraction is left out
+        roof = {"kernel": "k_jacobi", "bound": "alu", "achieved": None, "peak": PEAKS["fp64"], "unit": "TFLOP/s",
+                "frac": None, "traffic": None, "note": "SNR solve: Jacobi sweeps until converged"}
+    elif dom == "solve":
         if kind == tv.RBM:   # complex Hermitian Cholesky (4/3 n^3 real flops) and two triangular solves
             flops = T * (4.0 * dim ** 3 / 3.0 + 16.0 * dim * dim)
             kname = "k_zmw_solve"     # k_zmw_init, k_zmw_update, k_zmw_diag, k_zmw_trsm, k_zmw_backward
@@ -281,7 +292,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, ns_sample=256 if w.get("ansatz") == "rbm" else None)
+        cpu = cpu_baseline(w, ns_sample=256 if w.get("ansatz") == "rbm" else None, regulariser=reg)
 
     out = {
         "metric": "trajectory-steps/s at N=64 (batched+learned vs plain) at fixed xi^2 error",
@@ -295,7 +306,8 @@ def main():
                    **({"ljph_d": nh} if kind == tv.LJPH else {}), "proposal": w.get("proposal", "flip"),
                    "s_build": ("int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU") if kind != tv.RBM
                    else ("BF16-split MFMA, FP32 accumulate" if prec == tv.PREC_MFMA else "FP64 VALU (complex)"),
-                   "solve": "FP64 Cholesky" + (" (sample space)" if ss else ""), "solver": args.solver,
+                   "solve": ("FP64 Jacobi + SNR filter (tau %g)" % w.get("snr_tau", 4.0)) if reg == tv.tvmc.REG_SNR
+                   else "FP64 Cholesky" + (" (sample space)" if ss else ""), "solver": args.solver,
                    "obs_every": w["obs_every"]},
         "roofline": roof,
         "cpu_baseline": cpu,
