@@ -118,6 +118,128 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(Dev a) {
     if (tid == 0 && done < 0) a.flags[t] = 1;
 }
 
+// The same Jacobi with S held in LDS (packed lower triangle) when M <= JL_MAXM: a round is one
+// pass over the 2 x 2 blocks of every pair of rotation pairs (A <- J^T A J in one step, each
+// entry touched once; the diagonal blocks by the stable update A_pp - t A_pq, A_qq + t A_pq,
+// A_pq = 0), while V^T stays in global memory (row updates, coalesced).  S is written back at
+// the end.
+constexpr int JL_MAXM = 196;
+constexpr int JL_NA = JL_MAXM * (JL_MAXM + 1) / 2;
+constexpr int JL_MAXP = JL_MAXM / 2;
+
+__device__ __forceinline__ int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi_lds(Dev a) {
+    __shared__ double As[JL_NA];
+    __shared__ double sc[JL_MAXP], ss[JL_MAXP], stn[JL_MAXP];
+    __shared__ int sp[JL_MAXP], sq[JL_MAXP];
+    __shared__ double red[JAC_THREADS / 64][2];
+    __shared__ int done;
+    const int t = blockIdx.x, m = a.m;
+    const int mp = m + (m & 1), K = mp - 1, np = mp / 2, nb = np * (np + 1) / 2;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *S = a.S + (size_t)t * m * m;
+    double *Vt = a.snrV + (size_t)t * m * m;
+    for (int e = tid; e < m * m; e += JAC_THREADS) {
+        const int i = e / m, j = e % m;
+        if (j <= i) As[tri(i, j)] = S[e];
+    }
+    __syncthreads();
+    for (int sweep = 0;; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int e = tid; e < m * m; e += JAC_THREADS) {
+            const int i = e / m, j = e % m;
+            if (j > i) continue;
+            const double v = As[tri(i, j)];
+            tot += (i == j ? 1.0 : 2.0) * v * v;
+            if (i != j) off += 2.0 * v * v;
+        }
+        off = wave_sum(off);
+        tot = wave_sum(tot);
+        if (lane == 0) {
+            red[wave][0] = off;
+            red[wave][1] = tot;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double o = 0.0, s = 0.0;
+            for (int w = 0; w < JAC_THREADS / 64; ++w) {
+                o += red[w][0];
+                s += red[w][1];
+            }
+            done = (o <= 1e-30 * s) ? 1 : (sweep == JAC_MAX_SWEEPS ? -1 : 0);
+        }
+        __syncthreads();
+        if (done != 0) break;
+        for (int r = 0; r < K; ++r) {
+            if (tid < np) {
+                const int i = tid;
+                int p = i == 0 ? r : (r + i) % K;
+                int q = i == 0 ? K : (r - i + K) % K;
+                if (p > q) {
+                    const int x = p;
+                    p = q;
+                    q = x;
+                }
+                double c = 1.0, s = 0.0, tn = 0.0;
+                if (q < m) {
+                    const double apq = As[tri(q, p)];
+                    if (apq != 0.0) {
+                        const double theta = (As[tri(q, q)] - As[tri(p, p)]) / (2.0 * apq);
+                        tn = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                        c = 1.0 / sqrt(tn * tn + 1.0);
+                        s = tn * c;
+                    }
+                }
+                sp[i] = p;
+                sq[i] = q;
+                sc[i] = c;
+                ss[i] = s;
+                stn[i] = tn;
+            }
+            __syncthreads();
+            for (int b = tid; b < nb; b += JAC_THREADS) {
+                int i1 = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+                while ((i1 + 1) * (i1 + 2) / 2 <= b) ++i1;
+                while (i1 * (i1 + 1) / 2 > b) --i1;
+                const int i2 = b - i1 * (i1 + 1) / 2;
+                const int p1 = sp[i1], q1 = sq[i1], p2 = sp[i2], q2 = sq[i2];
+                const bool h1 = q1 < m, h2 = q2 < m;
+                if (i1 == i2) {
+                    if (!h1) continue;
+                    const double apq = As[tri(q1, p1)], tn = stn[i1];
+                    As[tri(p1, p1)] -= tn * apq;
+                    As[tri(q1, q1)] += tn * apq;
+                    As[tri(q1, p1)] = 0.0;
+                    continue;
+                }
+                const double c1 = sc[i1], s1 = ss[i1], c2 = sc[i2], s2 = ss[i2];
+                const double x00 = As[tri(p1, p2)];
+                const double x01 = h2 ? As[tri(p1, q2)] : 0.0;
+                const double x10 = h1 ? As[tri(q1, p2)] : 0.0;
+                const double x11 = (h1 && h2) ? As[tri(q1, q2)] : 0.0;
+                const double y00 = c1 * x00 - s1 * x10, y10 = s1 * x00 + c1 * x10;
+                const double y01 = c1 * x01 - s1 * x11, y11 = s1 * x01 + c1 * x11;
+                As[tri(p1, p2)] = c2 * y00 - s2 * y01;
+                if (h2) As[tri(p1, q2)] = s2 * y00 + c2 * y01;
+                if (h1) As[tri(q1, p2)] = c2 * y10 - s2 * y11;
+                if (h1 && h2) As[tri(q1, q2)] = s2 * y10 + c2 * y11;
+            }
+            for (int e = tid; e < np * m; e += JAC_THREADS) {   // rows p, q of V^T
+                const int i = e / m, j = e % m, p = sp[i], q = sq[i];
+                if (q >= m) continue;
+                const double c = sc[i], s = ss[i];
+                const double vpj = Vt[(size_t)p * m + j], vqj = Vt[(size_t)q * m + j];
+                Vt[(size_t)p * m + j] = c * vpj - s * vqj;
+                Vt[(size_t)q * m + j] = s * vpj + c * vqj;
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < m * m; e += JAC_THREADS) S[e] = As[tri(e / m, e % m)];
+    if (tid == 0 && done < 0) a.flags[t] = 1;
+}
+
 // rho_k = sum_l V_lk D_l
 __global__ void k_snr_rho(Dev a) {
     const int t = blockIdx.y;

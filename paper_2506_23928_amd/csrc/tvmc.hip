@@ -613,8 +613,13 @@ tvmc_status run_solve(tvmc_ctx *c) {
             const size_t mm = (size_t)d.m * d.m;
             hipLaunchKernelGGL(k_snr_init, dim3((unsigned)((mm + 255) / 256), d.nt), dim3(256), 0, c->stream, d);
             LAUNCHCHECK(c, "k_snr_init");
-            hipLaunchKernelGGL(k_jacobi, dim3(d.nt), dim3(JAC_THREADS), 0, c->stream, d);
-            LAUNCHCHECK(c, "k_jacobi");
+            if (d.m <= JL_MAXM) {
+                hipLaunchKernelGGL(k_jacobi_lds, dim3(d.nt), dim3(JAC_THREADS), 0, c->stream, d);
+                LAUNCHCHECK(c, "k_jacobi_lds");
+            } else {
+                hipLaunchKernelGGL(k_jacobi, dim3(d.nt), dim3(JAC_THREADS), 0, c->stream, d);
+                LAUNCHCHECK(c, "k_jacobi");
+            }
             hipLaunchKernelGGL(k_snr_rho, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d);
             LAUNCHCHECK(c, "k_snr_rho");
             hipLaunchKernelGGL(k_snr_var, dim3((d.m + SV_K - 1) / SV_K, d.snr_nxb, d.nt), dim3(256), 0, c->stream, d);

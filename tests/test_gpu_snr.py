@@ -3,7 +3,8 @@ oracle (cyclic Jacobi).  The two eigen-decompositions order and sign their eigen
 differently, so the comparison is on what is unique: the sorted eigenvalues (1e-12 of the
 largest: Jacobi is backward stable to a few ulps of ||S||), the SNR of the component with the
 same eigenvalue (1e-8 relative), and delta (1e-8 relative: eigenvector rounding amplified by
-1/lam_min with lam_min ~ eps).  With tau = 0 the solve is the Cholesky one."""
+1/lam_min with lam_min ~ eps).  With tau = 0 the solve is the Cholesky one.  M <= 196 runs
+the LDS-resident Jacobi, M = 231 (N = 21) the global-memory one."""
 import numpy as np
 import pytest
 
@@ -30,7 +31,7 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("kind,n,d,ns,nc,tau,prec", [(0, 6, 0, 512, 8, 4.0, 0), (0, 7, 0, 320, 16, 4.0, 0),
                                                      (LJPH, 9, 2, 256, 8, 4.0, 1), (0, 6, 0, 256, 8, 0.0, 1),
-                                                     (LJPH, 64, 1, 256, 8, 4.0, 1)])
+                                                     (LJPH, 64, 1, 256, 8, 4.0, 1), (0, 21, 0, 256, 8, 4.0, 1)])
 def test_snr_evaluation_parity(tv, orc, kind, n, d, ns, nc, tau, prec):
     from paper_2506_23928_amd import tvmc as T
     J, hx, jumps = wl.random_problem(n, seed=n + 5)
