@@ -80,7 +80,8 @@ def ansatz_of(tv, w):
 def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, solver=0, regulariser=0):
     from paper_2506_23928_amd.problem import kac_couplings
     import workloads as wl
-    J = kac_couplings(w["geom"], w["n"], w["alpha"], w["jscale"])
+    lx, ly = wl.lattice(w)
+    J = kac_couplings(w["geom"], lx, w["alpha"], w["jscale"], ly)
     prob = tv.Problem(J, w["h"], wl.jumps(w))
     steps = wl.n_steps(w)
     kind, nh, _, th0 = ansatz_of(tv, w)
@@ -105,7 +106,8 @@ def cpu_baseline(w, ns_sample=None, regulariser=0):
     import oracle as orc
     import workloads as wl
     cores = min(os.cpu_count() or 1, 16)
-    J = orc.couplings(w["geom"], w["n"], w["alpha"], w["jscale"])
+    lx, ly = wl.lattice(w)
+    J = orc.couplings(w["geom"], lx, w["alpha"], w["jscale"], ly)
     pb = orc.Problem(J, w["h"], wl.jumps(w))
     rbm = w.get("ansatz", "jastrow") == "rbm"
     kind, nh = (1, w["n_hidden"]) if rbm else (2, w["d"]) if w.get("ansatz") == "ljph" else (0, 0)
@@ -304,7 +306,8 @@ def main():
                    "n_chains": w["n_chains"], "n_jumps": len(wl.jumps(w)), "dt": w["dt"],
                    "ansatz": w.get("ansatz", "jastrow"), "n_hidden": nh if kind == tv.RBM else 0,
                    **({"ljph_d": nh} if kind == tv.LJPH else {}), "proposal": w.get("proposal", "flip"),
-                   "s_build": ("int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU") if kind != tv.RBM
+                   "s_build": "sample-space kernel O O^H (FP64 VALU)" if ss else
+                   ("int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU") if kind != tv.RBM
                    else ("BF16-split MFMA, FP32 accumulate" if prec == tv.PREC_MFMA else "FP64 VALU (complex)"),
                    "solve": ("FP64 Jacobi + SNR filter (tau %g)" % w.get("snr_tau", 4.0)) if reg == tv.tvmc.REG_SNR
                    else "FP64 Cholesky" + (" (sample space)" if ss else ""), "solver": args.solver,

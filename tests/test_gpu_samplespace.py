@@ -84,16 +84,17 @@ def test_sample_space_trajectory(tv, orc):
         assert _rel(ctx.get(T.Q_THETA, t), th_o[t]) < 1e-8
 
 
-def test_sample_space_full_size(tv, orc):
-    """The wide RBM workload (N = 64, N' = 256, M = 16704, 4096 samples, 32 trajectories) in
-    the benchmark's launch configuration: for the last trajectory the samples bit for bit
+@pytest.mark.parametrize("name", ["chain64_rbm_wide", "lattice8x8_rbm_ss"])
+def test_sample_space_full_size(tv, orc, name):
+    """The wide RBM workloads (chain N = 64, N' = 256, M = 16704; 8x8 lattice, alpha = 3,
+    N' = 128, M = 8384; 4096 samples, 32 trajectories) in the benchmark's launch configuration: for the last trajectory the samples bit for bit
     against the oracle, T against the closed form (1 + q)(1 + g) - 1 centred, built from the
     oracle's samples, and the increment against the parameter-space normal equations
     A^H (A delta) + eps delta = D with A = (O - <O>) / sqrt(N_s) from the oracle's
     log-derivatives (S itself, 16704^2, is never formed)."""
     from paper_2506_23928_amd import tvmc as T
     import bench
-    w = dict(wl.WORKLOADS["chain64_rbm_wide"])
+    w = dict(wl.WORKLOADS[name])
     ctx = bench.build_context(tv, w, tv.PREC_FP64)
     n, nh, ns, TT = w["n"], w["n_hidden"], w["n_samples"], w["n_traj"]
     m = orc.n_params(1, n, nh)
@@ -105,7 +106,8 @@ def test_sample_space_full_size(tv, orc):
     ctx.sr_solve()
     ctx.synchronize()
     th0 = wl.rbm_theta0(n, nh, w["w_scale"], w["seed"])
-    pb = orc.Problem(orc.couplings(w["geom"], n, w["alpha"], w["jscale"]), w["h"], wl.jumps(w))
+    lx, ly = wl.lattice(w)
+    pb = orc.Problem(orc.couplings(w["geom"], lx, w["alpha"], w["jscale"], ly), w["h"], wl.jumps(w))
     cfg_o = orc.Config(n_samples=ns, n_chains=w["n_chains"], burn_sweeps=w["burn_sweeps"],
                        thin_sweeps=w["thin_sweeps"], dt=w["dt"], diag_shift=w["diag_shift"], seed=w["seed"])
     r = orc.evaluate(pb, 1, nh, cfg_o, th0, orc.init_chains(w["seed"], t, n, w["n_chains"]), traj=t,

@@ -53,7 +53,21 @@ WORKLOADS = {
                              ansatz="rbm", n_hidden=256, n_samples=4096, n_chains=64, n_traj=32, dt=0.01,
                              t_end=1.0, diag_shift=1e-4, obs_every=10, burn_sweeps=2, thin_sweeps=1, seed=0,
                              proposal="flip", w_scale=0.01),
+    # 2D 8x8 open lattice, alpha = 3, h = 1, decay 0.1, RBM with hidden density 2 (N' = 128, 8384
+    # complex parameters, weights N(0, 0.01)), 4096 samples x 32 trajectories: M > N_s, the
+    # sample-space solve through the 4096 x 4096 kernel.  The paper-shaped 10x10 lattice (N = 100)
+    # needs two 64-bit configuration words; 8x8 is the largest square one word holds.
+    "lattice8x8_rbm_ss": dict(geom="2d", n=64, ly=8, alpha=3.0, jscale=1.0, h=1.0, decay=0.1, dephase=0.0,
+                              ansatz="rbm", n_hidden=128, n_samples=4096, n_chains=64, n_traj=32, dt=0.01,
+                              t_end=1.0, diag_shift=1e-4, obs_every=10, burn_sweeps=2, thin_sweeps=1, seed=0,
+                              proposal="flip", w_scale=0.01),
 }
+
+
+def lattice(w: dict):
+    """(lx, ly) of a workload's geometry (ly = 1 for chains)."""
+    ly = w.get("ly", 1)
+    return w["n"] // ly, ly
 
 
 def rbm_theta0(n: int, nh: int, scale: float, seed: int) -> np.ndarray:
