@@ -147,6 +147,49 @@ def cpu_baseline(w, ns_sample=None, regulariser=0):
             "sample": sample}
 
 
+def tau_int(series):
+    """Integrated autocorrelation time of chains' time series [C][L] (mean over chains of the
+    normalised autocorrelation, summed with Sokal's self-consistent window W >= 5 tau)."""
+    import numpy as np
+    x = np.asarray(series, dtype=np.float64)
+    x = x - x.mean(axis=1, keepdims=True)
+    var = (x * x).mean()
+    if var == 0.0:
+        return 0.5
+    L = x.shape[1]
+    tau = 0.5
+    for k in range(1, L // 2):
+        tau += (x[:, :-k] * x[:, k:]).mean() / var
+        if k >= 5 * tau:
+            break
+    return tau
+
+
+def autocorrelation(tv, w, steps, n_traj):
+    """tau_int of Re E_loc and of M_z along each Markov chain, learned proposal against single
+    flips, after `steps` SDE steps (the network retrained every ar_train_every steps)."""
+    import numpy as np
+    from paper_2506_23928_amd import tvmc as T
+    out = {}
+    for label, prop in (("learned", tv.PROPOSAL_LEARNED), ("flip", tv.PROPOSAL_FLIP)):
+        ctx = build_context(tv, w, tv.PREC_MFMA, n_traj=n_traj, proposal=prop)
+        ctx.sde_step(steps)
+        ctx.sample()
+        ctx.synchronize()
+        nc, per, n = w["n_chains"], w["n_samples"] // w["n_chains"], w["n"]
+        te, tm = [], []
+        for t in range(n_traj):
+            e = ctx.get(T.Q_ELOC, t).real.reshape(nc, per)
+            s = tv.unpack_samples(ctx.get(T.Q_SAMPLES, t), n).astype(np.float64).sum(axis=1).reshape(nc, per)
+            te.append(tau_int(e))
+            tm.append(tau_int(s))
+        out[label] = {"tau_eloc": float(np.mean(te)), "tau_mz": float(np.mean(tm)),
+                      "accept_learned": (float(np.mean([ctx.get(T.Q_AR_ACCEPTS, t).mean() for t in range(n_traj)]))
+                                         if prop == tv.PROPOSAL_LEARNED else None)}
+        del ctx
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +201,8 @@ def main():
                     help="FP64 Cholesky with one or several workgroups per trajectory (auto: by batch size)")
     ap.add_argument("--regulariser", choices=["shift", "snr"], default="shift",
                     help="diagonal shift (Cholesky) or the SNR filter in S's eigenbasis (Jastrow ansaetze)")
+    ap.add_argument("--autocorr", action="store_true",
+                    help="measure the integrated autocorrelation time with and without the learned proposal")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -190,6 +235,11 @@ def main():
         args.workload, n, m, T, w["n_samples"], w["n_chains"], len(wl.jumps(w)), args.precision,
         w.get("proposal", "flip")), file=sys.stderr, flush=True)
 
+    if args.autocorr:
+        res = autocorrelation(tv, w, args.steps, min(T, 16))
+        print(json.dumps({"workload": args.workload, "steps": args.steps, "samples_per_chain":
+                          w["n_samples"] // w["n_chains"], "thin_sweeps": w["thin_sweeps"], **res}), flush=True)
+        return
     solver = {"auto": tv.tvmc.SOLVER_AUTO, "one": tv.tvmc.SOLVER_ONE_GROUP, "multi": tv.tvmc.SOLVER_MULTI_GROUP}[args.solver]
     reg = tv.tvmc.REG_SNR if args.regulariser == "snr" else tv.tvmc.REG_SHIFT
     ctx = build_context(tv, w, prec, solver=solver, regulariser=reg)
