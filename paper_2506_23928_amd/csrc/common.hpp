@@ -90,9 +90,11 @@ __host__ __device__ __forceinline__ int pair_index(int n, int j, int k) {
     return n + j * n - j * (j + 1) / 2 + (k - j - 1);
 }
 
-// O_k of a packed configuration (bit i set <=> s_i = +1), as an integer
+// O_k of a packed configuration (bit i set <=> s_i = +1), as an integer.  DIST = false: the
+// +-1 log-derivatives of the all-pair Jastrow only (no shared distances to test for).
+template <bool DIST = true>
 __device__ __forceinline__ int o_int(uint64_t mk, int p, int q, int n) {
-    if (q == -2) {   // sum over j of s_j s_{j+p}: pairs that agree minus pairs that differ
+    if (DIST && q == -2) {   // sum over j of s_j s_{j+p}: pairs that agree minus pairs that differ
         const int len = n - p;
         const uint64_t low = len >= 64 ? ~0ull : ((1ull << len) - 1ull);
         return len - 2 * __popcll((mk ^ (mk >> p)) & low);

@@ -131,7 +131,9 @@ __global__ __launch_bounds__(256) void k_gbar(Dev a) {
 }
 
 // <O_k> and D_k = <O_k G> - <O_k><G> for the Jastrow ansaetze (O_k = s_i, s_j s_k, or an
-// LJPHd distance sum: real integers).
+// LJPHd distance sum when DIST: real integers; o G is exact for o = +-1, so the sums are the
+// same for either instance).
+template <bool DIST>
 __global__ __launch_bounds__(256) void k_obar_D(Dev a) {
     const int t = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,19 +144,12 @@ __global__ __launch_bounds__(256) void k_obar_D(Dev a) {
     int64_t cnt = 0;
     double re = 0.0, im = 0.0;
     for (int s = 0; s < a.ns; ++s) {
-        const int o = o_int(smp[s], p, q, a.n);
+        const int o = o_int<DIST>(smp[s], p, q, a.n);
         const double2 g = G[s];
+        const double od = (double)o;
         cnt += o;
-        if (o == 1) {
-            re += g.x;
-            im += g.y;
-        } else if (o == -1) {
-            re -= g.x;
-            im -= g.y;
-        } else {
-            re += (double)o * g.x;
-            im += (double)o * g.y;
-        }
+        re += od * g.x;
+        im += od * g.y;
     }
     const double inv = 1.0 / (double)a.ns;
     const double ob = (double)cnt * inv;

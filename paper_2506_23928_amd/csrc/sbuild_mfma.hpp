@@ -38,10 +38,11 @@ __device__ __forceinline__ uint32_t expand4(uint32_t nib) {
 // four samples' O of a shared distance p (sum of s_j s_{j+p}) as four int8 bytes
 __device__ __forceinline__ uint32_t dist_bytes4(const uint64_t *sp, int p, int n) {
     uint32_t w = 0;
-    for (int b = 0; b < 4; ++b) w |= (uint32_t)(uint8_t)(int8_t)o_int(sp[b], p, -2, n) << (8 * b);
+    for (int b = 0; b < 4; ++b) w |= (uint32_t)(uint8_t)(int8_t)o_int<true>(sp[b], p, -2, n) << (8 * b);
     return w;
 }
 
+template <bool DIST>
 __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
     __shared__ uint32_t As[SB_TILE * SB_ROWW];
     __shared__ uint32_t Bs[SB_TILE * SB_ROWW];
@@ -73,13 +74,20 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
         const uint32_t na = va ? (aq < 0 ? ~pa_ : (pa_ ^ planes[(size_t)aq * nw + w])) : 0u;
         const uint32_t pb_ = planes[(size_t)bp * nw + w];
         const uint32_t nb = vb ? (bq < 0 ? ~pb_ : (pb_ ^ planes[(size_t)bq * nw + w])) : 0u;
-        const uint64_t *sp = a.samples + (size_t)t * a.ns + (size_t)w * 32;
         __syncthreads();
-        for (int q = 0; q < 8; ++q) {
-            As[gr * SB_ROWW + gh * 8 + q] = !va ? 0u : aq == -2 ? dist_bytes4(sp + 4 * q, ap, a.n)
-                                                               : expand4((na >> (4 * q)) & 0xFu);
-            Bs[gr * SB_ROWW + gh * 8 + q] = !vb ? 0u : bq == -2 ? dist_bytes4(sp + 4 * q, bp, a.n)
-                                                               : expand4((nb >> (4 * q)) & 0xFu);
+        if (DIST) {
+            const uint64_t *sp = a.samples + (size_t)t * a.ns + (size_t)w * 32;
+            for (int q = 0; q < 8; ++q) {
+                As[gr * SB_ROWW + gh * 8 + q] = !va ? 0u : aq == -2 ? dist_bytes4(sp + 4 * q, ap, a.n)
+                                                                   : expand4((na >> (4 * q)) & 0xFu);
+                Bs[gr * SB_ROWW + gh * 8 + q] = !vb ? 0u : bq == -2 ? dist_bytes4(sp + 4 * q, bp, a.n)
+                                                                   : expand4((nb >> (4 * q)) & 0xFu);
+            }
+        } else {
+            for (int q = 0; q < 8; ++q) {
+                As[gr * SB_ROWW + gh * 8 + q] = va ? expand4((na >> (4 * q)) & 0xFu) : 0u;
+                Bs[gr * SB_ROWW + gh * 8 + q] = vb ? expand4((nb >> (4 * q)) & 0xFu) : 0u;
+            }
         }
         __syncthreads();
         v4i fa[4], fb[4];
@@ -117,7 +125,10 @@ inline tvmc_status launch_transpose_bits(const Dev &d, hipStream_t st) {
 
 inline tvmc_status launch_sbuild_mfma(const Dev &d, hipStream_t st) {
     const int nt = (d.m + SB_TILE - 1) / SB_TILE;
-    hipLaunchKernelGGL(k_sbuild_i8, dim3(nt * (nt + 1) / 2, d.nt), dim3(256), 0, st, d);
+    if (d.kind == TVMC_ANSATZ_LJPH)
+        hipLaunchKernelGGL(k_sbuild_i8<true>, dim3(nt * (nt + 1) / 2, d.nt), dim3(256), 0, st, d);
+    else
+        hipLaunchKernelGGL(k_sbuild_i8<false>, dim3(nt * (nt + 1) / 2, d.nt), dim3(256), 0, st, d);
     if (hipGetLastError() != hipSuccess) return TVMC_E_DEVICE;
     return TVMC_OK;
 }

@@ -430,7 +430,10 @@ tvmc_status run_estimate(tvmc_ctx *c) {
             hipLaunchKernelGGL(k_obar_D_rbm, dim3((d.m + 64 * OD_R - 1) / (64 * OD_R), T), dim3(256), 0, c->stream, d);
             LAUNCHCHECK(c, "k_obar_D_rbm");
         } else {
-            hipLaunchKernelGGL(k_obar_D, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
+            if (d.kind == TVMC_ANSATZ_LJPH)
+                hipLaunchKernelGGL(k_obar_D<true>, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
+            else
+                hipLaunchKernelGGL(k_obar_D<false>, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
             LAUNCHCHECK(c, "k_obar_D");
         }
     }
