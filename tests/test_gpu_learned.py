@@ -32,11 +32,11 @@ def _params(flat, n, h):
     return [W1, b1, W2, b2]
 
 
-def _ctx(tv, n, h, ns, nc, theta0=None, traj=1, seed=3, hx=0.6, burn=2, init=0, train_every=0):
+def _ctx(tv, n, h, ns, nc, theta0=None, traj=1, seed=3, hx=0.6, burn=2, init=0, train_every=0, kind=0, nh=0):
     J, hxr, jumps = wl.random_problem(n, seed=n)
     cfg = tv.make_config(traj, ns, nc, 0.01, 1e-3, burn, 1, init, seed=seed, proposal=tv.tvmc.PROPOSAL_LEARNED,
                          ar_hidden=h, ar_train_every=train_every, ar_train_iters=20, ar_lr=1e-2)
-    return tv.Context(tv.Problem(J, hx, jumps), cfg, theta0=theta0)
+    return tv.Context(tv.Problem(J, hx, jumps), cfg, kind=kind, n_hidden=nh, theta0=theta0)
 
 
 def test_logq_gradient_and_adam_match_oracle(tv):
@@ -70,16 +70,18 @@ def test_logq_gradient_and_adam_match_oracle(tv):
     assert np.abs(newp - wantf).max() < 1e-5 * 1e-2 + 1e-6 * np.abs(pf).max()
 
 
-def test_learned_chain_samples_psi_squared(tv, orc):
+@pytest.mark.parametrize("kind,d", [(0, 0), (2, 1)])
+def test_learned_chain_samples_psi_squared(tv, orc, kind, d):
     """Train the proposal on predictor samples, then sample the corrector point with the mixture
     of learned independent moves and single flips: the histogram over all 2^N configurations
-    must follow |psi(theta_eval)|^2 (chi-square), and learned moves must actually be accepted."""
+    must follow |psi(theta_eval)|^2 (chi-square), and learned moves must actually be accepted.
+    All-pair Jastrow and LJPH1 (the same sampler, eta expanded from shared parameters)."""
     import oracle.exact as ex
     from paper_2506_23928_amd import tvmc as T
     n, h, ns, nc = 7, 32, 32768, 64
-    m = n + n * (n - 1) // 2
+    m = orc.n_params(kind, n, d)
     th0 = wl.random_theta(m, 0.25, seed=11)
-    ctx = _ctx(tv, n, h, ns, nc, theta0=th0, init=20)
+    ctx = _ctx(tv, n, h, ns, nc, theta0=th0, init=20, kind=kind, nh=d)
     ctx.sample()
     ctx.train_proposal(60)
     ctx.estimate()
@@ -91,7 +93,7 @@ def test_learned_chain_samples_psi_squared(tv, orc):
     smp = tv.unpack_samples(ctx.get(T.Q_SAMPLES, 0), n)
     idx = ((smp > 0).astype(np.int64) * (1 << np.arange(n))).sum(1)
     counts = np.bincount(idx, minlength=1 << n)
-    p = np.abs(ex.jastrow_psi(n)(th_e)) ** 2
+    p = np.abs((ex.jastrow_psi(n) if kind == 0 else ex.ljph_psi(n, d))(th_e)) ** 2
     p /= p.sum()
     e = p * ns
     chi2 = np.sum((counts - e) ** 2 / e)

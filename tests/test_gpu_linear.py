@@ -107,3 +107,13 @@ def test_nonlinear_keeps_log_norm_zero_and_plain_average(tv, orc):
         assert np.all(ctx.get(T.Q_LOGNORM_HIST, t) == 0.0)
     M, C, _ = orc.ensemble(mom, n)
     assert np.abs(Mg - M).max() < 1e-12 and np.abs(Cg - C).max() < 1e-12
+
+
+def test_linear_ljph_trajectory_parity(tv, orc):
+    """The linear SSE with the LJPH1 ansatz (shared-distance log-derivatives in D), Heun."""
+    n, d = 8, 1
+    J = orc.couplings("pbc", n, 1.0, 1.0)
+    jumps = [(0, i, 0.15) for i in range(n)] + [(2, i, 0.05) for i in range(n)]
+    m = orc.n_params(2, n, d)
+    th0 = wl.random_theta(m, 0.05, seed=4)
+    _run_pair(tv, orc, 2, d, J, 0.4, jumps, th0, 3, 512, 8, 0.01, 1e-4, 7, 8, 4, 0)

@@ -92,3 +92,26 @@ def test_snr_trajectory_parity(tv, orc):
     for t in range(TT):
         assert _rel(ctx.get(T.Q_THETA, t), th_o[t]) < 1e-8, t
         assert np.abs(ctx.get(T.Q_MOMENTS, t) - obs_o[t, 2]).max() < 1e-9
+
+
+def test_snr_with_the_linear_sse(tv, orc):
+    """The SNR solve on the linear unravelling (G without the <L + L^dag> drive): theta and
+    log Q after 6 midpoint steps against the oracle."""
+    from paper_2506_23928_amd import tvmc as T
+    n, ns, nc, TT, steps = 6, 512, 8, 2, 6
+    J, hx, jumps = wl.random_problem(n, seed=3)
+    m = orc.n_params(0, n)
+    th0 = wl.random_theta(m, 0.05, seed=8)
+    cfg_o = orc.Config(n_samples=ns, n_chains=nc, burn_sweeps=2, dt=0.01, diag_shift=1e-4, seed=9, n_steps=steps,
+                       obs_every=steps, scheme=1, linear=True, regulariser=orc.REG_SNR, snr_tau=4.0)
+    th_o, _, st = orc.run(orc.Problem(J, hx, jumps), 0, 0, cfg_o, th0, TT, n_threads=2)
+    assert st == 0
+    lq = orc.run.last_lognorm
+    cfg = tv.make_config(TT, ns, nc, 0.01, 1e-4, 2, 1, 0, tv.MIDPOINT, tv.PREC_MFMA, steps, 2, 9,
+                         unravelling=T.SSE_LINEAR, regulariser=T.REG_SNR, snr_tau=4.0)
+    ctx = tv.Context(tv.Problem(J, hx, jumps), cfg, theta0=th0)
+    ctx.sde_step(steps)
+    ctx.synchronize()
+    for t in range(TT):
+        assert _rel(ctx.get(T.Q_THETA, t), th_o[t]) < 1e-8, t
+        assert abs(ctx.get(T.Q_LOGNORM, t)[0] - lq[t, 1]) < 1e-9
