@@ -214,6 +214,19 @@ def eigh_sym(A):
     return lam, V
 
 
+def eigh_herm(A):
+    """The oracle's cyclic-Jacobi eigen-decomposition of a complex Hermitian matrix -> (lam, V)."""
+    A = np.array(A, dtype=np.complex128, order="C")
+    m = A.shape[0]
+    V = np.zeros((m, m), np.complex128)
+    lam = np.zeros(m)
+    st = lib().orc_eigh_herm(ctypes.c_int32(m), _p(A.view(np.float64), _c_dp), _p(V.view(np.float64), _c_dp),
+                             _p(lam, _c_dp))
+    if st:
+        raise RuntimeError("Jacobi did not converge")
+    return lam, V
+
+
 def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, chains, traj=0, step=0, stage=0,
              first=True, dw=None, want_solve=True, want_moments=True):
     """One evaluation of Eq. 8's right-hand side at theta; returns a dict of every quantity.

@@ -63,7 +63,7 @@ typedef struct {
     uint64_t seed;
     int32_t linear;        /* 1: the linear SSE of App. B (E_eff^lin, norm SDE, weighted averages) */
     int32_t regulariser;   /* ORC_REG_SHIFT: (S + eps I) delta = D by Cholesky; ORC_REG_SNR: the
-                              signal-to-noise filter in the eigenbasis of S + eps I (real S only) */
+                              signal-to-noise filter in the eigenbasis of S + eps I */
     double snr_tau;        /* SNR threshold of the filter */
 } orc_config;
 
@@ -484,7 +484,7 @@ int orc_eigh_sym(int32_t m, double *A, double *V, double *lam)
  * whose mean is rho_k: SNR_k = |rho_k| sqrt(N_s) / sqrt(<|q_k|^2> - |rho_k|^2), and
  *   delta = sum_k V_k rho_k / lam_k * 1 / (1 + (tau / SNR_k)^6),
  * the smooth cutoff of Schmitt and Heyl's scheme; eigenvalues below 1e-14 of the largest are
- * dropped.  Real S only (O_k real): the Jastrow ansaetze. */
+ * dropped.  Real S (O_k real): the Jastrow ansaetze; the RBM's Hermitian S below. */
 static int snr_solve(int m, int ns, const double *wgt, double norm, const cplx *O, const cplx *ob, const cplx *S,
                      double eps, const cplx *dG, double tau, cplx *D, double *eig_out)
 {
@@ -517,6 +517,91 @@ static int snr_solve(int m, int ns, const double *wgt, double norm, const cplx *
     }
     for (int l = 0; l < m; ++l) D[l] = dl[l];
     free(A); free(V); free(lam); free(u); free(rho); free(dl);
+    return st;
+}
+
+/* The same for a complex Hermitian matrix: the rotation of (p, q) first turns A_pq real by the
+ * phase e^{-i phi} on q (phi = arg A_pq), then applies the real rotation of |A_pq|; with
+ * U_pp = c, U_pq = s, U_qp = -s e^{-i phi}, U_qq = c e^{-i phi}: A <- U^H A U, V <- V U. */
+int orc_eigh_herm(int32_t m, cplx *A, cplx *V, double *lam)
+{
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) V[(size_t)i * m + j] = (i == j) ? 1.0 : 0.0;
+    int sweep = 0;
+    for (; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                cplx a = A[(size_t)i * m + j];
+                double a2 = creal(a) * creal(a) + cimag(a) * cimag(a);
+                tot += a2;
+                if (i != j) off += a2;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                cplx apq = A[(size_t)p * m + q];
+                double aa = cabs(apq);
+                if (aa == 0.0) continue;
+                cplx ph = apq / aa;
+                double theta = (creal(A[(size_t)q * m + q]) - creal(A[(size_t)p * m + p])) / (2.0 * aa);
+                double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < m; ++k) {   /* A U */
+                    cplx akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
+                    A[(size_t)k * m + p] = c * akp - sn * conj(ph) * akq;
+                    A[(size_t)k * m + q] = sn * akp + c * conj(ph) * akq;
+                }
+                for (int k = 0; k < m; ++k) {   /* U^H (A U) */
+                    cplx apk = A[(size_t)p * m + k], aqk = A[(size_t)q * m + k];
+                    A[(size_t)p * m + k] = c * apk - sn * ph * aqk;
+                    A[(size_t)q * m + k] = sn * apk + c * ph * aqk;
+                }
+                for (int k = 0; k < m; ++k) {   /* V U */
+                    cplx vkp = V[(size_t)k * m + p], vkq = V[(size_t)k * m + q];
+                    V[(size_t)k * m + p] = c * vkp - sn * conj(ph) * vkq;
+                    V[(size_t)k * m + q] = sn * vkp + c * conj(ph) * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < m; ++i) lam[i] = creal(A[(size_t)i * m + i]);
+    return sweep < 100 ? ORC_OK : ORC_E_NUMERIC;
+}
+
+/* The SNR solve for a complex Hermitian S (the RBM): rho = V^H D, u_k(x) = sum_l V_lk
+ * (O_l(x) - <O_l>), q_k(x) = conj(u_k(x)) (G(x) - <G>), otherwise as for the real S. */
+static int snr_solve_herm(int m, int ns, const double *wgt, double norm, const cplx *O, const cplx *ob,
+                          const cplx *S, double eps, const cplx *dG, double tau, cplx *D, double *eig_out)
+{
+    cplx *A = malloc(sizeof(cplx) * (size_t)m * m), *V = malloc(sizeof(cplx) * (size_t)m * m);
+    double *lam = malloc(sizeof(double) * m);
+    cplx *rho = malloc(sizeof(cplx) * m), *dl = calloc(m, sizeof(cplx));
+    if (!A || !V || !lam || !rho || !dl) return ORC_E_NOMEM;
+    for (int k = 0; k < m; ++k)
+        for (int l = 0; l < m; ++l) A[(size_t)k * m + l] = S[(size_t)k * m + l] + (k == l ? eps : 0.0);
+    int st = orc_eigh_herm(m, A, V, lam);
+    double lmax = 0.0;
+    for (int k = 0; k < m; ++k) lmax = fmax(lmax, lam[k]);
+    for (int k = 0; k < m && st == ORC_OK; ++k) {
+        cplx r = 0.0;
+        for (int l = 0; l < m; ++l) r += conj(V[(size_t)l * m + k]) * D[l];
+        rho[k] = r;
+        double q2 = 0.0;
+        for (int x = 0; x < ns; ++x) {
+            cplx v = 0.0;
+            for (int l = 0; l < m; ++l) v += V[(size_t)l * m + k] * (O[(size_t)l * ns + x] - ob[l]);
+            double u2 = creal(v) * creal(v) + cimag(v) * cimag(v);
+            q2 += wgt[x] * u2 * (creal(dG[x]) * creal(dG[x]) + cimag(dG[x]) * cimag(dG[x]));
+        }
+        double var = q2 * norm - (creal(r) * creal(r) + cimag(r) * cimag(r));
+        double snr = var > 0.0 ? cabs(r) * sqrt((double)ns) / sqrt(var) : INFINITY;
+        double keep = (lam[k] > 1e-14 * lmax && cabs(r) > 0.0) ? 1.0 / (1.0 + pow(tau / snr, 6.0)) : 0.0;
+        if (eig_out) { eig_out[2 * k] = lam[k]; eig_out[2 * k + 1] = snr; }
+        if (keep > 0.0)
+            for (int l = 0; l < m; ++l) dl[l] += V[(size_t)l * m + k] * (keep * rho[k] / lam[k]);
+    }
+    for (int l = 0; l < m; ++l) D[l] = dl[l];
+    free(A); free(V); free(lam); free(rho); free(dl);
     return st;
 }
 
@@ -733,9 +818,7 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
         }
         /* regularised solve (S + eps I) delta = D */
         t2 = wall_seconds();
-        if (want_solve == 1 && cf->regulariser == ORC_REG_SNR && an->kind == ORC_RBM) {
-            status = ORC_E_INVAL;
-        } else if (want_solve == 1 && cf->regulariser == ORC_REG_SNR) {
+        if (want_solve == 1 && cf->regulariser == ORC_REG_SNR) {
             cplx *dG = malloc(sizeof(cplx) * ns), gm = 0.0;
             if (!dG) return ORC_E_NOMEM;
             for (int x = 0; x < ns; ++x) {   /* G(x) = -i dt E_eff(x) + sum_n dW_n B^n(x) */
@@ -746,7 +829,12 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
             }
             gm *= norm;
             for (int x = 0; x < ns; ++x) dG[x] -= gm;
-            status = snr_solve(m, ns, wgt, norm, O, ob, S, cf->diag_shift, dG, cf->snr_tau, D, out ? out->eig : NULL);
+            if (an->kind == ORC_RBM)
+                status = snr_solve_herm(m, ns, wgt, norm, O, ob, S, cf->diag_shift, dG, cf->snr_tau, D,
+                                        out ? out->eig : NULL);
+            else
+                status = snr_solve(m, ns, wgt, norm, O, ob, S, cf->diag_shift, dG, cf->snr_tau, D,
+                                   out ? out->eig : NULL);
             free(dG);
         } else if (want_solve == 1) {
             for (int k = 0; k < m; ++k) S[(size_t)k * m + k] += cf->diag_shift;

@@ -7,6 +7,7 @@ scheme the paper cites and does not reproduce, so it is pinned by what fixes it 
   tau -> infinity removes every component: delta = 0
   one spin (M = 1) with the closed-form local energy h exp(-2 a s): the filter by hand
   G scaled by c (dt -> c dt, no jumps): SNR unchanged, delta scaled by c
+  the Hermitian (RBM) variant: its Jacobi against LAPACK, the tau limits, the scale invariance
 """
 import numpy as np
 import pytest
@@ -98,8 +99,38 @@ def test_scale_invariance_of_the_filter(orc):
     assert np.abs(r2["delta"] - 3 * r1["delta"]).max() < 1e-12 * np.abs(r2["delta"]).max()
 
 
-def test_rbm_is_rejected(orc):
-    pb, th, dw, m = _case(orc, 1, 2, n=4)
-    c = orc.Config(n_samples=64, n_chains=4, seed=3, regulariser=orc.REG_SNR)
-    r = orc.evaluate(pb, 1, 2, c, th, orc.init_chains(3, 0, 4, 4), dw=dw)
-    assert r["status"] != 0
+@pytest.mark.parametrize("m", [1, 3, 12, 30])
+def test_hermitian_jacobi_matches_lapack(orc, m):
+    rng = np.random.default_rng(10 + m)
+    X = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    A = X + X.conj().T
+    lam, V = orc.eigh_herm(A)
+    ref = np.linalg.eigvalsh(A)
+    assert np.abs(np.sort(lam) - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+    assert np.abs(V.conj().T @ V - np.eye(m)).max() < 1e-13
+    assert np.abs(A @ V - V * lam[None, :]).max() < 1e-12 * max(1.0, np.abs(ref).max())
+    # a real symmetric input gives the real routine's spectrum
+    R = X.real + X.real.T
+    assert np.abs(np.sort(orc.eigh_herm(R)[0]) - np.sort(orc.eigh_sym(R)[0])).max() < 1e-12 * np.abs(R).max()
+
+
+def test_rbm_tau_limits(orc):
+    pb, th, dw, m = _case(orc, 1, 3, n=5)
+    r0 = _eval(orc, pb, 1, 3, th, dw, diag_shift=1e-3)
+    r1 = _eval(orc, pb, 1, 3, th, dw, diag_shift=1e-3, regulariser=orc.REG_SNR, snr_tau=0.0)
+    assert np.abs(r1["delta"] - r0["delta"]).max() < 1e-10 * np.abs(r0["delta"]).max()
+    ref = np.linalg.eigvalsh(r0["S"] + 1e-3 * np.eye(m))
+    assert np.abs(np.sort(r1["eig"][:, 0]) - ref).max() < 1e-13
+    r2 = _eval(orc, pb, 1, 3, th, dw, diag_shift=1e-3, regulariser=orc.REG_SNR, snr_tau=1e300)
+    assert np.all(r2["delta"] == 0)
+    r4 = _eval(orc, pb, 1, 3, th, dw, diag_shift=1e-3, regulariser=orc.REG_SNR, snr_tau=4.0)
+    assert (r4["eig"][:, 1] < 4).any() and (r4["eig"][:, 1] > 4).any()
+
+
+def test_rbm_scale_invariance(orc):
+    pb, th, _, m = _case(orc, 1, 3, n=5, jumps=False)
+    r1 = _eval(orc, pb, 1, 3, th, None, dt=0.01, diag_shift=1e-3, regulariser=orc.REG_SNR)
+    r2 = _eval(orc, pb, 1, 3, th, None, dt=0.03, diag_shift=1e-3, regulariser=orc.REG_SNR)
+    assert np.allclose(np.sort(r1["eig"][:, 0]), np.sort(r2["eig"][:, 0]), rtol=1e-12, atol=0)
+    assert np.allclose(np.sort(r1["eig"][:, 1]), np.sort(r2["eig"][:, 1]), rtol=1e-8, atol=0)
+    assert np.abs(r2["delta"] - 3 * r1["delta"]).max() < 1e-12 * np.abs(r2["delta"]).max()
