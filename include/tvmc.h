@@ -118,8 +118,9 @@ typedef struct {
  * |rho_k| sqrt(N_s) / sqrt(<|q_k|^2> - |rho_k|^2) over the per-sample contributions
  * q_k(x) = u_k(x) (G(x) - <G>), u_k(x) = sum_l V_lk (O_l(x) - <O_l>), G(x) = -i dt E_eff(x)
  * + sum_n B^n(x) dW_n; delta = sum_k V_k keep_k rho_k / lam_k, eigenvalues below 1e-14 of the
- * largest dropped.  Real S only (the Jastrow ansaetze), parameter space, M <= 2176; eps may be
- * 0.  The eigen-decomposition (parallel Jacobi) overwrites S: after tvmc_sr_solve, TVMC_Q_S
+ * largest dropped.  Parameter space, M <= 2176; eps may be 0.  For the RBM's complex Hermitian S
+ * the rotations carry the phase of A_pq and V is unitary (rho = V^H D, u_k = sum_l V_lk (O_l -
+ * <O_l>), q_k = conj(u_k) (G - <G>)).  The eigen-decomposition (parallel Jacobi) overwrites S: after tvmc_sr_solve, TVMC_Q_S
  * holds diag(lam) up to rounding, and TVMC_Q_EIG the pairs (lam_k, SNR_k). */
 enum { TVMC_REG_SHIFT = 0, TVMC_REG_SNR = 1 };
 

@@ -1,5 +1,5 @@
 // SNR-regularised solve (the regulariser named in the text after Eq. 9) for a real symmetric S
-// (the Jastrow ansaetze): D is written in the eigenbasis of S + eps I and each component
+// (the Jastrow ansaetze; the complex Hermitian S of the RBM at the end of this file): D is written in the eigenbasis of S + eps I and each component
 // rho_k = (V^T D)_k is kept with weight 1 / (1 + (tau / SNR_k)^6), the smooth cutoff of Schmitt
 // and Heyl's scheme, where SNR_k = |rho_k| sqrt(N_s) / sqrt(<|q_k|^2> - |rho_k|^2) is computed
 // from the per-sample contributions q_k(x) = u_k(x) (G(x) - <G>), u_k(x) = sum_l V_lk
@@ -355,6 +355,263 @@ __global__ void k_snr_back(Dev a, int stage) {
     double2 *out = stage ? a.d1 : a.d0;
     const double2 dl = make_double2(re, im);
     out[(size_t)t * a.m + l] = dl;
+    if (!isfinite(re) || !isfinite(im)) a.flags[t] = 1;
+}
+
+// ---------------------------------------------------------------- complex Hermitian S (RBM)
+// The same steps with W = V^H kept as rows.  The rotation of a pair (p, q) folds the phase
+// e^{i phi} = A_pq / |A_pq| into the real rotation of |A_pq|: A <- U^H A U with U_pp = c,
+// U_pq = s, U_qp = -s e^{-i phi}, U_qq = c e^{-i phi}, and W <- U^H W.  rho = W D,
+// u_k(x) = sum_l conj(W_kl) (O_l(x) - <O_l>), q_k = conj(u_k) (G - <G>), delta = W^H w.
+
+__device__ __forceinline__ double2 zmul_(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zconj_(double2 a) { return make_double2(a.x, -a.y); }
+// c a - s (ph b), s a + c (ph b)
+__device__ __forceinline__ void zrot(double2 &a, double2 &b, double c, double s, double2 ph) {
+    const double2 pb = zmul_(ph, b);
+    const double2 na = make_double2(c * a.x - s * pb.x, c * a.y - s * pb.y);
+    const double2 nb = make_double2(s * a.x + c * pb.x, s * a.y + c * pb.y);
+    a = na;
+    b = nb;
+}
+
+// S + eps I (lower triangle) -> full Hermitian matrix; W = I
+__global__ void k_zsnr_init(Dev a) {
+    const int t = blockIdx.y;
+    const size_t mm = (size_t)a.m * a.m;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= mm) return;
+    const int i = (int)(idx / a.m), j = (int)(idx % a.m);
+    double2 *S = (double2 *)a.S + (size_t)t * mm;
+    if (j > i) S[idx] = zconj_(S[(size_t)j * a.m + i]);
+    ((double2 *)a.snrV)[(size_t)t * mm + idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+}
+
+__global__ __launch_bounds__(JAC_THREADS) void k_zjacobi(Dev a) {
+    __shared__ int sp[JAC_MAXP], sq[JAC_MAXP];
+    __shared__ double sc[JAC_MAXP], ss[JAC_MAXP];
+    __shared__ double2 sph[JAC_MAXP];
+    __shared__ double red[JAC_THREADS / 64][2];
+    __shared__ int done;
+    const int t = blockIdx.x, m = a.m;
+    const int mp = m + (m & 1), K = mp - 1, np = mp / 2;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double2 *A = (double2 *)a.S + (size_t)t * m * m;
+    double2 *W = (double2 *)a.snrV + (size_t)t * m * m;
+    for (int sweep = 0;; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int e = tid; e < m * m; e += JAC_THREADS) {
+            const double2 v = A[e];
+            const double v2 = v.x * v.x + v.y * v.y;
+            tot += v2;
+            if (e / m != e % m) off += v2;
+        }
+        off = wave_sum(off);
+        tot = wave_sum(tot);
+        if (lane == 0) {
+            red[wave][0] = off;
+            red[wave][1] = tot;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double o = 0.0, s = 0.0;
+            for (int w = 0; w < JAC_THREADS / 64; ++w) {
+                o += red[w][0];
+                s += red[w][1];
+            }
+            done = (o <= 1e-30 * s) ? 1 : (sweep == JAC_MAX_SWEEPS ? -1 : 0);
+        }
+        __syncthreads();
+        if (done != 0) break;
+        for (int r = 0; r < K; ++r) {
+            for (int i = tid; i < np; i += JAC_THREADS) {
+                int p = i == 0 ? r : (r + i) % K;
+                int q = i == 0 ? K : (r - i + K) % K;
+                if (p > q) {
+                    const int x = p;
+                    p = q;
+                    q = x;
+                }
+                double c = 1.0, s = 0.0;
+                double2 ph = make_double2(1.0, 0.0);
+                if (q < m) {
+                    const double2 apq = A[(size_t)p * m + q];
+                    const double aa = sqrt(apq.x * apq.x + apq.y * apq.y);
+                    if (aa != 0.0) {
+                        ph = make_double2(apq.x / aa, apq.y / aa);
+                        const double theta = (A[(size_t)q * m + q].x - A[(size_t)p * m + p].x) / (2.0 * aa);
+                        const double tn = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                        c = 1.0 / sqrt(tn * tn + 1.0);
+                        s = tn * c;
+                    }
+                }
+                sp[i] = p;
+                sq[i] = q;
+                sc[i] = c;
+                ss[i] = s;
+                sph[i] = ph;
+            }
+            __syncthreads();
+            for (int e = tid; e < np * m; e += JAC_THREADS) {   // rows p, q of A and of W: U^H .
+                const int i = e / m, j = e % m, p = sp[i], q = sq[i];
+                if (q >= m) continue;
+                double2 x = A[(size_t)p * m + j], y = A[(size_t)q * m + j];
+                zrot(x, y, sc[i], ss[i], sph[i]);
+                A[(size_t)p * m + j] = x;
+                A[(size_t)q * m + j] = y;
+                double2 u = W[(size_t)p * m + j], v = W[(size_t)q * m + j];
+                zrot(u, v, sc[i], ss[i], sph[i]);
+                W[(size_t)p * m + j] = u;
+                W[(size_t)q * m + j] = v;
+            }
+            __syncthreads();
+            for (int e = tid; e < np * m; e += JAC_THREADS) {   // columns p, q of A: . U
+                const int i = e % np, k = e / np, p = sp[i], q = sq[i];
+                if (q >= m) continue;
+                double2 x = A[(size_t)k * m + p], y = A[(size_t)k * m + q];
+                zrot(x, y, sc[i], ss[i], zconj_(sph[i]));
+                A[(size_t)k * m + p] = x;
+                A[(size_t)k * m + q] = y;
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0 && done < 0) a.flags[t] = 1;
+}
+
+// rho_k = sum_l W_kl D_l
+__global__ void k_zsnr_rho(Dev a) {
+    const int t = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.m) return;
+    const double2 *w = (const double2 *)a.snrV + ((size_t)t * a.m + k) * a.m;
+    const double2 *D = a.D + (size_t)t * a.m;
+    double re = 0.0, im = 0.0;
+    for (int l = 0; l < a.m; ++l) {
+        const double2 v = zmul_(w[l], D[l]);
+        re += v.x;
+        im += v.y;
+    }
+    a.snrRho[(size_t)t * a.m + k] = make_double2(re, im);
+}
+
+// centred RBM log-derivative O_l(x) - <O_l>: s_l, tanh g_j, s_i tanh g_j
+__device__ __forceinline__ double2 rbm_dO(const Dev &a, int t, int l, int x) {
+    const uint64_t mk = a.samples[(size_t)t * a.ns + x];
+    double2 o;
+    if (l < a.n) {
+        o = make_double2(((mk >> l) & 1ull) ? 1.0 : -1.0, 0.0);
+    } else if (l < a.n + a.nh) {
+        o = a.tt[((size_t)t * a.ns + x) * a.nh + (l - a.n)];
+    } else {
+        const int i = (l - a.n - a.nh) / a.nh, j = (l - a.n - a.nh) % a.nh;
+        const double si = ((mk >> i) & 1ull) ? 1.0 : -1.0;
+        const double2 th = a.tt[((size_t)t * a.ns + x) * a.nh + j];
+        o = make_double2(si * th.x, si * th.y);
+    }
+    const double2 ob = a.obarc[(size_t)t * a.m + l];
+    return make_double2(o.x - ob.x, o.y - ob.y);
+}
+
+// Partial sums over 64-sample blocks of |u_k(x)|^2 |G(x) - <G>|^2 (as k_snr_var, complex)
+__global__ __launch_bounds__(256) void k_zsnr_var(Dev a) {
+    __shared__ double2 vs[SV_K][SV_L + 1];
+    __shared__ double2 os[SV_L][SV_X + 1];
+    __shared__ double red[16][SV_K];
+    const int t = blockIdx.z, k0 = blockIdx.x * SV_K, x0 = blockIdx.y * SV_X;
+    const int tid = threadIdx.x, tk = tid >> 4, tx = tid & 15;
+    const int m = a.m, ns = a.ns;
+    const double2 *W = (const double2 *)a.snrV + (size_t)t * m * m;
+    double ur[4][4] = {}, ui[4][4] = {};
+    for (int l0 = 0; l0 < m; l0 += SV_L) {
+        __syncthreads();
+        for (int e = tid; e < SV_K * SV_L; e += 256) {
+            const int kk = e / SV_L, ll = e % SV_L, k = k0 + kk, l = l0 + ll;
+            vs[kk][ll] = (k < m && l < m) ? zconj_(W[(size_t)k * m + l]) : make_double2(0.0, 0.0);
+        }
+        for (int e = tid; e < SV_L * SV_X; e += 256) {
+            const int ll = e / SV_X, xx = e % SV_X, l = l0 + ll, x = x0 + xx;
+            os[ll][xx] = (l < m && x < ns) ? rbm_dO(a, t, l, x) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        for (int ll = 0; ll < SV_L; ++ll) {
+            double2 v[4], o[4];
+            for (int i = 0; i < 4; ++i) v[i] = vs[tk * 4 + i][ll];
+            for (int j = 0; j < 4; ++j) o[j] = os[ll][tx * 4 + j];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    ur[i][j] += v[i].x * o[j].x - v[i].y * o[j].y;
+                    ui[i][j] += v[i].x * o[j].y + v[i].y * o[j].x;
+                }
+        }
+    }
+    const double2 gb = a.gbar[t];
+    double g2[4];
+    for (int j = 0; j < 4; ++j) {
+        const int x = x0 + tx * 4 + j;
+        g2[j] = 0.0;
+        if (x < ns) {
+            const double2 g = a.G[(size_t)t * ns + x];
+            const double dr = g.x - gb.x, di = g.y - gb.y;
+            g2[j] = dr * dr + di * di;
+        }
+    }
+    for (int i = 0; i < 4; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < 4; ++j) s += (ur[i][j] * ur[i][j] + ui[i][j] * ui[i][j]) * g2[j];
+        red[tx][tk * 4 + i] = s;
+    }
+    __syncthreads();
+    if (tid < SV_K && k0 + tid < m) {
+        double s = 0.0;
+        for (int q = 0; q < 16; ++q) s += red[q][tid];
+        a.snrPart[((size_t)t * a.snr_nxb + blockIdx.y) * m + k0 + tid] = s;
+    }
+}
+
+// SNR_k, keep_k and w_k (lam_k from the real diagonal)
+__global__ __launch_bounds__(256) void k_zsnr_finish(Dev a) {
+    __shared__ double red[4];
+    const int t = blockIdx.x, m = a.m, tid = threadIdx.x;
+    const double2 *A = (const double2 *)a.S + (size_t)t * m * m;
+    double lmax = 0.0;
+    for (int k = tid; k < m; k += 256) lmax = fmax(lmax, A[(size_t)k * m + k].x);
+    for (int o = 32; o > 0; o >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, o));
+    if ((tid & 63) == 0) red[tid >> 6] = lmax;
+    __syncthreads();
+    lmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    for (int k = tid; k < m; k += 256) {
+        double q2 = 0.0;
+        for (int b = 0; b < a.snr_nxb; ++b) q2 += a.snrPart[((size_t)t * a.snr_nxb + b) * m + k];
+        const double2 r = a.snrRho[(size_t)t * m + k];
+        const double ar = sqrt(r.x * r.x + r.y * r.y);
+        const double var = q2 / (double)a.ns - (r.x * r.x + r.y * r.y);
+        const double snr = var > 0.0 ? ar * sqrt((double)a.ns) / sqrt(var) : INFINITY;
+        const double lam = A[(size_t)k * m + k].x;
+        const double keep = (lam > 1e-14 * lmax && ar > 0.0) ? 1.0 / (1.0 + pow(a.snr_tau / snr, 6.0)) : 0.0;
+        a.snrW[(size_t)t * m + k] = keep > 0.0 ? make_double2(keep * r.x / lam, keep * r.y / lam) : make_double2(0.0, 0.0);
+        a.snrEig[((size_t)t * m + k) * 2] = lam;
+        a.snrEig[((size_t)t * m + k) * 2 + 1] = snr;
+    }
+}
+
+// delta_l = sum_k conj(W_kl) w_k
+__global__ void k_zsnr_back(Dev a, int stage) {
+    const int t = blockIdx.y;
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= a.m) return;
+    const double2 *W = (const double2 *)a.snrV + (size_t)t * a.m * a.m;
+    const double2 *w = a.snrW + (size_t)t * a.m;
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < a.m; ++k) {
+        const double2 v = zmul_(zconj_(W[(size_t)k * a.m + l]), w[k]);
+        re += v.x;
+        im += v.y;
+    }
+    double2 *out = stage ? a.d1 : a.d0;
+    out[(size_t)t * a.m + l] = make_double2(re, im);
     if (!isfinite(re) || !isfinite(im)) a.flags[t] = 1;
 }
 

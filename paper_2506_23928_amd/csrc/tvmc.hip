@@ -157,7 +157,7 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.lognorm = take(sizeof(double) * tt * 3);
     L.qhist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt);
     const size_t nxb = (size_t)(ns + 63) / 64;
-    L.snrV = take(snr ? sizeof(double) * tt * m * m : 0);
+    L.snrV = take(snr ? (rbm ? sizeof(double2) : sizeof(double)) * tt * m * m : 0);
     L.snrRho = take(snr ? sizeof(double2) * tt * m : 0);
     L.snrW = take(snr ? sizeof(double2) * tt * m : 0);
     L.snrEig = take(snr ? sizeof(double) * tt * m * 2 : 0);
@@ -256,8 +256,6 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
     if (c->regulariser != TVMC_REG_SHIFT && c->regulariser != TVMC_REG_SNR)
         return snprintf(msg, len, "bad regulariser"), TVMC_E_INVAL;
     if (c->regulariser == TVMC_REG_SNR) {
-        if (a->kind == TVMC_ANSATZ_RBM)
-            return snprintf(msg, len, "the SNR solve needs a real S (Jastrow ansaetze)"), TVMC_E_INVAL;
         if (c->solver == TVMC_SOLVER_SAMPLE_SPACE)
             return snprintf(msg, len, "the SNR solve works in parameter space"), TVMC_E_INVAL;
         if (n_params(a, p->n_sites) > 2 * JAC_MAXP)
@@ -612,6 +610,20 @@ tvmc_status run_solve(tvmc_ctx *c) {
             if (st != TVMC_OK) return st;
             hipLaunchKernelGGL(k_pushback, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage);
             LAUNCHCHECK(c, "k_pushback");
+        } else if (d.reg == TVMC_REG_SNR && d.kind == TVMC_ANSATZ_RBM) {
+            const size_t mm = (size_t)d.m * d.m;
+            hipLaunchKernelGGL(k_zsnr_init, dim3((unsigned)((mm + 255) / 256), d.nt), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_zsnr_init");
+            hipLaunchKernelGGL(k_zjacobi, dim3(d.nt), dim3(JAC_THREADS), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_zjacobi");
+            hipLaunchKernelGGL(k_zsnr_rho, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_zsnr_rho");
+            hipLaunchKernelGGL(k_zsnr_var, dim3((d.m + SV_K - 1) / SV_K, d.snr_nxb, d.nt), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_zsnr_var");
+            hipLaunchKernelGGL(k_zsnr_finish, dim3(d.nt), dim3(256), 0, c->stream, d);
+            LAUNCHCHECK(c, "k_zsnr_finish");
+            hipLaunchKernelGGL(k_zsnr_back, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage);
+            LAUNCHCHECK(c, "k_zsnr_back");
         } else if (d.reg == TVMC_REG_SNR) {
             const size_t mm = (size_t)d.m * d.m;
             hipLaunchKernelGGL(k_snr_init, dim3((unsigned)((mm + 255) / 256), d.nt), dim3(256), 0, c->stream, d);

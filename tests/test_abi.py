@@ -79,12 +79,16 @@ def test_configuration_checks_run_on_the_host():
     assert tvmc.tvmc_workspace_size(pb64, lj, ok) > 0
     with pytest.raises(tvmc.TvmcError):
         tvmc.tvmc_workspace_size(pb64, lj, tvmc.make_config(1, 1 << 20, 64, 0.01, precision=tvmc.PREC_MFMA))
-    # SNR solve: real S (Jastrow ansaetze), parameter space, M <= 2176, tau >= 0; it adds workspace
+    # SNR solve: parameter space, M <= 2176, tau >= 0; it adds workspace (complex for the RBM)
     snr = tvmc.make_config(2, 64, 8, 0.01, regulariser=tvmc.REG_SNR)
-    assert tvmc.tvmc_workspace_size(pb, an, snr) > tvmc.tvmc_workspace_size(pb, an, tvmc.make_config(2, 64, 8, 0.01))
+    plain = tvmc.make_config(2, 64, 8, 0.01)
+    assert tvmc.tvmc_workspace_size(pb, an, snr) > tvmc.tvmc_workspace_size(pb, an, plain)
+    rbm = tvmc.make_ansatz(tvmc.RBM, 2)
+    assert tvmc.tvmc_workspace_size(pb, rbm, snr) > tvmc.tvmc_workspace_size(pb, rbm, plain)
     assert tvmc.tvmc_workspace_size(pb64, an, snr) > 0          # M = 2080
-    for bad_an, bad_cfg in [(tvmc.make_ansatz(tvmc.RBM, 2), snr),
-                            (an, tvmc.make_config(2, 64, 8, 0.01, regulariser=tvmc.REG_SNR, snr_tau=-1.0)),
+    with pytest.raises(tvmc.TvmcError):
+        tvmc.tvmc_workspace_size(pb64, tvmc.make_ansatz(tvmc.RBM, 40), snr)   # M = 64 + 40 + 2560 > 2176
+    for bad_an, bad_cfg in [(an, tvmc.make_config(2, 64, 8, 0.01, regulariser=tvmc.REG_SNR, snr_tau=-1.0)),
                             (an, tvmc.make_config(2, 64, 8, 0.01, regulariser=tvmc.REG_SNR,
                                                   solver=tvmc.SOLVER_SAMPLE_SPACE)),
                             (an, tvmc.make_config(2, 64, 8, 0.01, regulariser=2))]:

@@ -4,7 +4,8 @@ differently, so the comparison is on what is unique: the sorted eigenvalues (1e-
 largest: Jacobi is backward stable to a few ulps of ||S||), the SNR of the component with the
 same eigenvalue (1e-8 relative), and delta (1e-8 relative: eigenvector rounding amplified by
 1/lam_min with lam_min ~ eps).  With tau = 0 the solve is the Cholesky one.  M <= 196 runs
-the LDS-resident Jacobi, M = 231 (N = 21) the global-memory one."""
+the LDS-resident Jacobi, M = 231 (N = 21) the global-memory one; the RBM (kind 1, FP64 S) the
+complex Hermitian Jacobi."""
 import numpy as np
 import pytest
 
@@ -31,7 +32,9 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("kind,n,d,ns,nc,tau,prec", [(0, 6, 0, 512, 8, 4.0, 0), (0, 7, 0, 320, 16, 4.0, 0),
                                                      (LJPH, 9, 2, 256, 8, 4.0, 1), (0, 6, 0, 256, 8, 0.0, 1),
-                                                     (LJPH, 64, 1, 256, 8, 4.0, 1), (0, 21, 0, 256, 8, 4.0, 1)])
+                                                     (LJPH, 64, 1, 256, 8, 4.0, 1), (0, 21, 0, 256, 8, 4.0, 1),
+                                                     (1, 5, 3, 256, 8, 4.0, 0), (1, 6, 6, 320, 8, 0.0, 0),
+                                                     (1, 7, 9, 512, 16, 4.0, 0)])
 def test_snr_evaluation_parity(tv, orc, kind, n, d, ns, nc, tau, prec):
     from paper_2506_23928_amd import tvmc as T
     J, hx, jumps = wl.random_problem(n, seed=n + 5)
@@ -115,3 +118,25 @@ def test_snr_with_the_linear_sse(tv, orc):
     for t in range(TT):
         assert _rel(ctx.get(T.Q_THETA, t), th_o[t]) < 1e-8, t
         assert abs(ctx.get(T.Q_LOGNORM, t)[0] - lq[t, 1]) < 1e-9
+
+
+def test_snr_rbm_trajectory_parity(tv, orc):
+    """6 Heun steps of an N = 5 RBM (N' = 4) with the Hermitian SNR solve and FP64 S against the
+    oracle's trajectory driver."""
+    from paper_2506_23928_amd import tvmc as T
+    n, nh, ns, nc, TT, steps = 5, 4, 512, 8, 2, 6
+    J = orc.couplings("obc", n, 1.5, 1.0)
+    jumps = [(0, i, 0.1) for i in range(n)]
+    m = orc.n_params(1, n, nh)
+    th0 = wl.random_theta(m, 0.05, seed=12)
+    cfg_o = orc.Config(n_samples=ns, n_chains=nc, burn_sweeps=2, dt=0.01, diag_shift=1e-4, seed=4, n_steps=steps,
+                       regulariser=orc.REG_SNR, snr_tau=4.0)
+    th_o, _, st = orc.run(orc.Problem(J, 0.7, jumps), 1, nh, cfg_o, th0, TT, n_threads=2)
+    assert st == 0
+    cfg = tv.make_config(TT, ns, nc, 0.01, 1e-4, 2, 1, 0, tv.HEUN, tv.PREC_FP64, 0, 0, 4, regulariser=T.REG_SNR,
+                         snr_tau=4.0)
+    ctx = tv.Context(tv.Problem(J, 0.7, jumps), cfg, kind=T.RBM, n_hidden=nh, theta0=th0)
+    ctx.sde_step(steps)
+    ctx.synchronize()
+    for t in range(TT):
+        assert _rel(ctx.get(T.Q_THETA, t), th_o[t]) < 1e-8, t
