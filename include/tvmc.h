@@ -221,6 +221,15 @@ tvmc_status tvmc_ensemble(tvmc_ctx *ctx, double *out);
 tvmc_status tvmc_get(tvmc_ctx *ctx, int32_t what, int32_t traj, void *host_out, size_t bytes);
 /* Overwrite theta (TVMC_Q_THETA) or the chain configurations (TVMC_Q_CHAINS) of a trajectory. */
 tvmc_status tvmc_set(tvmc_ctx *ctx, int32_t what, int32_t traj, const void *host_in, size_t bytes);
+/* Checkpoint at a step boundary (stage 0, before tvmc_sample): everything a later step reads --
+ * theta, the chain configurations, the step counter that keys the Philox streams, the moment
+ * and log Q histories and the last moments, log Q, the learned proposal's parameters and Adam
+ * state -- as one host blob of tvmc_state_size bytes.  Loading it into a context created with
+ * the same problem, ansatz and configuration continues the run bit for bit.  Saving off a step
+ * boundary returns TVMC_E_STATE; a blob of another shape returns TVMC_E_INVAL. */
+tvmc_status tvmc_state_size(const tvmc_ctx *ctx, size_t *bytes);
+tvmc_status tvmc_save_state(tvmc_ctx *ctx, void *host_out, size_t bytes);
+tvmc_status tvmc_load_state(tvmc_ctx *ctx, const void *host_in, size_t bytes);
 /* Current step index and stage (0 predictor, 1 corrector). */
 tvmc_status tvmc_position(const tvmc_ctx *ctx, int32_t *step, int32_t *stage);
 /* Wait for the stream and report TVMC_E_NUMERIC if any trajectory failed. */

@@ -945,6 +945,8 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     INITCHECK(hipMemsetAsync(d.flags, 0, sizeof(int) * T, ctx->stream));
     INITCHECK(hipMemsetAsync(d.lognorm, 0, sizeof(double) * 3 * (size_t)T, ctx->stream));
     INITCHECK(hipMemsetAsync(d.qhist, 0, sizeof(double) * (size_t)(d.nobs > 0 ? d.nobs : 1) * T, ctx->stream));
+    INITCHECK(hipMemsetAsync(d.hist, 0, sizeof(double) * 9 * (size_t)(d.nobs > 0 ? d.nobs : 1) * T, ctx->stream));
+    INITCHECK(hipMemsetAsync(d.mom, 0, sizeof(double) * 9 * (size_t)T, ctx->stream));
     INITCHECK(hipMemsetAsync(d.d0, 0, sizeof(double2) * (size_t)T * m, ctx->stream));
     INITCHECK(hipMemsetAsync(d.d1, 0, sizeof(double2) * (size_t)T * m, ctx->stream));
     hipLaunchKernelGGL(k_init_chains, dim3((c->n_chains + 63) / 64, T), dim3(64), 0, ctx->stream, d);
@@ -1121,6 +1123,111 @@ tvmc_status tvmc_set(tvmc_ctx *c, int32_t what, int32_t traj, const void *host, 
             if (!std::isfinite(((const double *)host)[i])) return set_err(c, "tvmc_set: theta not finite"), TVMC_E_INVAL;
     HIPCHECK(c, hipMemcpyAsync(dst, host, nb, hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TVMC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checkpoint blob: a header of 16 int64 (magic, version, N, M, T, chains, proposal parameters,
+// history slots, kind, step, slots used, Adam step, reserved...), then theta [T][M] double2,
+// chains [T][C] u64, log Q / predictor increment / log Q of the last moments [3][T] double,
+// last moments [T][9], moment history [nobs][T][9], log Q history [nobs][T], and with the
+// learned proposal its parameters and Adam moments [3][T][P] float.
+constexpr int64_t STATE_MAGIC = 0x31455441534d5654ll;   // "TVMSATE1"
+struct StatePart {
+    void *dev;
+    size_t bytes;
+};
+std::vector<StatePart> state_parts(const tvmc_ctx *c) {
+    const Dev &d = c->d;
+    const size_t T = (size_t)d.nt, nobs = (size_t)(d.nobs > 0 ? d.nobs : 0);
+    std::vector<StatePart> p = {{d.theta, sizeof(double2) * T * d.m}, {d.chains, sizeof(uint64_t) * T * d.nc},
+                                {d.lognorm, sizeof(double) * 3 * T}, {d.mom, sizeof(double) * T * 9}};
+    if (nobs) {
+        p.push_back({d.hist, sizeof(double) * nobs * T * 9});
+        p.push_back({d.qhist, sizeof(double) * nobs * T});
+    }
+    if (d.ar) {
+        p.push_back({d.arP, sizeof(float) * T * d.arnp});
+        p.push_back({d.arM, sizeof(float) * T * d.arnp});
+        p.push_back({d.arV, sizeof(float) * T * d.arnp});
+    }
+    return p;
+}
+void state_header(const tvmc_ctx *c, int64_t h[16]) {
+    const Dev &d = c->d;
+    for (int i = 0; i < 16; ++i) h[i] = 0;
+    h[0] = STATE_MAGIC;
+    h[1] = 1;
+    h[2] = d.n;
+    h[3] = d.m;
+    h[4] = d.nt;
+    h[5] = d.nc;
+    h[6] = (int64_t)d.arnp;
+    h[7] = d.nobs;
+    h[8] = d.kind;
+    h[9] = c->step;
+    h[10] = c->nobs;
+    h[11] = c->adam_t;
+}
+size_t state_bytes(const tvmc_ctx *c) {
+    size_t b = sizeof(int64_t) * 16;
+    for (const auto &p : state_parts(c)) b += p.bytes;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+tvmc_status tvmc_state_size(const tvmc_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return TVMC_E_INVAL;
+    *bytes = state_bytes(c);
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_save_state(tvmc_ctx *c, void *host, size_t bytes) {
+    if (!c || !host) return TVMC_E_INVAL;
+    if (c->stage != 0 || c->phase != 0) return set_err(c, "tvmc_save_state: not at a step boundary"), TVMC_E_STATE;
+    if (bytes < state_bytes(c)) return set_err(c, "tvmc_save_state: buffer too small"), TVMC_E_INVAL;
+    int64_t h[16];
+    state_header(c, h);
+    memcpy(host, h, sizeof(h));
+    char *o = (char *)host + sizeof(h);
+    for (const auto &p : state_parts(c)) {
+        HIPCHECK(c, hipMemcpyAsync(o, p.dev, p.bytes, hipMemcpyDeviceToHost, c->stream));
+        o += p.bytes;
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_load_state(tvmc_ctx *c, const void *host, size_t bytes) {
+    if (!c || !host) return TVMC_E_INVAL;
+    if (c->stage != 0 || c->phase != 0) return set_err(c, "tvmc_load_state: not at a step boundary"), TVMC_E_STATE;
+    if (bytes != state_bytes(c)) return set_err(c, "tvmc_load_state: blob of another size"), TVMC_E_INVAL;
+    int64_t h[16], mine[16];
+    memcpy(h, host, sizeof(h));
+    state_header(c, mine);
+    for (int i = 0; i < 9; ++i)
+        if (h[i] != mine[i]) return set_err(c, "tvmc_load_state: blob of another shape (header word %d)", i), TVMC_E_INVAL;
+    if (h[9] < 0 || h[10] < 0 || h[10] > c->d.nobs || h[11] < 0)
+        return set_err(c, "tvmc_load_state: bad counters"), TVMC_E_INVAL;
+    const char *in = (const char *)host + sizeof(h);
+    for (const auto &p : state_parts(c)) {
+        HIPCHECK(c, hipMemcpyAsync(p.dev, in, p.bytes, hipMemcpyHostToDevice, c->stream));
+        in += p.bytes;
+    }
+    if (c->d.ar) {
+        hipLaunchKernelGGL(k_ar_copy, dim3((c->d.ah * c->d.n + 255) / 256, c->d.nt), dim3(256), 0, c->stream, c->d);
+        LAUNCHCHECK(c, "k_ar_copy");
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->step = (int)h[9];
+    c->nobs = (int)h[10];
+    c->adam_t = (int)h[11];
     return TVMC_OK;
 }
 

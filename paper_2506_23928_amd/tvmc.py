@@ -59,7 +59,8 @@ class TvmcError(RuntimeError):
 _lib = None
 EXPORTED = ["tvmc_workspace_size", "tvmc_init", "tvmc_workspace_size_batch", "tvmc_init_batch", "tvmc_sample", "tvmc_estimate", "tvmc_sr_solve", "tvmc_update",
             "tvmc_sde_step", "tvmc_train_proposal", "tvmc_observables", "tvmc_ensemble", "tvmc_get", "tvmc_set", "tvmc_position",
-            "tvmc_synchronize", "tvmc_set_timing", "tvmc_timing", "tvmc_last_error", "tvmc_destroy"]
+            "tvmc_synchronize", "tvmc_set_timing", "tvmc_timing", "tvmc_last_error", "tvmc_destroy",
+            "tvmc_state_size", "tvmc_save_state", "tvmc_load_state"]
 
 
 def lib():
@@ -325,6 +326,20 @@ class Context:
         if what == Q_EIG:
             out = out.reshape(-1, 2)
         return out
+
+    def save_state(self) -> np.ndarray:
+        """Checkpoint at a step boundary (tvmc_save_state) as a uint8 array."""
+        n = ctypes.c_size_t(0)
+        _check(lib().tvmc_state_size(self.ctx, ctypes.byref(n)), self.ctx)
+        blob = np.zeros(n.value, np.uint8)
+        _check(lib().tvmc_save_state(self.ctx, blob.ctypes.data_as(ctypes.c_void_p), ctypes.c_size_t(blob.nbytes)),
+               self.ctx)
+        return blob
+
+    def load_state(self, blob):
+        blob = np.ascontiguousarray(blob, dtype=np.uint8)
+        _check(lib().tvmc_load_state(self.ctx, blob.ctypes.data_as(ctypes.c_void_p), ctypes.c_size_t(blob.nbytes)),
+               self.ctx)
 
     def train_proposal(self, n_iters):
         tvmc_train_proposal(self.ctx, n_iters)
