@@ -7,7 +7,13 @@
  * Bertaina, Galli).  Equation numbers below are those of the paper:
  *   (1) Lindblad equation, (2) nonlinear Ito SSE, (4)-(5) Stratonovich SSE and H_eff^Strat,
  *   (8) the otVMC equations with the definitions of O_k, E_eff, B^n, S, F, N^n that follow
- *   it, (10) LITF Hamiltonian, (11) RBM, (12) Jastrow, App. C (SDE solvers).
+ *   it, (10) LITF Hamiltonian, (11) RBM, (12) Jastrow, the LJPHd ansatz of the LITF section,
+ *   App. B (linear SSE), App. C (SDE solvers).
+ *
+ * Parity unpinned: the functional form of the SNR regulariser (snr_solve, snr_solve_herm).
+ * The paper names the scheme and its threshold but takes the form from a reference it does not
+ * reproduce; the form used here is stated where it is defined, and the tests pin its limits
+ * (tau = 0, tau -> infinity), a one-spin case and its scale invariance, not the form itself.
  *
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may load this
  * library.  It shares no source with the GPU library; the two only meet in the seeded
