@@ -77,7 +77,7 @@ def ansatz_of(tv, w):
     return tv.JASTROW, 0, tv.n_params(tv.JASTROW, w["n"]), None
 
 
-def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, solver=0, regulariser=0):
+def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, solver=0, regulariser=0, graph=False):
     from paper_2506_23928_amd.problem import kac_couplings
     import workloads as wl
     lx, ly = wl.lattice(w)
@@ -92,7 +92,7 @@ def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, s
                          steps // w["obs_every"] + 2, w["seed"], traj_offset, proposal=proposal,
                          ar_hidden=w.get("ar_hidden", 128), ar_train_every=w.get("ar_train_every", 20),
                          ar_train_iters=w.get("ar_train_iters", 50), ar_lr=w.get("ar_lr", 3e-3), solver=solver,
-                         regulariser=regulariser, snr_tau=w.get("snr_tau", 4.0))
+                         regulariser=regulariser, snr_tau=w.get("snr_tau", 4.0), use_graph=graph)
     return tv.Context(prob, cfg, kind=kind, n_hidden=nh, theta0=th0)
 
 
@@ -201,6 +201,8 @@ def main():
                     help="FP64 Cholesky with one or several workgroups per trajectory (auto: by batch size)")
     ap.add_argument("--regulariser", choices=["shift", "snr"], default="shift",
                     help="diagonal shift (Cholesky) or the SNR filter in S's eigenbasis (Jastrow ansaetze)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay one captured HIP graph per plain step (per-kernel timing is then off)")
     ap.add_argument("--autocorr", action="store_true",
                     help="measure the integrated autocorrelation time with and without the learned proposal")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -242,12 +244,12 @@ def main():
         return
     solver = {"auto": tv.tvmc.SOLVER_AUTO, "one": tv.tvmc.SOLVER_ONE_GROUP, "multi": tv.tvmc.SOLVER_MULTI_GROUP}[args.solver]
     reg = tv.tvmc.REG_SNR if args.regulariser == "snr" else tv.tvmc.REG_SHIFT
-    ctx = build_context(tv, w, prec, solver=solver, regulariser=reg)
+    ctx = build_context(tv, w, prec, solver=solver, regulariser=reg, graph=args.graph)
     for _ in range(args.warmup):
         ctx.sde_step(1)
     ctx.synchronize()
     print("bench: warmup done", file=sys.stderr, flush=True)
-    ctx.set_timing(True)
+    ctx.set_timing(not args.graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -266,7 +268,7 @@ def main():
           flush=True)
 
     # dominant kernel: the FP64 Cholesky solve (one launch covers every trajectory)
-    dom = max(groups, key=lambda g: groups[g]["total_ms"])
+    dom = max(groups, key=lambda g: groups[g]["total_ms"]) if groups else None   # None: graph replays, untimed
     ss, ns = ctx.sample_space, w["n_samples"]
     dim = ns if ss else m                 # dimension of the system solved
     if dom == "solve" and reg == tv.tvmc.REG_SNR:

@@ -110,6 +110,10 @@ typedef struct {
     int32_t unravelling;          /* TVMC_SSE_*: which stochastic Schroedinger equation is unravelled */
     int32_t regulariser;          /* TVMC_REG_*: how (S + eps I) delta = D is regularised */
     double snr_tau;               /* TVMC_REG_SNR: the SNR threshold (the paper uses 4) */
+    int32_t use_graph;            /* 1: tvmc_sde_step runs plain steps (no moments, no training, timing
+                                     off, step >= 1) by replaying one captured HIP graph of a step;
+                                     the results are the same bits as the eager launches; needs a
+                                     stream other than the default one */
 } tvmc_config;
 
 /* SHIFT: the Cholesky solve of (S + eps I) delta = D.  SNR: the regulariser the paper names in

@@ -65,7 +65,8 @@ __global__ void k_prepare_rbm(Dev a, const double2 *__restrict__ src) {
 // W_LDS: the weights fit in LDS (N N' <= 4096) and are read from there; a template flag, so
 // that every weight read compiles to an LDS or a global instruction rather than a generic one.
 template <int CPB, int QH, bool AR, bool W_LDS>
-__global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int step, int stage, int burn) {
+__global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int stage, int burn) {
+    const int step = a.dstep[0];
     __shared__ double lwr[W_LDS ? 64 * 64 : 1];
     __shared__ double lwi[W_LDS ? 64 * 64 : 1];
     __shared__ double2 tl[CPB][64 * QH];

@@ -45,9 +45,21 @@ __global__ void k_init_chains(Dev a) {
     a.chains[(size_t)t * a.nc + c] = m;
 }
 
+// the step index read by the samplers and k_draw_dw
+__global__ void k_set_step(Dev a, int step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) a.dstep[0] = step;
+}
+
+// theta_eval = theta (the predictor's evaluation point)
+__global__ void k_copy_theta(Dev a) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (size_t)a.nt * a.m) a.theta_eval[i] = a.theta[i];
+}
+
 // Real Gaussian Wiener increments dW ~ N(0, dt), Box-Muller on two 53-bit uniforms.
-__global__ void k_draw_dw(Dev a, int step) {
+__global__ void k_draw_dw(Dev a) {
     const int t = blockIdx.x;
+    const int step = a.dstep[0];
     const double two_pi = 6.283185307179586476925286766559;
     for (int q = threadIdx.x; 2 * q < a.nch; q += blockDim.x) {
         uint32_t r[4];
@@ -62,7 +74,8 @@ __global__ void k_draw_dw(Dev a, int step) {
 }
 
 template <int CPB, bool AR>
-__global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int step, int stage, int burn) {
+__global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int stage, int burn) {
+    const int step = a.dstep[0];
     __shared__ double lre[64 * 64];
     __shared__ double lim[64 * 64];
     __shared__ uint16_t arw_s[AR ? 2 * AR_LDS_W : 1];

@@ -50,6 +50,10 @@ struct tvmc_ctx {
     tvmc_config cfg{};
     int step = 0, stage = 0, phase = 0, nobs = 0, adam_t = 0;
     int cpb = 1;
+    // a plain step (no moments, no training, no timing) captured once and replayed
+    bool capturing = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     char err[512] = {0};
     bool timing = false;
     std::vector<std::string> groups;
@@ -63,7 +67,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t J, jk, js, jr, pa, pb, pidx, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
         bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, lognorm, qhist, snrV, snrRho, snrW, snrEig, snrPart, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
-        arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, total;
+        arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, dstep, total;
 };
 
 int mom_blocks_for(int ns) {
@@ -154,6 +158,7 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.hist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt * 9);
     L.ens = take(sizeof(double) * 16);
     L.flags = take(sizeof(int) * tt);
+    L.dstep = take(sizeof(int));
     L.lognorm = take(sizeof(double) * tt * 3);
     L.qhist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt);
     const size_t nxb = (size_t)(ns + 63) / 64;
@@ -255,6 +260,7 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
         return snprintf(msg, len, "bad unravelling"), TVMC_E_INVAL;
     if (c->regulariser != TVMC_REG_SHIFT && c->regulariser != TVMC_REG_SNR)
         return snprintf(msg, len, "bad regulariser"), TVMC_E_INVAL;
+    if (c->use_graph != 0 && c->use_graph != 1) return snprintf(msg, len, "bad use_graph"), TVMC_E_INVAL;
     if (c->regulariser == TVMC_REG_SNR) {
         if (c->solver == TVMC_SOLVER_SAMPLE_SPACE)
             return snprintf(msg, len, "the SNR solve works in parameter space"), TVMC_E_INVAL;
@@ -339,10 +345,15 @@ tvmc_status run_sample(tvmc_ctx *c) {
     Dev &d = c->d;
     const int T = d.nt;
     if (c->stage == 0) {
-        hipLaunchKernelGGL(k_draw_dw, dim3(T), dim3(64), 0, c->stream, d, c->step);
+        // a captured step graph leaves the step index out: it is set before every replay
+        if (!c->capturing) {
+            hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, c->stream, d, c->step);
+            LAUNCHCHECK(c, "k_set_step");
+        }
+        hipLaunchKernelGGL(k_draw_dw, dim3(T), dim3(64), 0, c->stream, d);
         LAUNCHCHECK(c, "k_draw_dw");
-        HIPCHECK(c, hipMemcpyAsync(d.theta_eval, d.theta, sizeof(double2) * (size_t)T * d.m, hipMemcpyDeviceToDevice,
-                                   c->stream));
+        hipLaunchKernelGGL(k_copy_theta, dim3((unsigned)(((size_t)T * d.m + 255) / 256)), dim3(256), 0, c->stream, d);
+        LAUNCHCHECK(c, "k_copy_theta");
     }
     const int nn = d.n * d.n;
     const int burn = d.burn + ((c->step == 0 && c->stage == 0) ? d.init_sweeps : 0);
@@ -356,7 +367,7 @@ tvmc_status run_sample(tvmc_ctx *c) {
         // chain count allows and the per-chain LDS rows fit (N' <= 128)
         const int cpb = (c->cpb == 8 && d.nc % 16 == 0 && qh <= 2) ? 16 : c->cpb;
         dim3 grid((d.nc / cpb * T + 7) / 8 * 8);
-#define RBM_LAUNCH(CPB, QH, AR, WL) hipLaunchKernelGGL((k_sample_rbm<CPB, QH, AR, WL>), grid, dim3(64 * CPB), 0, c->stream, d, c->step, c->stage, burn)
+#define RBM_LAUNCH(CPB, QH, AR, WL) hipLaunchKernelGGL((k_sample_rbm<CPB, QH, AR, WL>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
 #define RBM_CPB(QH, AR, WL)                         \
     switch (cpb) {                                  \
     case 16: if constexpr (QH <= 2) { RBM_LAUNCH(16, QH, AR, WL); } break; \
@@ -388,7 +399,7 @@ tvmc_status run_sample(tvmc_ctx *c) {
     {
         Scope sc(c, "sample");
         dim3 grid(d.nc / c->cpb, T);
-#define JAS_LAUNCH(CPB, AR) hipLaunchKernelGGL((k_sample_jastrow<CPB, AR>), grid, dim3(64 * CPB), 0, c->stream, d, c->step, c->stage, burn)
+#define JAS_LAUNCH(CPB, AR) hipLaunchKernelGGL((k_sample_jastrow<CPB, AR>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
         if (d.ar) {
             switch (c->cpb) {
             case 8: JAS_LAUNCH(8, true); break;
@@ -779,6 +790,8 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     if (!ws) return snprintf(g_err, sizeof(g_err), "workspace is null"), TVMC_E_INVAL;
     if (ws_bytes < L.total) return snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu", ws_bytes, L.total), TVMC_E_NOMEM;
     if ((uintptr_t)ws % 256) return snprintf(g_err, sizeof(g_err), "workspace must be 256-byte aligned"), TVMC_E_INVAL;
+    if (c->use_graph && !stream)   // the default stream cannot be captured
+        return snprintf(g_err, sizeof(g_err), "use_graph needs a stream other than the default one"), TVMC_E_INVAL;
 
     tvmc_ctx *ctx = new (std::nothrow) tvmc_ctx();
     if (!ctx) return TVMC_E_NOMEM;
@@ -858,6 +871,7 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.hist = (double *)(base + L.hist);
     d.ens = (double *)(base + L.ens);
     d.flags = (int *)(base + L.flags);
+    d.dstep = (int *)(base + L.dstep);
     d.linear = c->unravelling == TVMC_SSE_LINEAR;
     d.lognorm = (double *)(base + L.lognorm);
     d.dq0 = d.lognorm + T;
@@ -997,10 +1011,50 @@ tvmc_status tvmc_update(tvmc_ctx *c) {
     return run_update(c);
 }
 
+// One step through the captured graph: capture it on first use (the captured calls advance the
+// host-side position as an eager step does), then replay with the step index set beforehand.
+static tvmc_status graph_step(tvmc_ctx *c) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, c->stream, c->d, c->step);
+    LAUNCHCHECK(c, "k_set_step");
+    if (!c->gexec) {
+        HIPCHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        c->capturing = true;
+        tvmc_status st = TVMC_OK;
+        for (int stage = 0; stage < 2 && st == TVMC_OK; ++stage) {
+            if ((st = run_sample(c)) != TVMC_OK) break;
+            if ((st = run_estimate(c)) != TVMC_OK) break;
+            if ((st = run_solve(c)) != TVMC_OK) break;
+            st = run_update(c);
+        }
+        c->capturing = false;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->stream, &g);
+        if (st != TVMC_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            if (st == TVMC_OK) set_err(c, "step capture failed: %s", hipGetErrorString(e));
+            return st != TVMC_OK ? st : TVMC_E_DEVICE;
+        }
+        c->graph = g;
+        HIPCHECK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+        HIPCHECK(c, hipGraphLaunch(c->gexec, c->stream));
+        return TVMC_OK;
+    }
+    HIPCHECK(c, hipGraphLaunch(c->gexec, c->stream));
+    ++c->step;
+    return TVMC_OK;
+}
+
 tvmc_status tvmc_sde_step(tvmc_ctx *c, int32_t n_steps) {
     if (!c || n_steps < 0) return TVMC_E_INVAL;
     if (c->phase != 0 || c->stage != 0) return set_err(c, "tvmc_sde_step: a step is half done"), TVMC_E_STATE;
     for (int s = 0; s < n_steps; ++s) {
+        const bool obs = c->cfg.obs_every > 0 && c->step % c->cfg.obs_every == 0 && c->nobs < c->d.nobs;
+        const bool train = c->d.ar && c->cfg.ar_train_every > 0 && c->step % c->cfg.ar_train_every == 0;
+        if (c->cfg.use_graph && c->step >= 1 && !obs && !train && !c->timing) {
+            tvmc_status st = graph_step(c);
+            if (st != TVMC_OK) return st;
+            continue;
+        }
         for (int stage = 0; stage < 2; ++stage) {
             tvmc_status st = run_sample(c);
             if (st != TVMC_OK) return st;
@@ -1291,6 +1345,8 @@ tvmc_status tvmc_destroy(tvmc_ctx *c) {
         if (c->join[g]) (void)hipEventDestroy(c->join[g]);
     }
     if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     for (auto &t : c->timers) {
         for (auto e : t.start) (void)hipEventDestroy(e);
         for (auto e : t.stop) (void)hipEventDestroy(e);

@@ -42,7 +42,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tvmc.h"\nint main(){'
                     'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tvmc_problem), offsetof(tvmc_problem, jump_rate),'
                     'sizeof(tvmc_config), offsetof(tvmc_config, dt), offsetof(tvmc_config, precision),'
-                    'offsetof(tvmc_config, seed), offsetof(tvmc_config, unravelling), offsetof(tvmc_config, snr_tau),'
+                    'offsetof(tvmc_config, seed), offsetof(tvmc_config, unravelling), offsetof(tvmc_config, use_graph),'
                     'sizeof(tvmc_ansatz));'
                     ' return 0;}\n')
     exe = tmp_path / "layout"
@@ -50,7 +50,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     P, C, A = tvmc.tvmc_problem, tvmc.tvmc_config, tvmc.tvmc_ansatz
     want = [ctypes.sizeof(P), P.jump_rate.offset, ctypes.sizeof(C), C.dt.offset, C.precision.offset, C.seed.offset,
-            C.unravelling.offset, C.snr_tau.offset, ctypes.sizeof(A)]
+            C.unravelling.offset, C.use_graph.offset, ctypes.sizeof(A)]
     assert got == want
 
 

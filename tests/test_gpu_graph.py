@@ -1,0 +1,58 @@
+"""Captured step graphs (tvmc_config.use_graph) against eager launches.
+
+The graph holds one plain step (sampling, estimators, S, solve and update for both stages,
+the complex solver's side streams included); the step index that keys the random streams is
+set on the device before every replay.  Steps with moments or proposal training run eagerly
+in between.  Every replay is checked against the eager run, bit for bit, with the host reading
+theta (a synchronisation) between the replays."""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tv():
+    import torch
+    assert torch.cuda.is_available(), "the GPU tests need a HIP device"
+    import paper_2506_23928_amd as tv
+    from paper_2506_23928_amd import tvmc
+    tvmc.lib()
+    return tv
+
+
+@pytest.mark.parametrize("kind,nh,prec,learned,linear,reg", [
+    (0, 0, 1, False, False, 0),      # Jastrow, int8 S-build, one-workgroup Cholesky
+    (1, 4, 1, True, False, 0),       # RBM, BF16-split S, learned proposal, complex solve on two side streams
+    (2, 1, 1, False, True, 0),       # LJPH1, linear SSE
+    (0, 0, 0, False, False, 1),      # Jastrow, SNR solve
+])
+def test_graph_replays_match_eager_steps(tv, kind, nh, prec, learned, linear, reg):
+    from paper_2506_23928_amd import tvmc as T
+    n = 7
+    J, hx, jumps = wl.random_problem(n, seed=31)
+    m = tv.n_params(kind, n, nh)
+    th0 = wl.random_theta(m, 0.05, seed=6)
+    ctxs = []
+    for g in (0, 1):
+        cfg = tv.make_config(3, 256, 8, 0.01, 1e-4, 2, 1, 2, tv.HEUN, prec, 3, 4, 23,
+                             proposal=T.PROPOSAL_LEARNED if learned else T.PROPOSAL_FLIP, ar_hidden=16,
+                             ar_train_every=4, ar_train_iters=3, solver=T.SOLVER_MULTI_GROUP,
+                             unravelling=T.SSE_LINEAR if linear else T.SSE_NONLINEAR, regulariser=reg, use_graph=g)
+        ctxs.append(tv.Context(tv.Problem(J, hx, jumps), cfg, kind=kind, n_hidden=nh, theta0=th0))
+    for step in range(9):
+        for c in ctxs:
+            c.sde_step(1)
+        for t in range(3):
+            a, b = ctxs[0].get(T.Q_THETA, t), ctxs[1].get(T.Q_THETA, t)
+            assert np.array_equal(a, b), (step, t)
+            assert ctxs[0].get(T.Q_LOGNORM, t)[0] == ctxs[1].get(T.Q_LOGNORM, t)[0]
+        assert ctxs[0].position() == ctxs[1].position() == (step + 1, 0)
+    ctxs[0].sample()
+    ctxs[1].sample()
+    for t in range(3):
+        assert np.array_equal(ctxs[0].get(T.Q_SAMPLES, t), ctxs[1].get(T.Q_SAMPLES, t))
+    for c in ctxs:
+        c.synchronize()
