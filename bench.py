@@ -203,6 +203,8 @@ def main():
                     help="diagonal shift (Cholesky) or the SNR filter in S's eigenbasis (Jastrow ansaetze)")
     ap.add_argument("--graph", action="store_true",
                     help="replay one captured HIP graph per plain step (per-kernel timing is then off)")
+    ap.add_argument("--log", metavar="FILE",
+                    help="run --steps steps, appending per-step metrics as JSON lines to FILE (untimed)")
     ap.add_argument("--autocorr", action="store_true",
                     help="measure the integrated autocorrelation time with and without the learned proposal")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -237,6 +239,17 @@ def main():
         args.workload, n, m, T, w["n_samples"], w["n_chains"], len(wl.jumps(w)), args.precision,
         w.get("proposal", "flip")), file=sys.stderr, flush=True)
 
+    if args.log:
+        from paper_2506_23928_amd.metrics import JsonlLog
+        ctx = build_context(tv, w, prec)
+        ctx.set_timing(True)
+        log = JsonlLog(args.log)
+        for _ in range(args.steps):
+            ctx.sde_step(1)
+            log.write(ctx, workload=args.workload)
+        log.close()
+        print(json.dumps({"workload": args.workload, "steps": args.steps, "log": args.log}), flush=True)
+        return
     if args.autocorr:
         res = autocorrelation(tv, w, args.steps, min(T, 16))
         print(json.dumps({"workload": args.workload, "steps": args.steps, "samples_per_chain":

@@ -97,3 +97,22 @@ def test_checkpoint_errors(tv):
         c.load_state(bad)
     c.load_state(blob)
     assert c.position() == (1, 0)
+
+
+def test_metrics_log(tv, tmp_path):
+    """Per-step JSON-lines metrics (paper_2506_23928_amd.metrics) read back with sane values."""
+    import json
+    from paper_2506_23928_amd.metrics import JsonlLog
+    ctx = _make(tv, 1, 3, True, True)
+    ctx.set_timing(True)
+    log = JsonlLog(str(tmp_path / "m.jsonl"))
+    for _ in range(3):
+        ctx.sde_step(1)
+        log.write(ctx)
+    log.close()
+    recs = [json.loads(x) for x in open(tmp_path / "m.jsonl")]
+    assert [r["step"] for r in recs] == [1, 2, 3]
+    for r in recs:
+        assert 0.0 < r["accept_flip"] <= 1.0 and 0.0 <= r["accept_learned"] <= 1.0
+        assert np.isfinite(r["dtheta_norm_mean"]) and r["dtheta_norm_max"] >= r["dtheta_norm_mean"] > 0
+        assert r["log_q_std"] > 0 and "solve" in r["kernel_ms"]
