@@ -15,7 +15,11 @@ from . import tvmc
 
 
 class UnevenBatch:
-    def __init__(self, problems, kind=tvmc.JASTROW, n_hidden=0, device="cuda", streams=True, **config):
+    """autotune: None, or the path of a JSON cache: each group's solver form (and, for the
+    Jastrow ansaetze, S-build precision) is then the fastest one measured for its shape."""
+
+    def __init__(self, problems, kind=tvmc.JASTROW, n_hidden=0, device="cuda", streams=True, autotune=None,
+                 **config):
         import torch
         self.problems = list(problems)
         self.kind, self.n_hidden = kind, n_hidden
@@ -28,7 +32,12 @@ class UnevenBatch:
         start = 0
         for n in np.unique(ns):
             members = self.order[start:start + int((ns == n).sum())]
-            cfg = tvmc.make_config(n_traj=len(members), traj_offset=offset + start, **config)
+            gconf = dict(config, n_traj=len(members), traj_offset=offset + start)
+            if autotune:
+                from .autotune import tune
+                gconf.update(tune([self.problems[i] for i in members], gconf, kind, n_hidden, cache=autotune,
+                                  device=device)["choice"])
+            cfg = tvmc.make_config(**gconf)
             stream = torch.cuda.Stream(device=device) if streams else None
             ctx = tvmc.Context([self.problems[i] for i in members], cfg, kind=kind, n_hidden=n_hidden,
                                device=device, stream=stream)
