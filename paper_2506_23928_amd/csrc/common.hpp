@@ -165,6 +165,8 @@ struct Dev {
     double2 *snrRho, *snrW;   // [T][M] V^T D and the kept, scaled components
     double *snrEig;           // [T][M][2] eigenvalue, SNR
     double *snrPart;          // [T][snr_nxb][M] partial sums of u_k^2 |G - <G>|^2
+    double2 *snrRot;          // [T][sweeps][rounds][pairs] recorded rotations (c, s) of the LDS Jacobi
+    int *snrSweeps;           // [T] sweeps the LDS Jacobi ran
     int *dstep;               // [1] the step index that keys this step's Philox streams (device
                               //     resident, so a captured step graph replays for any step)
     // learned proposal (MADE): hidden width, parameter count per trajectory, buffers

@@ -121,8 +121,10 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(Dev a) {
 // The same Jacobi with S held in LDS (packed lower triangle) when M <= JL_MAXM: a round is one
 // pass over the 2 x 2 blocks of every pair of rotation pairs (A <- J^T A J in one step, each
 // entry touched once; the diagonal blocks by the stable update A_pp - t A_pq, A_qq + t A_pq,
-// A_pq = 0), while V^T stays in global memory (row updates, coalesced).  S is written back at
-// the end.
+// A_pq = 0).  The rotations (c, s) of every round are written out instead of being applied to
+// V^T at once; k_jacobi_apply_v applies them afterwards to column tiles of V^T = I held in LDS
+// (the pairs follow from the round index), so V^T crosses global memory once, not once per
+// round.  S is written back at the end.
 constexpr int JL_MAXM = 196;
 constexpr int JL_NA = JL_MAXM * (JL_MAXM + 1) / 2;
 constexpr int JL_MAXP = JL_MAXM / 2;
@@ -139,7 +141,8 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_lds(Dev a) {
     const int mp = m + (m & 1), K = mp - 1, np = mp / 2, nb = np * (np + 1) / 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double *S = a.S + (size_t)t * m * m;
-    double *Vt = a.snrV + (size_t)t * m * m;
+    double2 *rot = a.snrRot + (size_t)t * JAC_MAX_SWEEPS * K * np;
+    int nsweep = 0;
     for (int e = tid; e < m * m; e += JAC_THREADS) {
         const int i = e / m, j = e % m;
         if (j <= i) As[tri(i, j)] = S[e];
@@ -196,6 +199,7 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_lds(Dev a) {
                 sc[i] = c;
                 ss[i] = s;
                 stn[i] = tn;
+                rot[((size_t)nsweep * K + r) * np + i] = make_double2(c, s);
             }
             __syncthreads();
             for (int b = tid; b < nb; b += JAC_THREADS) {
@@ -225,19 +229,72 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_lds(Dev a) {
                 if (h1) As[tri(q1, p2)] = c2 * y10 - s2 * y11;
                 if (h1 && h2) As[tri(q1, q2)] = s2 * y10 + c2 * y11;
             }
-            for (int e = tid; e < np * m; e += JAC_THREADS) {   // rows p, q of V^T
-                const int i = e / m, j = e % m, p = sp[i], q = sq[i];
-                if (q >= m) continue;
-                const double c = sc[i], s = ss[i];
-                const double vpj = Vt[(size_t)p * m + j], vqj = Vt[(size_t)q * m + j];
-                Vt[(size_t)p * m + j] = c * vpj - s * vqj;
-                Vt[(size_t)q * m + j] = s * vpj + c * vqj;
-            }
             __syncthreads();
         }
+        ++nsweep;
     }
     for (int e = tid; e < m * m; e += JAC_THREADS) S[e] = As[tri(e / m, e % m)];
-    if (tid == 0 && done < 0) a.flags[t] = 1;
+    if (tid == 0) {
+        a.snrSweeps[t] = nsweep;
+        if (done < 0) a.flags[t] = 1;
+    }
+}
+
+// V^T = (product of the recorded rotations) applied to I, a tile of JV_COLS columns per
+// workgroup held in LDS: for every recorded round in order, rows p, q of the tile are rotated
+// (the pairs of round r follow from r as in k_jacobi_lds).
+constexpr int JV_COLS = 64;
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi_apply_v(Dev a) {
+    __shared__ double Vs[JL_MAXM * JV_COLS];
+    const int t = blockIdx.y, j0 = blockIdx.x * JV_COLS, m = a.m;
+    const int mp = m + (m & 1), K = mp - 1, np = mp / 2;
+    const int tid = threadIdx.x;
+    const int cols = (m - j0) < JV_COLS ? (m - j0) : JV_COLS;
+    for (int e = tid; e < m * JV_COLS; e += JAC_THREADS) {
+        const int i = e / JV_COLS, j = e % JV_COLS;
+        Vs[e] = (i == j0 + j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const double2 *rot = a.snrRot + (size_t)t * JAC_MAX_SWEEPS * K * np;
+    const int rounds = a.snrSweeps[t] * K;
+    // a thread's items (pair i, column j) are the same every round; the rotations of the next
+    // round are loaded while the current one is applied
+    constexpr int JV_ITEMS = (JL_MAXP * JV_COLS + JAC_THREADS - 1) / JAC_THREADS;
+    double2 cur[JV_ITEMS], nxt[JV_ITEMS];
+    for (int k = 0; k < JV_ITEMS; ++k) {
+        const int i = (tid + k * JAC_THREADS) / JV_COLS;
+        cur[k] = (rounds > 0 && i < np) ? rot[i] : make_double2(1.0, 0.0);
+    }
+    for (int rr = 0; rr < rounds; ++rr) {
+        const int r = rr % K;
+        for (int k = 0; k < JV_ITEMS; ++k) {
+            const int i = (tid + k * JAC_THREADS) / JV_COLS;
+            nxt[k] = (rr + 1 < rounds && i < np) ? rot[(size_t)(rr + 1) * np + i] : make_double2(1.0, 0.0);
+        }
+        for (int k = 0; k < JV_ITEMS; ++k) {
+            const int e = tid + k * JAC_THREADS, i = e / JV_COLS, j = e % JV_COLS;
+            if (i >= np) continue;
+            int p = i == 0 ? r : (r + i) % K;
+            int q = i == 0 ? K : (r - i + K) % K;
+            if (p > q) {
+                const int x = p;
+                p = q;
+                q = x;
+            }
+            if (q >= m || j >= cols) continue;
+            const double2 cs = cur[k];
+            const double vp = Vs[p * JV_COLS + j], vq = Vs[q * JV_COLS + j];
+            Vs[p * JV_COLS + j] = cs.x * vp - cs.y * vq;
+            Vs[q * JV_COLS + j] = cs.y * vp + cs.x * vq;
+        }
+        for (int k = 0; k < JV_ITEMS; ++k) cur[k] = nxt[k];
+        __syncthreads();
+    }
+    double *Vt = a.snrV + (size_t)t * m * m;
+    for (int e = tid; e < m * JV_COLS; e += JAC_THREADS) {
+        const int i = e / JV_COLS, j = e % JV_COLS;
+        if (j < cols) Vt[(size_t)i * m + j0 + j] = Vs[e];
+    }
 }
 
 // rho_k = sum_l V_lk D_l

@@ -66,7 +66,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, pidx, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, lognorm, qhist, snrV, snrRho, snrW, snrEig, snrPart, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
+        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, lognorm, qhist, snrV, snrRho, snrW, snrEig, snrPart, snrRot, snrSweeps, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
         arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, dstep, total;
 };
 
@@ -167,6 +167,10 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.snrW = take(snr ? sizeof(double2) * tt * m : 0);
     L.snrEig = take(snr ? sizeof(double) * tt * m * 2 : 0);
     L.snrPart = take(snr ? sizeof(double) * tt * nxb * m : 0);
+    const bool jl = snr && !rbm && m <= JL_MAXM;   // the LDS Jacobi records its rotations
+    const size_t mpe = (size_t)(m + (m & 1));
+    L.snrRot = take(jl ? sizeof(double2) * tt * JAC_MAX_SWEEPS * (mpe - 1) * (mpe / 2) : 0);
+    L.snrSweeps = take(jl ? sizeof(int) * tt : 0);
     const size_t np = ar ? ar_params(n, ah) : 0;
     L.arP = take(sizeof(float) * tt * np);
     L.arG = take(sizeof(float) * tt * np);
@@ -642,6 +646,9 @@ tvmc_status run_solve(tvmc_ctx *c) {
             if (d.m <= JL_MAXM) {
                 hipLaunchKernelGGL(k_jacobi_lds, dim3(d.nt), dim3(JAC_THREADS), 0, c->stream, d);
                 LAUNCHCHECK(c, "k_jacobi_lds");
+                hipLaunchKernelGGL(k_jacobi_apply_v, dim3((d.m + JV_COLS - 1) / JV_COLS, d.nt), dim3(JAC_THREADS), 0,
+                                   c->stream, d);
+                LAUNCHCHECK(c, "k_jacobi_apply_v");
             } else {
                 hipLaunchKernelGGL(k_jacobi, dim3(d.nt), dim3(JAC_THREADS), 0, c->stream, d);
                 LAUNCHCHECK(c, "k_jacobi");
@@ -885,6 +892,8 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.snrW = (double2 *)(base + L.snrW);
     d.snrEig = (double *)(base + L.snrEig);
     d.snrPart = (double *)(base + L.snrPart);
+    d.snrRot = (double2 *)(base + L.snrRot);
+    d.snrSweeps = (int *)(base + L.snrSweeps);
     d.ar = c->proposal;
     d.ah = c->proposal ? c->ar_hidden : 0;
     d.arnp = c->proposal ? ar_params(n, c->ar_hidden) : 0;
