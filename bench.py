@@ -223,8 +223,8 @@ def main():
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (trajectories shard across GPUs by design, "
-              "but no multi-GPU path is built); use --gpus 1", file=sys.stderr)
+        print("bench.py: one GPU only (trajectories shard across GPUs by design, but there is no "
+              "multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

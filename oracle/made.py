@@ -3,8 +3,7 @@
 Plain float64 numpy reference for the learned proposal: a two-layer masked autoregressive
 network (MADE: Germain, Gregor, Murray, Larochelle, ICML 2015) over spin configurations,
 q(s) = prod_i q(s_i | s_<i), used as an independent Metropolis-Hastings proposal for |psi|^2.
-The paper has no learned proposal; this component, its degrees and masks are this build's own
-definition:
+The paper has no learned proposal; this component, its degrees and masks are defined here:
   inputs s_j = +-1; hidden unit k has degree d(k) = 1 + (k mod (N-1)) and sees inputs j < d(k);
   output i sees hidden units with d(k) <= i (output 0 sees none: a bias only);
   a_k = b1_k + sum_{j < d(k)} W1[k, j] s_j,  h = relu(a),
