@@ -1026,6 +1026,7 @@ static tvmc_status graph_step(tvmc_ctx *c) {
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, c->stream, c->d, c->step);
     LAUNCHCHECK(c, "k_set_step");
     if (!c->gexec) {
+        const int step0 = c->step, stage0 = c->stage, phase0 = c->phase;
         HIPCHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         c->capturing = true;
         tvmc_status st = TVMC_OK;
@@ -1038,14 +1039,28 @@ static tvmc_status graph_step(tvmc_ctx *c) {
         c->capturing = false;
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(c->stream, &g);
-        if (st != TVMC_OK || e != hipSuccess) {
+        if (st != TVMC_OK || e != hipSuccess) {   // nothing ran: back to the step boundary
             if (g) (void)hipGraphDestroy(g);
+            c->step = step0;
+            c->stage = stage0;
+            c->phase = phase0;
             if (st == TVMC_OK) set_err(c, "step capture failed: %s", hipGetErrorString(e));
             return st != TVMC_OK ? st : TVMC_E_DEVICE;
         }
         c->graph = g;
-        HIPCHECK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
-        HIPCHECK(c, hipGraphLaunch(c->gexec, c->stream));
+        hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        if (ie == hipSuccess) ie = hipGraphLaunch(c->gexec, c->stream);
+        if (ie != hipSuccess) {
+            if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+            (void)hipGraphDestroy(g);
+            c->gexec = nullptr;
+            c->graph = nullptr;
+            c->step = step0;
+            c->stage = stage0;
+            c->phase = phase0;
+            set_err(c, "step graph instantiate / launch failed: %s", hipGetErrorString(ie));
+            return TVMC_E_DEVICE;
+        }
         return TVMC_OK;
     }
     HIPCHECK(c, hipGraphLaunch(c->gexec, c->stream));
