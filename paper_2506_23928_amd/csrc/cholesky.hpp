@@ -1,10 +1,10 @@
 // Regularised solve (S + eps I) delta = D in FP64 (the solve of the paragraph after Eq. 9).
 //
-// One workgroup (4 waves) per trajectory factors its own matrix, left-looking, in panels of
+// One workgroup (8 waves) per trajectory factors its own matrix, left-looking, in panels of
 // CN = 64 columns, on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
 //   for each panel j and each chunk of CR = 128 rows at or below it:
-//     C = A[rows, panel] - L[rows, 0:j] L[panel, 0:j]^T       (MFMA, operands staged in LDS
-//                                                              with the next chunk prefetched)
+//     C = A[rows, panel] - L[rows, 0:j] L[panel, 0:j]^T       (MFMA, k-slices of the operands
+//                                                              double-buffered through LDS)
 //     first chunk: factor the 64x64 diagonal block in LDS and invert it (Linv);
 //     rows below:  L[rows, panel] = C Linv^T                  (MFMA)
 // The forward substitution L y = D rides along panel by panel; the backward substitution
@@ -19,10 +19,13 @@ namespace tvmc {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int CN = 64;        // panel width
-constexpr int CR = 128;       // rows per chunk (4 waves x 32 rows)
+constexpr int CR = 128;       // rows per chunk (8 waves x 16 rows)
 constexpr int CK = 32;        // k-slice staged through LDS
 constexpr int CSP = CN + 1;   // padded LDS row of Cs / Ls
 constexpr int CKP = CK + 1;   // padded LDS row of As / Bs
+constexpr int CKBUF = (CR + CN) * CKP;   // one k-slice staging buffer: As [CR][CKP] then Bs [CN][CKP]
+constexpr int CT1 = 512;      // threads of the one-workgroup solver: 8 waves, 16 rows of a chunk each
+static_assert(CN % (2 * CK) == 0, "the update loop takes k-slices in pairs");
 
 __host__ __device__ inline int chol_panels(int m) { return (m + CN - 1) / CN; }
 
@@ -38,12 +41,12 @@ struct CholArgs {
     int m;
 };
 
-__global__ __launch_bounds__(256) void k_chol_solve(CholArgs a) {
-    __shared__ double Cs[CR * CSP];
+__global__ __launch_bounds__(CT1) void k_chol_solve(CholArgs a) {
+    // the two k-slice staging buffers (As | Bs) and the chunk tile Cs are never live at once
+    __shared__ double smem[2 * CKBUF > CR * CSP ? 2 * CKBUF : CR * CSP];
     __shared__ double Ls[CN * CSP];
-    __shared__ double As[CR * CKP];
-    __shared__ double Bs[CN * CKP];
     __shared__ double yre[CN], yim[CN];
+    double *Cs = smem;
     __shared__ int bad;
     const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(256) void k_chol_solve(CholArgs a) {
     double2 *z = a.x + (size_t)t * M;
     const double2 *Dv = a.rhs + (size_t)t * M;
     if (tid == 0) bad = 0;
-    for (int i = tid; i < M; i += 256) z[i] = Dv[i];
+    for (int i = tid; i < M; i += CT1) z[i] = Dv[i];
     __syncthreads();
 
     for (int j0 = 0, p = 0; j0 < M; j0 += CN, ++p) {
@@ -62,63 +65,78 @@ __global__ __launch_bounds__(256) void k_chol_solve(CholArgs a) {
             // ---- C = A - L[rows, 0:j0] L[panel, 0:j0]^T: the accumulators start from A (FP64
             // accumulator layout: register r of lane (lk, li) holds row lk + 4r, column li) and
             // the row operand is staged negated
-            v4d acc[2][4];
-            for (int u = 0; u < 2; ++u)
-                for (int v = 0; v < 4; ++v)
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
-                        acc[u][v][r] = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : 0.0;
-                    }
+            v4d acc[4];
+            for (int v = 0; v < 4; ++v)
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
+                    acc[v][r] = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : 0.0;
+                }
             if (j0 > 0) {
-                double pa[CR * CK / 256], pb[CN * CK / 256];
-                auto fetch = [&](int kc) {
-                    for (int q = 0; q < CR * CK / 256; ++q) {
-                        const int e = tid + 256 * q, rr = e / CK, kk = e % CK;
-                        pa[q] = (r0 + rr < M) ? A[(size_t)(r0 + rr) * M + kc + kk] : 0.0;
+                // one k-slice in registers: CR*CK/CT1 doubles of the chunk rows, CN*CK/CT1 of
+                // the panel rows
+                constexpr int QA = CR * CK / CT1, QB = CN * CK / CT1;
+                double ra[QA + QB], rb[QA + QB];
+                auto fetch = [&](double (&p)[QA + QB], int kc) {
+                    for (int q = 0; q < QA; ++q) {
+                        const int e = tid + CT1 * q, rr = e / CK, kk = e % CK;
+                        p[q] = (r0 + rr < M) ? A[(size_t)(r0 + rr) * M + kc + kk] : 0.0;
                     }
-                    for (int q = 0; q < CN * CK / 256; ++q) {
-                        const int e = tid + 256 * q, cc = e / CK, kk = e % CK;
-                        pb[q] = (cc < jb) ? A[(size_t)(j0 + cc) * M + kc + kk] : 0.0;
+                    for (int q = 0; q < QB; ++q) {
+                        const int e = tid + CT1 * q, cc = e / CK, kk = e % CK;
+                        p[QA + q] = (cc < jb) ? A[(size_t)(j0 + cc) * M + kc + kk] : 0.0;
                     }
                 };
-                fetch(0);
-                for (int kc = 0; kc < j0; kc += CK) {
-                    __syncthreads();
-                    for (int q = 0; q < CR * CK / 256; ++q) {
-                        const int e = tid + 256 * q;
-                        As[(e / CK) * CKP + e % CK] = -pa[q];
+                auto stash = [&](const double (&p)[QA + QB], int buf) {
+                    double *As = smem + buf * CKBUF, *Bs = As + CR * CKP;
+                    for (int q = 0; q < QA; ++q) {
+                        const int e = tid + CT1 * q;
+                        As[(e / CK) * CKP + e % CK] = -p[q];
                     }
-                    for (int q = 0; q < CN * CK / 256; ++q) {
-                        const int e = tid + 256 * q;
-                        Bs[(e / CK) * CKP + e % CK] = pb[q];
+                    for (int q = 0; q < QB; ++q) {
+                        const int e = tid + CT1 * q;
+                        Bs[(e / CK) * CKP + e % CK] = p[QA + q];
                     }
-                    __syncthreads();
-                    if (kc + CK < j0) fetch(kc + CK);
+                };
+                // Slice kc sits in LDS buffer buf and slice kc+CK in `cur` (in flight); slice
+                // kc+2CK is fetched into `nxt` before the MFMAs of slice kc, and `cur` is staged
+                // after them into the other buffer, whose last readers passed the previous
+                // barrier.  Two slices of global loads stay in flight behind the matrix cores.
+                auto step = [&](double (&cur)[QA + QB], double (&nxt)[QA + QB], int kc, int buf) {
+                    if (kc + 2 * CK < j0) fetch(nxt, kc + 2 * CK);
+                    const double *As = smem + buf * CKBUF, *Bs = As + CR * CKP;
                     for (int ks = 0; ks < CK / 4; ++ks) {
-                        double fa[2], fb[4];
-                        for (int u = 0; u < 2; ++u) fa[u] = As[(wave * 32 + u * 16 + li) * CKP + ks * 4 + lk];
+                        double fb[4];
+                        const double fa = As[(wave * 16 + li) * CKP + ks * 4 + lk];
                         for (int v = 0; v < 4; ++v) fb[v] = Bs[(v * 16 + li) * CKP + ks * 4 + lk];
-                        for (int u = 0; u < 2; ++u)
-                            for (int v = 0; v < 4; ++v)
-                                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[v], acc[u][v], 0, 0, 0);
+                        for (int v = 0; v < 4; ++v)
+                            acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb[v], acc[v], 0, 0, 0);
                     }
+                    if (kc + CK < j0) stash(cur, buf ^ 1);
+                    __syncthreads();
+                };
+                fetch(ra, 0);
+                stash(ra, 0);
+                fetch(ra, CK);          // j0 is a multiple of CN = 2 CK: the slice count is even
+                __syncthreads();
+                for (int kc = 0; kc < j0; kc += 2 * CK) {
+                    step(ra, rb, kc, 0);
+                    step(rb, ra, kc + CK, 1);
                 }
             }
             __syncthreads();
-            for (int u = 0; u < 2; ++u)
-                for (int v = 0; v < 4; ++v)
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
-                        Cs[row * CSP + col] = acc[u][v][r];
-                    }
+            for (int v = 0; v < 4; ++v)
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
+                    Cs[row * CSP + col] = acc[v][r];
+                }
             __syncthreads();
             int rstart = 0;
             if (r0 == j0) {
                 // ---- factor the diagonal block in LDS, right-looking; thread (row fr, phase fs)
-                // updates columns fs, fs+4, ... of its row.  Column c is read unscaled during
+                // updates columns c+1+fs, c+9+fs, ... of its row.  Column c is read unscaled during
                 // step c and scaled after the barrier, so one barrier per column suffices.
                 {
-                    const int fr = tid >> 2, fs = tid & 3;
+                    const int fr = tid >> 3, fs = tid & 7;
                     for (int c = 0; c < jb; ++c) {
                         const double piv = Cs[c * CSP + c];
                         if (tid == 0 && !(piv > 0.0)) bad = 1;
@@ -126,7 +144,7 @@ __global__ __launch_bounds__(256) void k_chol_solve(CholArgs a) {
                         double lrc = 0.0;
                         if (fr > c && fr < jb) {
                             lrc = Cs[fr * CSP + c] * inv;
-                            for (int k = c + 1 + fs; k <= fr; k += 4) Cs[fr * CSP + k] -= lrc * (Cs[k * CSP + c] * inv);
+                            for (int k = c + 1 + fs; k <= fr; k += 8) Cs[fr * CSP + k] -= lrc * (Cs[k * CSP + c] * inv);
                         }
                         __syncthreads();
                         if (fs == 0 && fr > c && fr < jb) Cs[fr * CSP + c] = lrc;
@@ -134,23 +152,24 @@ __global__ __launch_bounds__(256) void k_chol_solve(CholArgs a) {
                     }
                     __syncthreads();
                 }
-                for (int e = tid; e < jb * jb; e += 256) {
+                for (int e = tid; e < jb * jb; e += CT1) {
                     const int r = e / jb, c = e % jb;
                     if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
                 }
                 // ---- Linv, the inverse of the lower-triangular block by forward substitution:
-                // wave w owns columns 16w..16w+15, four lanes per column share each row's sum
+                // wave w owns columns 8w..8w+7, eight lanes per column share each row's sum
                 // (rows of one column are written and read back by the same wave, in order)
                 {
-                    const int c = wave * 16 + (lane >> 2), fs = lane & 3;
-                    for (int r = fs; r < CN; r += 4) Ls[r * CSP + c] = 0.0;
+                    const int c = wave * 8 + (lane >> 3), fs = lane & 7;
+                    for (int r = fs; r < CN; r += 8) Ls[r * CSP + c] = 0.0;
                     if (c < jb) {
                         if (fs == 0) Ls[c * CSP + c] = 1.0 / Cs[c * CSP + c];
                         for (int r = c + 1; r < jb; ++r) {
                             double sum = 0.0;
-                            for (int k = c + fs; k < r; k += 4) sum += Cs[r * CSP + k] * Ls[k * CSP + c];
+                            for (int k = c + fs; k < r; k += 8) sum += Cs[r * CSP + k] * Ls[k * CSP + c];
                             sum += __shfl_xor(sum, 1, 64);
                             sum += __shfl_xor(sum, 2, 64);
+                            sum += __shfl_xor(sum, 4, 64);
                             if (fs == 0) Ls[r * CSP + c] = -sum / Cs[r * CSP + r];
                         }
                     }
@@ -171,36 +190,33 @@ __global__ __launch_bounds__(256) void k_chol_solve(CholArgs a) {
                     yre[tid] = 0.0;
                     yim[tid] = 0.0;
                 }
-                for (int e = tid; e < CN * CN; e += 256) linv[(size_t)p * CN * CN + e] = Ls[(e / CN) * CSP + e % CN];
+                for (int e = tid; e < CN * CN; e += CT1) linv[(size_t)p * CN * CN + e] = Ls[(e / CN) * CSP + e % CN];
                 __syncthreads();
                 if (tid < jb) z[j0 + tid] = make_double2(yre[tid], yim[tid]);
                 rstart = CN;
             }
             // ---- rows below the diagonal block: X = C Linv^T (B[k][j] = Linv[j][k])
-            v4d x[2][4];
-            for (int u = 0; u < 2; ++u)
-                for (int v = 0; v < 4; ++v) x[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
+            v4d x[4];
+            for (int v = 0; v < 4; ++v) x[v] = (v4d){0.0, 0.0, 0.0, 0.0};
             for (int ks = 0; ks < CN / 4; ++ks) {
-                double fa[2], fb[4];
-                for (int u = 0; u < 2; ++u) fa[u] = Cs[(wave * 32 + u * 16 + li) * CSP + ks * 4 + lk];
+                double fb[4];
+                const double fa = Cs[(wave * 16 + li) * CSP + ks * 4 + lk];
                 for (int v = 0; v < 4; ++v) fb[v] = Ls[(v * 16 + li) * CSP + ks * 4 + lk];
-                for (int u = 0; u < 2; ++u)
-                    for (int v = 0; v < 4; ++v) x[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[v], x[u][v], 0, 0, 0);
+                for (int v = 0; v < 4; ++v) x[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb[v], x[v], 0, 0, 0);
             }
             __syncthreads();
-            for (int u = 0; u < 2; ++u)
-                for (int v = 0; v < 4; ++v)
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
-                        if (row >= rstart) Cs[row * CSP + col] = x[u][v][r];
-                    }
+            for (int v = 0; v < 4; ++v)
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
+                    if (row >= rstart) Cs[row * CSP + col] = x[v][r];
+                }
             __syncthreads();
             const int nrows = (M - r0) < CR ? (M - r0) : CR;
-            for (int e = tid; e < (nrows - rstart) * jb; e += 256) {
+            for (int e = tid; e < (nrows - rstart) * jb; e += CT1) {
                 const int rr = rstart + e / jb, c = e % jb;
                 A[(size_t)(r0 + rr) * M + j0 + c] = Cs[rr * CSP + c];
             }
-            for (int rr = rstart + tid; rr < nrows; rr += 256) {
+            for (int rr = rstart + tid; rr < nrows; rr += CT1) {
                 double2 zr = z[r0 + rr];
                 for (int c = 0; c < jb; ++c) {
                     const double xv = Cs[rr * CSP + c];
@@ -213,24 +229,24 @@ __global__ __launch_bounds__(256) void k_chol_solve(CholArgs a) {
         }
     }
 
-    // ---- backward substitution L^T x = y, last panel first; wave w owns 16 panel columns
+    // ---- backward substitution L^T x = y, last panel first; wave w owns 8 panel columns
     for (int p = chol_panels(M) - 1; p >= 0; --p) {
         const int j0 = p * CN, jb = (M - j0) < CN ? (M - j0) : CN;
-        double sr[16], si[16];
-        for (int q = 0; q < 16; ++q) sr[q] = si[q] = 0.0;
+        double sr[8], si[8];
+        for (int q = 0; q < 8; ++q) sr[q] = si[q] = 0.0;
         for (int r = j0 + jb + lane; r < M; r += 64) {
             const double2 xr = z[r];
-            const double *row = A + (size_t)r * M + j0 + wave * 16;
-            for (int q = 0; q < 16; ++q) {
-                const double l = (wave * 16 + q < jb) ? row[q] : 0.0;
+            const double *row = A + (size_t)r * M + j0 + wave * 8;
+            for (int q = 0; q < 8; ++q) {
+                const double l = (wave * 8 + q < jb) ? row[q] : 0.0;
                 sr[q] += l * xr.x;
                 si[q] += l * xr.y;
             }
         }
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < 8; ++q) {
             const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
             if (lane == 0) {
-                const int c = wave * 16 + q;
+                const int c = wave * 8 + q;
                 yre[c] = c < jb ? z[j0 + c].x - tr : 0.0;
                 yim[c] = c < jb ? z[j0 + c].y - ti : 0.0;
             }

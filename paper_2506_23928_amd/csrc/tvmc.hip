@@ -599,7 +599,7 @@ tvmc_status launch_chol(tvmc_ctx *c, const CholArgs &ca) {
     const bool multi = c->cfg.solver == TVMC_SOLVER_MULTI_GROUP ||
                        (c->cfg.solver != TVMC_SOLVER_ONE_GROUP && T < 192);
     if (!multi) {
-        hipLaunchKernelGGL(k_chol_solve, dim3(T), dim3(256), 0, c->stream, ca);
+        hipLaunchKernelGGL(k_chol_solve, dim3(T), dim3(CT1), 0, c->stream, ca);
         LAUNCHCHECK(c, "k_chol_solve");
         return TVMC_OK;
     }
