@@ -29,10 +29,11 @@ __global__ __launch_bounds__(256) void k_zmw_init(ZCholArgs a) {
 
 constexpr int ZK = 16;          // k-slice staged through LDS
 constexpr int ZKP = ZK + 1;
+constexpr int ZT = 512;         // threads of k_zmw_update: 8 waves, 16 rows of the 128-row chunk each
+constexpr int ZBUF = 2 * (CR + CN) * ZKP;   // one staging buffer: Ar, Ai [CR][ZKP], Br, Bi [CN][ZKP]
 
-__global__ __launch_bounds__(256) void k_zmw_update(ZCholArgs a, int j0) {
-    __shared__ double Ar[CR * ZKP], Ai[CR * ZKP];
-    __shared__ double Br[CN * ZKP], Bi[CN * ZKP];
+__global__ __launch_bounds__(ZT) void k_zmw_update(ZCholArgs a, int j0) {
+    __shared__ double stage[2 * ZBUF];
     const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int M = a.m;
@@ -40,67 +41,73 @@ __global__ __launch_bounds__(256) void k_zmw_update(ZCholArgs a, int j0) {
     if (r0 >= M) return;
     const int jb = (M - j0) < CN ? (M - j0) : CN;
     double2 *A = a.A + (size_t)t * M * M;
-    v4d cre[2][4], cim[2][4];
-    for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 4; ++v)
-            for (int r = 0; r < 4; ++r) {
-                const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
-                const double2 c = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : make_double2(0.0, 0.0);
-                cre[u][v][r] = c.x;
-                cim[u][v][r] = c.y;
+    v4d cre[4], cim[4];
+    for (int v = 0; v < 4; ++v)
+        for (int r = 0; r < 4; ++r) {
+            const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
+            const double2 c = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : make_double2(0.0, 0.0);
+            cre[v][r] = c.x;
+            cim[v][r] = c.y;
+        }
+    if (j0 > 0) {
+        double2 pa[CR * ZK / ZT], pb[CN * ZK / ZT];
+        auto fetch = [&](int kc) {
+            for (int q = 0; q < CR * ZK / ZT; ++q) {
+                const int e = tid + ZT * q, rr = e / ZK, kk = e % ZK;
+                pa[q] = (r0 + rr < M) ? A[(size_t)(r0 + rr) * M + kc + kk] : make_double2(0.0, 0.0);
             }
-    double2 pa[CR * ZK / 256], pb[CN * ZK / 256];
-    auto fetch = [&](int kc) {
-        for (int q = 0; q < CR * ZK / 256; ++q) {
-            const int e = tid + 256 * q, rr = e / ZK, kk = e % ZK;
-            pa[q] = (r0 + rr < M) ? A[(size_t)(r0 + rr) * M + kc + kk] : make_double2(0.0, 0.0);
-        }
-        for (int q = 0; q < CN * ZK / 256; ++q) {
-            const int e = tid + 256 * q, cc = e / ZK, kk = e % ZK;
-            pb[q] = (cc < jb) ? A[(size_t)(j0 + cc) * M + kc + kk] : make_double2(0.0, 0.0);
-        }
-    };
-    fetch(0);
-    for (int kc = 0; kc < j0; kc += ZK) {
+            for (int q = 0; q < CN * ZK / ZT; ++q) {
+                const int e = tid + ZT * q, cc = e / ZK, kk = e % ZK;
+                pb[q] = (cc < jb) ? A[(size_t)(j0 + cc) * M + kc + kk] : make_double2(0.0, 0.0);
+            }
+        };
+        auto stash = [&](int buf) {
+            double *Ar = stage + buf * ZBUF, *Ai = Ar + CR * ZKP, *Br = Ai + CR * ZKP, *Bi = Br + CN * ZKP;
+            for (int q = 0; q < CR * ZK / ZT; ++q) {
+                const int e = tid + ZT * q;
+                Ar[(e / ZK) * ZKP + e % ZK] = -pa[q].x;
+                Ai[(e / ZK) * ZKP + e % ZK] = -pa[q].y;
+            }
+            for (int q = 0; q < CN * ZK / ZT; ++q) {
+                const int e = tid + ZT * q;
+                Br[(e / ZK) * ZKP + e % ZK] = pb[q].x;
+                Bi[(e / ZK) * ZKP + e % ZK] = pb[q].y;
+            }
+        };
+        // double-buffered: slice k+1 is fetched before and staged after the products of slice
+        // k, into the buffer whose last readers passed the previous barrier
+        fetch(0);
+        stash(0);
         __syncthreads();
-        for (int q = 0; q < CR * ZK / 256; ++q) {
-            const int e = tid + 256 * q;
-            Ar[(e / ZK) * ZKP + e % ZK] = -pa[q].x;
-            Ai[(e / ZK) * ZKP + e % ZK] = -pa[q].y;
-        }
-        for (int q = 0; q < CN * ZK / 256; ++q) {
-            const int e = tid + 256 * q;
-            Br[(e / ZK) * ZKP + e % ZK] = pb[q].x;
-            Bi[(e / ZK) * ZKP + e % ZK] = pb[q].y;
-        }
-        __syncthreads();
-        if (kc + ZK < j0) fetch(kc + ZK);
-        for (int ks = 0; ks < ZK / 4; ++ks) {
-            double far_[2], fai[2], fbr[4], fbi[4];
-            for (int u = 0; u < 2; ++u) {
-                far_[u] = Ar[(wave * 32 + u * 16 + li) * ZKP + ks * 4 + lk];   // -Lr (rows)
-                fai[u] = Ai[(wave * 32 + u * 16 + li) * ZKP + ks * 4 + lk];    // -Li (rows)
-            }
-            for (int v = 0; v < 4; ++v) {
-                fbr[v] = Br[(v * 16 + li) * ZKP + ks * 4 + lk];                // Lr' (panel rows)
-                fbi[v] = Bi[(v * 16 + li) * ZKP + ks * 4 + lk];                // Li'
-            }
-            for (int u = 0; u < 2; ++u)
+        for (int kc = 0, buf = 0; kc < j0; kc += ZK, buf ^= 1) {
+            const bool more = kc + ZK < j0;
+            if (more) fetch(kc + ZK);
+            const double *Ar = stage + buf * ZBUF, *Ai = Ar + CR * ZKP, *Br = Ai + CR * ZKP, *Bi = Br + CN * ZKP;
+            for (int ks = 0; ks < ZK / 4; ++ks) {
+                double fbr[4], fbi[4];
+                const double far_ = Ar[(wave * 16 + li) * ZKP + ks * 4 + lk];   // -Lr (rows)
+                const double fai = Ai[(wave * 16 + li) * ZKP + ks * 4 + lk];    // -Li (rows)
                 for (int v = 0; v < 4; ++v) {
-                    cre[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(far_[u], fbr[v], cre[u][v], 0, 0, 0);
-                    cre[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fai[u], fbi[v], cre[u][v], 0, 0, 0);
-                    cim[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fai[u], fbr[v], cim[u][v], 0, 0, 0);
-                    cim[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(far_[u], -fbi[v], cim[u][v], 0, 0, 0);
+                    fbr[v] = Br[(v * 16 + li) * ZKP + ks * 4 + lk];                // Lr' (panel rows)
+                    fbi[v] = Bi[(v * 16 + li) * ZKP + ks * 4 + lk];                // Li'
                 }
+                for (int v = 0; v < 4; ++v) {
+                    cre[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(far_, fbr[v], cre[v], 0, 0, 0);
+                    cre[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fai, fbi[v], cre[v], 0, 0, 0);
+                    cim[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fai, fbr[v], cim[v], 0, 0, 0);
+                    cim[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(far_, -fbi[v], cim[v], 0, 0, 0);
+                }
+            }
+            if (more) stash(buf ^ 1);
+            __syncthreads();
         }
     }
-    for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 4; ++v)
-            for (int r = 0; r < 4; ++r) {
-                const int row = wave * 32 + u * 16 + lk + 4 * r, col = v * 16 + li;
-                if (r0 + row < M && col < jb)
-                    A[(size_t)(r0 + row) * M + j0 + col] = make_double2(cre[u][v][r], cim[u][v][r]);
-            }
+    for (int v = 0; v < 4; ++v)
+        for (int r = 0; r < 4; ++r) {
+            const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
+            if (r0 + row < M && col < jb)
+                A[(size_t)(r0 + row) * M + j0 + col] = make_double2(cre[v][r], cim[v][r]);
+        }
 }
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
@@ -110,7 +117,11 @@ __device__ __forceinline__ double2 zmulc(double2 a, double2 b) {   // a conj(b)
     return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
-__global__ __launch_bounds__(256) void k_zmw_diag(ZCholArgs a, int j0, int p) {
+// One workgroup of ZD threads per trajectory: 16 lanes per row of the block while factoring,
+// 16 lanes per column of the inverse.
+constexpr int ZD = 1024;
+
+__global__ __launch_bounds__(ZD) void k_zmw_diag(ZCholArgs a, int j0, int p) {
     __shared__ double2 Cs[CN * CSP];
     __shared__ double2 Ls[CN * CSP];
     __shared__ double2 ys[CN];
@@ -121,14 +132,16 @@ __global__ __launch_bounds__(256) void k_zmw_diag(ZCholArgs a, int j0, int p) {
     double2 *A = a.A + (size_t)t * M * M;
     double2 *z = a.x + (size_t)t * M;
     if (tid == 0) bad = 0;
-    for (int e = tid; e < CN * CN; e += 256) {
+    for (int e = tid; e < CN * CN; e += ZD) {
         const int r = e / CN, c = e % CN;
         Cs[r * CSP + c] = (r < jb && c <= r) ? A[(size_t)(j0 + r) * M + j0 + c] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    // right-looking factor in LDS: thread (row fr, phase fs); column c read unscaled in step c
+    // right-looking factor in LDS: thread (row fr, phase fs) updates columns c+1+fs, c+17+fs, ...
+    // of its row; column c is read unscaled in step c and scaled after the barrier.  Each
+    // thread loads its (at most 4) operand pairs before it stores any of them.
     {
-        const int fr = tid >> 2, fs = tid & 3;
+        const int fr = tid >> 4, fs = tid & 15;
         for (int c = 0; c < jb; ++c) {
             const double piv = Cs[c * CSP + c].x;
             if (tid == 0 && !(piv > 0.0)) bad = 1;
@@ -137,12 +150,20 @@ __global__ __launch_bounds__(256) void k_zmw_diag(ZCholArgs a, int j0, int p) {
             if (fr > c && fr < jb) {
                 const double2 crc = Cs[fr * CSP + c];
                 lrc = make_double2(crc.x * inv, crc.y * inv);
-                for (int k = c + 1 + fs; k <= fr; k += 4) {   // C_rk -= L_rc conj(L_kc)
-                    const double2 ckc = Cs[k * CSP + c];
-                    const double2 lkc = make_double2(ckc.x * inv, ckc.y * inv);
-                    const double2 pr = zmulc(lrc, lkc);
-                    Cs[fr * CSP + k].x -= pr.x;
-                    Cs[fr * CSP + k].y -= pr.y;
+                double2 ck[CN / 16], cr[CN / 16];
+                for (int q = 0; q < CN / 16; ++q) {
+                    const int k = c + 1 + fs + 16 * q;
+                    if (k <= fr) {
+                        ck[q] = Cs[k * CSP + c];
+                        cr[q] = Cs[fr * CSP + k];
+                    }
+                }
+                for (int q = 0; q < CN / 16; ++q) {   // C_rk -= L_rc conj(L_kc)
+                    const int k = c + 1 + fs + 16 * q;
+                    if (k <= fr) {
+                        const double2 pr = zmulc(lrc, make_double2(ck[q].x * inv, ck[q].y * inv));
+                        Cs[fr * CSP + k] = make_double2(cr[q].x - pr.x, cr[q].y - pr.y);
+                    }
                 }
             }
             __syncthreads();
@@ -151,27 +172,28 @@ __global__ __launch_bounds__(256) void k_zmw_diag(ZCholArgs a, int j0, int p) {
         }
         __syncthreads();
     }
-    for (int e = tid; e < jb * jb; e += 256) {
+    for (int e = tid; e < jb * jb; e += ZD) {
         const int r = e / jb, c = e % jb;
         if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
     }
-    // Linv: Linv_cc = 1 / L_cc, Linv_rc = -(sum_{c <= k < r} L_rk Linv_kc) / L_rr
+    // Linv: Linv_cc = 1 / L_cc, Linv_rc = -(sum_{c <= k < r} L_rk Linv_kc) / L_rr; wave w owns
+    // columns 4w..4w+3 (rows of one column are written and read back by the same wave, in order)
     {
-        const int c = wave * 16 + (lane >> 2), fs = lane & 3;
-        for (int r = fs; r < CN; r += 4) Ls[r * CSP + c] = make_double2(0.0, 0.0);
+        const int c = wave * 4 + (lane >> 4), fs = lane & 15;
+        for (int r = fs; r < CN; r += 16) Ls[r * CSP + c] = make_double2(0.0, 0.0);
         if (c < jb) {
             if (fs == 0) Ls[c * CSP + c] = make_double2(1.0 / Cs[c * CSP + c].x, 0.0);
             for (int r = c + 1; r < jb; ++r) {
                 double sr = 0.0, si = 0.0;
-                for (int k = c + fs; k < r; k += 4) {
+                for (int k = c + fs; k < r; k += 16) {
                     const double2 pr = zmul(Cs[r * CSP + k], Ls[k * CSP + c]);
                     sr += pr.x;
                     si += pr.y;
                 }
-                sr += __shfl_xor(sr, 1, 64);
-                sr += __shfl_xor(sr, 2, 64);
-                si += __shfl_xor(si, 1, 64);
-                si += __shfl_xor(si, 2, 64);
+                for (int o = 1; o < 16; o <<= 1) {
+                    sr += __shfl_xor(sr, o, 64);
+                    si += __shfl_xor(si, o, 64);
+                }
                 const double lrr = Cs[r * CSP + r].x;
                 if (fs == 0) Ls[r * CSP + c] = make_double2(-sr / lrr, -si / lrr);
             }
@@ -188,14 +210,17 @@ __global__ __launch_bounds__(256) void k_zmw_diag(ZCholArgs a, int j0, int p) {
         ys[tid] = make_double2(sr, si);
     }
     double2 *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
-    for (int e = tid; e < CN * CN; e += 256) lv[e] = Ls[(e / CN) * CSP + e % CN];
+    for (int e = tid; e < CN * CN; e += ZD) lv[e] = Ls[(e / CN) * CSP + e % CN];
     __syncthreads();
     if (tid < jb) z[j0 + tid] = ys[tid];
     if (tid == 0 && bad) a.flags[t] = 1;
 }
 
-// X = C Linv^H: X_ij = sum_k C_ik conj(Linv_jk); B[k][j] = Linv_jk
-__global__ __launch_bounds__(256) void k_zmw_trsm(ZCholArgs a, int j0, int p) {
+// X = C Linv^H: X_ij = sum_k C_ik conj(Linv_jk); B[k][j] = Linv_jk.  8 waves, 16 rows of the
+// 128-row chunk each; a lane loads all 16 of its C fragments before the products.
+constexpr int ZTT = 512;
+
+__global__ __launch_bounds__(ZTT) void k_zmw_trsm(ZCholArgs a, int j0, int p) {
     __shared__ double Lr[CN * CSP], Li[CN * CSP];
     __shared__ double yr[CN], yi[CN];
     const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -207,7 +232,15 @@ __global__ __launch_bounds__(256) void k_zmw_trsm(ZCholArgs a, int j0, int p) {
     double2 *A = a.A + (size_t)t * M * M;
     double2 *z = a.x + (size_t)t * M;
     const double2 *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
-    for (int e = tid; e < CN * CN; e += 256) {
+    double2 cf[CN / 4];   // C[row r0 + 16 wave + li][4 ks + lk]
+    {
+        const int row = r0 + wave * 16 + li;
+        for (int ks = 0; ks < CN / 4; ++ks) {
+            const int col = ks * 4 + lk;
+            cf[ks] = (row < M && col < jb) ? A[(size_t)row * M + j0 + col] : make_double2(0.0, 0.0);
+        }
+    }
+    for (int e = tid; e < CN * CN; e += ZTT) {
         const double2 l = lv[e];
         Lr[(e / CN) * CSP + e % CN] = l.x;
         Li[(e / CN) * CSP + e % CN] = l.y;
@@ -218,53 +251,45 @@ __global__ __launch_bounds__(256) void k_zmw_trsm(ZCholArgs a, int j0, int p) {
         yi[tid] = y.y;
     }
     __syncthreads();
-    v4d xr[2][4], xi[2][4];
-    for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 4; ++v) {
-            xr[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
-            xi[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
-        }
+    v4d xr[4], xi[4];
+    for (int v = 0; v < 4; ++v) {
+        xr[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+        xi[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+    }
     for (int ks = 0; ks < CN / 4; ++ks) {
-        double fcr[2], fci[2], fbr[4], fbi[4];
-        for (int u = 0; u < 2; ++u) {
-            const int row = r0 + wave * 32 + u * 16 + li, col = ks * 4 + lk;
-            const double2 c = (row < M && col < jb) ? A[(size_t)row * M + j0 + col] : make_double2(0.0, 0.0);
-            fcr[u] = c.x;
-            fci[u] = c.y;
-        }
+        double fbr[4], fbi[4];
         for (int v = 0; v < 4; ++v) {
             fbr[v] = Lr[(v * 16 + li) * CSP + ks * 4 + lk];
             fbi[v] = Li[(v * 16 + li) * CSP + ks * 4 + lk];
         }
-        for (int u = 0; u < 2; ++u)
-            for (int v = 0; v < 4; ++v) {
-                xr[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr[u], fbr[v], xr[u][v], 0, 0, 0);
-                xr[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci[u], fbi[v], xr[u][v], 0, 0, 0);
-                xi[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci[u], fbr[v], xi[u][v], 0, 0, 0);
-                xi[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr[u], -fbi[v], xi[u][v], 0, 0, 0);
-            }
-    }
-    __syncthreads();
-    for (int u = 0; u < 2; ++u)
-        for (int r = 0; r < 4; ++r) {
-            const int row = r0 + wave * 32 + u * 16 + lk + 4 * r;
-            double sr = 0.0, si = 0.0;
-            for (int v = 0; v < 4; ++v) {
-                const int col = v * 16 + li;
-                const double a_ = xr[u][v][r], b_ = xi[u][v][r];
-                if (row < M && col < jb) A[(size_t)row * M + j0 + col] = make_double2(a_, b_);
-                sr += a_ * yr[col] - b_ * yi[col];
-                si += a_ * yi[col] + b_ * yr[col];
-            }
-            for (int o = 1; o < 16; o <<= 1) {
-                sr += __shfl_xor(sr, o, 64);
-                si += __shfl_xor(si, o, 64);
-            }
-            if (li == 0 && row < M) {
-                const double2 zr = z[row];
-                z[row] = make_double2(zr.x - sr, zr.y - si);
-            }
+        const double fcr = cf[ks].x, fci = cf[ks].y;
+        for (int v = 0; v < 4; ++v) {
+            xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr, fbr[v], xr[v], 0, 0, 0);
+            xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbi[v], xr[v], 0, 0, 0);
+            xi[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbr[v], xi[v], 0, 0, 0);
+            xi[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr, -fbi[v], xi[v], 0, 0, 0);
         }
+    }
+    // each wave writes back only the 16 rows it read
+    for (int r = 0; r < 4; ++r) {
+        const int row = r0 + wave * 16 + lk + 4 * r;
+        double sr = 0.0, si = 0.0;
+        for (int v = 0; v < 4; ++v) {
+            const int col = v * 16 + li;
+            const double a_ = xr[v][r], b_ = xi[v][r];
+            if (row < M && col < jb) A[(size_t)row * M + j0 + col] = make_double2(a_, b_);
+            sr += a_ * yr[col] - b_ * yi[col];
+            si += a_ * yi[col] + b_ * yr[col];
+        }
+        for (int o = 1; o < 16; o <<= 1) {
+            sr += __shfl_xor(sr, o, 64);
+            si += __shfl_xor(si, o, 64);
+        }
+        if (li == 0 && row < M) {
+            const double2 zr = z[row];
+            z[row] = make_double2(zr.x - sr, zr.y - si);
+        }
+    }
 }
 
 // L^H x = y by row panels, last panel first, one launch per panel p (then a closing launch

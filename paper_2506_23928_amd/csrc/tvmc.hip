@@ -529,20 +529,20 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
     for (int j0 = 0, p = 0; j0 < x.m; j0 += CN, ++p) {
         if (j0 > 0) {
             if constexpr (CPLX)
-                hipLaunchKernelGGL(k_zmw_update, dim3((x.m - j0 + CR - 1) / CR, T), dim3(256), 0, st, x, j0);
+                hipLaunchKernelGGL(k_zmw_update, dim3((x.m - j0 + CR - 1) / CR, T), dim3(ZT), 0, st, x, j0);
             else
                 hipLaunchKernelGGL(k_cmw_update, dim3((x.m - j0 + CR - 1) / CR, T), dim3(256), 0, st, x, j0);
             LAUNCHCHECK(c, "panel update");
         }
         if constexpr (CPLX)
-            hipLaunchKernelGGL(k_zmw_diag, dim3(T), dim3(256), 0, st, x, j0, p);
+            hipLaunchKernelGGL(k_zmw_diag, dim3(T), dim3(ZD), 0, st, x, j0, p);
         else
             hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, st, x, j0, p);
         LAUNCHCHECK(c, "diagonal block");
         const int below = x.m - j0 - CN;
         if (below > 0) {
             if constexpr (CPLX)
-                hipLaunchKernelGGL(k_zmw_trsm, dim3((below + CR - 1) / CR, T), dim3(256), 0, st, x, j0, p);
+                hipLaunchKernelGGL(k_zmw_trsm, dim3((below + CR - 1) / CR, T), dim3(ZTT), 0, st, x, j0, p);
             else
                 hipLaunchKernelGGL(k_cmw_trsm, dim3((below + CR - 1) / CR, T), dim3(256), 0, st, x, j0, p);
             LAUNCHCHECK(c, "panel TRSM");
