@@ -147,6 +147,21 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_lds(Dev a) {
         const int i = e / m, j = e % m;
         if (j <= i) As[tri(i, j)] = S[e];
     }
+    // this thread's blocks b = tid + k JAC_THREADS, as pairs (i1 >= i2) of rotation pairs with
+    // b = i1 (i1 + 1) / 2 + i2: the same in every round
+    constexpr int JL_ITEMS = (JL_MAXP * (JL_MAXP + 1) / 2 + JAC_THREADS - 1) / JAC_THREADS;
+    int bi1[JL_ITEMS], bi2[JL_ITEMS];
+    for (int k = 0; k < JL_ITEMS; ++k) {
+        const int b = tid + k * JAC_THREADS;
+        int i1 = 0;
+        if (b < nb) {
+            i1 = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+            while ((i1 + 1) * (i1 + 2) / 2 <= b) ++i1;
+            while (i1 * (i1 + 1) / 2 > b) --i1;
+        }
+        bi1[k] = i1;
+        bi2[k] = b - i1 * (i1 + 1) / 2;
+    }
     __syncthreads();
     for (int sweep = 0;; ++sweep) {
         double off = 0.0, tot = 0.0;
@@ -202,11 +217,9 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_lds(Dev a) {
                 rot[((size_t)nsweep * K + r) * np + i] = make_double2(c, s);
             }
             __syncthreads();
-            for (int b = tid; b < nb; b += JAC_THREADS) {
-                int i1 = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
-                while ((i1 + 1) * (i1 + 2) / 2 <= b) ++i1;
-                while (i1 * (i1 + 1) / 2 > b) --i1;
-                const int i2 = b - i1 * (i1 + 1) / 2;
+            for (int k = 0; k < JL_ITEMS; ++k) {
+                if (tid + k * JAC_THREADS >= nb) continue;
+                const int i1 = bi1[k], i2 = bi2[k];
                 const int p1 = sp[i1], q1 = sq[i1], p2 = sp[i2], q2 = sq[i2];
                 const bool h1 = q1 < m, h2 = q2 < m;
                 if (i1 == i2) {
@@ -242,40 +255,38 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_lds(Dev a) {
 
 // V^T = (product of the recorded rotations) applied to I, a tile of JV_COLS columns per
 // workgroup held in LDS: for every recorded round in order, rows p, q of the tile are rotated
-// (the pairs of round r follow from r as in k_jacobi_lds).
-constexpr int JV_COLS = 64;
-__global__ __launch_bounds__(JAC_THREADS) void k_jacobi_apply_v(Dev a) {
+// (the pairs of round r follow from r as in k_jacobi_lds).  Tiles of 32 columns (48 KB) let
+// three workgroups share a compute unit, so one's per-round barrier overlaps the others' work.
+constexpr int JV_COLS = 32;
+constexpr int JV_THREADS = 512;
+__global__ __launch_bounds__(JV_THREADS, 6) void k_jacobi_apply_v(Dev a) {   // 6 waves per SIMD: three workgroups per CU
     __shared__ double Vs[JL_MAXM * JV_COLS];
     const int t = blockIdx.y, j0 = blockIdx.x * JV_COLS, m = a.m;
     const int mp = m + (m & 1), K = mp - 1, np = mp / 2;
     const int tid = threadIdx.x;
     const int cols = (m - j0) < JV_COLS ? (m - j0) : JV_COLS;
-    for (int e = tid; e < m * JV_COLS; e += JAC_THREADS) {
+    for (int e = tid; e < m * JV_COLS; e += JV_THREADS) {
         const int i = e / JV_COLS, j = e % JV_COLS;
         Vs[e] = (i == j0 + j) ? 1.0 : 0.0;
     }
     __syncthreads();
     const double2 *rot = a.snrRot + (size_t)t * JAC_MAX_SWEEPS * K * np;
     const int rounds = a.snrSweeps[t] * K;
-    // a thread's items (pair i, column j) are the same every round; the rotations of the next
-    // round are loaded while the current one is applied
-    constexpr int JV_ITEMS = (JL_MAXP * JV_COLS + JAC_THREADS - 1) / JAC_THREADS;
-    double2 cur[JV_ITEMS], nxt[JV_ITEMS];
-    for (int k = 0; k < JV_ITEMS; ++k) {
-        const int i = (tid + k * JAC_THREADS) / JV_COLS;
-        cur[k] = (rounds > 0 && i < np) ? rot[i] : make_double2(1.0, 0.0);
-    }
-    for (int rr = 0; rr < rounds; ++rr) {
-        const int r = rr % K;
+    // a thread's items (pair i, column j) are the same every round; the other workgroups on the
+    // compute unit cover the latency of loading each round's rotations at its start
+    constexpr int JV_ITEMS = (JL_MAXP * JV_COLS + JV_THREADS - 1) / JV_THREADS;
+    double2 cur[JV_ITEMS];
+    for (int rr = 0, r = 0; rr < rounds; ++rr, r = (r + 1 == K ? 0 : r + 1)) {
         for (int k = 0; k < JV_ITEMS; ++k) {
-            const int i = (tid + k * JAC_THREADS) / JV_COLS;
-            nxt[k] = (rr + 1 < rounds && i < np) ? rot[(size_t)(rr + 1) * np + i] : make_double2(1.0, 0.0);
+            const int i = (tid + k * JV_THREADS) / JV_COLS;
+            cur[k] = i < np ? rot[(size_t)rr * np + i] : make_double2(1.0, 0.0);
         }
         for (int k = 0; k < JV_ITEMS; ++k) {
-            const int e = tid + k * JAC_THREADS, i = e / JV_COLS, j = e % JV_COLS;
+            const int e = tid + k * JV_THREADS, i = e / JV_COLS, j = e % JV_COLS;
             if (i >= np) continue;
-            int p = i == 0 ? r : (r + i) % K;
-            int q = i == 0 ? K : (r - i + K) % K;
+            // pair i of round r: (r + i) mod K and (r - i) mod K, both arguments in [0, 2K)
+            int p = i == 0 ? r : (r + i >= K ? r + i - K : r + i);
+            int q = i == 0 ? K : (r - i < 0 ? r - i + K : r - i);
             if (p > q) {
                 const int x = p;
                 p = q;
@@ -287,11 +298,10 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi_apply_v(Dev a) {
             Vs[p * JV_COLS + j] = cs.x * vp - cs.y * vq;
             Vs[q * JV_COLS + j] = cs.y * vp + cs.x * vq;
         }
-        for (int k = 0; k < JV_ITEMS; ++k) cur[k] = nxt[k];
         __syncthreads();
     }
     double *Vt = a.snrV + (size_t)t * m * m;
-    for (int e = tid; e < m * JV_COLS; e += JAC_THREADS) {
+    for (int e = tid; e < m * JV_COLS; e += JV_THREADS) {
         const int i = e / JV_COLS, j = e % JV_COLS;
         if (j < cols) Vt[(size_t)i * m + j0 + j] = Vs[e];
     }

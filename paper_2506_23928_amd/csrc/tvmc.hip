@@ -646,7 +646,7 @@ tvmc_status run_solve(tvmc_ctx *c) {
             if (d.m <= JL_MAXM) {
                 hipLaunchKernelGGL(k_jacobi_lds, dim3(d.nt), dim3(JAC_THREADS), 0, c->stream, d);
                 LAUNCHCHECK(c, "k_jacobi_lds");
-                hipLaunchKernelGGL(k_jacobi_apply_v, dim3((d.m + JV_COLS - 1) / JV_COLS, d.nt), dim3(JAC_THREADS), 0,
+                hipLaunchKernelGGL(k_jacobi_apply_v, dim3((d.m + JV_COLS - 1) / JV_COLS, d.nt), dim3(JV_THREADS), 0,
                                    c->stream, d);
                 LAUNCHCHECK(c, "k_jacobi_apply_v");
             } else {
