@@ -14,6 +14,7 @@
 // continue until the off-diagonal mass is below 1e-30 of the total.
 #pragma once
 #include "common.hpp"
+#include "cholesky.hpp"   // v4d, the FP64 matrix-core accumulator
 
 namespace tvmc {
 
@@ -324,19 +325,21 @@ __global__ void k_snr_rho(Dev a) {
 
 // Partial sums over 64-sample blocks of u_k(x)^2 |G(x) - <G>|^2: a 64 x 64 (eigenvector x
 // sample) tile per workgroup, u = V^T (O - <O>) accumulated over 32-row slabs staged in LDS
-// (O_l(x) recomputed from the packed samples), 4 x 4 outputs per thread.
+// (O_l(x) recomputed from the packed samples) on the FP64 matrix cores: wave w takes
+// eigenvectors 16 w .. +15 against the 64 samples, four 16 x 16 accumulators (register r of
+// lane (lk, li) holds row lk + 4 r, column li).
 constexpr int SV_K = 64, SV_X = 64, SV_L = 32;
 __global__ __launch_bounds__(256) void k_snr_var(Dev a) {
     __shared__ double vs[SV_K][SV_L + 1];
     __shared__ double os[SV_L][SV_X + 1];
-    __shared__ double red[16][SV_K];
     const int t = blockIdx.z, k0 = blockIdx.x * SV_K, x0 = blockIdx.y * SV_X;
-    const int tid = threadIdx.x, tk = tid >> 4, tx = tid & 15;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
     const int m = a.m, ns = a.ns;
     const double *Vt = a.snrV + (size_t)t * m * m;
     const uint64_t *smp = a.samples + (size_t)t * ns;
     const double *ob = a.obar + (size_t)t * m;
-    double u[4][4] = {};
+    v4d u[4];
+    for (int v = 0; v < 4; ++v) u[v] = (v4d){0.0, 0.0, 0.0, 0.0};
     for (int l0 = 0; l0 < m; l0 += SV_L) {
         __syncthreads();
         for (int e = tid; e < SV_K * SV_L; e += 256) {
@@ -348,35 +351,29 @@ __global__ __launch_bounds__(256) void k_snr_var(Dev a) {
             os[ll][xx] = (l < m && x < ns) ? (double)o_int(smp[x], a.pa[l], a.pb[l], a.n) - ob[l] : 0.0;
         }
         __syncthreads();
-        for (int ll = 0; ll < SV_L; ++ll) {
-            double v[4], o[4];
-            for (int i = 0; i < 4; ++i) v[i] = vs[tk * 4 + i][ll];
-            for (int j = 0; j < 4; ++j) o[j] = os[ll][tx * 4 + j];
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) u[i][j] += v[i] * o[j];
+        for (int ks = 0; ks < SV_L / 4; ++ks) {
+            const double fa = vs[wave * 16 + li][ks * 4 + lk];
+            for (int v = 0; v < 4; ++v)
+                u[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, os[ks * 4 + lk][v * 16 + li], u[v], 0, 0, 0);
         }
     }
     const double2 gb = a.gbar[t];
     double g2[4];
-    for (int j = 0; j < 4; ++j) {
-        const int x = x0 + tx * 4 + j;
-        g2[j] = 0.0;
+    for (int v = 0; v < 4; ++v) {
+        const int x = x0 + v * 16 + li;
+        g2[v] = 0.0;
         if (x < ns) {
             const double2 g = a.G[(size_t)t * ns + x];
             const double dr = g.x - gb.x, di = g.y - gb.y;
-            g2[j] = dr * dr + di * di;
+            g2[v] = dr * dr + di * di;
         }
     }
-    for (int i = 0; i < 4; ++i) {
+    for (int r = 0; r < 4; ++r) {
         double s = 0.0;
-        for (int j = 0; j < 4; ++j) s += u[i][j] * u[i][j] * g2[j];
-        red[tx][tk * 4 + i] = s;
-    }
-    __syncthreads();
-    if (tid < SV_K && k0 + tid < m) {
-        double s = 0.0;
-        for (int q = 0; q < 16; ++q) s += red[q][tid];
-        a.snrPart[((size_t)t * a.snr_nxb + blockIdx.y) * m + k0 + tid] = s;
+        for (int v = 0; v < 4; ++v) s += u[v][r] * u[v][r] * g2[v];
+        for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, 64);
+        const int k = k0 + wave * 16 + lk + 4 * r;
+        if (li == 0 && k < m) a.snrPart[((size_t)t * a.snr_nxb + blockIdx.y) * m + k] = s;
     }
 }
 
