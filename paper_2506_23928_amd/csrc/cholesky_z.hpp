@@ -300,11 +300,15 @@ __global__ __launch_bounds__(ZTT) void k_zmw_trsm(ZCholArgs a, int j0, int p) {
 // writes x_{p+1} over w_{p+1}, which no workgroup of launch p reads.  The closing launch
 // writes x_0 and flags non-finite solutions.
 constexpr int ZB_COLS = 256;
-__device__ __forceinline__ void zbwd_x(const double2 *__restrict__ lv, const double2 *ws, double2 *xs, int jb, int tid) {
+// Called by the whole workgroup: the block inverse is staged in LDS by all threads first.
+__device__ __forceinline__ void zbwd_x(const double2 *__restrict__ lv, double2 *lvs, const double2 *ws, double2 *xs, int jb,
+                                       int tid) {
+    for (int e = tid; e < jb * CN; e += ZB_COLS) lvs[e] = lv[e];
+    __syncthreads();
     if (tid < jb) {   // x_c = sum_{k >= c} conj(Linv_kc) w_k
         double xr = 0.0, xi = 0.0;
         for (int k = tid; k < jb; ++k) {
-            const double2 l = lv[k * CN + tid], w = ws[k];
+            const double2 l = lvs[k * CN + tid], w = ws[k];
             xr += l.x * w.x + l.y * w.y;
             xi += l.x * w.y - l.y * w.x;
         }
@@ -314,6 +318,7 @@ __device__ __forceinline__ void zbwd_x(const double2 *__restrict__ lv, const dou
 
 __global__ __launch_bounds__(ZB_COLS) void k_zmw_bwd(ZCholArgs a, int p) {
     __shared__ double2 ws[CN], xs[CN];
+    __shared__ double2 lvs[CN * CN];
     const int t = blockIdx.y, tid = threadIdx.x;
     const int M = a.m, np = chol_panels(M);
     const double2 *A = a.A + (size_t)t * M * M;
@@ -323,7 +328,7 @@ __global__ __launch_bounds__(ZB_COLS) void k_zmw_bwd(ZCholArgs a, int p) {
         const int j1 = (p + 1) * CN, jb1 = min(CN, M - j1);
         if (tid < jb1) ws[tid] = z[j1 + tid];
         __syncthreads();
-        zbwd_x(linv + (size_t)(p + 1) * CN * CN, ws, xs, jb1, tid);
+        zbwd_x(linv + (size_t)(p + 1) * CN * CN, lvs, ws, xs, jb1, tid);
         __syncthreads();
         if (tid < jb1) z[j1 + tid] = xs[tid];
         __syncthreads();
@@ -340,7 +345,7 @@ __global__ __launch_bounds__(ZB_COLS) void k_zmw_bwd(ZCholArgs a, int p) {
     const int j0 = p * CN, jb = min(CN, M - j0);
     if (tid < jb) ws[tid] = z[j0 + tid];
     __syncthreads();
-    zbwd_x(linv + (size_t)p * CN * CN, ws, xs, jb, tid);
+    zbwd_x(linv + (size_t)p * CN * CN, lvs, ws, xs, jb, tid);
     __syncthreads();
     const int c = blockIdx.x * ZB_COLS + tid;
     if (c < j0) {
