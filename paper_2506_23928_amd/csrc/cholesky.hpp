@@ -251,12 +251,13 @@ __global__ __launch_bounds__(CT1) void k_chol_solve(CholArgs a) {
                 yim[c] = c < jb ? z[j0 + c].y - ti : 0.0;
             }
         }
+        // the block inverse to LDS (the staging space is free after the factorization)
+        for (int e = tid; e < jb * CN; e += CT1) smem[e] = linv[(size_t)p * CN * CN + e];
         __syncthreads();
         if (tid < jb) {   // x_c = sum_{k >= c} Linv[k][c] w_k
-            const double *lv = linv + (size_t)p * CN * CN;
             double xr = 0.0, xi = 0.0;
             for (int k = tid; k < jb; ++k) {
-                const double l = lv[k * CN + tid];
+                const double l = smem[k * CN + tid];
                 xr += l * yre[k];
                 xi += l * yim[k];
             }
