@@ -30,6 +30,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# CPU threads the oracle baseline may use: one GPU's share of the host (the GPU hosts allot 16
+# CPUs per GPU, whatever the machine's total count is)
+CPU_SHARE = 16
+
 PEAKS = {  # MI355X published dense peaks
     "fp64": 78.6,            # TFLOP/s, vector and matrix
     "int8": 5000.0,          # TOP/s, matrix cores
@@ -105,7 +109,7 @@ def cpu_baseline(w, ns_sample=None, regulariser=0):
     import numpy as np
     import oracle as orc
     import workloads as wl
-    cores = min(os.cpu_count() or 1, 16)
+    cores = min(len(os.sched_getaffinity(0)), CPU_SHARE)
     lx, ly = wl.lattice(w)
     J = orc.couplings(w["geom"], lx, w["alpha"], w["jscale"], ly)
     pb = orc.Problem(J, w["h"], wl.jumps(w))
@@ -144,7 +148,18 @@ def cpu_baseline(w, ns_sample=None, regulariser=0):
                   "the Cholesky solve as measured: %.1f s per full evaluation" % (
                       cores, w["name"], ns, ns_full, el, ns_full // ns, t_eval))
     return {"value": cores / t_eval / 2.0, "unit": "trajectory-steps/s", "cores": cores, "kind": "oracle",
-            "sample": sample}
+            "sample": sample, "host_cpus": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
+            "cpu_model": cpu_model(), "per_core": 1.0 / t_eval / 2.0}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def tau_int(series):

@@ -173,7 +173,9 @@ enum {
     TVMC_Q_AR_ACCEPTS = 19, /* uint32[n_chains] accepted learned proposals in the last sampling */
     TVMC_Q_LOGNORM = 20,    /* double[1] log Q of the linear SSE at the current step (0 for the nonlinear SSE) */
     TVMC_Q_LOGNORM_HIST = 21, /* double[n_obs_max] log Q at the times of the moment history */
-    TVMC_Q_EIG = 22           /* double[2M] (lam_k, SNR_k) of the last SNR solve, in the solver's order */
+    TVMC_Q_EIG = 22,          /* double[2M] (lam_k, SNR_k) of the last SNR solve, in the solver's order */
+    TVMC_Q_AR_LOGQ_BF16 = 23  /* float[n_samples] log q of the last samples under the BF16 network the
+                                 sampler's acceptance test uses (computed by the get, on its stream) */
 };
 
 /* Bytes of device workspace needed for this problem, ansatz and configuration. */

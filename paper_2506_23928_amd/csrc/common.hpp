@@ -177,6 +177,7 @@ struct Dev {
     float *arh, *arda;                // [T][Ns][H] training activations
     float *arg;                       // [T][Ns][N]
     float *arlogq;                    // [T][Ns]
+    float *arlogqb;                   // [T][Ns] log q under the sampler's BF16 network (on request)
     double *arloss;                   // [T]
     uint32_t *aracc;                  // [T][C] accepted learned proposals
 };

@@ -379,6 +379,21 @@ __device__ __forceinline__ float ar_logq(const Dev &a, const ArNet &net, uint64_
     return wave_sum_f(mylq);
 }
 
+// log q of trajectory t's last samples under the sampler's BF16 network (ar_logq, one
+// wavefront per sample), the value the sampler's acceptance test uses, for checking it
+// against a float64 evaluation of the same rounded weights.
+__global__ __launch_bounds__(256) void k_ar_logq_bf16(Dev a, int t) {
+    __shared__ uint16_t sW1T[AR_LDS_W], sW2T[AR_LDS_W];
+    __shared__ float sb1[256], sb2[64];
+    const ArNet net = ar_net(a, t, sW1T, sW2T, sb1, sb2);
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int s = blockIdx.x * 4 + w; s < a.ns; s += gridDim.x * 4) {
+        const float lq = ar_logq(a, net, a.samples[(size_t)t * a.ns + s], lane);
+        if (lane == 0) a.arlogqb[(size_t)t * a.ns + s] = lq;
+    }
+}
+
 // One independent proposal s' ~ q drawn autoregressively with the BF16 network (every lane
 // returns the same s', log q(s') and accept uniform).  Philox stream 6, counter
 // (17 idx + block, ctr1, step, 6 << 24 | traj): blocks 0..15 give one 24-bit site uniform per

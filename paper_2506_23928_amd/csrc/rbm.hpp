@@ -19,15 +19,13 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// log|cosh(x + i y)| = |x| - log 2 + log((1 + e)^2 - 4 e sin^2 y) / 2 with e = exp(-2|x|); the
-// last term in FP32.
-// The learned proposal's acceptance test takes its log-cosh differences as (|x'| - |x|) in FP64
-// plus these FP32 parts: an absolute error of ~1e-6 in a log acceptance ratio, far below the
-// Monte Carlo error, with single-precision transcendentals (32-bit constants, which keep the
-// sampler's registers for its state).
-__device__ __forceinline__ float log_cosh_rest_f(double x, double y) {
-    const float e = expf(-2.f * (float)fabs(x)), sy = sinf((float)y);
-    return 0.5f * logf((1.f + e) * (1.f + e) - 4.f * e * sy * sy);
+// log|cosh(x + i y)| = |x| - log 2 + log((1 + e)^2 - 4 e sin^2 y) / 2 with e = exp(-2|x|).
+// The learned proposal's acceptance test takes its log-cosh differences as (|x'| - |x|) plus
+// the differences of the last term (at most log 2), all in FP64, so the acceptance
+// is the Metropolis-Hastings ratio for |psi|^2 itself up to double rounding.
+__device__ __forceinline__ double log_cosh_rest(double x, double y) {
+    const double e = exp(-2.0 * fabs(x)), sy = sin(y);
+    return 0.5 * log((1.0 + e) * (1.0 + e) - 4.0 * e * sy * sy);
 }
 
 // tanh(x + i y) = (sinh 2x + i sin 2y) / (cosh 2x + cos 2y), written with e = exp(-2|x|)
@@ -187,12 +185,12 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int stage, int b
                         ngr[q] = xr;
                         ngi[q] = xi;
                         dsum += (fabs(xr) - fabs(gre[q])) +
-                                (double)(log_cosh_rest_f(xr, xi) - log_cosh_rest_f(gre[q], gim[q]));
+                                (log_cosh_rest(xr, xi) - log_cosh_rest(gre[q], gim[q]));
                     }
                 }
                 if (lane < n) dsum += th[lane].x * (spin(mnew, lane) - spin(mask, lane));
                 const double dlog = 2.0 * wave_sum(dsum) + ((double)lq_cur - (double)lqn);
-                if ((double)logf((float)uacc) < dlog) {
+                if (log(uacc) < dlog) {
                     mask = mnew;
                     for (int q = 0; q < QH; ++q) {
                         const int j = lane + 64 * q;

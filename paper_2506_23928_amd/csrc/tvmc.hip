@@ -67,7 +67,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t J, jk, js, jr, pa, pb, pidx, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
         bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, lognorm, qhist, snrV, snrRho, snrW, snrEig, snrPart, snrRot, snrSweeps, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
-        arg, arlogq, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, dstep, total;
+        arg, arlogq, arlogqb, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, dstep, total;
 };
 
 int mom_blocks_for(int ns) {
@@ -182,6 +182,7 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.arda = take(ar ? sizeof(float) * tt * ns * ah : 0);
     L.arg = take(ar ? sizeof(float) * tt * ns * n : 0);
     L.arlogq = take(ar ? sizeof(float) * tt * ns : 0);
+    L.arlogqb = take(ar ? sizeof(float) * tt * ns : 0);
     L.arloss = take(sizeof(double) * tt);
     L.aracc = take(sizeof(uint32_t) * tt * nc);
     const size_t mp = ((size_t)m + RQ_T - 1) / RQ_T * RQ_T;
@@ -753,7 +754,7 @@ size_t q_bytes(const tvmc_ctx *c, int what) {
     case TVMC_Q_MOMENTS: return sizeof(double) * 9;
     case TVMC_Q_OBS_HIST: return sizeof(double) * 9 * (size_t)d.nobs;
     case TVMC_Q_AR_PARAMS: case TVMC_Q_AR_GRAD: return d.ar ? sizeof(float) * d.arnp : 0;
-    case TVMC_Q_AR_LOGQ: return d.ar ? sizeof(float) * d.ns : 0;
+    case TVMC_Q_AR_LOGQ: case TVMC_Q_AR_LOGQ_BF16: return d.ar ? sizeof(float) * d.ns : 0;
     case TVMC_Q_AR_LOSS: return d.ar ? sizeof(double) : 0;
     case TVMC_Q_AR_ACCEPTS: return d.ar ? sizeof(uint32_t) * d.nc : 0;
     case TVMC_Q_LOGNORM: return sizeof(double);
@@ -907,6 +908,7 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     d.arda = (float *)(base + L.arda);
     d.arg = (float *)(base + L.arg);
     d.arlogq = (float *)(base + L.arlogq);
+    d.arlogqb = (float *)(base + L.arlogqb);
     d.arloss = (double *)(base + L.arloss);
     d.aracc = (uint32_t *)(base + L.aracc);
 
@@ -1153,6 +1155,12 @@ tvmc_status tvmc_get(tvmc_ctx *c, int32_t what, int32_t traj, void *host, size_t
     case TVMC_Q_AR_PARAMS: src = d.arP + t * d.arnp; break;
     case TVMC_Q_AR_GRAD: src = d.arG + t * d.arnp; break;
     case TVMC_Q_AR_LOGQ: src = d.arlogq + t * d.ns; break;
+    case TVMC_Q_AR_LOGQ_BF16:
+        hipLaunchKernelGGL(k_ar_logq_bf16, dim3((d.ns + 3) / 4 < 1024 ? (d.ns + 3) / 4 : 1024), dim3(256), 0, c->stream,
+                           d, traj);
+        LAUNCHCHECK(c, "k_ar_logq_bf16");
+        src = d.arlogqb + t * d.ns;
+        break;
     case TVMC_Q_AR_LOSS: src = d.arloss + t; break;
     case TVMC_Q_AR_ACCEPTS: src = d.aracc + t * d.nc; break;
     case TVMC_Q_LOGNORM: src = d.lognorm + t; break;

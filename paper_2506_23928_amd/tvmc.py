@@ -20,7 +20,7 @@ HEUN, MIDPOINT = 0, 1
 PREC_FP64, PREC_MFMA = 0, 1
 (Q_THETA, Q_THETA_EVAL, Q_DELTA0, Q_DELTA1, Q_SAMPLES, Q_ELOC, Q_S, Q_D, Q_OBAR, Q_BMEAN, Q_DW, Q_ACCEPTS,
  Q_CHAINS, Q_MOMENTS, Q_OBS_HIST, Q_AR_PARAMS, Q_AR_GRAD, Q_AR_LOGQ, Q_AR_LOSS, Q_AR_ACCEPTS, Q_LOGNORM,
- Q_LOGNORM_HIST, Q_EIG) = range(23)
+ Q_LOGNORM_HIST, Q_EIG, Q_AR_LOGQ_BF16) = range(24)
 PROPOSAL_FLIP, PROPOSAL_LEARNED = 0, 1
 SOLVER_AUTO, SOLVER_ONE_GROUP, SOLVER_MULTI_GROUP, SOLVER_SAMPLE_SPACE = 0, 1, 2, 3
 SSE_NONLINEAR, SSE_LINEAR = 0, 1
@@ -227,7 +227,7 @@ class Context:
                Q_BMEAN: ("c", "nch"), Q_DW: ("d", "nch"), Q_ACCEPTS: ("u4", "nc"), Q_CHAINS: ("u8", "nc"),
                Q_MOMENTS: ("d", "9"), Q_OBS_HIST: ("d", "hist"), Q_AR_PARAMS: ("f", "arnp"), Q_AR_GRAD: ("f", "arnp"),
                Q_AR_LOGQ: ("f", "ns"), Q_AR_LOSS: ("d", "1"), Q_AR_ACCEPTS: ("u4", "nc"), Q_LOGNORM: ("d", "1"),
-               Q_LOGNORM_HIST: ("d", "nobs"), Q_EIG: ("d", "2m")}
+               Q_LOGNORM_HIST: ("d", "nobs"), Q_EIG: ("d", "2m"), Q_AR_LOGQ_BF16: ("f", "ns")}
 
     def __init__(self, problem: Problem, config: tvmc_config, kind=JASTROW, n_hidden=0, theta0=None, device="cuda",
                  stream=None):

@@ -163,3 +163,82 @@ def test_learned_chain_rbm_samples_psi_squared(tv):
     assert chi2 < 2.0 * (1 << n), chi2
     ar = ctx.get(T.Q_AR_ACCEPTS, 0)
     assert ar.sum() > 0.2 * nc * (ns // nc + 2), ar.sum()
+
+
+def _bf16(x):
+    """float32 -> bfloat16 (round to nearest even) -> float64: the sampler's weight copies."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _fp32_logq_bound(p, s):
+    """Worst-case error of log q evaluated in FP32 with the float64 values of its weights:
+    each pre-activation sums N + 1 terms and each logit H + 1, so with g_K = K u / (1 - K u),
+    u = 2^-24, |d a_k| <= g_{N+1} (|b1_k| + sum_j |W1_kj|), |d l_i| <= g_{H+1} sum_k |W2_ik| |h_k|
+    + sum_k |W2_ik| |d a_k| + |b2_i| u, and log sigmoid is 1-Lipschitz (plus its own rounding
+    and that of the sum over sites)."""
+    import oracle.made as md
+    W1, b1, W2, b2 = p
+    n, h = W2.shape
+    m1, m2 = md.masks(n, h)
+    u = 2.0 ** -24
+    g = lambda k: k * u / (1 - k * u)
+    aw1, aw2 = np.abs(W1 * m1), np.abs(W2 * m2)
+    da = g(n + 1) * (np.abs(b1) + aw1.sum(axis=1))                      # [H]
+    logq, (_, a, hh, logits, _, _) = md.forward(p, s)
+    dl = g(h + 1) * (np.abs(hh) @ aw2.T + np.abs(b2)) + da @ aw2.T      # [B, N]
+    return dl.sum(axis=1) + g(n + 1) * np.abs(logq) + n * 4 * u
+
+
+def test_made_benchmark_shape_matches_oracle(tv):
+    """The network at the benchmark's shape: N = 64 inputs, H = 128 hidden units (so every
+    kernel's second 64-lane chunk of hidden units is used), 4096 samples of a random N = 64
+    problem, random masked parameters.  Training forward (FP32) against the float64 oracle within
+    the worst-case FP32 bound, loss, gradient and one Adam step; and the BF16 log q that the
+    samplers' acceptance test uses, element by element against a float64 evaluation of the same
+    BF16-rounded weights, within the same bound."""
+    import oracle.made as md
+    from paper_2506_23928_amd import tvmc as T
+    n, h, ns, nc = 64, 128, 4096, 64
+    m = n + n * (n - 1) // 2
+    ctx = _ctx(tv, n, h, ns, nc, theta0=wl.random_theta(m, 0.05, seed=21), init=4)
+    ctx.sample()
+    rng = np.random.default_rng(5)
+    m1, m2 = md.masks(n, h)
+    W1 = (rng.standard_normal((h, n)) * 0.3 * m1).astype(np.float32)
+    W2 = (rng.standard_normal((n, h)) * 0.3 * m2).astype(np.float32)
+    b1 = (rng.standard_normal(h) * 0.1).astype(np.float32)
+    b2 = (rng.standard_normal(n) * 0.1).astype(np.float32)
+    flat = np.concatenate([W1.reshape(-1), b1, W2.reshape(-1), b2]).astype(np.float32)
+    ctx.set(T.Q_AR_PARAMS, 0, flat)
+    ctx.train_proposal(0)
+    ctx.synchronize()
+    p = _params(ctx.get(T.Q_AR_PARAMS, 0), n, h)
+    assert np.array_equal(np.concatenate([x.reshape(-1) for x in p]), flat.astype(np.float64))
+    s = tv.unpack_samples(ctx.get(T.Q_SAMPLES, 0), n).astype(np.float64)
+    logq, (_, a, _, _, _, _) = md.forward(p, s)
+    assert (a[:, 64:] > 0).mean() > 0.2          # hidden units 64..127 are active
+    bound = _fp32_logq_bound(p, s)
+    err = np.abs(ctx.get(T.Q_AR_LOGQ, 0) - logq)
+    assert np.all(err <= bound), (err.max(), bound.min())
+    loss, grads = md.nll_and_grad(p, s)
+    assert abs(ctx.get(T.Q_AR_LOSS, 0)[0] - loss) <= bound.mean()
+    g = ctx.get(T.Q_AR_GRAD, 0).astype(np.float64)
+    gw = np.concatenate([x.reshape(-1) for x in grads])
+    assert np.abs(g - gw).max() < 3e-4 * np.abs(gw).max(), np.abs(g - gw).max() / np.abs(gw).max()
+    # the sampler's BF16 network (weights rounded to BF16, biases FP32, FP32 sums)
+    pb = [_bf16(p[0]), p[1], _bf16(p[2]), p[3]]
+    lqb, _ = md.forward(pb, s)
+    errb = np.abs(ctx.get(T.Q_AR_LOGQ_BF16, 0) - lqb)
+    assert np.all(errb <= _fp32_logq_bound(pb, s)), errb.max()
+    assert np.abs(lqb - logq).max() > 10 * errb.max()      # the comparison sees the BF16 rounding
+    # one Adam step from the GPU's own gradient
+    ctx.train_proposal(1)
+    ctx.synchronize()
+    newp = ctx.get(T.Q_AR_PARAMS, 0).astype(np.float64)
+    z = [np.zeros_like(x) for x in p]
+    want, _, _ = md.adam_step(p, _params(g, n, h), z, z, 1, lr=1e-2)
+    wantf = np.concatenate([x.reshape(-1) for x in want])
+    pf = np.concatenate([x.reshape(-1) for x in p])
+    assert np.abs(newp - wantf).max() < 1e-5 * 1e-2 + 1e-6 * np.abs(pf).max()

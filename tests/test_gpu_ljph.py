@@ -2,10 +2,11 @@
 
 Bars as for the all-pair Jastrow: samples, accept counts, <O_k> and S + eps I bit-exact (the
 shared O_k are integer sums of +-1, so every sum is an exact integer in FP64), D to 1e-12 and
-theta to 1e-9 relative.
+theta to 1e-10 relative.
 """
 import numpy as np
 import pytest
+from parity_log import parity
 
 import workloads as wl
 
@@ -62,7 +63,7 @@ def test_ljph_evaluation_parity(tv, orc, n, d, ns, nc):
             low = np.tril_indices(m)
             assert np.array_equal(S[t][low], (r["S"].real + eps * np.eye(m))[low])
             assert _rel(ctx.get(T.Q_D, t), r["D"]) < 1e-12
-            assert _rel(ctx.get(T.Q_DELTA0, t), r["delta"]) < 1e-9
+            parity("Q_DELTA0", _rel(ctx.get(T.Q_DELTA0, t), r["delta"]), 1e-10)
 
 
 @pytest.mark.parametrize("scheme", [0, 1])
@@ -85,7 +86,7 @@ def test_ljph_trajectory_parity(tv, orc, scheme):
     ctx.observables()
     ctx.synchronize()
     for t in range(TT):
-        assert _rel(ctx.get(T.Q_THETA, t), th_o[t]) < 1e-9, t
+        parity("Q_THETA", _rel(ctx.get(T.Q_THETA, t), th_o[t]), 1e-10)
         assert np.abs(ctx.get(T.Q_OBS_HIST, t)[:2] - obs_o[t, :2]).max() < 1e-10
         assert np.abs(ctx.get(T.Q_MOMENTS, t) - obs_o[t, 2]).max() < 1e-10
 

@@ -8,6 +8,7 @@ complex S, accumulated in different orders, are compared to 1e-12 of their scale
 """
 import numpy as np
 import pytest
+from parity_log import parity
 
 import workloads as wl
 
@@ -76,24 +77,24 @@ def test_rbm_step_parity(tv, orc, n, nh, ns, nc, scheme):
             want = r["S"] + eps * np.eye(dim)
             low = np.tril_indices(dim)
             assert np.abs(S[low] - want[low]).max() < 1e-12 * np.abs(want).max()
-            assert _rel(ctx.get(T.Q_D, t), r["D"]) < 1e-11
+            parity("Q_D", _rel(ctx.get(T.Q_D, t), r["D"]), 1e-11)
         ctx.sr_solve()
         for t in range(TT):
             r = ref[t][2 + stage]
-            assert _rel(ctx.get(T.Q_DELTA0 if stage == 0 else T.Q_DELTA1, t), r["delta"]) < 1e-8
+            parity("Q_DELTA0", _rel(ctx.get(T.Q_DELTA0 if stage == 0 else T.Q_DELTA1, t), r["delta"]), 1e-10)
         ctx.update()
         if stage == 0:
             for t in range(TT):
                 chains, dw, r0 = ref[t]
                 th_e = th0 + (r0["delta"] if scheme == 0 else 0.5 * r0["delta"])
-                assert _rel(ctx.get(T.Q_THETA_EVAL, t), th_e) < 1e-8
+                parity("Q_THETA_EVAL", _rel(ctx.get(T.Q_THETA_EVAL, t), th_e), 1e-10)
                 ref[t].append(orc.evaluate(pb, 1, nh, cfg_o, th_e, chains, traj=3 + t, stage=1, first=False, dw=dw,
                                            want_solve=want_solve))
     ctx.synchronize()
     for t in range(TT):
         r0, r1 = ref[t][2], ref[t][3]
         want = th0 + (0.5 * (r0["delta"] + r1["delta"]) if scheme == 0 else r1["delta"])
-        assert _rel(ctx.get(T.Q_THETA, t), want) < 1e-8
+        parity("Q_THETA", _rel(ctx.get(T.Q_THETA, t), want), 1e-10)
 
 
 def test_rbm_trajectory_and_moments(tv, orc):
@@ -117,7 +118,7 @@ def test_rbm_trajectory_and_moments(tv, orc):
     ctx.observables()
     ctx.synchronize()
     for t in range(TT):
-        assert _rel(ctx.get(T.Q_THETA, t), th_o[t]) < 1e-8
+        parity("Q_THETA", _rel(ctx.get(T.Q_THETA, t), th_o[t]), 1e-10)
         assert np.abs(ctx.get(T.Q_OBS_HIST, t)[:2] - obs_o[t, :2]).max() < 1e-10
         assert np.abs(ctx.get(T.Q_MOMENTS, t) - obs_o[t, 2]).max() < 1e-10
 
@@ -142,7 +143,7 @@ def test_rbm_weights_from_global_memory(tv, orc):
     assert np.array_equal(tv.unpack_samples(ctx.get(T.Q_SAMPLES, 0), n), r["samples"])
     assert _rel(ctx.get(T.Q_ELOC, 0), r["eloc"]) < 1e-12
     assert _rel(ctx.get(T.Q_BMEAN, 0), r["bmean"]) < 1e-12
-    assert _rel(ctx.get(T.Q_D, 0), r["D"]) < 1e-11
+    parity("Q_D", _rel(ctx.get(T.Q_D, 0), r["D"]), 1e-11)
 
 
 def _bf16_bound(Sref, ns):

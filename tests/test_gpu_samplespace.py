@@ -2,11 +2,12 @@
 
 Tolerances: T + eps I 1e-13 of its scale for the Jastrow ansatz (integer kernel, centring by
 separately rounded operations on both sides) and 1e-12 for the RBM (tanh rows, different
-summation order); increments 1e-9 against the oracle's sample-space solve and 1e-8 against
+summation order); increments 1e-10 against the oracle's sample-space solve and against
 its parameter-space solve (the push-through identity holds exactly; the two solves round
 differently, amplified by cond(T + eps I))."""
 import numpy as np
 import pytest
+from parity_log import parity
 
 import workloads as wl
 
@@ -62,8 +63,8 @@ def test_sample_space_evaluation(tv, orc, kind, n, nh, ns, nc):
         tol = 1e-13 if kind == 0 else 1e-12
         assert np.abs(Ts[t][low] - want[low]).max() < tol * np.abs(want).max()
         d = ctx.get(T.Q_DELTA0, t)
-        assert _rel(d, r3["delta"]) < 1e-9
-        assert _rel(d, r1["delta"]) < 1e-8
+        parity("delta_vs_oracle_sample_space", _rel(d, r3["delta"]), 1e-10)
+        parity("delta_vs_oracle_param_space", _rel(d, r1["delta"]), 1e-10)
 
 
 def test_sample_space_trajectory(tv, orc):
@@ -81,7 +82,7 @@ def test_sample_space_trajectory(tv, orc):
     ctx.sde_step(steps)
     ctx.synchronize()
     for t in range(TT):
-        assert _rel(ctx.get(T.Q_THETA, t), th_o[t]) < 1e-8
+        parity("Q_THETA", _rel(ctx.get(T.Q_THETA, t), th_o[t]), 1e-10)
 
 
 @pytest.mark.parametrize("name", ["chain64_rbm_wide", "lattice8x8_rbm_ss"])
