@@ -205,6 +205,148 @@ def autocorrelation(tv, w, steps, n_traj):
     return out
 
 
+APPD_REFERENCE = {"chain64_rbm_learned": "chain64_obc_a1.5_g0.1"}
+
+
+def load_appd(workload):
+    """App. D's exact xi^2 at the output times (tests/golden/appd_<case>.txt, written from the
+    oracle by tests/golden/make_appd_reference.py): {t: xi^2}."""
+    path = os.path.join(ROOT, "tests", "golden", "appd_%s.txt" % APPD_REFERENCE[workload])
+    out = {}
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        v = [float(x) for x in line.split()]
+        out[round(v[0], 6)] = v[-1]
+    return out
+
+
+def jackknife_sigma(loo):
+    import numpy as np
+    loo = np.asarray(loo, dtype=np.float64)
+    T = loo.shape[0]
+    return float(np.sqrt((T - 1) / T * np.sum((loo - loo.mean(axis=0)) ** 2, axis=0)))
+
+
+# forms of the error protocol: (S-build precision, proposal)
+FORMS = {"plain": ("fp64", "flip"), "precision": ("mfma", "flip"), "fast": ("mfma", "learned")}
+
+
+def error_run(tv, w, form, ns, out_dir, dt=None, max_seconds=None, resume_dir=None):
+    """One form of the fixed-xi^2-error protocol: every trajectory of the workload from t = 0 to
+    t_end with N_s samples per evaluation, moments every obs_every steps; xi^2 at each output
+    time from the library's trajectory average, with a jackknife over the trajectories (each
+    leave-one-out ensemble on the GPU), and e = max_t |xi^2(t) - xi^2_exact(t)| with its own
+    jackknife sigma.  Writes <out_dir>/error_<form>_<ns>[_dt<dt>].json.  With max_seconds, a run
+    that has not finished after that much wall time stops at the next output time and leaves a
+    checkpoint (tvmc_save_state) and its elapsed time in out_dir; the same call resumes from it
+    (found in out_dir or resume_dir)."""
+    import numpy as np
+    import workloads as wl
+    prec, prop = FORMS[form]
+    ww = dict(w)
+    ww["n_samples"] = ns
+    if dt:
+        ww["dt"] = dt
+        ww["obs_every"] = int(round(0.1 / dt))
+    tag = "%s_%d" % (form, ns) + ("_dt%g" % dt if dt else "")
+    exact = load_appd(w["name"])
+    ctx = build_context(tv, ww, tv.PREC_MFMA if prec == "mfma" else tv.PREC_FP64,
+                        proposal=tv.PROPOSAL_LEARNED if prop == "learned" else tv.PROPOSAL_FLIP)
+    steps, every, T = wl.n_steps(ww), ww["obs_every"], ww["n_traj"]
+    os.makedirs(out_dir, exist_ok=True)
+    ckpt, part = os.path.join(out_dir, "ckpt_%s.npy" % tag), os.path.join(out_dir, "partial_%s.json" % tag)
+    el0, start = 0.0, 0
+    if resume_dir and not os.path.exists(ckpt):
+        ckpt_in, part_in = (os.path.join(resume_dir, os.path.basename(x)) for x in (ckpt, part))
+    else:
+        ckpt_in, part_in = ckpt, part
+    if os.path.exists(ckpt_in) and os.path.exists(part_in):
+        ctx.load_state(np.load(ckpt_in))
+        start = ctx.position()[0]
+        el0 = json.load(open(part_in))["seconds"]
+        print("error protocol: %s resumed at step %d" % (tag, start), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for s0 in range(start, steps, every):
+        ctx.sde_step(every)
+        ctx.synchronize()
+        print("error protocol: %s step %d of %d (%.0f s)" % (tag, s0 + every, steps, time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+        if max_seconds and s0 + every < steps and time.perf_counter() - t0 > max_seconds:
+            np.save(ckpt, ctx.save_state())
+            with open(part, "w") as f:
+                json.dump({"seconds": el0 + time.perf_counter() - t0, "step": s0 + every}, f)
+            print(json.dumps({"form": form, "n_samples": ns, "checkpoint_step": s0 + every}), flush=True)
+            return None
+    el = el0 + time.perf_counter() - t0
+    ctx.sample()
+    ctx.observables()
+    ctx.synchronize()
+    times, xi, sig, dev, loo_dev, mx = [], [], [], [], [], []
+    for k in range(1, steps // every + 1):
+        slot = k if k < steps // every else -1          # record k holds step k * every; the last is the final pass
+        t = round(k * every * ww["dt"], 6)
+        M, C, x2, loo = ctx.ensemble_at(slot, jackknife=True)
+        times.append(t)
+        xi.append(x2)
+        mx.append(float(M[0]))
+        sig.append(jackknife_sigma(loo))
+        dev.append(x2 - exact[t])
+        loo_dev.append(loo - exact[t])
+    loo_dev = np.abs(np.array(loo_dev))                  # [times][T]
+    e = float(np.max(np.abs(dev)))
+    res = {"workload": w["name"], "form": form, "s_build": prec, "proposal": prop, "n_samples": ns, "n_traj": T,
+           "steps": steps, "dt": ww["dt"], "seconds": el, "traj_steps_per_s": T * steps / el, "t": times,
+           "xi2": xi, "xi2_sigma": sig, "xi2_exact": [exact[t] for t in times], "mx": mx, "e": e,
+           "e_sigma": jackknife_sigma(loo_dev.max(axis=0)), "t_of_e": times[int(np.argmax(np.abs(dev)))],
+           "kernel_sources_sha": kernel_sources_sha()}
+    with open(os.path.join(out_dir, "error_%s.json" % tag), "w") as f:
+        json.dump(res, f)
+    for fn in (ckpt, part):
+        if os.path.exists(fn):
+            os.remove(fn)
+    print(json.dumps({k: res[k] for k in ("form", "n_samples", "e", "e_sigma", "t_of_e", "traj_steps_per_s")}),
+          flush=True)
+    del ctx
+    return res
+
+
+def error_summary(in_dir, workload, autocorr_path=None):
+    """The fixed-xi^2-error protocol from the --error-run results in in_dir: the plain form (FP64
+    S, single flips) at the workload's N_s gives e_plain; the fast form (BF16-split S, learned
+    proposal) is taken at the smallest N_s whose e_fast <= e_plain + 2 sigma_e, sigma_e the
+    jackknife errors of the two e added in quadrature.  Returns the summary dict."""
+    import glob
+    runs = [json.load(open(f)) for f in sorted(glob.glob(os.path.join(in_dir, "error_*.json")))]
+    runs = [r for r in runs if r["workload"] == workload]
+    import workloads as wl
+    ns0, dt0 = wl.WORKLOADS[workload]["n_samples"], wl.WORKLOADS[workload]["dt"]
+    plain = [r for r in runs if r["form"] == "plain" and r["n_samples"] == ns0 and r["dt"] == dt0][0]
+    fast = sorted([r for r in runs if r["form"] == "fast" and r["dt"] == dt0], key=lambda r: r["n_samples"])
+    rows = []
+    for r in runs:
+        rows.append({k: r[k] for k in ("form", "n_samples", "dt", "e", "e_sigma", "t_of_e", "traj_steps_per_s", "t",
+                                       "xi2", "xi2_sigma", "xi2_exact", "mx", "kernel_sources_sha")})
+    ok = []
+    for r in fast:
+        sig = (plain["e_sigma"] ** 2 + r["e_sigma"] ** 2) ** 0.5
+        r["equal_error"] = r["e"] <= plain["e"] + 2.0 * sig
+        r["sigma_e"] = sig
+        if r["equal_error"]:
+            ok.append(r)
+    star = ok[0] if ok else None
+    out = {"workload": workload, "protocol": "e = max over t in 0.1..t_end of |xi^2 - xi^2_exact(App. D)|, jackknife "
+           "over trajectories; fast form accepted when e_fast <= e_plain + 2 sigma_e",
+           "n_samples_plain": plain["n_samples"], "e_plain": plain["e"], "e_plain_sigma": plain["e_sigma"],
+           "fast": [{"n_samples": r["n_samples"], "e": r["e"], "e_sigma": r["e_sigma"], "sigma_e": r["sigma_e"],
+                     "equal_error": r["equal_error"], "traj_steps_per_s": r["traj_steps_per_s"]} for r in fast],
+           "n_samples_fast": star["n_samples"] if star else None, "e_fast": star["e"] if star else None,
+           "runs": rows}
+    if autocorr_path and os.path.exists(autocorr_path):
+        out["autocorr"] = json.load(open(autocorr_path))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +364,17 @@ def main():
                     help="run --steps steps, appending per-step metrics as JSON lines to FILE (untimed)")
     ap.add_argument("--autocorr", action="store_true",
                     help="measure the integrated autocorrelation time with and without the learned proposal")
+    ap.add_argument("--error-run", metavar="FORM:NS",
+                    help="one form of the fixed-xi^2-error protocol (plain, precision or fast, at NS samples, "
+                         "optionally FORM:NS:DT): the "
+                         "whole run against App. D, written as JSON to --out")
+    ap.add_argument("--out", default="gpurun_out", help="directory of --error-run results")
+    ap.add_argument("--max-seconds", type=float, default=None,
+                    help="--error-run: checkpoint and stop after this much wall time (the next call resumes)")
+    ap.add_argument("--resume-from", default=None, help="--error-run: another directory holding a checkpoint")
+    ap.add_argument("--error-summary", metavar="DIR",
+                    help="summarise the --error-run results in DIR into profiles/fixed_error_<workload>.json")
+    ap.add_argument("--autocorr-json", default=None, help="--error-summary: a saved --autocorr result to include")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -236,6 +389,13 @@ def main():
         torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}))
+        return
+    if args.error_summary:
+        res = error_summary(args.error_summary, args.workload, args.autocorr_json)
+        path = os.path.join(ROOT, "profiles", "fixed_error_%s.json" % args.workload)
+        with open(path, "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps({k: res[k] for k in ("n_samples_plain", "e_plain", "n_samples_fast", "e_fast")}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: one GPU only (trajectories shard across GPUs by design, but there is no "
@@ -264,6 +424,11 @@ def main():
             log.write(ctx, workload=args.workload)
         log.close()
         print(json.dumps({"workload": args.workload, "steps": args.steps, "log": args.log}), flush=True)
+        return
+    if args.error_run:
+        parts = args.error_run.split(":")
+        error_run(tv, w, parts[0], int(parts[1]), args.out, dt=float(parts[2]) if len(parts) > 2 else None,
+                  max_seconds=args.max_seconds, resume_dir=args.resume_from)
         return
     if args.autocorr:
         res = autocorrelation(tv, w, args.steps, min(T, 16))
@@ -355,6 +520,37 @@ def main():
     del ctx
     torch.cuda.empty_cache()
 
+    # the fixed-xi^2-error protocol's result (profiles/fixed_error_<workload>.json, from --error-run
+    # and --error-summary): the fast form's N_s at equal error, timed here over the same steps
+    fixed = None
+    fe_path = os.path.join(ROOT, "profiles", "fixed_error_%s.json" % args.workload)
+    if os.path.exists(fe_path) and not args.graph:
+        fe = json.load(open(fe_path))
+        ns_f = fe["n_samples_fast"]
+        rate_f = value
+        if ns_f and ns_f != w["n_samples"]:
+            wf = dict(w)
+            wf["n_samples"] = ns_f
+            fctx = build_context(tv, wf, prec, solver=solver, regulariser=reg)
+            for _ in range(args.warmup):
+                fctx.sde_step(1)
+            fctx.synchronize()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                fctx.sde_step(1)
+            torch.cuda.synchronize()
+            rate_f = T * args.steps / (time.perf_counter() - t1)
+            del fctx
+            torch.cuda.empty_cache()
+            print("bench: fast form at the equal-error N_s = %d: %.1f trajectory-steps/s" % (ns_f, rate_f),
+                  file=sys.stderr, flush=True)
+        f8 = [r for r in fe["fast"] if r["n_samples"] == w["n_samples"]]
+        fixed = {"source": os.path.relpath(fe_path, ROOT), "n_samples_plain": fe["n_samples_plain"],
+                 "e_plain": fe["e_plain"], "e_plain_sigma": fe["e_plain_sigma"], "n_samples_fast": ns_f,
+                 "e_fast": fe["e_fast"], "e_fast_at_config_n_samples": f8[0]["e"] if f8 else None,
+                 "value_fast_at_equal_error": rate_f}
+
     plain = None
     if not args.no_plain:
         # the plain form: FP64 S-build, one trajectory per launch
@@ -395,6 +591,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_form_value": plain,
+        "fixed_error": dict(fixed, ratio_at_equal_error=(fixed["value_fast_at_equal_error"] / plain) if plain else None)
+        if fixed else None,
         "kernel_ms": {g: round(v["avg_ms"], 4) for g, v in groups.items()},
         "kernel_sources_sha": kernel_sources_sha(),
     }

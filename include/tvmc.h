@@ -16,7 +16,8 @@
  *   H = sum_{i<j} J_ij sz_i sz_j + hx sum_i sx_i        (the LITF Hamiltonian, Eq. 10, with
  *       the couplings and field passed in: the paper's sign is J_ij < 0, hx = -h)
  *   L_n = sqrt(rate_n) * op_n(site_n), op in {sigma^-, sigma^+, sigma^z}   (Eq. 1)
- *   configuration sigma_i = +-1 (sz eigenvalues); bit i of a packed word set <=> sigma_i = +1.
+ *   configuration sigma_i = +-1 (sz eigenvalues), packed into W = ceil(N / 64) 64-bit words:
+ *   bit i % 64 of word i / 64 set <=> sigma_i = +1; bits at and above N are zero.
  *
  * Parameter layout theta (interleaved re, im doubles):
  *   Jastrow (Eq. 12): [a_0..a_{N-1}, eta_01, eta_02, .., eta_0,N-1, eta_12, .., eta_N-2,N-1]
@@ -67,7 +68,7 @@ enum { TVMC_PREC_FP64 = 0, TVMC_PREC_MFMA = 1 };
 /* One Lindblad problem (Eq. 1 with the Hamiltonian of Eq. 10), shared by all trajectories of a
  * context (see tvmc_init_batch for one problem per trajectory). */
 typedef struct {
-    int32_t n_sites;              /* N, 1..64 */
+    int32_t n_sites;              /* N, 1..128 (the learned proposal and the SNR solve: 1..64) */
     const double *J;              /* host, N*N row-major, symmetric, zero diagonal */
     double hx;
     int32_t n_jumps;              /* 0..256 */
@@ -153,7 +154,7 @@ enum {
     TVMC_Q_THETA_EVAL = 1,  /* double[2M] theta of the current evaluation */
     TVMC_Q_DELTA0 = 2,      /* double[2M] predictor increment */
     TVMC_Q_DELTA1 = 3,      /* double[2M] corrector increment */
-    TVMC_Q_SAMPLES = 4,     /* uint64[n_samples] packed configurations of the last sampling */
+    TVMC_Q_SAMPLES = 4,     /* uint64[n_samples][W] packed configurations of the last sampling */
     TVMC_Q_ELOC = 5,        /* double[2 n_samples] local energy of H */
     TVMC_Q_S = 6,           /* double[M*M] S + eps I, lower triangle valid (before the solve, which
                                factorises it in place); for the RBM complex, double[2 M*M] interleaved */
@@ -162,7 +163,7 @@ enum {
     TVMC_Q_BMEAN = 9,       /* double[2 n_jumps] <B^n> */
     TVMC_Q_DW = 10,         /* double[n_jumps] Wiener increments of the current step */
     TVMC_Q_ACCEPTS = 11,    /* uint32[n_chains] accepted proposals in the last sampling */
-    TVMC_Q_CHAINS = 12,     /* uint64[n_chains] chain configurations */
+    TVMC_Q_CHAINS = 12,     /* uint64[n_chains][W] chain configurations (settable) */
     TVMC_Q_MOMENTS = 13,    /* double[9] moments (mx,my,mz,sxx,syy,szz,sxy,sxz,syz) */
     TVMC_Q_OBS_HIST = 14,   /* double[n_obs_max*9] moment history; traj selects the trajectory */
     TVMC_Q_AR_PARAMS = 15,  /* float[P] network parameters W1 [H][N] | b1 [H] | W2 [N][H] | b2 [N],
@@ -223,6 +224,11 @@ tvmc_status tvmc_observables(tvmc_ctx *ctx, double *moments_out);
  * average is App. B's weighted one, each trajectory's moments times its Q at the time they were
  * taken, divided by N_T. */
 tvmc_status tvmc_ensemble(tvmc_ctx *ctx, double *out);
+/* The same average for history record `slot` of the moments (slot < 0: the last moments), and,
+ * when loo_xi2 is not NULL, a jackknife over the trajectories: loo_xi2[t] (n_traj doubles) is
+ * xi^2 of the average with trajectory t left out (n_traj >= 2).  A record not yet taken returns
+ * TVMC_E_INVAL. */
+tvmc_status tvmc_ensemble_at(tvmc_ctx *ctx, int32_t slot, double *out, double *loo_xi2);
 /* Copy a quantity (TVMC_Q_*) of one trajectory to host memory of at least `bytes` bytes. */
 tvmc_status tvmc_get(tvmc_ctx *ctx, int32_t what, int32_t traj, void *host_out, size_t bytes);
 /* Overwrite theta (TVMC_Q_THETA) or the chain configurations (TVMC_Q_CHAINS) of a trajectory. */

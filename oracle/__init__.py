@@ -59,7 +59,7 @@ class _Config(ctypes.Structure):
 class _EvalOut(ctypes.Structure):
     _fields_ = [("samples", _c_i8p), ("eloc", _c_dp), ("S", _c_dp), ("F", _c_dp), ("Nn", _c_dp), ("D", _c_dp),
                 ("bmean", _c_dp), ("obar", _c_dp), ("delta", _c_dp), ("accepts", _c_i64p), ("obs", _c_dp),
-                ("seconds", _c_dp), ("dlognorm", _c_dp), ("eig", _c_dp)]
+                ("seconds", _c_dp), ("dlognorm", _c_dp), ("eig", _c_dp), ("G", _c_dp)]
 
 
 def build(force: bool = True) -> str:
@@ -249,6 +249,7 @@ def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, cha
         "bmean": np.zeros(max(nch, 1), np.complex128), "obar": np.zeros(m, np.complex128),
         "delta": np.zeros(m, np.complex128), "accepts": np.zeros(max(cfg.n_chains, 1), np.int64),
         "obs": np.zeros(9), "seconds": np.zeros(3), "dlognorm": np.zeros(1), "eig": np.zeros((m, 2)),
+        "G": np.zeros(ns, np.complex128),
     }
     eo = _EvalOut(_p(r["samples"], _c_i8p), _p(r["eloc"].view(np.float64), _c_dp),
                   _p(r["S"].view(np.float64), _c_dp), _p(r["F"].view(np.float64), _c_dp),
@@ -256,7 +257,7 @@ def evaluate(problem: Problem, kind: int, n_hidden: int, cfg: Config, theta, cha
                   _p(r["bmean"].view(np.float64), _c_dp), _p(r["obar"].view(np.float64), _c_dp),
                   _p(r["delta"].view(np.float64), _c_dp), _p(r["accepts"], _c_i64p),
                   _p(r["obs"], _c_dp) if want_moments else None, _p(r["seconds"], _c_dp),
-                  _p(r["dlognorm"], _c_dp), _p(r["eig"], _c_dp))
+                  _p(r["dlognorm"], _c_dp), _p(r["eig"], _c_dp), _p(r["G"].view(np.float64), _c_dp))
     ch = chains if chains is not None else np.zeros((1, n), np.int8)
     assert ch.dtype == np.int8 and ch.flags.c_contiguous
     pc = problem._c()

@@ -8,7 +8,10 @@ Dense / sparse state-space references for small N, written from the paper:
     of App. C;
   * dense-algebra S, F, N^n (definitions after Eq. 8) from derivative vectors of psi;
   * the closed form of App. D for the LITF without transverse field, as printed for the
-    periodic chain, and its site-resolved form for arbitrary couplings J_ij.
+    periodic chain, and its site-resolved form for arbitrary couplings J_ij;
+  * a second, vectorised statement of the SNR-regularised solve (the regulariser named after
+    Eq. 9, in the reading the C oracle also takes) from per-sample O_k(x) and G(x), with LAPACK's
+    eigen-decomposition, so that the C oracle's Jacobi-based form can be checked against it.
 Basis convention: configuration index x, bit i of x set <=> sigma_i = +1 (spin up).
 Only tests and the benchmark's CPU-baseline leg import this module.
 """
@@ -424,3 +427,38 @@ def rbm_psi(n, nh):
         g = b[None, :] + s @ w
         return np.exp(s @ a) * np.prod(2 * np.cosh(g), axis=1)
     return f
+
+
+# ------------------------------------------------------------------ SNR-regularised solve
+def snr_solve(O, G, eps, tau, weights=None, cut=1e-14, hermitian=None):
+    """delta of the SNR-filtered solve of (S + eps I) delta = D from per-sample log-derivatives
+    O [ns, M] and G(x) = -i dt E_eff(x) + sum_n B^n(x) dW_n [ns] (weights: normalised
+    |psi|^2 weights in place of the sample mean).  The filter (text after Eq. 9, with the form
+    of the scheme the paper cites): with S + eps I = V diag(lam) V^H,
+      rho = V^H D,  u_k(x) = sum_l V_lk (O_l(x) - <O_l>),  q_k(x) = conj(u_k(x)) (G(x) - <G>),
+      SNR_k = |rho_k| sqrt(ns) / sqrt(<|q_k|^2> - |rho_k|^2)   (<q_k> = rho_k),
+      delta = sum_k V_k rho_k / lam_k / (1 + (tau / SNR_k)^6),  lam_k <= cut * lam_max dropped.
+    Real O (the Jastrow ansaetze) gives a real symmetric S.  Returns (delta, lam, snr, S, D), the
+    eigenvalues ascending."""
+    O = np.asarray(O)
+    G = np.asarray(G, dtype=np.complex128)
+    ns, m = O.shape
+    if hermitian is None:
+        hermitian = np.iscomplexobj(O) and np.abs(O.imag).max() > 0
+    if not hermitian:
+        O = O.real.astype(np.float64)
+    w = np.full(ns, 1.0 / ns) if weights is None else np.asarray(weights, np.float64) / np.sum(weights)
+    Oc = O - w @ O
+    Gc = G - w @ G
+    S = (Oc.conj() * w[:, None]).T @ Oc
+    D = (Oc.conj() * w[:, None]).T @ Gc
+    lam, V = np.linalg.eigh(S + eps * np.eye(m))
+    rho = V.conj().T @ D
+    u = Oc @ V
+    q = u.conj() * Gc[:, None]
+    var = w @ np.abs(q) ** 2 - np.abs(rho) ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        snr = np.where(var > 0, np.abs(rho) * np.sqrt(ns) / np.sqrt(np.maximum(var, 1e-300)), np.inf)
+        keep = np.where((lam > cut * lam.max()) & (np.abs(rho) > 0), 1.0 / (1.0 + (tau / snr) ** 6), 0.0)
+    delta = V @ (keep * rho / lam)
+    return delta, lam, snr, S, D

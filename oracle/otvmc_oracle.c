@@ -10,10 +10,11 @@
  *   it, (10) LITF Hamiltonian, (11) RBM, (12) Jastrow, the LJPHd ansatz of the LITF section,
  *   App. B (linear SSE), App. C (SDE solvers).
  *
- * Parity unpinned: the functional form of the SNR regulariser (snr_solve, snr_solve_herm).
- * The paper names the scheme and its threshold but takes the form from a reference it does not
- * reproduce; the form used here is stated where it is defined, and the tests pin its limits
- * (tau = 0, tau -> infinity), a one-spin case and its scale invariance, not the form itself.
+ * Parity unpinned against the paper: the functional form of the SNR regulariser (snr_solve,
+ * snr_solve_herm).  The paper names the scheme and its threshold but takes the form from a
+ * reference it does not reproduce; the form used here is stated where it is defined.  The tests
+ * pin its arithmetic against an independent vectorised statement of the same form (oracle/exact.py),
+ * its limits (tau = 0, tau -> infinity), a one-spin case and its scale invariance, not the form.
  *
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may load this
  * library.  It shares no source with the GPU library; the two only meet in the seeded
@@ -90,6 +91,7 @@ typedef struct {           /* optional outputs of one evaluation (any pointer ma
     double *seconds;       /* [3] wall time of: sampling and local quantities; means, S, F, N^n, D; solve */
     double *dlognorm;      /* [1] linear SSE: increment of log Q over the step (App. B, norm SDE) */
     double *eig;           /* [M][2] SNR solve: eigenvalue of S + eps I and the SNR of D's component */
+    double *G;             /* [n_samples][2] G(x) = -i dt E_eff(x) + sum_n B^n(x) dW_n per sample */
 } orc_eval_out;
 
 /* ------------------------------------------------------------------ Philox4x32-10 */
@@ -803,6 +805,13 @@ int orc_eval(const orc_problem *pb, const orc_ansatz *an, const orc_config *cf, 
             for (int c = 0; c < nch; ++c) d += Nn[(size_t)c * m + k] * dw[c];
             D[k] = d;
         }
+        if (out && out->G && !cf->enumerate)
+            for (int x = 0; x < ns; ++x) {   /* G(x), whose covariance with O^* is D */
+                cplx g = -I * cf->dt * eeff[x];
+                for (int c = 0; c < nch; ++c) g += dw[c] * B[(size_t)c * ns + x];
+                out->G[2 * x] = creal(g);
+                out->G[2 * x + 1] = cimag(g);
+            }
         if (out) {
             for (int k = 0; k < m; ++k) {
                 if (out->F) { out->F[2 * k] = creal(F[k]); out->F[2 * k + 1] = cimag(F[k]); }

@@ -85,6 +85,68 @@ __device__ __forceinline__ int wave_sum_i(int v) {
 
 __device__ __forceinline__ double spin(uint64_t mask, int i) { return ((mask >> i) & 1ull) ? 1.0 : -1.0; }
 
+// A configuration of up to 64 W spins as W words: bit i % 64 of word i / 64 set <=> s_i = +1;
+// bits at and above N are zero.  Stored as W consecutive words per configuration.
+constexpr int MAX_WORDS = 2;   // N <= 128
+template <int W>
+struct Cfg {
+    uint64_t w[W];
+};
+template <int W>
+__device__ __forceinline__ Cfg<W> cfg_load(const uint64_t *p) {
+    Cfg<W> c;
+#pragma unroll
+    for (int q = 0; q < W; ++q) c.w[q] = p[q];
+    return c;
+}
+template <int W>
+__device__ __forceinline__ void cfg_store(uint64_t *p, const Cfg<W> &c) {
+#pragma unroll
+    for (int q = 0; q < W; ++q) p[q] = c.w[q];
+}
+template <int W>
+__device__ __forceinline__ bool cfg_up(const Cfg<W> &c, int i) {
+    if constexpr (W == 1) return (c.w[0] >> i) & 1ull;
+    else return (c.w[i >> 6] >> (i & 63)) & 1ull;
+}
+template <int W>
+__device__ __forceinline__ double spin(const Cfg<W> &c, int i) { return cfg_up(c, i) ? 1.0 : -1.0; }
+template <int W>
+__device__ __forceinline__ void cfg_flip(Cfg<W> &c, int i) {
+    if constexpr (W == 1) c.w[0] ^= 1ull << i;
+    else c.w[i >> 6] ^= 1ull << (i & 63);
+}
+// number of sites where two configurations differ
+template <int W>
+__device__ __forceinline__ int cfg_diff(const Cfg<W> &x, const Cfg<W> &y) {
+    int d = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) d += __popcll(x.w[q] ^ y.w[q]);
+    return d;
+}
+// word q of the configuration shifted down by p sites (site j + p moves to site j), 0 < p < 64 W
+template <int W>
+__device__ __forceinline__ uint64_t cfg_shr_word(const Cfg<W> &c, int p, int q) {
+    const int ws = p >> 6, bs = p & 63;
+    const uint64_t lo = q + ws < W ? c.w[q + ws] : 0ull;
+    const uint64_t hi = q + ws + 1 < W ? c.w[q + ws + 1] : 0ull;
+    return bs ? ((lo >> bs) | (hi << (64 - bs))) : lo;
+}
+// sum over j of s_j s_{j+p}, j = 0 .. n-p-1: pairs that agree minus pairs that differ
+template <int W>
+__device__ __forceinline__ int cfg_dist_sum(const Cfg<W> &c, int p, int n) {
+    const int len = n - p;
+    int diff = 0;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        const int bits = len - 64 * q;
+        if (bits <= 0) break;
+        const uint64_t low = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
+        diff += __popcll((c.w[q] ^ cfg_shr_word(c, p, q)) & low);
+    }
+    return len - 2 * diff;
+}
+
 // Jastrow pair index of eta_{jk} (j < k) after the N one-body parameters.
 __host__ __device__ __forceinline__ int pair_index(int n, int j, int k) {
     return n + j * n - j * (j + 1) / 2 + (k - j - 1);
@@ -102,10 +164,21 @@ __device__ __forceinline__ int o_int(uint64_t mk, int p, int q, int n) {
     const uint64_t par = (q < 0) ? (((mk >> p) & 1ull) ^ 1ull) : (((mk >> p) ^ (mk >> q)) & 1ull);
     return par ? -1 : 1;   // par = 1 <=> O = -1
 }
+template <bool DIST = true, int W>
+__device__ __forceinline__ int o_int(const Cfg<W> &c, int p, int q, int n) {
+    if constexpr (W == 1) {
+        return o_int<DIST>(c.w[0], p, q, n);
+    } else {
+        if (DIST && q == -2) return cfg_dist_sum(c, p, n);
+        const bool par = (q < 0) ? !cfg_up(c, p) : (cfg_up(c, p) != cfg_up(c, q));
+        return par ? -1 : 1;
+    }
+}
 
 // Everything a kernel may touch, as raw device pointers into the caller's workspace.
 struct Dev {
     int n, m, nch, ns, nc, per, nt, nobs;
+    int nw;                   // 64-bit words per configuration (1 for N <= 64, 2 for N <= 128)
     int kind, nh;             // ansatz (0 Jastrow, 1 RBM), hidden units
     int mp;                   // M rounded up to 128 (rows of the RBM's BF16 operand planes)
     int ss;                   // 1: the solve runs in sample space (S holds T = O_c O_c^H / N_s)
@@ -127,8 +200,8 @@ struct Dev {
     double2 *theta, *theta_eval, *d0, *d1;   // [T][M]
     double *eta_re, *eta_im;  // [T][N*N] dense symmetric pair parameters of the evaluation point
     double2 *epair;           // [T][2][N*N] exp(+-4 eta_jk) for two-flip ratios
-    uint64_t *chains;         // [T][C]
-    uint64_t *samples;        // [T][Ns]
+    uint64_t *chains;         // [T][C][nw]
+    uint64_t *samples;        // [T][Ns][nw]
     uint32_t *sbits;          // [T][N][Ns/32] site-major bit planes of the samples
     double2 *R;               // [T][Ns][N] single-flip ratios psi(s^(i))/psi(s)
     double2 *eloc;            // [T][Ns] local energy of H

@@ -15,15 +15,17 @@
 
 namespace tvmc {
 
-__device__ __forceinline__ double2 jump_local(int kind, int site, double sq, uint64_t mask, const double2 *Rrow) {
-    const bool up = (mask >> site) & 1ull;
+template <int W>
+__device__ __forceinline__ double2 jump_local(int kind, int site, double sq, const Cfg<W> &mask, const double2 *Rrow) {
+    const bool up = cfg_up(mask, site);
     if (kind == 0) return up ? make_double2(0.0, 0.0) : make_double2(sq * Rrow[site].x, sq * Rrow[site].y);
     if (kind == 1) return up ? make_double2(sq * Rrow[site].x, sq * Rrow[site].y) : make_double2(0.0, 0.0);
     return make_double2(sq * (up ? 1.0 : -1.0), 0.0);
 }
 
-__device__ __forceinline__ double jump_ll(int kind, int site, double g, uint64_t mask) {
-    const bool up = (mask >> site) & 1ull;
+template <int W>
+__device__ __forceinline__ double jump_ll(int kind, int site, double g, const Cfg<W> &mask) {
+    const bool up = cfg_up(mask, site);
     if (kind == 0) return up ? g : 0.0;
     if (kind == 1) return up ? 0.0 : g;
     return g + g;
@@ -32,11 +34,12 @@ __device__ __forceinline__ double jump_ll(int kind, int site, double g, uint64_t
 // <B^n> per channel.  A workgroup takes CM_CH channels of one trajectory; each thread sums a
 // strided subset of the samples, then the block reduces in a fixed order (reproducible).
 constexpr int CM_CH = 8;
+template <int W>
 __global__ __launch_bounds__(256) void k_channel_means(Dev a) {
     __shared__ double red[4][2 * CM_CH];
     const int t = blockIdx.y, c0 = blockIdx.x * CM_CH;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint64_t *smp = a.samples + (size_t)t * a.ns;
+    const uint64_t *smp = a.samples + (size_t)t * a.ns * W;
     const double2 *R = a.R + (size_t)t * a.ns * a.n;
     int kind[CM_CH], st[CM_CH];
     double sq[CM_CH], re[CM_CH], im[CM_CH];
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(256) void k_channel_means(Dev a) {
         re[q] = im[q] = 0.0;
     }
     for (int s = threadIdx.x; s < a.ns; s += blockDim.x) {
-        const uint64_t mk = smp[s];
+        const Cfg<W> mk = cfg_load<W>(smp + (size_t)s * W);
         const double2 *Rrow = R + (size_t)s * a.n;
         for (int q = 0; q < CM_CH; ++q) {
             const double2 b = jump_local(kind[q], st[q], sq[q], mk, Rrow);
@@ -74,6 +77,7 @@ __global__ __launch_bounds__(256) void k_channel_means(Dev a) {
 }
 
 // G(x) per sample.
+template <int W>
 __global__ __launch_bounds__(256) void k_build_G(Dev a) {
     __shared__ int skind[256], ssite[256];
     __shared__ double srate[256], ssq[256], sdw[256], sc[256];
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(256) void k_build_G(Dev a) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= a.ns) return;
     const size_t sidx = (size_t)t * a.ns + s;
-    const uint64_t mask = a.samples[sidx];
+    const Cfg<W> mask = cfg_load<W>(a.samples + sidx * W);
     const double2 *Rrow = a.R + sidx * a.n;
     double dre = 0.0, dim = 0.0, ll = 0.0, nre = 0.0, nim = 0.0;
     for (int ch = 0; ch < a.nch; ++ch) {
@@ -133,18 +137,18 @@ __global__ __launch_bounds__(256) void k_gbar(Dev a) {
 // <O_k> and D_k = <O_k G> - <O_k><G> for the Jastrow ansaetze (O_k = s_i, s_j s_k, or an
 // LJPHd distance sum when DIST: real integers; o G is exact for o = +-1, so the sums are the
 // same for either instance).
-template <bool DIST>
+template <bool DIST, int W>
 __global__ __launch_bounds__(256) void k_obar_D(Dev a) {
     const int t = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.m) return;
     const int p = a.pa[k], q = a.pb[k];
-    const uint64_t *smp = a.samples + (size_t)t * a.ns;
+    const uint64_t *smp = a.samples + (size_t)t * a.ns * W;
     const double2 *G = a.G + (size_t)t * a.ns;
     int64_t cnt = 0;
     double re = 0.0, im = 0.0;
     for (int s = 0; s < a.ns; ++s) {
-        const int o = o_int<DIST>(smp[s], p, q, a.n);
+        const int o = o_int<DIST>(cfg_load<W>(smp + (size_t)s * W), p, q, a.n);
         const double2 g = G[s];
         const double od = (double)o;
         cnt += o;

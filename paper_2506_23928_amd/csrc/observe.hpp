@@ -46,8 +46,10 @@ __global__ void k_prepare_pairs(Dev a) {
     a.epair[(size_t)t * 2 * nn + nn + idx] = make_double2(em * cs, -em * sn);
 }
 
-// One wavefront per sample, lane a = site a; per-block partial sums of the 9 moments.
+// One wavefront per sample, lane a = site a (and a + 64 for two-word configurations);
+// per-block partial sums of the 9 moments.
 constexpr int MOM_WAVES = 4;
+template <int W>
 __global__ __launch_bounds__(64 * MOM_WAVES) void k_moments(Dev a) {
     __shared__ double part[MOM_WAVES][9];
     const int t = blockIdx.y;
@@ -58,29 +60,40 @@ __global__ __launch_bounds__(64 * MOM_WAVES) void k_moments(Dev a) {
     const double2 *ep = a.epair + (size_t)t * 2 * nn;
     for (int s = blockIdx.x * MOM_WAVES + w; s < a.ns; s += gridDim.x * MOM_WAVES) {
         const size_t sidx = (size_t)t * a.ns + s;
-        const uint64_t mk = a.samples[sidx];
-        const bool act = lane < n;
-        const double sa = spin(mk, lane);
-        const double2 Ra = act ? a.R[sidx * n + lane] : make_double2(0.0, 0.0);
+        const Cfg<W> mk = cfg_load<W>(a.samples + sidx * W);
+        double sa[W];
+        double2 Ra[W];
+        bool act[W];
         double v[9] = {};
-        if (act) {
-            v[0] = Ra.x;
-            v[1] = sa * Ra.y;
-            v[2] = sa;
+        for (int q = 0; q < W; ++q) {
+            const int ai = lane + 64 * q;
+            act[q] = ai < n;
+            sa[q] = spin(mk, ai < n ? ai : 0);
+            Ra[q] = act[q] ? a.R[sidx * n + ai] : make_double2(0.0, 0.0);
+            if (act[q]) {
+                v[0] += Ra[q].x;
+                v[1] += sa[q] * Ra[q].y;
+                v[2] += sa[q];
+            }
         }
         for (int b = 0; b < n; ++b) {
-            const double rbx = readlane_d(Ra.x, b), rby = readlane_d(Ra.y, b);
-            if (!act || b == lane) continue;
-            const double sb = spin(mk, b), ss = sa * sb;
-            const double2 e = ep[(ss > 0.0 ? 0 : nn) + b * n + lane];
-            const double px = Ra.x * rbx - Ra.y * rby, py = Ra.x * rby + Ra.y * rbx;
-            const double rx = px * e.x - py * e.y, ry = px * e.y + py * e.x;
-            v[3] += rx;
-            v[4] += -ss * rx;
-            v[5] += ss;
-            v[6] += sb * ry;
-            v[7] += sb * Ra.x;
-            v[8] += ss * Ra.y;
+            const int bq = W == 1 ? 0 : (b >> 6);
+            const double rbx = readlane_d(Ra[bq].x, b & 63), rby = readlane_d(Ra[bq].y, b & 63);
+            const double sb = spin(mk, b);
+            for (int q = 0; q < W; ++q) {
+                const int ai = lane + 64 * q;
+                if (!act[q] || b == ai) continue;
+                const double ss = sa[q] * sb;
+                const double2 e = ep[(ss > 0.0 ? 0 : nn) + b * n + ai];
+                const double px = Ra[q].x * rbx - Ra[q].y * rby, py = Ra[q].x * rby + Ra[q].y * rbx;
+                const double rx = px * e.x - py * e.y, ry = px * e.y + py * e.x;
+                v[3] += rx;
+                v[4] += -ss * rx;
+                v[5] += ss;
+                v[6] += sb * ry;
+                v[7] += sb * Ra[q].x;
+                v[8] += ss * Ra[q].y;
+            }
         }
         for (int q = 0; q < 9; ++q) v[q] = wave_sum(v[q]);
         acc[0] += v[0] / N;
@@ -120,16 +133,23 @@ __global__ void k_moments_reduce(Dev a, int slot) {
 
 // Trajectory average (Eq. 3) -> M, C, xi^2 = N lambda_min(C restricted to the plane
 // orthogonal to M) / |M|^2.  Linear SSE: each trajectory's moments weighted by its Q (App. B),
-// still divided by N_T.
-__global__ void k_ensemble(Dev a) {
+// still divided by N_T.  slot < 0: the last moments; otherwise history record `slot`.  Block b
+// of the launch leaves out trajectory b - 1 (block 0 leaves out none) and writes its 13 values
+// to out[16 b ..]: the leave-one-out ensembles of a jackknife over the trajectories.
+__global__ void k_ensemble(Dev a, int slot, double *out) {
     __shared__ double avg[9];
+    const int skip = (int)blockIdx.x - 1;
+    const double *mom = slot < 0 ? a.mom : a.hist + (size_t)slot * a.nt * 9;
+    const double *lq = slot < 0 ? a.momlq : a.qhist + (size_t)slot * a.nt;
+    const int cnt = skip < 0 ? a.nt : a.nt - 1;
     if (threadIdx.x < 9) {
         double s = 0.0;
         for (int t = 0; t < a.nt; ++t) {
-            const double v = a.mom[(size_t)t * 9 + threadIdx.x];
-            s += a.linear ? v * exp(a.momlq[t]) : v;
+            if (t == skip) continue;
+            const double v = mom[(size_t)t * 9 + threadIdx.x];
+            s += a.linear ? v * exp(lq[t]) : v;
         }
-        avg[threadIdx.x] = s / (double)a.nt;
+        avg[threadIdx.x] = s / (double)cnt;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -161,10 +181,11 @@ __global__ void k_ensemble(Dev a) {
             c12 += e1[i] * C[i][j] * e2[j];
         }
     const double lmin = 0.5 * (c11 + c22) - sqrt(0.25 * (c11 - c22) * (c11 - c22) + c12 * c12);
-    for (int i = 0; i < 3; ++i) a.ens[i] = M[i];
+    double *o = out + 16 * (size_t)blockIdx.x;
+    for (int i = 0; i < 3; ++i) o[i] = M[i];
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) a.ens[3 + 3 * i + j] = C[i][j];
-    a.ens[12] = (double)a.n * lmin / (nm * nm);
+        for (int j = 0; j < 3; ++j) o[3 + 3 * i + j] = C[i][j];
+    o[12] = (double)a.n * lmin / (nm * nm);
 }
 
 }  // namespace tvmc

@@ -62,8 +62,11 @@ __global__ void k_prepare_rbm(Dev a, const double2 *__restrict__ src) {
 
 // W_LDS: the weights fit in LDS (N N' <= 4096) and are read from there; a template flag, so
 // that every weight read compiles to an LDS or a global instruction rather than a generic one.
-template <int CPB, int QH, bool AR, bool W_LDS>
+// W: 64-bit words per configuration (W = 2: lane l owns the visible sites l and l + 64 for the
+// single-flip factors and the recorded ratios; no learned proposal).
+template <int CPB, int QH, bool AR, bool W_LDS, int W = 1>
 __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int stage, int burn) {
+    static_assert(!AR || W == 1, "the learned proposal works on one configuration word");
     const int step = a.dstep[0];
     __shared__ double lwr[W_LDS ? 64 * 64 : 1];
     __shared__ double lwi[W_LDS ? 64 * 64 : 1];
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int stage, int b
     const double *wr = W_LDS ? lwr : gwr;
     const double *wi = W_LDS ? lwi : gwi;
     const double2 *th = a.theta_eval + (size_t)t * a.m;
-    uint64_t mask = a.chains[(size_t)t * a.nc + c];
+    Cfg<W> mask = cfg_load<W>(a.chains + ((size_t)t * a.nc + c) * W);
 
     // per hidden unit j (lane j, j + 64, ...): theta_j = b_j + sum_i w_ij s_i (updated in place)
     // and t_j = tanh theta_j
@@ -116,11 +119,14 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int stage, int b
             ti[q] = tj.y;
         }
     }
-    // lane l: |exp(a_l (s'_l - s_l))|^2 for s_l = +1 (ev_dn) and s_l = -1 (ev_up)
-    double ev_dn = 1.0, ev_up = 1.0;
-    if (lane < n) {
-        ev_dn = exp(-4.0 * th[lane].x);
-        ev_up = exp(4.0 * th[lane].x);
+    // lane l, site l + 64 q: |exp(a (s' - s))|^2 for s = +1 (ev_dn) and s = -1 (ev_up)
+    double ev_dn[W], ev_up[W];
+    for (int q = 0; q < W; ++q) {
+        ev_dn[q] = ev_up[q] = 1.0;
+        if (lane + 64 * q < n) {
+            ev_dn[q] = exp(-4.0 * th[lane + 64 * q].x);
+            ev_up[q] = exp(4.0 * th[lane + 64 * q].x);
+        }
     }
 
     const uint32_t ctr1 = ((uint32_t)stage << 31) | (uint32_t)c;
@@ -163,7 +169,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int stage, int b
             if (AR && base + jj == next_ar) {
                 next_ar += n;
                 if (!lq_valid) {
-                    lq_cur = ar_logq(a, net, mask, lane);
+                    lq_cur = ar_logq(a, net, mask.w[0], lane);
                     lq_valid = true;
                 }
                 float lqn;
@@ -191,7 +197,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int stage, int b
                 if (lane < n) dsum += th[lane].x * (spin(mnew, lane) - spin(mask, lane));
                 const double dlog = 2.0 * wave_sum(dsum) + ((double)lq_cur - (double)lqn);
                 if (log(uacc) < dlog) {
-                    mask = mnew;
+                    mask.w[0] = mnew;
                     for (int q = 0; q < QH; ++q) {
                         const int j = lane + 64 * q;
                         gre[q] = ngr[q];
@@ -245,9 +251,10 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int stage, int b
             pm = wave_prod(pm);
             pe = wave_sum_i(pe);
             int ev;
-            const double mv = frexp(si > 0.0 ? readlane_d(ev_dn, i) : readlane_d(ev_up, i), &ev);
+            const int iq = W == 1 ? 0 : (i >> 6);
+            const double mv = frexp(si > 0.0 ? readlane_d(ev_dn[iq], i & 63) : readlane_d(ev_up[iq], i & 63), &ev);
             if (u < ldexp(pm * mv, pe + ev)) {
-                mask ^= (1ull << i);
+                cfg_flip(mask, i);
                 for (int q = 0; q < QH; ++q) {
                     const int j = lane + 64 * q;
                     if (j < nh) {
@@ -279,14 +286,16 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int stage, int b
                     }
                 }
                 double ere = 0.0, eim = 0.0;
-                if (lane < n) {
-                    const double sl = spin(mask, lane);
+                for (int q = 0; q < W; ++q) {
+                    const int site = lane + 64 * q;
+                    if (site >= n) continue;
+                    const double sl = spin(mask, site);
                     // prod_j (cosh 2w_lj - s_l t_j sinh 2w_lj), rescaled by a power of two every
                     // 16 factors (exponents summed in pe)
                     double pr = 1.0, pi = 0.0;
                     int pe = 0;
                     for (int j = 0; j < nh; ++j) {
-                        const double2 ch = cT[(size_t)j * n + lane], sh = sT[(size_t)j * n + lane];
+                        const double2 ch = cT[(size_t)j * n + site], sh = sT[(size_t)j * n + site];
                         const double2 ts = cmul(tl[w][j], sh);
                         const double fr = ch.x - sl * ts.x, fi = ch.y - sl * ts.y;
                         const double nr = pr * fr - pi * fi, ni = pr * fi + pi * fr;
@@ -300,36 +309,37 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_rbm(Dev a, int stage, int b
                             pe += e;
                         }
                     }
-                    const double er = -2.0 * sl * th[lane].x, ei = -2.0 * sl * th[lane].y;
+                    const double er = -2.0 * sl * th[site].x, ei = -2.0 * sl * th[site].y;
                     const double ex = exp(er);
                     double sn, cs;
                     sincos(ei, &sn, &cs);
                     const double2 Rm = cmul(make_double2(pr, pi), make_double2(ex * cs, ex * sn));
                     const double2 R = make_double2(ldexp(Rm.x, pe), ldexp(Rm.y, pe));
-                    a.R[sidx * n + lane] = R;
+                    a.R[sidx * n + site] = R;
                     double hj = 0.0;
-                    for (int k = 0; k < n; ++k) hj += a.J[t * a.j_stride + k * n + lane] * spin(mask, k);
-                    ere = 0.5 * sl * hj + a.hx * R.x;
-                    eim = a.hx * R.y;
+                    for (int k = 0; k < n; ++k) hj += a.J[t * a.j_stride + k * n + site] * spin(mask, k);
+                    ere += 0.5 * sl * hj + a.hx * R.x;
+                    eim += a.hx * R.y;
                 }
                 ere = wave_sum(ere);
                 eim = wave_sum(eim);
                 if (lane == 0) {
-                    a.samples[sidx] = mask;
+                    cfg_store(a.samples + sidx * W, mask);
                     a.eloc[sidx] = make_double2(ere, eim);
                 }
             }
         }
     }
     if (lane == 0) {
-        a.chains[(size_t)t * a.nc + c] = mask;
+        cfg_store(a.chains + ((size_t)t * a.nc + c) * W, mask);
         a.acc[(size_t)t * a.nc + c] = nacc;
         if (AR) a.aracc[(size_t)t * a.nc + c] = ar_nacc;
     }
 }
 
 // O_k of sample s (complex): one-body s_i, hidden tanh g_j, weights s_i tanh g_j
-__device__ __forceinline__ double2 rbm_o(const Dev &a, int k, uint64_t mk, const double2 *tts) {
+template <typename C>
+__device__ __forceinline__ double2 rbm_o(const Dev &a, int k, const C &mk, const double2 *tts) {
     if (k < a.n) return make_double2(spin(mk, k), 0.0);
     if (k < a.n + a.nh) return tts[k - a.n];
     const int idx = k - a.n - a.nh, i = idx / a.nh, j = idx % a.nh;
@@ -344,6 +354,7 @@ __device__ __forceinline__ double2 rbm_o(const Dev &a, int k, uint64_t mk, const
 // added in wave order.  Weight rows k_c with the same hidden unit j (all 8 of them when N'
 // divides 64 and the weights start on a multiple of 64) share one load of tanh g_j per sample.
 constexpr int OD_R = 8;
+template <int W>
 __global__ __launch_bounds__(256) void k_obar_D_rbm(Dev a) {
     __shared__ double part[4][OD_R][4][64];
     const int t = blockIdx.y, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -361,12 +372,12 @@ __global__ __launch_bounds__(256) void k_obar_D_rbm(Dev a) {
     }
     double acc[OD_R][4];
     for (int c = 0; c < OD_R; ++c) acc[c][0] = acc[c][1] = acc[c][2] = acc[c][3] = 0.0;
-    const uint64_t *smp = a.samples + (size_t)t * a.ns;
+    const uint64_t *smp = a.samples + (size_t)t * a.ns * W;
     const double2 *G = a.G + (size_t)t * a.ns;
     const double2 *tt = a.tt + (size_t)t * a.ns * nh;
     const int q = (a.ns + 3) / 4, s1 = min(a.ns, (w + 1) * q);
     for (int s = w * q; s < s1; ++s) {
-        const uint64_t mk = smp[s];
+        const Cfg<W> mk = cfg_load<W>(smp + (size_t)s * W);
         const double2 g = G[s];
         const double2 *tts = tt + (size_t)s * nh;
         const double2 tv = jl >= 0 ? tts[jl] : make_double2(0.0, 0.0);
@@ -409,8 +420,9 @@ __global__ __launch_bounds__(256) void k_obar_D_rbm(Dev a) {
 // a time (configuration word and tanh g row) through LDS.
 constexpr int RB_T = 32;
 constexpr int RB_S = 8;
+template <int W>
 __global__ __launch_bounds__(256) void k_sbuild_rbm_f64(Dev a) {
-    __shared__ uint64_t smask[RB_S];
+    __shared__ Cfg<W> smask[RB_S];
     __shared__ double2 stt[RB_S][256];
     const int t = blockIdx.y;
     const int tile = blockIdx.x;
@@ -421,12 +433,12 @@ __global__ __launch_bounds__(256) void k_sbuild_rbm_f64(Dev a) {
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int m = a.m, nh = a.nh;
     double2 acc[2][2] = {};
-    const uint64_t *smp = a.samples + (size_t)t * a.ns;
+    const uint64_t *smp = a.samples + (size_t)t * a.ns * W;
     const double2 *tt = a.tt + (size_t)t * a.ns * nh;
     for (int s0 = 0; s0 < a.ns; s0 += RB_S) {
         const int cnt = (a.ns - s0) < RB_S ? (a.ns - s0) : RB_S;
         __syncthreads();
-        if (threadIdx.x < cnt) smask[threadIdx.x] = smp[s0 + threadIdx.x];
+        if (threadIdx.x < cnt) smask[threadIdx.x] = cfg_load<W>(smp + (size_t)(s0 + threadIdx.x) * W);
         for (int e = threadIdx.x; e < cnt * nh; e += blockDim.x) stt[e / nh][e % nh] = tt[(size_t)(s0 + e / nh) * nh + e % nh];
         __syncthreads();
         for (int s = 0; s < cnt; ++s) {
@@ -587,6 +599,7 @@ __global__ __launch_bounds__(64 * RMF_WAVES) void k_moments_rbm_f(Dev a) {
 // Moments for the RBM, direct form: two-flip ratios psi(s^(ab))/psi(s) = exp(-2 s_a a_a - 2 s_b a_b)
 // prod_j [cosh(u+v) - tanh(g_j) sinh(u+v)],  u = 2 s_a w_aj, v = 2 s_b w_bj.
 constexpr int RMOM_WAVES = 4;
+template <int W>
 __global__ __launch_bounds__(64 * RMOM_WAVES) void k_moments_rbm(Dev a) {
     __shared__ double part[RMOM_WAVES][9];
     __shared__ double2 tl[RMOM_WAVES][256];
@@ -599,51 +612,55 @@ __global__ __launch_bounds__(64 * RMOM_WAVES) void k_moments_rbm(Dev a) {
     const double2 *th = a.theta_eval + (size_t)t * a.m;
     for (int s = blockIdx.x * RMOM_WAVES + w; s < a.ns; s += gridDim.x * RMOM_WAVES) {
         const size_t sidx = (size_t)t * a.ns + s;
-        const uint64_t mk = a.samples[sidx];
+        const Cfg<W> mk = cfg_load<W>(a.samples + sidx * W);
         for (int j = lane; j < nh; j += 64) tl[w][j] = a.tt[sidx * nh + j];
-        const bool act = lane < n;
-        const double sa = spin(mk, lane);
-        const double2 Ra = act ? a.R[sidx * n + lane] : make_double2(0.0, 0.0);
         double v[9] = {};
-        if (act) {
-            v[0] = Ra.x;
-            v[1] = sa * Ra.y;
-            v[2] = sa;
-        }
-        for (int b = 0; b < n; ++b) {
-            if (!act || b == lane) continue;
-            const double sb = spin(mk, b), ss = sa * sb;
-            double pr = 1.0, pi = 0.0, lsum = 0.0;
-            for (int j = 0; j < nh; ++j) {
-                const double2 ca = cT[(size_t)j * n + lane], sa_ = sT[(size_t)j * n + lane];
-                const double2 cb = cT[(size_t)j * n + b], sb_ = sT[(size_t)j * n + b];
-                const double2 cc = cmul(ca, cb), s2 = cmul(sa_, cb), s3 = cmul(ca, sb_), s4 = cmul(sa_, sb_);
-                const double2 chu = make_double2(cc.x + ss * s4.x, cc.y + ss * s4.y);
-                const double2 shu = make_double2(sa * s2.x + sb * s3.x, sa * s2.y + sb * s3.y);
-                const double2 tsh = cmul(tl[w][j], shu);
-                const double fr = chu.x - tsh.x, fi = chu.y - tsh.y;
-                const double nr = pr * fr - pi * fi, ni = pr * fi + pi * fr;
-                pr = nr;
-                pi = ni;
-                if ((j & 15) == 15) {
-                    const double mg = sqrt(pr * pr + pi * pi);
-                    lsum += log(mg);
-                    pr /= mg;
-                    pi /= mg;
-                }
+        // lane l takes the sites a = l + 64 q
+        for (int q = 0; q < W; ++q) {
+            const int sa_i = lane + 64 * q;
+            const bool act = sa_i < n;
+            const double sa = act ? spin(mk, sa_i) : 1.0;
+            const double2 Ra = act ? a.R[sidx * n + sa_i] : make_double2(0.0, 0.0);
+            if (act) {
+                v[0] += Ra.x;
+                v[1] += sa * Ra.y;
+                v[2] += sa;
             }
-            const double er = lsum - 2.0 * sa * th[lane].x - 2.0 * sb * th[b].x;
-            const double ei = -2.0 * sa * th[lane].y - 2.0 * sb * th[b].y;
-            const double ex = exp(er);
-            double sn, cs;
-            sincos(ei, &sn, &cs);
-            const double2 Rab = cmul(make_double2(pr, pi), make_double2(ex * cs, ex * sn));
-            v[3] += Rab.x;
-            v[4] += -ss * Rab.x;
-            v[5] += ss;
-            v[6] += sb * Rab.y;
-            v[7] += sb * Ra.x;
-            v[8] += ss * Ra.y;
+            for (int b = 0; b < n; ++b) {
+                if (!act || b == sa_i) continue;
+                const double sb = spin(mk, b), ss = sa * sb;
+                double pr = 1.0, pi = 0.0, lsum = 0.0;
+                for (int j = 0; j < nh; ++j) {
+                    const double2 ca = cT[(size_t)j * n + sa_i], sa_ = sT[(size_t)j * n + sa_i];
+                    const double2 cb = cT[(size_t)j * n + b], sb_ = sT[(size_t)j * n + b];
+                    const double2 cc = cmul(ca, cb), s2 = cmul(sa_, cb), s3 = cmul(ca, sb_), s4 = cmul(sa_, sb_);
+                    const double2 chu = make_double2(cc.x + ss * s4.x, cc.y + ss * s4.y);
+                    const double2 shu = make_double2(sa * s2.x + sb * s3.x, sa * s2.y + sb * s3.y);
+                    const double2 tsh = cmul(tl[w][j], shu);
+                    const double fr = chu.x - tsh.x, fi = chu.y - tsh.y;
+                    const double nr = pr * fr - pi * fi, ni = pr * fi + pi * fr;
+                    pr = nr;
+                    pi = ni;
+                    if ((j & 15) == 15) {
+                        const double mg = sqrt(pr * pr + pi * pi);
+                        lsum += log(mg);
+                        pr /= mg;
+                        pi /= mg;
+                    }
+                }
+                const double er = lsum - 2.0 * sa * th[sa_i].x - 2.0 * sb * th[b].x;
+                const double ei = -2.0 * sa * th[sa_i].y - 2.0 * sb * th[b].y;
+                const double ex = exp(er);
+                double sn, cs;
+                sincos(ei, &sn, &cs);
+                const double2 Rab = cmul(make_double2(pr, pi), make_double2(ex * cs, ex * sn));
+                v[3] += Rab.x;
+                v[4] += -ss * Rab.x;
+                v[5] += ss;
+                v[6] += sb * Rab.y;
+                v[7] += sb * Ra.x;
+                v[8] += ss * Ra.y;
+            }
         }
         for (int q = 0; q < 9; ++q) v[q] = wave_sum(v[q]);
         acc[0] += v[0] / N;

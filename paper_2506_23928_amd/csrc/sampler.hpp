@@ -1,8 +1,8 @@
 // Metropolis sampling of |psi_theta|^2 for the two-body Jastrow ansatz (Eq. 12) and the
 // local quantities the estimators need (text after Eq. 9; definitions after Eq. 8).
 //
-// One wavefront per Markov chain; lane i owns spin i (N <= 64).  The configuration lives in a
-// wave-uniform 64-bit mask.  Lane i keeps the complex field f_i = a_i + sum_{k!=i} eta_ik s_k,
+// One wavefront per Markov chain; lane i owns spin i (N <= 64; two spins per lane up to N = 128
+// in k_sample_jastrow_w2).  The configuration lives in a wave-uniform 64-bit mask.  Lane i keeps the complex field f_i = a_i + sum_{k!=i} eta_ik s_k,
 // so the flip log-ratio of site i is -2 s_i f_i (O(1)); an accepted flip of site i updates
 // every lane's field with one row of eta, read from LDS (the dense symmetric eta of the
 // trajectory, staged once per workgroup and shared by its CPB chains).  Random numbers for
@@ -38,11 +38,15 @@ __global__ void k_init_chains(Dev a) {
     const int t = blockIdx.y;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.nc) return;
+    // one block of 128 random bits: sites 0..63 from words 0, 1 and sites 64..127 from words 2, 3
     uint32_t r[4];
     philox4x32_10(0u, (uint32_t)c, 0u, (3u << 24) | (uint32_t)(a.traj0 + t), a.key0, a.key1, r);
-    uint64_t m = (uint64_t)r[0] | ((uint64_t)r[1] << 32);
-    if (a.n < 64) m &= (1ull << a.n) - 1ull;
-    a.chains[(size_t)t * a.nc + c] = m;
+    for (int q = 0; q < a.nw; ++q) {
+        uint64_t m = (uint64_t)r[2 * q] | ((uint64_t)r[2 * q + 1] << 32);
+        const int bits = a.n - 64 * q;
+        if (bits < 64) m &= (1ull << bits) - 1ull;
+        a.chains[((size_t)t * a.nc + c) * a.nw + q] = m;
+    }
 }
 
 // the step index read by the samplers and k_draw_dw
@@ -212,6 +216,109 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int stage, i
         a.chains[(size_t)t * a.nc + c] = mask;
         a.acc[(size_t)t * a.nc + c] = nacc;
         if (AR) a.aracc[(size_t)t * a.nc + c] = ar_nacc;
+    }
+}
+
+// The same chain for 64 < N <= 128 (two configuration words).  Lane l owns sites l and l + 64
+// and keeps their real fields only, which is all the accept test needs; the real eta plane
+// (N x N doubles, at most 128 KB) is staged in LDS.  The imaginary fields a recorded sample
+// needs for its flip ratios are summed afresh from the imaginary plane in global memory, in
+// the order a_i, then k = 0..N-1.  No learned proposal.
+template <int CPB>
+__global__ __launch_bounds__(64 * CPB) void k_sample_jastrow_w2(Dev a, int stage, int burn) {
+    const int step = a.dstep[0];
+    __shared__ double lre[128 * 128];
+    const int n = a.n;
+    const int t = blockIdx.y;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * CPB + w;
+    {
+        const double *er = a.eta_re + (size_t)t * n * n;
+        for (int i = threadIdx.x; i < n * n; i += blockDim.x) lre[i] = er[i];
+    }
+    __syncthreads();
+    const double *eim_g = a.eta_im + (size_t)t * n * n;
+    const double2 *th = a.theta_eval + (size_t)t * a.m;
+    Cfg<2> cfg = cfg_load<2>(a.chains + ((size_t)t * a.nc + c) * 2);
+
+    double fre[2] = {0.0, 0.0};
+    for (int q = 0; q < 2; ++q) {
+        const int site = lane + 64 * q;
+        if (site >= n) continue;
+        double f = th[site].x;
+        for (int k = 0; k < n; ++k) {
+            if (k == site) continue;
+            f += lre[k * n + site] * spin(cfg, k);
+        }
+        fre[q] = f;
+    }
+
+    const uint32_t ctr1 = ((uint32_t)stage << 31) | (uint32_t)c;
+    const uint32_t ctr3 = (1u << 24) | (uint32_t)(a.traj0 + t);
+    const int total = (burn + a.per * a.thin) * n;
+    const int rec_stride = a.thin * n;
+    int next_rec = burn * n + rec_stride - 1;
+    int rec = 0;
+    uint32_t nacc = 0;
+    const size_t tbase = (size_t)t * a.ns;
+
+    for (int base = 0; base < total; base += 64) {
+        uint32_t r[4];
+        philox4x32_10((uint32_t)(base + lane), ctr1, (uint32_t)step, ctr3, a.key0, a.key1, r);
+        const int site_l = (int)(((uint64_t)r[0] * (uint64_t)n) >> 32);
+        const double logu_l = log(u53(r[1], r[2]));
+        const int cnt = (total - base) < 64 ? (total - base) : 64;
+        for (int j = 0; j < cnt; ++j) {
+            const int i = __builtin_amdgcn_readlane(site_l, j);
+            const double lu = readlane_d(logu_l, j);
+            const double fi = readlane_d(i < 64 ? fre[0] : fre[1], i & 63);
+            const double si = spin(cfg, i);
+            const double dre = -2.0 * si * fi;
+            if (lu < 2.0 * dre) {
+                cfg_flip(cfg, i);
+                const double c2 = -2.0 * si;
+                for (int q = 0; q < 2; ++q) {
+                    const int site = lane + 64 * q;
+                    if (site < n) fre[q] += c2 * lre[i * n + site];
+                }
+                ++nacc;
+            }
+            if (base + j == next_rec) {
+                const size_t sidx = tbase + (size_t)c * a.per + rec;
+                ++rec;
+                next_rec += rec_stride;
+                double ere = 0.0, eim = 0.0;
+                for (int q = 0; q < 2; ++q) {
+                    const int site = lane + 64 * q;
+                    if (site >= n) continue;
+                    const double sl = spin(cfg, site);
+                    double fim = th[site].y, hj = 0.0;
+                    for (int k = 0; k < n; ++k) {
+                        const double sk = spin(cfg, k);
+                        if (k != site) fim += eim_g[k * n + site] * sk;
+                        hj += a.J[t * a.j_stride + k * n + site] * sk;
+                    }
+                    const double dr = -2.0 * sl * fre[q], di = -2.0 * sl * fim;
+                    const double ex = exp(dr);
+                    double sn, cs;
+                    sincos(di, &sn, &cs);
+                    const double2 R = make_double2(ex * cs, ex * sn);
+                    a.R[sidx * n + site] = R;
+                    ere += 0.5 * sl * hj + a.hx * R.x;
+                    eim += a.hx * R.y;
+                }
+                ere = wave_sum(ere);
+                eim = wave_sum(eim);
+                if (lane == 0) {
+                    cfg_store(a.samples + sidx * 2, cfg);
+                    a.eloc[sidx] = make_double2(ere, eim);
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        cfg_store(a.chains + ((size_t)t * a.nc + c) * 2, cfg);
+        a.acc[(size_t)t * a.nc + c] = nacc;
     }
 }
 

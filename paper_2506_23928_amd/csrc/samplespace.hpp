@@ -17,17 +17,19 @@
 
 namespace tvmc {
 
-__device__ __forceinline__ int spin_overlap(uint64_t x, uint64_t y, int n) {
-    return n - 2 * __popcll(x ^ y);   // bits above n are zero in both
+template <int W>
+__device__ __forceinline__ int spin_overlap(const uint64_t *x, const uint64_t *y, int n) {
+    return n - 2 * cfg_diff(cfg_load<W>(x), cfg_load<W>(y));   // bits at and above n are zero in both
 }
 
 // Jastrow K (real) into the S buffer, full matrix.  Grid (ceil(N_s/256), N_s, T).
+template <int W>
 __global__ __launch_bounds__(256) void k_tk_jastrow(Dev a) {
     const int t = blockIdx.z, x = blockIdx.y;
     const int y = blockIdx.x * 256 + threadIdx.x;
     if (y >= a.ns) return;
-    const uint64_t *smp = a.samples + (size_t)t * a.ns;
-    const double q = (double)spin_overlap(smp[x], smp[y], a.n);
+    const uint64_t *smp = a.samples + (size_t)t * a.ns * W;
+    const double q = (double)spin_overlap<W>(smp + (size_t)x * W, smp + (size_t)y * W, a.n);
     a.S[((size_t)t * a.ns + x) * a.ns + y] = q + 0.5 * (q * q - (double)a.n);
 }
 
@@ -35,6 +37,7 @@ __global__ __launch_bounds__(256) void k_tk_jastrow(Dev a) {
 // per thread, tanh rows staged 16 hidden units at a time through LDS.  Grid (tiles^2, T).
 constexpr int TK_T = 64;
 constexpr int TK_J = 16;
+template <int W>
 __global__ __launch_bounds__(256) void k_tk_rbm(Dev a) {
     __shared__ double2 tx[TK_T][TK_J + 1], ty[TK_T][TK_J + 1];
     const int t = blockIdx.y;
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(256) void k_tk_rbm(Dev a) {
                 }
         }
     }
-    const uint64_t *smp = a.samples + (size_t)t * a.ns;
+    const uint64_t *smp = a.samples + (size_t)t * a.ns * W;
     double2 *K = (double2 *)a.S + (size_t)t * a.ns * a.ns;
     for (int u = 0; u < 4; ++u) {
         const int x = x0 + ix + 16 * u;
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(256) void k_tk_rbm(Dev a) {
         for (int v = 0; v < 4; ++v) {
             const int y = y0 + iy + 16 * v;
             if (y >= a.ns) continue;
-            const double q1 = 1.0 + (double)spin_overlap(smp[x], smp[y], a.n);
+            const double q1 = 1.0 + (double)spin_overlap<W>(smp + (size_t)x * W, smp + (size_t)y * W, a.n);
             K[(size_t)x * a.ns + y] = make_double2(q1 * (1.0 + gr[u][v]) - 1.0, q1 * gi[u][v]);
         }
     }
@@ -156,18 +159,19 @@ __global__ __launch_bounds__(256) void k_tk_centre(Dev a) {
 }
 
 // delta_k = (1/N_s) [sum_x O_k(x)^* u_x - <O_k>^* sum_x u_x].  Grid (ceil(M/256), T).
+template <int W>
 __global__ __launch_bounds__(256) void k_pushback(Dev a, int which) {
     const int t = blockIdx.y;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.m) return;
-    const uint64_t *smp = a.samples + (size_t)t * a.ns;
+    const uint64_t *smp = a.samples + (size_t)t * a.ns * W;
     const double2 *u = a.ssu + (size_t)t * a.ns;
     double re = 0.0, im = 0.0, ur = 0.0, ui = 0.0;
     double2 ob;
     if (a.kind == 1) {
         const double2 *tt = a.tt + (size_t)t * a.ns * a.nh;
         for (int x = 0; x < a.ns; ++x) {
-            const double2 o = rbm_o(a, k, smp[x], tt + (size_t)x * a.nh);
+            const double2 o = rbm_o(a, k, cfg_load<W>(smp + (size_t)x * W), tt + (size_t)x * a.nh);
             const double2 v = u[x];
             re += o.x * v.x + o.y * v.y;   // conj(o) u
             im += o.x * v.y - o.y * v.x;
@@ -178,9 +182,8 @@ __global__ __launch_bounds__(256) void k_pushback(Dev a, int which) {
     } else {
         const int p = a.pa[k], q = a.pb[k];
         for (int x = 0; x < a.ns; ++x) {
-            const uint64_t mk = smp[x];
-            const uint64_t par = (q < 0) ? ((mk >> p) & 1ull) : (((mk >> p) ^ (mk >> q)) & 1ull);
-            const bool plus = (q < 0) ? (par == 1ull) : (par == 0ull);
+            const Cfg<W> mk = cfg_load<W>(smp + (size_t)x * W);
+            const bool plus = (q < 0) ? cfg_up(mk, p) : (cfg_up(mk, p) == cfg_up(mk, q));
             const double2 v = u[x];
             re += plus ? v.x : -v.x;
             im += plus ? v.y : -v.y;

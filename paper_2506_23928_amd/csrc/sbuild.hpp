@@ -24,11 +24,13 @@ __device__ __forceinline__ double add_shift(double v, double eps) {
     return v + eps;
 }
 
-__device__ __forceinline__ double o_value(uint64_t mk, int p, int q, int n) { return (double)o_int(mk, p, q, n); }
+template <int W>
+__device__ __forceinline__ double o_value(const Cfg<W> &mk, int p, int q, int n) { return (double)o_int<true>(mk, p, q, n); }
 
 // Plain form: 64x64 tile per workgroup, 4x4 register tile per thread, FP64 FMAs.
+template <int W>
 __global__ __launch_bounds__(256) void k_sbuild_f64(Dev a) {
-    __shared__ uint64_t smask[256];
+    __shared__ Cfg<W> smask[256];
     const int t = blockIdx.y;
     // lower-triangular tile index -> (bi, bj), bi >= bj
     const int tile = blockIdx.x;
@@ -46,14 +48,14 @@ __global__ __launch_bounds__(256) void k_sbuild_f64(Dev a) {
         cq[u] = l < a.m ? a.pb[l] : -1;
     }
     double acc[4][4] = {};
-    const uint64_t *smp = a.samples + (size_t)t * a.ns;
+    const uint64_t *smp = a.samples + (size_t)t * a.ns * W;
     for (int s0 = 0; s0 < a.ns; s0 += 256) {
         __syncthreads();
-        if (s0 + threadIdx.x < a.ns) smask[threadIdx.x] = smp[s0 + threadIdx.x];
+        if (s0 + threadIdx.x < a.ns) smask[threadIdx.x] = cfg_load<W>(smp + (size_t)(s0 + threadIdx.x) * W);
         __syncthreads();
         const int cnt = (a.ns - s0) < 256 ? (a.ns - s0) : 256;
         for (int s = 0; s < cnt; ++s) {
-            const uint64_t mk = smask[s];
+            const Cfg<W> mk = smask[s];
             double ov[4], cv[4];
             for (int u = 0; u < 4; ++u) {
                 ov[u] = o_value(mk, rp[u], rq[u], a.n);

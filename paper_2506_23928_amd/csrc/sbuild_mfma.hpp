@@ -1,6 +1,6 @@
 // S + eps I for the Jastrow ansaetze on the int8 matrix cores (v_mfma_i32_16x16x64_i8).
 //
-// O_sk is +-1, or for a shared LJPHd distance an integer of magnitude <= N - 1 <= 63, so
+// O_sk is +-1, or for a shared LJPHd distance an integer of magnitude <= N - 1 <= 127, so
 // sum_s O_sk O_sl is computed exactly as an int32 dot product of int8 values.
 // Samples are first transposed to site-major bit planes (bit s of plane i = spin i of sample
 // s is up).  For a 64-sample chunk the sign bits of a parameter row are one XOR of two planes
@@ -17,13 +17,15 @@ namespace tvmc {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-// samples[t][s] (u64, bit i = site i) -> sbits[t][i][s/32] (u32, bit s%32 = sample s)
+// samples[t][s] (W words, bit i % 64 of word i / 64 = site i) -> sbits[t][i][s/32] (u32, bit
+// s%32 = sample s); one thread per site
 __global__ void k_transpose_bits(Dev a) {
     const int t = blockIdx.y, wd = blockIdx.x, i = threadIdx.x;
     if (i >= a.n) return;
-    const uint64_t *smp = a.samples + (size_t)t * a.ns + (size_t)wd * 32;
+    const int W = a.nw;
+    const uint64_t *smp = a.samples + ((size_t)t * a.ns + (size_t)wd * 32) * W + (i >> 6);
     uint32_t v = 0;
-    for (int b = 0; b < 32; ++b) v |= (uint32_t)((smp[b] >> i) & 1ull) << b;
+    for (int b = 0; b < 32; ++b) v |= (uint32_t)((smp[(size_t)b * W] >> (i & 63)) & 1ull) << b;
     a.sbits[((size_t)t * a.n + i) * (a.ns / 32) + wd] = v;
 }
 
@@ -36,13 +38,15 @@ __device__ __forceinline__ uint32_t expand4(uint32_t nib) {
 }
 
 // four samples' O of a shared distance p (sum of s_j s_{j+p}) as four int8 bytes
+template <int W>
 __device__ __forceinline__ uint32_t dist_bytes4(const uint64_t *sp, int p, int n) {
     uint32_t w = 0;
-    for (int b = 0; b < 4; ++b) w |= (uint32_t)(uint8_t)(int8_t)o_int<true>(sp[b], p, -2, n) << (8 * b);
+    for (int b = 0; b < 4; ++b)
+        w |= (uint32_t)(uint8_t)(int8_t)o_int<true>(cfg_load<W>(sp + (size_t)b * W), p, -2, n) << (8 * b);
     return w;
 }
 
-template <bool DIST>
+template <bool DIST, int W>
 __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
     __shared__ uint32_t As[SB_TILE * SB_ROWW];
     __shared__ uint32_t Bs[SB_TILE * SB_ROWW];
@@ -76,11 +80,11 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
         const uint32_t nb = vb ? (bq < 0 ? ~pb_ : (pb_ ^ planes[(size_t)bq * nw + w])) : 0u;
         __syncthreads();
         if (DIST) {
-            const uint64_t *sp = a.samples + (size_t)t * a.ns + (size_t)w * 32;
+            const uint64_t *sp = a.samples + ((size_t)t * a.ns + (size_t)w * 32) * W;
             for (int q = 0; q < 8; ++q) {
-                As[gr * SB_ROWW + gh * 8 + q] = !va ? 0u : aq == -2 ? dist_bytes4(sp + 4 * q, ap, a.n)
+                As[gr * SB_ROWW + gh * 8 + q] = !va ? 0u : aq == -2 ? dist_bytes4<W>(sp + 4 * q * W, ap, a.n)
                                                                    : expand4((na >> (4 * q)) & 0xFu);
-                Bs[gr * SB_ROWW + gh * 8 + q] = !vb ? 0u : bq == -2 ? dist_bytes4(sp + 4 * q, bp, a.n)
+                Bs[gr * SB_ROWW + gh * 8 + q] = !vb ? 0u : bq == -2 ? dist_bytes4<W>(sp + 4 * q * W, bp, a.n)
                                                                    : expand4((nb >> (4 * q)) & 0xFu);
             }
         } else {
@@ -119,16 +123,19 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
 }
 
 inline tvmc_status launch_transpose_bits(const Dev &d, hipStream_t st) {
-    hipLaunchKernelGGL(k_transpose_bits, dim3(d.ns / 32, d.nt), dim3(64), 0, st, d);
+    hipLaunchKernelGGL(k_transpose_bits, dim3(d.ns / 32, d.nt), dim3(64 * d.nw), 0, st, d);
     return hipGetLastError() == hipSuccess ? TVMC_OK : TVMC_E_DEVICE;
 }
 
 inline tvmc_status launch_sbuild_mfma(const Dev &d, hipStream_t st) {
     const int nt = (d.m + SB_TILE - 1) / SB_TILE;
-    if (d.kind == TVMC_ANSATZ_LJPH)
-        hipLaunchKernelGGL(k_sbuild_i8<true>, dim3(nt * (nt + 1) / 2, d.nt), dim3(256), 0, st, d);
-    else
-        hipLaunchKernelGGL(k_sbuild_i8<false>, dim3(nt * (nt + 1) / 2, d.nt), dim3(256), 0, st, d);
+    const dim3 grid(nt * (nt + 1) / 2, d.nt);
+    if (d.kind == TVMC_ANSATZ_LJPH) {
+        if (d.nw == 1) hipLaunchKernelGGL((k_sbuild_i8<true, 1>), grid, dim3(256), 0, st, d);
+        else hipLaunchKernelGGL((k_sbuild_i8<true, 2>), grid, dim3(256), 0, st, d);
+    } else {
+        hipLaunchKernelGGL((k_sbuild_i8<false, 1>), grid, dim3(256), 0, st, d);   // the samples are not read
+    }
     if (hipGetLastError() != hipSuccess) return TVMC_E_DEVICE;
     return TVMC_OK;
 }

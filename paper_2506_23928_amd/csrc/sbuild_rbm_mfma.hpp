@@ -35,13 +35,14 @@ __device__ __forceinline__ void split_bf16(double x, uint16_t &hi, uint16_t &lo)
 constexpr int RQ_CHUNK = 4 * 128 * 32;   // elements of one staged step of one row block
 constexpr int SPL_R = 8;
 typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+template <int W>
 __global__ __launch_bounds__(256) void k_rbm_split(Dev a) {
     const int t = blockIdx.z, st = blockIdx.x, n = a.n, nh = a.nh, wb = n + nh;
     const int s0 = st * 32 + 8 * (threadIdx.x & 3);
     const size_t sbase = (size_t)t * a.ns + s0;
     const double2 *tts = a.tt + sbase * nh;
-    uint64_t mk[8];
-    for (int e = 0; e < 8; ++e) mk[e] = a.samples[sbase + e];
+    Cfg<W> mk[8];
+    for (int e = 0; e < 8; ++e) mk[e] = cfg_load<W>(a.samples + (sbase + e) * W);
     double2 tv[8];
     int jc = -1;
     const int nst = a.ns / 32;

@@ -125,8 +125,9 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.eta_re = take(sizeof(double) * tt * n * n);
     L.eta_im = take(sizeof(double) * tt * n * n);
     L.epair = take(sizeof(double2) * tt * 2 * n * n);
-    L.chains = take(sizeof(uint64_t) * tt * nc);
-    L.samples = take(sizeof(uint64_t) * tt * ns);
+    const size_t nw = (size_t)(n + 63) / 64;   // words per configuration
+    L.chains = take(sizeof(uint64_t) * tt * nc * nw);
+    L.samples = take(sizeof(uint64_t) * tt * ns * nw);
     L.sbits = take(sizeof(uint32_t) * tt * n * ((ns + 31) / 32));
     L.R = take(sizeof(double2) * tt * ns * n);
     L.eloc = take(sizeof(double2) * tt * ns);
@@ -156,7 +157,7 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.mom_part = take(sizeof(double) * tt * mom_blocks_for(ns) * 9);
     L.mom = take(sizeof(double) * tt * 9);
     L.hist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt * 9);
-    L.ens = take(sizeof(double) * 16);
+    L.ens = take(sizeof(double) * 16 * (tt + 1));
     L.flags = take(sizeof(int) * tt);
     L.dstep = take(sizeof(int));
     L.lognorm = take(sizeof(double) * tt * 3);
@@ -203,7 +204,8 @@ thread_local char g_err[512];
 
 tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_config *c, char *msg, size_t len) {
     if (!p || !a || !c) return snprintf(msg, len, "null argument"), TVMC_E_INVAL;
-    if (p->n_sites < 1 || p->n_sites > 64) return snprintf(msg, len, "n_sites must be in [1, 64]"), TVMC_E_INVAL;
+    if (p->n_sites < 1 || p->n_sites > 64 * MAX_WORDS)
+        return snprintf(msg, len, "n_sites must be in [1, %d]", 64 * MAX_WORDS), TVMC_E_INVAL;
     if (!p->J) return snprintf(msg, len, "J is null"), TVMC_E_INVAL;
     if (p->n_jumps < 0 || p->n_jumps > 256) return snprintf(msg, len, "n_jumps must be in [0, 256]"), TVMC_E_INVAL;
     if (p->n_jumps > 0 && (!p->jump_kind || !p->jump_site || !p->jump_rate))
@@ -254,6 +256,7 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
     if (c->proposal != TVMC_PROPOSAL_FLIP && c->proposal != TVMC_PROPOSAL_LEARNED)
         return snprintf(msg, len, "bad proposal"), TVMC_E_INVAL;
     if (c->proposal == TVMC_PROPOSAL_LEARNED) {
+        if (p->n_sites > 64) return snprintf(msg, len, "the learned proposal takes at most 64 sites"), TVMC_E_INVAL;
         if (c->ar_hidden < 1 || c->ar_hidden > 256 || c->ar_hidden * p->n_sites > AR_LDS_W)
             return snprintf(msg, len, "ar_hidden must be in [1, 256] with ar_hidden * n_sites <= %d", AR_LDS_W), TVMC_E_INVAL;
         if (c->ar_train_every < 0 || c->ar_train_iters < 0 || !(c->ar_lr > 0.0))
@@ -267,6 +270,7 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
         return snprintf(msg, len, "bad regulariser"), TVMC_E_INVAL;
     if (c->use_graph != 0 && c->use_graph != 1) return snprintf(msg, len, "bad use_graph"), TVMC_E_INVAL;
     if (c->regulariser == TVMC_REG_SNR) {
+        if (p->n_sites > 64) return snprintf(msg, len, "the SNR solve takes at most 64 sites"), TVMC_E_INVAL;
         if (c->solver == TVMC_SOLVER_SAMPLE_SPACE)
             return snprintf(msg, len, "the SNR solve works in parameter space"), TVMC_E_INVAL;
         if (n_params(a, p->n_sites) > 2 * JAC_MAXP)
@@ -312,6 +316,18 @@ tvmc_status check_batch(const tvmc_problem *p, int np, const tvmc_ansatz *a, con
             set_err(ctx, "launch of %s failed: %s", name, hipGetErrorString(e_));        \
             return TVMC_E_DEVICE;                                                        \
         }                                                                                \
+    } while (0)
+
+// Launch a kernel template instantiated for the context's configuration words (W_ = 1 or 2).
+#define BY_WORDS(d, LAUNCH)              \
+    do {                                 \
+        if ((d).nw == 1) {               \
+            constexpr int W_ = 1;        \
+            LAUNCH;                      \
+        } else {                         \
+            constexpr int W_ = 2;        \
+            LAUNCH;                      \
+        }                                \
     } while (0)
 
 struct Scope {
@@ -372,25 +388,29 @@ tvmc_status run_sample(tvmc_ctx *c) {
         // chain count allows and the per-chain LDS rows fit (N' <= 128)
         const int cpb = (c->cpb == 8 && d.nc % 16 == 0 && qh <= 2) ? 16 : c->cpb;
         dim3 grid((d.nc / cpb * T + 7) / 8 * 8);
-#define RBM_LAUNCH(CPB, QH, AR, WL) hipLaunchKernelGGL((k_sample_rbm<CPB, QH, AR, WL>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
-#define RBM_CPB(QH, AR, WL)                         \
-    switch (cpb) {                                  \
-    case 16: if constexpr (QH <= 2) { RBM_LAUNCH(16, QH, AR, WL); } break; \
-    case 8: RBM_LAUNCH(8, QH, AR, WL); break;       \
-    case 4: RBM_LAUNCH(4, QH, AR, WL); break;       \
-    case 2: RBM_LAUNCH(2, QH, AR, WL); break;       \
-    default: RBM_LAUNCH(1, QH, AR, WL); break;      \
+#define RBM_LAUNCH(CPB, QH, AR, WL, WD) hipLaunchKernelGGL((k_sample_rbm<CPB, QH, AR, WL, WD>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
+#define RBM_CPB(QH, AR, WL, WD)                         \
+    switch (cpb) {                                      \
+    case 16: if constexpr (QH <= 2) { RBM_LAUNCH(16, QH, AR, WL, WD); } break; \
+    case 8: RBM_LAUNCH(8, QH, AR, WL, WD); break;       \
+    case 4: RBM_LAUNCH(4, QH, AR, WL, WD); break;       \
+    case 2: RBM_LAUNCH(2, QH, AR, WL, WD); break;       \
+    default: RBM_LAUNCH(1, QH, AR, WL, WD); break;      \
     }
-        // N' <= 64 always fits in LDS (N <= 64); wider layers fit when N N' <= 4096
+        // N' <= 64 fits in LDS with N <= 64; other layers fit when N N' <= 4096
         const bool wl = d.n * d.nh <= 64 * 64;
-        if (d.ar) {
-            if (qh == 1) { RBM_CPB(1, true, true) }
-            else if (qh == 2) { if (wl) { RBM_CPB(2, true, true) } else { RBM_CPB(2, true, false) } }
-            else { if (wl) { RBM_CPB(4, true, true) } else { RBM_CPB(4, true, false) } }
+        if (d.ar) {   // one configuration word (checked at initialisation)
+            if (qh == 1) { RBM_CPB(1, true, true, 1) }
+            else if (qh == 2) { if (wl) { RBM_CPB(2, true, true, 1) } else { RBM_CPB(2, true, false, 1) } }
+            else { if (wl) { RBM_CPB(4, true, true, 1) } else { RBM_CPB(4, true, false, 1) } }
+        } else if (d.nw == 1) {
+            if (qh == 1) { RBM_CPB(1, false, true, 1) }
+            else if (qh == 2) { if (wl) { RBM_CPB(2, false, true, 1) } else { RBM_CPB(2, false, false, 1) } }
+            else { if (wl) { RBM_CPB(4, false, true, 1) } else { RBM_CPB(4, false, false, 1) } }
         } else {
-            if (qh == 1) { RBM_CPB(1, false, true) }
-            else if (qh == 2) { if (wl) { RBM_CPB(2, false, true) } else { RBM_CPB(2, false, false) } }
-            else { if (wl) { RBM_CPB(4, false, true) } else { RBM_CPB(4, false, false) } }
+            if (qh == 1) { if (wl) { RBM_CPB(1, false, true, 2) } else { RBM_CPB(1, false, false, 2) } }
+            else if (qh == 2) { if (wl) { RBM_CPB(2, false, true, 2) } else { RBM_CPB(2, false, false, 2) } }
+            else { if (wl) { RBM_CPB(4, false, true, 2) } else { RBM_CPB(4, false, false, 2) } }
         }
 #undef RBM_CPB
 #undef RBM_LAUNCH
@@ -405,7 +425,15 @@ tvmc_status run_sample(tvmc_ctx *c) {
         Scope sc(c, "sample");
         dim3 grid(d.nc / c->cpb, T);
 #define JAS_LAUNCH(CPB, AR) hipLaunchKernelGGL((k_sample_jastrow<CPB, AR>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
-        if (d.ar) {
+#define JAS2_LAUNCH(CPB) hipLaunchKernelGGL((k_sample_jastrow_w2<CPB>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
+        if (d.nw == 2) {
+            switch (c->cpb) {
+            case 8: JAS2_LAUNCH(8); break;
+            case 4: JAS2_LAUNCH(4); break;
+            case 2: JAS2_LAUNCH(2); break;
+            default: JAS2_LAUNCH(1); break;
+            }
+        } else if (d.ar) {
             switch (c->cpb) {
             case 8: JAS_LAUNCH(8, true); break;
             case 4: JAS_LAUNCH(4, true); break;
@@ -421,6 +449,7 @@ tvmc_status run_sample(tvmc_ctx *c) {
             }
         }
 #undef JAS_LAUNCH
+#undef JAS2_LAUNCH
         LAUNCHCHECK(c, "k_sample_jastrow");
     }
     c->phase = 1;
@@ -433,21 +462,21 @@ tvmc_status run_estimate(tvmc_ctx *c) {
     {
         Scope sc(c, "estimate");
         if (d.nch > 0) {
-            hipLaunchKernelGGL(k_channel_means, dim3((d.nch + CM_CH - 1) / CM_CH, T), dim3(256), 0, c->stream, d);
+            BY_WORDS(d, hipLaunchKernelGGL((k_channel_means<W_>), dim3((d.nch + CM_CH - 1) / CM_CH, T), dim3(256), 0, c->stream, d));
             LAUNCHCHECK(c, "k_channel_means");
         }
-        hipLaunchKernelGGL(k_build_G, dim3((d.ns + 255) / 256, T), dim3(256), 0, c->stream, d);
+        BY_WORDS(d, hipLaunchKernelGGL((k_build_G<W_>), dim3((d.ns + 255) / 256, T), dim3(256), 0, c->stream, d));
         LAUNCHCHECK(c, "k_build_G");
         hipLaunchKernelGGL(k_gbar, dim3(T), dim3(256), 0, c->stream, d);
         LAUNCHCHECK(c, "k_gbar");
         if (d.kind == TVMC_ANSATZ_RBM) {
-            hipLaunchKernelGGL(k_obar_D_rbm, dim3((d.m + 64 * OD_R - 1) / (64 * OD_R), T), dim3(256), 0, c->stream, d);
+            BY_WORDS(d, hipLaunchKernelGGL((k_obar_D_rbm<W_>), dim3((d.m + 64 * OD_R - 1) / (64 * OD_R), T), dim3(256), 0, c->stream, d));
             LAUNCHCHECK(c, "k_obar_D_rbm");
         } else {
             if (d.kind == TVMC_ANSATZ_LJPH)
-                hipLaunchKernelGGL(k_obar_D<true>, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
+                BY_WORDS(d, hipLaunchKernelGGL((k_obar_D<true, W_>), dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d));
             else
-                hipLaunchKernelGGL(k_obar_D<false>, dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d);
+                BY_WORDS(d, hipLaunchKernelGGL((k_obar_D<false, W_>), dim3((d.m + 255) / 256, T), dim3(256), 0, c->stream, d));
             LAUNCHCHECK(c, "k_obar_D");
         }
     }
@@ -455,10 +484,10 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         Scope sc(c, "sbuild");
         if (d.kind == TVMC_ANSATZ_RBM) {
             const int nb = (d.ns + TK_T - 1) / TK_T;
-            hipLaunchKernelGGL(k_tk_rbm, dim3(nb * nb, T), dim3(256), 0, c->stream, d);
+            BY_WORDS(d, hipLaunchKernelGGL((k_tk_rbm<W_>), dim3(nb * nb, T), dim3(256), 0, c->stream, d));
             LAUNCHCHECK(c, "k_tk_rbm");
         } else {
-            hipLaunchKernelGGL(k_tk_jastrow, dim3((d.ns + 255) / 256, d.ns, T), dim3(256), 0, c->stream, d);
+            BY_WORDS(d, hipLaunchKernelGGL((k_tk_jastrow<W_>), dim3((d.ns + 255) / 256, d.ns, T), dim3(256), 0, c->stream, d));
             LAUNCHCHECK(c, "k_tk_jastrow");
         }
         hipLaunchKernelGGL(k_tk_rowmean, dim3(d.ns, T), dim3(256), 0, c->stream, d);
@@ -474,7 +503,7 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         if (c->cfg.precision == TVMC_PREC_MFMA) {
             {
                 Scope sc(c, "transpose");
-                hipLaunchKernelGGL(k_rbm_split, dim3(d.ns / 32, (d.mp + 64 * SPL_R - 1) / (64 * SPL_R), T), dim3(256), 0, c->stream, d);
+                BY_WORDS(d, hipLaunchKernelGGL((k_rbm_split<W_>), dim3(d.ns / 32, (d.mp + 64 * SPL_R - 1) / (64 * SPL_R), T), dim3(256), 0, c->stream, d));
                 LAUNCHCHECK(c, "k_rbm_split");
             }
             Scope sc(c, "sbuild");
@@ -484,7 +513,7 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         } else {
             Scope sc(c, "sbuild");
             const int nt = (d.m + RB_T - 1) / RB_T;
-            hipLaunchKernelGGL(k_sbuild_rbm_f64, dim3(nt * (nt + 1) / 2, T), dim3(256), 0, c->stream, d);
+            BY_WORDS(d, hipLaunchKernelGGL((k_sbuild_rbm_f64<W_>), dim3(nt * (nt + 1) / 2, T), dim3(256), 0, c->stream, d));
             LAUNCHCHECK(c, "k_sbuild_rbm_f64");
         }
         c->phase = 2;
@@ -507,7 +536,7 @@ tvmc_status run_estimate(tvmc_ctx *c) {
             }
         } else {
             const int nt = (d.m + 63) / 64;
-            hipLaunchKernelGGL(k_sbuild_f64, dim3(nt * (nt + 1) / 2, T), dim3(256), 0, c->stream, d);
+            BY_WORDS(d, hipLaunchKernelGGL((k_sbuild_f64<W_>), dim3(nt * (nt + 1) / 2, T), dim3(256), 0, c->stream, d));
             LAUNCHCHECK(c, "k_sbuild_f64");
         }
     }
@@ -624,7 +653,7 @@ tvmc_status run_solve(tvmc_ctx *c) {
                 st = launch_chol(c, ca);
             }
             if (st != TVMC_OK) return st;
-            hipLaunchKernelGGL(k_pushback, dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage);
+            BY_WORDS(d, hipLaunchKernelGGL((k_pushback<W_>), dim3((d.m + 255) / 256, d.nt), dim3(256), 0, c->stream, d, c->stage));
             LAUNCHCHECK(c, "k_pushback");
         } else if (d.reg == TVMC_REG_SNR && d.kind == TVMC_ANSATZ_RBM) {
             const size_t mm = (size_t)d.m * d.m;
@@ -721,16 +750,16 @@ tvmc_status run_moments(tvmc_ctx *c, int slot) {
     Dev &d = c->d;
     const int T = d.nt, nn = d.n * d.n;
     Scope sc(c, "observe");
-    if (d.kind == TVMC_ANSATZ_RBM && d.n * d.nh <= 64 * 64) {
+    if (d.kind == TVMC_ANSATZ_RBM && d.nw == 1 && d.n * d.nh <= 64 * 64) {
         hipLaunchKernelGGL(k_moments_rbm_f, dim3(d.mom_blocks, T), dim3(64 * RMF_WAVES), 0, c->stream, d);
         LAUNCHCHECK(c, "k_moments_rbm_f");
     } else if (d.kind == TVMC_ANSATZ_RBM) {
-        hipLaunchKernelGGL(k_moments_rbm, dim3(d.mom_blocks, T), dim3(64 * RMOM_WAVES), 0, c->stream, d);
+        BY_WORDS(d, hipLaunchKernelGGL((k_moments_rbm<W_>), dim3(d.mom_blocks, T), dim3(64 * RMOM_WAVES), 0, c->stream, d));
         LAUNCHCHECK(c, "k_moments_rbm");
     } else {
         hipLaunchKernelGGL(k_prepare_pairs, dim3((nn + 255) / 256, T), dim3(256), 0, c->stream, d);
         LAUNCHCHECK(c, "k_prepare_pairs");
-        hipLaunchKernelGGL(k_moments, dim3(d.mom_blocks, T), dim3(64 * MOM_WAVES), 0, c->stream, d);
+        BY_WORDS(d, hipLaunchKernelGGL((k_moments<W_>), dim3(d.mom_blocks, T), dim3(64 * MOM_WAVES), 0, c->stream, d));
         LAUNCHCHECK(c, "k_moments");
     }
     hipLaunchKernelGGL(k_moments_reduce, dim3((T + 127) / 128), dim3(128), 0, c->stream, d, slot);
@@ -743,14 +772,14 @@ size_t q_bytes(const tvmc_ctx *c, int what) {
     switch (what) {
     case TVMC_Q_THETA: case TVMC_Q_THETA_EVAL: case TVMC_Q_DELTA0: case TVMC_Q_DELTA1: case TVMC_Q_D:
         return sizeof(double2) * d.m;
-    case TVMC_Q_SAMPLES: return sizeof(uint64_t) * d.ns;
+    case TVMC_Q_SAMPLES: return sizeof(uint64_t) * d.ns * d.nw;
     case TVMC_Q_ELOC: return sizeof(double2) * d.ns;
     case TVMC_Q_S: return sizeof(double) * s_doubles(d.kind, d.ss ? d.ns : d.m);
     case TVMC_Q_OBAR: return (d.kind == TVMC_ANSATZ_RBM ? sizeof(double2) : sizeof(double)) * d.m;
     case TVMC_Q_BMEAN: return sizeof(double2) * d.nch;
     case TVMC_Q_DW: return sizeof(double) * d.nch;
     case TVMC_Q_ACCEPTS: return sizeof(uint32_t) * d.nc;
-    case TVMC_Q_CHAINS: return sizeof(uint64_t) * d.nc;
+    case TVMC_Q_CHAINS: return sizeof(uint64_t) * d.nc * d.nw;
     case TVMC_Q_MOMENTS: return sizeof(double) * 9;
     case TVMC_Q_OBS_HIST: return sizeof(double) * 9 * (size_t)d.nobs;
     case TVMC_Q_AR_PARAMS: case TVMC_Q_AR_GRAD: return d.ar ? sizeof(float) * d.arnp : 0;
@@ -809,6 +838,7 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
     char *base = (char *)ws;
     Dev &d = ctx->d;
     d.n = n;
+    d.nw = (n + 63) / 64;
     d.m = m;
     d.kind = a->kind;
     d.nh = nh;
@@ -1119,12 +1149,22 @@ tvmc_status tvmc_observables(tvmc_ctx *c, double *out) {
     return TVMC_OK;
 }
 
-tvmc_status tvmc_ensemble(tvmc_ctx *c, double *out) {
+tvmc_status tvmc_ensemble(tvmc_ctx *c, double *out) { return tvmc_ensemble_at(c, -1, out, nullptr); }
+
+tvmc_status tvmc_ensemble_at(tvmc_ctx *c, int32_t slot, double *out, double *loo_xi2) {
     if (!c || !out) return TVMC_E_INVAL;
-    hipLaunchKernelGGL(k_ensemble, dim3(1), dim3(64), 0, c->stream, c->d);
+    const Dev &d = c->d;
+    if (slot >= c->nobs) return set_err(c, "tvmc_ensemble_at: history record %d not taken yet", slot), TVMC_E_INVAL;
+    if (loo_xi2 && d.nt < 2) return set_err(c, "tvmc_ensemble_at: the jackknife needs two trajectories"), TVMC_E_INVAL;
+    const int blocks = loo_xi2 ? d.nt + 1 : 1;
+    hipLaunchKernelGGL(k_ensemble, dim3(blocks), dim3(64), 0, c->stream, d, slot < 0 ? -1 : slot, d.ens);
     LAUNCHCHECK(c, "k_ensemble");
-    HIPCHECK(c, hipMemcpyAsync(out, c->d.ens, sizeof(double) * 13, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> buf((size_t)16 * blocks);
+    HIPCHECK(c, hipMemcpyAsync(buf.data(), d.ens, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
+    memcpy(out, buf.data(), sizeof(double) * 13);
+    if (loo_xi2)
+        for (int t = 0; t < d.nt; ++t) loo_xi2[t] = buf[(size_t)16 * (t + 1) + 12];
     return TVMC_OK;
 }
 
@@ -1142,7 +1182,7 @@ tvmc_status tvmc_get(tvmc_ctx *c, int32_t what, int32_t traj, void *host, size_t
     case TVMC_Q_THETA_EVAL: src = d.theta_eval + t * d.m; break;
     case TVMC_Q_DELTA0: src = d.d0 + t * d.m; break;
     case TVMC_Q_DELTA1: src = d.d1 + t * d.m; break;
-    case TVMC_Q_SAMPLES: src = d.samples + t * d.ns; break;
+    case TVMC_Q_SAMPLES: src = d.samples + t * d.ns * d.nw; break;
     case TVMC_Q_ELOC: src = d.eloc + t * d.ns; break;
     case TVMC_Q_S: src = d.S + t * s_doubles(d.kind, d.ss ? d.ns : d.m); break;
     case TVMC_Q_D: src = d.D + t * d.m; break;
@@ -1150,7 +1190,7 @@ tvmc_status tvmc_get(tvmc_ctx *c, int32_t what, int32_t traj, void *host, size_t
     case TVMC_Q_BMEAN: src = d.bmean + t * d.nch; break;
     case TVMC_Q_DW: src = d.dw + t * d.nch; break;
     case TVMC_Q_ACCEPTS: src = d.acc + t * d.nc; break;
-    case TVMC_Q_CHAINS: src = d.chains + t * d.nc; break;
+    case TVMC_Q_CHAINS: src = d.chains + t * d.nc * d.nw; break;
     case TVMC_Q_MOMENTS: src = d.mom + t * 9; break;
     case TVMC_Q_AR_PARAMS: src = d.arP + t * d.arnp; break;
     case TVMC_Q_AR_GRAD: src = d.arG + t * d.arnp; break;
@@ -1200,10 +1240,14 @@ tvmc_status tvmc_set(tvmc_ctx *c, int32_t what, int32_t traj, const void *host, 
         HIPCHECK(c, hipStreamSynchronize(c->stream));
         return TVMC_OK;
     }
-    void *dst = what == TVMC_Q_THETA ? (void *)(d.theta + (size_t)traj * d.m) : (void *)(d.chains + (size_t)traj * d.nc);
-    if (what == TVMC_Q_CHAINS && d.n < 64)
+    void *dst = what == TVMC_Q_THETA ? (void *)(d.theta + (size_t)traj * d.m) : (void *)(d.chains + (size_t)traj * d.nc * d.nw);
+    if (what == TVMC_Q_CHAINS)
         for (int i = 0; i < d.nc; ++i)
-            if (((const uint64_t *)host)[i] >> d.n) return set_err(c, "tvmc_set: chain word has bits above N"), TVMC_E_INVAL;
+            for (int q = 0; q < d.nw; ++q) {
+                const int bits = d.n - 64 * q;
+                const uint64_t v = ((const uint64_t *)host)[(size_t)i * d.nw + q];
+                if (bits < 64 && (v >> bits)) return set_err(c, "tvmc_set: chain word has bits above N"), TVMC_E_INVAL;
+            }
     if (what == TVMC_Q_THETA)
         for (size_t i = 0; i < 2 * (size_t)d.m; ++i)
             if (!std::isfinite(((const double *)host)[i])) return set_err(c, "tvmc_set: theta not finite"), TVMC_E_INVAL;
@@ -1229,7 +1273,7 @@ struct StatePart {
 std::vector<StatePart> state_parts(const tvmc_ctx *c) {
     const Dev &d = c->d;
     const size_t T = (size_t)d.nt, nobs = (size_t)(d.nobs > 0 ? d.nobs : 0);
-    std::vector<StatePart> p = {{d.theta, sizeof(double2) * T * d.m}, {d.chains, sizeof(uint64_t) * T * d.nc},
+    std::vector<StatePart> p = {{d.theta, sizeof(double2) * T * d.m}, {d.chains, sizeof(uint64_t) * T * d.nc * d.nw},
                                 {d.lognorm, sizeof(double) * 3 * T}, {d.mom, sizeof(double) * T * 9}};
     if (nobs) {
         p.push_back({d.hist, sizeof(double) * nobs * T * 9});

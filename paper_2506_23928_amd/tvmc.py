@@ -58,7 +58,7 @@ class TvmcError(RuntimeError):
 
 _lib = None
 EXPORTED = ["tvmc_workspace_size", "tvmc_init", "tvmc_workspace_size_batch", "tvmc_init_batch", "tvmc_sample", "tvmc_estimate", "tvmc_sr_solve", "tvmc_update",
-            "tvmc_sde_step", "tvmc_train_proposal", "tvmc_observables", "tvmc_ensemble", "tvmc_get", "tvmc_set", "tvmc_position",
+            "tvmc_sde_step", "tvmc_train_proposal", "tvmc_observables", "tvmc_ensemble", "tvmc_ensemble_at", "tvmc_get", "tvmc_set", "tvmc_position",
             "tvmc_synchronize", "tvmc_set_timing", "tvmc_timing", "tvmc_last_error", "tvmc_destroy",
             "tvmc_state_size", "tvmc_save_state", "tvmc_load_state"]
 
@@ -208,6 +208,16 @@ def tvmc_ensemble(ctx):
     return out[0:3], out[3:12].reshape(3, 3), float(out[12])
 
 
+def tvmc_ensemble_at(ctx, slot, n_traj=0):
+    """(M, C, xi^2) at history record `slot` (slot < 0: the last moments) and, with n_traj > 1,
+    the n_traj leave-one-out xi^2 values of a jackknife over the trajectories (else None)."""
+    out = np.zeros(13)
+    loo = np.zeros(n_traj) if n_traj > 1 else None
+    _check(lib().tvmc_ensemble_at(ctx, ctypes.c_int32(slot), out.ctypes.data_as(_dp),
+                                  loo.ctypes.data_as(_dp) if loo is not None else None), ctx)
+    return out[0:3], out[3:12].reshape(3, 3), float(out[12]), loo
+
+
 def tvmc_synchronize(ctx):
     _check(lib().tvmc_synchronize(ctx), ctx)
 
@@ -223,8 +233,8 @@ class Context:
     and d for LJPHd."""
 
     _shapes = {Q_THETA: ("c", "m"), Q_THETA_EVAL: ("c", "m"), Q_DELTA0: ("c", "m"), Q_DELTA1: ("c", "m"),
-               Q_SAMPLES: ("u8", "ns"), Q_ELOC: ("c", "ns"), Q_S: ("d", "mm"), Q_D: ("c", "m"), Q_OBAR: ("d", "m"),
-               Q_BMEAN: ("c", "nch"), Q_DW: ("d", "nch"), Q_ACCEPTS: ("u4", "nc"), Q_CHAINS: ("u8", "nc"),
+               Q_SAMPLES: ("u8", "ns_w"), Q_ELOC: ("c", "ns"), Q_S: ("d", "mm"), Q_D: ("c", "m"), Q_OBAR: ("d", "m"),
+               Q_BMEAN: ("c", "nch"), Q_DW: ("d", "nch"), Q_ACCEPTS: ("u4", "nc"), Q_CHAINS: ("u8", "nc_w"),
                Q_MOMENTS: ("d", "9"), Q_OBS_HIST: ("d", "hist"), Q_AR_PARAMS: ("f", "arnp"), Q_AR_GRAD: ("f", "arnp"),
                Q_AR_LOGQ: ("f", "ns"), Q_AR_LOSS: ("d", "1"), Q_AR_ACCEPTS: ("u4", "nc"), Q_LOGNORM: ("d", "1"),
                Q_LOGNORM_HIST: ("d", "nobs"), Q_EIG: ("d", "2m"), Q_AR_LOGQ_BF16: ("f", "ns")}
@@ -278,6 +288,9 @@ class Context:
     def ensemble(self):
         return tvmc_ensemble(self.ctx)
 
+    def ensemble_at(self, slot, jackknife=False):
+        return tvmc_ensemble_at(self.ctx, slot, self.config.n_traj if jackknife else 0)
+
     def synchronize(self):
         tvmc_synchronize(self.ctx)
 
@@ -296,8 +309,11 @@ class Context:
 
     @property
     def sample_space(self):
-        """Whether the solve runs in sample space (the library's rule: requested, or M > N_s)."""
+        """Whether the solve runs in sample space (the library's rule: requested, or M > N_s; never
+        for LJPHd or the SNR solve, which work in parameter space)."""
         c = self.config
+        if self.ansatz.kind == LJPH or c.regulariser == REG_SNR:
+            return False
         return c.solver == SOLVER_SAMPLE_SPACE or (c.solver == SOLVER_AUTO and self.m > c.n_samples)
 
     @property
@@ -306,9 +322,15 @@ class Context:
         Jastrow ansatz, complex Hermitian for the RBM)."""
         return self.config.n_samples if self.sample_space else self.m
 
+    @property
+    def words(self):
+        """64-bit words per configuration (sites 64 q .. 64 q + 63 in word q)."""
+        return (self.problem.n + 63) // 64
+
     def _count(self, key):
         c = self.config
-        return {"m": self.m, "ns": c.n_samples, "mm": self.solve_dim ** 2, "nch": len(self.problem.jumps),
+        w = self.words
+        return {"m": self.m, "ns": c.n_samples, "ns_w": c.n_samples * w, "nc_w": c.n_chains * w, "mm": self.solve_dim ** 2, "nch": len(self.problem.jumps),
                 "nc": c.n_chains, "9": 9, "hist": 9 * c.n_obs_max, "nobs": c.n_obs_max, "1": 1, "2m": 2 * self.m,
                 "arnp": 2 * self.problem.n * c.ar_hidden + self.problem.n + c.ar_hidden}[key]
 
@@ -322,6 +344,8 @@ class Context:
         _check(lib().tvmc_get(self.ctx, ctypes.c_int32(what), ctypes.c_int32(traj), out.ctypes.data_as(ctypes.c_void_p),
                               ctypes.c_size_t(out.nbytes)), self.ctx)
         out = out[:cnt]
+        if what in (Q_SAMPLES, Q_CHAINS) and self.words > 1:
+            out = out.reshape(-1, self.words)
         if what == Q_S:
             out = out.reshape(self.solve_dim, self.solve_dim)
         if what == Q_OBS_HIST:
@@ -355,6 +379,11 @@ class Context:
 
 
 def unpack_samples(words: np.ndarray, n: int) -> np.ndarray:
-    """uint64 configuration words -> int8 spins (+1 where the bit is set)."""
-    bits = (np.asarray(words, dtype=np.uint64)[:, None] >> np.arange(n, dtype=np.uint64)[None, :]) & np.uint64(1)
+    """uint64 configuration words ([count] or [count, words]: site i in bit i % 64 of word i // 64)
+    -> int8 spins [count, n] (+1 where the bit is set)."""
+    w = np.asarray(words, dtype=np.uint64)
+    if w.ndim == 1:
+        w = w[:, None]
+    site = np.arange(n)
+    bits = (w[:, site // 64] >> (site % 64).astype(np.uint64)[None, :]) & np.uint64(1)
     return np.where(bits == 1, 1, -1).astype(np.int8)

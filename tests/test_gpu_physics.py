@@ -136,3 +136,76 @@ def test_n64_linear_sse_is_unbiased_and_noisier(orc):
                 assert abs(q[:, k].mean() - 1) < 4 * q[:, k].std() / np.sqrt(TT)
     for k in range(1, nobs + 1):
         assert se_mx[(T.SSE_LINEAR, k)] > 10 * se_mx[(T.SSE_NONLINEAR, k)]
+
+
+def _history(ctx, TT, nobs):
+    from paper_2506_23928_amd import tvmc as T
+    hist = np.stack([ctx.get(T.Q_OBS_HIST, t) for t in range(TT)])[:, :nobs]
+    final = np.stack([ctx.get(T.Q_MOMENTS, t) for t in range(TT)])
+    return np.concatenate([hist, final[:, None]], axis=1)
+
+
+def _run_workload(tv, name, steps, precision, proposal=None, **over):
+    import bench
+    import workloads as wl
+    w = dict(wl.WORKLOADS[name])
+    w.update(over)
+    w["name"] = name
+    w["t_end"] = steps * w["dt"]
+    ctx = bench.build_context(tv, w, precision, proposal=proposal)
+    ctx.sde_step(steps)
+    ctx.sample()
+    ctx.observables()
+    ctx.synchronize()
+    mom = _history(ctx, w["n_traj"], steps // w["obs_every"])
+    del ctx
+    return w, mom
+
+
+def test_benchmark_form_through_the_squeezing_minimum(orc):
+    """The benchmark's form itself (RBM N' = 64, BF16-split S, learned proposal; N = 64 open chain,
+    alpha = 1.5, h = 0, decay 0.1, 8192 samples, 64 trajectories, dt = 0.01) against App. D at
+    every output time up to t = 0.5, past the squeezing minimum (t ~ 0.4).  Budget: 4 jackknife
+    errors plus the systematic errors assigned in the design notes: 5e-3 in xi^2 up to t = 0.3
+    (time step), 0.02 at t = 0.4 and 0.5 (the RBM's variational error, the same in the FP64
+    single-flip form); 2e-3 in M_x."""
+    import torch
+    assert torch.cuda.is_available()
+    import oracle.exact as ex
+    import paper_2506_23928_amd as tv
+    w, mom = _run_workload(tv, "chain64_rbm_learned", 50, tv.PREC_MFMA)
+    n = w["n"]
+    Jo = orc.couplings("obc", n, 1.5, 1.0)
+    x2s = []
+    for k in range(1, mom.shape[1]):
+        t = k * w["obs_every"] * w["dt"]
+        M, C, x2 = orc.ensemble(mom[:, k], n)
+        Me, Ce = ex.appd_general(Jo, w["decay"], t)
+        xe = ex.xi2(Me, Ce, n)
+        se_x2 = _jack(mom[:, k], lambda v: orc.ensemble(v, n)[2])
+        se_mx = _jack(mom[:, k, 0], lambda v: v.mean())
+        assert abs(M[0] - Me[0]) < 4 * se_mx + 2e-3, (t, M[0], Me[0], se_mx)
+        assert abs(x2 - xe) < 4 * se_x2 + (5e-3 if t < 0.35 else 0.02), (t, x2, xe, se_x2)
+        x2s.append(x2)
+    assert np.argmin(x2s) >= 3          # the minimum of the squeezing is inside the window
+
+
+def test_precision_form_observables(orc):
+    """The precision form's error per observable: the RBM workload (N = 64, N' = 64, 4096 samples,
+    16 trajectories, single flips) with the BF16-split S against the FP64 S on the same seeds, to
+    t = 0.3: M_x, M_y, M_z, xi^2 and the covariance entries differ by less than 2 jackknife errors
+    of either at every output time (they start bit-identical and separate only as accept
+    decisions diverge)."""
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2506_23928_amd as tv
+    over = dict(n_traj=16, n_samples=4096)
+    w, m64 = _run_workload(tv, "chain64_rbm_learned", 30, tv.PREC_FP64, proposal=tv.PROPOSAL_FLIP, **over)
+    _, mbf = _run_workload(tv, "chain64_rbm_learned", 30, tv.PREC_MFMA, proposal=tv.PROPOSAL_FLIP, **over)
+    n = w["n"]
+    for k in range(1, m64.shape[1]):
+        for f in (lambda v: orc.ensemble(v, n)[2],) + tuple((lambda v, q=q: orc.ensemble(v, n)[0][q]) for q in range(3)) + \
+                tuple((lambda v, i=i, j=j: orc.ensemble(v, n)[1][i, j]) for i in range(3) for j in range(i, 3)):
+            a, b = f(m64[:, k]), f(mbf[:, k])
+            se = max(_jack(m64[:, k], f), _jack(mbf[:, k], f))
+            assert abs(a - b) < 2 * se + 1e-12, (k, a, b, se)

@@ -8,6 +8,8 @@ scheme the paper cites and does not reproduce, so it is pinned by what fixes it 
   one spin (M = 1) with the closed-form local energy h exp(-2 a s): the filter by hand
   G scaled by c (dt -> c dt, no jumps): SNR unchanged, delta scaled by c
   the Hermitian (RBM) variant: its Jacobi against LAPACK, the tau limits, the scale invariance
+  the whole solve against an independent numpy statement of the same form (oracle/exact.py)
+  why the form biases the h = 0 quench at small N_s: it cuts components that are exact
 """
 import numpy as np
 import pytest
@@ -134,3 +136,85 @@ def test_rbm_scale_invariance(orc):
     assert np.allclose(np.sort(r1["eig"][:, 0]), np.sort(r2["eig"][:, 0]), rtol=1e-12, atol=0)
     assert np.allclose(np.sort(r1["eig"][:, 1]), np.sort(r2["eig"][:, 1]), rtol=1e-8, atol=0)
     assert np.abs(r2["delta"] - 3 * r1["delta"]).max() < 1e-12 * np.abs(r2["delta"]).max()
+
+
+def _jastrow_features(s):
+    """O_k(x) of the all-pair Jastrow straight from the spins: s_i, then s_j s_k for j < k in
+    the parameter order (independent of the oracle's log-derivative code)."""
+    s = np.asarray(s, np.float64)
+    n = s.shape[1]
+    cols = [s[:, i] for i in range(n)] + [s[:, j] * s[:, k] for j in range(n) for k in range(j + 1, n)]
+    return np.stack(cols, axis=1)
+
+
+@pytest.mark.parametrize("kind,n,nh,ns,tau,eps,seed", [
+    (0, 6, 0, 512, 4.0, 1e-4, 1), (0, 7, 0, 256, 2.0, 1e-3, 2), (0, 5, 0, 1024, 4.0, 0.0, 3),
+    (1, 5, 3, 512, 4.0, 1e-4, 4), (1, 6, 3, 384, 3.0, 1e-3, 5), (2, 8, 1, 512, 4.0, 1e-4, 6)])
+def test_snr_solve_matches_independent_statement(orc, kind, n, nh, ns, tau, eps, seed):
+    """The C oracle's SNR solve (cyclic Jacobi, loops) against the vectorised numpy statement of
+    the same reading (LAPACK eigh, per-sample contributions as arrays), element by element, on
+    random problems with sigma^-, sigma^+ and sigma^z channels and nonzero Wiener increments:
+    S and D rebuilt from the per-sample O and G, the sorted eigenvalues, the SNR of each
+    eigencomponent, and delta.  Real symmetric S (all-pair Jastrow, LJPH1) and complex Hermitian
+    S (RBM)."""
+    import oracle.exact as ex
+    import workloads as wl
+    J, hx, jumps = wl.random_problem(n, seed=50 + seed)
+    pb = orc.Problem(J, hx, jumps)
+    m = orc.n_params(kind, n, nh)
+    th = wl.random_theta(m, 0.15, seed=seed)
+    dt = 0.01
+    dw = orc.draw_dw(seed, 0, 0, len(jumps), dt)
+    c = orc.Config(n_samples=ns, n_chains=8, seed=seed, init_sweeps=10, dt=dt, diag_shift=eps,
+                   regulariser=orc.REG_SNR, snr_tau=tau)
+    r = orc.evaluate(pb, kind, nh, c, th, orc.init_chains(seed, 0, n, 8), dw=dw)
+    assert r["status"] == 0
+    smp = r["samples"]
+    O = np.stack([orc.local_quantities(kind, n, nh, th, smp[x], two_flip=False)[2] for x in range(ns)])
+    if kind == 0:
+        assert np.array_equal(O.real, _jastrow_features(smp)) and not O.imag.any()
+    delta, lam, snr, S, D = ex.snr_solve(O, r["G"], eps, tau)
+    assert np.abs(S - (r["S"] if kind == 1 else r["S"].real)).max() < 1e-13 * np.abs(S).max()
+    assert np.abs(D - r["D"]).max() < 1e-13 * np.abs(D).max()
+    eo = r["eig"]
+    order = np.argsort(eo[:, 0])
+    assert np.abs(eo[order, 0] - lam).max() < 1e-12 * lam.max()
+    # SNR is defined per eigencomponent: compare where the eigenvalue is well separated
+    gap = np.minimum(np.diff(lam, prepend=-np.inf), np.diff(lam, append=np.inf))
+    sep = gap > 1e-6 * lam.max()
+    assert sep.sum() >= m // 2
+    fin = sep & np.isfinite(snr)
+    assert np.abs(eo[order, 1][fin] - snr[fin]).max() < 1e-7 * np.abs(snr[fin]).max()
+    assert (snr[fin] < tau).any() and (snr[fin] > tau).any()     # the filter acts on both sides
+    assert np.abs(delta - r["delta"]).max() < 1e-9 * np.abs(delta).max()
+
+
+def test_snr_filter_cuts_components_that_are_exact(orc):
+    """What biases the SNR-filtered quench at h = 0 (the reading of the filter taken here): the
+    local energy is then linear in the pair log-derivatives, E_H(x) - <E_H> = sum_l J_l (O_l(x)
+    - <O_l>), so F = S J on every sample set and the shift solve returns the exact increment
+    -i J dt (up to eps) whatever the samples.  The filter instead measures each eigencomponent's
+    SNR as if the sample fluctuations of rho = V^T D were independent of those of S; a weak
+    long-distance pair then has SNR ~ |J_jk| sqrt(N_s) / std(E_H) < 4 and is cut although it is
+    exact.  The number of kept components grows with N_s (as sqrt(N_s) in the SNR).  N = 10
+    periodic chain, alpha = 1 (the setting of the paper's N = 10 comparison), no jumps."""
+    n, dt = 10, 0.01
+    J = orc.couplings("pbc", n, 1.0, 1.0)
+    pb = orc.Problem(J, 0.0, [])
+    m = orc.n_params(0, n)
+    pairs = [(j, k) for j in range(n) for k in range(j + 1, n)]
+    exact = np.array([-1j * dt * J[j, k] for j, k in pairs])
+    kept, err_snr = {}, {}
+    for ns in (1024, 16384):
+        c0 = orc.Config(n_samples=ns, n_chains=16, seed=2, dt=dt, diag_shift=1e-6)
+        cs = orc.Config(n_samples=ns, n_chains=16, seed=2, dt=dt, diag_shift=1e-6, regulariser=orc.REG_SNR,
+                        snr_tau=4.0)
+        r0 = orc.evaluate(pb, 0, 0, c0, np.zeros(m), orc.init_chains(2, 0, n, 16))
+        rs = orc.evaluate(pb, 0, 0, cs, np.zeros(m), orc.init_chains(2, 0, n, 16))
+        assert r0["status"] == 0 and rs["status"] == 0
+        assert np.abs(r0["delta"][n:] - exact).max() < 1e-4 * np.abs(exact).max()   # exact up to eps
+        kept[ns] = int((rs["eig"][:, 1] > 4.0).sum())
+        err_snr[ns] = np.abs(rs["delta"][n:] - exact).max() / np.abs(exact).max()
+    assert kept[1024] < kept[16384] <= m
+    assert kept[1024] < 0.6 * m                 # at 1024 samples most components are cut
+    assert err_snr[1024] > 0.1 and err_snr[16384] < err_snr[1024]

@@ -53,10 +53,23 @@ WORKLOADS = {
                              ansatz="rbm", n_hidden=256, n_samples=4096, n_chains=64, n_traj=32, dt=0.01,
                              t_end=1.0, diag_shift=1e-4, obs_every=10, burn_sweeps=2, thin_sweeps=1, seed=0,
                              proposal="flip", w_scale=0.01),
+    # The sample-space configuration at its stated shape: 2D 10x10 open lattice (N = 100, two
+    # configuration words), alpha = 3, h = 1, decay 0.1, RBM with hidden density 2 (N' = 200,
+    # 20300 complex parameters, weights N(0, 0.01)), 4096 samples x 32 trajectories, solved through
+    # the 4096 x 4096 sample-space kernel
+    "lattice10x10_rbm_ss": dict(geom="2d", n=100, ly=10, alpha=3.0, jscale=1.0, h=1.0, decay=0.1, dephase=0.0,
+                                ansatz="rbm", n_hidden=200, n_samples=4096, n_chains=64, n_traj=32, dt=0.01,
+                                t_end=1.0, diag_shift=1e-4, obs_every=10, burn_sweeps=2, thin_sweeps=1, seed=0,
+                                proposal="flip", w_scale=0.01),
+    # The paper's N = 100 quench (the transverse-field figure's setting at h = 0, where App. D is
+    # exact): periodic chain (nearest replica), alpha = 1, decay kappa = 0.27, LJPH1 (297
+    # parameters), 4096 samples x 64 trajectories, dt = 0.005
+    "chain100_ljph1": dict(geom="pbc", n=100, alpha=1.0, jscale=1.0, h=0.0, decay=0.27, dephase=0.0, ansatz="ljph",
+                           d=1, n_samples=4096, n_chains=64, n_traj=64, dt=0.005, t_end=1.0, diag_shift=1e-4,
+                           obs_every=20, burn_sweeps=2, thin_sweeps=1, seed=0),
     # 2D 8x8 open lattice, alpha = 3, h = 1, decay 0.1, RBM with hidden density 2 (N' = 128, 8384
     # complex parameters, weights N(0, 0.01)), 4096 samples x 32 trajectories: M > N_s, the
-    # sample-space solve through the 4096 x 4096 kernel.  The paper-shaped 10x10 lattice (N = 100)
-    # needs two 64-bit configuration words; 8x8 is the largest square one word holds.
+    # sample-space solve through the 4096 x 4096 kernel (the 10x10 shape at one configuration word)
     "lattice8x8_rbm_ss": dict(geom="2d", n=64, ly=8, alpha=3.0, jscale=1.0, h=1.0, decay=0.1, dephase=0.0,
                               ansatz="rbm", n_hidden=128, n_samples=4096, n_chains=64, n_traj=32, dt=0.01,
                               t_end=1.0, diag_shift=1e-4, obs_every=10, burn_sweeps=2, thin_sweeps=1, seed=0,
