@@ -200,6 +200,21 @@ tvmc_status tvmc_init_batch(const tvmc_problem *problems, int32_t n_problems, co
                             const tvmc_config *config, const double *theta0, void *d_workspace,
                             size_t workspace_bytes, void *stream, tvmc_ctx **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): tvmc_init with the library's own static workspace in
+ * place of a caller-allocated one.  The workspace is a device array of tvmc_static_workspace_bytes
+ * bytes (64 MiB) that every device loading the library holds until the process ends; a problem
+ * needing more (tvmc_workspace_size) returns TVMC_E_NOMEM.  One problem shared by every
+ * trajectory; the context works on the current device and runs every solve on `stream` (no side
+ * streams or events are created).  No device memory is allocated.  A device's static workspace
+ * serves one live context at a time: a second tvmc_init_static on that device returns
+ * TVMC_E_STATE until the first is destroyed (contexts on one device would otherwise overwrite
+ * each other's state).  It keeps the last context's contents; tvmc_init_static clears or writes
+ * everything a run reads before it is read, as tvmc_init does. */
+tvmc_status tvmc_static_workspace_bytes(size_t *bytes);
+tvmc_status tvmc_init_static(const tvmc_problem *problem, const tvmc_ansatz *ansatz, const tvmc_config *config,
+                             const double *theta0, void *stream, tvmc_ctx **out);
+
 /* Metropolis sampling of |psi|^2 at the current evaluation point (text after Eq. 9); at the
  * predictor stage it also draws the step's Wiener increments.  Requires the stage to be ready. */
 tvmc_status tvmc_sample(tvmc_ctx *ctx);

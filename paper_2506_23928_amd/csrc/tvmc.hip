@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -55,6 +56,7 @@ struct tvmc_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     char err[512] = {0};
+    int static_dev = -1;   // device whose static workspace this context uses (tvmc_init_static), or -1
     bool timing = false;
     std::vector<std::string> groups;
     std::vector<Timer> timers;
@@ -813,8 +815,15 @@ tvmc_status tvmc_workspace_size(const tvmc_problem *p, const tvmc_ansatz *a, con
     return tvmc_workspace_size_batch(p, 1, a, c, bytes);
 }
 
-tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansatz *a, const tvmc_config *c,
-                            const double *theta0, void *ws, size_t ws_bytes, void *stream, tvmc_ctx **out) {
+}  // extern "C"
+
+namespace {
+
+// Context creation shared by tvmc_init_batch and tvmc_init_static; side_streams = false keeps
+// every solve on the caller's stream (no stream or event is created).
+tvmc_status init_impl(const tvmc_problem *pbs, int32_t np, const tvmc_ansatz *a, const tvmc_config *c,
+                      const double *theta0, void *ws, size_t ws_bytes, void *stream, bool side_streams,
+                      tvmc_ctx **out) {
     if (!out) return TVMC_E_INVAL;
     *out = nullptr;
     tvmc_status st = check_batch(pbs, np, a, c, g_err, sizeof(g_err));
@@ -1012,14 +1021,75 @@ tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansa
         hipLaunchKernelGGL(k_ar_copy, dim3((d.ah * n + 255) / 256, T), dim3(256), 0, ctx->stream, d);
         INITCHECK(hipGetLastError());
     }
-    for (int g = 0; g < NSIDE; ++g) {
-        INITCHECK(hipStreamCreateWithFlags(&ctx->side[g], hipStreamNonBlocking));
-        INITCHECK(hipEventCreateWithFlags(&ctx->join[g], hipEventDisableTiming));
+    if (side_streams) {
+        for (int g = 0; g < NSIDE; ++g) {
+            INITCHECK(hipStreamCreateWithFlags(&ctx->side[g], hipStreamNonBlocking));
+            INITCHECK(hipEventCreateWithFlags(&ctx->join[g], hipEventDisableTiming));
+        }
+        INITCHECK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
     }
-    INITCHECK(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
     INITCHECK(hipStreamSynchronize(ctx->stream));
 #undef INITCHECK
     *out = ctx;
+    return TVMC_OK;
+}
+
+// The static workspace of tvmc_init_static: one array per device (each device that loads the
+// library holds its own copy until the process ends).  Host code never uses the array's name as
+// an address: the device address comes from hipGetSymbolAddress, once per device, with that
+// device current.  At most one live context per device uses it.
+constexpr size_t STATIC_BYTES = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[STATIC_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[MAX_DEVICES] = {};
+bool g_static_busy[MAX_DEVICES] = {};
+
+}  // namespace
+
+extern "C" {
+
+tvmc_status tvmc_init_batch(const tvmc_problem *pbs, int32_t np, const tvmc_ansatz *a, const tvmc_config *c,
+                            const double *theta0, void *ws, size_t ws_bytes, void *stream, tvmc_ctx **out) {
+    return init_impl(pbs, np, a, c, theta0, ws, ws_bytes, stream, true, out);
+}
+
+tvmc_status tvmc_static_workspace_bytes(size_t *bytes) {
+    if (!bytes) return TVMC_E_INVAL;
+    *bytes = STATIC_BYTES;
+    return TVMC_OK;
+}
+
+tvmc_status tvmc_init_static(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_config *c, const double *theta0,
+                             void *stream, tvmc_ctx **out) {
+    if (!out) return TVMC_E_INVAL;
+    *out = nullptr;
+    size_t need = 0;
+    tvmc_status st = tvmc_workspace_size(p, a, c, &need);
+    if (st != TVMC_OK) return st;
+    if (need > STATIC_BYTES)
+        return snprintf(g_err, sizeof(g_err), "tvmc_init_static: the problem needs %zu bytes of workspace, more than the "
+                        "static %zu", need, STATIC_BYTES), TVMC_E_NOMEM;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+        return snprintf(g_err, sizeof(g_err), "tvmc_init_static: no usable current device"), TVMC_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_busy[dev])
+        return snprintf(g_err, sizeof(g_err), "tvmc_init_static: device %d's static workspace is held by a live "
+                        "context (destroy it first)", dev), TVMC_E_STATE;
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return snprintf(g_err, sizeof(g_err), "tvmc_init_static: hipGetSymbolAddress failed: %s",
+                            hipGetErrorString(e)), TVMC_E_DEVICE;
+        g_static_ptr[dev] = ptr;
+    }
+    st = init_impl(p, 1, a, c, theta0, g_static_ptr[dev], STATIC_BYTES, stream, false, out);
+    if (st != TVMC_OK) return st;
+    (*out)->static_dev = dev;
+    g_static_busy[dev] = true;
     return TVMC_OK;
 }
 
@@ -1421,6 +1491,10 @@ tvmc_status tvmc_destroy(tvmc_ctx *c) {
         if (c->join[g]) (void)hipEventDestroy(c->join[g]);
     }
     if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_busy[c->static_dev] = false;
+    }
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     for (auto &t : c->timers) {

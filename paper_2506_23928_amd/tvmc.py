@@ -60,7 +60,8 @@ _lib = None
 EXPORTED = ["tvmc_workspace_size", "tvmc_init", "tvmc_workspace_size_batch", "tvmc_init_batch", "tvmc_sample", "tvmc_estimate", "tvmc_sr_solve", "tvmc_update",
             "tvmc_sde_step", "tvmc_train_proposal", "tvmc_observables", "tvmc_ensemble", "tvmc_ensemble_at", "tvmc_get", "tvmc_set", "tvmc_position",
             "tvmc_synchronize", "tvmc_set_timing", "tvmc_timing", "tvmc_last_error", "tvmc_destroy",
-            "tvmc_state_size", "tvmc_save_state", "tvmc_load_state"]
+            "tvmc_state_size", "tvmc_save_state", "tvmc_load_state", "tvmc_static_workspace_bytes",
+            "tvmc_init_static"]
 
 
 def lib():
@@ -144,6 +145,25 @@ def tvmc_init(problem, ansatz, config, theta0, workspace_ptr, workspace_bytes, s
     _check(lib().tvmc_init(ctypes.byref(pc), ctypes.byref(ansatz), ctypes.byref(config),
                            th.ctypes.data_as(_dp) if th is not None else None, ctypes.c_void_p(workspace_ptr),
                            ctypes.c_size_t(workspace_bytes), ctypes.c_void_p(stream), ctypes.byref(ctx)))
+    return ctx
+
+
+def tvmc_static_workspace_bytes() -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().tvmc_static_workspace_bytes(ctypes.byref(b)))
+    return b.value
+
+
+def tvmc_init_static(problem, ansatz, config, theta0, stream):
+    """tvmc_init on the library's static device workspace (no device allocation)."""
+    ctx = ctypes.c_void_p()
+    pc = problem.c()
+    th = None
+    if theta0 is not None:
+        th = np.ascontiguousarray(np.asarray(theta0, dtype=np.complex128)).view(np.float64)
+    _check(lib().tvmc_init_static(ctypes.byref(pc), ctypes.byref(ansatz), ctypes.byref(config),
+                                  th.ctypes.data_as(_dp) if th is not None else None, ctypes.c_void_p(stream),
+                                  ctypes.byref(ctx)))
     return ctx
 
 
@@ -240,7 +260,7 @@ class Context:
                Q_LOGNORM_HIST: ("d", "nobs"), Q_EIG: ("d", "2m"), Q_AR_LOGQ_BF16: ("f", "ns")}
 
     def __init__(self, problem: Problem, config: tvmc_config, kind=JASTROW, n_hidden=0, theta0=None, device="cuda",
-                 stream=None):
+                 stream=None, static_workspace=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required")
@@ -250,6 +270,14 @@ class Context:
         self.config = config
         self.ansatz = make_ansatz(kind, n_hidden)
         self.m = n_params(kind, self.problem.n, n_hidden)
+        if static_workspace:        # the library's static device workspace: nothing is allocated here
+            if batch:
+                raise ValueError("the static workspace takes one shared problem")
+            self.workspace = None
+            self.stream = stream if stream is not None else torch.cuda.current_stream()
+            self.ctx = tvmc_init_static(self.problem, self.ansatz, config, theta0, self.stream.cuda_stream)
+            self._lib = lib()
+            return
         nbytes = tvmc_workspace_size_batch(self.problems, self.ansatz, config)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         ptr = self.workspace.data_ptr()
