@@ -576,7 +576,7 @@ def main():
         "metric": "trajectory-steps/s at N=64 (batched+learned vs plain) at fixed xi^2 error",
         "value": value, "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if (prec == tv.PREC_FP64 or kind != tv.RBM) else "f64+bf16x3",
+        "dtype": "f64" if (prec == tv.PREC_FP64 or kind != tv.RBM or ss) else "f64+bf16x3",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_spins": n, "n_params": m, "n_traj": T, "n_samples": w["n_samples"],
                    "n_chains": w["n_chains"], "n_jumps": len(wl.jumps(w)), "dt": w["dt"],

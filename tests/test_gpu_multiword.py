@@ -172,3 +172,57 @@ def test_two_word_limits(tv):
         tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, proposal=T.PROPOSAL_LEARNED, ar_hidden=32))
     with pytest.raises(T.TvmcError):
         tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, regulariser=T.REG_SNR))
+
+
+def test_lattice10x10_full_size_launch(tv, orc):
+    """The sample-space configuration at its stated shape (10 x 10 open lattice, N = 100 in two
+    words, alpha = 3, RBM N' = 200, M = 20300, 4096 samples x 32 trajectories) in the benchmark's
+    launch configuration.  For the last trajectory: the samples bit for bit against the oracle,
+    T against the closed form (1 + q)(1 + g) - 1 centred, built from the oracle's samples, and the
+    increment against the parameter-space normal equations A^H (A delta) + eps delta = D with
+    A = (O - <O>) / sqrt(N_s), applied through the RBM's factored O = (s, t, s t^T) rather than
+    the 4096 x 20300 matrix."""
+    from paper_2506_23928_amd import tvmc as T
+    import bench
+    w = dict(wl.WORKLOADS["lattice10x10_rbm_ss"])
+    ctx = bench.build_context(tv, w, tv.PREC_FP64)
+    n, nh, ns, TT = w["n"], w["n_hidden"], w["n_samples"], w["n_traj"]
+    assert ctx.sample_space and ctx.words == 2
+    ctx.sample()
+    ctx.estimate()
+    t = TT - 1
+    Tg = ctx.get(T.Q_S, t)
+    ctx.sr_solve()
+    ctx.synchronize()
+    th0 = wl.rbm_theta0(n, nh, w["w_scale"], w["seed"])
+    lx, ly = wl.lattice(w)
+    pb = orc.Problem(orc.couplings(w["geom"], lx, w["alpha"], w["jscale"], ly), w["h"], wl.jumps(w))
+    cfg_o = orc.Config(n_samples=ns, n_chains=w["n_chains"], burn_sweeps=w["burn_sweeps"],
+                       thin_sweeps=w["thin_sweeps"], dt=w["dt"], diag_shift=w["diag_shift"], seed=w["seed"])
+    r = orc.evaluate(pb, 1, nh, cfg_o, th0, orc.init_chains(w["seed"], t, n, w["n_chains"]), traj=t,
+                     first=True, want_solve=0, want_moments=False)
+    smp = r["samples"]
+    assert np.array_equal(tv.unpack_samples(ctx.get(T.Q_SAMPLES, t), n), smp)
+    s = smp.astype(np.float64)
+    b, wm = th0[n:n + nh], th0[n + nh:].reshape(n, nh)
+    tt = np.tanh(b[None, :] + s @ wm)
+    K = (1.0 + s @ s.T) * (1.0 + tt @ tt.conj().T) - 1.0
+    H = np.eye(ns) - 1.0 / ns
+    Tc = H @ K @ H / ns + w["diag_shift"] * np.eye(ns)
+    low = np.tril_indices(ns)
+    assert np.abs(Tg[low] - Tc[low]).max() < 1e-12 * np.abs(Tc).max()
+    del K, H, Tc, Tg
+    # A delta and A^H v with O(x) = (s(x), t(x), vec(s(x) t(x)^T)), centred, / sqrt(N_s)
+    d = ctx.get(T.Q_DELTA0, t)
+    D = ctx.get(T.Q_D, t)
+    da, db, dw = d[:n], d[n:n + nh], d[n + nh:].reshape(n, nh)
+    Od = s @ da + tt @ db + np.einsum("xi,ij,xj->x", s, dw, tt)
+    Ad = (Od - Od.mean()) / np.sqrt(ns)
+    v = Ad / np.sqrt(ns)
+    ob_s, ob_t = s.mean(0), tt.mean(0)
+    ob_w = (s.T @ tt) / ns
+    vs = v.sum()
+    AhAd = np.concatenate([s.T @ v - ob_s * vs, tt.conj().T @ v - ob_t.conj() * vs,
+                           (s.T @ (v[:, None] * tt.conj()) - ob_w.conj() * vs).reshape(-1)])
+    res = AhAd + w["diag_shift"] * d - D
+    assert np.abs(res).max() < 1e-8 * np.abs(D).max()

@@ -209,3 +209,27 @@ def test_precision_form_observables(orc):
             a, b = f(m64[:, k]), f(mbf[:, k])
             se = max(_jack(m64[:, k], f), _jack(mbf[:, k], f))
             assert abs(a - b) < 2 * se + 1e-12, (k, a, b, se)
+
+
+def test_n100_ljph1_matches_appendix_d(orc):
+    """The paper's N = 100 quench at h = 0 (periodic chain, nearest replica, alpha = 1, decay
+    kappa = 0.27; two configuration words): LJPH1 (297 parameters), 4096 samples, 64
+    trajectories, int8 S-build, dt = 0.005, against App. D up to t = 0.3 with the N = 64 tests'
+    budget (4 jackknife errors plus 1e-3 in M_x and 5e-3 in xi^2)."""
+    import torch
+    assert torch.cuda.is_available()
+    import oracle.exact as ex
+    import paper_2506_23928_amd as tv
+    w, mom = _run_workload(tv, "chain100_ljph1", 60, tv.PREC_MFMA)
+    n = w["n"]
+    Jo = orc.couplings("pbc", n, 1.0, 1.0)
+    for k in range(1, mom.shape[1]):
+        t = k * w["obs_every"] * w["dt"]
+        M, C, x2 = orc.ensemble(mom[:, k], n)
+        Me, Ce = ex.appd_general(Jo, w["decay"], t)
+        xe = ex.xi2(Me, Ce, n)
+        se_x2 = _jack(mom[:, k], lambda v: orc.ensemble(v, n)[2])
+        se_mx = _jack(mom[:, k, 0], lambda v: v.mean())
+        assert abs(M[0] - Me[0]) < 4 * se_mx + 1e-3, (t, M[0], Me[0], se_mx)
+        assert abs(x2 - xe) < 4 * se_x2 + 5e-3, (t, x2, xe, se_x2)
+        assert xe < 0.9
