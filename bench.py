@@ -162,6 +162,68 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, solver_arg):
+    """The dominant kernel group's algorithmic work per launch (every trajectory of the context)
+    over its average launch time (HIP events on the library's stream), against the peak of the
+    unit it runs on."""
+    dom = max(groups, key=lambda g: groups[g]["total_ms"]) if groups else None   # None: graph replays, untimed
+    dim = ns if ss else m                 # dimension of the system solved
+    if dom == "solve" and reg == tv.tvmc.REG_SNR:
+        # Jacobi: per sweep M' - 1 rounds rotating every row of S and V^T and every column of S
+        # (12 flops per rotated pair of entries); the sweep count is not known here, so the
+        # figure is per sweep and the fraction is left out
+        roof = {"kernel": "k_jacobi", "bound": "alu", "achieved": None, "peak": PEAKS["fp64"], "unit": "TFLOP/s",
+                "frac": None, "traffic": None, "note": "SNR solve: Jacobi sweeps until converged"}
+    elif dom == "solve":
+        if kind == tv.RBM:   # complex Hermitian Cholesky (4/3 n^3 real flops) and two triangular solves
+            flops = T * (4.0 * dim ** 3 / 3.0 + 16.0 * dim * dim)
+            kname = "k_zmw_solve"     # k_zmw_init, k_zmw_update, k_zmw_diag, k_zmw_trsm, k_zmw_backward
+        else:
+            flops = T * (dim ** 3 / 3.0 + dim * dim / 2.0 + dim / 6.0 + 4.0 * dim * dim)
+            multi = solver_arg == "multi" or (solver_arg != "one" and T < 192)
+            kname = "k_cmw_solve" if multi else "k_chol_solve"   # k_cmw_*: the several-workgroup launches
+        if ss:               # push-back delta = A^H u: M x N_s complex multiply-adds
+            flops += T * 8.0 * m * ns
+        achieved = flops / (groups["solve"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": kname, "bound": "mfma", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic(kname),
+                "note": "one evaluation's solve (every launch of the solver for all trajectories)"}
+    elif dom == "sbuild" and ss and kind == tv.RBM:
+        # K = (1 + q)(1 + g) - 1 with g = t t^H over N' hidden units: N_s^2 N' complex multiply-adds
+        flops = T * 8.0 * ns * ns * nh
+        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_tk_rbm", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_tk_rbm")}
+    elif dom == "sbuild" and kind == tv.RBM and prec == tv.PREC_MFMA:
+        # complex Hermitian S: M (M + 1) / 2 entries, N_s complex multiply-adds (8 flops) each,
+        # on BF16 matrix cores (three split products per real product)
+        flops = T * (m * (m + 1) / 2.0) * ns * 8.0
+        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_sbuild_rbm_bf16", "bound": "mfma", "achieved": achieved, "peak": PEAKS["bf16"] / 3.0,
+                "unit": "TFLOP/s", "frac": achieved / (PEAKS["bf16"] / 3.0), "traffic": read_traffic("k_sbuild_rbm_bf16"),
+                "note": "peak = BF16 dense peak / 3 (three split products per real product)"}
+    elif dom == "sbuild" and kind == tv.RBM:
+        # complex Hermitian S: M (M + 1) / 2 entries, N_s complex multiply-adds (8 flops) each
+        flops = T * (m * (m + 1) / 2.0) * ns * 8.0
+        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_sbuild_rbm_f64", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_sbuild_rbm_f64")}
+    elif dom == "sbuild" and not ss and prec == tv.PREC_FP64:
+        flops = T * (m * (m + 1) / 2.0) * ns * 2.0
+        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_sbuild_f64", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_sbuild_f64")}
+    elif dom == "sbuild" and not ss:
+        ops = T * (m * (m + 1) / 2.0) * ns * 2.0
+        achieved = ops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "k_sbuild_i8", "bound": "mfma", "achieved": achieved, "peak": PEAKS["int8"],
+                "unit": "TOP/s", "frac": achieved / PEAKS["int8"], "traffic": read_traffic("k_sbuild_i8")}
+    else:
+        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None}
+    return roof
+
+
 def tau_int(series):
     """Integrated autocorrelation time of chains' time series [C][L] (mean over chains of the
     normalised autocorrelation, summed with Sokal's self-consistent window W >= 5 tau)."""
@@ -347,6 +409,71 @@ def error_summary(in_dir, workload, autocorr_path=None):
     return out
 
 
+def bench_uneven(tv, args):
+    """The uneven batch: 512 trajectories of open chains with N drawn from {16, 24, 32, 48, 64},
+    alpha and gamma per trajectory (all-pair Jastrow, 2048 samples, int8 S-build), one context per
+    N on its own stream, optionally with each group's plain steps replayed from a captured HIP
+    graph and each group's forms and sampler workgroup shape from the autotuner's cache.  Timed:
+    K whole steps of every trajectory; then two eager steps with per-kernel HIP events give the
+    kernel times of every group and the roofline of the busiest group's dominant kernel."""
+    import torch
+    import workloads as wl
+    from paper_2506_23928_amd.problem import litf_problem
+    from paper_2506_23928_amd.uneven import UnevenBatch
+    w = wl.UNEVEN
+    params = wl.uneven_params(w["n_traj"], seed=w["seed"])
+    probs = [litf_problem(n, a, w["h"], g) for n, a, g in params]
+    conf = dict(n_samples=w["n_samples"], n_chains=w["n_chains"], dt=w["dt"], diag_shift=w["diag_shift"],
+                seed=w["seed"], precision=tv.PREC_MFMA, burn_sweeps=w["burn_sweeps"], thin_sweeps=w["thin_sweeps"],
+                use_graph=int(args.graph))
+    print("bench: uneven batch of %d trajectories, N in %s, graph=%d, autotune=%s" % (
+        w["n_traj"], w["sizes"], int(args.graph), args.autotune), file=sys.stderr, flush=True)
+    ub = UnevenBatch(probs, autotune=args.autotune, **conf)
+    ub.sde_step(max(args.warmup, 1))
+    ub.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ub.sde_step(args.steps)
+    ub.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = w["n_traj"] * args.steps / el
+    print("bench: %d steps in %.3f s -> %.1f trajectory-steps/s" % (args.steps, el, value), file=sys.stderr,
+          flush=True)
+    per_n, busiest = {}, None
+    for n, members, ctx in ub.groups:
+        ctx.set_timing(True)
+    ub.sde_step(2)
+    ub.synchronize()
+    for n, members, ctx in ub.groups:
+        gms = {}
+        for g in ("sample", "estimate", "transpose", "sbuild", "solve", "update"):
+            ms, cnt = ctx.timing(g)
+            if cnt:
+                gms[g] = {"avg_ms": ms, "launches": cnt, "total_ms": ms * cnt}
+        ctx.set_timing(False)
+        tot = sum(v["total_ms"] for v in gms.values())
+        per_n[n] = {"n_traj": len(members), "n_params": ctx.m, "sample_space": bool(ctx.sample_space),
+                    "choice": {k: int(getattr(ctx.config, k)) for k in ("solver", "precision", "sampler_chains")},
+                    "kernel_ms": {g: round(v["avg_ms"], 4) for g, v in gms.items()}, "ms_per_step": tot / 2}
+        if busiest is None or tot > busiest[0]:
+            busiest = (tot, n, ctx, gms)
+    _, n, ctx, gms = busiest
+    roof = roofline_of(tv, gms, tv.JASTROW, tv.PREC_MFMA, ctx.sample_space, ctx.m, w["n_samples"], 0,
+                       ctx.config.n_traj, tv.tvmc.REG_SHIFT, "auto")
+    roof["group"] = "N = %d" % n
+    out = {"metric": "trajectory-steps/s, uneven batch (512 trajectories, N in {16, 24, 32, 48, 64})", "value": value,
+           "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "uneven", "n_traj": w["n_traj"], "sizes": list(w["sizes"]), "n_samples": w["n_samples"],
+                      "n_chains": w["n_chains"], "dt": w["dt"], "ansatz": "jastrow", "s_build": "int8 MFMA (exact)",
+                      "graph": bool(args.graph), "autotune": bool(args.autotune)},
+           "roofline": roof, "groups": {str(k): v for k, v in per_n.items()},
+           "kernel_sources_sha": kernel_sources_sha()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,6 +485,9 @@ def main():
                     help="FP64 Cholesky with one or several workgroups per trajectory (auto: by batch size)")
     ap.add_argument("--regulariser", choices=["shift", "snr"], default="shift",
                     help="diagonal shift (Cholesky) or the SNR filter in S's eigenbasis (Jastrow ansaetze)")
+    ap.add_argument("--autotune", metavar="JSON", default=None,
+                    help="--workload uneven: take each group's forms and sampler shape from this autotuner cache "
+                         "(tuned and written there first when missing)")
     ap.add_argument("--graph", action="store_true",
                     help="replay one captured HIP graph per plain step (per-kernel timing is then off)")
     ap.add_argument("--log", metavar="FILE",
@@ -405,6 +535,9 @@ def main():
     import torch
     import paper_2506_23928_amd as tv
     import workloads as wl
+    if args.workload == "uneven":
+        bench_uneven(tv, args)
+        return
     w = dict(wl.WORKLOADS[args.workload])
     w["name"] = args.workload
     kind, nh, m, _ = ansatz_of(tv, w)
@@ -460,63 +593,8 @@ def main():
     print("bench: %d steps in %.3f s -> %.1f trajectory-steps/s" % (args.steps, el, value), file=sys.stderr,
           flush=True)
 
-    # dominant kernel: the FP64 Cholesky solve (one launch covers every trajectory)
-    dom = max(groups, key=lambda g: groups[g]["total_ms"]) if groups else None   # None: graph replays, untimed
     ss, ns = ctx.sample_space, w["n_samples"]
-    dim = ns if ss else m                 # dimension of the system solved
-    if dom == "solve" and reg == tv.tvmc.REG_SNR:
-        # Jacobi: per sweep M' - 1 rounds rotating every row of S and V^T and every column of S
-        # (12 flops per rotated pair of entries); the sweep count is not known here, so the
-        # figure is per sweep and the fraction is left out
-        roof = {"kernel": "k_jacobi", "bound": "alu", "achieved": None, "peak": PEAKS["fp64"], "unit": "TFLOP/s",
-                "frac": None, "traffic": None, "note": "SNR solve: Jacobi sweeps until converged"}
-    elif dom == "solve":
-        if kind == tv.RBM:   # complex Hermitian Cholesky (4/3 n^3 real flops) and two triangular solves
-            flops = T * (4.0 * dim ** 3 / 3.0 + 16.0 * dim * dim)
-            kname = "k_zmw_solve"     # k_zmw_init, k_zmw_update, k_zmw_diag, k_zmw_trsm, k_zmw_backward
-        else:
-            flops = T * (dim ** 3 / 3.0 + dim * dim / 2.0 + dim / 6.0 + 4.0 * dim * dim)
-            multi = args.solver == "multi" or (args.solver != "one" and T < 192)
-            kname = "k_cmw_solve" if multi else "k_chol_solve"   # k_cmw_*: the several-workgroup launches
-        if ss:               # push-back delta = A^H u: M x N_s complex multiply-adds
-            flops += T * 8.0 * m * ns
-        achieved = flops / (groups["solve"]["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": kname, "bound": "mfma", "achieved": achieved, "peak": PEAKS["fp64"],
-                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic(kname),
-                "note": "one evaluation's solve (every launch of the solver for all trajectories)"}
-    elif dom == "sbuild" and ss and kind == tv.RBM:
-        # K = (1 + q)(1 + g) - 1 with g = t t^H over N' hidden units: N_s^2 N' complex multiply-adds
-        flops = T * 8.0 * ns * ns * nh
-        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": "k_tk_rbm", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
-                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_tk_rbm")}
-    elif dom == "sbuild" and kind == tv.RBM and prec == tv.PREC_MFMA:
-        # complex Hermitian S: M (M + 1) / 2 entries, N_s complex multiply-adds (8 flops) each,
-        # on BF16 matrix cores (three split products per real product)
-        flops = T * (m * (m + 1) / 2.0) * ns * 8.0
-        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": "k_sbuild_rbm_bf16", "bound": "mfma", "achieved": achieved, "peak": PEAKS["bf16"] / 3.0,
-                "unit": "TFLOP/s", "frac": achieved / (PEAKS["bf16"] / 3.0), "traffic": read_traffic("k_sbuild_rbm_bf16"),
-                "note": "peak = BF16 dense peak / 3 (three split products per real product)"}
-    elif dom == "sbuild" and kind == tv.RBM:
-        # complex Hermitian S: M (M + 1) / 2 entries, N_s complex multiply-adds (8 flops) each
-        flops = T * (m * (m + 1) / 2.0) * ns * 8.0
-        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": "k_sbuild_rbm_f64", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
-                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_sbuild_rbm_f64")}
-    elif dom == "sbuild" and not ss and prec == tv.PREC_FP64:
-        flops = T * (m * (m + 1) / 2.0) * ns * 2.0
-        achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": "k_sbuild_f64", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
-                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_sbuild_f64")}
-    elif dom == "sbuild" and not ss:
-        ops = T * (m * (m + 1) / 2.0) * ns * 2.0
-        achieved = ops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": "k_sbuild_i8", "bound": "mfma", "achieved": achieved, "peak": PEAKS["int8"],
-                "unit": "TOP/s", "frac": achieved / PEAKS["int8"], "traffic": read_traffic("k_sbuild_i8")}
-    else:
-        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
-                "traffic": None}
+    roof = roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, args.solver)
     del ctx
     torch.cuda.empty_cache()
 

@@ -5,7 +5,10 @@ interchangeable forms of a step and keeps the fastest, cached in a JSON file per
 
   * the solve: one workgroup per trajectory, several per trajectory (two side streams), or, for
     M > N_s, the sample-space solve (the push-through identity gives the same increment);
-  * for the Jastrow ansaetze the S-build: int8 matrix cores or FP64 (both exact, the same bits).
+  * for the Jastrow ansaetze the S-build: int8 matrix cores or FP64 (both exact, the same bits);
+  * then, with the fastest of those, the sampler's workgroup shape: 1, 2, 4, 8 (or, for the RBM
+    with N' <= 128, 16) Markov chains per workgroup, each chain one wavefront (the samples are
+    the same bits for every shape).
 
 Only forms with the same result are candidates, so tuning changes the speed of a run, never its
 numbers beyond rounding of the solve.  Each candidate runs on a fresh context of its own (the
@@ -30,6 +33,12 @@ def candidates(kind, m, n_samples, regulariser=0):
         solvers.append(tvmc.SOLVER_SAMPLE_SPACE)
     precisions = [tvmc.PREC_MFMA, tvmc.PREC_FP64] if kind != tvmc.RBM else [None]
     return [{"solver": s, **({"precision": p} if p is not None else {})} for s in solvers for p in precisions]
+
+
+def sampler_shapes(kind, n_hidden, n_chains):
+    """Chains per sampler workgroup the library accepts for this shape."""
+    shapes = [1, 2, 4, 8] + ([16] if kind == tvmc.RBM and n_hidden <= 128 else [])
+    return [s for s in shapes if n_chains % s == 0]
 
 
 def _time_steps(problems, kind, n_hidden, config, theta0, steps, device):
@@ -77,8 +86,18 @@ def tune(problems, config: dict, kind=tvmc.JASTROW, n_hidden=0, theta0=None, ste
     if not times:
         raise RuntimeError("no candidate form runs for bucket %s: %s" % (key, last_err))
     best = min(times, key=times.get)
-    choice = dict(kv.split("=") for kv in best.split(","))
-    result = {"bucket": key, "choice": {k: int(v) for k, v in choice.items()}, "ms_per_step": times}
+    choice = {k: int(v) for k, v in (kv.split("=") for kv in best.split(","))}
+    # the sampler's workgroup shape, with the fastest form
+    for sc in sampler_shapes(kind, n_hidden, config["n_chains"]):
+        label = best + ",sampler_chains=%d" % sc
+        try:
+            times[label] = 1e3 * _time_steps(problems, kind, n_hidden, dict(base, **choice, sampler_chains=sc), theta0,
+                                             steps, device)
+        except tvmc.TvmcError as e:
+            last_err = e
+    best = min(times, key=times.get)
+    choice = {k: int(v) for k, v in (kv.split("=") for kv in best.split(","))}
+    result = {"bucket": key, "choice": choice, "ms_per_step": times}
     if cache:
         table[key] = result
         tmp = cache + ".tmp"

@@ -271,6 +271,13 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
     if (c->regulariser != TVMC_REG_SHIFT && c->regulariser != TVMC_REG_SNR)
         return snprintf(msg, len, "bad regulariser"), TVMC_E_INVAL;
     if (c->use_graph != 0 && c->use_graph != 1) return snprintf(msg, len, "bad use_graph"), TVMC_E_INVAL;
+    if (c->sampler_chains != 0) {
+        const int sc = c->sampler_chains;
+        const bool rbm16 = a->kind == TVMC_ANSATZ_RBM && a->n_hidden <= 128;
+        if (!(sc == 1 || sc == 2 || sc == 4 || sc == 8 || (sc == 16 && rbm16)) || c->n_chains % sc)
+            return snprintf(msg, len, "sampler_chains must be 1, 2, 4, 8 (or 16 for the RBM with N' <= 128) and "
+                            "divide n_chains"), TVMC_E_INVAL;
+    }
     if (c->regulariser == TVMC_REG_SNR) {
         if (p->n_sites > 64) return snprintf(msg, len, "the SNR solve takes at most 64 sites"), TVMC_E_INVAL;
         if (c->solver == TVMC_SOLVER_SAMPLE_SPACE)
@@ -388,7 +395,7 @@ tvmc_status run_sample(tvmc_ctx *c) {
         const int qh = (d.nh + 63) / 64;
         // 16 chains per workgroup (4 waves per SIMD, every chain resident at once) where the
         // chain count allows and the per-chain LDS rows fit (N' <= 128)
-        const int cpb = (c->cpb == 8 && d.nc % 16 == 0 && qh <= 2) ? 16 : c->cpb;
+        const int cpb = c->cfg.sampler_chains > 0 ? c->cpb : (c->cpb == 8 && d.nc % 16 == 0 && qh <= 2) ? 16 : c->cpb;
         dim3 grid((d.nc / cpb * T + 7) / 8 * 8);
 #define RBM_LAUNCH(CPB, QH, AR, WL, WD) hipLaunchKernelGGL((k_sample_rbm<CPB, QH, AR, WL, WD>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
 #define RBM_CPB(QH, AR, WL, WD)                         \
@@ -843,7 +850,8 @@ tvmc_status init_impl(const tvmc_problem *pbs, int32_t np, const tvmc_ansatz *a,
     if (!ctx) return TVMC_E_NOMEM;
     ctx->stream = (hipStream_t)stream;
     ctx->cfg = *c;
-    ctx->cpb = c->n_chains % 8 == 0 ? 8 : (c->n_chains % 4 == 0 ? 4 : (c->n_chains % 2 == 0 ? 2 : 1));
+    ctx->cpb = c->sampler_chains > 0 ? c->sampler_chains
+                                     : (c->n_chains % 8 == 0 ? 8 : (c->n_chains % 4 == 0 ? 4 : (c->n_chains % 2 == 0 ? 2 : 1)));
     char *base = (char *)ws;
     Dev &d = ctx->d;
     d.n = n;

@@ -47,7 +47,8 @@ class tvmc_config(ctypes.Structure):
                 ("n_obs_max", ctypes.c_int32), ("seed", ctypes.c_uint64), ("proposal", ctypes.c_int32),
                 ("ar_hidden", ctypes.c_int32), ("ar_train_every", ctypes.c_int32), ("ar_train_iters", ctypes.c_int32),
                 ("ar_lr", ctypes.c_double), ("solver", ctypes.c_int32), ("unravelling", ctypes.c_int32),
-                ("regulariser", ctypes.c_int32), ("snr_tau", ctypes.c_double), ("use_graph", ctypes.c_int32)]
+                ("regulariser", ctypes.c_int32), ("snr_tau", ctypes.c_double), ("use_graph", ctypes.c_int32),
+                ("sampler_chains", ctypes.c_int32)]
 
 
 class TvmcError(RuntimeError):
@@ -121,11 +122,12 @@ def n_params(kind: int, n: int, n_hidden: int = 0) -> int:
 def make_config(n_traj, n_samples, n_chains, dt, diag_shift=1e-4, burn_sweeps=2, thin_sweeps=1, init_sweeps=0,
                 scheme=HEUN, precision=PREC_FP64, obs_every=0, n_obs_max=0, seed=0, traj_offset=0,
                 proposal=PROPOSAL_FLIP, ar_hidden=128, ar_train_every=20, ar_train_iters=50, ar_lr=3e-3,
-                solver=0, unravelling=SSE_NONLINEAR, regulariser=REG_SHIFT, snr_tau=4.0, use_graph=0):
+                solver=0, unravelling=SSE_NONLINEAR, regulariser=REG_SHIFT, snr_tau=4.0, use_graph=0,
+                sampler_chains=0):
     return tvmc_config(n_traj, traj_offset, n_samples, n_chains, burn_sweeps, thin_sweeps, init_sweeps, scheme, dt,
                        diag_shift, precision, obs_every, n_obs_max, ctypes.c_uint64(seed), proposal, ar_hidden,
                        ar_train_every, ar_train_iters, ar_lr, solver, unravelling, regulariser, snr_tau,
-                       int(bool(use_graph)))
+                       int(bool(use_graph)), sampler_chains)
 
 
 # ---------------------------------------------------------------- functions named as in the C ABI

@@ -40,9 +40,10 @@ def test_struct_layouts_match_the_header(tmp_path):
     from paper_2506_23928_amd import tvmc
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tvmc.h"\nint main(){'
-                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tvmc_problem), offsetof(tvmc_problem, jump_rate),'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tvmc_problem), offsetof(tvmc_problem, jump_rate),'
                     'sizeof(tvmc_config), offsetof(tvmc_config, dt), offsetof(tvmc_config, precision),'
                     'offsetof(tvmc_config, seed), offsetof(tvmc_config, unravelling), offsetof(tvmc_config, use_graph),'
+                    'offsetof(tvmc_config, sampler_chains),'
                     'sizeof(tvmc_ansatz));'
                     ' return 0;}\n')
     exe = tmp_path / "layout"
@@ -50,7 +51,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     P, C, A = tvmc.tvmc_problem, tvmc.tvmc_config, tvmc.tvmc_ansatz
     want = [ctypes.sizeof(P), P.jump_rate.offset, ctypes.sizeof(C), C.dt.offset, C.precision.offset, C.seed.offset,
-            C.unravelling.offset, C.use_graph.offset, ctypes.sizeof(A)]
+            C.unravelling.offset, C.use_graph.offset, C.sampler_chains.offset, ctypes.sizeof(A)]
     assert got == want
 
 

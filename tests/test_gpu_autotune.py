@@ -20,7 +20,7 @@ def tv():
     return tv
 
 
-@pytest.mark.parametrize("n,ncand", [(12, 4), (24, 6)])
+@pytest.mark.parametrize("n,ncand", [(12, 4 + 4), (24, 6 + 4)])
 def test_tune_caches_and_keeps_the_numbers(tv, tmp_path, n, ncand):
     from paper_2506_23928_amd import tvmc as T
     from paper_2506_23928_amd.autotune import tune
@@ -30,6 +30,7 @@ def test_tune_caches_and_keeps_the_numbers(tv, tmp_path, n, ncand):
     cache = str(tmp_path / "tune.json")
     r = tune([pb], conf, cache=cache)
     assert len(r["ms_per_step"]) == ncand and all(v > 0 for v in r["ms_per_step"].values())
+    assert r["choice"]["sampler_chains"] in (1, 2, 4, 8)          # the sampler's workgroup shape was tuned
     assert json.load(open(cache))[r["bucket"]] == r
     assert tune([pb], conf, cache=cache) == r                 # from the cache, nothing run
     th = []

@@ -106,3 +106,20 @@ def test_uneven_full_size_launch(tv, orc):
         res = A.T @ (A @ d) + w["diag_shift"] * d - D
         assert np.abs(res).max() < 1e-9 * np.abs(D).max(), n
     assert sorted({c[0] for c in checked}) == list(w["sizes"])
+
+
+def test_uneven_graph_replay_is_the_eager_run(tv, orc):
+    """Each group's plain steps replayed from its captured HIP graph (every group on its own
+    stream) give the eager run's theta bit for bit, with a tuned sampler workgroup shape."""
+    from paper_2506_23928_amd.uneven import UnevenBatch
+    w = dict(wl.UNEVEN, sizes=(8, 16, 24))
+    params = wl.uneven_params(12, seed=5, w=w)
+    gpu, _ = _problems(tv, orc, params, w["h"])
+    conf = dict(n_samples=512, n_chains=16, dt=0.01, diag_shift=1e-4, seed=4, precision=1)
+    eager = UnevenBatch(gpu, **conf)
+    graph = UnevenBatch(gpu, use_graph=1, sampler_chains=4, **conf)
+    for ub in (eager, graph):
+        ub.sde_step(5)
+        ub.synchronize()
+    for i in range(len(params)):
+        assert np.array_equal(eager.theta(i), graph.theta(i)), i
