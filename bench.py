@@ -177,7 +177,7 @@ def roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, solver_arg):
     elif dom == "solve":
         if kind == tv.RBM:   # complex Hermitian Cholesky (4/3 n^3 real flops) and two triangular solves
             flops = T * (4.0 * dim ** 3 / 3.0 + 16.0 * dim * dim)
-            kname = "k_zmw_solve"     # k_zmw_init, k_zmw_update, k_zmw_diag, k_zmw_trsm, k_zmw_backward
+            kname = "k_zmw_solve"     # k_zmw_init, k_zmw_update(_lds), k_zmw_diag, k_zmw_bwd
         else:
             flops = T * (dim ** 3 / 3.0 + dim * dim / 2.0 + dim / 6.0 + 4.0 * dim * dim)
             multi = solver_arg == "multi" or (solver_arg != "one" and T < 192)

@@ -1,10 +1,15 @@
 // Regularised solve for a complex Hermitian S (RBM ansatz): (S + eps I) delta = D with
 // S + eps I = L L^H, in FP64 on the matrix cores, several workgroups per trajectory.  The
 // steps mirror the real solver (left-looking panels of CN = 64 columns, one launch per step):
-//   k_zmw_update(j0):  C[rows, panel] = A[rows, panel] - L[rows, 0:j0] L[panel, 0:j0]^H
+//   k_zmw_update(j0):  for this chunk's rows below the current panel, the previous panel's
+//                      TRSM L[rows, prev] = C Linv_prev^H, z[rows] -= L[rows, prev] y_prev; then
+//                      C[rows, panel] = A[rows, panel] - L[rows, 0:j0] L[panel, 0:j0]^H
 //                      Re C -= Lr Lr'^T + Li Li'^T,  Im C -= Li Lr'^T - Lr Li'^T   (4 real MFMA products)
-//   k_zmw_diag(j0):    L_pp L_pp^H = C_pp in LDS, Linv = L_pp^-1, y_p = Linv z_p
-//   k_zmw_trsm(j0):    L[rows, panel] = C Linv^H, z[rows] -= L[rows, panel] y_p
+//   k_zmw_diag(j0):    L_pp L_pp^H = C_pp in LDS, Linv = L_pp^-1, y_p = Linv z_p, and the TRSM of
+//                      the next panel's rows (the next update reads them as its panel rows)
+//   so a panel takes two launches on the chain of dependent launches instead of three.
+//   k_zmw_update_lds is the same update with its operand slices copied straight into LDS; the
+//   host takes it whenever a trajectory's matrix is under 4 GiB (32-bit byte offsets).
 //   k_zmw_bwd(p):      L^H x = y by row panels: x_p = Linv^H w_p, w_c -= L[p, c]^H x_p (c < j0)
 // Matrices are complex [T][M][M] (lower triangle), interleaved (re, im).
 #pragma once
@@ -32,7 +37,15 @@ constexpr int ZKP = ZK + 1;
 constexpr int ZT = 512;         // threads of k_zmw_update: 8 waves, 16 rows of the 128-row chunk each
 constexpr int ZBUF = 2 * (CR + CN) * ZKP;   // one staging buffer: Ar, Ai [CR][ZKP], Br, Bi [CN][ZKP]
 
-__global__ __launch_bounds__(ZT) void k_zmw_update(ZCholArgs a, int j0) {
+static_assert(2 * ZBUF >= 2 * CN * CSP + 2 * CN, "the staging buffers hold a block inverse and y");
+
+// The TRSM of the previous panel pp for this chunk's rows below the current panel (the
+// diagonal kernel did the current panel's own rows), then the update of the current panel:
+//   X = C[rows, panel pp] Linv_pp^H written over C, z[rows] -= X y_pp;
+//   C[rows, panel] = A[rows, panel] - L[rows, 0:j0] L[panel, 0:j0]^H.
+// pp < 0: no previous panel (j0 = 0).  The TRSM's values are read back by the update loop from
+// global memory after a workgroup barrier (same workgroup, so the barrier orders them).
+__global__ __launch_bounds__(ZT) void k_zmw_update(ZCholArgs a, int j0, int pp) {
     __shared__ double stage[2 * ZBUF];
     const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
@@ -41,6 +54,72 @@ __global__ __launch_bounds__(ZT) void k_zmw_update(ZCholArgs a, int j0) {
     if (r0 >= M) return;
     const int jb = (M - j0) < CN ? (M - j0) : CN;
     double2 *A = a.A + (size_t)t * M * M;
+    if (pp >= 0) {
+        const int jq = j0 - CN;   // the previous panel's columns (a full panel: another follows it)
+        double *Lr = stage, *Li = stage + CN * CSP, *yr = stage + 2 * CN * CSP, *yi = yr + CN;
+        double2 *z = a.x + (size_t)t * M;
+        const double2 *lv = a.linv + ((size_t)t * chol_panels(M) + pp) * CN * CN;
+        for (int e = tid; e < CN * CN; e += ZT) {
+            const double2 l = lv[e];
+            Lr[(e / CN) * CSP + e % CN] = l.x;
+            Li[(e / CN) * CSP + e % CN] = l.y;
+        }
+        if (tid < CN) {
+            const double2 y = z[jq + tid];
+            yr[tid] = y.x;
+            yi[tid] = y.y;
+        }
+        __syncthreads();
+        // rows j0 .. j0 + CN - 1 belong to the diagonal kernel; a wave's 16 rows lie on one side
+        const int wrow = r0 + wave * 16;
+        if (wrow >= j0 + CN && wrow < M) {
+            double2 cf[CN / 4];   // C[row wrow + li][4 ks + lk]
+            {
+                const int row = wrow + li;
+                for (int ks = 0; ks < CN / 4; ++ks)
+                    cf[ks] = row < M ? A[(size_t)row * M + jq + ks * 4 + lk] : make_double2(0.0, 0.0);
+            }
+            v4d xr[4], xi[4];
+            for (int v = 0; v < 4; ++v) {
+                xr[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+                xi[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+            }
+            for (int ks = 0; ks < CN / 4; ++ks) {
+                double fbr[4], fbi[4];
+                for (int v = 0; v < 4; ++v) {
+                    fbr[v] = Lr[(v * 16 + li) * CSP + ks * 4 + lk];
+                    fbi[v] = Li[(v * 16 + li) * CSP + ks * 4 + lk];
+                }
+                const double fcr = cf[ks].x, fci = cf[ks].y;
+                for (int v = 0; v < 4; ++v) {
+                    xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr, fbr[v], xr[v], 0, 0, 0);
+                    xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbi[v], xr[v], 0, 0, 0);
+                    xi[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbr[v], xi[v], 0, 0, 0);
+                    xi[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr, -fbi[v], xi[v], 0, 0, 0);
+                }
+            }
+            for (int r = 0; r < 4; ++r) {
+                const int row = wrow + lk + 4 * r;
+                double sr = 0.0, si = 0.0;
+                for (int v = 0; v < 4; ++v) {
+                    const int col = v * 16 + li;
+                    const double a_ = xr[v][r], b_ = xi[v][r];
+                    if (row < M) A[(size_t)row * M + jq + col] = make_double2(a_, b_);
+                    sr += a_ * yr[col] - b_ * yi[col];
+                    si += a_ * yi[col] + b_ * yr[col];
+                }
+                for (int o = 1; o < 16; o <<= 1) {
+                    sr += __shfl_xor(sr, o, 64);
+                    si += __shfl_xor(si, o, 64);
+                }
+                if (li == 0 && row < M) {
+                    const double2 zr = z[row];
+                    z[row] = make_double2(zr.x - sr, zr.y - si);
+                }
+            }
+        }
+        __syncthreads();   // the staging buffers are free again; this chunk's X is visible to every wave
+    }
     v4d cre[4], cim[4];
     for (int v = 0; v < 4; ++v)
         for (int r = 0; r < 4; ++r) {
@@ -107,6 +186,173 @@ __global__ __launch_bounds__(ZT) void k_zmw_update(ZCholArgs a, int j0) {
             const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
             if (r0 + row < M && col < jb)
                 A[(size_t)(r0 + row) * M + j0 + col] = make_double2(cre[v][r], cim[v][r]);
+        }
+}
+
+// The same update with the operand slices copied from global memory straight into LDS
+// (global_load_lds, no register staging) through three buffers, so that the copies run up to
+// two slices ahead of the products and a slice costs one barrier and one partial wait.  A slice is
+// ZK complex columns: CR chunk rows and CN panel rows of 256 bytes each, the 16-byte pieces of
+// row r stored at position piece ^ (r & 15), which puts the 16 rows of a fragment read on
+// distinct banks.  Each fragment is one 16-byte read of (re, im).  The product P = L[rows, 0:j0]
+// L[panel, 0:j0]^H accumulates from zero as Re P (two products per block), Im P's two halves
+// Li Lr'^T and Lr Li'^T separately (no negated operands), and C = A - P at the end.
+constexpr int ZU_STAGES = 3;
+constexpr int ZU_ROWS = CR + CN;                       // rows of one staged slice
+constexpr int ZU_SLICE = ZU_ROWS * ZK;                 // double2 elements of one staged slice
+static_assert(ZK == 16 && ZT == 512, "one slice is 48 wave copies of 1 KB: six per wave");
+__global__ __launch_bounds__(ZT) void k_zmw_update_lds(ZCholArgs a, int j0, int pp) {
+    __shared__ __attribute__((aligned(1024))) double2 sl[ZU_STAGES * ZU_SLICE];   // 144 KB
+    const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int M = a.m;
+    const int r0 = j0 + blockIdx.x * CR;
+    if (r0 >= M) return;
+    const int jb = (M - j0) < CN ? (M - j0) : CN;
+    double2 *A = a.A + (size_t)t * M * M;
+    if (pp >= 0) {   // the previous panel's TRSM of this chunk's rows below the current panel
+        const int jq = j0 - CN;
+        double *Lr = (double *)sl, *Li = Lr + CN * CSP, *yr = Lr + 2 * CN * CSP, *yi = yr + CN;
+        double2 *z = a.x + (size_t)t * M;
+        const double2 *lv = a.linv + ((size_t)t * chol_panels(M) + pp) * CN * CN;
+        for (int e = tid; e < CN * CN; e += ZT) {
+            const double2 l = lv[e];
+            Lr[(e / CN) * CSP + e % CN] = l.x;
+            Li[(e / CN) * CSP + e % CN] = l.y;
+        }
+        if (tid < CN) {
+            const double2 y = z[jq + tid];
+            yr[tid] = y.x;
+            yi[tid] = y.y;
+        }
+        __syncthreads();
+        const int wrow = r0 + wave * 16;
+        if (wrow >= j0 + CN && wrow < M) {
+            double2 cf[CN / 4];
+            {
+                const int row = wrow + li;
+                for (int ks = 0; ks < CN / 4; ++ks)
+                    cf[ks] = row < M ? A[(size_t)row * M + jq + ks * 4 + lk] : make_double2(0.0, 0.0);
+            }
+            v4d xr[4], xi[4];
+            for (int v = 0; v < 4; ++v) {
+                xr[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+                xi[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+            }
+            for (int ks = 0; ks < CN / 4; ++ks) {
+                double fbr[4], fbi[4];
+                for (int v = 0; v < 4; ++v) {
+                    fbr[v] = Lr[(v * 16 + li) * CSP + ks * 4 + lk];
+                    fbi[v] = Li[(v * 16 + li) * CSP + ks * 4 + lk];
+                }
+                const double fcr = cf[ks].x, fci = cf[ks].y;
+                for (int v = 0; v < 4; ++v) {
+                    xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr, fbr[v], xr[v], 0, 0, 0);
+                    xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbi[v], xr[v], 0, 0, 0);
+                    xi[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbr[v], xi[v], 0, 0, 0);
+                    xi[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr, -fbi[v], xi[v], 0, 0, 0);
+                }
+            }
+            for (int r = 0; r < 4; ++r) {
+                const int row = wrow + lk + 4 * r;
+                double sr = 0.0, si = 0.0;
+                for (int v = 0; v < 4; ++v) {
+                    const int col = v * 16 + li;
+                    const double a_ = xr[v][r], b_ = xi[v][r];
+                    if (row < M) A[(size_t)row * M + jq + col] = make_double2(a_, b_);
+                    sr += a_ * yr[col] - b_ * yi[col];
+                    si += a_ * yi[col] + b_ * yr[col];
+                }
+                for (int o = 1; o < 16; o <<= 1) {
+                    sr += __shfl_xor(sr, o, 64);
+                    si += __shfl_xor(si, o, 64);
+                }
+                if (li == 0 && row < M) {
+                    const double2 zr = z[row];
+                    z[row] = make_double2(zr.x - sr, zr.y - si);
+                }
+            }
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // X is stored before the copies read it
+        __syncthreads();
+    }
+    v4d pre[4], pia[4], pib[4];
+    for (int v = 0; v < 4; ++v) {
+        pre[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+        pia[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+        pib[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+    }
+    if (j0 > 0) {
+        // copy instruction c (0..5) of this wave: 1 KB = slice rows 4 (6 wave + c) .. +3; lane L
+        // takes row 4 (6 wave + c) + L / 16 at LDS piece position L % 16, i.e. the logical piece
+        // (L % 16) ^ (row % 16) of that row; slice rows < CR are chunk rows, the rest panel rows
+        // (rows past M are read from row M - 1: they only feed outputs that are not stored)
+        unsigned voff[6];   // byte offset of this lane's piece within the trajectory's matrix
+        for (int c = 0; c < 6; ++c) {
+            const int srow = 4 * (6 * wave + c) + (lane >> 4);
+            const int grow0 = srow < CR ? r0 + srow : j0 + (srow - CR);
+            const int grow = grow0 < M ? grow0 : M - 1;
+            voff[c] = (unsigned)(((size_t)grow * M + ((lane & 15) ^ (srow & 15))) * sizeof(double2));
+        }
+        // The copies are issued from inline assembly (scalar base: the slice's first column,
+        // vector offsets fixed for the launch): the compiler then keeps no record of them, and
+        // the waits above each slice are the explicit partial ones below (a copy the compiler
+        // knew of would make it wait for every outstanding copy before the first LDS read of a
+        // slice, which is the whole look-ahead).  M0 holds the wave's LDS destination.
+        typedef __attribute__((address_space(3))) void lvoid_t;
+#define ZU_COPY(BUF, KC)                                                                          \
+        for (int c = 0; c < 6; ++c) {                                                             \
+            const unsigned dst = __builtin_amdgcn_readfirstlane(                                  \
+                (unsigned)(size_t)(lvoid_t *)(sl + (BUF) * ZU_SLICE + 64 * (6 * wave + c)));      \
+            asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"                      \
+                         :: "v"(voff[c]), "s"(A + (KC)), "s"(dst) : "memory", "m0");              \
+        }
+        const int nk = j0 / ZK;
+        ZU_COPY(0, 0)
+        if (nk > 1) ZU_COPY(1, ZK)
+        const int arow = wave * 16 + li;
+        for (int k = 0; k < nk; ++k) {
+            // this wave's part of slice k has landed once at most the six copies of slice k + 1
+            // are outstanding; the barrier then makes every wave's part visible, and also
+            // certifies that every wave has finished reading slice k - 1, whose buffer the copy
+            // of slice k + 2 refills
+            if (k + 1 < nk)
+                asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+            else
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (k + 2 < nk) ZU_COPY((k + 2) % ZU_STAGES, (k + 2) * ZK)
+            const double2 *Sb = sl + (k % ZU_STAGES) * ZU_SLICE;
+            for (int ks = 0; ks < ZK / 4; ++ks) {
+                const int p = ks * 4 + lk;
+                const double2 fa = Sb[arow * ZK + (p ^ (arow & 15))];
+                double2 fb[4];
+                for (int v = 0; v < 4; ++v) {
+                    const int brow = CR + v * 16 + li;
+                    fb[v] = Sb[brow * ZK + (p ^ (brow & 15))];
+                }
+                for (int v = 0; v < 4; ++v) {
+                    pre[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.x, fb[v].x, pre[v], 0, 0, 0);
+                    pia[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.y, fb[v].x, pia[v], 0, 0, 0);
+                }
+                for (int v = 0; v < 4; ++v) {
+                    pre[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.y, fb[v].y, pre[v], 0, 0, 0);
+                    pib[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.x, fb[v].y, pib[v], 0, 0, 0);
+                }
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // this wave's reads of slice k are done
+        }
+#undef ZU_COPY
+    }
+    for (int v = 0; v < 4; ++v)
+        for (int r = 0; r < 4; ++r) {
+            const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
+            if (r0 + row < M && col < jb) {
+                double2 *c = A + (size_t)(r0 + row) * M + j0 + col;
+                const double2 cv = *c;
+                *c = make_double2(cv.x - pre[v][r], cv.y - (pia[v][r] - pib[v][r]));
+            }
         }
 }
 
@@ -212,84 +458,45 @@ __global__ __launch_bounds__(ZD) void k_zmw_diag(ZCholArgs a, int j0, int p) {
     double2 *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
     for (int e = tid; e < CN * CN; e += ZD) lv[e] = Ls[(e / CN) * CSP + e % CN];
     __syncthreads();
-    if (tid < jb) z[j0 + tid] = ys[tid];
-    if (tid == 0 && bad) a.flags[t] = 1;
-}
-
-// X = C Linv^H: X_ij = sum_k C_ik conj(Linv_jk); B[k][j] = Linv_jk.  8 waves, 16 rows of the
-// 128-row chunk each; a lane loads all 16 of its C fragments before the products.
-constexpr int ZTT = 512;
-
-__global__ __launch_bounds__(ZTT) void k_zmw_trsm(ZCholArgs a, int j0, int p) {
-    __shared__ double Lr[CN * CSP], Li[CN * CSP];
-    __shared__ double yr[CN], yi[CN];
-    const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int M = a.m;
-    const int jb = (M - j0) < CN ? (M - j0) : CN;
-    const int r0 = j0 + jb + blockIdx.x * CR;
-    if (r0 >= M) return;
-    double2 *A = a.A + (size_t)t * M * M;
-    double2 *z = a.x + (size_t)t * M;
-    const double2 *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
-    double2 cf[CN / 4];   // C[row r0 + 16 wave + li][4 ks + lk]
-    {
-        const int row = r0 + wave * 16 + li;
-        for (int ks = 0; ks < CN / 4; ++ks) {
-            const int col = ks * 4 + lk;
-            cf[ks] = (row < M && col < jb) ? A[(size_t)row * M + j0 + col] : make_double2(0.0, 0.0);
+    // the next panel's rows (the first CN rows below the block): L[r, panel] = C[r, panel]
+    // Linv^H over C and z[r] -= L[r, panel] y; the update kernel of the next panel does the
+    // TRSM of the rows below those.  Thread (fr, fs): row fr, columns fs, fs + 16, ...
+    const int nr0 = j0 + jb, nrb = (M - nr0) < CN ? (M - nr0) : CN;
+    if (nrb > 0) {
+        for (int e = tid; e < nrb * CN; e += ZD) {
+            const int r = e / CN, c = e % CN;
+            Cs[r * CSP + c] = c < jb ? A[(size_t)(nr0 + r) * M + j0 + c] : make_double2(0.0, 0.0);
         }
-    }
-    for (int e = tid; e < CN * CN; e += ZTT) {
-        const double2 l = lv[e];
-        Lr[(e / CN) * CSP + e % CN] = l.x;
-        Li[(e / CN) * CSP + e % CN] = l.y;
-    }
-    if (tid < CN) {
-        const double2 y = tid < jb ? z[j0 + tid] : make_double2(0.0, 0.0);
-        yr[tid] = y.x;
-        yi[tid] = y.y;
-    }
-    __syncthreads();
-    v4d xr[4], xi[4];
-    for (int v = 0; v < 4; ++v) {
-        xr[v] = (v4d){0.0, 0.0, 0.0, 0.0};
-        xi[v] = (v4d){0.0, 0.0, 0.0, 0.0};
-    }
-    for (int ks = 0; ks < CN / 4; ++ks) {
-        double fbr[4], fbi[4];
-        for (int v = 0; v < 4; ++v) {
-            fbr[v] = Lr[(v * 16 + li) * CSP + ks * 4 + lk];
-            fbi[v] = Li[(v * 16 + li) * CSP + ks * 4 + lk];
-        }
-        const double fcr = cf[ks].x, fci = cf[ks].y;
-        for (int v = 0; v < 4; ++v) {
-            xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr, fbr[v], xr[v], 0, 0, 0);
-            xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbi[v], xr[v], 0, 0, 0);
-            xi[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbr[v], xi[v], 0, 0, 0);
-            xi[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr, -fbi[v], xi[v], 0, 0, 0);
-        }
-    }
-    // each wave writes back only the 16 rows it read
-    for (int r = 0; r < 4; ++r) {
-        const int row = r0 + wave * 16 + lk + 4 * r;
+        __syncthreads();
+        const int fr = tid >> 4, fs = tid & 15;
         double sr = 0.0, si = 0.0;
-        for (int v = 0; v < 4; ++v) {
-            const int col = v * 16 + li;
-            const double a_ = xr[v][r], b_ = xi[v][r];
-            if (row < M && col < jb) A[(size_t)row * M + j0 + col] = make_double2(a_, b_);
-            sr += a_ * yr[col] - b_ * yi[col];
-            si += a_ * yi[col] + b_ * yr[col];
+        if (fr < nrb) {
+            for (int q = 0; q < CN / 16; ++q) {
+                const int c = fs + 16 * q;
+                if (c >= jb) continue;
+                double xr = 0.0, xi = 0.0;   // sum_{k <= c} C_rk conj(Linv_ck)
+                for (int k = 0; k <= c; ++k) {
+                    const double2 pr = zmulc(Cs[fr * CSP + k], Ls[c * CSP + k]);
+                    xr += pr.x;
+                    xi += pr.y;
+                }
+                A[(size_t)(nr0 + fr) * M + j0 + c] = make_double2(xr, xi);
+                const double2 xy = zmul(make_double2(xr, xi), ys[c]);
+                sr += xy.x;
+                si += xy.y;
+            }
         }
         for (int o = 1; o < 16; o <<= 1) {
             sr += __shfl_xor(sr, o, 64);
             si += __shfl_xor(si, o, 64);
         }
-        if (li == 0 && row < M) {
-            const double2 zr = z[row];
-            z[row] = make_double2(zr.x - sr, zr.y - si);
+        if (fs == 0 && fr < nrb) {
+            const double2 zr = z[nr0 + fr];
+            z[nr0 + fr] = make_double2(zr.x - sr, zr.y - si);
         }
     }
+    if (tid < jb) z[j0 + tid] = ys[tid];
+    if (tid == 0 && bad) a.flags[t] = 1;
 }
 
 // L^H x = y by row panels, last panel first, one launch per panel p (then a closing launch

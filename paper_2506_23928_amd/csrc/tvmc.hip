@@ -567,9 +567,15 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
     LAUNCHCHECK(c, "solver init");
     for (int j0 = 0, p = 0; j0 < x.m; j0 += CN, ++p) {
         if (j0 > 0) {
-            if constexpr (CPLX)
-                hipLaunchKernelGGL(k_zmw_update, dim3((x.m - j0 + CR - 1) / CR, T), dim3(ZT), 0, st, x, j0);
-            else
+            // complex: the previous panel's TRSM of the rows below this panel rides in the update;
+            // the direct-to-LDS form addresses a trajectory's matrix by 32-bit byte offsets
+            if constexpr (CPLX) {
+                const dim3 grid((x.m - j0 + CR - 1) / CR, T);
+                if ((size_t)x.m * x.m * sizeof(double2) <= 0xffffffffull)
+                    hipLaunchKernelGGL(k_zmw_update_lds, grid, dim3(ZT), 0, st, x, j0, p - 1);
+                else
+                    hipLaunchKernelGGL(k_zmw_update, grid, dim3(ZT), 0, st, x, j0, p - 1);
+            } else
                 hipLaunchKernelGGL(k_cmw_update, dim3((x.m - j0 + CR - 1) / CR, T), dim3(256), 0, st, x, j0);
             LAUNCHCHECK(c, "panel update");
         }
@@ -579,12 +585,11 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
             hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, st, x, j0, p);
         LAUNCHCHECK(c, "diagonal block");
         const int below = x.m - j0 - CN;
-        if (below > 0) {
-            if constexpr (CPLX)
-                hipLaunchKernelGGL(k_zmw_trsm, dim3((below + CR - 1) / CR, T), dim3(ZTT), 0, st, x, j0, p);
-            else
+        if constexpr (!CPLX) {
+            if (below > 0) {
                 hipLaunchKernelGGL(k_cmw_trsm, dim3((below + CR - 1) / CR, T), dim3(256), 0, st, x, j0, p);
-            LAUNCHCHECK(c, "panel TRSM");
+                LAUNCHCHECK(c, "panel TRSM");
+            }
         }
     }
     if constexpr (CPLX) {
