@@ -162,11 +162,17 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, solver_arg):
-    """The dominant kernel group's algorithmic work per launch (every trajectory of the context)
-    over its average launch time (HIP events on the library's stream), against the peak of the
-    unit it runs on."""
-    dom = max(groups, key=lambda g: groups[g]["total_ms"]) if groups else None   # None: graph replays, untimed
+# kernels that time as one group (a secondary entry skips the dominant one's group)
+_KERNELS_OF = {"solve": ("k_zmw_solve", "k_cmw_solve", "k_chol_solve", "k_jacobi"),
+               "sbuild": ("k_sbuild_rbm_bf16", "k_sbuild_rbm_f64", "k_sbuild_f64", "k_sbuild_i8", "k_tk_rbm"),
+               "transpose": ("k_rbm_split",)}
+
+
+def roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, solver_arg, group=None, n=64):
+    """A kernel group's algorithmic work per launch (every trajectory of the context) over its
+    average launch time (HIP events on the library's stream), against the peak of the unit it
+    runs on: the dominant group (largest total time), or `group`."""
+    dom = group or (max(groups, key=lambda g: groups[g]["total_ms"]) if groups else None)   # None: untimed
     dim = ns if ss else m                 # dimension of the system solved
     if dom == "solve" and reg == tv.tvmc.REG_SNR:
         # Jacobi: per sweep M' - 1 rounds rotating every row of S and V^T and every column of S
@@ -218,6 +224,14 @@ def roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, solver_arg):
         achieved = ops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": "k_sbuild_i8", "bound": "mfma", "achieved": achieved, "peak": PEAKS["int8"],
                 "unit": "TOP/s", "frac": achieved / PEAKS["int8"], "traffic": read_traffic("k_sbuild_i8")}
+    elif dom == "transpose" and kind == tv.RBM and prec == tv.PREC_MFMA and not ss:
+        # k_rbm_split: reads the samples (ceil(N/64) words each), tanh(theta_h) (N' complex per
+        # sample) and <O> (M complex), writes the four BF16 planes of Mp x N_s
+        words, mp = (n + 63) // 64, (m + 127) // 128 * 128
+        nbytes = T * (ns * words * 8.0 + ns * nh * 16.0 + m * 16.0 + mp * ns * 8.0)
+        achieved = nbytes / (groups["transpose"]["avg_ms"] * 1e-3) / 1e9
+        roof = {"kernel": "k_rbm_split", "bound": "hbm", "achieved": achieved, "peak": PEAKS["hbm"], "unit": "GB/s",
+                "frac": achieved / PEAKS["hbm"], "traffic": read_traffic("k_rbm_split")}
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None}
@@ -594,7 +608,12 @@ def main():
           flush=True)
 
     ss, ns = ctx.sample_space, w["n_samples"]
-    roof = roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, args.solver)
+    roof = roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, args.solver, n=n)
+    # the other heavy groups against their own roofs (the S-build, the operand split, the solve)
+    secondary = [r for r in (roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, args.solver, group=g, n=n)
+                             for g in ("sbuild", "solve", "transpose") if g in groups and g != roof["kernel"] and
+                             roof["kernel"] not in _KERNELS_OF.get(g, ()))
+                 if r["achieved"] is not None]
     del ctx
     torch.cuda.empty_cache()
 
@@ -667,6 +686,7 @@ def main():
                    else "FP64 Cholesky" + (" (sample space)" if ss else ""), "solver": args.solver,
                    "obs_every": w["obs_every"]},
         "roofline": roof,
+        "rooflines_secondary": secondary,
         "cpu_baseline": cpu,
         "plain_form_value": plain,
         "fixed_error": dict(fixed, ratio_at_equal_error=(fixed["value_fast_at_equal_error"] / plain) if plain else None)

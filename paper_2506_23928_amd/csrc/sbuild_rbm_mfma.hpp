@@ -153,16 +153,17 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
     const size_t ns = (size_t)a.ns, nst = ns / RQ_K;
     const uint16_t *Pt = a.rbmP + (size_t)t * (a.mp / RQ_T) * nst * RQ_CHUNK;
     // LDS layout of a staged operand: [plane][128 rows][32 samples], rows of 64 bytes with the
-    // four 16-byte pieces of row r permuted by c -> c ^ ((r >> 2) & 3), which puts the 16-byte
-    // fragment reads of 16 consecutive rows on distinct banks.  The chunks are copied from
+    // four 16-byte pieces of row r permuted by c -> c ^ ((r >> 1) & 3), under which the 16-byte
+    // fragment reads of 16 consecutive rows meet no bank conflict (measured with the LDS bank
+    // conflict counter: the permutation by r >> 2 costs a second pass on every read).  The chunks are copied from
     // global memory straight into LDS: wave instruction i (of 32 per operand and step) fills
     // bytes 1024 i .. +1023, i.e. plane i / 8, rows 16 (i % 8) .. +15; lane L lands in row
-    // 16 (i % 8) + L / 4 at piece L % 4, so it reads the logical piece (L % 4) ^ ((row >> 2) & 3)
+    // 16 (i % 8) + L / 4 at piece L % 4, so it reads the logical piece (L % 4) ^ ((row >> 1) & 3)
     const uint16_t *gA = Pt + (size_t)bi * nst * RQ_CHUNK, *gB = Pt + (size_t)bj * nst * RQ_CHUNK;
     int gofs[4];                                   // element offset in the chunk, per instruction
     for (int j = 0; j < 4; ++j) {
         const int i = w * 4 + j, q = i >> 3, row = (i & 7) * 16 + (lane >> 2);
-        gofs[j] = q * 4096 + row * 32 + (((lane & 3) ^ ((row >> 2) & 3)) * 8);
+        gofs[j] = q * 4096 + row * 32 + (((lane & 3) ^ ((row >> 1) & 3)) * 8);
     }
     typedef __attribute__((address_space(1))) void gvoid_t;
     typedef __attribute__((address_space(3))) void lvoid_t;
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(RQ_THREADS) void k_sbuild_rbm_bf16(Dev a) {
             sim[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         }
     const int arow = wr * 64 + rr, brow = wc * 32 + rr;
-#define RQ_SW(row) ((((kg) ^ (((row) >> 2) & 3))) * 8)
+#define RQ_SW(row) ((((kg) ^ (((row) >> 1) & 3))) * 8)
 #define RQ_LDA(BUF, Q) for (int u = 0; u < 4; ++u) A[u][Q] = *(const bf16x8_t *)(sbuf[BUF][0] + ((Q) * RQ_T + arow + 16 * u) * 32 + RQ_SW(arow + 16 * u));
 #define RQ_LDB(BUF, Q) for (int v = 0; v < 2; ++v) B[v][Q] = *(const bf16x8_t *)(sbuf[BUF][1] + ((Q) * RQ_T + brow + 16 * v) * 32 + RQ_SW(brow + 16 * v));
 #define RQ_TERM(ACC, AX, BX) for (int u = 0; u < 4; ++u) for (int v = 0; v < 2; ++v) ACC[u][v] = MFMA_BF16(AX, BX, ACC[u][v]);
