@@ -195,11 +195,14 @@ def roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, solver_arg, group
                 "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic(kname),
                 "note": "one evaluation's solve (every launch of the solver for all trajectories)"}
     elif dom == "sbuild" and ss and kind == tv.RBM:
-        # K = (1 + q)(1 + g) - 1 with g = t t^H over N' hidden units: N_s^2 N' complex multiply-adds
-        flops = T * 8.0 * ns * ns * nh
+        # K = (1 + q)(1 + g) - 1 with g = t t^H over N' hidden units, Hermitian: N_s (N_s + 1) / 2
+        # entries of N' complex multiply-adds (FP64 matrix cores); the group also holds the
+        # centring passes over K (row means, T = H K H / N_s + eps I)
+        flops = T * 8.0 * ns * (ns + 1) / 2.0 * nh
         achieved = flops / (groups["sbuild"]["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": "k_tk_rbm", "bound": "alu", "achieved": achieved, "peak": PEAKS["fp64"],
-                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_tk_rbm")}
+        roof = {"kernel": "k_tk_rbm", "bound": "mfma", "achieved": achieved, "peak": PEAKS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp64"], "traffic": read_traffic("k_tk_rbm"),
+                "note": "the K-build group: the Gram on the matrix cores and the centring passes"}
     elif dom == "sbuild" and kind == tv.RBM and prec == tv.PREC_MFMA:
         # complex Hermitian S: M (M + 1) / 2 entries, N_s complex multiply-adds (8 flops) each,
         # on BF16 matrix cores (three split products per real product)
@@ -679,7 +682,8 @@ def main():
                    "n_chains": w["n_chains"], "n_jumps": len(wl.jumps(w)), "dt": w["dt"],
                    "ansatz": w.get("ansatz", "jastrow"), "n_hidden": nh if kind == tv.RBM else 0,
                    **({"ljph_d": nh} if kind == tv.LJPH else {}), "proposal": w.get("proposal", "flip"),
-                   "s_build": "sample-space kernel O O^H (FP64 VALU)" if ss else
+                   "s_build": ("sample-space kernel O O^H (FP64 MFMA Gram)" if kind == tv.RBM else
+                               "sample-space kernel O O^H (integer closed form)") if ss else
                    ("int8 MFMA (exact)" if prec == tv.PREC_MFMA else "FP64 VALU") if kind != tv.RBM
                    else ("BF16-split MFMA, FP32 accumulate" if prec == tv.PREC_MFMA else "FP64 VALU (complex)"),
                    "solve": ("FP64 Jacobi + SNR filter (tau %g)" % w.get("snr_tau", 4.0)) if reg == tv.tvmc.REG_SNR

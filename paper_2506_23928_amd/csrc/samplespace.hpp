@@ -13,6 +13,7 @@
 // diagonal) replaces the lower triangle in place.
 #pragma once
 #include "common.hpp"
+#include "cholesky.hpp"
 #include "rbm.hpp"
 
 namespace tvmc {
@@ -33,52 +34,84 @@ __global__ __launch_bounds__(256) void k_tk_jastrow(Dev a) {
     a.S[((size_t)t * a.ns + x) * a.ns + y] = q + 0.5 * (q * q - (double)a.n);
 }
 
-// RBM K (complex) into the S buffer, full matrix: a 64 x 64 tile per workgroup, 4 x 4 outputs
-// per thread, tanh rows staged 16 hidden units at a time through LDS.  Grid (tiles^2, T).
+// RBM K (complex) into the S buffer, full matrix, on the FP64 matrix cores.  K is Hermitian, so
+// one workgroup forms one 64 x 64 tile of the lower block triangle (bi >= bj) and writes it and,
+// off the diagonal, its conjugate transpose (through LDS, so that both stores are row-contiguous).
+// g = t(x) t(y)^H accumulates over the hidden units in chunks of 16 staged through LDS: rows of
+// 256 bytes, the 16-byte piece j of row r at position j ^ (r & 15), which puts the 16-byte
+// fragment reads of 16 rows on distinct banks.  Wave w takes rows 16 w .. +15 of the tile and all
+// 64 columns (four 16 x 16 blocks); per block and step of 4 hidden units
+//   Re g += tr tr'^T + ti ti'^T,   Im g = ti tr'^T - tr ti'^T   (the two halves kept apart).
+// Grid (tiles nb (nb + 1) / 2, T), 256 threads; LDS 65 KB (the transpose buffer; staging takes
+// its first 32 KB).
 constexpr int TK_T = 64;
 constexpr int TK_J = 16;
+constexpr int TK_TP = TK_T + 1;   // row stride of the transpose buffer (16-byte slots)
 template <int W>
 __global__ __launch_bounds__(256) void k_tk_rbm(Dev a) {
-    __shared__ double2 tx[TK_T][TK_J + 1], ty[TK_T][TK_J + 1];
-    const int t = blockIdx.y;
-    const int nb = (a.ns + TK_T - 1) / TK_T;
-    const int x0 = (blockIdx.x / nb) * TK_T, y0 = (blockIdx.x % nb) * TK_T;
-    const int ix = threadIdx.x >> 4, iy = threadIdx.x & 15;   // rows x0 + ix + 16 u, cols y0 + iy + 16 v
-    const int nh = a.nh;
-    const double2 *tt = a.tt + (size_t)t * a.ns * nh;
-    double gr[4][4], gi[4][4];
-    for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v) gr[u][v] = gi[u][v] = 0.0;
+    __shared__ __attribute__((aligned(16))) double2 sm[TK_T * TK_TP];
+    const int t = blockIdx.y, tile = blockIdx.x, tid = threadIdx.x;
+    int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= tile) ++bi;
+    while (bi * (bi + 1) / 2 > tile) --bi;
+    const int bj = tile - bi * (bi + 1) / 2;
+    const int x0 = bi * TK_T, y0 = bj * TK_T, ns = a.ns, nh = a.nh;
+    const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const double2 *tt = a.tt + (size_t)t * ns * nh;
+    double2 *tx = sm, *ty = sm + TK_T * TK_J;
+    v4d gre[4], gia[4], gib[4];
+    for (int v = 0; v < 4; ++v) {
+        gre[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+        gia[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+        gib[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+    }
+    const int ar = wave * 16 + li;
     for (int j0 = 0; j0 < nh; j0 += TK_J) {
         __syncthreads();
-        for (int e = threadIdx.x; e < TK_T * TK_J; e += 256) {
-            const int r = e / TK_J, j = e % TK_J;
+        for (int e = tid; e < TK_T * TK_J; e += 256) {
+            const int r = e / TK_J, j = e % TK_J, pos = r * TK_J + (j ^ (r & 15));
             const bool okj = j0 + j < nh;
-            tx[r][j] = (okj && x0 + r < a.ns) ? tt[(size_t)(x0 + r) * nh + j0 + j] : make_double2(0.0, 0.0);
-            ty[r][j] = (okj && y0 + r < a.ns) ? tt[(size_t)(y0 + r) * nh + j0 + j] : make_double2(0.0, 0.0);
+            tx[pos] = (okj && x0 + r < ns) ? tt[(size_t)(x0 + r) * nh + j0 + j] : make_double2(0.0, 0.0);
+            ty[pos] = (okj && y0 + r < ns) ? tt[(size_t)(y0 + r) * nh + j0 + j] : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        for (int j = 0; j < TK_J; ++j) {
-            double2 xv[4], yv[4];
-            for (int u = 0; u < 4; ++u) xv[u] = tx[ix + 16 * u][j];
-            for (int v = 0; v < 4; ++v) yv[v] = ty[iy + 16 * v][j];
-            for (int u = 0; u < 4; ++u)
-                for (int v = 0; v < 4; ++v) {   // t(x) t(y)^*
-                    gr[u][v] += xv[u].x * yv[v].x + xv[u].y * yv[v].y;
-                    gi[u][v] += xv[u].y * yv[v].x - xv[u].x * yv[v].y;
-                }
+        for (int ks = 0; ks < TK_J / 4; ++ks) {
+            const int p = ks * 4 + lk;
+            const double2 fa = tx[ar * TK_J + (p ^ (ar & 15))];
+            double2 fb[4];
+            for (int v = 0; v < 4; ++v) {
+                const int br = v * 16 + li;
+                fb[v] = ty[br * TK_J + (p ^ (br & 15))];
+            }
+            for (int v = 0; v < 4; ++v) {
+                gre[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.x, fb[v].x, gre[v], 0, 0, 0);
+                gre[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.y, fb[v].y, gre[v], 0, 0, 0);
+                gia[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.y, fb[v].x, gia[v], 0, 0, 0);
+                gib[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa.x, fb[v].y, gib[v], 0, 0, 0);
+            }
         }
     }
-    const uint64_t *smp = a.samples + (size_t)t * a.ns * W;
-    double2 *K = (double2 *)a.S + (size_t)t * a.ns * a.ns;
-    for (int u = 0; u < 4; ++u) {
-        const int x = x0 + ix + 16 * u;
-        if (x >= a.ns) continue;
+    __syncthreads();   // the staging buffers become the transpose buffer
+    const uint64_t *smp = a.samples + (size_t)t * ns * W;
+    double2 *K = (double2 *)a.S + (size_t)t * ns * ns;
+    for (int r = 0; r < 4; ++r) {
+        const int row = wave * 16 + lk + 4 * r, x = x0 + row;
         for (int v = 0; v < 4; ++v) {
-            const int y = y0 + iy + 16 * v;
-            if (y >= a.ns) continue;
+            const int col = v * 16 + li, y = y0 + col;
+            if (x >= ns || y >= ns) continue;
             const double q1 = 1.0 + (double)spin_overlap<W>(smp + (size_t)x * W, smp + (size_t)y * W, a.n);
-            K[(size_t)x * a.ns + y] = make_double2(q1 * (1.0 + gr[u][v]) - 1.0, q1 * gi[u][v]);
+            const double2 k = make_double2(q1 * (1.0 + gre[v][r]) - 1.0, q1 * (gia[v][r] - gib[v][r]));
+            K[(size_t)x * ns + y] = k;
+            sm[row * TK_TP + col] = k;
+        }
+    }
+    if (bi == bj) return;   // the diagonal tile was formed whole
+    __syncthreads();
+    for (int e = tid; e < TK_T * TK_T; e += 256) {   // K[y][x] = K[x][y]^*
+        const int yr = e / TK_T, xc = e % TK_T;
+        if (y0 + yr < ns && x0 + xc < ns) {
+            const double2 k = sm[xc * TK_TP + yr];
+            K[(size_t)(y0 + yr) * ns + x0 + xc] = make_double2(k.x, -k.y);
         }
     }
 }

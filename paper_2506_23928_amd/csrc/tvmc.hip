@@ -493,7 +493,7 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         Scope sc(c, "sbuild");
         if (d.kind == TVMC_ANSATZ_RBM) {
             const int nb = (d.ns + TK_T - 1) / TK_T;
-            BY_WORDS(d, hipLaunchKernelGGL((k_tk_rbm<W_>), dim3(nb * nb, T), dim3(256), 0, c->stream, d));
+            BY_WORDS(d, hipLaunchKernelGGL((k_tk_rbm<W_>), dim3(nb * (nb + 1) / 2, T), dim3(256), 0, c->stream, d));
             LAUNCHCHECK(c, "k_tk_rbm");
         } else {
             BY_WORDS(d, hipLaunchKernelGGL((k_tk_jastrow<W_>), dim3((d.ns + 255) / 256, d.ns, T), dim3(256), 0, c->stream, d));
