@@ -186,7 +186,7 @@ def roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, solver_arg, group
             kname = "k_zmw_solve"     # k_zmw_init, k_zmw_update(_lds), k_zmw_diag, k_zmw_bwd
         else:
             flops = T * (dim ** 3 / 3.0 + dim * dim / 2.0 + dim / 6.0 + 4.0 * dim * dim)
-            multi = solver_arg == "multi" or (solver_arg != "one" and T < 192)
+            multi = solver_arg != "one"
             kname = "k_cmw_solve" if multi else "k_chol_solve"   # k_cmw_*: the several-workgroup launches
         if ss:               # push-back delta = A^H u: M x N_s complex multiply-adds
             flops += T * 8.0 * m * ns

@@ -9,6 +9,11 @@
 //   k_cmw_trsm(j0):    L[rows, panel] = C Linv^T for the chunks below, and the right-hand side
 //                      update z[rows] -= L[rows, panel] y_panel
 //   k_cmw_backward:    backward substitution L^T x = y with the stored block inverses.
+// k_cmw_update_lds and k_cmw_diag(.., next > 0) are the form the host takes when a trajectory's
+// matrix is under 4 GiB: the update copies its operand slices straight into LDS and first does
+// the previous panel's TRSM of its rows below those the diagonal kernel did, and the diagonal
+// kernel does the TRSM of the next CN or 2 CN rows, so k_cmw_trsm drops out; panels go in
+// pairs (one 128-column update over [0, j0), one 64-column update over the first panel).
 #pragma once
 #include "cholesky.hpp"
 
@@ -80,7 +85,166 @@ __global__ __launch_bounds__(256) void k_cmw_update(CholArgs a, int j0) {
             }
 }
 
-__global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p) {
+// The update with the operand slices copied from global memory straight into LDS, with partial
+// waits and one barrier per slice (as the complex k_zmw_update_lds), for NC = 64 or 128 output
+// columns j0 .. j0 + NC - 1 and the k range [k0, j0):
+//   C[rows, cols] = A[rows, cols] - L[rows, k0:j0] L[cols, k0:j0]^T.
+// A slice is CW = 32 columns of k, CR chunk rows and NC panel rows of 256 bytes, the 16-byte
+// pieces of row r at position piece ^ (r & 15); three slices deep for NC = 64, two for NC = 128
+// (a slice of 64 KB: the products of one cover the copy of the next).  Lane (li, lk) reads the
+// pieces lk, lk + 4, lk + 8, lk + 12 of its row (16 bytes each, the same bank-conflict-free
+// pattern as the complex update) and feeds their 8 columns to 8 products: the k order of a slice
+// is permuted the same way for both operands, which the sum does not see.  Before the update,
+// the previous panel pp's TRSM of this chunk's rows from j0 + skip on: X = C Linv_pp^T over C,
+// z[rows] -= X y_pp (the diagonal kernel of panel pp did the rows before; skip = CN or 2 CN).
+// The product accumulates from zero and C = A - P at the end.  NC = 128 halves the reads of
+// L[rows, 0:j0] per column factored: the host pairs panels, one wide update over [0, j0) and a
+// narrow one of the second panel over the first panel's columns.
+constexpr int CW = 32;
+constexpr int CUT = 512;   // 8 waves, 16 rows of the chunk each
+static_assert(CW * 8 == 256 && CUT == 512, "a slice row is 16 pieces of 16 bytes");
+template <int NC>
+__global__ __launch_bounds__(CUT) void k_cmw_update_lds(CholArgs a, int j0, int pp, int k0, int skip) {
+    constexpr int STAGES = NC == 64 ? 3 : 2;
+    constexpr int SLICE = (CR + NC) * CW;               // doubles of one staged slice
+    constexpr int COPIES = (CR + NC) * CW * 8 / 8192;   // 1 KB wave copies per wave and slice
+    constexpr int NV = NC / 16;                          // 16 x 16 output blocks per wave
+    static_assert(STAGES * SLICE * 8 <= 160 * 1024 && STAGES * SLICE >= CN * CSP + 2 * CN, "LDS budget");
+    __shared__ __attribute__((aligned(1024))) double sl[STAGES * SLICE];
+    const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int M = a.m;
+    const int r0 = j0 + blockIdx.x * CR;
+    if (r0 >= M) return;
+    const int jb = (M - j0) < NC ? (M - j0) : NC;
+    double *A = a.A + (size_t)t * M * M;
+    if (pp >= 0) {
+        const int jq = j0 - CN;   // the previous panel's columns (a full panel: another follows it)
+        double *Ls = sl, *yr = sl + CN * CSP, *yi = yr + CN;
+        double2 *z = a.x + (size_t)t * M;
+        const double *lv = a.linv + ((size_t)t * chol_panels(M) + pp) * CN * CN;
+        for (int e = tid; e < CN * CN; e += CUT) Ls[(e / CN) * CSP + e % CN] = lv[e];
+        if (tid < CN) {
+            const double2 y = z[jq + tid];
+            yr[tid] = y.x;
+            yi[tid] = y.y;
+        }
+        __syncthreads();
+        const int wrow = r0 + wave * 16;
+        if (wrow >= j0 + skip && wrow < M) {
+            double cf[CN / 4];   // C[row wrow + li][4 ks + lk]
+            {
+                const int row = wrow + li;
+                for (int ks = 0; ks < CN / 4; ++ks) cf[ks] = row < M ? A[(size_t)row * M + jq + ks * 4 + lk] : 0.0;
+            }
+            v4d x[4];
+            for (int v = 0; v < 4; ++v) x[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int ks = 0; ks < CN / 4; ++ks) {
+                double fb[4];
+                for (int v = 0; v < 4; ++v) fb[v] = Ls[(v * 16 + li) * CSP + ks * 4 + lk];
+                for (int v = 0; v < 4; ++v) x[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[ks], fb[v], x[v], 0, 0, 0);
+            }
+            for (int r = 0; r < 4; ++r) {
+                const int row = wrow + lk + 4 * r;
+                double sr = 0.0, si = 0.0;
+                for (int v = 0; v < 4; ++v) {
+                    const int col = v * 16 + li;
+                    const double xv = x[v][r];
+                    if (row < M) A[(size_t)row * M + jq + col] = xv;
+                    sr += xv * yr[col];
+                    si += xv * yi[col];
+                }
+                for (int o = 1; o < 16; o <<= 1) {
+                    sr += __shfl_xor(sr, o, 64);
+                    si += __shfl_xor(si, o, 64);
+                }
+                if (li == 0 && row < M) {
+                    const double2 zr = z[row];
+                    z[row] = make_double2(zr.x - sr, zr.y - si);
+                }
+            }
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // X is stored before the copies read it
+        __syncthreads();
+    }
+    v4d acc[NV];
+    for (int v = 0; v < NV; ++v) acc[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+    const int nk = (j0 - k0) / CW;
+    if (nk > 0) {
+        // copy instruction c of this wave: 1 KB = slice rows 4 (COPIES wave + c) .. +3; lane L
+        // takes row 4 (COPIES wave + c) + L / 16 at LDS piece position L % 16, i.e. the logical
+        // piece (L % 16) ^ (row % 16) of that row; rows < CR are chunk rows, the rest panel rows
+        // (rows past M are read from row M - 1: they only feed outputs that are not stored)
+        unsigned voff[COPIES];   // byte offset of this lane's piece within the trajectory's matrix
+        for (int c = 0; c < COPIES; ++c) {
+            const int srow = 4 * (COPIES * wave + c) + (lane >> 4);
+            const int grow0 = srow < CR ? r0 + srow : j0 + (srow - CR);
+            const int grow = grow0 < M ? grow0 : M - 1;
+            voff[c] = (unsigned)(((size_t)grow * M + 2 * ((lane & 15) ^ (srow & 15))) * sizeof(double));
+        }
+        // issued from inline assembly, so that the compiler keeps no record of the copies and the
+        // waits are the explicit partial ones below; M0 holds the wave's LDS destination
+        typedef __attribute__((address_space(3))) void lvoid_t;
+#define CU_COPY(BUF, KC)                                                                          \
+        for (int c = 0; c < COPIES; ++c) {                                                        \
+            const unsigned dst = __builtin_amdgcn_readfirstlane(                                  \
+                (unsigned)(size_t)(lvoid_t *)(sl + (BUF) * SLICE + 128 * (COPIES * wave + c)));   \
+            asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"                      \
+                         :: "v"(voff[c]), "s"(A + (KC)), "s"(dst) : "memory", "m0");              \
+        }
+        for (int k = 0; k < STAGES - 1 && k < nk; ++k) CU_COPY(k, k0 + k * CW)
+        const int arow = wave * 16 + li;
+        for (int k = 0; k < nk; ++k) {
+            // this wave's part of slice k has landed once at most the copies of the slices after
+            // it are outstanding; the barrier then makes every wave's part visible, and also
+            // certifies that every wave has finished reading slice k - 1, whose buffer the copy
+            // of slice k + STAGES - 1 refills
+            if (STAGES == 3 && k + 1 < nk)
+                asm volatile("s_waitcnt vmcnt(%0)" :: "n"(COPIES) : "memory");
+            else
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+            if (k + STAGES - 1 < nk) CU_COPY((k + STAGES - 1) % STAGES, k0 + (k + STAGES - 1) * CW)
+            const double2 *Sb = (const double2 *)(sl + (k % STAGES) * SLICE);
+            for (int h = 0; h < 2; ++h) {   // pieces 4 (2 h + j) + lk, j = 0, 1: steps 4 h .. 4 h + 3
+                double2 fa[2], fb[NV][2];
+                for (int j = 0; j < 2; ++j) {
+                    const int q = 4 * (2 * h + j) + lk;
+                    fa[j] = Sb[arow * 16 + (q ^ (arow & 15))];
+                    for (int v = 0; v < NV; ++v) {
+                        const int brow = CR + v * 16 + li;
+                        fb[v][j] = Sb[brow * 16 + (q ^ (brow & 15))];
+                    }
+                }
+                for (int j = 0; j < 2; ++j) {
+                    for (int v = 0; v < NV; ++v)
+                        acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[j].x, fb[v][j].x, acc[v], 0, 0, 0);
+                    for (int v = 0; v < NV; ++v)
+                        acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[j].y, fb[v][j].y, acc[v], 0, 0, 0);
+                }
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // this wave's reads of slice k are done
+        }
+#undef CU_COPY
+    }
+    double cv[NV][4];   // every load of C issued before the first subtraction waits for one
+    for (int v = 0; v < NV; ++v)
+        for (int r = 0; r < 4; ++r) {
+            const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
+            cv[v][r] = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : 0.0;
+        }
+    for (int v = 0; v < NV; ++v)
+        for (int r = 0; r < 4; ++r) {
+            const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
+            if (r0 + row < M && col < jb) A[(size_t)(r0 + row) * M + j0 + col] = cv[v][r] - acc[v][r];
+        }
+}
+
+// One workgroup of CDT threads per trajectory: 16 lanes per row of the block while factoring,
+// 16 lanes per column of the inverse, one wave per 16 of the following rows in the TRSM.
+constexpr int CDT = 1024;
+__global__ __launch_bounds__(CDT) void k_cmw_diag(CholArgs a, int j0, int p, int next) {
     __shared__ double Cs[CN * CSP];
     __shared__ double Ls[CN * CSP];
     __shared__ double yre[CN], yim[CN];
@@ -91,15 +255,16 @@ __global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p) {
     double *A = a.A + (size_t)t * M * M;
     double2 *z = a.x + (size_t)t * M;
     if (tid == 0) bad = 0;
-    for (int e = tid; e < CN * CN; e += 256) {
+    for (int e = tid; e < CN * CN; e += CDT) {
         const int r = e / CN, c = e % CN;
         Cs[r * CSP + c] = (r < jb && c <= r) ? A[(size_t)(j0 + r) * M + j0 + c] : 0.0;
     }
     __syncthreads();
-    // right-looking factor of the block in LDS; thread (row fr, phase fs) updates columns fs,
-    // fs+4, ... of its row; column c is read unscaled during step c and scaled after the barrier
+    // right-looking factor of the block in LDS; thread (row fr, phase fs) updates columns
+    // c+1+fs, c+17+fs, ... of its row; column c is read unscaled during step c and scaled after
+    // the barrier
     {
-        const int fr = tid >> 2, fs = tid & 3;
+        const int fr = tid >> 4, fs = tid & 15;
         for (int c = 0; c < jb; ++c) {
             const double piv = Cs[c * CSP + c];
             if (tid == 0 && !(piv > 0.0)) bad = 1;
@@ -107,7 +272,7 @@ __global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p) {
             double lrc = 0.0;
             if (fr > c && fr < jb) {
                 lrc = Cs[fr * CSP + c] * inv;
-                for (int k = c + 1 + fs; k <= fr; k += 4) Cs[fr * CSP + k] -= lrc * (Cs[k * CSP + c] * inv);
+                for (int k = c + 1 + fs; k <= fr; k += 16) Cs[fr * CSP + k] -= lrc * (Cs[k * CSP + c] * inv);
             }
             __syncthreads();
             if (fs == 0 && fr > c && fr < jb) Cs[fr * CSP + c] = lrc;
@@ -115,21 +280,21 @@ __global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p) {
         }
         __syncthreads();
     }
-    for (int e = tid; e < jb * jb; e += 256) {
+    for (int e = tid; e < jb * jb; e += CDT) {
         const int r = e / jb, c = e % jb;
         if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
     }
-    // Linv by forward substitution: wave w owns columns 16w..16w+15, four lanes per column
+    // Linv by forward substitution: wave w owns columns 4w..4w+3, 16 lanes per column (rows of
+    // one column are written and read back by the same wave, in order)
     {
-        const int c = wave * 16 + (lane >> 2), fs = lane & 3;
-        for (int r = fs; r < CN; r += 4) Ls[r * CSP + c] = 0.0;
+        const int c = wave * 4 + (lane >> 4), fs = lane & 15;
+        for (int r = fs; r < CN; r += 16) Ls[r * CSP + c] = 0.0;
         if (c < jb) {
             if (fs == 0) Ls[c * CSP + c] = 1.0 / Cs[c * CSP + c];
             for (int r = c + 1; r < jb; ++r) {
                 double sum = 0.0;
-                for (int k = c + fs; k < r; k += 4) sum += Cs[r * CSP + k] * Ls[k * CSP + c];
-                sum += __shfl_xor(sum, 1, 64);
-                sum += __shfl_xor(sum, 2, 64);
+                for (int k = c + fs; k < r; k += 16) sum += Cs[r * CSP + k] * Ls[k * CSP + c];
+                for (int o = 1; o < 16; o <<= 1) sum += __shfl_xor(sum, o, 64);
                 if (fs == 0) Ls[r * CSP + c] = -sum / Cs[r * CSP + r];
             }
         }
@@ -147,8 +312,48 @@ __global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p) {
         yim[tid] = si;
     }
     double *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
-    for (int e = tid; e < CN * CN; e += 256) lv[e] = Ls[(e / CN) * CSP + e % CN];
+    for (int e = tid; e < CN * CN; e += CDT) lv[e] = Ls[(e / CN) * CSP + e % CN];
+    if (tid >= jb && tid < CN) {
+        yre[tid] = 0.0;
+        yim[tid] = 0.0;
+    }
     __syncthreads();
+    if (next > 0) {
+        // the following rows (the first `next` <= 16 x 16 rows below the block): X = C Linv^T over
+        // C and z[rows] -= X y; wave w takes rows 16 w .. +15 (the next update does the TRSM of
+        // the rows below those)
+        const int li = lane & 15, lk = lane >> 4;
+        const int nr0 = j0 + jb, nend = min(M, nr0 + next);
+        v4d x[4];
+        for (int v = 0; v < 4; ++v) x[v] = (v4d){0.0, 0.0, 0.0, 0.0};
+        for (int ks = 0; ks < CN / 4; ++ks) {
+            double fb[4];
+            const int row = nr0 + wave * 16 + li, col = ks * 4 + lk;
+            const double fa = (row < nend && col < jb) ? A[(size_t)row * M + j0 + col] : 0.0;
+            for (int v = 0; v < 4; ++v) fb[v] = Ls[(v * 16 + li) * CSP + ks * 4 + lk];
+            for (int v = 0; v < 4; ++v) x[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb[v], x[v], 0, 0, 0);
+        }
+        __syncthreads();   // every lane has read its C before any lane overwrites it
+        for (int r = 0; r < 4; ++r) {
+            const int row = nr0 + wave * 16 + lk + 4 * r;
+            double sr = 0.0, si = 0.0;
+            for (int v = 0; v < 4; ++v) {
+                const int col = v * 16 + li;
+                const double xv = x[v][r];
+                if (row < nend && col < jb) A[(size_t)row * M + j0 + col] = xv;
+                sr += xv * yre[col];
+                si += xv * yim[col];
+            }
+            for (int o = 1; o < 16; o <<= 1) {
+                sr += __shfl_xor(sr, o, 64);
+                si += __shfl_xor(si, o, 64);
+            }
+            if (li == 0 && row < nend) {
+                const double2 zr = z[row];
+                z[row] = make_double2(zr.x - sr, zr.y - si);
+            }
+        }
+    }
     if (tid < jb) z[j0 + tid] = make_double2(yre[tid], yim[tid]);
     if (tid == 0 && bad) a.flags[t] = 1;
 }
@@ -209,6 +414,74 @@ __global__ __launch_bounds__(256) void k_cmw_trsm(CholArgs a, int j0, int p) {
                 z[row] = make_double2(zr.x - sr, zr.y - si);
             }
         }
+}
+
+// L^T x = y by row panels over every compute unit, last panel first, one launch per panel p
+// (then a closing launch p = -1), as the complex solver's: w starts as y (in x) and, once every
+// panel below p has been applied, w_p = y_p - sum_{r below} L_rp x_r, so x_p = Linv_p^T w_p.
+// Launch p: every workgroup forms x_p in LDS and subtracts L[rows of p][c] x_p from w_c for its
+// chunk of CB_COLS columns c < j0 (one column per thread, the panel's rows read row by row,
+// coalesced); workgroup 0 also writes x_{p+1} over w_{p+1}, which no workgroup of launch p
+// reads.  The closing launch writes x_0 and flags non-finite solutions.
+constexpr int CB_COLS = 256;
+// Called by the whole workgroup: the block inverse is staged in LDS by all threads first.
+__device__ __forceinline__ void cbwd_x(const double *__restrict__ lv, double *lvs, const double2 *ws, double2 *xs, int jb,
+                                       int tid) {
+    for (int e = tid; e < jb * CN; e += CB_COLS) lvs[e] = lv[e];
+    __syncthreads();
+    if (tid < jb) {   // x_c = sum_{k >= c} Linv_kc w_k
+        double xr = 0.0, xi = 0.0;
+        for (int k = tid; k < jb; ++k) {
+            const double l = lvs[k * CN + tid];
+            xr += l * ws[k].x;
+            xi += l * ws[k].y;
+        }
+        xs[tid] = make_double2(xr, xi);
+    }
+}
+
+__global__ __launch_bounds__(CB_COLS) void k_cmw_bwd(CholArgs a, int p) {
+    __shared__ double2 ws[CN], xs[CN];
+    __shared__ double lvs[CN * CN];
+    const int t = blockIdx.y, tid = threadIdx.x;
+    const int M = a.m, np = chol_panels(M);
+    const double *A = a.A + (size_t)t * M * M;
+    const double *linv = a.linv + (size_t)t * np * CN * CN;
+    double2 *z = a.x + (size_t)t * M;
+    if (blockIdx.x == 0 && p + 1 < np) {   // x_{p+1} over w_{p+1}
+        const int j1 = (p + 1) * CN, jb1 = min(CN, M - j1);
+        if (tid < jb1) ws[tid] = z[j1 + tid];
+        __syncthreads();
+        cbwd_x(linv + (size_t)(p + 1) * CN * CN, lvs, ws, xs, jb1, tid);
+        __syncthreads();
+        if (tid < jb1) z[j1 + tid] = xs[tid];
+        __syncthreads();
+    }
+    if (p < 0) {
+        if (tid == 0) {
+            int nf = 0;
+            for (int i = 0; i < M && !nf; ++i)
+                if (!isfinite(z[i].x) || !isfinite(z[i].y)) nf = 1;
+            if (nf) a.flags[t] = 1;
+        }
+        return;
+    }
+    const int j0 = p * CN, jb = min(CN, M - j0);
+    if (tid < jb) ws[tid] = z[j0 + tid];
+    __syncthreads();
+    cbwd_x(linv + (size_t)p * CN * CN, lvs, ws, xs, jb, tid);
+    __syncthreads();
+    const int c = blockIdx.x * CB_COLS + tid;
+    if (c < j0) {
+        double sr = 0.0, si = 0.0;
+        const double *col = A + (size_t)j0 * M + c;
+        for (int r = 0; r < jb; ++r) {
+            const double l = col[(size_t)r * M];
+            sr += l * xs[r].x;
+            si += l * xs[r].y;
+        }
+        z[c] = make_double2(z[c].x - sr, z[c].y - si);
+    }
 }
 
 // backward substitution L^T x = y, last panel first; wave w owns 16 panel columns

@@ -345,14 +345,18 @@ __global__ __launch_bounds__(ZT) void k_zmw_update_lds(ZCholArgs a, int j0, int 
         }
 #undef ZU_COPY
     }
+    double2 cv[4][4];   // every load of C issued before the first subtraction waits for one
     for (int v = 0; v < 4; ++v)
         for (int r = 0; r < 4; ++r) {
             const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
-            if (r0 + row < M && col < jb) {
-                double2 *c = A + (size_t)(r0 + row) * M + j0 + col;
-                const double2 cv = *c;
-                *c = make_double2(cv.x - pre[v][r], cv.y - (pia[v][r] - pib[v][r]));
-            }
+            cv[v][r] = (r0 + row < M && col < jb) ? A[(size_t)(r0 + row) * M + j0 + col] : make_double2(0.0, 0.0);
+        }
+    for (int v = 0; v < 4; ++v)
+        for (int r = 0; r < 4; ++r) {
+            const int row = wave * 16 + lk + 4 * r, col = v * 16 + li;
+            if (r0 + row < M && col < jb)
+                A[(size_t)(r0 + row) * M + j0 + col] =
+                    make_double2(cv[v][r].x - pre[v][r], cv[v][r].y - (pia[v][r] - pib[v][r]));
         }
 }
 

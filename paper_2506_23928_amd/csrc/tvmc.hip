@@ -565,6 +565,42 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
         hipLaunchKernelGGL(k_cmw_init, dim3((x.m + 255) / 256, T), dim3(256), 0, st, x);
     }
     LAUNCHCHECK(c, "solver init");
+    // real: the direct-to-LDS updates (32-bit byte offsets into a trajectory's matrix) carry the
+    // previous panel's TRSM of their rows below those the diagonal kernel did, and the diagonal
+    // kernel the following rows; panels go in pairs: one 128-column update over [0, j0), the
+    // first panel's diagonal step (TRSM of the second panel's rows), the second panel's update
+    // over the first panel's columns, its diagonal step (TRSM of the next pair's 2 CN rows)
+    const bool real_lds = !CPLX && (size_t)x.m * x.m * sizeof(double) <= 0xffffffffull;
+    if constexpr (!CPLX) {
+        if (real_lds) {
+            for (int j0 = 0, p = 0; j0 < x.m; j0 += 2 * CN, p += 2) {
+                const bool second = j0 + CN < x.m;
+                if (j0 > 0) {
+                    hipLaunchKernelGGL(k_cmw_update_lds<2 * CN>, dim3((x.m - j0 + CR - 1) / CR, T), dim3(CUT), 0, st,
+                                       x, j0, p - 1, 0, 2 * CN);
+                    LAUNCHCHECK(c, "panel-pair update");
+                }
+                hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(CDT), 0, st, x, j0, p, second ? CN : 0);
+                LAUNCHCHECK(c, "diagonal block");
+                if (second) {
+                    const int j1 = j0 + CN;
+                    hipLaunchKernelGGL(k_cmw_update_lds<CN>, dim3((x.m - j1 + CR - 1) / CR, T), dim3(CUT), 0, st, x,
+                                       j1, p, j0, CN);
+                    LAUNCHCHECK(c, "panel update");
+                    hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(CDT), 0, st, x, j1, p + 1,
+                                       j1 + CN < x.m ? 2 * CN : 0);
+                    LAUNCHCHECK(c, "diagonal block");
+                }
+            }
+            for (int p = chol_panels(x.m) - 1; p >= -1; --p) {
+                const int cols = p > 0 ? p * CN : 0;
+                hipLaunchKernelGGL(k_cmw_bwd, dim3(cols > 0 ? (cols + CB_COLS - 1) / CB_COLS : 1, T), dim3(CB_COLS), 0,
+                                   st, x, p);
+            }
+            LAUNCHCHECK(c, "backward substitution");
+            return TVMC_OK;
+        }
+    }
     for (int j0 = 0, p = 0; j0 < x.m; j0 += CN, ++p) {
         if (j0 > 0) {
             // complex: the previous panel's TRSM of the rows below this panel rides in the update;
@@ -575,14 +611,15 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
                     hipLaunchKernelGGL(k_zmw_update_lds, grid, dim3(ZT), 0, st, x, j0, p - 1);
                 else
                     hipLaunchKernelGGL(k_zmw_update, grid, dim3(ZT), 0, st, x, j0, p - 1);
-            } else
+            } else {
                 hipLaunchKernelGGL(k_cmw_update, dim3((x.m - j0 + CR - 1) / CR, T), dim3(256), 0, st, x, j0);
+            }
             LAUNCHCHECK(c, "panel update");
         }
         if constexpr (CPLX)
             hipLaunchKernelGGL(k_zmw_diag, dim3(T), dim3(ZD), 0, st, x, j0, p);
         else
-            hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, st, x, j0, p);
+            hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(CDT), 0, st, x, j0, p, 0);
         LAUNCHCHECK(c, "diagonal block");
         const int below = x.m - j0 - CN;
         if constexpr (!CPLX) {
@@ -636,12 +673,11 @@ tvmc_status solve_split(tvmc_ctx *c, const Args &x) {
     return TVMC_OK;
 }
 
-// The FP64 Cholesky solve: one workgroup per trajectory, or several per trajectory when the
-// batch alone would leave most compute units idle.
+// The FP64 Cholesky solve: several workgroups per trajectory unless one per trajectory is
+// asked for.
 tvmc_status launch_chol(tvmc_ctx *c, const CholArgs &ca) {
     const int T = c->d.nt;
-    const bool multi = c->cfg.solver == TVMC_SOLVER_MULTI_GROUP ||
-                       (c->cfg.solver != TVMC_SOLVER_ONE_GROUP && T < 192);
+    const bool multi = c->cfg.solver != TVMC_SOLVER_ONE_GROUP;
     if (!multi) {
         hipLaunchKernelGGL(k_chol_solve, dim3(T), dim3(CT1), 0, c->stream, ca);
         LAUNCHCHECK(c, "k_chol_solve");
