@@ -81,7 +81,8 @@ def ansatz_of(tv, w):
     return tv.JASTROW, 0, tv.n_params(tv.JASTROW, w["n"]), None
 
 
-def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, solver=0, regulariser=0, graph=False):
+def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, solver=0, regulariser=0, graph=False,
+                  sampler_chains=0):
     from paper_2506_23928_amd.problem import kac_couplings
     import workloads as wl
     lx, ly = wl.lattice(w)
@@ -96,7 +97,8 @@ def build_context(tv, w, precision, n_traj=None, traj_offset=0, proposal=None, s
                          steps // w["obs_every"] + 2, w["seed"], traj_offset, proposal=proposal,
                          ar_hidden=w.get("ar_hidden", 128), ar_train_every=w.get("ar_train_every", 20),
                          ar_train_iters=w.get("ar_train_iters", 50), ar_lr=w.get("ar_lr", 3e-3), solver=solver,
-                         regulariser=regulariser, snr_tau=w.get("snr_tau", 4.0), use_graph=graph)
+                         regulariser=regulariser, snr_tau=w.get("snr_tau", 4.0), use_graph=graph,
+                         sampler_chains=sampler_chains)
     return tv.Context(prob, cfg, kind=kind, n_hidden=nh, theta0=th0)
 
 
@@ -498,6 +500,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="chain64_rbm_learned")
     ap.add_argument("--precision", choices=["mfma", "fp64"], default="mfma")
+    ap.add_argument("--sampler-chains", type=int, default=0,
+                    help="Markov chains per sampler workgroup (1, 2, 4, 8, 16; 0: the library's choice)")
     ap.add_argument("--solver", choices=["auto", "one", "multi"], default="auto",
                     help="FP64 Cholesky with one or several workgroups per trajectory (auto: by batch size)")
     ap.add_argument("--regulariser", choices=["shift", "snr"], default="shift",
@@ -587,7 +591,8 @@ def main():
         return
     solver = {"auto": tv.tvmc.SOLVER_AUTO, "one": tv.tvmc.SOLVER_ONE_GROUP, "multi": tv.tvmc.SOLVER_MULTI_GROUP}[args.solver]
     reg = tv.tvmc.REG_SNR if args.regulariser == "snr" else tv.tvmc.REG_SHIFT
-    ctx = build_context(tv, w, prec, solver=solver, regulariser=reg, graph=args.graph)
+    ctx = build_context(tv, w, prec, solver=solver, regulariser=reg, graph=args.graph,
+                        sampler_chains=args.sampler_chains)
     for _ in range(args.warmup):
         ctx.sde_step(1)
     ctx.synchronize()
