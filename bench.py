@@ -188,7 +188,7 @@ def roofline_of(tv, groups, kind, prec, ss, m, ns, nh, T, reg, solver_arg, group
             kname = "k_zmw_solve"     # k_zmw_init, k_zmw_update(_lds), k_zmw_diag, k_zmw_bwd
         else:
             flops = T * (dim ** 3 / 3.0 + dim * dim / 2.0 + dim / 6.0 + 4.0 * dim * dim)
-            multi = solver_arg != "one"
+            multi = solver_arg == "multi" or (solver_arg != "one" and T < 192)
             kname = "k_cmw_solve" if multi else "k_chol_solve"   # k_cmw_*: the several-workgroup launches
         if ss:               # push-back delta = A^H u: M x N_s complex multiply-adds
             flops += T * 8.0 * m * ns
@@ -528,6 +528,8 @@ def main():
     ap.add_argument("--autocorr-json", default=None, help="--error-summary: a saved --autocorr result to include")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-fixed-error", action="store_true",
+                    help="skip re-timing the fast form at its equal-error sample count (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run an elementwise device copy of 1 GiB (read 1 GiB, write 1 GiB), the known-size "
                          "reference that scales the FETCH_SIZE / WRITE_SIZE counters")
@@ -629,7 +631,7 @@ def main():
     # and --error-summary): the fast form's N_s at equal error, timed here over the same steps
     fixed = None
     fe_path = os.path.join(ROOT, "profiles", "fixed_error_%s.json" % args.workload)
-    if os.path.exists(fe_path) and not args.graph:
+    if os.path.exists(fe_path) and not args.graph and not args.no_fixed_error:
         fe = json.load(open(fe_path))
         ns_f = fe["n_samples_fast"]
         rate_f = value

@@ -144,8 +144,8 @@ enum { TVMC_SSE_NONLINEAR = 0, TVMC_SSE_LINEAR = 1 };
 
 enum { TVMC_PROPOSAL_FLIP = 0, TVMC_PROPOSAL_LEARNED = 1 };
 /* FP64 Cholesky of S + eps I: one workgroup per trajectory (one launch per solve), or several
- * workgroups per trajectory (about one launch per 64-column panel, spread over every compute
- * unit); AUTO takes the several-workgroup form, the faster one at every batch size measured. */
+ * workgroups per trajectory (a few launches per 64-column panel), which fills the device when
+ * the batch has fewer trajectories than compute units; AUTO picks by batch size. */
 enum { TVMC_SOLVER_AUTO = 0, TVMC_SOLVER_ONE_GROUP = 1, TVMC_SOLVER_MULTI_GROUP = 2 };
 /* Sample space: the same increment through the push-through identity
  * (A^H A + eps I)^-1 A^H = A^H (A A^H + eps I)^-1 with A = (O - <O>) / sqrt(N_s), i.e. an

@@ -241,10 +241,7 @@ __global__ __launch_bounds__(CUT) void k_cmw_update_lds(CholArgs a, int j0, int 
         }
 }
 
-// One workgroup of CDT threads per trajectory: 16 lanes per row of the block while factoring,
-// 16 lanes per column of the inverse, one wave per 16 of the following rows in the TRSM.
-constexpr int CDT = 1024;
-__global__ __launch_bounds__(CDT) void k_cmw_diag(CholArgs a, int j0, int p, int next) {
+__global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p, int next) {
     __shared__ double Cs[CN * CSP];
     __shared__ double Ls[CN * CSP];
     __shared__ double yre[CN], yim[CN];
@@ -255,16 +252,15 @@ __global__ __launch_bounds__(CDT) void k_cmw_diag(CholArgs a, int j0, int p, int
     double *A = a.A + (size_t)t * M * M;
     double2 *z = a.x + (size_t)t * M;
     if (tid == 0) bad = 0;
-    for (int e = tid; e < CN * CN; e += CDT) {
+    for (int e = tid; e < CN * CN; e += 256) {
         const int r = e / CN, c = e % CN;
         Cs[r * CSP + c] = (r < jb && c <= r) ? A[(size_t)(j0 + r) * M + j0 + c] : 0.0;
     }
     __syncthreads();
-    // right-looking factor of the block in LDS; thread (row fr, phase fs) updates columns
-    // c+1+fs, c+17+fs, ... of its row; column c is read unscaled during step c and scaled after
-    // the barrier
+    // right-looking factor of the block in LDS; thread (row fr, phase fs) updates columns fs,
+    // fs+4, ... of its row; column c is read unscaled during step c and scaled after the barrier
     {
-        const int fr = tid >> 4, fs = tid & 15;
+        const int fr = tid >> 2, fs = tid & 3;
         for (int c = 0; c < jb; ++c) {
             const double piv = Cs[c * CSP + c];
             if (tid == 0 && !(piv > 0.0)) bad = 1;
@@ -272,7 +268,7 @@ __global__ __launch_bounds__(CDT) void k_cmw_diag(CholArgs a, int j0, int p, int
             double lrc = 0.0;
             if (fr > c && fr < jb) {
                 lrc = Cs[fr * CSP + c] * inv;
-                for (int k = c + 1 + fs; k <= fr; k += 16) Cs[fr * CSP + k] -= lrc * (Cs[k * CSP + c] * inv);
+                for (int k = c + 1 + fs; k <= fr; k += 4) Cs[fr * CSP + k] -= lrc * (Cs[k * CSP + c] * inv);
             }
             __syncthreads();
             if (fs == 0 && fr > c && fr < jb) Cs[fr * CSP + c] = lrc;
@@ -280,21 +276,21 @@ __global__ __launch_bounds__(CDT) void k_cmw_diag(CholArgs a, int j0, int p, int
         }
         __syncthreads();
     }
-    for (int e = tid; e < jb * jb; e += CDT) {
+    for (int e = tid; e < jb * jb; e += 256) {
         const int r = e / jb, c = e % jb;
         if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
     }
-    // Linv by forward substitution: wave w owns columns 4w..4w+3, 16 lanes per column (rows of
-    // one column are written and read back by the same wave, in order)
+    // Linv by forward substitution: wave w owns columns 16w..16w+15, four lanes per column
     {
-        const int c = wave * 4 + (lane >> 4), fs = lane & 15;
-        for (int r = fs; r < CN; r += 16) Ls[r * CSP + c] = 0.0;
+        const int c = wave * 16 + (lane >> 2), fs = lane & 3;
+        for (int r = fs; r < CN; r += 4) Ls[r * CSP + c] = 0.0;
         if (c < jb) {
             if (fs == 0) Ls[c * CSP + c] = 1.0 / Cs[c * CSP + c];
             for (int r = c + 1; r < jb; ++r) {
                 double sum = 0.0;
-                for (int k = c + fs; k < r; k += 16) sum += Cs[r * CSP + k] * Ls[k * CSP + c];
-                for (int o = 1; o < 16; o <<= 1) sum += __shfl_xor(sum, o, 64);
+                for (int k = c + fs; k < r; k += 4) sum += Cs[r * CSP + k] * Ls[k * CSP + c];
+                sum += __shfl_xor(sum, 1, 64);
+                sum += __shfl_xor(sum, 2, 64);
                 if (fs == 0) Ls[r * CSP + c] = -sum / Cs[r * CSP + r];
             }
         }
@@ -312,24 +308,23 @@ __global__ __launch_bounds__(CDT) void k_cmw_diag(CholArgs a, int j0, int p, int
         yim[tid] = si;
     }
     double *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
-    for (int e = tid; e < CN * CN; e += CDT) lv[e] = Ls[(e / CN) * CSP + e % CN];
+    for (int e = tid; e < CN * CN; e += 256) lv[e] = Ls[(e / CN) * CSP + e % CN];
     if (tid >= jb && tid < CN) {
         yre[tid] = 0.0;
         yim[tid] = 0.0;
     }
     __syncthreads();
-    if (next > 0) {
-        // the following rows (the first `next` <= 16 x 16 rows below the block): X = C Linv^T over
-        // C and z[rows] -= X y; wave w takes rows 16 w .. +15 (the next update does the TRSM of
-        // the rows below those)
+    for (int nr0 = j0 + jb; nr0 < j0 + jb + next; nr0 += CN) {
+        // the following rows (the first `next` rows below the block, CN at a time): X = C Linv^T
+        // over C and z[rows] -= X y; wave w takes rows 16 w .. +15 (the next update does the
+        // TRSM of the rows below those)
         const int li = lane & 15, lk = lane >> 4;
-        const int nr0 = j0 + jb, nend = min(M, nr0 + next);
         v4d x[4];
         for (int v = 0; v < 4; ++v) x[v] = (v4d){0.0, 0.0, 0.0, 0.0};
         for (int ks = 0; ks < CN / 4; ++ks) {
             double fb[4];
             const int row = nr0 + wave * 16 + li, col = ks * 4 + lk;
-            const double fa = (row < nend && col < jb) ? A[(size_t)row * M + j0 + col] : 0.0;
+            const double fa = (row < M && col < jb) ? A[(size_t)row * M + j0 + col] : 0.0;
             for (int v = 0; v < 4; ++v) fb[v] = Ls[(v * 16 + li) * CSP + ks * 4 + lk];
             for (int v = 0; v < 4; ++v) x[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb[v], x[v], 0, 0, 0);
         }
@@ -340,7 +335,7 @@ __global__ __launch_bounds__(CDT) void k_cmw_diag(CholArgs a, int j0, int p, int
             for (int v = 0; v < 4; ++v) {
                 const int col = v * 16 + li;
                 const double xv = x[v][r];
-                if (row < nend && col < jb) A[(size_t)row * M + j0 + col] = xv;
+                if (row < M && col < jb) A[(size_t)row * M + j0 + col] = xv;
                 sr += xv * yre[col];
                 si += xv * yim[col];
             }
@@ -348,7 +343,7 @@ __global__ __launch_bounds__(CDT) void k_cmw_diag(CholArgs a, int j0, int p, int
                 sr += __shfl_xor(sr, o, 64);
                 si += __shfl_xor(si, o, 64);
             }
-            if (li == 0 && row < nend) {
+            if (li == 0 && row < M) {
                 const double2 zr = z[row];
                 z[row] = make_double2(zr.x - sr, zr.y - si);
             }
@@ -414,74 +409,6 @@ __global__ __launch_bounds__(256) void k_cmw_trsm(CholArgs a, int j0, int p) {
                 z[row] = make_double2(zr.x - sr, zr.y - si);
             }
         }
-}
-
-// L^T x = y by row panels over every compute unit, last panel first, one launch per panel p
-// (then a closing launch p = -1), as the complex solver's: w starts as y (in x) and, once every
-// panel below p has been applied, w_p = y_p - sum_{r below} L_rp x_r, so x_p = Linv_p^T w_p.
-// Launch p: every workgroup forms x_p in LDS and subtracts L[rows of p][c] x_p from w_c for its
-// chunk of CB_COLS columns c < j0 (one column per thread, the panel's rows read row by row,
-// coalesced); workgroup 0 also writes x_{p+1} over w_{p+1}, which no workgroup of launch p
-// reads.  The closing launch writes x_0 and flags non-finite solutions.
-constexpr int CB_COLS = 256;
-// Called by the whole workgroup: the block inverse is staged in LDS by all threads first.
-__device__ __forceinline__ void cbwd_x(const double *__restrict__ lv, double *lvs, const double2 *ws, double2 *xs, int jb,
-                                       int tid) {
-    for (int e = tid; e < jb * CN; e += CB_COLS) lvs[e] = lv[e];
-    __syncthreads();
-    if (tid < jb) {   // x_c = sum_{k >= c} Linv_kc w_k
-        double xr = 0.0, xi = 0.0;
-        for (int k = tid; k < jb; ++k) {
-            const double l = lvs[k * CN + tid];
-            xr += l * ws[k].x;
-            xi += l * ws[k].y;
-        }
-        xs[tid] = make_double2(xr, xi);
-    }
-}
-
-__global__ __launch_bounds__(CB_COLS) void k_cmw_bwd(CholArgs a, int p) {
-    __shared__ double2 ws[CN], xs[CN];
-    __shared__ double lvs[CN * CN];
-    const int t = blockIdx.y, tid = threadIdx.x;
-    const int M = a.m, np = chol_panels(M);
-    const double *A = a.A + (size_t)t * M * M;
-    const double *linv = a.linv + (size_t)t * np * CN * CN;
-    double2 *z = a.x + (size_t)t * M;
-    if (blockIdx.x == 0 && p + 1 < np) {   // x_{p+1} over w_{p+1}
-        const int j1 = (p + 1) * CN, jb1 = min(CN, M - j1);
-        if (tid < jb1) ws[tid] = z[j1 + tid];
-        __syncthreads();
-        cbwd_x(linv + (size_t)(p + 1) * CN * CN, lvs, ws, xs, jb1, tid);
-        __syncthreads();
-        if (tid < jb1) z[j1 + tid] = xs[tid];
-        __syncthreads();
-    }
-    if (p < 0) {
-        if (tid == 0) {
-            int nf = 0;
-            for (int i = 0; i < M && !nf; ++i)
-                if (!isfinite(z[i].x) || !isfinite(z[i].y)) nf = 1;
-            if (nf) a.flags[t] = 1;
-        }
-        return;
-    }
-    const int j0 = p * CN, jb = min(CN, M - j0);
-    if (tid < jb) ws[tid] = z[j0 + tid];
-    __syncthreads();
-    cbwd_x(linv + (size_t)p * CN * CN, lvs, ws, xs, jb, tid);
-    __syncthreads();
-    const int c = blockIdx.x * CB_COLS + tid;
-    if (c < j0) {
-        double sr = 0.0, si = 0.0;
-        const double *col = A + (size_t)j0 * M + c;
-        for (int r = 0; r < jb; ++r) {
-            const double l = col[(size_t)r * M];
-            sr += l * xs[r].x;
-            si += l * xs[r].y;
-        }
-        z[c] = make_double2(z[c].x - sr, z[c].y - si);
-    }
 }
 
 // backward substitution L^T x = y, last panel first; wave w owns 16 panel columns

@@ -580,23 +580,19 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
                                        x, j0, p - 1, 0, 2 * CN);
                     LAUNCHCHECK(c, "panel-pair update");
                 }
-                hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(CDT), 0, st, x, j0, p, second ? CN : 0);
+                hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, st, x, j0, p, second ? CN : 0);
                 LAUNCHCHECK(c, "diagonal block");
                 if (second) {
                     const int j1 = j0 + CN;
                     hipLaunchKernelGGL(k_cmw_update_lds<CN>, dim3((x.m - j1 + CR - 1) / CR, T), dim3(CUT), 0, st, x,
                                        j1, p, j0, CN);
                     LAUNCHCHECK(c, "panel update");
-                    hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(CDT), 0, st, x, j1, p + 1,
+                    hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, st, x, j1, p + 1,
                                        j1 + CN < x.m ? 2 * CN : 0);
                     LAUNCHCHECK(c, "diagonal block");
                 }
             }
-            for (int p = chol_panels(x.m) - 1; p >= -1; --p) {
-                const int cols = p > 0 ? p * CN : 0;
-                hipLaunchKernelGGL(k_cmw_bwd, dim3(cols > 0 ? (cols + CB_COLS - 1) / CB_COLS : 1, T), dim3(CB_COLS), 0,
-                                   st, x, p);
-            }
+            hipLaunchKernelGGL(k_cmw_backward, dim3(T), dim3(256), 0, st, x);
             LAUNCHCHECK(c, "backward substitution");
             return TVMC_OK;
         }
@@ -619,7 +615,7 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
         if constexpr (CPLX)
             hipLaunchKernelGGL(k_zmw_diag, dim3(T), dim3(ZD), 0, st, x, j0, p);
         else
-            hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(CDT), 0, st, x, j0, p, 0);
+            hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, st, x, j0, p, 0);
         LAUNCHCHECK(c, "diagonal block");
         const int below = x.m - j0 - CN;
         if constexpr (!CPLX) {
@@ -673,11 +669,12 @@ tvmc_status solve_split(tvmc_ctx *c, const Args &x) {
     return TVMC_OK;
 }
 
-// The FP64 Cholesky solve: several workgroups per trajectory unless one per trajectory is
-// asked for.
+// The FP64 Cholesky solve: one workgroup per trajectory, or several per trajectory when the
+// batch alone would leave most compute units idle.
 tvmc_status launch_chol(tvmc_ctx *c, const CholArgs &ca) {
     const int T = c->d.nt;
-    const bool multi = c->cfg.solver != TVMC_SOLVER_ONE_GROUP;
+    const bool multi = c->cfg.solver == TVMC_SOLVER_MULTI_GROUP ||
+                       (c->cfg.solver != TVMC_SOLVER_ONE_GROUP && T < 192);
     if (!multi) {
         hipLaunchKernelGGL(k_chol_solve, dim3(T), dim3(CT1), 0, c->stream, ca);
         LAUNCHCHECK(c, "k_chol_solve");

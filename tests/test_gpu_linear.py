@@ -121,3 +121,30 @@ def test_linear_ljph_trajectory_parity(tv, orc):
     m = orc.n_params(2, n, d)
     th0 = wl.random_theta(m, 0.05, seed=4)
     _run_pair(tv, orc, 2, d, J, 0.4, jumps, th0, 3, 512, 8, 0.01, 1e-4, 7, 8, 4, 0)
+
+
+def test_ensemble_at_and_leave_one_out_match_oracle(orc):
+    """tvmc_ensemble_at at every history record and at the last moments, and its jackknife (the
+    leave-one-out xi^2 of every trajectory, formed on the GPU), against the oracle's ensemble of
+    the same per-trajectory moments, with and without each trajectory in turn (1e-12)."""
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2506_23928_amd as tv
+    from paper_2506_23928_amd import tvmc as T
+    n, ns, nc, TT, steps, every = 6, 256, 8, 7, 6, 2
+    J, hx, jumps = wl.random_problem(n, seed=21)
+    nobs = steps // every
+    cfg = tv.make_config(TT, ns, nc, 0.01, 1e-4, 2, 1, 0, tv.HEUN, tv.PREC_FP64, every, nobs + 1, 5)
+    ctx = tv.Context(tv.Problem(J, hx, jumps), cfg)
+    ctx.sde_step(steps)
+    ctx.sample()
+    ctx.observables()
+    ctx.synchronize()
+    hist = np.stack([ctx.get(T.Q_OBS_HIST, t) for t in range(TT)])
+    final = np.stack([ctx.get(T.Q_MOMENTS, t) for t in range(TT)])
+    for slot, mom in [(k, hist[:, k]) for k in range(nobs)] + [(-1, final)]:
+        M, C, x2, loo = ctx.ensemble_at(slot, jackknife=True)
+        Mo, Co, xo = orc.ensemble(mom, n)
+        assert np.abs(M - Mo).max() < 1e-12 and np.abs(C - Co).max() < 1e-12 and abs(x2 - xo) < 1e-12, slot
+        want = np.array([orc.ensemble(np.delete(mom, d, axis=0), n)[2] for d in range(TT)])
+        assert np.abs(loo - want).max() < 1e-12, (slot, loo, want)
