@@ -479,10 +479,12 @@ __global__ __launch_bounds__(256) void k_sbuild_rbm_f64(Dev a) {
 // so psi(s^(ab))/psi(s) = R_a R_b prod_j (1 + beta_j(a) alpha_j(b)) with alpha_j(a) =
 // sinh u / f_j(a), beta_j(a) = (1 - t_j^2) alpha_j(a) and R_a the single-flip ratio.  A
 // workgroup takes one sample at a time: alpha and beta for all (j, a) in LDS, then every
-// unordered pair a < b (pairs spread over the 4 waves, a on the lanes) multiplies N' factors
-// 1 + beta alpha, rescaled by a power of two every 16 (exact).  The pair terms are symmetric except
-// s_b Im R_ab, which enters as (s_a + s_b) Im R_ab.
-constexpr int RMF_WAVES = 4;
+// unordered pair a < b (pairs spread over the 8 waves, a on the lanes, RMF_PB values of b per
+// pass: that many independent product chains per lane, with two waves per SIMD, to cover the
+// multiply latency) multiplies N' factors 1 + beta alpha, rescaled by a power of two every 16
+// (exact).  The pair terms are symmetric except s_b Im R_ab, which enters as (s_a + s_b) Im R_ab.
+constexpr int RMF_WAVES = 8;
+constexpr int RMF_PB = 8;
 __global__ __launch_bounds__(64 * RMF_WAVES) void k_moments_rbm_f(Dev a) {
     __shared__ double2 al[64 * 64], be[64 * 64];      // [j][a]
     __shared__ double2 tl[64];
@@ -529,25 +531,25 @@ __global__ __launch_bounds__(64 * RMF_WAVES) void k_moments_rbm_f(Dev a) {
             v[7] = ssum * Ra.x;
             v[8] = sa * ssum * Ra.y;
         }
-        // wave w takes b = 1 + w + 4 c; four values of b at a time (b0 + 4 k) give four
-        // independent product chains per lane
+        // wave w takes b = 1 + w + RMF_WAVES c; RMF_PB values of b at a time (b0 + RMF_WAVES k)
+        // give RMF_PB independent product chains per lane
         const int li = act ? lane : 0;
-        for (int b0 = 1 + w; b0 < n; b0 += 4 * RMF_WAVES) {
-            double pr[4], pi[4];
-            int ex2[4], bk[4];   // products kept as (pr + i pi) 2^ex2, rescaled by powers of two
-            for (int k = 0; k < 4; ++k) {
+        for (int b0 = 1 + w; b0 < n; b0 += RMF_PB * RMF_WAVES) {
+            double pr[RMF_PB], pi[RMF_PB];
+            int ex2[RMF_PB], bk[RMF_PB];   // products kept as (pr + i pi) 2^ex2, rescaled by powers of two
+            for (int k = 0; k < RMF_PB; ++k) {
                 pr[k] = 1.0;
                 pi[k] = 0.0;
                 ex2[k] = 0;
-                bk[k] = b0 + 4 * k < n ? b0 + 4 * k : n - 1;
+                bk[k] = b0 + RMF_WAVES * k < n ? b0 + RMF_WAVES * k : n - 1;
             }
             int blast = b0;
-            for (int k = 1; k < 4; ++k)
-                if (b0 + 4 * k < n) blast = b0 + 4 * k;
+            for (int k = 1; k < RMF_PB; ++k)
+                if (b0 + RMF_WAVES * k < n) blast = b0 + RMF_WAVES * k;
             if (!(act && lane < blast)) continue;   // pairs a < b of the group
             for (int j = 0; j < nh; ++j) {
                 const double2 x = be[j * n + li];
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < RMF_PB; ++k) {
                     const double2 y = al[j * n + bk[k]];
                     const double fr = 1.0 + (x.x * y.x - x.y * y.y), fi = x.x * y.y + x.y * y.x;
                     const double nr = pr[k] * fr - pi[k] * fi, ni = pr[k] * fi + pi[k] * fr;
@@ -555,7 +557,7 @@ __global__ __launch_bounds__(64 * RMF_WAVES) void k_moments_rbm_f(Dev a) {
                     pi[k] = ni;
                 }
                 if ((j & 15) == 15)
-                    for (int k = 0; k < 4; ++k) {
+                    for (int k = 0; k < RMF_PB; ++k) {
                         int e;
                         frexp(fabs(pr[k]) + fabs(pi[k]), &e);
                         pr[k] = ldexp(pr[k], -e);
@@ -563,8 +565,8 @@ __global__ __launch_bounds__(64 * RMF_WAVES) void k_moments_rbm_f(Dev a) {
                         ex2[k] += e;
                     }
             }
-            for (int k = 0; k < 4; ++k) {
-                const int b = b0 + 4 * k;
+            for (int k = 0; k < RMF_PB; ++k) {
+                const int b = b0 + RMF_WAVES * k;
                 if (b >= n) break;
                 if (lane >= b) continue;
                 const double sb = spin(mk, b), ss = sa * sb;
