@@ -220,6 +220,7 @@ struct Dev {
     double *S;                // [T][M][M]
     double *linv;             // [T][panels][64*64] inverses of the Cholesky diagonal blocks
     double *mom_part;         // [T][mom_blocks][9]
+    double2 *momtab;          // RBM moments with N > 64 or N N' > 4096: [T][mom_blocks][2][N'][N] tables
     double *mom;              // [T][9]
     double *hist;             // [nobs][T][9]
     double *ens;              // [16]

@@ -598,90 +598,121 @@ __global__ __launch_bounds__(64 * RMF_WAVES) void k_moments_rbm_f(Dev a) {
     }
 }
 
-// Moments for the RBM, direct form: two-flip ratios psi(s^(ab))/psi(s) = exp(-2 s_a a_a - 2 s_b a_b)
-// prod_j [cosh(u+v) - tanh(g_j) sinh(u+v)],  u = 2 s_a w_aj, v = 2 s_b w_bj.
-constexpr int RMOM_WAVES = 4;
+// Moments for the RBM, factored form with the tables in global memory (N > 64 or N N' > 4096,
+// where alpha and beta do not fit LDS): the same pair products as k_moments_rbm_f, each
+// workgroup writing alpha and beta of its current sample to its own slice of the workspace
+// (2 N N' complex, read back from L2), lanes a = lane + 64 q over the configuration's words.
 template <int W>
-__global__ __launch_bounds__(64 * RMOM_WAVES) void k_moments_rbm(Dev a) {
-    __shared__ double part[RMOM_WAVES][9];
-    __shared__ double2 tl[RMOM_WAVES][256];
+__global__ __launch_bounds__(64 * RMF_WAVES) void k_moments_rbm_g(Dev a) {
+    __shared__ double2 tl[256];
+    __shared__ double part[RMF_WAVES][9];
     const int t = blockIdx.y;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int n = a.n, nh = a.nh;
     const double N = (double)n;
     double acc[9] = {};
     const double2 *cT = a.cT + (size_t)t * nh * n, *sT = a.sT + (size_t)t * nh * n;
-    const double2 *th = a.theta_eval + (size_t)t * a.m;
-    for (int s = blockIdx.x * RMOM_WAVES + w; s < a.ns; s += gridDim.x * RMOM_WAVES) {
+    double2 *al = a.momtab + ((size_t)t * a.mom_blocks + blockIdx.x) * 2 * (size_t)n * nh;   // [j][a]
+    double2 *be = al + (size_t)n * nh;
+    for (int s = blockIdx.x; s < a.ns; s += gridDim.x) {
         const size_t sidx = (size_t)t * a.ns + s;
         const Cfg<W> mk = cfg_load<W>(a.samples + sidx * W);
-        for (int j = lane; j < nh; j += 64) tl[w][j] = a.tt[sidx * nh + j];
+        __syncthreads();   // the previous sample's tables are no longer read
+        for (int j = tid; j < nh; j += blockDim.x) tl[j] = a.tt[sidx * nh + j];
+        __syncthreads();
+        for (int e = tid; e < n * nh; e += blockDim.x) {
+            const int j = e / n, i = e % n;
+            const double si = spin(mk, i);
+            const double2 ch = cT[e], sh = sT[e], tj = tl[j];
+            const double2 sh_s = make_double2(si * sh.x, si * sh.y);            // sinh u
+            const double2 ts = cmul(tj, sh_s);
+            const double2 f = make_double2(ch.x - ts.x, ch.y - ts.y);           // f_j(i)
+            const double fi = 1.0 / (f.x * f.x + f.y * f.y);
+            const double2 alpha = make_double2((sh_s.x * f.x + sh_s.y * f.y) * fi, (sh_s.y * f.x - sh_s.x * f.y) * fi);
+            const double2 t2 = cmul(tj, tj);
+            al[e] = alpha;
+            be[e] = cmul(make_double2(1.0 - t2.x, -t2.y), alpha);
+        }
+        __syncthreads();   // the tables are written before any wave reads them
         double v[9] = {};
-        // lane l takes the sites a = l + 64 q
+        int up = 0;
+        for (int q = 0; q < W; ++q) up += __popcll(mk.w[q]);
         for (int q = 0; q < W; ++q) {
-            const int sa_i = lane + 64 * q;
-            const bool act = sa_i < n;
-            const double sa = act ? spin(mk, sa_i) : 1.0;
-            const double2 Ra = act ? a.R[sidx * n + sa_i] : make_double2(0.0, 0.0);
-            if (act) {
+            const int ai = lane + 64 * q;
+            const bool act = ai < n;
+            const double sa = act ? spin(mk, ai) : 1.0;
+            const double2 Ra = act ? a.R[sidx * n + ai] : make_double2(0.0, 0.0);
+            if (w == 0 && act) {
+                // single-flip terms and the pair sums that need only R_a
+                const double ssum = (double)(2 * up - n) - sa;   // sum_{b != a} s_b
                 v[0] += Ra.x;
                 v[1] += sa * Ra.y;
                 v[2] += sa;
+                v[5] += sa * ssum;
+                v[7] += ssum * Ra.x;
+                v[8] += sa * ssum * Ra.y;
             }
-            for (int b = 0; b < n; ++b) {
-                if (!act || b == sa_i) continue;
-                const double sb = spin(mk, b), ss = sa * sb;
-                double pr = 1.0, pi = 0.0, lsum = 0.0;
-                for (int j = 0; j < nh; ++j) {
-                    const double2 ca = cT[(size_t)j * n + sa_i], sa_ = sT[(size_t)j * n + sa_i];
-                    const double2 cb = cT[(size_t)j * n + b], sb_ = sT[(size_t)j * n + b];
-                    const double2 cc = cmul(ca, cb), s2 = cmul(sa_, cb), s3 = cmul(ca, sb_), s4 = cmul(sa_, sb_);
-                    const double2 chu = make_double2(cc.x + ss * s4.x, cc.y + ss * s4.y);
-                    const double2 shu = make_double2(sa * s2.x + sb * s3.x, sa * s2.y + sb * s3.y);
-                    const double2 tsh = cmul(tl[w][j], shu);
-                    const double fr = chu.x - tsh.x, fi = chu.y - tsh.y;
-                    const double nr = pr * fr - pi * fi, ni = pr * fi + pi * fr;
-                    pr = nr;
-                    pi = ni;
-                    if ((j & 15) == 15) {
-                        const double mg = sqrt(pr * pr + pi * pi);
-                        lsum += log(mg);
-                        pr /= mg;
-                        pi /= mg;
-                    }
+            const int li = act ? ai : 0;
+            for (int b0 = 1 + w; b0 < n; b0 += RMF_PB * RMF_WAVES) {
+                double pr[RMF_PB], pi[RMF_PB];
+                int ex2[RMF_PB], bk[RMF_PB];
+                for (int k = 0; k < RMF_PB; ++k) {
+                    pr[k] = 1.0;
+                    pi[k] = 0.0;
+                    ex2[k] = 0;
+                    bk[k] = b0 + RMF_WAVES * k < n ? b0 + RMF_WAVES * k : n - 1;
                 }
-                const double er = lsum - 2.0 * sa * th[sa_i].x - 2.0 * sb * th[b].x;
-                const double ei = -2.0 * sa * th[sa_i].y - 2.0 * sb * th[b].y;
-                const double ex = exp(er);
-                double sn, cs;
-                sincos(ei, &sn, &cs);
-                const double2 Rab = cmul(make_double2(pr, pi), make_double2(ex * cs, ex * sn));
-                v[3] += Rab.x;
-                v[4] += -ss * Rab.x;
-                v[5] += ss;
-                v[6] += sb * Rab.y;
-                v[7] += sb * Ra.x;
-                v[8] += ss * Ra.y;
+                int blast = b0;
+                for (int k = 1; k < RMF_PB; ++k)
+                    if (b0 + RMF_WAVES * k < n) blast = b0 + RMF_WAVES * k;
+                if (!(act && ai < blast)) continue;   // pairs a < b of the group
+                for (int j = 0; j < nh; ++j) {
+                    const double2 x = be[(size_t)j * n + li];
+                    for (int k = 0; k < RMF_PB; ++k) {
+                        const double2 y = al[(size_t)j * n + bk[k]];
+                        const double fr = 1.0 + (x.x * y.x - x.y * y.y), fi = x.x * y.y + x.y * y.x;
+                        const double nr = pr[k] * fr - pi[k] * fi, ni = pr[k] * fi + pi[k] * fr;
+                        pr[k] = nr;
+                        pi[k] = ni;
+                    }
+                    if ((j & 15) == 15)
+                        for (int k = 0; k < RMF_PB; ++k) {
+                            int e;
+                            frexp(fabs(pr[k]) + fabs(pi[k]), &e);
+                            pr[k] = ldexp(pr[k], -e);
+                            pi[k] = ldexp(pi[k], -e);
+                            ex2[k] += e;
+                        }
+                }
+                for (int k = 0; k < RMF_PB; ++k) {
+                    const int b = b0 + RMF_WAVES * k;
+                    if (b >= n) break;
+                    if (ai >= b) continue;
+                    const double sb = spin(mk, b), ss = sa * sb;
+                    const double2 Rb = a.R[sidx * n + b];
+                    const double2 Rab = cmul(cmul(Ra, Rb), make_double2(ldexp(pr[k], ex2[k]), ldexp(pi[k], ex2[k])));
+                    v[3] += 2.0 * Rab.x;
+                    v[4] += -2.0 * ss * Rab.x;
+                    v[6] += (sa + sb) * Rab.y;
+                }
             }
         }
-        for (int q = 0; q < 9; ++q) v[q] = wave_sum(v[q]);
-        acc[0] += v[0] / N;
-        acc[1] += v[1] / N;
-        acc[2] += v[2] / N;
-        acc[3] += (N + v[3]) / (N * N);
-        acc[4] += (N + v[4]) / (N * N);
-        acc[5] += (N + v[5]) / (N * N);
-        acc[6] += v[6] / (N * N);
-        acc[7] += v[7] / (N * N);
-        acc[8] += v[8] / (N * N);
+        for (int q = 0; q < 9; ++q) acc[q] += v[q];
     }
+    for (int q = 0; q < 9; ++q) acc[q] = wave_sum(acc[q]);
     if (lane == 0)
         for (int q = 0; q < 9; ++q) part[w][q] = acc[q];
     __syncthreads();
-    if (threadIdx.x < 9) {
-        double s = 0.0;
-        for (int ww = 0; ww < RMOM_WAVES; ++ww) s += part[ww][threadIdx.x];
-        a.mom_part[((size_t)t * a.mom_blocks + blockIdx.x) * 9 + threadIdx.x] = s;
+    if (tid < 9) {
+        double v = 0.0;
+        for (int ww = 0; ww < RMF_WAVES; ++ww) v += part[ww][tid];
+        int cnt = 0;   // samples this workgroup took
+        for (int s = blockIdx.x; s < a.ns; s += gridDim.x) ++cnt;
+        double r;
+        if (tid < 3) r = v / N;
+        else if (tid < 6) r = (N * cnt + v) / (N * N);
+        else r = v / (N * N);
+        a.mom_part[((size_t)t * a.mom_blocks + blockIdx.x) * 9 + tid] = r;
     }
 }
 

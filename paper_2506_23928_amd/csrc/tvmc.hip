@@ -68,7 +68,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t J, jk, js, jr, pa, pb, pidx, theta, theta_eval, d0, d1, eta_re, eta_im, epair, chains, samples, sbits, R, eloc, acc, dw,
-        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, mom, hist, ens, flags, lognorm, qhist, snrV, snrRho, snrW, snrEig, snrPart, snrRot, snrSweeps, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
+        bmean, G, gbar, obar, obarc, w_re, w_im, cT, sT, cW, sW, tt, D, S, linv, mom_part, momtab, mom, hist, ens, flags, lognorm, qhist, snrV, snrRho, snrW, snrEig, snrPart, snrRot, snrSweeps, arP, arG, arM, arV, arW1Tb, arW2Tb, arh, arda,
         arg, arlogq, arlogqb, arloss, aracc, rbmP, ssrow, ssrhs, ssu, ssbar, dstep, total;
 };
 
@@ -157,6 +157,7 @@ Layout layout(int kind, int n, int nh, int m, int nch, int T, int ns, int nc, in
     L.ssu = take(ss ? sizeof(double2) * tt * ns : 0);
     L.ssbar = take(ss ? sizeof(double) * tt : 0);
     L.mom_part = take(sizeof(double) * tt * mom_blocks_for(ns) * 9);
+    L.momtab = take(rbm && (nw > 1 || (size_t)n * nh > 64 * 64) ? sizeof(double2) * tt * mom_blocks_for(ns) * 2 * n * nh : 0);
     L.mom = take(sizeof(double) * tt * 9);
     L.hist = take(sizeof(double) * (size_t)(nobs > 0 ? nobs : 1) * tt * 9);
     L.ens = take(sizeof(double) * 16 * (tt + 1));
@@ -801,8 +802,8 @@ tvmc_status run_moments(tvmc_ctx *c, int slot) {
         hipLaunchKernelGGL(k_moments_rbm_f, dim3(d.mom_blocks, T), dim3(64 * RMF_WAVES), 0, c->stream, d);
         LAUNCHCHECK(c, "k_moments_rbm_f");
     } else if (d.kind == TVMC_ANSATZ_RBM) {
-        BY_WORDS(d, hipLaunchKernelGGL((k_moments_rbm<W_>), dim3(d.mom_blocks, T), dim3(64 * RMOM_WAVES), 0, c->stream, d));
-        LAUNCHCHECK(c, "k_moments_rbm");
+        BY_WORDS(d, hipLaunchKernelGGL((k_moments_rbm_g<W_>), dim3(d.mom_blocks, T), dim3(64 * RMF_WAVES), 0, c->stream, d));
+        LAUNCHCHECK(c, "k_moments_rbm_g");
     } else {
         hipLaunchKernelGGL(k_prepare_pairs, dim3((nn + 255) / 256, T), dim3(256), 0, c->stream, d);
         LAUNCHCHECK(c, "k_prepare_pairs");
@@ -960,6 +961,7 @@ tvmc_status init_impl(const tvmc_problem *pbs, int32_t np, const tvmc_ansatz *a,
     d.S = (double *)(base + L.S);
     d.linv = (double *)(base + L.linv);
     d.mom_part = (double *)(base + L.mom_part);
+    d.momtab = (double2 *)(base + L.momtab);
     d.mom = (double *)(base + L.mom);
     d.hist = (double *)(base + L.hist);
     d.ens = (double *)(base + L.ens);

@@ -240,3 +240,25 @@ def test_rbm_bf16_full_size_launch(tv, orc):
         x = ctx.get(T.Q_DELTA0, t)
         D = ctx.get(T.Q_D, t)
         assert np.abs(_hermitian(S) @ x - D).max() < 1e-9 * np.abs(D).max()
+
+
+@pytest.mark.parametrize("n,nh,ns,nc", [(20, 256, 256, 8), (70, 3, 256, 8), (100, 48, 128, 8)])
+def test_rbm_moments_with_global_tables(tv, orc, n, nh, ns, nc):
+    """The moment estimators where the factored two-flip tables (2 N N' complex) leave LDS for the
+    workspace: N N' > 4096 (N = 20, N' = 256) and two configuration words (N = 70 and 100):
+    the moments of the first evaluation's samples against the oracle's (1e-10)."""
+    from paper_2506_23928_amd import tvmc as T
+    J, hx, jumps = wl.random_problem(n, seed=n + 3)
+    m = orc.n_params(1, n, nh)
+    th0 = wl.random_theta(m, 0.02, seed=nh + 1)
+    seed, dt, eps = 5, 0.01, 1e-4
+    cfg = tv.make_config(1, ns, nc, dt, eps, 2, 1, 3, seed=seed)
+    ctx = tv.Context(tv.Problem(J, hx, jumps), cfg, kind=tv.tvmc.RBM, n_hidden=nh, theta0=th0)
+    ctx.sample()
+    ctx.observables()
+    ctx.synchronize()
+    cfg_o = orc.Config(n_samples=ns, n_chains=nc, burn_sweeps=2, init_sweeps=3, dt=dt, diag_shift=eps, seed=seed)
+    r = orc.evaluate(orc.Problem(J, hx, jumps), 1, nh, cfg_o, th0, orc.init_chains(seed, 0, n, nc), traj=0,
+                     first=True, dw=orc.draw_dw(seed, 0, 0, len(jumps), dt), want_solve=0, want_moments=True)
+    assert np.array_equal(tv.unpack_samples(ctx.get(T.Q_SAMPLES, 0), n), r["samples"])
+    assert np.abs(ctx.get(T.Q_MOMENTS, 0) - r["obs"]).max() < 1e-10, (ctx.get(T.Q_MOMENTS, 0), r["obs"])
