@@ -12,12 +12,8 @@
 
 namespace tvmc {
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
-    u += 0x7fffu + ((u >> 16) & 1u);                                      // round to nearest even
-    return (uint16_t)(u >> 16);
-}
+// float -> bfloat16, round to nearest even (the hardware conversion, v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 __device__ __forceinline__ int ar_degree(int k, int n) { return 1 + (n > 1 ? k % (n - 1) : 0); }

@@ -19,9 +19,18 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
+// hi = bf16(float(x)), lo = bf16(float(x - hi)), each step rounded to nearest even.  The float is
+// passed through an empty asm so that the compiler keeps the two hardware conversions
+// (v_cvt_f32_f64, v_cvt_pk_bf16_f32) instead of fusing them into one longer double -> bfloat16
+// sequence.
+__device__ __forceinline__ uint16_t f64_to_bf(double x) {
+    float f = (float)x;
+    asm volatile("" : "+v"(f));
+    return f2bf(f);
+}
 __device__ __forceinline__ void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
-    hi = f2bf((float)x);
-    lo = f2bf((float)(x - (double)bf2f(hi)));
+    hi = f64_to_bf(x);
+    lo = f64_to_bf(x - (double)bf2f(hi));
 }
 
 // P holds the four BF16 planes 0 Re hi, 1 Re lo, 2 Im hi, 3 Im lo in the order the S-build
