@@ -367,125 +367,266 @@ __device__ __forceinline__ double2 zmulc(double2 a, double2 b) {   // a conj(b)
     return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
-// One workgroup of ZD threads per trajectory: 16 lanes per row of the block while factoring,
-// 16 lanes per column of the inverse.
+// One workgroup of ZD threads per trajectory factors the 64 x 64 diagonal block in blocks of
+// ZDB = 16 columns (right-looking): one wavefront factors a 16 x 16 diagonal block in registers,
+// the rows below it solve for their part of the block column (one lane per row, forward
+// substitution), and the workgroup applies the trailing update.  Then the inverse: the four
+// diagonal blocks at once (a wavefront each), the off-diagonal blocks by block rows,
+// Linv_ij = -Linv_ii sum_{j <= k < i} L_ik Linv_kj.  About twenty workgroup barriers in all,
+// against one per column for a column-by-column factor; the serial chain is the 16 steps of
+// each diagonal block and the substitution below it.
 constexpr int ZD = 1024;
+constexpr int ZDB = 16;
+
+__device__ __forceinline__ double2 zshfl(double2 v, int src) {
+    return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+// v from lane SEL of each quad of lanes, to all four
+template <int SEL>
+__device__ __forceinline__ double2 zquad_bcast_t(double2 v) {
+    return make_double2(dpp_d<SEL * 0x55, 0xF>(v.x, v.x), dpp_d<SEL * 0x55, 0xF>(v.y, v.y));
+}
+__device__ __forceinline__ double2 zquad_bcast(double2 v, int sel) {
+    switch (sel) {
+    case 0: return zquad_bcast_t<0>(v);
+    case 1: return zquad_bcast_t<1>(v);
+    case 2: return zquad_bcast_t<2>(v);
+    default: return zquad_bcast_t<3>(v);
+    }
+}
+
+// The 16 x 16 diagonal block at (o, o) of Cs (already updated by the blocks to its left),
+// factored by one wavefront: lane (r, q) = (lane / 4, lane % 4) holds columns q, q + 4, q + 8,
+// q + 12 of row r.  Step c scales column c by 1 / sqrt(C_cc) (the hardware's reciprocal square
+// root and two Newton steps) and subtracts L_rc conj(L_kc) from the columns k > c: L_rc comes
+// from the lane's own quad, L_kc from lane (k, c % 4).  Column c + 1, which holds the next
+// pivot, is updated first from the one value L_{c+1,c} it needs, so the next step's chain does
+// not wait for the moves of the other columns.  L goes over the block's lower triangle in Cs,
+// the reciprocals of its diagonal into dinv.  Returns true on lanes that saw a pivot that is not
+// positive.
+__device__ __forceinline__ bool zdiag_block16(double2 *Cs, double *dinv, int o, int lane) {
+    asm volatile("" : "+v"(lane));   // keeps the lane masks of the unrolled steps inside the caller's loop
+    const int r = lane >> 2, q = lane & 3;
+    double2 a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = q + 4 * s;
+        a[s] = c <= r ? Cs[(o + r) * CSP + o + c] : make_double2(0.0, 0.0);
+    }
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < ZDB; ++c) {
+        const double piv = readlane_d(a[c >> 2].x, c * 4 + (c & 3));
+        bad |= !(piv > 0.0);
+        double y = __builtin_amdgcn_rsq(piv);
+        y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
+        y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
+        const double d = piv * y;
+        if (lane == 0) dinv[o + c] = y;
+        const double2 lc = make_double2(a[c >> 2].x * y, a[c >> 2].y * y);   // L_rc on lanes q == c % 4
+        const double2 lrc = zquad_bcast(lc, c & 3);
+        if (c + 1 < ZDB) {
+            const int l1 = 4 * (c + 1) + (c & 3);
+            const double2 lk = make_double2(readlane_d(lc.x, l1), readlane_d(lc.y, l1));   // L_{c+1,c}
+            if (q == ((c + 1) & 3) && r > c) {
+                a[(c + 1) >> 2].x -= lrc.x * lk.x + lrc.y * lk.y;
+                a[(c + 1) >> 2].y -= lrc.y * lk.x - lrc.x * lk.y;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {   // C_rk -= L_rc conj(L_kc), c + 1 < k <= r
+            const int k = q + 4 * s;
+            const double2 lkc = zshfl(lc, k * 4 + (c & 3));
+            if (k > c + 1 && k <= r) {
+                a[s].x -= lrc.x * lkc.x + lrc.y * lkc.y;
+                a[s].y -= lrc.y * lkc.x - lrc.x * lkc.y;
+            }
+        }
+        if (q == (c & 3)) a[c >> 2] = r > c ? lc : (r == c ? make_double2(d, 0.0) : make_double2(0.0, 0.0));
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = q + 4 * s;
+        if (c <= r) Cs[(o + r) * CSP + o + c] = a[s];
+    }
+    return bad;
+}
+
+// L^-1 of the factored 16 x 16 diagonal block at (o, o) into the same block of Ls (zeros above
+// the diagonal), by one wavefront: lane c < 16 solves L x = e_c down the rows (x_k = 0 above row
+// c), x in registers.
+__device__ __forceinline__ void zdiag_inv16(const double2 *Cs, double2 *Ls, const double *dinv, int o, int lane) {
+    asm volatile("" : "+v"(lane));
+    if (lane < ZDB) {
+        const int c = lane;
+        double2 x[ZDB];
+#pragma unroll
+        for (int rr = 0; rr < ZDB; ++rr) {
+            double sr = rr == c ? 1.0 : 0.0, si = 0.0;
+#pragma unroll
+            for (int k = 0; k < rr; ++k) {
+                const double2 l = Cs[(o + rr) * CSP + o + k];
+                sr -= l.x * x[k].x - l.y * x[k].y;
+                si -= l.x * x[k].y + l.y * x[k].x;
+            }
+            const double il = dinv[o + rr];
+            x[rr] = make_double2(sr * il, si * il);
+            Ls[(o + rr) * CSP + o + c] = x[rr];
+        }
+    }
+}
 
 __global__ __launch_bounds__(ZD) void k_zmw_diag(ZCholArgs a, int j0, int p) {
     __shared__ double2 Cs[CN * CSP];
     __shared__ double2 Ls[CN * CSP];
-    __shared__ double2 ys[CN];
+    __shared__ double2 Ws[(CN / ZDB - 1) * ZDB * ZDB];
+    __shared__ double2 ys[CN], zs[CN];
+    __shared__ double dinv[CN];
     __shared__ int bad;
     const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int M = a.m;
     const int jb = (M - j0) < CN ? (M - j0) : CN;
+    const int nblk = (jb + ZDB - 1) / ZDB;
     double2 *A = a.A + (size_t)t * M * M;
     double2 *z = a.x + (size_t)t * M;
     if (tid == 0) bad = 0;
+    // rows and columns past jb (the last, ragged panel) are padded with the identity
     for (int e = tid; e < CN * CN; e += ZD) {
         const int r = e / CN, c = e % CN;
-        Cs[r * CSP + c] = (r < jb && c <= r) ? A[(size_t)(j0 + r) * M + j0 + c] : make_double2(0.0, 0.0);
+        Cs[r * CSP + c] = (r < jb && c <= r) ? A[(size_t)(j0 + r) * M + j0 + c]
+                        : make_double2(r == c ? 1.0 : 0.0, 0.0);
+        if (c / ZDB > r / ZDB) Ls[r * CSP + c] = make_double2(0.0, 0.0);
     }
     __syncthreads();
-    // right-looking factor in LDS: thread (row fr, phase fs) updates columns c+1+fs, c+17+fs, ...
-    // of its row; column c is read unscaled in step c and scaled after the barrier.  Each
-    // thread loads its (at most 4) operand pairs before it stores any of them.
-    {
-        const int fr = tid >> 4, fs = tid & 15;
-        for (int c = 0; c < jb; ++c) {
-            const double piv = Cs[c * CSP + c].x;
-            if (tid == 0 && !(piv > 0.0)) bad = 1;
-            const double d = sqrt(piv), inv = 1.0 / d;
-            double2 lrc = make_double2(0.0, 0.0);
-            if (fr > c && fr < jb) {
-                const double2 crc = Cs[fr * CSP + c];
-                lrc = make_double2(crc.x * inv, crc.y * inv);
-                double2 ck[CN / 16], cr[CN / 16];
-                for (int q = 0; q < CN / 16; ++q) {
-                    const int k = c + 1 + fs + 16 * q;
-                    if (k <= fr) {
-                        ck[q] = Cs[k * CSP + c];
-                        cr[q] = Cs[fr * CSP + k];
-                    }
+    for (int b = 0; b < nblk; ++b) {
+        const int o = b * ZDB;
+        if (wave == 0 && zdiag_block16(Cs, dinv, o, lane)) bad = 1;
+        __syncthreads();
+        const int n = CN - o - ZDB;   // rows below the block (padding included)
+        if (b + 1 == nblk || n <= 0) break;
+        // L[r, block] L_bb^H = C[r, block]: forward substitution along the row, one lane per row
+        for (int e = tid; e < n; e += ZD) {
+            const int r = o + ZDB + e;
+            double2 x[ZDB];
+#pragma unroll
+            for (int c = 0; c < ZDB; ++c) {
+                double2 v = Cs[r * CSP + o + c];
+#pragma unroll
+                for (int k = 0; k < c; ++k) {   // v -= x_k conj(L_ck)
+                    const double2 l = Cs[(o + c) * CSP + o + k];
+                    v.x -= x[k].x * l.x + x[k].y * l.y;
+                    v.y -= x[k].y * l.x - x[k].x * l.y;
                 }
-                for (int q = 0; q < CN / 16; ++q) {   // C_rk -= L_rc conj(L_kc)
-                    const int k = c + 1 + fs + 16 * q;
-                    if (k <= fr) {
-                        const double2 pr = zmulc(lrc, make_double2(ck[q].x * inv, ck[q].y * inv));
-                        Cs[fr * CSP + k] = make_double2(cr[q].x - pr.x, cr[q].y - pr.y);
-                    }
-                }
+                const double il = dinv[o + c];
+                x[c] = make_double2(v.x * il, v.y * il);
             }
-            __syncthreads();
-            if (fs == 0 && fr > c && fr < jb) Cs[fr * CSP + c] = lrc;
-            if (tid == 0) Cs[c * CSP + c] = make_double2(d, 0.0);
+#pragma unroll
+            for (int c = 0; c < ZDB; ++c) Cs[r * CSP + o + c] = x[c];
+        }
+        __syncthreads();
+        // trailing update C[r, k] -= L[r, block] L[k, block]^H, o + 16 <= k <= r
+        for (int e = tid; e < n * n; e += ZD) {
+            const int rr = e / n, kk = e % n;
+            if (kk > rr) continue;
+            const int r = o + ZDB + rr, k = o + ZDB + kk;
+            double sr = 0.0, si = 0.0;
+#pragma unroll 4
+            for (int m = 0; m < ZDB; ++m) {
+                const double2 u = Cs[r * CSP + o + m], v = Cs[k * CSP + o + m];
+                sr += u.x * v.x + u.y * v.y;
+                si += u.y * v.x - u.x * v.y;
+            }
+            const double2 cv = Cs[r * CSP + k];
+            Cs[r * CSP + k] = make_double2(cv.x - sr, cv.y - si);
         }
         __syncthreads();
     }
+    if (tid == 0 && bad) a.flags[t] = 1;
     for (int e = tid; e < jb * jb; e += ZD) {
         const int r = e / jb, c = e % jb;
         if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
     }
-    // Linv: Linv_cc = 1 / L_cc, Linv_rc = -(sum_{c <= k < r} L_rk Linv_kc) / L_rr; wave w owns
-    // columns 4w..4w+3 (rows of one column are written and read back by the same wave, in order)
-    {
-        const int c = wave * 4 + (lane >> 4), fs = lane & 15;
-        for (int r = fs; r < CN; r += 16) Ls[r * CSP + c] = make_double2(0.0, 0.0);
-        if (c < jb) {
-            if (fs == 0) Ls[c * CSP + c] = make_double2(1.0 / Cs[c * CSP + c].x, 0.0);
-            for (int r = c + 1; r < jb; ++r) {
-                double sr = 0.0, si = 0.0;
-                for (int k = c + fs; k < r; k += 16) {
-                    const double2 pr = zmul(Cs[r * CSP + k], Ls[k * CSP + c]);
-                    sr += pr.x;
-                    si += pr.y;
-                }
-                for (int o = 1; o < 16; o <<= 1) {
-                    sr += __shfl_xor(sr, o, 64);
-                    si += __shfl_xor(si, o, 64);
-                }
-                const double lrr = Cs[r * CSP + r].x;
-                if (fs == 0) Ls[r * CSP + c] = make_double2(-sr / lrr, -si / lrr);
+    // the diagonal blocks of Linv, one wavefront each, then the off-diagonal blocks by block rows
+    if (wave < nblk) zdiag_inv16(Cs, Ls, dinv, wave * ZDB, lane);
+    __syncthreads();
+    for (int i = 1; i < nblk; ++i) {
+        for (int e = tid; e < i * ZDB * ZDB; e += ZD) {   // W_ij = sum_{j <= k < i} L_ik Linv_kj
+            const int j = e / (ZDB * ZDB), c = (e / ZDB) % ZDB, r = e % ZDB;
+            double sr = 0.0, si = 0.0;
+#pragma unroll 8
+            for (int m = j * ZDB; m < i * ZDB; ++m) {
+                const double2 l = Cs[(i * ZDB + r) * CSP + m], v = Ls[m * CSP + j * ZDB + c];
+                sr += l.x * v.x - l.y * v.y;
+                si += l.x * v.y + l.y * v.x;
             }
+            Ws[(j * ZDB + r) * ZDB + c] = make_double2(sr, si);
         }
+        __syncthreads();
+        for (int e = tid; e < i * ZDB * ZDB; e += ZD) {   // Linv_ij = -Linv_ii W_ij
+            const int j = e / (ZDB * ZDB), c = (e / ZDB) % ZDB, r = e % ZDB;
+            double sr = 0.0, si = 0.0;
+#pragma unroll 4
+            for (int m = 0; m < ZDB; ++m) {
+                const double2 l = Ls[(i * ZDB + r) * CSP + i * ZDB + m], w = Ws[(j * ZDB + m) * ZDB + c];
+                sr += l.x * w.x - l.y * w.y;
+                si += l.x * w.y + l.y * w.x;
+            }
+            Ls[(i * ZDB + r) * CSP + j * ZDB + c] = make_double2(-sr, -si);
+        }
+        __syncthreads();
     }
+    if (tid < jb) zs[tid] = z[j0 + tid];
     __syncthreads();
     if (tid < jb) {   // y = Linv z_panel
         double sr = 0.0, si = 0.0;
+#pragma unroll 8
         for (int k = 0; k <= tid; ++k) {
-            const double2 pr = zmul(Ls[tid * CSP + k], z[j0 + k]);
+            const double2 pr = zmul(Ls[tid * CSP + k], zs[k]);
             sr += pr.x;
             si += pr.y;
         }
         ys[tid] = make_double2(sr, si);
     }
     double2 *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
-    for (int e = tid; e < CN * CN; e += ZD) lv[e] = Ls[(e / CN) * CSP + e % CN];
-    __syncthreads();
+    for (int e = tid; e < CN * CN; e += ZD) {
+        const int r = e / CN, c = e % CN;
+        lv[e] = (r < jb && c < jb) ? Ls[r * CSP + c] : make_double2(0.0, 0.0);
+    }
     // the next panel's rows (the first CN rows below the block): L[r, panel] = C[r, panel]
     // Linv^H over C and z[r] -= L[r, panel] y; the update kernel of the next panel does the
-    // TRSM of the rows below those.  Thread (fr, fs): row fr, columns fs, fs + 16, ...
+    // TRSM of the rows below those.  Thread (fr, fs): row fr, columns fs, fs + 16, fs + 32, fs + 48
+    // (Linv is zero above its diagonal, so column block q needs the k blocks up to q).
     const int nr0 = j0 + jb, nrb = (M - nr0) < CN ? (M - nr0) : CN;
     if (nrb > 0) {
         for (int e = tid; e < nrb * CN; e += ZD) {
             const int r = e / CN, c = e % CN;
-            Cs[r * CSP + c] = c < jb ? A[(size_t)(nr0 + r) * M + j0 + c] : make_double2(0.0, 0.0);
+            Cs[r * CSP + c] = A[(size_t)(nr0 + r) * M + j0 + c];
         }
         __syncthreads();
         const int fr = tid >> 4, fs = tid & 15;
         double sr = 0.0, si = 0.0;
         if (fr < nrb) {
-            for (int q = 0; q < CN / 16; ++q) {
-                const int c = fs + 16 * q;
-                if (c >= jb) continue;
-                double xr = 0.0, xi = 0.0;   // sum_{k <= c} C_rk conj(Linv_ck)
-                for (int k = 0; k <= c; ++k) {
-                    const double2 pr = zmulc(Cs[fr * CSP + k], Ls[c * CSP + k]);
-                    xr += pr.x;
-                    xi += pr.y;
+            double2 x[CN / ZDB];
+#pragma unroll
+            for (int q = 0; q < CN / ZDB; ++q) x[q] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int kb = 0; kb < CN / ZDB; ++kb)
+#pragma unroll 4
+                for (int k = kb * ZDB; k < kb * ZDB + ZDB; ++k) {
+                    const double2 cv = Cs[fr * CSP + k];
+#pragma unroll
+                    for (int q = kb; q < CN / ZDB; ++q) {   // sum_k C_rk conj(Linv_ck)
+                        const double2 l = Ls[(fs + ZDB * q) * CSP + k];
+                        x[q].x += cv.x * l.x + cv.y * l.y;
+                        x[q].y += cv.y * l.x - cv.x * l.y;
+                    }
                 }
-                A[(size_t)(nr0 + fr) * M + j0 + c] = make_double2(xr, xi);
-                const double2 xy = zmul(make_double2(xr, xi), ys[c]);
+#pragma unroll
+            for (int q = 0; q < CN / ZDB; ++q) {
+                const int c = fs + ZDB * q;
+                A[(size_t)(nr0 + fr) * M + j0 + c] = x[q];
+                const double2 xy = zmul(x[q], ys[c]);
                 sr += xy.x;
                 si += xy.y;
             }
@@ -499,8 +640,8 @@ __global__ __launch_bounds__(ZD) void k_zmw_diag(ZCholArgs a, int j0, int p) {
             z[nr0 + fr] = make_double2(zr.x - sr, zr.y - si);
         }
     }
+    __syncthreads();
     if (tid < jb) z[j0 + tid] = ys[tid];
-    if (tid == 0 && bad) a.flags[t] = 1;
 }
 
 // L^H x = y by row panels, last panel first, one launch per panel p (then a closing launch
