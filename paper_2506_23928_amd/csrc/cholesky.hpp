@@ -201,8 +201,9 @@ __global__ __launch_bounds__(CT1) void k_chol_solve(CholArgs a) {
             for (int ks = 0; ks < CN / 4; ++ks) {
                 double fb[4];
                 const double fa = Cs[(wave * 16 + li) * CSP + ks * 4 + lk];
-                for (int v = 0; v < 4; ++v) fb[v] = Ls[(v * 16 + li) * CSP + ks * 4 + lk];
-                for (int v = 0; v < 4; ++v) x[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb[v], x[v], 0, 0, 0);
+                for (int v = 0; v < 4; ++v) fb[v] = v >= (ks >> 2) ? Ls[(v * 16 + li) * CSP + ks * 4 + lk] : 0.0;
+                for (int v = 0; v < 4; ++v)   // Linv^T is zero in the k-steps past 4 v + 3
+                    if (v >= (ks >> 2)) x[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb[v], x[v], 0, 0, 0);
             }
             __syncthreads();
             for (int v = 0; v < 4; ++v)

@@ -141,8 +141,9 @@ __global__ __launch_bounds__(CUT) void k_cmw_update_lds(CholArgs a, int j0, int 
             for (int v = 0; v < 4; ++v) x[v] = (v4d){0.0, 0.0, 0.0, 0.0};
             for (int ks = 0; ks < CN / 4; ++ks) {
                 double fb[4];
-                for (int v = 0; v < 4; ++v) fb[v] = Ls[(v * 16 + li) * CSP + ks * 4 + lk];
-                for (int v = 0; v < 4; ++v) x[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[ks], fb[v], x[v], 0, 0, 0);
+                for (int v = 0; v < 4; ++v) fb[v] = v >= (ks >> 2) ? Ls[(v * 16 + li) * CSP + ks * 4 + lk] : 0.0;
+                for (int v = 0; v < 4; ++v)   // Linv^T is zero in the k-steps past 4 v + 3
+                    if (v >= (ks >> 2)) x[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[ks], fb[v], x[v], 0, 0, 0);
             }
             for (int r = 0; r < 4; ++r) {
                 const int row = wrow + lk + 4 * r;
@@ -325,8 +326,9 @@ __global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p, int
             double fb[4];
             const int row = nr0 + wave * 16 + li, col = ks * 4 + lk;
             const double fa = (row < M && col < jb) ? A[(size_t)row * M + j0 + col] : 0.0;
-            for (int v = 0; v < 4; ++v) fb[v] = Ls[(v * 16 + li) * CSP + ks * 4 + lk];
-            for (int v = 0; v < 4; ++v) x[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb[v], x[v], 0, 0, 0);
+            for (int v = 0; v < 4; ++v) fb[v] = v >= (ks >> 2) ? Ls[(v * 16 + li) * CSP + ks * 4 + lk] : 0.0;
+            for (int v = 0; v < 4; ++v)   // Linv^T is zero in the k-steps past 4 v + 3
+                    if (v >= (ks >> 2)) x[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb[v], x[v], 0, 0, 0);
         }
         __syncthreads();   // every lane has read its C before any lane overwrites it
         for (int r = 0; r < 4; ++r) {
@@ -382,9 +384,10 @@ __global__ __launch_bounds__(256) void k_cmw_trsm(CholArgs a, int j0, int p) {
             const int row = r0 + wave * 32 + u * 16 + li, col = ks * 4 + lk;
             fa[u] = (row < M && col < jb) ? A[(size_t)row * M + j0 + col] : 0.0;
         }
-        for (int v = 0; v < 4; ++v) fb[v] = Ls[(v * 16 + li) * CSP + ks * 4 + lk];
+        for (int v = 0; v < 4; ++v) fb[v] = v >= (ks >> 2) ? Ls[(v * 16 + li) * CSP + ks * 4 + lk] : 0.0;
         for (int u = 0; u < 2; ++u)
-            for (int v = 0; v < 4; ++v) x[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[v], x[u][v], 0, 0, 0);
+            for (int v = 0; v < 4; ++v)   // Linv^T is zero in the k-steps past 4 v + 3
+                if (v >= (ks >> 2)) x[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[v], x[u][v], 0, 0, 0);
     }
     // every lane has finished reading C before any lane overwrites it
     __syncthreads();

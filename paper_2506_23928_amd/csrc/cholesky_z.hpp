@@ -84,14 +84,17 @@ __global__ __launch_bounds__(ZT) void k_zmw_update(ZCholArgs a, int j0, int pp) 
                 xr[v] = (v4d){0.0, 0.0, 0.0, 0.0};
                 xi[v] = (v4d){0.0, 0.0, 0.0, 0.0};
             }
+            // Linv is lower triangular: column block v of Linv^H is zero in the k-steps ks >= 4 v + 4
             for (int ks = 0; ks < CN / 4; ++ks) {
                 double fbr[4], fbi[4];
                 for (int v = 0; v < 4; ++v) {
+                    if (v < (ks >> 2)) continue;
                     fbr[v] = Lr[(v * 16 + li) * CSP + ks * 4 + lk];
                     fbi[v] = Li[(v * 16 + li) * CSP + ks * 4 + lk];
                 }
                 const double fcr = cf[ks].x, fci = cf[ks].y;
                 for (int v = 0; v < 4; ++v) {
+                    if (v < (ks >> 2)) continue;
                     xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr, fbr[v], xr[v], 0, 0, 0);
                     xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbi[v], xr[v], 0, 0, 0);
                     xi[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbr[v], xi[v], 0, 0, 0);
@@ -239,14 +242,17 @@ __global__ __launch_bounds__(ZT) void k_zmw_update_lds(ZCholArgs a, int j0, int 
                 xr[v] = (v4d){0.0, 0.0, 0.0, 0.0};
                 xi[v] = (v4d){0.0, 0.0, 0.0, 0.0};
             }
+            // Linv is lower triangular: column block v of Linv^H is zero in the k-steps ks >= 4 v + 4
             for (int ks = 0; ks < CN / 4; ++ks) {
                 double fbr[4], fbi[4];
                 for (int v = 0; v < 4; ++v) {
+                    if (v < (ks >> 2)) continue;
                     fbr[v] = Lr[(v * 16 + li) * CSP + ks * 4 + lk];
                     fbi[v] = Li[(v * 16 + li) * CSP + ks * 4 + lk];
                 }
                 const double fcr = cf[ks].x, fci = cf[ks].y;
                 for (int v = 0; v < 4; ++v) {
+                    if (v < (ks >> 2)) continue;
                     xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fcr, fbr[v], xr[v], 0, 0, 0);
                     xr[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbi[v], xr[v], 0, 0, 0);
                     xi[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(fci, fbr[v], xi[v], 0, 0, 0);
