@@ -266,12 +266,10 @@ __global__ __launch_bounds__(CT1) void k_chol_solve(CholArgs a) {
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        int nf = bad;
-        for (int i = 0; i < M && !nf; ++i)
-            if (!isfinite(z[i].x) || !isfinite(z[i].y)) nf = 1;
-        if (nf) a.flags[t] = 1;
-    }
+    int nf = 0;   // a non-finite entry of the solution
+    for (int i = tid; i < M; i += CT1) nf |= !isfinite(z[i].x) || !isfinite(z[i].y);
+    nf = __syncthreads_or(nf);
+    if (tid == 0 && (nf || bad)) a.flags[t] = 1;
 }
 
 }  // namespace tvmc

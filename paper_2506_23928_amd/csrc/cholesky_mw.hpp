@@ -456,12 +456,10 @@ __global__ __launch_bounds__(256) void k_cmw_backward(CholArgs a) {
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        int nf = 0;
-        for (int i = 0; i < M && !nf; ++i)
-            if (!isfinite(z[i].x) || !isfinite(z[i].y)) nf = 1;
-        if (nf) a.flags[t] = 1;
-    }
+    int nf = 0;   // a non-finite entry of the solution
+    for (int i = tid; i < M; i += 256) nf |= !isfinite(z[i].x) || !isfinite(z[i].y);
+    nf = __syncthreads_or(nf);
+    if (tid == 0 && nf) a.flags[t] = 1;
 }
 
 }  // namespace tvmc

@@ -652,31 +652,40 @@ __global__ __launch_bounds__(ZD) void k_zmw_diag(ZCholArgs a, int j0, int p) {
 
 // L^H x = y by row panels, last panel first, one launch per panel p (then a closing launch
 // p = -1).  w starts as y (in x) and, once every panel below p has been applied, w_p = y_p -
-// sum_{r below} conj(L_rp) x_r, so x_p = Linv_p^H w_p.  Launch p: every workgroup forms x_p in
-// LDS and subtracts conj(L[rows of p][c]) x_p from w_c for its chunk of ZB_COLS columns c < j0
-// (one column per thread, the panel's rows read row by row, coalesced); workgroup 0 also
-// writes x_{p+1} over w_{p+1}, which no workgroup of launch p reads.  The closing launch
-// writes x_0 and flags non-finite solutions.
+// sum_{r below} conj(L_rp) x_r, so x_p = Linv_p^H w_p.  Launch p: every workgroup forms x_p
+// and subtracts conj(L[rows of p][c]) x_p from w_c for its chunk of ZB_COLS columns c < j0 (one
+// column per thread, the panel's rows read row by row, coalesced); workgroup 0 also writes
+// x_{p+1} over w_{p+1}, which no workgroup of launch p reads.  The closing launch writes x_0
+// and flags non-finite solutions.
 constexpr int ZB_COLS = 256;
-// Called by the whole workgroup: the block inverse is staged in LDS by all threads first.
-__device__ __forceinline__ void zbwd_x(const double2 *__restrict__ lv, double2 *lvs, const double2 *ws, double2 *xs, int jb,
-                                       int tid) {
-    for (int e = tid; e < jb * CN; e += ZB_COLS) lvs[e] = lv[e];
+// x = Linv^H w for one panel, by the whole workgroup: thread (c, g) = (tid % 64, tid / 64) sums
+// conj(Linv_kc) w_k over the rows k = g, g + 4, ... of the stored inverse (zero above its
+// diagonal; a row is 64 contiguous entries, so each step is one coalesced read per wavefront),
+// and the four partial sums meet in LDS.  w in LDS (ws); x into xs.
+__device__ __forceinline__ void zbwd_x(const double2 *__restrict__ lv, const double2 *ws, double2 *part, double2 *xs,
+                                       int jb, int tid) {
+    const int c = tid & (CN - 1), g = tid >> 6;
+    double xr = 0.0, xi = 0.0;
+#pragma unroll 4
+    for (int k = g; k < jb; k += ZB_COLS / CN) {
+        const double2 l = lv[k * CN + c], w = ws[k];
+        xr += l.x * w.x + l.y * w.y;
+        xi += l.x * w.y - l.y * w.x;
+    }
+    part[tid] = make_double2(xr, xi);
     __syncthreads();
-    if (tid < jb) {   // x_c = sum_{k >= c} conj(Linv_kc) w_k
-        double xr = 0.0, xi = 0.0;
-        for (int k = tid; k < jb; ++k) {
-            const double2 l = lvs[k * CN + tid], w = ws[k];
-            xr += l.x * w.x + l.y * w.y;
-            xi += l.x * w.y - l.y * w.x;
+    if (tid < jb) {
+        double2 s = part[tid];
+        for (int q = 1; q < ZB_COLS / CN; ++q) {
+            s.x += part[tid + q * CN].x;
+            s.y += part[tid + q * CN].y;
         }
-        xs[tid] = make_double2(xr, xi);
+        xs[tid] = s;
     }
 }
 
 __global__ __launch_bounds__(ZB_COLS) void k_zmw_bwd(ZCholArgs a, int p) {
-    __shared__ double2 ws[CN], xs[CN];
-    __shared__ double2 lvs[CN * CN];
+    __shared__ double2 ws[CN], xs[CN], part[ZB_COLS];
     const int t = blockIdx.y, tid = threadIdx.x;
     const int M = a.m, np = chol_panels(M);
     const double2 *A = a.A + (size_t)t * M * M;
@@ -686,29 +695,28 @@ __global__ __launch_bounds__(ZB_COLS) void k_zmw_bwd(ZCholArgs a, int p) {
         const int j1 = (p + 1) * CN, jb1 = min(CN, M - j1);
         if (tid < jb1) ws[tid] = z[j1 + tid];
         __syncthreads();
-        zbwd_x(linv + (size_t)(p + 1) * CN * CN, lvs, ws, xs, jb1, tid);
+        zbwd_x(linv + (size_t)(p + 1) * CN * CN, ws, part, xs, jb1, tid);
         __syncthreads();
         if (tid < jb1) z[j1 + tid] = xs[tid];
         __syncthreads();
     }
-    if (p < 0) {
-        if (tid == 0) {
-            int nf = 0;
-            for (int i = 0; i < M && !nf; ++i)
-                if (!isfinite(z[i].x) || !isfinite(z[i].y)) nf = 1;
-            if (nf) a.flags[t] = 1;
-        }
+    if (p < 0) {   // every thread scans a share of the solution for non-finite entries
+        int nf = 0;
+        for (int i = tid; i < M; i += ZB_COLS) nf |= !isfinite(z[i].x) || !isfinite(z[i].y);
+        nf = __syncthreads_or(nf);
+        if (tid == 0 && nf) a.flags[t] = 1;
         return;
     }
     const int j0 = p * CN, jb = min(CN, M - j0);
     if (tid < jb) ws[tid] = z[j0 + tid];
     __syncthreads();
-    zbwd_x(linv + (size_t)p * CN * CN, lvs, ws, xs, jb, tid);
+    zbwd_x(linv + (size_t)p * CN * CN, ws, part, xs, jb, tid);
     __syncthreads();
     const int c = blockIdx.x * ZB_COLS + tid;
     if (c < j0) {
         double sr = 0.0, si = 0.0;
         const double2 *col = A + (size_t)j0 * M + c;
+#pragma unroll 16
         for (int r = 0; r < jb; ++r) {
             const double2 l = col[(size_t)r * M], x = xs[r];
             sr += l.x * x.x + l.y * x.y;   // conj(l) x
