@@ -242,38 +242,154 @@ __global__ __launch_bounds__(CUT) void k_cmw_update_lds(CholArgs a, int j0, int 
         }
 }
 
+// The 64 x 64 diagonal block in blocks of RDB = 16 columns, as the complex kernel does it: one
+// wavefront factors each 16 x 16 diagonal block in registers (lane (r, q) = (lane / 4, lane % 4)
+// holds columns q, q + 4, q + 8, q + 12 of row r; the pivot by readlane, the row's column value
+// by a quad broadcast, 1 / sqrt by the hardware reciprocal square root and two Newton steps,
+// the next pivot's column updated first), the rows below solve for their block column by
+// forward substitution (a lane per row), the workgroup applies the trailing update; then the
+// inverse: the diagonal blocks at once (a wavefront each), the off-diagonal blocks by block rows,
+// Linv_ij = -Linv_ii sum_{j <= k < i} L_ik Linv_kj.
+constexpr int RDB = 16;
+
+template <int SEL>
+__device__ __forceinline__ double rquad_bcast_t(double v) { return dpp_d<SEL * 0x55, 0xF>(v, v); }
+__device__ __forceinline__ double rquad_bcast(double v, int sel) {
+    switch (sel) {
+    case 0: return rquad_bcast_t<0>(v);
+    case 1: return rquad_bcast_t<1>(v);
+    case 2: return rquad_bcast_t<2>(v);
+    default: return rquad_bcast_t<3>(v);
+    }
+}
+
+// L of the 16 x 16 diagonal block at (o, o) of Cs over its lower triangle, the reciprocals of
+// its diagonal into dinv; true on lanes that saw a pivot that is not positive.
+__device__ __forceinline__ bool rdiag_block16(double *Cs, double *dinv, int o, int lane) {
+    asm volatile("" : "+v"(lane));   // keeps the lane masks of the unrolled steps inside the caller's loop
+    const int r = lane >> 2, q = lane & 3;
+    double a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = q + 4 * s;
+        a[s] = c <= r ? Cs[(o + r) * CSP + o + c] : 0.0;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < RDB; ++c) {
+        const double piv = readlane_d(a[c >> 2], c * 4 + (c & 3));
+        bad |= !(piv > 0.0);
+        double y = __builtin_amdgcn_rsq(piv);
+        y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
+        y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
+        const double d = piv * y;
+        if (lane == 0) dinv[o + c] = y;
+        const double lc = a[c >> 2] * y;   // L_rc on lanes q == c % 4
+        const double lrc = rquad_bcast(lc, c & 3);
+        if (c + 1 < RDB) {
+            const double lk = readlane_d(lc, 4 * (c + 1) + (c & 3));   // L_{c+1,c}
+            if (q == ((c + 1) & 3) && r > c) a[(c + 1) >> 2] -= lrc * lk;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {   // C_rk -= L_rc L_kc, c + 1 < k <= r
+            const int k = q + 4 * s;
+            const double lkc = __shfl(lc, k * 4 + (c & 3), 64);
+            if (k > c + 1 && k <= r) a[s] -= lrc * lkc;
+        }
+        if (q == (c & 3)) a[c >> 2] = r > c ? lc : (r == c ? d : 0.0);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = q + 4 * s;
+        if (c <= r) Cs[(o + r) * CSP + o + c] = a[s];
+    }
+    return bad;
+}
+
+// L^-1 of the factored 16 x 16 diagonal block at (o, o) into the same block of Ls (zeros above
+// the diagonal): lane c < 16 solves L x = e_c down the rows, x in registers.
+__device__ __forceinline__ void rdiag_inv16(const double *Cs, double *Ls, const double *dinv, int o, int lane) {
+    asm volatile("" : "+v"(lane));
+    if (lane < RDB) {
+        const int c = lane;
+        double x[RDB];
+#pragma unroll
+        for (int rr = 0; rr < RDB; ++rr) {
+            double s = rr == c ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < rr; ++k) s -= Cs[(o + rr) * CSP + o + k] * x[k];
+            x[rr] = s * dinv[o + rr];
+            Ls[(o + rr) * CSP + o + c] = x[rr];
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p, int next) {
     __shared__ double Cs[CN * CSP];
     __shared__ double Ls[CN * CSP];
-    __shared__ double yre[CN], yim[CN];
+    __shared__ double Ws[(CN / RDB - 1) * RDB * RDB];
+    __shared__ double yre[CN], yim[CN], dinv[CN];
+    __shared__ double2 zs[CN];
     __shared__ int bad;
     const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int M = a.m;
     const int jb = (M - j0) < CN ? (M - j0) : CN;
+    const int nblk = (jb + RDB - 1) / RDB;
     double *A = a.A + (size_t)t * M * M;
     double2 *z = a.x + (size_t)t * M;
     if (tid == 0) bad = 0;
+    // rows and columns past jb (the last, ragged panel) are padded with the identity
     for (int e = tid; e < CN * CN; e += 256) {
         const int r = e / CN, c = e % CN;
-        Cs[r * CSP + c] = (r < jb && c <= r) ? A[(size_t)(j0 + r) * M + j0 + c] : 0.0;
+        Cs[r * CSP + c] = (r < jb && c <= r) ? A[(size_t)(j0 + r) * M + j0 + c] : (r == c ? 1.0 : 0.0);
+        if (c / RDB > r / RDB) Ls[r * CSP + c] = 0.0;
     }
     __syncthreads();
-    // right-looking factor of the block in LDS; thread (row fr, phase fs) updates columns fs,
-    // fs+4, ... of its row; column c is read unscaled during step c and scaled after the barrier
-    {
-        const int fr = tid >> 2, fs = tid & 3;
-        for (int c = 0; c < jb; ++c) {
-            const double piv = Cs[c * CSP + c];
-            if (tid == 0 && !(piv > 0.0)) bad = 1;
-            const double d = sqrt(piv), inv = 1.0 / d;
-            double lrc = 0.0;
-            if (fr > c && fr < jb) {
-                lrc = Cs[fr * CSP + c] * inv;
-                for (int k = c + 1 + fs; k <= fr; k += 4) Cs[fr * CSP + k] -= lrc * (Cs[k * CSP + c] * inv);
+    for (int b = 0; b < nblk; ++b) {
+        const int o = b * RDB;
+        if (wave == 0 && rdiag_block16(Cs, dinv, o, lane)) bad = 1;
+        __syncthreads();
+        const int n = CN - o - RDB;   // rows below the block (padding included)
+        if (b + 1 == nblk || n <= 0) break;
+        // L[r, block] L_bb^T = C[r, block]: forward substitution along the row, a lane per row
+        for (int e = tid; e < n; e += 256) {
+            const int r = o + RDB + e;
+            double x[RDB];
+#pragma unroll
+            for (int c = 0; c < RDB; ++c) {
+                double v = Cs[r * CSP + o + c];
+#pragma unroll
+                for (int k = 0; k < c; ++k) v -= x[k] * Cs[(o + c) * CSP + o + k];
+                x[c] = v * dinv[o + c];
             }
-            __syncthreads();
-            if (fs == 0 && fr > c && fr < jb) Cs[fr * CSP + c] = lrc;
-            if (tid == 0) Cs[c * CSP + c] = d;
+#pragma unroll
+            for (int c = 0; c < RDB; ++c) Cs[r * CSP + o + c] = x[c];
+        }
+        __syncthreads();
+        // trailing update C[r, k] -= L[r, block] L[k, block]^T, o + 16 <= k <= r: thread
+        // (row rr, phase kq) takes the columns kk = kq, kq + 4, ... of its row
+        {
+            const int rr = tid >> 2, kq = tid & 3;
+            if (rr < n) {
+                const int r = o + RDB + rr;
+                double acc[(CN - RDB) / 4];
+#pragma unroll
+                for (int j = 0; j < (CN - RDB) / 4; ++j) acc[j] = 0.0;
+#pragma unroll 4
+                for (int m = 0; m < RDB; ++m) {
+                    const double u = Cs[r * CSP + o + m];
+#pragma unroll
+                    for (int j = 0; j < (CN - RDB) / 4; ++j) {
+                        const int kk = kq + 4 * j;
+                        if (kk <= rr) acc[j] += u * Cs[(o + RDB + kk) * CSP + o + m];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < (CN - RDB) / 4; ++j) {
+                    const int kk = kq + 4 * j;
+                    if (kk <= rr) Cs[r * CSP + o + RDB + kk] -= acc[j];
+                }
+            }
         }
         __syncthreads();
     }
@@ -281,35 +397,45 @@ __global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p, int
         const int r = e / jb, c = e % jb;
         if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
     }
-    // Linv by forward substitution: wave w owns columns 16w..16w+15, four lanes per column
-    {
-        const int c = wave * 16 + (lane >> 2), fs = lane & 3;
-        for (int r = fs; r < CN; r += 4) Ls[r * CSP + c] = 0.0;
-        if (c < jb) {
-            if (fs == 0) Ls[c * CSP + c] = 1.0 / Cs[c * CSP + c];
-            for (int r = c + 1; r < jb; ++r) {
-                double sum = 0.0;
-                for (int k = c + fs; k < r; k += 4) sum += Cs[r * CSP + k] * Ls[k * CSP + c];
-                sum += __shfl_xor(sum, 1, 64);
-                sum += __shfl_xor(sum, 2, 64);
-                if (fs == 0) Ls[r * CSP + c] = -sum / Cs[r * CSP + r];
-            }
-        }
-    }
+    // the diagonal blocks of Linv, a wavefront each, then the off-diagonal blocks by block rows
+    if (wave < nblk) rdiag_inv16(Cs, Ls, dinv, wave * RDB, lane);
     __syncthreads();
-    if (tid < jb) {
+    for (int i = 1; i < nblk; ++i) {
+        for (int e = tid; e < i * RDB * RDB; e += 256) {   // W_ij = sum_{j <= k < i} L_ik Linv_kj
+            const int j = e / (RDB * RDB), c = (e / RDB) % RDB, r = e % RDB;
+            double s = 0.0;
+#pragma unroll 8
+            for (int m = j * RDB; m < i * RDB; ++m) s += Cs[(i * RDB + r) * CSP + m] * Ls[m * CSP + j * RDB + c];
+            Ws[(j * RDB + r) * RDB + c] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < i * RDB * RDB; e += 256) {   // Linv_ij = -Linv_ii W_ij
+            const int j = e / (RDB * RDB), c = (e / RDB) % RDB, r = e % RDB;
+            double s = 0.0;
+#pragma unroll 4
+            for (int m = 0; m < RDB; ++m) s += Ls[(i * RDB + r) * CSP + i * RDB + m] * Ws[(j * RDB + m) * RDB + c];
+            Ls[(i * RDB + r) * CSP + j * RDB + c] = -s;
+        }
+        __syncthreads();
+    }
+    if (tid < jb) zs[tid] = z[j0 + tid];
+    __syncthreads();
+    if (tid < jb) {   // y = Linv z_panel
         double sr = 0.0, si = 0.0;
+#pragma unroll 8
         for (int k = 0; k <= tid; ++k) {
             const double l = Ls[tid * CSP + k];
-            const double2 zk = z[j0 + k];
-            sr += l * zk.x;
-            si += l * zk.y;
+            sr += l * zs[k].x;
+            si += l * zs[k].y;
         }
         yre[tid] = sr;
         yim[tid] = si;
     }
     double *lv = a.linv + ((size_t)t * chol_panels(M) + p) * CN * CN;
-    for (int e = tid; e < CN * CN; e += 256) lv[e] = Ls[(e / CN) * CSP + e % CN];
+    for (int e = tid; e < CN * CN; e += 256) {
+        const int r = e / CN, c = e % CN;
+        lv[e] = (r < jb && c < jb) ? Ls[r * CSP + c] : 0.0;
+    }
     if (tid >= jb && tid < CN) {
         yre[tid] = 0.0;
         yim[tid] = 0.0;
