@@ -29,6 +29,82 @@ static_assert(CN % (2 * CK) == 0, "the update loop takes k-slices in pairs");
 
 __host__ __device__ inline int chol_panels(int m) { return (m + CN - 1) / CN; }
 
+// The 64 x 64 diagonal block of a panel is factored in blocks of RDB = 16 columns (the
+// kernels below and the several-workgroup k_cmw_diag): one wavefront per 16 x 16 block.
+constexpr int RDB = 16;
+
+template <int SEL>
+__device__ __forceinline__ double rquad_bcast_t(double v) { return dpp_d<SEL * 0x55, 0xF>(v, v); }
+__device__ __forceinline__ double rquad_bcast(double v, int sel) {
+    switch (sel) {
+    case 0: return rquad_bcast_t<0>(v);
+    case 1: return rquad_bcast_t<1>(v);
+    case 2: return rquad_bcast_t<2>(v);
+    default: return rquad_bcast_t<3>(v);
+    }
+}
+
+// L of the 16 x 16 diagonal block at (o, o) of Cs over its lower triangle, the reciprocals of
+// its diagonal into dinv; true on lanes that saw a pivot that is not positive.
+__device__ __forceinline__ bool rdiag_block16(double *Cs, double *dinv, int o, int lane) {
+    asm volatile("" : "+v"(lane));   // keeps the lane masks of the unrolled steps inside the caller's loop
+    const int r = lane >> 2, q = lane & 3;
+    double a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = q + 4 * s;
+        a[s] = c <= r ? Cs[(o + r) * CSP + o + c] : 0.0;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < RDB; ++c) {
+        const double piv = readlane_d(a[c >> 2], c * 4 + (c & 3));
+        bad |= !(piv > 0.0);
+        double y = __builtin_amdgcn_rsq(piv);
+        y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
+        y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
+        const double d = piv * y;
+        if (lane == 0) dinv[o + c] = y;
+        const double lc = a[c >> 2] * y;   // L_rc on lanes q == c % 4
+        const double lrc = rquad_bcast(lc, c & 3);
+        if (c + 1 < RDB) {
+            const double lk = readlane_d(lc, 4 * (c + 1) + (c & 3));   // L_{c+1,c}
+            if (q == ((c + 1) & 3) && r > c) a[(c + 1) >> 2] -= lrc * lk;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {   // C_rk -= L_rc L_kc, c + 1 < k <= r
+            const int k = q + 4 * s;
+            const double lkc = __shfl(lc, k * 4 + (c & 3), 64);
+            if (k > c + 1 && k <= r) a[s] -= lrc * lkc;
+        }
+        if (q == (c & 3)) a[c >> 2] = r > c ? lc : (r == c ? d : 0.0);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = q + 4 * s;
+        if (c <= r) Cs[(o + r) * CSP + o + c] = a[s];
+    }
+    return bad;
+}
+
+// L^-1 of the factored 16 x 16 diagonal block at (o, o) into the same block of Ls (zeros above
+// the diagonal): lane c < 16 solves L x = e_c down the rows, x in registers.
+__device__ __forceinline__ void rdiag_inv16(const double *Cs, double *Ls, const double *dinv, int o, int lane) {
+    asm volatile("" : "+v"(lane));
+    if (lane < RDB) {
+        const int c = lane;
+        double x[RDB];
+#pragma unroll
+        for (int rr = 0; rr < RDB; ++rr) {
+            double s = rr == c ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < rr; ++k) s -= Cs[(o + rr) * CSP + o + k] * x[k];
+            x[rr] = s * dinv[o + rr];
+            Ls[(o + rr) * CSP + o + c] = x[rr];
+        }
+    }
+}
+
 // One real symmetric positive-definite system per trajectory: A [T][M][M] (lower triangle,
 // overwritten by L), right-hand sides rhs [T][M] (two real columns packed as double2),
 // solution x [T][M], block inverses linv [T][panels][64*64], failure flags [T].
@@ -45,7 +121,8 @@ __global__ __launch_bounds__(CT1) void k_chol_solve(CholArgs a) {
     // the two k-slice staging buffers (As | Bs) and the chunk tile Cs are never live at once
     __shared__ double smem[2 * CKBUF > CR * CSP ? 2 * CKBUF : CR * CSP];
     __shared__ double Ls[CN * CSP];
-    __shared__ double yre[CN], yim[CN];
+    __shared__ double yre[CN], yim[CN], dinv[CN];
+    __shared__ double Ws[(CN / RDB - 1) * RDB * RDB];
     double *Cs = smem;
     __shared__ int bad;
     const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -132,23 +209,59 @@ __global__ __launch_bounds__(CT1) void k_chol_solve(CholArgs a) {
             __syncthreads();
             int rstart = 0;
             if (r0 == j0) {
-                // ---- factor the diagonal block in LDS, right-looking; thread (row fr, phase fs)
-                // updates columns c+1+fs, c+9+fs, ... of its row.  Column c is read unscaled during
-                // step c and scaled after the barrier, so one barrier per column suffices.
-                {
-                    const int fr = tid >> 3, fs = tid & 7;
-                    for (int c = 0; c < jb; ++c) {
-                        const double piv = Cs[c * CSP + c];
-                        if (tid == 0 && !(piv > 0.0)) bad = 1;
-                        const double d = sqrt(piv), inv = 1.0 / d;
-                        double lrc = 0.0;
-                        if (fr > c && fr < jb) {
-                            lrc = Cs[fr * CSP + c] * inv;
-                            for (int k = c + 1 + fs; k <= fr; k += 8) Cs[fr * CSP + k] -= lrc * (Cs[k * CSP + c] * inv);
+                // ---- factor the diagonal block in LDS in blocks of 16 columns (rows and columns
+                // past jb, the last panel's, padded with the identity): a wavefront factors each
+                // 16 x 16 block, the rows below solve for their block column (a lane per row),
+                // the workgroup applies the trailing update
+                const int nblk = (jb + RDB - 1) / RDB;
+                for (int e = tid; e < CN * CN; e += CT1) {
+                    const int r = e / CN, c = e % CN;
+                    if (r >= jb && c <= r) Cs[r * CSP + c] = r == c ? 1.0 : 0.0;
+                    if (c / RDB > r / RDB) Ls[r * CSP + c] = 0.0;
+                }
+                __syncthreads();
+                for (int b = 0; b < nblk; ++b) {
+                    const int o = b * RDB;
+                    if (wave == 0 && rdiag_block16(Cs, dinv, o, lane)) bad = 1;
+                    __syncthreads();
+                    const int n = CN - o - RDB;
+                    if (b + 1 == nblk || n <= 0) break;
+                    for (int e = tid; e < n; e += CT1) {   // L[r, block] L_bb^T = C[r, block]
+                        const int r = o + RDB + e;
+                        double x[RDB];
+#pragma unroll
+                        for (int c = 0; c < RDB; ++c) {
+                            double v = Cs[r * CSP + o + c];
+#pragma unroll
+                            for (int k = 0; k < c; ++k) v -= x[k] * Cs[(o + c) * CSP + o + k];
+                            x[c] = v * dinv[o + c];
                         }
-                        __syncthreads();
-                        if (fs == 0 && fr > c && fr < jb) Cs[fr * CSP + c] = lrc;
-                        if (tid == 0) Cs[c * CSP + c] = d;
+#pragma unroll
+                        for (int c = 0; c < RDB; ++c) Cs[r * CSP + o + c] = x[c];
+                    }
+                    __syncthreads();
+                    {   // C[r, k] -= L[r, block] L[k, block]^T: thread (row rr, phase kq), columns kq + 8 j
+                        const int rr = tid >> 3, kq = tid & 7;
+                        if (rr < n) {
+                            const int r = o + RDB + rr;
+                            double acc[(CN - RDB) / 8];
+#pragma unroll
+                            for (int j = 0; j < (CN - RDB) / 8; ++j) acc[j] = 0.0;
+#pragma unroll 4
+                            for (int m = 0; m < RDB; ++m) {
+                                const double u = Cs[r * CSP + o + m];
+#pragma unroll
+                                for (int j = 0; j < (CN - RDB) / 8; ++j) {
+                                    const int kk = kq + 8 * j;
+                                    if (kk <= rr) acc[j] += u * Cs[(o + RDB + kk) * CSP + o + m];
+                                }
+                            }
+#pragma unroll
+                            for (int j = 0; j < (CN - RDB) / 8; ++j) {
+                                const int kk = kq + 8 * j;
+                                if (kk <= rr) Cs[r * CSP + o + RDB + kk] -= acc[j];
+                            }
+                        }
                     }
                     __syncthreads();
                 }
@@ -156,23 +269,31 @@ __global__ __launch_bounds__(CT1) void k_chol_solve(CholArgs a) {
                     const int r = e / jb, c = e % jb;
                     if (c <= r) A[(size_t)(j0 + r) * M + j0 + c] = Cs[r * CSP + c];
                 }
-                // ---- Linv, the inverse of the lower-triangular block by forward substitution:
-                // wave w owns columns 8w..8w+7, eight lanes per column share each row's sum
-                // (rows of one column are written and read back by the same wave, in order)
-                {
-                    const int c = wave * 8 + (lane >> 3), fs = lane & 7;
-                    for (int r = fs; r < CN; r += 8) Ls[r * CSP + c] = 0.0;
-                    if (c < jb) {
-                        if (fs == 0) Ls[c * CSP + c] = 1.0 / Cs[c * CSP + c];
-                        for (int r = c + 1; r < jb; ++r) {
-                            double sum = 0.0;
-                            for (int k = c + fs; k < r; k += 8) sum += Cs[r * CSP + k] * Ls[k * CSP + c];
-                            sum += __shfl_xor(sum, 1, 64);
-                            sum += __shfl_xor(sum, 2, 64);
-                            sum += __shfl_xor(sum, 4, 64);
-                            if (fs == 0) Ls[r * CSP + c] = -sum / Cs[r * CSP + r];
-                        }
+                // ---- Linv: the diagonal blocks at once (a wavefront each), then the
+                // off-diagonal blocks by block rows, Linv_ij = -Linv_ii sum_{j <= k < i} L_ik Linv_kj
+                if (wave < nblk) rdiag_inv16(Cs, Ls, dinv, wave * RDB, lane);
+                __syncthreads();
+                for (int i = 1; i < nblk; ++i) {
+                    for (int e = tid; e < i * RDB * RDB; e += CT1) {
+                        const int j = e / (RDB * RDB), c = (e / RDB) % RDB, r = e % RDB;
+                        double sm = 0.0;
+#pragma unroll 8
+                        for (int m = j * RDB; m < i * RDB; ++m) sm += Cs[(i * RDB + r) * CSP + m] * Ls[m * CSP + j * RDB + c];
+                        Ws[(j * RDB + r) * RDB + c] = sm;
                     }
+                    __syncthreads();
+                    for (int e = tid; e < i * RDB * RDB; e += CT1) {
+                        const int j = e / (RDB * RDB), c = (e / RDB) % RDB, r = e % RDB;
+                        double sm = 0.0;
+#pragma unroll 4
+                        for (int m = 0; m < RDB; ++m) sm += Ls[(i * RDB + r) * CSP + i * RDB + m] * Ws[(j * RDB + m) * RDB + c];
+                        Ls[(i * RDB + r) * CSP + j * RDB + c] = -sm;
+                    }
+                    __syncthreads();
+                }
+                for (int e = tid; e < CN * CN; e += CT1) {   // padding rows and columns of Linv are zero
+                    const int r = e / CN, c = e % CN;
+                    if (r >= jb || c >= jb) Ls[r * CSP + c] = 0.0;
                 }
                 __syncthreads();
                 // ---- forward substitution of this panel: y = Linv z_panel

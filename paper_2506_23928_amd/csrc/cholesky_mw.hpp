@@ -250,80 +250,6 @@ __global__ __launch_bounds__(CUT) void k_cmw_update_lds(CholArgs a, int j0, int 
 // forward substitution (a lane per row), the workgroup applies the trailing update; then the
 // inverse: the diagonal blocks at once (a wavefront each), the off-diagonal blocks by block rows,
 // Linv_ij = -Linv_ii sum_{j <= k < i} L_ik Linv_kj.
-constexpr int RDB = 16;
-
-template <int SEL>
-__device__ __forceinline__ double rquad_bcast_t(double v) { return dpp_d<SEL * 0x55, 0xF>(v, v); }
-__device__ __forceinline__ double rquad_bcast(double v, int sel) {
-    switch (sel) {
-    case 0: return rquad_bcast_t<0>(v);
-    case 1: return rquad_bcast_t<1>(v);
-    case 2: return rquad_bcast_t<2>(v);
-    default: return rquad_bcast_t<3>(v);
-    }
-}
-
-// L of the 16 x 16 diagonal block at (o, o) of Cs over its lower triangle, the reciprocals of
-// its diagonal into dinv; true on lanes that saw a pivot that is not positive.
-__device__ __forceinline__ bool rdiag_block16(double *Cs, double *dinv, int o, int lane) {
-    asm volatile("" : "+v"(lane));   // keeps the lane masks of the unrolled steps inside the caller's loop
-    const int r = lane >> 2, q = lane & 3;
-    double a[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int c = q + 4 * s;
-        a[s] = c <= r ? Cs[(o + r) * CSP + o + c] : 0.0;
-    }
-    bool bad = false;
-#pragma unroll
-    for (int c = 0; c < RDB; ++c) {
-        const double piv = readlane_d(a[c >> 2], c * 4 + (c & 3));
-        bad |= !(piv > 0.0);
-        double y = __builtin_amdgcn_rsq(piv);
-        y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
-        y = fma(0.5 * y, fma(-piv * y, y, 1.0), y);
-        const double d = piv * y;
-        if (lane == 0) dinv[o + c] = y;
-        const double lc = a[c >> 2] * y;   // L_rc on lanes q == c % 4
-        const double lrc = rquad_bcast(lc, c & 3);
-        if (c + 1 < RDB) {
-            const double lk = readlane_d(lc, 4 * (c + 1) + (c & 3));   // L_{c+1,c}
-            if (q == ((c + 1) & 3) && r > c) a[(c + 1) >> 2] -= lrc * lk;
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {   // C_rk -= L_rc L_kc, c + 1 < k <= r
-            const int k = q + 4 * s;
-            const double lkc = __shfl(lc, k * 4 + (c & 3), 64);
-            if (k > c + 1 && k <= r) a[s] -= lrc * lkc;
-        }
-        if (q == (c & 3)) a[c >> 2] = r > c ? lc : (r == c ? d : 0.0);
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int c = q + 4 * s;
-        if (c <= r) Cs[(o + r) * CSP + o + c] = a[s];
-    }
-    return bad;
-}
-
-// L^-1 of the factored 16 x 16 diagonal block at (o, o) into the same block of Ls (zeros above
-// the diagonal): lane c < 16 solves L x = e_c down the rows, x in registers.
-__device__ __forceinline__ void rdiag_inv16(const double *Cs, double *Ls, const double *dinv, int o, int lane) {
-    asm volatile("" : "+v"(lane));
-    if (lane < RDB) {
-        const int c = lane;
-        double x[RDB];
-#pragma unroll
-        for (int rr = 0; rr < RDB; ++rr) {
-            double s = rr == c ? 1.0 : 0.0;
-#pragma unroll
-            for (int k = 0; k < rr; ++k) s -= Cs[(o + rr) * CSP + o + k] * x[k];
-            x[rr] = s * dinv[o + rr];
-            Ls[(o + rr) * CSP + o + c] = x[rr];
-        }
-    }
-}
-
 __global__ __launch_bounds__(256) void k_cmw_diag(CholArgs a, int j0, int p, int next) {
     __shared__ double Cs[CN * CSP];
     __shared__ double Ls[CN * CSP];
