@@ -466,9 +466,15 @@ __global__ __launch_bounds__(256) void k_cmw_trsm(CholArgs a, int j0, int p) {
         }
 }
 
-// backward substitution L^T x = y, last panel first; wave w owns 16 panel columns
+// backward substitution L^T x = y, last panel first; wave w owns 16 panel columns.  Per panel:
+// the block inverse is copied to LDS (its loads in flight during the row loop), w_p = y_p -
+// sum over the rows below of L[r, panel]^T x_r (each lane walks rows 64 apart, four rows per
+// pass), then x_p = Linv_p^T w_p by all 256 threads: thread (c, g) sums the rows k = g, g + 4,
+// ... of the inverse (zero above its diagonal) and the four partial sums meet in LDS.
 __global__ __launch_bounds__(256) void k_cmw_backward(CholArgs a) {
     __shared__ double yre[CN], yim[CN];
+    __shared__ double lvs[CN * CN];
+    __shared__ double2 part[256];
     const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int M = a.m;
     const double *A = a.A + (size_t)t * M * M;
@@ -476,8 +482,17 @@ __global__ __launch_bounds__(256) void k_cmw_backward(CholArgs a) {
     double2 *z = a.x + (size_t)t * M;
     for (int p = chol_panels(M) - 1; p >= 0; --p) {
         const int j0 = p * CN, jb = (M - j0) < CN ? (M - j0) : CN;
+        {
+            const double *lv = linv + (size_t)p * CN * CN;
+            double lq[CN * CN / 256];
+#pragma unroll
+            for (int q = 0; q < CN * CN / 256; ++q) lq[q] = lv[tid + 256 * q];
+#pragma unroll
+            for (int q = 0; q < CN * CN / 256; ++q) lvs[tid + 256 * q] = lq[q];
+        }
         double sr[16], si[16];
         for (int q = 0; q < 16; ++q) sr[q] = si[q] = 0.0;
+#pragma unroll 4
         for (int r = j0 + jb + lane; r < M; r += 64) {
             const double2 xr = z[r];
             const double *row = A + (size_t)r * M + j0 + wave * 16;
@@ -496,15 +511,25 @@ __global__ __launch_bounds__(256) void k_cmw_backward(CholArgs a) {
             }
         }
         __syncthreads();
-        if (tid < jb) {
-            const double *lv = linv + (size_t)p * CN * CN;
+        {
+            const int c = tid & (CN - 1), g = tid >> 6;
             double xr = 0.0, xi = 0.0;
-            for (int k = tid; k < jb; ++k) {
-                const double l = lv[k * CN + tid];
+#pragma unroll 4
+            for (int k = g; k < jb; k += 4) {
+                const double l = lvs[k * CN + c];
                 xr += l * yre[k];
                 xi += l * yim[k];
             }
-            z[j0 + tid] = make_double2(xr, xi);
+            part[tid] = make_double2(xr, xi);
+        }
+        __syncthreads();
+        if (tid < jb) {
+            double2 x = part[tid];
+            for (int g = 1; g < 4; ++g) {
+                x.x += part[tid + CN * g].x;
+                x.y += part[tid + CN * g].y;
+            }
+            z[j0 + tid] = x;
         }
         __syncthreads();
     }
