@@ -68,7 +68,7 @@ enum { TVMC_PREC_FP64 = 0, TVMC_PREC_MFMA = 1 };
 /* One Lindblad problem (Eq. 1 with the Hamiltonian of Eq. 10), shared by all trajectories of a
  * context (see tvmc_init_batch for one problem per trajectory). */
 typedef struct {
-    int32_t n_sites;              /* N, 1..128 (the learned proposal and the SNR solve: 1..64) */
+    int32_t n_sites;              /* N, 1..192 (the learned proposal and the SNR solve: 1..64) */
     const double *J;              /* host, N*N row-major, symmetric, zero diagonal */
     double hx;
     int32_t n_jumps;              /* 0..256 */

@@ -87,7 +87,7 @@ __device__ __forceinline__ double spin(uint64_t mask, int i) { return ((mask >> 
 
 // A configuration of up to 64 W spins as W words: bit i % 64 of word i / 64 set <=> s_i = +1;
 // bits at and above N are zero.  Stored as W consecutive words per configuration.
-constexpr int MAX_WORDS = 2;   // N <= 128
+constexpr int MAX_WORDS = 3;   // N <= 192
 template <int W>
 struct Cfg {
     uint64_t w[W];
@@ -178,7 +178,7 @@ __device__ __forceinline__ int o_int(const Cfg<W> &c, int p, int q, int n) {
 // Everything a kernel may touch, as raw device pointers into the caller's workspace.
 struct Dev {
     int n, m, nch, ns, nc, per, nt, nobs;
-    int nw;                   // 64-bit words per configuration (1 for N <= 64, 2 for N <= 128)
+    int nw;                   // 64-bit words per configuration (1 for N <= 64, 2 for N <= 128, 3 for N <= 192)
     int kind, nh;             // ansatz (0 Jastrow, 1 RBM), hidden units
     int mp;                   // M rounded up to 128 (rows of the RBM's BF16 operand planes)
     int ss;                   // 1: the solve runs in sample space (S holds T = O_c O_c^H / N_s)

@@ -2,7 +2,7 @@
 // local quantities the estimators need (text after Eq. 9; definitions after Eq. 8).
 //
 // One wavefront per Markov chain; lane i owns spin i (N <= 64; two spins per lane up to N = 128
-// in k_sample_jastrow_w2).  The configuration lives in a wave-uniform 64-bit mask.  Lane i keeps the complex field f_i = a_i + sum_{k!=i} eta_ik s_k,
+// in k_sample_jastrow_wn).  The configuration lives in a wave-uniform 64-bit mask.  Lane i keeps the complex field f_i = a_i + sum_{k!=i} eta_ik s_k,
 // so the flip log-ratio of site i is -2 s_i f_i (O(1)); an accepted flip of site i updates
 // every lane's field with one row of eta, read from LDS (the dense symmetric eta of the
 // trajectory, staged once per workgroup and shared by its CPB chains).  Random numbers for
@@ -38,11 +38,13 @@ __global__ void k_init_chains(Dev a) {
     const int t = blockIdx.y;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.nc) return;
-    // one block of 128 random bits: sites 0..63 from words 0, 1 and sites 64..127 from words 2, 3
-    uint32_t r[4];
-    philox4x32_10(0u, (uint32_t)c, 0u, (3u << 24) | (uint32_t)(a.traj0 + t), a.key0, a.key1, r);
+    // blocks of 128 random bits, block b from the counter (b, chain, 0, 3 << 24 | trajectory):
+    // its sites 0..63 from words 0, 1 of the draw and 64..127 from words 2, 3
     for (int q = 0; q < a.nw; ++q) {
-        uint64_t m = (uint64_t)r[2 * q] | ((uint64_t)r[2 * q + 1] << 32);
+        uint32_t r[4];
+        philox4x32_10((uint32_t)(q >> 1), (uint32_t)c, 0u, (3u << 24) | (uint32_t)(a.traj0 + t), a.key0, a.key1, r);
+        const int h = 2 * (q & 1);
+        uint64_t m = (uint64_t)r[h] | ((uint64_t)r[h + 1] << 32);
         const int bits = a.n - 64 * q;
         if (bits < 64) m &= (1ull << bits) - 1ull;
         a.chains[((size_t)t * a.nc + c) * a.nw + q] = m;
@@ -219,30 +221,35 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int stage, i
     }
 }
 
-// The same chain for 64 < N <= 128 (two configuration words).  Lane l owns sites l and l + 64
-// and keeps their real fields only, which is all the accept test needs; the real eta plane
-// (N x N doubles, at most 128 KB) is staged in LDS.  The imaginary fields a recorded sample
-// needs for its flip ratios are summed afresh from the imaginary plane in global memory, in
-// the order a_i, then k = 0..N-1.  No learned proposal.
-template <int CPB>
-__global__ __launch_bounds__(64 * CPB) void k_sample_jastrow_w2(Dev a, int stage, int burn) {
+// The same chain for 64 < N <= 192 (W = 2 or 3 configuration words).  Lane l owns sites l,
+// l + 64, l + 128 and keeps their real fields only, which is all the accept test needs; the real
+// eta plane is staged in LDS where it fits (N <= 128: at most 128 KB) and read from global
+// memory otherwise (a row of it is contiguous over the lanes' sites).  The imaginary fields a
+// recorded sample needs for its flip ratios are summed afresh from the imaginary plane in
+// global memory, in the order a_i, then k = 0..N-1.  No learned proposal.
+template <int CPB, int W>
+__global__ __launch_bounds__(64 * CPB) void k_sample_jastrow_wn(Dev a, int stage, int burn) {
+    static_assert(W == 2 || W == 3, "two or three configuration words");
+    constexpr bool ETA_LDS = W == 2;
     const int step = a.dstep[0];
-    __shared__ double lre[128 * 128];
+    __shared__ double lre_s[ETA_LDS ? 128 * 128 : 1];
     const int n = a.n;
     const int t = blockIdx.y;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * CPB + w;
-    {
-        const double *er = a.eta_re + (size_t)t * n * n;
-        for (int i = threadIdx.x; i < n * n; i += blockDim.x) lre[i] = er[i];
+    const double *er = a.eta_re + (size_t)t * n * n;
+    if (ETA_LDS) {
+        for (int i = threadIdx.x; i < n * n; i += blockDim.x) lre_s[i] = er[i];
+        __syncthreads();
     }
-    __syncthreads();
+    const double *lre = ETA_LDS ? lre_s : er;
     const double *eim_g = a.eta_im + (size_t)t * n * n;
     const double2 *th = a.theta_eval + (size_t)t * a.m;
-    Cfg<2> cfg = cfg_load<2>(a.chains + ((size_t)t * a.nc + c) * 2);
+    Cfg<W> cfg = cfg_load<W>(a.chains + ((size_t)t * a.nc + c) * W);
 
-    double fre[2] = {0.0, 0.0};
-    for (int q = 0; q < 2; ++q) {
+    double fre[W];
+    for (int q = 0; q < W; ++q) {
+        fre[q] = 0.0;
         const int site = lane + 64 * q;
         if (site >= n) continue;
         double f = th[site].x;
@@ -271,13 +278,18 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow_w2(Dev a, int stage
         for (int j = 0; j < cnt; ++j) {
             const int i = __builtin_amdgcn_readlane(site_l, j);
             const double lu = readlane_d(logu_l, j);
-            const double fi = readlane_d(i < 64 ? fre[0] : fre[1], i & 63);
+            const int iq = i >> 6;
+            double fsel = fre[0];
+#pragma unroll
+            for (int q = 1; q < W; ++q)
+                if (iq == q) fsel = fre[q];
+            const double fi = readlane_d(fsel, i & 63);
             const double si = spin(cfg, i);
             const double dre = -2.0 * si * fi;
             if (lu < 2.0 * dre) {
                 cfg_flip(cfg, i);
                 const double c2 = -2.0 * si;
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < W; ++q) {
                     const int site = lane + 64 * q;
                     if (site < n) fre[q] += c2 * lre[i * n + site];
                 }
@@ -288,7 +300,7 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow_w2(Dev a, int stage
                 ++rec;
                 next_rec += rec_stride;
                 double ere = 0.0, eim = 0.0;
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < W; ++q) {
                     const int site = lane + 64 * q;
                     if (site >= n) continue;
                     const double sl = spin(cfg, site);
@@ -310,14 +322,14 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow_w2(Dev a, int stage
                 ere = wave_sum(ere);
                 eim = wave_sum(eim);
                 if (lane == 0) {
-                    cfg_store(a.samples + sidx * 2, cfg);
+                    cfg_store(a.samples + sidx * W, cfg);
                     a.eloc[sidx] = make_double2(ere, eim);
                 }
             }
         }
     }
     if (lane == 0) {
-        cfg_store(a.chains + ((size_t)t * a.nc + c) * 2, cfg);
+        cfg_store(a.chains + ((size_t)t * a.nc + c) * W, cfg);
         a.acc[(size_t)t * a.nc + c] = nacc;
     }
 }

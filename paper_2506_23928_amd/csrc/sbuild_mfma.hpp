@@ -132,7 +132,8 @@ inline tvmc_status launch_sbuild_mfma(const Dev &d, hipStream_t st) {
     const dim3 grid(nt * (nt + 1) / 2, d.nt);
     if (d.kind == TVMC_ANSATZ_LJPH) {
         if (d.nw == 1) hipLaunchKernelGGL((k_sbuild_i8<true, 1>), grid, dim3(256), 0, st, d);
-        else hipLaunchKernelGGL((k_sbuild_i8<true, 2>), grid, dim3(256), 0, st, d);
+        else if (d.nw == 2) hipLaunchKernelGGL((k_sbuild_i8<true, 2>), grid, dim3(256), 0, st, d);
+        else hipLaunchKernelGGL((k_sbuild_i8<true, 3>), grid, dim3(256), 0, st, d);
     } else {
         hipLaunchKernelGGL((k_sbuild_i8<false, 1>), grid, dim3(256), 0, st, d);   // the samples are not read
     }

@@ -237,6 +237,11 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
         const int64_t omax = p->n_sites - 1;   // largest |O_k| of a shared distance
         if (c->precision == TVMC_PREC_MFMA && (int64_t)c->n_samples * omax * omax >= ((int64_t)1 << 31))
             return snprintf(msg, len, "LJPHd int8 S-build: n_samples (N-1)^2 must stay below 2^31"), TVMC_E_INVAL;
+        // a shared distance D > d has O = sum over the N - D pairs at that distance of s_j s_{j+D}:
+        // the int8 operands hold it exactly only while N - d - 1 <= 127
+        if (c->precision == TVMC_PREC_MFMA && a->range < p->n_sites - 1 && p->n_sites - a->range - 1 > 127)
+            return snprintf(msg, len, "LJPHd int8 S-build: the shared-distance sums need N - d - 1 <= 127 "
+                                      "(use the FP64 S-build)"), TVMC_E_INVAL;
         if (c->solver == TVMC_SOLVER_SAMPLE_SPACE)
             return snprintf(msg, len, "LJPHd solves in parameter space"), TVMC_E_INVAL;
     }
@@ -334,8 +339,11 @@ tvmc_status check_batch(const tvmc_problem *p, int np, const tvmc_ansatz *a, con
         if ((d).nw == 1) {               \
             constexpr int W_ = 1;        \
             LAUNCH;                      \
-        } else {                         \
+        } else if ((d).nw == 2) {        \
             constexpr int W_ = 2;        \
+            LAUNCH;                      \
+        } else {                         \
+            constexpr int W_ = 3;        \
             LAUNCH;                      \
         }                                \
     } while (0)
@@ -417,10 +425,14 @@ tvmc_status run_sample(tvmc_ctx *c) {
             if (qh == 1) { RBM_CPB(1, false, true, 1) }
             else if (qh == 2) { if (wl) { RBM_CPB(2, false, true, 1) } else { RBM_CPB(2, false, false, 1) } }
             else { if (wl) { RBM_CPB(4, false, true, 1) } else { RBM_CPB(4, false, false, 1) } }
-        } else {
+        } else if (d.nw == 2) {
             if (qh == 1) { if (wl) { RBM_CPB(1, false, true, 2) } else { RBM_CPB(1, false, false, 2) } }
             else if (qh == 2) { if (wl) { RBM_CPB(2, false, true, 2) } else { RBM_CPB(2, false, false, 2) } }
             else { if (wl) { RBM_CPB(4, false, true, 2) } else { RBM_CPB(4, false, false, 2) } }
+        } else {
+            if (qh == 1) { if (wl) { RBM_CPB(1, false, true, 3) } else { RBM_CPB(1, false, false, 3) } }
+            else if (qh == 2) { if (wl) { RBM_CPB(2, false, true, 3) } else { RBM_CPB(2, false, false, 3) } }
+            else { if (wl) { RBM_CPB(4, false, true, 3) } else { RBM_CPB(4, false, false, 3) } }
         }
 #undef RBM_CPB
 #undef RBM_LAUNCH
@@ -435,13 +447,20 @@ tvmc_status run_sample(tvmc_ctx *c) {
         Scope sc(c, "sample");
         dim3 grid(d.nc / c->cpb, T);
 #define JAS_LAUNCH(CPB, AR) hipLaunchKernelGGL((k_sample_jastrow<CPB, AR>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
-#define JAS2_LAUNCH(CPB) hipLaunchKernelGGL((k_sample_jastrow_w2<CPB>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
+#define JASW_LAUNCH(CPB, W) hipLaunchKernelGGL((k_sample_jastrow_wn<CPB, W>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
         if (d.nw == 2) {
             switch (c->cpb) {
-            case 8: JAS2_LAUNCH(8); break;
-            case 4: JAS2_LAUNCH(4); break;
-            case 2: JAS2_LAUNCH(2); break;
-            default: JAS2_LAUNCH(1); break;
+            case 8: JASW_LAUNCH(8, 2); break;
+            case 4: JASW_LAUNCH(4, 2); break;
+            case 2: JASW_LAUNCH(2, 2); break;
+            default: JASW_LAUNCH(1, 2); break;
+            }
+        } else if (d.nw == 3) {
+            switch (c->cpb) {
+            case 8: JASW_LAUNCH(8, 3); break;
+            case 4: JASW_LAUNCH(4, 3); break;
+            case 2: JASW_LAUNCH(2, 3); break;
+            default: JASW_LAUNCH(1, 3); break;
             }
         } else if (d.ar) {
             switch (c->cpb) {
@@ -459,7 +478,7 @@ tvmc_status run_sample(tvmc_ctx *c) {
             }
         }
 #undef JAS_LAUNCH
-#undef JAS2_LAUNCH
+#undef JASW_LAUNCH
         LAUNCHCHECK(c, "k_sample_jastrow");
     }
     c->phase = 1;

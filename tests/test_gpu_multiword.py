@@ -1,8 +1,8 @@
-"""Configurations of 65 to 128 spins (two 64-bit words: sites 0..63 in word 0, 64..127 in word 1)
-on the GPU against the oracle.  The bars are those of the one-word tests: samples, accept counts,
+"""Configurations of 65 to 192 spins (two or three 64-bit words: site i in word i // 64) on the
+GPU against the oracle.  The bars are those of the one-word tests: samples, accept counts,
 <O_k> and the Jastrow S bit for bit, local energies and <B^n> 1e-13 (RBM 1e-12), D 1e-12,
 increments and theta 1e-10 relative.  N = 65 leaves one site in the second word (the ragged
-case), N = 128 fills both."""
+case), N = 128 fills both, N = 129 puts one site in a third word and N = 192 fills three."""
 import numpy as np
 import pytest
 from parity_log import parity
@@ -34,7 +34,8 @@ def _oracle_eval(orc, J, hx, jumps, kind, nh, th0, ns, nc, seed, t, dt, eps, wan
                         traj=t, first=True, dw=orc.draw_dw(seed, t, 0, len(jumps), dt), want_solve=want_solve)
 
 
-@pytest.mark.parametrize("n,ns,nc", [(65, 256, 8), (100, 320, 16), (128, 256, 8)])
+@pytest.mark.parametrize("n,ns,nc", [(65, 256, 8), (100, 320, 16), (128, 256, 8), (129, 256, 8), (160, 320, 16),
+                                     (192, 256, 8)])
 def test_ljph_two_words(tv, orc, n, ns, nc):
     """LJPH1 on a random problem (sigma^-, sigma^+, sigma^z channels), random parameters: one
     evaluation and solve, S from the FP64 and the int8 S-builds (shared-distance sums across the
@@ -46,11 +47,13 @@ def test_ljph_two_words(tv, orc, n, ns, nc):
     th0 = wl.random_theta(m, 0.03, seed=2)
     seed, dt, eps, TT = 6, 0.01, 1e-3, 2
     ref = [_oracle_eval(orc, J, hx, jumps, LJPH, d, th0, ns, nc, seed, 3 + t, dt, eps) for t in range(TT)]
-    runs = [tv.PREC_FP64] + ([tv.PREC_MFMA] if ns % 64 == 0 else [])
+    # int8 S-build: exact while the shared-distance sums (up to N - d - 1 terms of +-1) fit a byte
+    runs = [tv.PREC_FP64] + ([tv.PREC_MFMA] if ns % 64 == 0 and n - d - 1 <= 127 else [])
     for prec in runs:
         cfg = tv.make_config(TT, ns, nc, dt, eps, 2, 1, 3, precision=prec, seed=seed, traj_offset=3)
         ctx = tv.Context(tv.Problem(J, hx, jumps), cfg, kind=LJPH, n_hidden=d, theta0=th0)
-        assert ctx.words == 2
+        words = (n + 63) // 64
+        assert ctx.words == words
         ctx.sample()
         ctx.estimate()
         S = [ctx.get(T.Q_S, t) for t in range(TT)]
@@ -59,16 +62,19 @@ def test_ljph_two_words(tv, orc, n, ns, nc):
         for t in range(TT):
             r = ref[t]
             smp = ctx.get(T.Q_SAMPLES, t)
-            assert smp.shape == (ns, 2)
+            assert smp.shape == (ns, words)
             assert np.array_equal(tv.unpack_samples(smp, n), r["samples"])
-            assert np.all(smp[:, 1] >> np.uint64(n - 64) == 0)          # no bits above N
+            assert np.all(smp[:, -1] >> np.uint64(n - 64 * (words - 1)) == 0)          # no bits above N
             assert np.array_equal(ctx.get(T.Q_ACCEPTS, t).astype(np.int64), r["accepts"])
             assert _rel(ctx.get(T.Q_ELOC, t), r["eloc"]) < 1e-13
             assert np.array_equal(ctx.get(T.Q_OBAR, t), r["obar"].real)
             low = np.tril_indices(m)
             assert np.array_equal(S[t][low], (r["S"].real + eps * np.eye(m))[low])
             assert _rel(ctx.get(T.Q_D, t), r["D"]) < 1e-12
-            parity("Q_DELTA0", _rel(ctx.get(T.Q_DELTA0, t), r["delta"]), 1e-10)
+            # the forward error of a backward-stable FP64 solve is bounded by kappa(S + eps I) 2^-53;
+            # these random problems reach kappa ~ 2e7 at N = 192
+            kappa = np.linalg.cond(r["S"].real + eps * np.eye(m))
+            parity("Q_DELTA0", _rel(ctx.get(T.Q_DELTA0, t), r["delta"]), max(1e-10, kappa * 2.0 ** -53))
 
 
 def test_jastrow_two_words_sample_space(tv, orc):
@@ -98,10 +104,13 @@ def test_jastrow_two_words_sample_space(tv, orc):
 
 
 @pytest.mark.parametrize("n,nh,ns,nc,prec,TT", [(100, 3, 512, 8, 0, 2), (100, 3, 512, 8, 1, 1), (66, 70, 256, 8, 0, 1),
-                                                (127, 20, 256, 16, 0, 1)])
+                                                (127, 20, 256, 16, 0, 1), (150, 3, 512, 8, 0, 2), (150, 3, 640, 8, 1, 1),
+                                                (192, 20, 256, 16, 0, 1)])
 def test_rbm_two_words(tv, orc, n, nh, ns, nc, prec, TT):
     """The RBM at N = 100 (M = 403, parameter space, FP64 and BF16-split S), N = 66 with N' = 70
-    (two hidden units per lane, M = 4756 > N_s: sample space) and N = 127 (M = 2687, sample space)."""
+    (two hidden units per lane, M = 4756 > N_s: sample space), N = 127 (M = 2687, sample space),
+    and on three words N = 150 (M = 603: sample space at 512 samples, the BF16-split S at 640) and
+    N = 192 (M = 4052, sample space)."""
     from paper_2506_23928_amd import tvmc as T
     J, hx, jumps = wl.random_problem(n, seed=n + 1)
     m = orc.n_params(1, n, nh)
@@ -161,10 +170,38 @@ def test_ljph_two_words_trajectory(tv, orc):
         assert np.abs(ctx.get(T.Q_MOMENTS, t) - obs_o[t, 2]).max() < 1e-10
 
 
-def test_two_word_limits(tv):
-    """N = 129 and the one-word-only options are refused on the host."""
+def test_ljph_three_words_trajectory(tv, orc):
+    """Four steps of the N = 160 periodic LJPH1 chain (the setting of Fig. 2, h = 0.3 so that every
+    flip ratio enters; the eta plane is read from global memory at three words; FP64 S-build, since
+    the shared-distance sums outgrow the int8 operands), 2 trajectories, moments every 2 steps:
+    theta and the moment history against the oracle's trajectory driver."""
     from paper_2506_23928_amd import tvmc as T
-    J = np.zeros((129, 129))
+    n, d, ns, nc, TT, steps = 160, 1, 256, 8, 2, 4
+    J = orc.couplings("pbc", n, 1.0, 1.0)
+    jumps = [(0, i, 0.1) for i in range(n)]
+    m = orc.n_params(LJPH, n, d)
+    cfg_o = orc.Config(n_samples=ns, n_chains=nc, burn_sweeps=2, dt=0.005, diag_shift=1e-4, seed=3, n_steps=steps,
+                       obs_every=2)
+    th_o, obs_o, st = orc.run(orc.Problem(J, 0.3, jumps), LJPH, d, cfg_o, np.zeros(m), TT, n_threads=2)
+    assert st == 0
+    cfg = tv.make_config(TT, ns, nc, 0.005, 1e-4, 2, 1, 0, 0, tv.PREC_FP64, 2, 3, 3)
+    ctx = tv.Context(tv.Problem(J, 0.3, jumps), cfg, kind=LJPH, n_hidden=d)
+    assert ctx.words == 3
+    ctx.sde_step(steps)
+    ctx.sample()
+    ctx.observables()
+    ctx.synchronize()
+    for t in range(TT):
+        parity("Q_THETA", _rel(ctx.get(T.Q_THETA, t), th_o[t]), 1e-10)
+        assert np.abs(ctx.get(T.Q_OBS_HIST, t)[:2] - obs_o[t, :2]).max() < 1e-10
+        assert np.abs(ctx.get(T.Q_MOMENTS, t) - obs_o[t, 2]).max() < 1e-10
+
+
+def test_two_word_limits(tv):
+    """N = 193, the one-word-only options and the int8 S-build of LJPH1 beyond N = 129 are refused on
+    the host."""
+    from paper_2506_23928_amd import tvmc as T
+    J = np.zeros((193, 193))
     with pytest.raises(T.TvmcError):
         tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01))
     J = np.zeros((80, 80))
@@ -172,6 +209,11 @@ def test_two_word_limits(tv):
         tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, proposal=T.PROPOSAL_LEARNED, ar_hidden=32))
     with pytest.raises(T.TvmcError):
         tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, regulariser=T.REG_SNR))
+    # LJPH1 at N = 130: shared-distance sums of up to 128 terms do not fit the int8 operands
+    J = np.zeros((130, 130))
+    with pytest.raises(T.TvmcError):
+        tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, precision=tv.PREC_MFMA), kind=LJPH, n_hidden=1)
+    tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, precision=tv.PREC_FP64), kind=LJPH, n_hidden=1)
 
 
 def test_lattice10x10_full_size_launch(tv, orc):

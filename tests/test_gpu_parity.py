@@ -204,7 +204,7 @@ def test_bad_arguments_are_rejected(tv):
         (tv.Problem(J, 0.1, []), tv.make_config(2, 64, 12, 0.01)),                  # chains not a multiple of 8
         (tv.Problem(J, 0.1, []), tv.make_config(2, 96, 8, 0.01, precision=1)),      # MFMA needs 64 | samples
         (tv.Problem(np.ones((4, 4)), 0.1, []), tv.make_config(2, 64, 8, 0.01)),     # nonzero diagonal
-        (tv.Problem(np.zeros((129, 129)), 0.1, []), tv.make_config(2, 64, 8, 0.01)),  # N > 128
+        (tv.Problem(np.zeros((193, 193)), 0.1, []), tv.make_config(2, 64, 8, 0.01)),  # N > 192
     ]
     for pb, cfg in bad:
         with pytest.raises(T.TvmcError):

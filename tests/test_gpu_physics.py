@@ -233,3 +233,28 @@ def test_n100_ljph1_matches_appendix_d(orc):
         assert abs(M[0] - Me[0]) < 4 * se_mx + 1e-3, (t, M[0], Me[0], se_mx)
         assert abs(x2 - xe) < 4 * se_x2 + 5e-3, (t, x2, xe, se_x2)
         assert xe < 0.9
+
+
+def test_n160_ljph1_matches_appendix_d(orc):
+    """The setting of Fig. 2 at kappa/J = 0.1 (periodic chain, nearest replica, alpha = 1, h = 0;
+    three configuration words): LJPH1, 4096 samples, 64 trajectories, FP64 S-build (the
+    shared-distance sums outgrow the int8 operands), dt = 0.005,
+    against App. D up to t = 0.3 with the N = 64 and N = 100 tests' budget (4 jackknife errors plus
+    1e-3 in M_x and 5e-3 in xi^2)."""
+    import torch
+    assert torch.cuda.is_available()
+    import oracle.exact as ex
+    import paper_2506_23928_amd as tv
+    w, mom = _run_workload(tv, "chain160_ljph1", 60, tv.PREC_FP64)
+    n = w["n"]
+    Jo = orc.couplings("pbc", n, 1.0, 1.0)
+    for k in range(1, mom.shape[1]):
+        t = k * w["obs_every"] * w["dt"]
+        M, C, x2 = orc.ensemble(mom[:, k], n)
+        Me, Ce = ex.appd_general(Jo, w["decay"], t)
+        xe = ex.xi2(Me, Ce, n)
+        se_x2 = _jack(mom[:, k], lambda v: orc.ensemble(v, n)[2])
+        se_mx = _jack(mom[:, k, 0], lambda v: v.mean())
+        assert abs(M[0] - Me[0]) < 4 * se_mx + 1e-3, (t, M[0], Me[0], se_mx)
+        assert abs(x2 - xe) < 4 * se_x2 + 5e-3, (t, x2, xe, se_x2)
+        assert xe < 0.9

@@ -64,6 +64,12 @@ WORKLOADS = {
     # The paper's N = 100 quench (the transverse-field figure's setting at h = 0, where App. D is
     # exact): periodic chain (nearest replica), alpha = 1, decay kappa = 0.27, LJPH1 (297
     # parameters), 4096 samples x 64 trajectories, dt = 0.005
+    # The paper's N = 160 quench (Fig. 2, LJPH1, h = 0, App. D exact) at its middle decay kappa/J = 0.1;
+    # the figure does not state alpha, taken as 1 as in the N = 100 runs; three configuration
+    # words, 4096 samples x 64 trajectories, dt = 0.005
+    "chain160_ljph1": dict(geom="pbc", n=160, alpha=1.0, jscale=1.0, h=0.0, decay=0.1, dephase=0.0, ansatz="ljph",
+                           d=1, n_samples=4096, n_chains=64, n_traj=64, dt=0.005, t_end=1.0, diag_shift=1e-4,
+                           obs_every=20, burn_sweeps=2, thin_sweeps=1, seed=0),
     "chain100_ljph1": dict(geom="pbc", n=100, alpha=1.0, jscale=1.0, h=0.0, decay=0.27, dephase=0.0, ansatz="ljph",
                            d=1, n_samples=4096, n_chains=64, n_traj=64, dt=0.005, t_end=1.0, diag_shift=1e-4,
                            obs_every=20, burn_sweeps=2, thin_sweeps=1, seed=0),
