@@ -1,7 +1,11 @@
 // S + eps I for the Jastrow ansaetze on the int8 matrix cores (v_mfma_i32_16x16x64_i8).
 //
-// O_sk is +-1, or for a shared LJPHd distance an integer of magnitude <= N - 1 <= 127, so
-// sum_s O_sk O_sl is computed exactly as an int32 dot product of int8 values.
+// O_sk is +-1, or for a shared LJPHd distance D the sum over the len = N - D pairs at that
+// distance of s_j s_{j+D}, an integer of len's parity with |O| <= len <= N - 1 <= 191.  Such a
+// row is fed as its half h = (O - (len & 1)) / 2, |h| <= 96, and with c = 2, p = len & 1 for
+// those rows (c = 1, p = 0, h = O for the +-1 rows) the exact sum is rebuilt from the int32
+// MFMA sum of h_k h_l and the row sums of h:
+//   sum_s O_k O_l = c_k c_l sum h_k h_l + c_k p_l sum h_k + c_l p_k sum h_l + N_s p_k p_l.
 // Samples are first transposed to site-major bit planes (bit s of plane i = spin i of sample
 // s is up).  For a 64-sample chunk the sign bits of a parameter row are one XOR of two planes
 // (two-body) or a complement (one-body); four sign bits expand to four +-1 bytes with one
@@ -37,12 +41,17 @@ __device__ __forceinline__ uint32_t expand4(uint32_t nib) {
     return 0x01010101u ^ (spread * 0xFEu);                        // 0x01 (+1) or 0xFF (-1)
 }
 
-// four samples' O of a shared distance p (sum of s_j s_{j+p}) as four int8 bytes
+// four samples' halves h = (O - (len & 1)) / 2 of a shared distance p (O = sum of s_j s_{j+p}
+// over the len = n - p pairs) as four int8 bytes; their sum is added to hsum
 template <int W>
-__device__ __forceinline__ uint32_t dist_bytes4(const uint64_t *sp, int p, int n) {
+__device__ __forceinline__ uint32_t dist_bytes4(const uint64_t *sp, int p, int n, int &hsum) {
+    const int par = (n - p) & 1;
     uint32_t w = 0;
-    for (int b = 0; b < 4; ++b)
-        w |= (uint32_t)(uint8_t)(int8_t)o_int<true>(cfg_load<W>(sp + (size_t)b * W), p, -2, n) << (8 * b);
+    for (int b = 0; b < 4; ++b) {
+        const int h = (o_int<true>(cfg_load<W>(sp + (size_t)b * W), p, -2, n) - par) >> 1;   // exact: O - par is even
+        hsum += h;
+        w |= (uint32_t)(uint8_t)(int8_t)h << (8 * b);
+    }
     return w;
 }
 
@@ -50,6 +59,9 @@ template <bool DIST, int W>
 __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
     __shared__ uint32_t As[SB_TILE * SB_ROWW];
     __shared__ uint32_t Bs[SB_TILE * SB_ROWW];
+    // DIST: per tile row of A and B, the two halves' sums of h, then c + 4 p and a scaled sum
+    __shared__ int hs[DIST ? 2 * 2 * SB_TILE : 1];
+    __shared__ int rw[DIST ? 2 * 2 * SB_TILE : 1];
     const int t = blockIdx.y;
     const int tile = blockIdx.x;
     int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
@@ -71,6 +83,7 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
     v4i acc[4][4];
     for (int u = 0; u < 4; ++u)
         for (int v = 0; v < 4; ++v) acc[u][v] = (v4i){0, 0, 0, 0};
+    int hsa = 0, hsb = 0;   // DIST: this thread's share of the row sums of h
 
     for (int w0 = 0; w0 < nw; w0 += 2) {
         const int w = w0 + gh;
@@ -81,10 +94,13 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
         __syncthreads();
         if (DIST) {
             const uint64_t *sp = a.samples + ((size_t)t * a.ns + (size_t)w * 32) * W;
+            // a +-1 row's 32 values sum to 32 - 2 popcount (a set bit is -1)
+            if (va && aq != -2) hsa += 32 - 2 * __popc(na);
+            if (vb && bq != -2) hsb += 32 - 2 * __popc(nb);
             for (int q = 0; q < 8; ++q) {
-                As[gr * SB_ROWW + gh * 8 + q] = !va ? 0u : aq == -2 ? dist_bytes4<W>(sp + 4 * q * W, ap, a.n)
+                As[gr * SB_ROWW + gh * 8 + q] = !va ? 0u : aq == -2 ? dist_bytes4<W>(sp + 4 * q * W, ap, a.n, hsa)
                                                                    : expand4((na >> (4 * q)) & 0xFu);
-                Bs[gr * SB_ROWW + gh * 8 + q] = !vb ? 0u : bq == -2 ? dist_bytes4<W>(sp + 4 * q * W, bp, a.n)
+                Bs[gr * SB_ROWW + gh * 8 + q] = !vb ? 0u : bq == -2 ? dist_bytes4<W>(sp + 4 * q * W, bp, a.n, hsb)
                                                                    : expand4((nb >> (4 * q)) & 0xFu);
             }
         } else {
@@ -106,17 +122,43 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
             for (int v = 0; v < 4; ++v) acc[u][v] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[u], fb[v], acc[u][v], 0, 0, 0);
     }
 
+    if (DIST) {
+        // with x_k = c_k sum h_k for the rows k of A and y_l = c_l sum h_l + N_s p_l for the rows
+        // l of B, sum_s O_k O_l = c_k c_l sum h_k h_l + p_l x_k + p_k y_l (p is 0 or 1); rw holds
+        // [A / B][c + 4 p, x or y][row]
+        hs[gh * SB_TILE + gr] = hsa;
+        hs[(2 + gh) * SB_TILE + gr] = hsb;
+        __syncthreads();
+        if (gh == 0) {
+            const int ca = aq == -2 ? 2 : 1, pa_ = aq == -2 ? (a.n - ap) & 1 : 0;
+            const int cb = bq == -2 ? 2 : 1, pb_ = bq == -2 ? (a.n - bp) & 1 : 0;
+            rw[gr] = ca + 4 * pa_;
+            rw[SB_TILE + gr] = ca * (hs[gr] + hs[SB_TILE + gr]);
+            rw[2 * SB_TILE + gr] = cb + 4 * pb_;
+            rw[3 * SB_TILE + gr] = cb * (hs[2 * SB_TILE + gr] + hs[3 * SB_TILE + gr]) + a.ns * pb_;
+        }
+        __syncthreads();
+    }
     // epilogue: lane holds rows 4*(lane/16)+r, column lane%16 of each 16x16 block
     const double inv = 1.0 / (double)a.ns;
     const double *ob = a.obar + (size_t)t * a.m;
     double *S = a.S + (size_t)t * a.m * a.m;
+#pragma unroll
     for (int u = 0; u < 4; ++u)
+#pragma unroll
         for (int v = 0; v < 4; ++v)
+#pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int k = bi * SB_TILE + wr * 64 + u * 16 + 4 * (lane >> 4) + r;
-                const int l = bj * SB_TILE + wc * 64 + v * 16 + (lane & 15);
+                const int rk = wr * 64 + u * 16 + 4 * (lane >> 4) + r, rl = wc * 64 + v * 16 + (lane & 15);
+                const int k = bi * SB_TILE + rk, l = bj * SB_TILE + rl;
                 if (k >= a.m || l >= a.m || l > k) continue;
-                double sv = centre((double)acc[u][v][r], inv, ob[k], ob[l]);
+                double g = (double)acc[u][v][r];
+                if (DIST) {   // every term an integer below 2^53: exact in FP64
+                    const int fk = rw[rk], fl = rw[2 * SB_TILE + rl];
+                    g = (double)((fk & 3) * (fl & 3)) * g + (double)((fl & 4) ? rw[SB_TILE + rk] : 0) +
+                        (double)((fk & 4) ? rw[3 * SB_TILE + rl] : 0);
+                }
+                double sv = centre(g, inv, ob[k], ob[l]);
                 if (k == l) sv = add_shift(sv, a.eps);
                 S[(size_t)k * a.m + l] = sv;
             }

@@ -234,14 +234,12 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
     if (a->kind == TVMC_ANSATZ_LJPH) {
         if (a->range < 0 || a->range > p->n_sites - 1)
             return snprintf(msg, len, "LJPHd range d must be in [0, N-1]"), TVMC_E_INVAL;
-        const int64_t omax = p->n_sites - 1;   // largest |O_k| of a shared distance
-        if (c->precision == TVMC_PREC_MFMA && (int64_t)c->n_samples * omax * omax >= ((int64_t)1 << 31))
-            return snprintf(msg, len, "LJPHd int8 S-build: n_samples (N-1)^2 must stay below 2^31"), TVMC_E_INVAL;
-        // a shared distance D > d has O = sum over the N - D pairs at that distance of s_j s_{j+D}:
-        // the int8 operands hold it exactly only while N - d - 1 <= 127
-        if (c->precision == TVMC_PREC_MFMA && a->range < p->n_sites - 1 && p->n_sites - a->range - 1 > 127)
-            return snprintf(msg, len, "LJPHd int8 S-build: the shared-distance sums need N - d - 1 <= 127 "
-                                      "(use the FP64 S-build)"), TVMC_E_INVAL;
+        // the int8 S-build feeds a shared distance D > d (O = sum over the len = N - D pairs at that
+        // distance of s_j s_{j+D}) as h = (O - (len & 1)) / 2, |h| <= (N - d) / 2; its int32
+        // sums of h_k h_l stay exact below 2^31
+        const int64_t hmax = std::max<int64_t>(1, (p->n_sites - a->range) / 2);
+        if (c->precision == TVMC_PREC_MFMA && (int64_t)c->n_samples * hmax * hmax >= ((int64_t)1 << 31))
+            return snprintf(msg, len, "LJPHd int8 S-build: n_samples ((N-d)/2)^2 must stay below 2^31"), TVMC_E_INVAL;
         if (c->solver == TVMC_SOLVER_SAMPLE_SPACE)
             return snprintf(msg, len, "LJPHd solves in parameter space"), TVMC_E_INVAL;
     }

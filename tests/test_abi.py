@@ -74,12 +74,13 @@ def test_configuration_checks_run_on_the_host():
                             (lj, tvmc.make_config(2, 64, 8, 0.01, solver=tvmc.SOLVER_SAMPLE_SPACE))]:
         with pytest.raises(tvmc.TvmcError):
             tvmc.tvmc_workspace_size(pb, bad_an, bad_cfg)
-    # the int8 S-build sums n_samples products of magnitude up to (N-1)^2 in int32
+    # the int8 S-build sums n_samples products of the halved distance sums, magnitude up to
+    # ((N - d) / 2)^2 = 31^2 at N = 64, d = 1, in int32: 2^21 * 961 < 2^31 <= 2^22 * 961
     pb64 = tvmc.Problem(np.zeros((64, 64)), 0.1, [(0, 0, 0.1)])
-    ok = tvmc.make_config(1, 1 << 19, 64, 0.01, precision=tvmc.PREC_MFMA)
+    ok = tvmc.make_config(1, 1 << 21, 64, 0.01, precision=tvmc.PREC_MFMA)
     assert tvmc.tvmc_workspace_size(pb64, lj, ok) > 0
     with pytest.raises(tvmc.TvmcError):
-        tvmc.tvmc_workspace_size(pb64, lj, tvmc.make_config(1, 1 << 20, 64, 0.01, precision=tvmc.PREC_MFMA))
+        tvmc.tvmc_workspace_size(pb64, lj, tvmc.make_config(1, 1 << 22, 64, 0.01, precision=tvmc.PREC_MFMA))
     # SNR solve: parameter space, M <= 2176, tau >= 0; it adds workspace (complex for the RBM)
     snr = tvmc.make_config(2, 64, 8, 0.01, regulariser=tvmc.REG_SNR)
     plain = tvmc.make_config(2, 64, 8, 0.01)

@@ -47,8 +47,9 @@ def test_ljph_two_words(tv, orc, n, ns, nc):
     th0 = wl.random_theta(m, 0.03, seed=2)
     seed, dt, eps, TT = 6, 0.01, 1e-3, 2
     ref = [_oracle_eval(orc, J, hx, jumps, LJPH, d, th0, ns, nc, seed, 3 + t, dt, eps) for t in range(TT)]
-    # int8 S-build: exact while the shared-distance sums (up to N - d - 1 terms of +-1) fit a byte
-    runs = [tv.PREC_FP64] + ([tv.PREC_MFMA] if ns % 64 == 0 and n - d - 1 <= 127 else [])
+    # int8 S-build (64-sample chunks): the shared-distance sums, up to N - d - 1 terms of +-1 (191
+    # at N = 192), go in as their halves and the exact sums are rebuilt in the epilogue
+    runs = [tv.PREC_FP64] + ([tv.PREC_MFMA] if ns % 64 == 0 else [])
     for prec in runs:
         cfg = tv.make_config(TT, ns, nc, dt, eps, 2, 1, 3, precision=prec, seed=seed, traj_offset=3)
         ctx = tv.Context(tv.Problem(J, hx, jumps), cfg, kind=LJPH, n_hidden=d, theta0=th0)
@@ -198,8 +199,8 @@ def test_ljph_three_words_trajectory(tv, orc):
 
 
 def test_two_word_limits(tv):
-    """N = 193, the one-word-only options and the int8 S-build of LJPH1 beyond N = 129 are refused on
-    the host."""
+    """N = 193, the one-word-only options and an int8 LJPHd S-build whose int32 sums of the halved
+    distance sums could pass 2^31 are refused on the host."""
     from paper_2506_23928_amd import tvmc as T
     J = np.zeros((193, 193))
     with pytest.raises(T.TvmcError):
@@ -209,11 +210,12 @@ def test_two_word_limits(tv):
         tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, proposal=T.PROPOSAL_LEARNED, ar_hidden=32))
     with pytest.raises(T.TvmcError):
         tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, regulariser=T.REG_SNR))
-    # LJPH1 at N = 130: shared-distance sums of up to 128 terms do not fit the int8 operands
-    J = np.zeros((130, 130))
-    with pytest.raises(T.TvmcError):
-        tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, precision=tv.PREC_MFMA), kind=LJPH, n_hidden=1)
-    tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, precision=tv.PREC_FP64), kind=LJPH, n_hidden=1)
+    # LJH at N = 192: halves up to |h| = 96, so N_s 96^2 must stay below 2^31 (N_s < 233017)
+    J = np.zeros((192, 192))
+    with pytest.raises(T.TvmcError, match="2\\^31"):
+        tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 233024, 8, 0.01, precision=tv.PREC_MFMA), kind=LJPH,
+                   n_hidden=0)
+    tv.Context(tv.Problem(J, 0.5, []), tv.make_config(1, 64, 8, 0.01, precision=tv.PREC_MFMA), kind=LJPH, n_hidden=0)
 
 
 def test_lattice10x10_full_size_launch(tv, orc):
