@@ -60,10 +60,10 @@ enum { TVMC_JUMP_SIGMA_MINUS = 0, TVMC_JUMP_SIGMA_PLUS = 1, TVMC_JUMP_SIGMA_Z = 
 enum { TVMC_ANSATZ_JASTROW = 0, TVMC_ANSATZ_RBM = 1, TVMC_ANSATZ_LJPH = 2 };
 enum { TVMC_SCHEME_HEUN = 0, TVMC_SCHEME_MIDPOINT = 1 };
 /* FP64: S accumulated with FP64 vector FMAs.  MFMA: for the Jastrow ansaetze S is accumulated on
- * int8 matrix cores (every O_k is +-1, or an LJPHd distance sum, fed as its half, which fits a
- * byte up to N = 192), exactly, so both give the same S bit for bit; the int8 form refuses
- * n_samples ((N-d)/2)^2 >= 2^31 (TVMC_E_INVAL); for the RBM it is the three-term BF16 split with FP32
- * accumulation.  Solve and theta stay FP64 in both. */
+ * int8 matrix cores (every O_k is +-1, or an LJPHd distance sum, |O| <= N-d-1, fed as itself up to
+ * N = 128 and as its half, |h| <= (N-d)/2, beyond), exactly, so both give the same S bit for bit;
+ * the int8 form refuses n_samples times that bound squared >= 2^31 (TVMC_E_INVAL); for the RBM it
+ * is the three-term BF16 split with FP32 accumulation.  Solve and theta stay FP64 in both. */
 enum { TVMC_PREC_FP64 = 0, TVMC_PREC_MFMA = 1 };
 
 /* One Lindblad problem (Eq. 1 with the Hamiltonian of Eq. 10), shared by all trajectories of a

@@ -1,7 +1,8 @@
 // S + eps I for the Jastrow ansaetze on the int8 matrix cores (v_mfma_i32_16x16x64_i8).
 //
 // O_sk is +-1, or for a shared LJPHd distance D the sum over the len = N - D pairs at that
-// distance of s_j s_{j+D}, an integer of len's parity with |O| <= len <= N - 1 <= 191.  Such a
+// distance of s_j s_{j+D}, an integer of len's parity with |O| <= len <= N - 1.  Up to N = 128
+// (one or two configuration words) |O| <= 127 fits a byte.  With three words (N <= 192) such a
 // row is fed as its half h = (O - (len & 1)) / 2, |h| <= 96, and with c = 2, p = len & 1 for
 // those rows (c = 1, p = 0, h = O for the +-1 rows) the exact sum is rebuilt from the int32
 // MFMA sum of h_k h_l and the row sums of h:
@@ -41,27 +42,31 @@ __device__ __forceinline__ uint32_t expand4(uint32_t nib) {
     return 0x01010101u ^ (spread * 0xFEu);                        // 0x01 (+1) or 0xFF (-1)
 }
 
-// four samples' halves h = (O - (len & 1)) / 2 of a shared distance p (O = sum of s_j s_{j+p}
-// over the len = n - p pairs) as four int8 bytes; their sum is added to hsum
-template <int W>
+// four samples' O of a shared distance p (O = sum of s_j s_{j+p} over the len = n - p pairs) as
+// four int8 bytes, or with HALF their halves h = (O - (len & 1)) / 2, whose sum is added to hsum
+template <int W, bool HALF>
 __device__ __forceinline__ uint32_t dist_bytes4(const uint64_t *sp, int p, int n, int &hsum) {
     const int par = (n - p) & 1;
     uint32_t w = 0;
     for (int b = 0; b < 4; ++b) {
-        const int h = (o_int<true>(cfg_load<W>(sp + (size_t)b * W), p, -2, n) - par) >> 1;   // exact: O - par is even
-        hsum += h;
-        w |= (uint32_t)(uint8_t)(int8_t)h << (8 * b);
+        int o = o_int<true>(cfg_load<W>(sp + (size_t)b * W), p, -2, n);
+        if (HALF) {
+            o = (o - par) >> 1;   // exact: O - par is even
+            hsum += o;
+        }
+        w |= (uint32_t)(uint8_t)(int8_t)o << (8 * b);
     }
     return w;
 }
 
 template <bool DIST, int W>
 __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
+    constexpr bool HALF = DIST && W == 3;   // shared-distance rows fed as halves
     __shared__ uint32_t As[SB_TILE * SB_ROWW];
     __shared__ uint32_t Bs[SB_TILE * SB_ROWW];
-    // DIST: per tile row of A and B, the two halves' sums of h, then c + 4 p and a scaled sum
-    __shared__ int hs[DIST ? 2 * 2 * SB_TILE : 1];
-    __shared__ int rw[DIST ? 2 * 2 * SB_TILE : 1];
+    // HALF: per tile row of A and B, the two halves' sums of h, then c + 4 p and a scaled sum
+    __shared__ int hs[HALF ? 2 * 2 * SB_TILE : 1];
+    __shared__ int rw[HALF ? 2 * 2 * SB_TILE : 1];
     const int t = blockIdx.y;
     const int tile = blockIdx.x;
     int bi = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
@@ -83,7 +88,7 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
     v4i acc[4][4];
     for (int u = 0; u < 4; ++u)
         for (int v = 0; v < 4; ++v) acc[u][v] = (v4i){0, 0, 0, 0};
-    int hsa = 0, hsb = 0;   // DIST: this thread's share of the row sums of h
+    int hsa = 0, hsb = 0;   // HALF: this thread's share of the row sums of h
 
     for (int w0 = 0; w0 < nw; w0 += 2) {
         const int w = w0 + gh;
@@ -94,13 +99,14 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
         __syncthreads();
         if (DIST) {
             const uint64_t *sp = a.samples + ((size_t)t * a.ns + (size_t)w * 32) * W;
-            // a +-1 row's 32 values sum to 32 - 2 popcount (a set bit is -1)
-            if (va && aq != -2) hsa += 32 - 2 * __popc(na);
-            if (vb && bq != -2) hsb += 32 - 2 * __popc(nb);
+            if (HALF) {   // a +-1 row's 32 values sum to 32 - 2 popcount (a set bit is -1)
+                if (va && aq != -2) hsa += 32 - 2 * __popc(na);
+                if (vb && bq != -2) hsb += 32 - 2 * __popc(nb);
+            }
             for (int q = 0; q < 8; ++q) {
-                As[gr * SB_ROWW + gh * 8 + q] = !va ? 0u : aq == -2 ? dist_bytes4<W>(sp + 4 * q * W, ap, a.n, hsa)
+                As[gr * SB_ROWW + gh * 8 + q] = !va ? 0u : aq == -2 ? dist_bytes4<W, HALF>(sp + 4 * q * W, ap, a.n, hsa)
                                                                    : expand4((na >> (4 * q)) & 0xFu);
-                Bs[gr * SB_ROWW + gh * 8 + q] = !vb ? 0u : bq == -2 ? dist_bytes4<W>(sp + 4 * q * W, bp, a.n, hsb)
+                Bs[gr * SB_ROWW + gh * 8 + q] = !vb ? 0u : bq == -2 ? dist_bytes4<W, HALF>(sp + 4 * q * W, bp, a.n, hsb)
                                                                    : expand4((nb >> (4 * q)) & 0xFu);
             }
         } else {
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
             for (int v = 0; v < 4; ++v) acc[u][v] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[u], fb[v], acc[u][v], 0, 0, 0);
     }
 
-    if (DIST) {
+    if (HALF) {
         // with x_k = c_k sum h_k for the rows k of A and y_l = c_l sum h_l + N_s p_l for the rows
         // l of B, sum_s O_k O_l = c_k c_l sum h_k h_l + p_l x_k + p_k y_l (p is 0 or 1); rw holds
         // [A / B][c + 4 p, x or y][row]
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(256) void k_sbuild_i8(Dev a) {
                 const int k = bi * SB_TILE + rk, l = bj * SB_TILE + rl;
                 if (k >= a.m || l >= a.m || l > k) continue;
                 double g = (double)acc[u][v][r];
-                if (DIST) {   // every term an integer below 2^53: exact in FP64
+                if (HALF) {   // every term an integer below 2^53: exact in FP64
                     const int fk = rw[rk], fl = rw[2 * SB_TILE + rl];
                     g = (double)((fk & 3) * (fl & 3)) * g + (double)((fl & 4) ? rw[SB_TILE + rk] : 0) +
                         (double)((fk & 4) ? rw[3 * SB_TILE + rl] : 0);

@@ -235,11 +235,14 @@ tvmc_status check_args(const tvmc_problem *p, const tvmc_ansatz *a, const tvmc_c
         if (a->range < 0 || a->range > p->n_sites - 1)
             return snprintf(msg, len, "LJPHd range d must be in [0, N-1]"), TVMC_E_INVAL;
         // the int8 S-build feeds a shared distance D > d (O = sum over the len = N - D pairs at that
-        // distance of s_j s_{j+D}) as h = (O - (len & 1)) / 2, |h| <= (N - d) / 2; its int32
-        // sums of h_k h_l stay exact below 2^31
-        const int64_t hmax = std::max<int64_t>(1, (p->n_sites - a->range) / 2);
-        if (c->precision == TVMC_PREC_MFMA && (int64_t)c->n_samples * hmax * hmax >= ((int64_t)1 << 31))
-            return snprintf(msg, len, "LJPHd int8 S-build: n_samples ((N-d)/2)^2 must stay below 2^31"), TVMC_E_INVAL;
+        // distance of s_j s_{j+D}, |O| <= N - d - 1) as O itself up to N = 128 and as its half
+        // h = (O - (len & 1)) / 2, |h| <= (N - d) / 2, beyond; the int32 sums of products of
+        // these operands stay exact below 2^31
+        const int64_t nd = p->n_sites - a->range;
+        const int64_t omax = std::max<int64_t>(1, p->n_sites <= 128 ? nd - 1 : nd / 2);
+        if (c->precision == TVMC_PREC_MFMA && (int64_t)c->n_samples * omax * omax >= ((int64_t)1 << 31))
+            return snprintf(msg, len, "LJPHd int8 S-build: n_samples times the squared largest operand (N-d-1, or "
+                                      "(N-d)/2 beyond N = 128) must stay below 2^31"), TVMC_E_INVAL;
         if (c->solver == TVMC_SOLVER_SAMPLE_SPACE)
             return snprintf(msg, len, "LJPHd solves in parameter space"), TVMC_E_INVAL;
     }

@@ -74,13 +74,20 @@ def test_configuration_checks_run_on_the_host():
                             (lj, tvmc.make_config(2, 64, 8, 0.01, solver=tvmc.SOLVER_SAMPLE_SPACE))]:
         with pytest.raises(tvmc.TvmcError):
             tvmc.tvmc_workspace_size(pb, bad_an, bad_cfg)
-    # the int8 S-build sums n_samples products of the halved distance sums, magnitude up to
-    # ((N - d) / 2)^2 = 31^2 at N = 64, d = 1, in int32: 2^21 * 961 < 2^31 <= 2^22 * 961
+    # the int8 S-build sums n_samples products of magnitude up to (N - d - 1)^2 = 62^2 at N = 64,
+    # d = 1, in int32: 2^19 * 3844 < 2^31 <= 2^20 * 3844
     pb64 = tvmc.Problem(np.zeros((64, 64)), 0.1, [(0, 0, 0.1)])
-    ok = tvmc.make_config(1, 1 << 21, 64, 0.01, precision=tvmc.PREC_MFMA)
+    ok = tvmc.make_config(1, 1 << 19, 64, 0.01, precision=tvmc.PREC_MFMA)
     assert tvmc.tvmc_workspace_size(pb64, lj, ok) > 0
     with pytest.raises(tvmc.TvmcError):
-        tvmc.tvmc_workspace_size(pb64, lj, tvmc.make_config(1, 1 << 22, 64, 0.01, precision=tvmc.PREC_MFMA))
+        tvmc.tvmc_workspace_size(pb64, lj, tvmc.make_config(1, 1 << 20, 64, 0.01, precision=tvmc.PREC_MFMA))
+    # beyond N = 128 the distance sums enter as halves: at N = 192, d = 0 (LJH) up to 96^2 per
+    # product, 232960 * 9216 < 2^31 <= 233024 * 9216 (n_samples a multiple of 64)
+    pb192 = tvmc.Problem(np.zeros((192, 192)), 0.1, [(0, 0, 0.1)])
+    ljh = tvmc.make_ansatz(tvmc.LJPH, 0)
+    assert tvmc.tvmc_workspace_size(pb192, ljh, tvmc.make_config(1, 232960, 8, 0.01, precision=tvmc.PREC_MFMA)) > 0
+    with pytest.raises(tvmc.TvmcError):
+        tvmc.tvmc_workspace_size(pb192, ljh, tvmc.make_config(1, 233024, 8, 0.01, precision=tvmc.PREC_MFMA))
     # SNR solve: parameter space, M <= 2176, tau >= 0; it adds workspace (complex for the RBM)
     snr = tvmc.make_config(2, 64, 8, 0.01, regulariser=tvmc.REG_SNR)
     plain = tvmc.make_config(2, 64, 8, 0.01)

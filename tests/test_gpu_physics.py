@@ -237,15 +237,15 @@ def test_n100_ljph1_matches_appendix_d(orc):
 
 def test_n160_ljph1_matches_appendix_d(orc):
     """The setting of Fig. 2 at kappa/J = 0.1 (periodic chain, nearest replica, alpha = 1, h = 0;
-    three configuration words): LJPH1, 4096 samples, 64 trajectories, FP64 S-build (the
-    shared-distance sums outgrow the int8 operands), dt = 0.005,
+    three configuration words): LJPH1, 4096 samples, 64 trajectories, int8 S-build (the
+    shared-distance sums, up to 158 terms, enter as their halves), dt = 0.005,
     against App. D up to t = 0.3 with the N = 64 and N = 100 tests' budget (4 jackknife errors plus
     1e-3 in M_x and 5e-3 in xi^2)."""
     import torch
     assert torch.cuda.is_available()
     import oracle.exact as ex
     import paper_2506_23928_amd as tv
-    w, mom = _run_workload(tv, "chain160_ljph1", 60, tv.PREC_FP64)
+    w, mom = _run_workload(tv, "chain160_ljph1", 60, tv.PREC_MFMA)
     n = w["n"]
     Jo = orc.couplings("pbc", n, 1.0, 1.0)
     for k in range(1, mom.shape[1]):
