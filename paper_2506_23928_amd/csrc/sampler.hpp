@@ -222,21 +222,29 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow(Dev a, int stage, i
 }
 
 // The same chain for 64 < N <= 192 (W = 2 or 3 configuration words).  Lane l owns sites l,
-// l + 64, l + 128 and keeps their real fields only, which is all the accept test needs; the real
-// eta plane is staged in LDS where it fits (N <= 128: at most 128 KB) and read from global
-// memory otherwise (a row of it is contiguous over the lanes' sites).  The imaginary fields a
-// recorded sample needs for its flip ratios are summed afresh from the imaginary plane in
-// global memory, in the order a_i, then k = 0..N-1.  No learned proposal.
+// l + 64, l + 128 and keeps their real fields, their imaginary fields and their Ising fields
+// h_l = sum_k J_kl s_k; the real eta plane is staged in LDS where it fits (N <= 128: at most
+// 128 KB) and read from global memory otherwise (a row of it is contiguous over the lanes'
+// sites), and an accepted flip of site i adds -2 s_i times row i of each of the three planes
+// (the imaginary eta plane and J from global memory), so a recorded sample reads its flip
+// ratios and diagonal energy off the lanes' fields.  No learned proposal.
 template <int CPB, int W>
-__global__ __launch_bounds__(64 * CPB) void k_sample_jastrow_wn(Dev a, int stage, int burn) {
+__global__ __launch_bounds__(64 * CPB, W == 3 ? 4 : 1) void k_sample_jastrow_wn(Dev a, int stage, int burn) {
     static_assert(W == 2 || W == 3, "two or three configuration words");
     constexpr bool ETA_LDS = W == 2;
     const int step = a.dstep[0];
     __shared__ double lre_s[ETA_LDS ? 128 * 128 : 1];
     const int n = a.n;
-    const int t = blockIdx.y;
+    // Workgroup L runs on XCD L % 8; XCD x takes work items x * per .. x * per + per - 1, so
+    // the N_c / CPB workgroups of a trajectory share one XCD's L2 (the rows of its eta planes
+    // and of J that accepted flips read).  The grid is padded to a multiple of 8; padding
+    // workgroups exit at once.
+    const int nb = a.nc / CPB, per = (int)gridDim.x / 8;
+    const int g = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+    if (g >= nb * a.nt) return;
+    const int t = g / nb;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int c = blockIdx.x * CPB + w;
+    const int c = (g % nb) * CPB + w;
     const double *er = a.eta_re + (size_t)t * n * n;
     if (ETA_LDS) {
         for (int i = threadIdx.x; i < n * n; i += blockDim.x) lre_s[i] = er[i];
@@ -247,17 +255,23 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow_wn(Dev a, int stage
     const double2 *th = a.theta_eval + (size_t)t * a.m;
     Cfg<W> cfg = cfg_load<W>(a.chains + ((size_t)t * a.nc + c) * W);
 
-    double fre[W];
+    const double *Jt = a.J + t * a.j_stride;
+    double fre[W], fim[W], fh[W];
     for (int q = 0; q < W; ++q) {
-        fre[q] = 0.0;
+        fre[q] = fim[q] = fh[q] = 0.0;
         const int site = lane + 64 * q;
         if (site >= n) continue;
-        double f = th[site].x;
+        double f = th[site].x, g = th[site].y, h = 0.0;
         for (int k = 0; k < n; ++k) {
+            const double sk = spin(cfg, k);
+            h += Jt[k * n + site] * sk;
             if (k == site) continue;
-            f += lre[k * n + site] * spin(cfg, k);
+            f += lre[k * n + site] * sk;
+            g += eim_g[k * n + site] * sk;
         }
         fre[q] = f;
+        fim[q] = g;
+        fh[q] = h;
     }
 
     const uint32_t ctr1 = ((uint32_t)stage << 31) | (uint32_t)c;
@@ -291,7 +305,11 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow_wn(Dev a, int stage
                 const double c2 = -2.0 * si;
                 for (int q = 0; q < W; ++q) {
                     const int site = lane + 64 * q;
-                    if (site < n) fre[q] += c2 * lre[i * n + site];
+                    if (site < n) {   // eta_ii = 0; J_ii s_i is in h_i, as in the fresh sum
+                        fre[q] += c2 * lre[i * n + site];
+                        fim[q] += c2 * eim_g[i * n + site];
+                        fh[q] += c2 * Jt[i * n + site];
+                    }
                 }
                 ++nacc;
             }
@@ -304,13 +322,8 @@ __global__ __launch_bounds__(64 * CPB) void k_sample_jastrow_wn(Dev a, int stage
                     const int site = lane + 64 * q;
                     if (site >= n) continue;
                     const double sl = spin(cfg, site);
-                    double fim = th[site].y, hj = 0.0;
-                    for (int k = 0; k < n; ++k) {
-                        const double sk = spin(cfg, k);
-                        if (k != site) fim += eim_g[k * n + site] * sk;
-                        hj += a.J[t * a.j_stride + k * n + site] * sk;
-                    }
-                    const double dr = -2.0 * sl * fre[q], di = -2.0 * sl * fim;
+                    const double hj = fh[q];
+                    const double dr = -2.0 * sl * fre[q], di = -2.0 * sl * fim[q];
                     const double ex = exp(dr);
                     double sn, cs;
                     sincos(di, &sn, &cs);

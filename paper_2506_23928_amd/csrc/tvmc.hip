@@ -447,17 +447,24 @@ tvmc_status run_sample(tvmc_ctx *c) {
     {
         Scope sc(c, "sample");
         dim3 grid(d.nc / c->cpb, T);
+        // several words: 16 chains per workgroup (4 waves per SIMD, every chain resident at once:
+        // the eta plane in LDS allows one workgroup per compute unit) where the chain count
+        // allows, on a grid padded to a multiple of 8 for the XCD-aware placement
+        const int cpbw = c->cfg.sampler_chains > 0 ? c->cpb : (c->cpb == 8 && d.nc % 16 == 0) ? 16 : c->cpb;
+        const dim3 gridw((d.nc / cpbw * T + 7) / 8 * 8);
 #define JAS_LAUNCH(CPB, AR) hipLaunchKernelGGL((k_sample_jastrow<CPB, AR>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
-#define JASW_LAUNCH(CPB, W) hipLaunchKernelGGL((k_sample_jastrow_wn<CPB, W>), grid, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
+#define JASW_LAUNCH(CPB, W) hipLaunchKernelGGL((k_sample_jastrow_wn<CPB, W>), gridw, dim3(64 * CPB), 0, c->stream, d, c->stage, burn)
         if (d.nw == 2) {
-            switch (c->cpb) {
+            switch (cpbw) {
+            case 16: JASW_LAUNCH(16, 2); break;
             case 8: JASW_LAUNCH(8, 2); break;
             case 4: JASW_LAUNCH(4, 2); break;
             case 2: JASW_LAUNCH(2, 2); break;
             default: JASW_LAUNCH(1, 2); break;
             }
         } else if (d.nw == 3) {
-            switch (c->cpb) {
+            switch (cpbw) {
+            case 16: JASW_LAUNCH(16, 3); break;
             case 8: JASW_LAUNCH(8, 3); break;
             case 4: JASW_LAUNCH(4, 3); break;
             case 2: JASW_LAUNCH(2, 3); break;
