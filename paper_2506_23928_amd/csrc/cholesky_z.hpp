@@ -26,6 +26,20 @@ struct ZCholArgs {
     int m;
 };
 
+// Work item of an update workgroup on a one-dimensional grid padded to a multiple of 8: the
+// items (trajectory, row chunk) are numbered trajectory by trajectory; workgroup L runs on XCD
+// L % 8 and XCD x takes the items x * per .. x * per + per - 1, so the row chunks of a
+// trajectory run on one XCD and share its L2 copy of the panel rows and of the previous panel's
+// block inverse.  False for a padding workgroup.
+__device__ __forceinline__ bool zmw_item(int nchunk, int nt, int &t, int &chunk) {
+    const int per = (int)gridDim.x / 8;
+    const int g = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+    if (g >= nchunk * nt) return false;
+    t = g / nchunk;
+    chunk = g % nchunk;
+    return true;
+}
+
 __global__ __launch_bounds__(256) void k_zmw_init(ZCholArgs a) {
     const int t = blockIdx.y;
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -45,13 +59,14 @@ static_assert(2 * ZBUF >= 2 * CN * CSP + 2 * CN, "the staging buffers hold a blo
 //   C[rows, panel] = A[rows, panel] - L[rows, 0:j0] L[panel, 0:j0]^H.
 // pp < 0: no previous panel (j0 = 0).  The TRSM's values are read back by the update loop from
 // global memory after a workgroup barrier (same workgroup, so the barrier orders them).
-__global__ __launch_bounds__(ZT) void k_zmw_update(ZCholArgs a, int j0, int pp) {
+__global__ __launch_bounds__(ZT) void k_zmw_update(ZCholArgs a, int j0, int pp, int nt) {
     __shared__ double stage[2 * ZBUF];
-    const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int M = a.m;
-    const int r0 = j0 + blockIdx.x * CR;
-    if (r0 >= M) return;
+    int t, chunk;
+    if (!zmw_item((M - j0 + CR - 1) / CR, nt, t, chunk)) return;
+    const int r0 = j0 + chunk * CR;
     const int jb = (M - j0) < CN ? (M - j0) : CN;
     double2 *A = a.A + (size_t)t * M * M;
     if (pp >= 0) {
@@ -204,13 +219,14 @@ constexpr int ZU_STAGES = 3;
 constexpr int ZU_ROWS = CR + CN;                       // rows of one staged slice
 constexpr int ZU_SLICE = ZU_ROWS * ZK;                 // double2 elements of one staged slice
 static_assert(ZK == 16 && ZT == 512, "one slice is 48 wave copies of 1 KB: six per wave");
-__global__ __launch_bounds__(ZT) void k_zmw_update_lds(ZCholArgs a, int j0, int pp) {
+__global__ __launch_bounds__(ZT) void k_zmw_update_lds(ZCholArgs a, int j0, int pp, int nt) {
     __shared__ __attribute__((aligned(1024))) double2 sl[ZU_STAGES * ZU_SLICE];   // 144 KB
-    const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int M = a.m;
-    const int r0 = j0 + blockIdx.x * CR;
-    if (r0 >= M) return;
+    int t, chunk;
+    if (!zmw_item((M - j0 + CR - 1) / CR, nt, t, chunk)) return;
+    const int r0 = j0 + chunk * CR;
     const int jb = (M - j0) < CN ? (M - j0) : CN;
     double2 *A = a.A + (size_t)t * M * M;
     if (pp >= 0) {   // the previous panel's TRSM of this chunk's rows below the current panel

@@ -630,11 +630,12 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
             // complex: the previous panel's TRSM of the rows below this panel rides in the update;
             // the direct-to-LDS form addresses a trajectory's matrix by 32-bit byte offsets
             if constexpr (CPLX) {
-                const dim3 grid((x.m - j0 + CR - 1) / CR, T);
+                // one-dimensional grid of (trajectory, row chunk) items, padded to a multiple of 8
+                const dim3 grid(((x.m - j0 + CR - 1) / CR * T + 7) / 8 * 8);
                 if ((size_t)x.m * x.m * sizeof(double2) <= 0xffffffffull)
-                    hipLaunchKernelGGL(k_zmw_update_lds, grid, dim3(ZT), 0, st, x, j0, p - 1);
+                    hipLaunchKernelGGL(k_zmw_update_lds, grid, dim3(ZT), 0, st, x, j0, p - 1, T);
                 else
-                    hipLaunchKernelGGL(k_zmw_update, grid, dim3(ZT), 0, st, x, j0, p - 1);
+                    hipLaunchKernelGGL(k_zmw_update, grid, dim3(ZT), 0, st, x, j0, p - 1, T);
             } else {
                 hipLaunchKernelGGL(k_cmw_update, dim3((x.m - j0 + CR - 1) / CR, T), dim3(256), 0, st, x, j0);
             }
