@@ -25,6 +25,20 @@ constexpr int CSP = CN + 1;   // padded LDS row of Cs / Ls
 constexpr int CKP = CK + 1;   // padded LDS row of As / Bs
 constexpr int CKBUF = (CR + CN) * CKP;   // one k-slice staging buffer: As [CR][CKP] then Bs [CN][CKP]
 constexpr int CT1 = 512;      // threads of the one-workgroup solver: 8 waves, 16 rows of a chunk each
+
+// Work item of a panel-update workgroup on a one-dimensional grid padded to a multiple of 8:
+// the items (trajectory, row chunk) are numbered trajectory by trajectory; workgroup L runs on
+// XCD L % 8 and XCD x takes the items x * per .. x * per + per - 1, so the row chunks of a
+// trajectory run on one XCD and share its L2 copy of the panel rows and of the previous panel's
+// block inverse.  False for a padding workgroup.
+__device__ __forceinline__ bool chunk_item(int nchunk, int nt, int &t, int &chunk) {
+    const int per = (int)gridDim.x / 8;
+    const int g = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+    if (g >= nchunk * nt) return false;
+    t = g / nchunk;
+    chunk = g % nchunk;
+    return true;
+}
 static_assert(CN % (2 * CK) == 0, "the update loop takes k-slices in pairs");
 
 __host__ __device__ inline int chol_panels(int m) { return (m + CN - 1) / CN; }

@@ -104,18 +104,19 @@ constexpr int CW = 32;
 constexpr int CUT = 512;   // 8 waves, 16 rows of the chunk each
 static_assert(CW * 8 == 256 && CUT == 512, "a slice row is 16 pieces of 16 bytes");
 template <int NC>
-__global__ __launch_bounds__(CUT) void k_cmw_update_lds(CholArgs a, int j0, int pp, int k0, int skip) {
+__global__ __launch_bounds__(CUT) void k_cmw_update_lds(CholArgs a, int j0, int pp, int k0, int skip, int nt) {
     constexpr int STAGES = NC == 64 ? 3 : 2;
     constexpr int SLICE = (CR + NC) * CW;               // doubles of one staged slice
     constexpr int COPIES = (CR + NC) * CW * 8 / 8192;   // 1 KB wave copies per wave and slice
     constexpr int NV = NC / 16;                          // 16 x 16 output blocks per wave
     static_assert(STAGES * SLICE * 8 <= 160 * 1024 && STAGES * SLICE >= CN * CSP + 2 * CN, "LDS budget");
     __shared__ __attribute__((aligned(1024))) double sl[STAGES * SLICE];
-    const int t = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int M = a.m;
-    const int r0 = j0 + blockIdx.x * CR;
-    if (r0 >= M) return;
+    int t, chunk;
+    if (!chunk_item((M - j0 + CR - 1) / CR, nt, t, chunk)) return;
+    const int r0 = j0 + chunk * CR;
     const int jb = (M - j0) < NC ? (M - j0) : NC;
     double *A = a.A + (size_t)t * M * M;
     if (pp >= 0) {

@@ -26,19 +26,6 @@ struct ZCholArgs {
     int m;
 };
 
-// Work item of an update workgroup on a one-dimensional grid padded to a multiple of 8: the
-// items (trajectory, row chunk) are numbered trajectory by trajectory; workgroup L runs on XCD
-// L % 8 and XCD x takes the items x * per .. x * per + per - 1, so the row chunks of a
-// trajectory run on one XCD and share its L2 copy of the panel rows and of the previous panel's
-// block inverse.  False for a padding workgroup.
-__device__ __forceinline__ bool zmw_item(int nchunk, int nt, int &t, int &chunk) {
-    const int per = (int)gridDim.x / 8;
-    const int g = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
-    if (g >= nchunk * nt) return false;
-    t = g / nchunk;
-    chunk = g % nchunk;
-    return true;
-}
 
 __global__ __launch_bounds__(256) void k_zmw_init(ZCholArgs a) {
     const int t = blockIdx.y;
@@ -65,7 +52,7 @@ __global__ __launch_bounds__(ZT) void k_zmw_update(ZCholArgs a, int j0, int pp, 
     const int li = lane & 15, lk = lane >> 4;
     const int M = a.m;
     int t, chunk;
-    if (!zmw_item((M - j0 + CR - 1) / CR, nt, t, chunk)) return;
+    if (!chunk_item((M - j0 + CR - 1) / CR, nt, t, chunk)) return;
     const int r0 = j0 + chunk * CR;
     const int jb = (M - j0) < CN ? (M - j0) : CN;
     double2 *A = a.A + (size_t)t * M * M;
@@ -225,7 +212,7 @@ __global__ __launch_bounds__(ZT) void k_zmw_update_lds(ZCholArgs a, int j0, int 
     const int li = lane & 15, lk = lane >> 4;
     const int M = a.m;
     int t, chunk;
-    if (!zmw_item((M - j0 + CR - 1) / CR, nt, t, chunk)) return;
+    if (!chunk_item((M - j0 + CR - 1) / CR, nt, t, chunk)) return;
     const int r0 = j0 + chunk * CR;
     const int jb = (M - j0) < CN ? (M - j0) : CN;
     double2 *A = a.A + (size_t)t * M * M;

@@ -604,16 +604,16 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
             for (int j0 = 0, p = 0; j0 < x.m; j0 += 2 * CN, p += 2) {
                 const bool second = j0 + CN < x.m;
                 if (j0 > 0) {
-                    hipLaunchKernelGGL(k_cmw_update_lds<2 * CN>, dim3((x.m - j0 + CR - 1) / CR, T), dim3(CUT), 0, st,
-                                       x, j0, p - 1, 0, 2 * CN);
+                    hipLaunchKernelGGL(k_cmw_update_lds<2 * CN>, dim3(((x.m - j0 + CR - 1) / CR * T + 7) / 8 * 8), dim3(CUT),
+                                       0, st, x, j0, p - 1, 0, 2 * CN, T);
                     LAUNCHCHECK(c, "panel-pair update");
                 }
                 hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, st, x, j0, p, second ? CN : 0);
                 LAUNCHCHECK(c, "diagonal block");
                 if (second) {
                     const int j1 = j0 + CN;
-                    hipLaunchKernelGGL(k_cmw_update_lds<CN>, dim3((x.m - j1 + CR - 1) / CR, T), dim3(CUT), 0, st, x,
-                                       j1, p, j0, CN);
+                    hipLaunchKernelGGL(k_cmw_update_lds<CN>, dim3(((x.m - j1 + CR - 1) / CR * T + 7) / 8 * 8), dim3(CUT), 0,
+                                       st, x, j1, p, j0, CN, T);
                     LAUNCHCHECK(c, "panel update");
                     hipLaunchKernelGGL(k_cmw_diag, dim3(T), dim3(256), 0, st, x, j1, p + 1,
                                        j1 + CN < x.m ? 2 * CN : 0);
@@ -631,6 +631,7 @@ tvmc_status solve_sequence(tvmc_ctx *c, const Args &x, int T, hipStream_t st) {
             // the direct-to-LDS form addresses a trajectory's matrix by 32-bit byte offsets
             if constexpr (CPLX) {
                 // one-dimensional grid of (trajectory, row chunk) items, padded to a multiple of 8
+                // (XCD-aware placement, chunk_item)
                 const dim3 grid(((x.m - j0 + CR - 1) / CR * T + 7) / 8 * 8);
                 if ((size_t)x.m * x.m * sizeof(double2) <= 0xffffffffull)
                     hipLaunchKernelGGL(k_zmw_update_lds, grid, dim3(ZT), 0, st, x, j0, p - 1, T);
