@@ -117,10 +117,11 @@ typedef struct {
                                      the results are the same bits as the eager launches; needs a
                                      stream other than the default one */
     int32_t sampler_chains;       /* Markov chains per sampler workgroup (one wavefront each): 0 picks
-                                     the largest of 8, 4, 2, 1 dividing n_chains (16 for the RBM when
-                                     it divides and N' <= 128); else 1, 2, 4, 8 or 16 (RBM with
-                                     N' <= 128 only), dividing n_chains.  A launch shape only: the
-                                     samples are the same bits for every value */
+                                     the largest of 8, 4, 2, 1 dividing n_chains (16 when it divides
+                                     for the RBM with N' <= 128 and for the Jastrow ansaetze with
+                                     N > 64); else 1, 2, 4, 8 or 16 (RBM with N' <= 128 only),
+                                     dividing n_chains.  A launch shape only: the samples are the
+                                     same bits for every value */
 } tvmc_config;
 
 /* SHIFT: the Cholesky solve of (S + eps I) delta = D.  SNR: the regulariser the paper names in
