@@ -349,20 +349,30 @@ __device__ __forceinline__ double2 rbm_o(const Dev &a, int k, const C &mk, const
 }
 
 // <O_k> and D_k = <O_k^* G> - <O_k>^* <G>
-// Lane l of the workgroup's 4 waves takes the 8 parameters k_c = 512 blockIdx.x + 64 c + l
+// Lane l of the workgroup's 4 waves takes the 8 parameters k_c = 512 b + 64 c + l (b: the
+// workgroup's block of its trajectory's parameters)
 // (c < 8); wave w sums the samples of quarter w of the batch, and the four partial sums are
 // added in wave order.  Weight rows k_c with the same hidden unit j (all 8 of them when N'
 // divides 64 and the weights start on a multiple of 64) share one load of tanh g_j per sample.
 constexpr int OD_R = 8;
 template <int W>
 __global__ __launch_bounds__(256) void k_obar_D_rbm(Dev a) {
-    __shared__ double part[4][OD_R][4][64];
-    const int t = blockIdx.y, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // waves 1..3 leave their partial sums here; wave 0 keeps its own in registers (48 KB, three
+    // workgroups per compute unit)
+    __shared__ double part[3][OD_R][4][64];
+    // Workgroup L runs on XCD L % 8; XCD x takes work items x * per .. x * per + per - 1, so
+    // the workgroups of a trajectory share one XCD's L2 copy of its samples, G and tanh rows.
+    // The grid is padded to a multiple of 8; padding workgroups exit at once.
+    const int nb = (a.m + 64 * OD_R - 1) / (64 * OD_R), per = (int)gridDim.x / 8;
+    const int g = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+    if (g >= nb * a.nt) return;
+    const int t = g / nb, bx = g % nb;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = a.n, nh = a.nh, wb = n + nh;
     int ki[OD_R], kj[OD_R];
     int jl = -1;
     for (int c = 0; c < OD_R; ++c) {
-        const int k = blockIdx.x * 64 * OD_R + 64 * c + lane;
+        const int k = bx * 64 * OD_R + 64 * c + lane;
         ki[c] = kj[c] = -1;
         if (k >= wb && k < a.m) {
             ki[c] = (k - wb) / nh;
@@ -382,7 +392,7 @@ __global__ __launch_bounds__(256) void k_obar_D_rbm(Dev a) {
         const double2 *tts = tt + (size_t)s * nh;
         const double2 tv = jl >= 0 ? tts[jl] : make_double2(0.0, 0.0);
         for (int c = 0; c < OD_R; ++c) {
-            const int k = blockIdx.x * 64 * OD_R + 64 * c + lane;
+            const int k = bx * 64 * OD_R + 64 * c + lane;
             if (k >= a.m) continue;
             double2 o;
             if (ki[c] >= 0 && kj[c] == jl) {
@@ -397,17 +407,18 @@ __global__ __launch_bounds__(256) void k_obar_D_rbm(Dev a) {
             acc[c][3] += o.x * g.y - o.y * g.x;
         }
     }
-    for (int c = 0; c < OD_R; ++c)
-        for (int v = 0; v < 4; ++v) part[w][c][v][lane] = acc[c][v];
+    if (w > 0)
+        for (int c = 0; c < OD_R; ++c)
+            for (int v = 0; v < 4; ++v) part[w - 1][c][v][lane] = acc[c][v];
     __syncthreads();
     if (w != 0) return;
     const double inv = 1.0 / (double)a.ns;
     const double2 gb = a.gbar[t];
     for (int c = 0; c < OD_R; ++c) {
-        const int k = blockIdx.x * 64 * OD_R + 64 * c + lane;
+        const int k = bx * 64 * OD_R + 64 * c + lane;
         if (k >= a.m) continue;
         double sum[4];
-        for (int v = 0; v < 4; ++v) sum[v] = part[0][c][v][lane] + part[1][c][v][lane] + part[2][c][v][lane] + part[3][c][v][lane];
+        for (int v = 0; v < 4; ++v) sum[v] = acc[c][v] + part[0][c][v][lane] + part[1][c][v][lane] + part[2][c][v][lane];
         const double obr = sum[0] * inv, obi = sum[1] * inv;
         a.obarc[(size_t)t * a.m + k] = make_double2(obr, obi);
         a.D[(size_t)t * a.m + k] =

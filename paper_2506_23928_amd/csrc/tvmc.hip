@@ -507,7 +507,8 @@ tvmc_status run_estimate(tvmc_ctx *c) {
         hipLaunchKernelGGL(k_gbar, dim3(T), dim3(256), 0, c->stream, d);
         LAUNCHCHECK(c, "k_gbar");
         if (d.kind == TVMC_ANSATZ_RBM) {
-            BY_WORDS(d, hipLaunchKernelGGL((k_obar_D_rbm<W_>), dim3((d.m + 64 * OD_R - 1) / (64 * OD_R), T), dim3(256), 0, c->stream, d));
+            BY_WORDS(d, hipLaunchKernelGGL((k_obar_D_rbm<W_>), dim3(((d.m + 64 * OD_R - 1) / (64 * OD_R) * T + 7) / 8 * 8),
+                                           dim3(256), 0, c->stream, d));
             LAUNCHCHECK(c, "k_obar_D_rbm");
         } else {
             if (d.kind == TVMC_ANSATZ_LJPH)
